@@ -1,0 +1,198 @@
+"""Throughput of the binned power-waveform path on one MI355X.
+
+One step = one forward pass over the whole synthetic trace (gate preparation,
+per-event energies and leakage steps, time-tile accumulation, leakage prefix
+scan, FP32 power), with the events already resident in HBM and the plan
+(which depends only on event times, pins and the bin width) built during
+warm-up. The workload is the 1M-gate, 200M-event, 50 ps-bin configuration;
+``--config`` selects another synthetic configuration.
+
+Prints one JSON line (see the keys below). The per-kernel durations come from
+HIP events recorded on the library's stream around every launch inside the
+timed region.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+EVENT_BYTES = 13           # t int64 + slew float32 + pin/value uint8 read per event
+GATE_BYTES = 32            # prepared gate record read per gate (written once per call by k_gate_prep)
+BIN_BYTES = 4              # FP32 power written per bin
+
+WORKLOADS = {
+    "C1": "1k gates, 8 cells (1-3 inputs), 100k events over 1k cycles of 1 ns, 100 ps bins",
+    "C2": "1M gates, 64 cells (1-4 inputs), 200M events over 100k cycles of 1 ns, 50 ps bins, "
+          "lognormal(4,2) per-gate counts, 200 clock gates",
+    "C3": "5M gates, 64 cells, 1B events, Zipf(1.2) per-gate counts, 200k cycles, 100 ps bins",
+    "C5": "1M gates, 64 cells, 100M events over 50k cycles, 50 ps bins (adjoint workload)",
+}
+
+
+def cpu_brand() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--algo", type=int, default=0, help="0 time-tiled, 1 one gate per thread")
+    ap.add_argument("--tile-log2", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work for the oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
+                                   "(the multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    import paper_2609_05960_amd as gtp
+
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    prob = synth.make_problem(args.config)
+    gen_s = time.time() - t0
+    print(f"# generated {args.config}: {prob.ev.n_events} events, {prob.net.n_gates} gates, {prob.n_bins} bins "
+          f"in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    net, ev = prob.net, prob.ev
+    ctx = gtp.Context(0)
+    ctx.load_library(prob.lib)
+    ctx.load_netlist(torch.from_numpy(net.gate_cell).to(dev), torch.from_numpy(net.gate_out_net).to(dev),
+                     torch.from_numpy(net.gate_init.view(np.int32)).to(dev), net.n_nets)
+    tens = [torch.from_numpy(a).to(dev) for a in (ev.gate_off, ev.t, ev.pin_bit, ev.slew)]
+    torch.cuda.synchronize()
+    tp = time.time()
+    ctx.load_events(*tens, t_end=ev.t_end, validate=False)
+    ctx.set_params(vdd=prob.vdd, bin_ps=prob.bin_ps, sw_mode=prob.sw_mode)
+    ctx.set_tuning(algo=args.algo, bins_per_tile_log2=args.tile_log2)
+    load = torch.from_numpy(net.net_load).to(dev)
+    lam = torch.from_numpy(net.leak_scale).to(dev)
+    P = torch.empty(ctx.n_bins, dtype=torch.float32, device=dev)
+    ctx.forward(load, lam, out=P)  # builds the time-tile plan
+    torch.cuda.synchronize()
+    plan_s = time.time() - tp
+    for _ in range(args.warmup):
+        ctx.forward(load, lam, out=P)
+    torch.cuda.synchronize()
+
+    # ---- timed forward ---------------------------------------------------
+    stream = torch.cuda.current_stream(dev)
+    ctx.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.forward(load, lam, out=P)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    kern = ctx.profile_read()
+    ctx.profile(False)
+    ctx.sync()
+    ms_step = ms_total / args.steps
+    N, G, NB = ev.n_events, net.n_gates, ctx.n_bins
+    value = N * args.steps / (ms_total * 1e-3)
+
+    kern_avg = {k: dict(launches=n, avg_ms=ms / max(n, 1), total_ms=ms) for k, (n, ms) in kern.items()}
+    dom = max(kern_avg, key=lambda k: kern_avg[k]["total_ms"])
+    algo_bytes = {"k_fwd_records": EVENT_BYTES * N, "k_gate_serial": EVENT_BYTES * N + GATE_BYTES * G,
+                  "k_tile_accum": 16 * NB, "k_gate_prep": 24 * G, "k_finalize": 28 * NB}
+    dom_bytes = algo_bytes.get(dom)
+    dom_ms = kern_avg[dom]["avg_ms"]
+    achieved = dom_bytes / (dom_ms * 1e-3) if dom_bytes else None
+    step_bytes = EVENT_BYTES * N + GATE_BYTES * G + BIN_BYTES * NB
+
+    out = {
+        "metric": "events/s into binned power waveform (fwd, fwd+adjoint); % of HBM roofline",
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "n_gates": G, "n_events": N,
+                   "n_bins": NB, "bin_ps": prob.bin_ps, "t_end_ps": ev.t_end, "algo": args.algo,
+                   "tuning": ctx.get_tuning()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": (achieved / 1e9) if achieved else None,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK) if achieved else None, "traffic": None,
+                     "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms},
+        "step_hbm_frac": step_bytes / (ms_step * 1e-3) / HBM_PEAK,
+        "kernels": kern_avg,
+        "plan_s": plan_s,
+        "gen_s": gen_s,
+    }
+
+    # ---- forward + adjoint -------------------------------------------------
+    if not args.no_adjoint:
+        beta = float(1.0 / (0.05 * P.double().mean().item()))
+        gP = torch.empty_like(P)
+        for _ in range(2):
+            ctx.forward(load, lam, out=P)
+            gP.copy_(torch.softmax(beta * P, dim=0))
+            ctx.adjoint(load, lam, gP)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            ctx.forward(load, lam, out=P)
+            gP.copy_(torch.softmax(beta * P, dim=0))
+            ctx.adjoint(load, lam, gP)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_fa = e0.elapsed_time(e1) / args.steps
+        out["fwd_adjoint"] = {"value": N / (ms_fa * 1e-3), "unit": "events/s", "ms_per_step": ms_fa}
+
+    # ---- CPU oracle on a bounded sample ------------------------------------
+    if not args.no_cpu:
+        import oracle
+        O = oracle.get()
+        counts = np.diff(ev.gate_off)
+        cum = np.cumsum(counts)
+        # calibrate on ~2M events, then size the sample for about --cpu-seconds
+        m = int(np.searchsorted(cum, 2_000_000)) + 1
+        t1 = time.time()
+        O.forward(prob, gates=np.arange(m), nthreads=0)
+        rate = cum[m - 1] / max(time.time() - t1, 1e-6)
+        target = min(N, int(rate * args.cpu_seconds))
+        m = int(np.searchsorted(cum, target)) + 1
+        m = min(m, G)
+        t1 = time.time()
+        O.forward(prob, gates=np.arange(m), nthreads=0)
+        dt = time.time() - t1
+        ns = int(cum[m - 1])
+        out["cpu_baseline"] = {"value": ns / dt, "unit": "events/s", "cores": O.max_threads(), "kind": "oracle",
+                               "sample": f"gates 0..{m - 1} of {args.config} ({ns} events, all {NB} bins), "
+                                         f"FP64, {dt:.1f} s", "cpu": cpu_brand()}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

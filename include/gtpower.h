@@ -1,0 +1,204 @@
+/*
+ * gtpower — C ABI of the MI355X (gfx950) binned power-waveform library.
+ *
+ * The library turns per-gate toggle-event streams into a time-binned power
+ * waveform (the power computation of the paper's Sec. 2.2-2.3 models, fused
+ * as in Sec. 4.3 / Algorithm 1): every event gets a state-indexed internal
+ * energy lookup (Sec. 4.1: the gate's input state selects a table, which is
+ * interpolated bilinearly over input slew x output load, Sec. 2.2), output
+ * toggles add switching energy (Eq. switching energy; see gtp_params), the
+ * leakage of each held input state is charged for its duration (Eq. leakage
+ * energy) and everything is accumulated into fixed-width time bins, an
+ * interval being split over the bins it overlaps (Sec. 2.3).
+ * The adjoint gives d(loss)/d(net load) and d(loss)/d(per-gate leakage
+ * scale) for a loss of the binned power.
+ *
+ * Units: time ps (int64), slew ps, load fF, table energy fJ per transition,
+ * leakage nW, supply V; power mW (1 fJ/ps = 1 mW).
+ *
+ * Conventions for every call:
+ *   - Status returns only; nothing aborts and no C++ exception leaves the ABI.
+ *     gtp_last_error() gives a message for the last non-OK status of a ctx.
+ *   - Device work is asynchronous on the ctx stream (a hipStream_t passed as
+ *     void*; NULL = the null stream). A non-OK status reports argument or
+ *     enqueue errors; conditions found by kernels (a leakage scale out of
+ *     range, an invalid event when validating) are reported by the next
+ *     synchronising call: gtp_sync(), gtp_load_events(validate=1).
+ *   - "DEVICE" pointers are HIP device memory on the ctx device; "HOST"
+ *     pointers are host memory. Library and netlist arrays are copied into
+ *     ctx-owned memory; event arrays are BORROWED (they are large) and must
+ *     stay alive and unchanged until the next gtp_load_events or gtp_destroy.
+ *     Outputs are caller-allocated and overwritten.
+ *   - A ctx is not thread-safe; use one per host thread.
+ */
+#ifndef GTPOWER_H
+#define GTPOWER_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gtp_ctx_s* gtp_ctx;
+
+typedef enum {
+  GTP_OK = 0,
+  GTP_ERR_INVALID_ARG = 1,   /* null pointer, negative or mismatched size, bad table */
+  GTP_ERR_OUT_OF_MEMORY = 2, /* device allocation failed */
+  GTP_ERR_HIP = 3,           /* a HIP runtime call failed */
+  GTP_ERR_NOT_LOADED = 4,    /* library, netlist, events or params missing */
+  GTP_ERR_EVENT_ORDER = 5,   /* time decreases within a gate, or a pin repeats at one time */
+  GTP_ERR_EVENT_RANGE = 6,   /* time outside [0, t_end) or pin above the output pin */
+  GTP_ERR_NOT_TOGGLE = 7,    /* an event sets a pin to the value it already holds */
+  GTP_ERR_UNSUPPORTED = 8,   /* valid input outside the sizes this build handles */
+  GTP_ERR_SCALE_RANGE = 9    /* a leakage scale is negative, not finite or above GTP_MAX_LEAK_SCALE */
+} gtp_status;
+
+/* Leakage scales must lie in [0, GTP_MAX_LEAK_SCALE]; the fixed-point range of
+ * the leakage accumulators is sized from it and the library's largest value. */
+#define GTP_MAX_LEAK_SCALE 16.0f
+
+/* Create a context on HIP device `hip_device`, enqueuing on `hip_stream`. */
+gtp_status gtp_create(gtp_ctx* out, int hip_device, void* hip_stream);
+/* Free every ctx-owned buffer (synchronises the stream first). NULL is a no-op. */
+gtp_status gtp_destroy(gtp_ctx ctx);
+/* Change the stream later calls enqueue on. */
+gtp_status gtp_set_stream(gtp_ctx ctx, void* hip_stream);
+/* Message for the last non-OK status on ctx (never NULL; "" if none). */
+const char* gtp_last_error(gtp_ctx ctx);
+/* Wait for the ctx stream; report a condition flagged by kernels since the
+ * last check (GTP_ERR_SCALE_RANGE) or a HIP error. */
+gtp_status gtp_sync(gtp_ctx ctx);
+
+/*
+ * Cell library (HOST pointers, copied). For cell c with I = n_inputs[c]
+ * input pins (pins 0..I-1; the output is pin I):
+ *   state s = sum_p value(p) * 2^p over the input pins (Sec. 4.1, the
+ *   state-indexed lookup: bit p = input pin p);
+ *   state_to_table[map_base[c] + 2*s + dir] = local table id k of the cell
+ *   for an event with new value dir (1 = rise) at input state s;
+ *   table k: tables_fj[((table_base[c] + k) * n_slew + i) * n_load + j] = energy
+ *   at slew_axis_ps[c*n_slew + i], load_axis_ff[c*n_load + j];
+ *   leak_nw[leak_base[c] + s] = leakage power at state s.
+ * Axes strictly increasing; n_slew, n_load in [2, 16]; I in [1, 8];
+ * leakage values finite and >= 0; every table id in range.
+ * Local table ids may be shared by several (state, dir) pairs.
+ */
+typedef struct {
+  int32_t n_cells, n_slew, n_load;
+  const int32_t* n_inputs;      /* [n_cells] */
+  const float* slew_axis_ps;    /* [n_cells * n_slew] */
+  const float* load_axis_ff;    /* [n_cells * n_load] */
+  const int64_t* map_base;      /* [n_cells] */
+  const int16_t* state_to_table;
+  const int64_t* table_base;    /* [n_cells] */
+  const float* tables_fj;
+  const int64_t* leak_base;     /* [n_cells] */
+  const float* leak_nw;
+  int64_t n_map, n_tables, n_leak; /* lengths of state_to_table, tables (in tables), leak_nw */
+} gtp_library;
+gtp_status gtp_load_library(gtp_ctx ctx, const gtp_library* lib);
+
+/*
+ * Netlist (DEVICE pointers, copied): gate g is an instance of cell
+ * gate_cell[g] driving net gate_out_net[g]; bit p of gate_init_bits[g] is the
+ * initial value of pin p (inputs 0..I-1, output I). Requires a library.
+ */
+gtp_status gtp_load_netlist(gtp_ctx ctx, int64_t n_gates, int64_t n_nets, const int32_t* gate_cell,
+                            const int32_t* gate_out_net, const uint32_t* gate_init_bits);
+
+/*
+ * Toggle events (DEVICE pointers, BORROWED), gate-major: the events of gate g
+ * are [gate_off[g], gate_off[g+1]), sorted by time (events of one gate that
+ * share a time form a group and may come in any order within it).
+ * pin_bit = (pin << 1) | new_value; every event toggles its pin.
+ * Window [0, t_end); every t in it.
+ */
+typedef struct {
+  int64_t n_events, t_end_ps;
+  const int64_t* gate_off;  /* [n_gates + 1], gate_off[0] = 0, gate_off[n_gates] = n_events */
+  const int64_t* t_ps;      /* [n_events] */
+  const uint8_t* pin_bit;   /* [n_events] */
+  const float* slew_ps;     /* [n_events] */
+} gtp_events;
+/* Record the events and (re)build the execution plan. validate = 1 also
+ * checks every event on the device and synchronises: the first offending
+ * event in gate-major order gives GTP_ERR_EVENT_ORDER / _EVENT_RANGE /
+ * _NOT_TOGGLE (its index in gtp_last_error). validate = 0 trusts the input
+ * (invalid events then give unspecified waveforms, never a fault). */
+gtp_status gtp_load_events(gtp_ctx ctx, const gtp_events* ev, int validate);
+/* Index of the event named by the last validation failure, else -1. */
+int64_t gtp_bad_event(gtp_ctx ctx);
+
+/*
+ * Analysis parameters. Bins are half-open [b*bin_ps, (b+1)*bin_ps),
+ * n_bins = ceil(t_end / bin_ps); a partial last bin is still divided by
+ * bin_ps. sw_mode 0: switching energy 0.5*C*V^2 on every output toggle;
+ * sw_mode 1: C*V^2 on an output rise only (the paper's Eq. switching energy).
+ * bin_ps in [1, 2^24].
+ */
+typedef struct {
+  double vdd;
+  int64_t bin_ps;
+  int32_t sw_mode;
+} gtp_params;
+gtp_status gtp_set_params(gtp_ctx ctx, const gtp_params* p);
+gtp_status gtp_num_bins(gtp_ctx ctx, int64_t* n_bins);
+
+/*
+ * Execution choices. algo 0: time-tiled path (contributions bucketed by time
+ * tile, tiles accumulated in LDS); algo 1: one gate per thread with global
+ * atomics (baseline). bins_per_tile_log2 0 = automatic, else 8..13.
+ * Both paths give bit-identical waveforms.
+ */
+typedef struct {
+  int32_t algo;
+  int32_t bins_per_tile_log2;
+} gtp_tuning;
+gtp_status gtp_set_tuning(gtp_ctx ctx, const gtp_tuning* t);
+gtp_status gtp_get_tuning(gtp_ctx ctx, gtp_tuning* t);
+
+/*
+ * Forward: power_mw[b] (DEVICE, [n_bins], FP32) = binned power for net loads
+ * net_load_ff (DEVICE, [n_nets]) and leakage scales leak_scale (DEVICE,
+ * [n_gates]; NULL = all 1). Accumulation is exact int64 fixed point, so the
+ * result does not depend on the execution order.
+ */
+gtp_status gtp_forward(gtp_ctx ctx, const float* net_load_ff, const float* leak_scale, float* power_mw);
+
+/*
+ * Adjoint: given grad_power[b] = dL/dP_b (DEVICE, [n_bins]) writes
+ * grad_net_load[n] = dL/d(net_load_ff[n]) (DEVICE, [n_nets]; nets no gate
+ * drives get 0) and grad_leak_scale[g] = dL/d(leak_scale[g]) (DEVICE,
+ * [n_gates]). Event times and states are not differentiated.
+ */
+gtp_status gtp_adjoint(gtp_ctx ctx, const float* net_load_ff, const float* leak_scale, const float* grad_power,
+                       float* grad_net_load, float* grad_leak_scale);
+
+/*
+ * Per-event trace of the state tracking (DEVICE outputs, [n_events]):
+ * state_before[e] = input state of e's gate before e's timestamp group
+ * (the state every event of the group is looked up with, Algorithm 1),
+ * bin[e] = floor(t_e / bin_ps).
+ */
+gtp_status gtp_debug_event_trace(gtp_ctx ctx, int32_t* state_before, int64_t* bin);
+
+/*
+ * Kernel timing. gtp_profile_enable(ctx, 1) clears earlier records and makes
+ * every later launch of the ctx record a HIP event pair on the ctx stream
+ * around it (0 stops recording). gtp_profile_read synchronises the stream and
+ * writes, for up to cap kernels in first-launch order, the kernel name (owned
+ * by ctx, valid until the next gtp_profile_enable or gtp_destroy), its number
+ * of launches and their summed duration in ms; *n_out = number of kernels.
+ */
+gtp_status gtp_profile_enable(gtp_ctx ctx, int enable);
+gtp_status gtp_profile_read(gtp_ctx ctx, int32_t cap, const char** names, int64_t* launches, double* total_ms,
+                            int32_t* n_out);
+
+/* Bytes of ctx-owned device memory currently allocated. */
+int64_t gtp_device_bytes(gtp_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

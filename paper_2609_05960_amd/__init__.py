@@ -1,0 +1,331 @@
+"""gtpower: binned gate-level power waveforms on MI355X (gfx950).
+
+A thin ctypes binding over the C ABI in ``include/gtpower.h`` (argument
+marshalling only; every step runs in the library's HIP kernels). PyTorch
+provides device memory and the stream. The library must be built first
+(``build()`` or ``__graft_entry__.build()``); importing never falls back to
+any other implementation.
+
+    ctx = Context(device=0)
+    ctx.load_library(lib)                     # host arrays (see Context.load_library)
+    ctx.load_netlist(gate_cell, gate_out, gate_init, n_nets)   # device int32/uint32 tensors
+    ctx.load_events(gate_off, t, pin_bit, slew, t_end)         # device tensors (borrowed)
+    ctx.set_params(vdd=0.8, bin_ps=50)
+    P = ctx.forward(net_load, leak_scale)     # FP32 mW per bin
+    P = binned_power(ctx, net_load, leak_scale)   # differentiable (BinnedPower)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+SO_PATH = os.path.join(_HERE, "libgtpower.so")
+_SRC = os.path.join(_HERE, "csrc", "gtpower.hip")
+
+HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-shared", "-fPIC",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "HIP", 4: "NOT_LOADED", 5: "EVENT_ORDER",
+          6: "EVENT_RANGE", 7: "NOT_TOGGLE", 8: "UNSUPPORTED", 9: "SCALE_RANGE"}
+
+ABI_SYMBOLS = ["gtp_create", "gtp_destroy", "gtp_set_stream", "gtp_last_error", "gtp_sync", "gtp_load_library",
+               "gtp_load_netlist", "gtp_load_events", "gtp_bad_event", "gtp_set_params", "gtp_num_bins",
+               "gtp_set_tuning", "gtp_get_tuning", "gtp_forward", "gtp_adjoint", "gtp_debug_event_trace",
+               "gtp_device_bytes", "gtp_profile_enable", "gtp_profile_read"]
+
+
+def build(out: Optional[str] = None) -> str:
+    """Compile libgtpower.so for gfx950 in-tree with hipcc (always recompiles)."""
+    out = out or SO_PATH
+    tmp = out + ".tmp"
+    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, _SRC]
+    subprocess.check_call(cmd)
+    os.replace(tmp, out)
+    return out
+
+
+class GtpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gtpower {STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class _Library(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int32), ("n_slew", ctypes.c_int32), ("n_load", ctypes.c_int32),
+                ("n_inputs", ctypes.c_void_p), ("slew_axis_ps", ctypes.c_void_p), ("load_axis_ff", ctypes.c_void_p),
+                ("map_base", ctypes.c_void_p), ("state_to_table", ctypes.c_void_p), ("table_base", ctypes.c_void_p),
+                ("tables_fj", ctypes.c_void_p), ("leak_base", ctypes.c_void_p), ("leak_nw", ctypes.c_void_p),
+                ("n_map", ctypes.c_int64), ("n_tables", ctypes.c_int64), ("n_leak", ctypes.c_int64)]
+
+
+class _Events(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_int64), ("t_end_ps", ctypes.c_int64), ("gate_off", ctypes.c_void_p),
+                ("t_ps", ctypes.c_void_p), ("pin_bit", ctypes.c_void_p), ("slew_ps", ctypes.c_void_p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("vdd", ctypes.c_double), ("bin_ps", ctypes.c_int64), ("sw_mode", ctypes.c_int32)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("bins_per_tile_log2", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load libgtpower.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or SO_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is not built: run paper_2609_05960_amd.build() (no CPU fallback exists)")
+    L = ctypes.CDLL(p)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    sig = {
+        "gtp_create": [ctypes.POINTER(vp), i32, vp], "gtp_destroy": [vp], "gtp_set_stream": [vp, vp],
+        "gtp_sync": [vp], "gtp_load_library": [vp, ctypes.POINTER(_Library)],
+        "gtp_load_netlist": [vp, i64, i64, vp, vp, vp], "gtp_load_events": [vp, ctypes.POINTER(_Events), i32],
+        "gtp_set_params": [vp, ctypes.POINTER(_Params)], "gtp_num_bins": [vp, ctypes.POINTER(i64)],
+        "gtp_set_tuning": [vp, ctypes.POINTER(_Tuning)], "gtp_get_tuning": [vp, ctypes.POINTER(_Tuning)],
+        "gtp_forward": [vp, vp, vp, vp], "gtp_adjoint": [vp, vp, vp, vp, vp, vp],
+        "gtp_debug_event_trace": [vp, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.gtp_last_error.argtypes = [vp]
+    L.gtp_last_error.restype = ctypes.c_char_p
+    L.gtp_bad_event.argtypes = [vp]
+    L.gtp_bad_event.restype = i64
+    L.gtp_device_bytes.argtypes = [vp]
+    L.gtp_device_bytes.restype = i64
+    L.gtp_profile_enable.argtypes = [vp, i32]
+    L.gtp_profile_enable.restype = ctypes.c_int
+    L.gtp_profile_read.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i64),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+    L.gtp_profile_read.restype = ctypes.c_int
+    if path is None:
+        _lib = L
+    return L
+
+
+def _dptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    return x.data_ptr()
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Context:
+    """One library context on a HIP device (not thread-safe)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.L = load_library()
+        self.device = torch.device("cuda", device)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        self._chk(self.L.gtp_create(ctypes.byref(h), device, ctypes.c_void_p(s.cuda_stream)), None)
+        self.h = h
+        self._keep = {}
+        self.n_gates = self.n_nets = self.n_events = 0
+        self.n_bins = 0
+
+    def _chk(self, rc, h="self"):
+        if rc != 0:
+            handle = self.h if h == "self" else None
+            msg = self.L.gtp_last_error(handle).decode() if handle else ""
+            raise GtpError(rc, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.gtp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self._chk(self.L.gtp_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def sync(self):
+        self._chk(self.L.gtp_sync(self.h))
+
+    # -- loading ------------------------------------------------------------
+    def load_library(self, lib):
+        """lib: object with n_cells, n_slew, n_load and host arrays n_inputs,
+        slew_axis, load_axis, map_base, state_to_table, table_base, tables,
+        leak_base, leak (the layout of include/gtpower.h gtp_library)."""
+        arrs = dict(n_inputs=_np(lib.n_inputs, np.int32), slew=_np(lib.slew_axis, np.float32),
+                    load=_np(lib.load_axis, np.float32), map_base=_np(lib.map_base, np.int64),
+                    s2t=_np(lib.state_to_table, np.int16), table_base=_np(lib.table_base, np.int64),
+                    tables=_np(lib.tables, np.float32), leak_base=_np(lib.leak_base, np.int64),
+                    leak=_np(lib.leak, np.float32))
+        S = _Library()
+        S.n_cells, S.n_slew, S.n_load = int(lib.n_cells), int(lib.n_slew), int(lib.n_load)
+        S.n_inputs, S.slew_axis_ps, S.load_axis_ff = (arrs[k].ctypes.data for k in ("n_inputs", "slew", "load"))
+        S.map_base, S.state_to_table, S.table_base = (arrs[k].ctypes.data for k in ("map_base", "s2t", "table_base"))
+        S.tables_fj, S.leak_base, S.leak_nw = (arrs[k].ctypes.data for k in ("tables", "leak_base", "leak"))
+        S.n_map = arrs["s2t"].size
+        S.n_tables = arrs["tables"].size // (S.n_slew * S.n_load)
+        S.n_leak = arrs["leak"].size
+        self._chk(self.L.gtp_load_library(self.h, ctypes.byref(S)))
+
+    def load_netlist(self, gate_cell, gate_out_net, gate_init, n_nets: int):
+        t = self.torch
+        gc = gate_cell.to(self.device, t.int32).contiguous()
+        go = gate_out_net.to(self.device, t.int32).contiguous()
+        gi = gate_init.to(self.device, t.int32).contiguous()
+        self._chk(self.L.gtp_load_netlist(self.h, gc.numel(), int(n_nets), _dptr(gc), _dptr(go), _dptr(gi)))
+        self.n_gates, self.n_nets = gc.numel(), int(n_nets)
+
+    def load_events(self, gate_off, t_ps, pin_bit, slew_ps, t_end: int, validate: bool = False):
+        """Device tensors: gate_off int64 [G+1], t int64, pin_bit uint8, slew
+        float32. They are borrowed: this object keeps references to them."""
+        t = self.torch
+        for x, dt in ((gate_off, t.int64), (t_ps, t.int64), (pin_bit, t.uint8), (slew_ps, t.float32)):
+            if x.dtype != dt or not x.is_contiguous() or x.device != self.device:
+                raise ValueError(f"event tensors must be contiguous {dt} on {self.device}")
+        E = _Events()
+        E.n_events, E.t_end_ps = t_ps.numel(), int(t_end)
+        E.gate_off, E.t_ps, E.pin_bit, E.slew_ps = _dptr(gate_off), _dptr(t_ps), _dptr(pin_bit), _dptr(slew_ps)
+        self._keep["events"] = (gate_off, t_ps, pin_bit, slew_ps)
+        rc = self.L.gtp_load_events(self.h, ctypes.byref(E), 1 if validate else 0)
+        if rc != 0:
+            err = GtpError(rc, self.L.gtp_last_error(self.h).decode())
+            err.bad_event = self.L.gtp_bad_event(self.h)
+            raise err
+        self.n_events = t_ps.numel()
+        self.t_end = int(t_end)
+
+    def set_params(self, vdd: float = 0.8, bin_ps: int = 50, sw_mode: int = 0):
+        p = _Params(float(vdd), int(bin_ps), int(sw_mode))
+        self._chk(self.L.gtp_set_params(self.h, ctypes.byref(p)))
+        n = ctypes.c_int64()
+        self._chk(self.L.gtp_num_bins(self.h, ctypes.byref(n)))
+        self.n_bins = n.value
+        self.vdd, self.bin_ps, self.sw_mode = float(vdd), int(bin_ps), int(sw_mode)
+
+    def set_tuning(self, algo: int = 0, bins_per_tile_log2: int = 0):
+        tu = _Tuning(int(algo), int(bins_per_tile_log2))
+        self._chk(self.L.gtp_set_tuning(self.h, ctypes.byref(tu)))
+
+    def get_tuning(self):
+        tu = _Tuning()
+        self._chk(self.L.gtp_get_tuning(self.h, ctypes.byref(tu)))
+        return dict(algo=tu.algo, bins_per_tile_log2=tu.bins_per_tile_log2)
+
+    def device_bytes(self) -> int:
+        return self.L.gtp_device_bytes(self.h)
+
+    def profile(self, enable: bool = True):
+        """Start (clearing earlier records) or stop per-kernel HIP-event timing."""
+        self._chk(self.L.gtp_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel name: (launches, total ms)} since profile(True)."""
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        cnt = (ctypes.c_int64 * cap)()
+        ms = (ctypes.c_double * cap)()
+        n = ctypes.c_int32()
+        self._chk(self.L.gtp_profile_read(self.h, cap, names, cnt, ms, ctypes.byref(n)))
+        return {names[i].decode(): (cnt[i], ms[i]) for i in range(min(n.value, cap))}
+
+    # -- compute ------------------------------------------------------------
+    def _vec(self, x, n, name):
+        t = self.torch
+        if x is None:
+            return None
+        if x.dtype != t.float32 or x.device != self.device or not x.is_contiguous() or x.numel() != n:
+            raise ValueError(f"{name} must be a contiguous float32 tensor of {n} elements on {self.device}")
+        return x
+
+    def forward(self, net_load, leak_scale=None, out=None):
+        net_load = self._vec(net_load, self.n_nets, "net_load")
+        leak_scale = self._vec(leak_scale, self.n_gates, "leak_scale")
+        if out is None:
+            out = self.torch.empty(self.n_bins, dtype=self.torch.float32, device=self.device)
+        self._chk(self.L.gtp_forward(self.h, _dptr(net_load), _dptr(leak_scale), _dptr(out)))
+        return out
+
+    def adjoint(self, net_load, leak_scale, grad_power):
+        net_load = self._vec(net_load, self.n_nets, "net_load")
+        leak_scale = self._vec(leak_scale, self.n_gates, "leak_scale")
+        grad_power = self._vec(grad_power, self.n_bins, "grad_power")
+        t = self.torch
+        gl = t.empty(self.n_nets, dtype=t.float32, device=self.device)
+        gs = t.empty(self.n_gates, dtype=t.float32, device=self.device)
+        self._chk(self.L.gtp_adjoint(self.h, _dptr(net_load), _dptr(leak_scale), _dptr(grad_power), _dptr(gl),
+                                     _dptr(gs)))
+        return gl, gs
+
+    def event_trace(self):
+        t = self.torch
+        st = t.empty(self.n_events, dtype=t.int32, device=self.device)
+        b = t.empty(self.n_events, dtype=t.int64, device=self.device)
+        self._chk(self.L.gtp_debug_event_trace(self.h, _dptr(st), _dptr(b)))
+        return st, b
+
+
+def _binned_power_fn():
+    import torch
+
+    class BinnedPower(torch.autograd.Function):
+        """P = forward(net_load, leak_scale); backward through the library's
+        adjoint kernel. Event times and states are context, not inputs."""
+
+        @staticmethod
+        def forward(actx, ctx: Context, net_load, leak_scale):
+            P = ctx.forward(net_load.detach().contiguous(), leak_scale.detach().contiguous())
+            actx.gtp = ctx
+            actx.save_for_backward(net_load, leak_scale)
+            return P
+
+        @staticmethod
+        def backward(actx, grad_P):
+            net_load, leak_scale = actx.saved_tensors
+            gl, gs = actx.gtp.adjoint(net_load.detach().contiguous(), leak_scale.detach().contiguous(),
+                                      grad_P.detach().to(torch.float32).contiguous())
+            return None, gl, gs
+
+    return BinnedPower
+
+
+_BP = None
+
+
+def binned_power(ctx: Context, net_load, leak_scale):
+    """Differentiable binned power (FP32 mW per bin)."""
+    global _BP
+    if _BP is None:
+        _BP = _binned_power_fn()
+    return _BP.apply(ctx, net_load, leak_scale)
+
+
+def peak_power_loss(P, beta: float):
+    """Smooth peak-power loss (1/beta) * log sum_b exp(beta * P_b)."""
+    import torch
+    return torch.logsumexp(beta * P, dim=0) / beta
+
+
+__all__ = ["Context", "GtpError", "binned_power", "peak_power_loss", "build", "load_library", "SO_PATH",
+           "ABI_SYMBOLS"]

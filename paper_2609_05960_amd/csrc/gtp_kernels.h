@@ -1,0 +1,829 @@
+// Kernels of the binned power-waveform library (gfx950, wave64).
+//
+// Work decomposition. The gate-major event array is cut into lane blocks of
+// kLaneEvents consecutive events. One lane walks one block in order, so the
+// gate state is a running register (each event toggles one pin: the state is
+// the gate's initial bits XOR the parity of the toggles seen so far). A block
+// may hold the tail of one gate and many short gates (sparse gates are packed)
+// or a slice of one long gate (dense gates are cut into many blocks), so work
+// per lane is fixed whatever the per-gate event counts. The plan gives every
+// block its first gate and the toggle parity that gate carries into the block.
+//
+// Order of operations per event follows Algorithm 1 (Sec. 4.3): the events of
+// one gate that share a timestamp are looked up with the state before the
+// group, then applied; leakage is charged in the step form described in
+// gtp_device.h.
+#pragma once
+#include "gtp_device.h"
+
+namespace gtp {
+
+struct EvView {
+  const int64_t* t;
+  const uint8_t* pb;
+  const float* slew;
+  const int64_t* gate_off;
+  int64_t n;        // events
+  int64_t n_gates;
+};
+
+// ---------------------------------------------------------------------------
+// lane-block walker
+// ---------------------------------------------------------------------------
+// Visitor interface:
+//   begin_gate(g, par)  par = parity the gate carries into this block
+//   event(e, t, pin, v, slew, par_group, par_now)
+//   end_gate(g)
+template <class V>
+__device__ __forceinline__ void walk_block(int64_t kb, const EvView& E, const uint2* __restrict__ plan, V& vis) {
+  const int64_t e0 = kb * kLaneEvents;
+  if (e0 >= E.n) return;
+  const int nk = (int)min((int64_t)kLaneEvents, E.n - e0);
+  int64_t tt[kLaneEvents];
+  uint32_t pw[kLaneEvents / 4];
+  float sl[kLaneEvents];
+  if (nk == kLaneEvents) {
+    const longlong2* tp = reinterpret_cast<const longlong2*>(E.t + e0);
+#pragma unroll
+    for (int k = 0; k < kLaneEvents / 2; ++k) {
+      longlong2 v = tp[k];
+      tt[2 * k] = v.x;
+      tt[2 * k + 1] = v.y;
+    }
+    const uint4 p4 = *reinterpret_cast<const uint4*>(E.pb + e0);
+    pw[0] = p4.x; pw[1] = p4.y; pw[2] = p4.z; pw[3] = p4.w;
+    const float4* sp = reinterpret_cast<const float4*>(E.slew + e0);
+#pragma unroll
+    for (int k = 0; k < kLaneEvents / 4; ++k) {
+      float4 v = sp[k];
+      sl[4 * k] = v.x; sl[4 * k + 1] = v.y; sl[4 * k + 2] = v.z; sl[4 * k + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kLaneEvents / 4; ++k) pw[k] = 0;
+#pragma unroll
+    for (int k = 0; k < kLaneEvents; ++k) {
+      if (k < nk) {
+        tt[k] = E.t[e0 + k];
+        pw[k >> 2] |= (uint32_t)E.pb[e0 + k] << (8 * (k & 3));
+        sl[k] = E.slew[e0 + k];
+      } else {
+        tt[k] = 0;
+        sl[k] = 0.f;
+      }
+    }
+  }
+  const uint2 pl = plan[kb];
+  int64_t g = (int64_t)pl.x;
+  uint32_t par = pl.y;
+  int64_t gstart = E.gate_off[g];
+  int64_t next_off = E.gate_off[g + 1];
+  // A timestamp group may straddle the block start: the group-start parity
+  // then excludes the group's earlier events (looked back in memory).
+  uint32_t par_gs = par;
+  int64_t tprev = INT64_MIN;
+  if (e0 > gstart && E.t[e0 - 1] == tt[0]) {
+    uint32_t x = 0;
+    int64_t j = e0 - 1;
+    int guard = 0;
+    while (j >= gstart && E.t[j] == tt[0] && guard < 64) {
+      x ^= 1u << ((E.pb[j] >> 1) & 31);
+      --j;
+      ++guard;
+    }
+    par_gs = par ^ x;
+    tprev = tt[0];
+  }
+  vis.begin_gate(g, par);
+#pragma unroll
+  for (int k = 0; k < kLaneEvents; ++k) {
+    if (k < nk) {
+      const int64_t e = e0 + k;
+      if (e >= next_off) {
+        vis.end_gate(g);
+        while (e >= next_off && g < E.n_gates - 1) {
+          ++g;
+          next_off = E.gate_off[g + 1];
+        }
+        par = 0;
+        tprev = INT64_MIN;
+        vis.begin_gate(g, 0u);
+      }
+      const uint32_t b = (pw[k >> 2] >> (8 * (k & 3))) & 0xffu;
+      const int pin = (int)(b >> 1);
+      const int v = (int)(b & 1u);
+      if (tt[k] != tprev) {
+        par_gs = par;
+        tprev = tt[k];
+      }
+      vis.event(e, tt[k], pin, v, sl[k], par_gs, par);
+      par ^= 1u << (pin & 31);
+    }
+  }
+  vis.end_gate(g);
+}
+
+// Lookup and energy of one event (shared by every path so results agree bit
+// for bit). Updates the running quantised leakage rate q_cur.
+struct GateCtx {
+  GatePrep gp;
+  CellMeta cm;
+  uint32_t in_mask;
+  int32_t q_cur;
+};
+
+__device__ __forceinline__ void gate_begin(GateCtx& G, const GatePrep* __restrict__ gprep, const LdsLib& L, int64_t g,
+                                           uint32_t par, float scale_k) {
+  const int4* src = reinterpret_cast<const int4*>(gprep + g);
+  int4 a = src[0], b = src[1];
+  G.gp.cell = a.x; G.gp.init = (uint32_t)a.y; G.gp.jq = a.z; G.gp.beta = __int_as_float(a.w);
+  G.gp.esw_rise = __int_as_float(b.x); G.gp.esw_fall = __int_as_float(b.y);
+  G.gp.lam = __int_as_float(b.z); G.gp.dbeta_dc = __int_as_float(b.w);
+  G.cm = L.meta[G.gp.cell];
+  G.in_mask = (1u << G.cm.n_in) - 1u;
+  const uint32_t s = (G.gp.init ^ par) & G.in_mask;
+  G.q_cur = qrate(G.gp.lam, L.leak[G.cm.leak_off + (int)s], scale_k);
+}
+
+struct LutArgs {
+  const float4* __restrict__ quads;
+  int32_t n_slew, n_load;
+  float scale_k;
+};
+
+__device__ __forceinline__ EventOut event_energy(GateCtx& G, const LdsLib& L, const LutArgs& A, int pin, int v,
+                                                 float slew, uint32_t par_gs, uint32_t par) {
+  EventOut o;
+  const uint32_t s = (G.gp.init ^ par_gs) & G.in_mask;
+  const int32_t qb = L.map_q[G.cm.map_off + 2 * (int)s + v];
+  int i;
+  float alpha;
+  slew_segment(L.slew + G.cm.axis_off, L.slew_inv + G.cm.axis_off, A.n_slew, slew, i, alpha);
+  const float4 q = A.quads[qb + i * (A.n_load - 1) + G.gp.jq];
+  float e = bilerp_quad(q, alpha, G.gp.beta);
+  if (pin == G.cm.n_in) e = __fadd_rn(e, v ? G.gp.esw_rise : G.gp.esw_fall);
+  int32_t delta = 0;
+  if (pin < G.cm.n_in) {
+    const uint32_t s_new = (G.gp.init ^ par ^ (1u << pin)) & G.in_mask;
+    const int32_t qn = qrate(G.gp.lam, L.leak[G.cm.leak_off + (int)s_new], A.scale_k);
+    delta = qn - G.q_cur;
+    G.q_cur = qn;
+  }
+  o.e = e;
+  o.delta = delta;
+  o.s = (int32_t)s;
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// forward, time-tiled path
+// ---------------------------------------------------------------------------
+struct FwdArgs {
+  EvView ev;
+  const uint2* plan;
+  const GatePrep* gprep;
+  LibView lib;
+  LutArgs lut;
+  BinSpec bins;
+  int64_t group_events;     // events per workgroup (multiple of kSubChunk)
+  const uint32_t* off_gm;   // [n_groups][n_tiles] first record slot
+  uint3* rec;               // records (loc, energy bits, leakage step)
+  int64_t n_rec;
+  int32_t* dbg_state;       // optional per-event trace
+  int64_t* dbg_bin;
+};
+
+struct FwdVisitor {
+  const FwdArgs* A;
+  const LdsLib* L;
+  uint32_t* cursor;
+  GateCtx G;
+  __device__ __forceinline__ void begin_gate(int64_t g, uint32_t par) {
+    gate_begin(G, A->gprep, *L, g, par, A->lut.scale_k);
+  }
+  __device__ __forceinline__ void end_gate(int64_t) {}
+  __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
+                                        uint32_t par) {
+    const EventOut o = event_energy(G, *L, A->lut, pin, v, slew, par_gs, par);
+    const BinSpec& B = A->bins;
+    if (t < 0 || t >= B.t_end) return;  // invalid input: dropped (the plan drops it too)
+    const int64_t b = bin_of(t, B);
+    if (A->dbg_state) {
+      A->dbg_state[e] = o.s;
+      A->dbg_bin[e] = b;
+    }
+    const uint32_t r = (uint32_t)(t - b * B.D);
+    const uint32_t tile = (uint32_t)(b >> B.tile_log2);
+    const uint32_t loc = (((uint32_t)b & ((1u << B.tile_log2) - 1u)) << B.r_bits) | r;
+    const uint32_t pos = atomicAdd(&cursor[tile], 1u);
+    if ((int64_t)pos < A->n_rec) A->rec[pos] = make_uint3(loc, __float_as_uint(o.e), (uint32_t)o.delta);
+  }
+};
+
+__global__ void __launch_bounds__(kFwdThreads) k_fwd_records(FwdArgs a) {
+  extern __shared__ uint32_t lds[];
+  const LdsLib L = stage_library(a.lib, lds);
+  uint32_t* cursor = lds + a.lib.lds_words;
+  const int64_t grp = blockIdx.x;
+  for (int b = threadIdx.x; b < a.bins.n_tiles; b += blockDim.x) cursor[b] = a.off_gm[grp * a.bins.n_tiles + b];
+  __syncthreads();
+  FwdVisitor vis;
+  vis.A = &a;
+  vis.L = &L;
+  vis.cursor = cursor;
+  const int64_t g0 = grp * a.group_events;
+  const int64_t g1 = min(a.ev.n, g0 + a.group_events);
+  for (int64_t sub = g0; sub < g1; sub += kSubChunk) walk_block(sub / kLaneEvents + threadIdx.x, a.ev, a.plan, vis);
+}
+
+// Per tile: accumulate its records into LDS bins, then store the tile.
+struct TileArgs {
+  const uint3* rec;
+  const uint32_t* tile_off;  // [n_tiles + 1]
+  int64_t* X;
+  int64_t* S;
+  BinSpec bins;
+  double dyn_scale;          // 2^k * 1e6: fJ -> units of 2^-k nW*ps
+};
+
+__global__ void __launch_bounds__(kTileThreads) k_tile_accum(TileArgs a) {
+  extern __shared__ unsigned long long tl[];
+  const int nb = 1 << a.bins.tile_log2;
+  unsigned long long* xs = tl;
+  unsigned long long* ss = tl + nb;
+  for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) tl[i] = 0ull;
+  __syncthreads();
+  const int64_t tile = blockIdx.x;
+  const int64_t r0 = a.tile_off[tile], r1 = a.tile_off[tile + 1];
+  const uint32_t rmask = (1u << a.bins.r_bits) - 1u;
+  const int64_t D = a.bins.D;
+  constexpr int U = 4;
+  int64_t r = r0 + threadIdx.x;
+  for (; r + (U - 1) * kTileThreads < r1; r += U * kTileThreads) {
+    uint3 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = a.rec[r + u * kTileThreads];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t bl = (v[u].x >> a.bins.r_bits) & (uint32_t)(nb - 1);
+      const int64_t rr = (int64_t)(v[u].x & rmask);
+      const int32_t d = (int32_t)v[u].z;
+      const int64_t x = dyn_fixed(__uint_as_float(v[u].y), a.dyn_scale) + (int64_t)d * (D - rr);
+      atomicAdd(&xs[bl], (unsigned long long)x);
+      if (d != 0) atomicAdd(&ss[bl], (unsigned long long)(int64_t)d);
+    }
+  }
+  for (; r < r1; r += kTileThreads) {
+    const uint3 v = a.rec[r];
+    const uint32_t bl = (v.x >> a.bins.r_bits) & (uint32_t)(nb - 1);
+    const int64_t rr = (int64_t)(v.x & rmask);
+    const int32_t d = (int32_t)v.z;
+    const int64_t x = dyn_fixed(__uint_as_float(v.y), a.dyn_scale) + (int64_t)d * (D - rr);
+    atomicAdd(&xs[bl], (unsigned long long)x);
+    if (d != 0) atomicAdd(&ss[bl], (unsigned long long)(int64_t)d);
+  }
+  __syncthreads();
+  const int64_t b0 = tile * nb;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    if (b0 + i < a.bins.n_bins) {
+      a.X[b0 + i] = (int64_t)xs[i];
+      a.S[b0 + i] = (int64_t)ss[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward, one gate per thread (baseline): global int64 atomics per event
+// ---------------------------------------------------------------------------
+struct SerialArgs {
+  EvView ev;
+  const GatePrep* gprep;
+  LibView lib;
+  LutArgs lut;
+  BinSpec bins;
+  unsigned long long* X;
+  unsigned long long* S;
+  double dyn_scale;
+};
+
+__global__ void __launch_bounds__(kFwdThreads) k_gate_serial(SerialArgs a) {
+  extern __shared__ uint32_t lds[];
+  const LdsLib L = stage_library(a.lib, lds);
+  __syncthreads();
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.ev.n_gates) return;
+  const int64_t e0 = a.ev.gate_off[g], e1 = a.ev.gate_off[g + 1];
+  if (e1 <= e0) return;
+  GateCtx G;
+  gate_begin(G, a.gprep, L, g, 0u, a.lut.scale_k);
+  uint32_t par = 0, par_gs = 0;
+  int64_t tprev = INT64_MIN;
+  const BinSpec& B = a.bins;
+  for (int64_t e = e0; e < e1; ++e) {
+    const int64_t t = a.ev.t[e];
+    const uint32_t b8 = a.ev.pb[e];
+    const int pin = (int)(b8 >> 1), v = (int)(b8 & 1u);
+    if (t != tprev) {
+      par_gs = par;
+      tprev = t;
+    }
+    const EventOut o = event_energy(G, L, a.lut, pin, v, a.ev.slew[e], par_gs, par);
+    par ^= 1u << (pin & 31);
+    if (t < 0 || t >= B.t_end) continue;
+    const int64_t b = bin_of(t, B);
+    const int64_t rr = t - b * B.D;
+    const int64_t x = dyn_fixed(o.e, a.dyn_scale) + (int64_t)o.delta * (B.D - rr);
+    atomicAdd(&a.X[b], (unsigned long long)x);
+    if (o.delta != 0) atomicAdd(&a.S[b], (unsigned long long)(int64_t)o.delta);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gate preparation (per call): load interpolation, switching energy, scale
+// ---------------------------------------------------------------------------
+struct PrepArgs {
+  const int32_t* gate_cell;
+  const int32_t* gate_out;
+  const uint32_t* gate_init;
+  const float* net_load;
+  const float* leak_scale;   // may be null (all 1)
+  const CellMeta* meta;
+  const float* leak;
+  const float* load;         // [n_cells * n_load]
+  const float* load_inv;
+  int32_t n_load;
+  int64_t n_gates;
+  double vdd;
+  int32_t sw_mode;
+  float scale_k;
+  float max_scale;
+  GatePrep* out;
+  unsigned long long* L0;    // sum of quantised initial leakage rates
+  int32_t* flag;             // bit 0: a leakage scale out of range
+};
+
+__global__ void __launch_bounds__(256) k_gate_prep(PrepArgs a) {
+  __shared__ long long red[256];
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  long long q0 = 0;
+  if (g < a.n_gates) {
+    const int32_t c = a.gate_cell[g];
+    const CellMeta cm = a.meta[c];
+    const float C = a.net_load[a.gate_out[g]];
+    float lam = a.leak_scale ? a.leak_scale[g] : 1.0f;
+    if (!(lam >= 0.0f && lam <= a.max_scale)) {
+      atomicOr(a.flag, 1);
+      lam = 0.0f;
+    }
+    const float* la = a.load + (int64_t)c * a.n_load;
+    int j = 0;
+    for (int m = 1; m < a.n_load - 1; ++m) j += (la[m] <= C) ? 1 : 0;
+    const float inv = a.load_inv[(int64_t)c * a.n_load + j];
+    GatePrep p;
+    p.cell = c;
+    p.init = a.gate_init[g];
+    p.jq = j;
+    p.beta = __fmul_rn(__fsub_rn(C, la[j]), inv);
+    const double v2 = a.vdd * a.vdd;
+    if (a.sw_mode == 0) {
+      p.esw_rise = (float)(0.5 * (double)C * v2);
+      p.esw_fall = p.esw_rise;
+    } else {
+      p.esw_rise = (float)((double)C * v2);
+      p.esw_fall = 0.0f;
+    }
+    p.lam = lam;
+    p.dbeta_dc = inv;
+    a.out[g] = p;
+    const uint32_t s0 = p.init & ((1u << cm.n_in) - 1u);
+    q0 = (long long)qrate(lam, a.leak[cm.leak_off + (int)s0], a.scale_k);
+  }
+  red[threadIdx.x] = q0;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != 0) atomicAdd(a.L0, (unsigned long long)red[0]);
+}
+
+// ---------------------------------------------------------------------------
+// finalize: P_b = (X[b] + D * (L0 + sum_{b'<b} S[b'])) * 2^-k * 1e-6 / D
+// ---------------------------------------------------------------------------
+struct FinArgs {
+  const int64_t* X;
+  const int64_t* S;
+  const int64_t* exS;   // exclusive prefix of S
+  const unsigned long long* L0;
+  float* P;
+  int64_t n_bins, D, t_end;
+  double out_scale;     // 2^-k * 1e-6 / D
+};
+
+__global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.n_bins) return;
+  const int64_t R = (int64_t)*a.L0 + a.exS[b];
+  int64_t E;
+  if (b == a.n_bins - 1 && a.n_bins * a.D != a.t_end) {
+    const int64_t w = a.t_end - b * a.D;
+    E = a.X[b] - a.S[b] * (a.n_bins * a.D - a.t_end) + w * R;
+  } else {
+    E = a.X[b] + a.D * R;
+  }
+  a.P[b] = (float)((double)E * a.out_scale);
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+// Per bin: w_b = g_b / D (the density of dL/dP over time) and the suffix
+// integral G_b = sum_{b' > b} w_b' * width_b' (width D, the last bin its
+// partial width). For a leakage step of size d (nW, unscaled) at time t in
+// bin b, d(loss)/d(lambda) gains 1e-6 * d * (w_b * (end_b - t) + G_b), with
+// end_b = min((b+1) D, t_end): the integral of w from t to the end of the
+// window. Each event adds w_b * dE/dC to its gate's load gradient.
+struct AdjArgs {
+  EvView ev;
+  const uint2* plan;
+  const GatePrep* gprep;
+  const int32_t* gate_out;
+  LibView lib;
+  LutArgs lut;
+  BinSpec bins;
+  const double2* wg;   // [n_bins] (w_b, G_b)
+  float dsw_rise, dsw_fall;  // d(switching energy)/dC
+  double* gC;          // [n_nets]
+  double* gL;          // [n_gates] (sum of d * integral, without the 1e-6)
+};
+
+struct AdjVisitor {
+  const AdjArgs* A;
+  const LdsLib* L;
+  GateCtx G;
+  uint32_t s_cur;
+  double acc_c, acc_l;
+  __device__ __forceinline__ void begin_gate(int64_t g, uint32_t par) {
+    gate_begin(G, A->gprep, *L, g, par, A->lut.scale_k);
+    s_cur = (G.gp.init ^ par) & G.in_mask;
+    acc_c = 0.0;
+    acc_l = 0.0;
+  }
+  __device__ __forceinline__ void end_gate(int64_t g) {
+    if (acc_c != 0.0) unsafeAtomicAdd(&A->gC[A->gate_out[g]], acc_c);
+    if (acc_l != 0.0) unsafeAtomicAdd(&A->gL[g], acc_l);
+    acc_c = 0.0;
+    acc_l = 0.0;
+  }
+  __device__ __forceinline__ void event(int64_t, int64_t t, int pin, int v, float slew, uint32_t par_gs,
+                                        uint32_t par) {
+    const BinSpec& B = A->bins;
+    const uint32_t s_new = (G.gp.init ^ par ^ (1u << (pin & 31))) & G.in_mask;
+    if (t < 0 || t >= B.t_end) {  // invalid input: dropped, state still tracked
+      if (pin < G.cm.n_in) s_cur = s_new;
+      return;
+    }
+    const int64_t b = bin_of(t, B);
+    const double2 wg = A->wg[b];
+    const uint32_t s = (G.gp.init ^ par_gs) & G.in_mask;
+    const int32_t qb = L->map_q[G.cm.map_off + 2 * (int)s + v];
+    int i;
+    float alpha;
+    slew_segment(L->slew + G.cm.axis_off, L->slew_inv + G.cm.axis_off, A->lut.n_slew, slew, i, alpha);
+    const float4 q = A->lut.quads[qb + i * (A->lut.n_load - 1) + G.gp.jq];
+    float dedc = __fmul_rn(bilerp_dbeta(q, alpha), G.gp.dbeta_dc);
+    if (pin == G.cm.n_in) dedc = __fadd_rn(dedc, v ? A->dsw_rise : A->dsw_fall);
+    acc_c += wg.x * (double)dedc;
+    if (pin < G.cm.n_in) {
+      const double d = (double)L->leak[G.cm.leak_off + (int)s_new] - (double)L->leak[G.cm.leak_off + (int)s_cur];
+      const int64_t end_b = min((b + 1) * B.D, B.t_end);
+      acc_l += d * (wg.x * (double)(end_b - t) + wg.y);
+      s_cur = s_new;
+    }
+  }
+};
+
+__global__ void __launch_bounds__(kFwdThreads) k_adjoint_events(AdjArgs a) {
+  extern __shared__ uint32_t lds[];
+  const LdsLib L = stage_library(a.lib, lds);
+  __syncthreads();
+  AdjVisitor vis;
+  vis.A = &a;
+  vis.L = &L;
+  const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  walk_block(kb, a.ev, a.plan, vis);
+}
+
+struct AdjBinArgs {
+  const float* gP;
+  double* c;       // w_b * width_b
+  double* wgtmp;   // w_b
+  int64_t n_bins, D, t_end;
+};
+
+__global__ void __launch_bounds__(256) k_adj_bins(AdjBinArgs a) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.n_bins) return;
+  const double w = (double)a.gP[b] / (double)a.D;
+  const int64_t width = min((b + 1) * a.D, a.t_end) - b * a.D;
+  a.wgtmp[b] = w;
+  a.c[b] = w * (double)width;
+}
+
+__global__ void __launch_bounds__(256) k_adj_suffix(const double* w, const double* c, const double* exc, double2* wg,
+                                                     double* total, int64_t n_bins) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_bins) return;
+  const double tot = exc[n_bins - 1] + c[n_bins - 1];
+  wg[b] = make_double2(w[b], tot - (exc[b] + c[b]));
+  if (b == 0) *total = tot;
+}
+
+struct AdjOutArgs {
+  const double* gC;
+  const double* gL;
+  const double* total;      // integral of w over the window
+  const int32_t* gate_cell;
+  const uint32_t* gate_init;
+  const CellMeta* meta;
+  const float* leak;
+  float* grad_load;
+  float* grad_scale;
+  int64_t n_nets, n_gates;
+};
+
+__global__ void __launch_bounds__(256) k_adj_out(AdjOutArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.n_nets) a.grad_load[i] = (float)a.gC[i];
+  if (i < a.n_gates) {
+    const CellMeta cm = a.meta[a.gate_cell[i]];
+    const uint32_t s0 = a.gate_init[i] & ((1u << cm.n_in) - 1u);
+    const double base = (double)a.leak[cm.leak_off + (int)s0] * *a.total;
+    a.grad_scale[i] = (float)(1e-6 * (base + a.gL[i]));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// validation: first offending event in gate-major order
+// ---------------------------------------------------------------------------
+// Codes ranked by the order the checks are made on one event: time range,
+// time order, pin range, pin repeated within a timestamp group, not a toggle.
+struct ValArgs {
+  EvView ev;
+  const uint2* plan;
+  const int32_t* gate_cell;
+  const uint32_t* gate_init;
+  const CellMeta* meta;
+  int64_t t_end;
+  unsigned long long* first;   // min over (event << 3 | code)
+};
+
+struct ValVisitor {
+  const ValArgs* A;
+  uint32_t init;
+  int n_in;
+  int64_t gstart;
+  unsigned long long best;
+  __device__ __forceinline__ void begin_gate(int64_t g, uint32_t) {
+    init = A->gate_init[g];
+    n_in = A->meta[A->gate_cell[g]].n_in;
+    gstart = A->ev.gate_off[g];
+  }
+  __device__ __forceinline__ void end_gate(int64_t) {}
+  __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float, uint32_t, uint32_t par) {
+    int code = 0;
+    if (t < 0 || t >= A->t_end) code = 1;
+    else if (e > gstart && A->ev.t[e - 1] > t) code = 2;
+    else if (pin > n_in) code = 3;
+    else {
+      // same pin earlier in this timestamp group (a valid group has at most n_in + 1 events)
+      int64_t j = e - 1;
+      for (int k = 0; k < 17 && j >= gstart && A->ev.t[j] == t; ++k, --j)
+        if ((A->ev.pb[j] >> 1) == pin) { code = 4; break; }
+      if (code == 0 && (int)(((init ^ par) >> pin) & 1u) == v) code = 5;
+    }
+    if (code) {
+      const unsigned long long key = ((unsigned long long)e << 3) | (unsigned long long)code;
+      if (key < best) best = key;
+    }
+  }
+};
+
+__global__ void __launch_bounds__(kFwdThreads) k_validate(ValArgs a) {
+  ValVisitor vis;
+  vis.A = &a;
+  vis.best = ~0ull;
+  const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  walk_block(kb, a.ev, a.plan, vis);
+  if (vis.best != ~0ull) atomicMin(a.first, vis.best);
+}
+
+// per-event trace without the tiled records (one lane block per thread)
+struct TraceArgs {
+  EvView ev;
+  const uint2* plan;
+  const GatePrep* gprep;
+  LibView lib;
+  LutArgs lut;
+  BinSpec bins;
+  int32_t* state;
+  int64_t* bin;
+};
+
+struct TraceVisitor {
+  const TraceArgs* A;
+  const LdsLib* L;
+  GateCtx G;
+  __device__ __forceinline__ void begin_gate(int64_t g, uint32_t par) {
+    gate_begin(G, A->gprep, *L, g, par, A->lut.scale_k);
+  }
+  __device__ __forceinline__ void end_gate(int64_t) {}
+  __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
+                                        uint32_t par) {
+    const EventOut o = event_energy(G, *L, A->lut, pin, v, slew, par_gs, par);
+    A->state[e] = o.s;
+    A->bin[e] = (t >= 0 && t < A->bins.t_end) ? bin_of(t, A->bins) : -1;
+  }
+};
+
+__global__ void __launch_bounds__(kFwdThreads) k_event_trace(TraceArgs a) {
+  extern __shared__ uint32_t lds[];
+  const LdsLib L = stage_library(a.lib, lds);
+  __syncthreads();
+  TraceVisitor vis;
+  vis.A = &a;
+  vis.L = &L;
+  const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  walk_block(kb, a.ev, a.plan, vis);
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+// Block b (events [16b, 16b+16)): its first gate, by binary search of the CSR
+// offsets for the last gate starting at or before the block's first event.
+__global__ void __launch_bounds__(256) k_plan_block_gate(const int64_t* gate_off, int64_t n_gates, int64_t n_events,
+                                                         uint2* plan, int64_t n_blocks) {
+  const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (kb >= n_blocks) return;
+  const int64_t e0 = kb * kLaneEvents;
+  int64_t lo = 0, hi = n_gates;  // invariant: gate_off[lo] <= e0 < gate_off[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (gate_off[mid] <= e0) lo = mid; else hi = mid;
+  }
+  plan[kb] = make_uint2((uint32_t)lo, 0u);
+}
+
+// XOR of the toggle masks of a block's events.
+__global__ void __launch_bounds__(256) k_plan_block_xor(const uint8_t* pb, int64_t n_events, uint32_t* bx,
+                                                        int64_t n_blocks) {
+  const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (kb >= n_blocks) return;
+  const int64_t e0 = kb * kLaneEvents, e1 = min(e0 + kLaneEvents, n_events);
+  uint32_t x = 0;
+  for (int64_t e = e0; e < e1; ++e) x ^= 1u << ((pb[e] >> 1) & 31);
+  bx[kb] = x;
+}
+
+// Carried parity: with P(x) the XOR of all toggle masks before event x (any
+// gate), the parity gate g carries into block b is P(16b) ^ P(gate_off[g]):
+// the events of earlier gates cancel.
+__global__ void __launch_bounds__(256) k_plan_block_carry(const int64_t* gate_off, const uint8_t* pb,
+                                                          const uint32_t* bpre, uint2* plan, int64_t n_blocks) {
+  const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (kb >= n_blocks) return;
+  const int64_t e0 = kb * kLaneEvents;
+  const uint32_t g = plan[kb].x;
+  const int64_t gs = gate_off[g];
+  uint32_t carry = 0;
+  if (gs < e0) {
+    const int64_t kb0 = gs / kLaneEvents;
+    uint32_t p = bpre[kb0];
+    for (int64_t e = kb0 * kLaneEvents; e < gs; ++e) p ^= 1u << ((pb[e] >> 1) & 31);
+    carry = bpre[kb] ^ p;
+  }
+  plan[kb].y = carry;
+}
+
+// Records per (tile, workgroup group), tile-major, for the placement scan.
+__global__ void __launch_bounds__(256) k_plan_count(const int64_t* t, int64_t n_events, BinSpec bins,
+                                                    int64_t group_events, int64_t n_groups, uint32_t* cnt_tm) {
+  extern __shared__ uint32_t hist[];
+  for (int i = threadIdx.x; i < bins.n_tiles; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int64_t grp = blockIdx.x;
+  const int64_t e0 = grp * group_events, e1 = min(n_events, e0 + group_events);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int64_t tv = t[e];
+    if (tv < 0 || tv >= bins.t_end) continue;
+    const int64_t b = bin_of(tv, bins);
+    atomicAdd(&hist[(uint32_t)(b >> bins.tile_log2)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < bins.n_tiles; i += blockDim.x) cnt_tm[(int64_t)i * n_groups + grp] = hist[i];
+}
+
+__global__ void __launch_bounds__(256) k_plan_tile_off(const uint32_t* off_tm, int64_t n_groups, int32_t n_tiles,
+                                                       uint32_t n_rec, uint32_t* tile_off) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_tiles) tile_off[i] = off_tm[i * n_groups];
+  if (i == n_tiles) tile_off[i] = n_rec;
+}
+
+__global__ void __launch_bounds__(256) k_plan_transpose(const uint32_t* off_tm, uint32_t* off_gm, int64_t n_groups,
+                                                        int32_t n_tiles) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_groups * (int64_t)n_tiles) return;
+  const int64_t grp = i / n_tiles, tile = i - grp * n_tiles;
+  off_gm[i] = off_tm[tile * n_groups + grp];
+}
+
+// ---------------------------------------------------------------------------
+// utilities
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Exclusive scan, three passes: per tile (kScanTile items) local scan and
+// total; scan of tile totals by one workgroup; add the tile prefix.
+struct OpAdd {
+  template <class T>
+  __device__ __forceinline__ T operator()(T a, T b) const { return a + b; }
+};
+struct OpXor {
+  template <class T>
+  __device__ __forceinline__ T operator()(T a, T b) const { return a ^ b; }
+};
+
+template <class T, class Op>
+__device__ __forceinline__ T block_exclusive(T v, T ident, Op op, T* sh, T& total) {
+  // Hillis-Steele over kScanThreads values in LDS
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    T x = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : ident;
+    __syncthreads();
+    if (threadIdx.x >= (unsigned)off) sh[threadIdx.x] = op(x, sh[threadIdx.x]);
+    __syncthreads();
+  }
+  const T excl = threadIdx.x == 0 ? ident : sh[threadIdx.x - 1];
+  total = sh[kScanThreads - 1];
+  __syncthreads();
+  return excl;
+}
+
+template <class T, class Op>
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const T* in, T* out, T* sums, int64_t n, T ident, Op op) {
+  __shared__ T sh[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  T loc[kScanItems];
+  T acc = ident;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const T x = (base + k < n) ? in[base + k] : ident;
+    loc[k] = acc;
+    acc = op(acc, x);
+  }
+  T total;
+  const T pre = block_exclusive(acc, ident, op, sh, total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) out[base + k] = op(pre, loc[k]);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+template <class T, class Op>
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(T* sums, int64_t n, T ident, Op op) {
+  __shared__ T sh[kScanThreads];
+  T carry = ident;
+  for (int64_t base0 = 0; base0 < n; base0 += kScanTile) {
+    const int64_t base = base0 + (int64_t)threadIdx.x * kScanItems;
+    T loc[kScanItems];
+    T acc = ident;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const T x = (base + k < n) ? sums[base + k] : ident;
+      loc[k] = acc;
+      acc = op(acc, x);
+    }
+    T total;
+    const T pre = block_exclusive(acc, ident, op, sh, total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+      if (base + k < n) sums[base + k] = op(carry, op(pre, loc[k]));
+    carry = op(carry, total);
+    __syncthreads();
+  }
+}
+
+template <class T, class Op>
+__global__ void __launch_bounds__(256) k_scan_add(T* out, const T* sums, int64_t n, Op op) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = op(sums[i / kScanTile], out[i]);
+}
+
+}  // namespace gtp

@@ -1,0 +1,945 @@
+// Host side of the C ABI declared in include/gtpower.h.
+//
+// Call flow of one forward (all on the ctx stream, asynchronous):
+//   k_gate_prep      per gate: load-axis segment and weight, switching
+//                    energies, leakage scale; sum of initial leakage rates
+//   algo 0 (time-tiled):
+//     k_fwd_records  per workgroup of consecutive lane blocks: every event's
+//                    energy and leakage step, written as a 12-byte record into
+//                    the slot range of its time tile (slots from the plan)
+//     k_tile_accum   per time tile: records accumulated into LDS bins (int64),
+//                    tile stored
+//   algo 1 (baseline):
+//     k_gate_serial  one gate per thread, global int64 atomics per event
+//   scan of S, k_finalize -> FP32 power per bin
+// The plan (lane-block gates and carried parities; record slots per time
+// tile) depends only on the event times and pins and on the bin width, so it
+// is built once per gtp_load_events / gtp_set_params.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gtpower.h"
+#include "gtp_kernels.h"
+
+using namespace gtp;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct gtp_ctx_s {
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int64_t bad_event = -1;
+  std::vector<DevBuf*> bufs;
+  int64_t dev_bytes = 0;
+
+  // library
+  bool lib_ok = false;
+  int32_t n_cells = 0, n_slew = 0, n_load = 0, n_map = 0, n_leak = 0;
+  int64_t n_tables = 0;
+  int32_t lds_words = 0;
+  int32_t kfix = 16;          // fixed-point exponent
+  std::vector<int32_t> h_nin;
+  DevBuf lib_img;             // meta | map_q | leak | slew | slew_inv
+  DevBuf load_axis, load_inv, quads;
+
+  // netlist
+  bool net_ok = false;
+  int64_t n_gates = 0, n_nets = 0;
+  DevBuf gate_cell, gate_out, gate_init;
+
+  // events
+  bool ev_ok = false;
+  gtp_events ev{};
+  int64_t n_blocks = 0;
+  DevBuf plan_blk, blk_tmp, blk_tmp2, scan_sums;
+
+  // params
+  bool par_ok = false;
+  gtp_params par{};
+  BinSpec bins{};
+
+  // tuning + tile plan
+  gtp_tuning tun{0, 0};
+  bool tiles_ok = false;
+  int64_t group_events = 0, n_groups = 0;
+  DevBuf cnt_tm, off_tm, off_gm, tile_off, rec;
+
+  // kernel timing (gtp_profile_enable)
+  bool prof_on = false;
+  std::vector<std::string> prof_names;
+  struct ProfRec { int id; hipEvent_t a, b; };
+  std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> prof_pool;
+  int prof_open = -1;
+  hipEvent_t prof_a = nullptr;
+
+  // per-call work buffers
+  DevBuf gprep, X, S, exS, L0, flag, first_bad;
+  DevBuf adj_w, adj_c, adj_exc, adj_wg, adj_total, gC, gL;
+};
+
+namespace {
+
+gtp_status fail(gtp_ctx c, gtp_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                                          \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess) return fail((ctx), GTP_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCHCHK(ctx, name)                                                                                     \
+  do {                                                                                                           \
+    hipError_t e_ = hipGetLastError();                                                                           \
+    if (e_ != hipSuccess) return fail((ctx), GTP_ERR_HIP, "launch of %s failed: %s", name, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRY(...)                     \
+  do {                               \
+    gtp_status s_ = (__VA_ARGS__);   \
+    if (s_ != GTP_OK) return s_;     \
+  } while (0)
+
+hipEvent_t prof_event(gtp_ctx c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+void prof_begin(gtp_ctx c, const char* name) {
+  if (!c->prof_on) return;
+  int id = -1;
+  for (size_t i = 0; i < c->prof_names.size(); ++i)
+    if (c->prof_names[i] == name) id = (int)i;
+  if (id < 0) {
+    id = (int)c->prof_names.size();
+    c->prof_names.push_back(name);
+  }
+  c->prof_open = id;
+  c->prof_a = prof_event(c);
+  if (c->prof_a) (void)hipEventRecord(c->prof_a, c->stream);
+}
+
+void prof_end(gtp_ctx c) {
+  if (!c->prof_on || c->prof_open < 0) return;
+  hipEvent_t b = prof_event(c);
+  if (b && c->prof_a) {
+    (void)hipEventRecord(b, c->stream);
+    c->prof_recs.push_back({c->prof_open, c->prof_a, b});
+  }
+  c->prof_open = -1;
+  c->prof_a = nullptr;
+}
+
+void prof_clear(gtp_ctx c) {
+  for (auto& r : c->prof_recs) {
+    c->prof_pool.push_back(r.a);
+    c->prof_pool.push_back(r.b);
+  }
+  c->prof_recs.clear();
+}
+
+// Launch on the ctx stream; with profiling on, bracketed by HIP events.
+#define LAUNCH(c, name, kern, grid, block, lds, ...)                      \
+  do {                                                                    \
+    prof_begin((c), name);                                                \
+    hipLaunchKernelGGL(kern, grid, block, lds, (c)->stream, __VA_ARGS__); \
+    LAUNCHCHK((c), name);                                                 \
+    prof_end((c));                                                        \
+  } while (0)
+
+gtp_status ensure(gtp_ctx c, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.bytes >= bytes) return GTP_OK;
+  if (b.p) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(b.p);
+    c->dev_bytes -= (int64_t)b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(c, GTP_ERR_OUT_OF_MEMORY, "device allocation of %zu bytes failed", bytes);
+  }
+  b.p = p;
+  b.bytes = bytes;
+  c->dev_bytes += (int64_t)bytes;
+  return GTP_OK;
+}
+
+void release(gtp_ctx c, DevBuf& b) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    c->dev_bytes -= (int64_t)b.bytes;
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+template <class T>
+T* ptr(DevBuf& b) {
+  return reinterpret_cast<T*>(b.p);
+}
+
+inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+gtp_status fill_u64(gtp_ctx c, void* p, int64_t n, unsigned long long v) {
+  if (n <= 0) return GTP_OK;
+  LAUNCH(c, "k_fill_u64", k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, (unsigned long long*)p, n, v);
+  return GTP_OK;
+}
+
+// exclusive scan of n items of T (in -> out), three passes
+template <class T, class Op>
+gtp_status scan_exclusive(gtp_ctx c, const T* in, T* out, int64_t n, T ident, Op op) {
+  if (n <= 0) return GTP_OK;
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  TRY(ensure(c, c->scan_sums, (size_t)nt * sizeof(T)));
+  T* sums = ptr<T>(c->scan_sums);
+  LAUNCH(c, "k_scan_tiles", (k_scan_tiles<T, Op>), dim3((unsigned)nt), dim3(kScanThreads), 0, in, out, sums, n, ident, op);
+  if (nt > 1) {
+    LAUNCH(c, "k_scan_sums", (k_scan_sums<T, Op>), dim3(1), dim3(kScanThreads), 0, sums, nt, ident, op);
+    LAUNCH(c, "k_scan_add", (k_scan_add<T, Op>), dim3(grid_for(n, 256)), dim3(256), 0, out, (const T*)sums, n, op);
+  }
+  return GTP_OK;
+}
+
+LibView lib_view(gtp_ctx c) {
+  LibView L;
+  const uint32_t* img = ptr<uint32_t>(c->lib_img);
+  L.meta = reinterpret_cast<const CellMeta*>(img);
+  L.map_q = reinterpret_cast<const int32_t*>(img + 4 * c->n_cells);
+  L.leak = reinterpret_cast<const float*>(img + 4 * c->n_cells + c->n_map);
+  L.slew = reinterpret_cast<const float*>(img + 4 * c->n_cells + c->n_map + c->n_leak);
+  L.slew_inv = L.slew + c->n_cells * c->n_slew;
+  L.quads = ptr<float4>(c->quads);
+  L.n_cells = c->n_cells;
+  L.n_slew = c->n_slew;
+  L.n_load = c->n_load;
+  L.n_map = c->n_map;
+  L.n_leak = c->n_leak;
+  L.lds_words = c->lds_words;
+  return L;
+}
+
+LutArgs lut_args(gtp_ctx c) {
+  LutArgs A;
+  A.quads = ptr<float4>(c->quads);
+  A.n_slew = c->n_slew;
+  A.n_load = c->n_load;
+  A.scale_k = ldexpf(1.0f, c->kfix);
+  return A;
+}
+
+EvView ev_view(gtp_ctx c) {
+  EvView E;
+  E.t = c->ev.t_ps;
+  E.pb = c->ev.pin_bit;
+  E.slew = c->ev.slew_ps;
+  E.gate_off = c->ev.gate_off;
+  E.n = c->ev.n_events;
+  E.n_gates = c->n_gates;
+  return E;
+}
+
+int ceil_log2(uint64_t x) {
+  int l = 0;
+  while ((1ull << l) < x) ++l;
+  return l;
+}
+
+Div32 make_div32(uint32_t d) {
+  Div32 r;
+  const int l = ceil_log2(d);
+  const uint64_t m = ((((uint64_t)1 << l) - d) << 32) / d + 1;
+  r.m = (uint32_t)m;
+  r.s1 = std::min(l, 1);
+  r.s2 = std::max(l - 1, 0);
+  return r;
+}
+
+gtp_status need(gtp_ctx c, bool lib, bool net, bool ev, bool par) {
+  if (!c) return GTP_ERR_INVALID_ARG;
+  if (lib && !c->lib_ok) return fail(c, GTP_ERR_NOT_LOADED, "no library loaded");
+  if (net && !c->net_ok) return fail(c, GTP_ERR_NOT_LOADED, "no netlist loaded");
+  if (ev && !c->ev_ok) return fail(c, GTP_ERR_NOT_LOADED, "no events loaded");
+  if (par && !c->par_ok) return fail(c, GTP_ERR_NOT_LOADED, "no parameters set");
+  return GTP_OK;
+}
+
+// ----------------------------------------------------------------------------
+// plan
+// ----------------------------------------------------------------------------
+gtp_status build_block_plan(gtp_ctx c) {
+  const int64_t N = c->ev.n_events;
+  c->n_blocks = (N + kLaneEvents - 1) / kLaneEvents;
+  if (c->n_blocks == 0) return GTP_OK;
+  TRY(ensure(c, c->plan_blk, (size_t)c->n_blocks * sizeof(uint2)));
+  TRY(ensure(c, c->blk_tmp, (size_t)c->n_blocks * sizeof(uint32_t)));
+  TRY(ensure(c, c->blk_tmp2, (size_t)c->n_blocks * sizeof(uint32_t)));
+  uint2* plan = ptr<uint2>(c->plan_blk);
+  LAUNCH(c, "k_plan_block_gate", k_plan_block_gate, dim3(grid_for(c->n_blocks, 256)), dim3(256), 0, c->ev.gate_off, c->n_gates, N, plan, c->n_blocks);
+  LAUNCH(c, "k_plan_block_xor", k_plan_block_xor, dim3(grid_for(c->n_blocks, 256)), dim3(256), 0, c->ev.pin_bit, N, ptr<uint32_t>(c->blk_tmp), c->n_blocks);
+  TRY(scan_exclusive<uint32_t, OpXor>(c, ptr<uint32_t>(c->blk_tmp), ptr<uint32_t>(c->blk_tmp2), c->n_blocks, 0u,
+                                      OpXor()));
+  LAUNCH(c, "k_plan_block_carry", k_plan_block_carry, dim3(grid_for(c->n_blocks, 256)), dim3(256), 0, c->ev.gate_off, c->ev.pin_bit, (const uint32_t*)ptr<uint32_t>(c->blk_tmp2), plan, c->n_blocks);
+  return GTP_OK;
+}
+
+int auto_tile_log2(int64_t n_bins, int r_bits) {
+  int lb = 12;
+  while (lb > 8 && (n_bins + (1ll << lb) - 1) / (1ll << lb) < 256) --lb;
+  while (lb > 8 && lb + r_bits > 32) --lb;
+  return lb;
+}
+
+gtp_status build_tile_plan(gtp_ctx c) {
+  if (c->tiles_ok) return GTP_OK;
+  const int64_t N = c->ev.n_events;
+  BinSpec& B = c->bins;
+  int lb = c->tun.bins_per_tile_log2 ? c->tun.bins_per_tile_log2 : auto_tile_log2(B.n_bins, B.r_bits);
+  if (lb < 8 || lb > 13) return fail(c, GTP_ERR_INVALID_ARG, "bins_per_tile_log2 %d outside [8, 13]", lb);
+  if (lb + B.r_bits > 32)
+    return fail(c, GTP_ERR_UNSUPPORTED, "tile of 2^%d bins with %d-bit in-bin offsets exceeds 32 bits", lb, B.r_bits);
+  B.tile_log2 = lb;
+  const int64_t nt = (B.n_bins + (1ll << lb) - 1) >> lb;
+  if (nt > 8192) return fail(c, GTP_ERR_UNSUPPORTED, "%lld time tiles (max 8192): raise bins_per_tile_log2",
+                             (long long)nt);
+  B.n_tiles = (int32_t)nt;
+  if (N >= (int64_t)UINT32_MAX) return fail(c, GTP_ERR_UNSUPPORTED, "more than 2^32-1 events in one trace");
+  // about 16 records per (workgroup, tile) on average
+  int64_t ge = kSubChunk;
+  while (ge < 16 * nt) ge <<= 1;
+  c->group_events = ge;
+  c->n_groups = std::max<int64_t>(1, (N + ge - 1) / ge);
+  const int64_t cells = c->n_groups * nt;
+  if (cells >= (int64_t)INT32_MAX) return fail(c, GTP_ERR_UNSUPPORTED, "placement table too large");
+  TRY(ensure(c, c->cnt_tm, (size_t)cells * 4));
+  TRY(ensure(c, c->off_tm, (size_t)cells * 4 + 8));
+  TRY(ensure(c, c->off_gm, (size_t)cells * 4));
+  TRY(ensure(c, c->tile_off, (size_t)(nt + 1) * 4));
+  TRY(ensure(c, c->rec, (size_t)std::max<int64_t>(N, 1) * sizeof(uint3)));
+  if (N > 0) {
+    LAUNCH(c, "k_plan_count", k_plan_count, dim3((unsigned)c->n_groups), dim3(256), (size_t)nt * 4, c->ev.t_ps, N, B, ge, c->n_groups, ptr<uint32_t>(c->cnt_tm));
+    TRY(scan_exclusive<uint32_t, OpAdd>(c, ptr<uint32_t>(c->cnt_tm), ptr<uint32_t>(c->off_tm), cells, 0u, OpAdd()));
+  } else {
+    TRY(fill_u64(c, c->off_tm.p, (cells + 1) / 2, 0ull));
+  }
+  // records beyond valid times are dropped, so the total is read back from the scan
+  uint32_t last_off = 0, last_cnt = 0;
+  if (N > 0) {
+    HIPCHK(c, hipMemcpyAsync(&last_off, ptr<uint32_t>(c->off_tm) + cells - 1, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&last_cnt, ptr<uint32_t>(c->cnt_tm) + cells - 1, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  const uint32_t n_rec = last_off + last_cnt;
+  LAUNCH(c, "k_plan_tile_off", k_plan_tile_off, dim3(grid_for(nt + 1, 256)), dim3(256), 0, (const uint32_t*)ptr<uint32_t>(c->off_tm), c->n_groups, (int32_t)nt, n_rec, ptr<uint32_t>(c->tile_off));
+  LAUNCH(c, "k_plan_transpose", k_plan_transpose, dim3(grid_for(cells, 256)), dim3(256), 0, (const uint32_t*)ptr<uint32_t>(c->off_tm), ptr<uint32_t>(c->off_gm), c->n_groups, (int32_t)nt);
+  c->tiles_ok = true;
+  return GTP_OK;
+}
+
+gtp_status gate_prep(gtp_ctx c, const float* net_load, const float* leak_scale) {
+  TRY(ensure(c, c->gprep, (size_t)std::max<int64_t>(c->n_gates, 1) * sizeof(GatePrep)));
+  TRY(ensure(c, c->L0, 8));
+  TRY(fill_u64(c, c->L0.p, 1, 0ull));
+  if (c->n_gates == 0) return GTP_OK;
+  PrepArgs a;
+  const LibView L = lib_view(c);
+  a.gate_cell = ptr<int32_t>(c->gate_cell);
+  a.gate_out = ptr<int32_t>(c->gate_out);
+  a.gate_init = ptr<uint32_t>(c->gate_init);
+  a.net_load = net_load;
+  a.leak_scale = leak_scale;
+  a.meta = L.meta;
+  a.leak = L.leak;
+  a.load = ptr<float>(c->load_axis);
+  a.load_inv = ptr<float>(c->load_inv);
+  a.n_load = c->n_load;
+  a.n_gates = c->n_gates;
+  a.vdd = c->par.vdd;
+  a.sw_mode = c->par.sw_mode;
+  a.scale_k = ldexpf(1.0f, c->kfix);
+  a.max_scale = GTP_MAX_LEAK_SCALE;
+  a.out = ptr<GatePrep>(c->gprep);
+  a.L0 = ptr<unsigned long long>(c->L0);
+  a.flag = ptr<int32_t>(c->flag);
+  LAUNCH(c, "k_gate_prep", k_gate_prep, dim3(grid_for(c->n_gates, 256)), dim3(256), 0, a);
+  return GTP_OK;
+}
+
+size_t lib_lds_bytes(gtp_ctx c) { return (size_t)c->lds_words * 4; }
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+gtp_status gtp_create(gtp_ctx* out, int hip_device, void* hip_stream) {
+  if (!out) return GTP_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) {
+    (void)hipGetLastError();
+    return GTP_ERR_INVALID_ARG;
+  }
+  gtp_ctx c = new (std::nothrow) gtp_ctx_s();
+  if (!c) return GTP_ERR_OUT_OF_MEMORY;
+  c->dev = hip_device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(hip_device) != hipSuccess) {
+    delete c;
+    return GTP_ERR_HIP;
+  }
+  if (ensure(c, c->flag, 256) != GTP_OK || ensure(c, c->first_bad, 256) != GTP_OK) {
+    delete c;
+    return GTP_ERR_OUT_OF_MEMORY;
+  }
+  // dynamic LDS above the 64 KB default: tiles of up to 2^13 bins (128 KB),
+  // library image plus tile cursors (48 + 32 KB)
+  if (hipFuncSetAttribute((const void*)k_tile_accum, hipFuncAttributeMaxDynamicSharedMemorySize, 16 << 13) !=
+          hipSuccess ||
+      hipFuncSetAttribute((const void*)k_fwd_records, hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return GTP_ERR_HIP;
+  }
+  if (fill_u64(c, c->flag.p, 1, 0ull) != GTP_OK) {
+    delete c;
+    return GTP_ERR_HIP;
+  }
+  *out = c;
+  return GTP_OK;
+}
+
+gtp_status gtp_destroy(gtp_ctx c) {
+  if (!c) return GTP_OK;
+  (void)hipSetDevice(c->dev);
+  (void)hipStreamSynchronize(c->stream);
+  DevBuf* all[] = {&c->lib_img, &c->load_axis, &c->load_inv, &c->quads, &c->gate_cell, &c->gate_out,
+                   &c->gate_init, &c->plan_blk, &c->blk_tmp, &c->blk_tmp2, &c->scan_sums, &c->cnt_tm,
+                   &c->off_tm, &c->off_gm, &c->tile_off, &c->rec, &c->gprep, &c->X, &c->S, &c->exS,
+                   &c->L0, &c->flag, &c->first_bad, &c->adj_w, &c->adj_c, &c->adj_exc, &c->adj_wg,
+                   &c->adj_total, &c->gC, &c->gL};
+  for (DevBuf* b : all) release(c, *b);
+  prof_clear(c);
+  for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+  delete c;
+  return GTP_OK;
+}
+
+gtp_status gtp_set_stream(gtp_ctx c, void* s) {
+  if (!c) return GTP_ERR_INVALID_ARG;
+  c->stream = (hipStream_t)s;
+  return GTP_OK;
+}
+
+const char* gtp_last_error(gtp_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+int64_t gtp_bad_event(gtp_ctx c) { return c ? c->bad_event : -1; }
+
+int64_t gtp_device_bytes(gtp_ctx c) { return c ? c->dev_bytes : 0; }
+
+gtp_status gtp_sync(gtp_ctx c) {
+  if (!c) return GTP_ERR_INVALID_ARG;
+  HIPCHK(c, hipSetDevice(c->dev));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int32_t flag = 0;
+  HIPCHK(c, hipMemcpy(&flag, c->flag.p, 4, hipMemcpyDeviceToHost));
+  if (flag) {
+    fill_u64(c, c->flag.p, 1, 0ull);
+    (void)hipStreamSynchronize(c->stream);
+    return fail(c, GTP_ERR_SCALE_RANGE, "a leakage scale was negative, not finite or above %g (used as 0)",
+                (double)GTP_MAX_LEAK_SCALE);
+  }
+  return GTP_OK;
+}
+
+gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
+  if (!c || !lib) return GTP_ERR_INVALID_ARG;
+  HIPCHK(c, hipSetDevice(c->dev));
+  const int nc = lib->n_cells, ns = lib->n_slew, nl = lib->n_load;
+  if (nc <= 0 || ns < 2 || ns > 16 || nl < 2 || nl > 16)
+    return fail(c, GTP_ERR_INVALID_ARG, "library sizes n_cells=%d n_slew=%d n_load=%d", nc, ns, nl);
+  if (!lib->n_inputs || !lib->slew_axis_ps || !lib->load_axis_ff || !lib->map_base || !lib->state_to_table ||
+      !lib->table_base || !lib->tables_fj || !lib->leak_base || !lib->leak_nw)
+    return fail(c, GTP_ERR_INVALID_ARG, "null library array");
+  if (lib->n_map <= 0 || lib->n_tables <= 0 || lib->n_leak <= 0)
+    return fail(c, GTP_ERR_INVALID_ARG, "library array lengths must be positive");
+  const int64_t Q = (int64_t)(ns - 1) * (nl - 1);
+  if (lib->n_tables * Q >= (int64_t)INT32_MAX) return fail(c, GTP_ERR_UNSUPPORTED, "tables too large");
+  std::vector<CellMeta> meta(nc);
+  std::vector<int32_t> mapq;
+  std::vector<float> leak;
+  float leak_max = 0.f;
+  for (int cc = 0; cc < nc; ++cc) {
+    const int I = lib->n_inputs[cc];
+    if (I < 1 || I > 8) return fail(c, GTP_ERR_UNSUPPORTED, "cell %d has %d inputs (supported 1..8)", cc, I);
+    const int64_t nst = 1ll << I;
+    const int64_t mb = lib->map_base[cc], tb = lib->table_base[cc], lbs = lib->leak_base[cc];
+    if (mb < 0 || mb + 2 * nst > lib->n_map || lbs < 0 || lbs + nst > lib->n_leak || tb < 0 || tb >= lib->n_tables)
+      return fail(c, GTP_ERR_INVALID_ARG, "cell %d: map/leak/table base out of range", cc);
+    for (int i = 0; i + 1 < ns; ++i)
+      if (!(lib->slew_axis_ps[cc * ns + i] < lib->slew_axis_ps[cc * ns + i + 1]))
+        return fail(c, GTP_ERR_INVALID_ARG, "cell %d: slew axis not strictly increasing", cc);
+    for (int j = 0; j + 1 < nl; ++j)
+      if (!(lib->load_axis_ff[cc * nl + j] < lib->load_axis_ff[cc * nl + j + 1]))
+        return fail(c, GTP_ERR_INVALID_ARG, "cell %d: load axis not strictly increasing", cc);
+    meta[cc].n_in = I;
+    meta[cc].map_off = (int32_t)mapq.size();
+    meta[cc].leak_off = (int32_t)leak.size();
+    meta[cc].axis_off = cc * ns;
+    for (int64_t e = 0; e < 2 * nst; ++e) {
+      const int64_t k = lib->state_to_table[mb + e];
+      if (k < 0 || tb + k >= lib->n_tables)
+        return fail(c, GTP_ERR_INVALID_ARG, "cell %d: table id %lld out of range", cc, (long long)k);
+      mapq.push_back((int32_t)((tb + k) * Q));
+    }
+    for (int64_t s = 0; s < nst; ++s) {
+      const float v = lib->leak_nw[lbs + s];
+      if (!(v >= 0.f) || !std::isfinite(v)) return fail(c, GTP_ERR_INVALID_ARG, "cell %d: bad leakage value", cc);
+      leak.push_back(v);
+      leak_max = std::max(leak_max, v);
+    }
+  }
+  for (int64_t i = 0; i < lib->n_tables * ns * nl; ++i)
+    if (!std::isfinite(lib->tables_fj[i])) return fail(c, GTP_ERR_INVALID_ARG, "non-finite table entry %lld",
+                                                       (long long)i);
+  const int32_t n_map = (int32_t)mapq.size(), n_leak = (int32_t)leak.size();
+  const int64_t words = 4ll * nc + n_map + n_leak + 2ll * nc * ns;
+  if (words * 4 > 48 * 1024)
+    return fail(c, GTP_ERR_UNSUPPORTED, "library image of %lld bytes exceeds the 48 KB LDS budget",
+                (long long)(words * 4));
+  std::vector<uint32_t> img((size_t)words);
+  memcpy(img.data(), meta.data(), sizeof(CellMeta) * nc);
+  memcpy(img.data() + 4 * nc, mapq.data(), 4 * (size_t)n_map);
+  memcpy(img.data() + 4 * nc + n_map, leak.data(), 4 * (size_t)n_leak);
+  float* slew = reinterpret_cast<float*>(img.data() + 4 * nc + n_map + n_leak);
+  float* slew_inv = slew + (size_t)nc * ns;
+  std::vector<float> load((size_t)nc * nl), load_inv((size_t)nc * nl, 0.f);
+  for (int cc = 0; cc < nc; ++cc) {
+    for (int i = 0; i < ns; ++i) {
+      slew[cc * ns + i] = lib->slew_axis_ps[cc * ns + i];
+      slew_inv[cc * ns + i] =
+          (i + 1 < ns) ? (float)(1.0 / ((double)lib->slew_axis_ps[cc * ns + i + 1] - lib->slew_axis_ps[cc * ns + i]))
+                       : 0.f;
+    }
+    for (int j = 0; j < nl; ++j) {
+      load[cc * nl + j] = lib->load_axis_ff[cc * nl + j];
+      load_inv[cc * nl + j] =
+          (j + 1 < nl) ? (float)(1.0 / ((double)lib->load_axis_ff[cc * nl + j + 1] - lib->load_axis_ff[cc * nl + j]))
+                       : 0.f;
+    }
+  }
+  // quads: (T[i][j], T[i][j+1], T[i+1][j], T[i+1][j+1]) per table and axis cell
+  std::vector<float> quads((size_t)(lib->n_tables * Q * 4));
+  for (int64_t T = 0; T < lib->n_tables; ++T) {
+    const float* tb = lib->tables_fj + T * ns * nl;
+    for (int i = 0; i + 1 < ns; ++i)
+      for (int j = 0; j + 1 < nl; ++j) {
+        float* q = &quads[(size_t)((T * Q + i * (nl - 1) + j) * 4)];
+        q[0] = tb[i * nl + j];
+        q[1] = tb[i * nl + j + 1];
+        q[2] = tb[(i + 1) * nl + j];
+        q[3] = tb[(i + 1) * nl + j + 1];
+      }
+  }
+  TRY(ensure(c, c->lib_img, img.size() * 4));
+  TRY(ensure(c, c->load_axis, load.size() * 4));
+  TRY(ensure(c, c->load_inv, load_inv.size() * 4));
+  TRY(ensure(c, c->quads, quads.size() * 4));
+  HIPCHK(c, hipMemcpy(c->lib_img.p, img.data(), img.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->load_axis.p, load.data(), load.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->load_inv.p, load_inv.data(), load_inv.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->quads.p, quads.data(), quads.size() * 4, hipMemcpyHostToDevice));
+  c->n_cells = nc;
+  c->n_slew = ns;
+  c->n_load = nl;
+  c->n_map = n_map;
+  c->n_leak = n_leak;
+  c->n_tables = lib->n_tables;
+  c->lds_words = (int32_t)words;
+  c->h_nin.assign(lib->n_inputs, lib->n_inputs + nc);
+  // fixed-point exponent: a quantised rate lambda*leak*2^k must stay below 2^30
+  double top = (double)GTP_MAX_LEAK_SCALE * std::max(leak_max, 1e-3f);
+  int k = (int)std::floor(std::log2((double)(1 << 30) / top));
+  c->kfix = std::max(4, std::min(24, k));
+  c->lib_ok = true;
+  c->net_ok = false;
+  c->ev_ok = false;
+  c->tiles_ok = false;
+  return GTP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+__global__ void k_check_netlist(const int32_t* cell, const int32_t* out, int64_t n, int32_t n_cells, int64_t n_nets,
+                                int32_t* bad) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  if (cell[g] < 0 || cell[g] >= n_cells || out[g] < 0 || (int64_t)out[g] >= n_nets) atomicOr(bad, 1);
+}
+}  // namespace
+
+extern "C" {
+
+gtp_status gtp_load_netlist(gtp_ctx c, int64_t n_gates, int64_t n_nets, const int32_t* gate_cell,
+                            const int32_t* gate_out_net, const uint32_t* gate_init_bits) {
+  TRY(need(c, true, false, false, false));
+  HIPCHK(c, hipSetDevice(c->dev));
+  if (n_gates < 0 || n_nets < 0 || n_gates >= (int64_t)INT32_MAX || n_nets >= (int64_t)INT32_MAX)
+    return fail(c, GTP_ERR_INVALID_ARG, "n_gates=%lld n_nets=%lld", (long long)n_gates, (long long)n_nets);
+  if (n_gates > 0 && (!gate_cell || !gate_out_net || !gate_init_bits))
+    return fail(c, GTP_ERR_INVALID_ARG, "null netlist array");
+  TRY(ensure(c, c->gate_cell, (size_t)n_gates * 4));
+  TRY(ensure(c, c->gate_out, (size_t)n_gates * 4));
+  TRY(ensure(c, c->gate_init, (size_t)n_gates * 4));
+  if (n_gates > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->gate_cell.p, gate_cell, (size_t)n_gates * 4, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->gate_out.p, gate_out_net, (size_t)n_gates * 4, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->gate_init.p, gate_init_bits, (size_t)n_gates * 4, hipMemcpyDeviceToDevice,
+                             c->stream));
+    TRY(ensure(c, c->first_bad, 256));
+    TRY(fill_u64(c, c->first_bad.p, 1, 0ull));
+    LAUNCH(c, "k_check_netlist", k_check_netlist, dim3(grid_for(n_gates, 256)), dim3(256), 0, ptr<int32_t>(c->gate_cell), ptr<int32_t>(c->gate_out), n_gates, c->n_cells, n_nets, ptr<int32_t>(c->first_bad));
+    int32_t bad = 0;
+    HIPCHK(c, hipMemcpyAsync(&bad, c->first_bad.p, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (bad) return fail(c, GTP_ERR_INVALID_ARG, "a gate names a cell or output net out of range");
+  }
+  c->n_gates = n_gates;
+  c->n_nets = n_nets;
+  c->net_ok = true;
+  c->ev_ok = false;
+  c->tiles_ok = false;
+  return GTP_OK;
+}
+
+gtp_status gtp_load_events(gtp_ctx c, const gtp_events* ev, int validate) {
+  TRY(need(c, true, true, false, false));
+  HIPCHK(c, hipSetDevice(c->dev));
+  c->bad_event = -1;
+  if (!ev || ev->n_events < 0 || ev->t_end_ps <= 0) return fail(c, GTP_ERR_INVALID_ARG, "bad event descriptor");
+  if (!ev->gate_off) return fail(c, GTP_ERR_INVALID_ARG, "null gate_off");
+  if (ev->n_events > 0 && (!ev->t_ps || !ev->pin_bit || !ev->slew_ps))
+    return fail(c, GTP_ERR_INVALID_ARG, "null event array");
+  if (((uintptr_t)ev->t_ps | (uintptr_t)ev->pin_bit | (uintptr_t)ev->slew_ps) & 15)
+    return fail(c, GTP_ERR_INVALID_ARG, "event arrays must be 16-byte aligned");
+  if (c->n_gates == 0 && ev->n_events > 0) return fail(c, GTP_ERR_INVALID_ARG, "events without gates");
+  int64_t ends[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(&ends[0], ev->gate_off, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&ends[1], ev->gate_off + c->n_gates, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (ends[0] != 0 || ends[1] != ev->n_events)
+    return fail(c, GTP_ERR_INVALID_ARG, "gate_off must start at 0 and end at n_events (%lld, %lld)",
+                (long long)ends[0], (long long)ends[1]);
+  c->ev = *ev;
+  c->ev_ok = false;
+  c->tiles_ok = false;
+  TRY(build_block_plan(c));
+  c->ev_ok = true;
+  if (c->par_ok && c->bins.t_end != ev->t_end_ps) c->par_ok = false;  // bins depend on t_end
+  if (validate && c->n_blocks > 0) {
+    TRY(fill_u64(c, c->first_bad.p, 1, ~0ull));
+    ValArgs a;
+    a.ev = ev_view(c);
+    a.plan = ptr<uint2>(c->plan_blk);
+    a.gate_cell = ptr<int32_t>(c->gate_cell);
+    a.gate_init = ptr<uint32_t>(c->gate_init);
+    a.meta = lib_view(c).meta;
+    a.t_end = ev->t_end_ps;
+    a.first = ptr<unsigned long long>(c->first_bad);
+    LAUNCH(c, "k_validate", k_validate, dim3(grid_for(c->n_blocks, kFwdThreads)), dim3(kFwdThreads), 0, a);
+    unsigned long long key = 0;
+    HIPCHK(c, hipMemcpyAsync(&key, c->first_bad.p, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (key != ~0ull) {
+      const int code = (int)(key & 7);
+      c->bad_event = (int64_t)(key >> 3);
+      c->ev_ok = false;
+      static const char* what[] = {"", "time outside [0, t_end)", "time decreases within its gate",
+                                   "pin above the output pin", "pin repeated at one timestamp", "not a toggle"};
+      const gtp_status st = (code == 1 || code == 3) ? GTP_ERR_EVENT_RANGE
+                            : (code == 5)            ? GTP_ERR_NOT_TOGGLE
+                                                     : GTP_ERR_EVENT_ORDER;
+      return fail(c, st, "event %lld: %s", (long long)c->bad_event, what[code]);
+    }
+  }
+  return GTP_OK;
+}
+
+gtp_status gtp_set_params(gtp_ctx c, const gtp_params* p) {
+  TRY(need(c, false, false, true, false));
+  if (!p || !(p->vdd > 0.0) || !std::isfinite(p->vdd) || p->bin_ps < 1 || p->bin_ps > (1 << 24) ||
+      (p->sw_mode != 0 && p->sw_mode != 1))
+    return fail(c, GTP_ERR_INVALID_ARG, "bad parameters");
+  c->par = *p;
+  BinSpec& B = c->bins;
+  B.D = p->bin_ps;
+  B.t_end = c->ev.t_end_ps;
+  B.n_bins = (B.t_end + B.D - 1) / B.D;
+  B.t32 = (B.t_end <= ((int64_t)1 << 32)) ? 1 : 0;
+  B.div = make_div32((uint32_t)B.D);
+  B.r_bits = ceil_log2((uint64_t)B.D);
+  B.tile_log2 = 8;
+  B.n_tiles = 0;
+  c->par_ok = true;
+  c->tiles_ok = false;
+  return GTP_OK;
+}
+
+gtp_status gtp_num_bins(gtp_ctx c, int64_t* n) {
+  TRY(need(c, false, false, true, true));
+  if (!n) return GTP_ERR_INVALID_ARG;
+  *n = c->bins.n_bins;
+  return GTP_OK;
+}
+
+gtp_status gtp_set_tuning(gtp_ctx c, const gtp_tuning* t) {
+  if (!c || !t) return GTP_ERR_INVALID_ARG;
+  if (t->algo < 0 || t->algo > 1) return fail(c, GTP_ERR_INVALID_ARG, "algo %d", t->algo);
+  if (t->bins_per_tile_log2 != 0 && (t->bins_per_tile_log2 < 8 || t->bins_per_tile_log2 > 13))
+    return fail(c, GTP_ERR_INVALID_ARG, "bins_per_tile_log2 %d", t->bins_per_tile_log2);
+  if (t->bins_per_tile_log2 != c->tun.bins_per_tile_log2) c->tiles_ok = false;
+  c->tun = *t;
+  return GTP_OK;
+}
+
+gtp_status gtp_get_tuning(gtp_ctx c, gtp_tuning* t) {
+  if (!c || !t) return GTP_ERR_INVALID_ARG;
+  *t = c->tun;
+  if (c->tiles_ok && t->bins_per_tile_log2 == 0) t->bins_per_tile_log2 = c->bins.tile_log2;
+  return GTP_OK;
+}
+
+gtp_status gtp_forward(gtp_ctx c, const float* net_load_ff, const float* leak_scale, float* power_mw) {
+  TRY(need(c, true, true, true, true));
+  if (!net_load_ff || !power_mw) return fail(c, GTP_ERR_INVALID_ARG, "null forward argument");
+  HIPCHK(c, hipSetDevice(c->dev));
+  const int64_t NB = c->bins.n_bins;
+  TRY(gate_prep(c, net_load_ff, leak_scale));
+  TRY(ensure(c, c->X, (size_t)NB * 8));
+  TRY(ensure(c, c->S, (size_t)NB * 8));
+  TRY(ensure(c, c->exS, (size_t)NB * 8));
+  const double dyn_scale = std::ldexp(1.0, c->kfix) * 1e6;
+  const int64_t N = c->ev.n_events;
+  if (c->tun.algo == 0) {
+    TRY(build_tile_plan(c));
+    const BinSpec& B = c->bins;
+    if (N > 0) {
+      FwdArgs a;
+      a.ev = ev_view(c);
+      a.plan = ptr<uint2>(c->plan_blk);
+      a.gprep = ptr<GatePrep>(c->gprep);
+      a.lib = lib_view(c);
+      a.lut = lut_args(c);
+      a.bins = B;
+      a.group_events = c->group_events;
+      a.off_gm = ptr<uint32_t>(c->off_gm);
+      a.rec = ptr<uint3>(c->rec);
+      a.n_rec = N;
+      a.dbg_state = nullptr;
+      a.dbg_bin = nullptr;
+      const size_t lds = lib_lds_bytes(c) + (size_t)B.n_tiles * 4;
+      LAUNCH(c, "k_fwd_records", k_fwd_records, dim3((unsigned)c->n_groups), dim3(kFwdThreads), lds, a);
+    }
+    TileArgs ta;
+    ta.rec = ptr<uint3>(c->rec);
+    ta.tile_off = ptr<uint32_t>(c->tile_off);
+    ta.X = ptr<int64_t>(c->X);
+    ta.S = ptr<int64_t>(c->S);
+    ta.bins = B;
+    ta.dyn_scale = dyn_scale;
+    const size_t lds = (size_t)16 << B.tile_log2;
+    LAUNCH(c, "k_tile_accum", k_tile_accum, dim3((unsigned)B.n_tiles), dim3(kTileThreads), lds, ta);
+  } else {
+    TRY(fill_u64(c, c->X.p, NB, 0ull));
+    TRY(fill_u64(c, c->S.p, NB, 0ull));
+    if (c->n_gates > 0 && N > 0) {
+      SerialArgs a;
+      a.ev = ev_view(c);
+      a.gprep = ptr<GatePrep>(c->gprep);
+      a.lib = lib_view(c);
+      a.lut = lut_args(c);
+      a.bins = c->bins;
+      a.X = ptr<unsigned long long>(c->X);
+      a.S = ptr<unsigned long long>(c->S);
+      a.dyn_scale = dyn_scale;
+      LAUNCH(c, "k_gate_serial", k_gate_serial, dim3(grid_for(c->n_gates, kFwdThreads)), dim3(kFwdThreads), lib_lds_bytes(c), a);
+    }
+  }
+  TRY(scan_exclusive<int64_t, OpAdd>(c, ptr<int64_t>(c->S), ptr<int64_t>(c->exS), NB, (int64_t)0, OpAdd()));
+  FinArgs f;
+  f.X = ptr<int64_t>(c->X);
+  f.S = ptr<int64_t>(c->S);
+  f.exS = ptr<int64_t>(c->exS);
+  f.L0 = ptr<unsigned long long>(c->L0);
+  f.P = power_mw;
+  f.n_bins = NB;
+  f.D = c->bins.D;
+  f.t_end = c->bins.t_end;
+  f.out_scale = std::ldexp(1.0, -c->kfix) * 1e-6 / (double)c->bins.D;
+  LAUNCH(c, "k_finalize", k_finalize, dim3(grid_for(NB, 256)), dim3(256), 0, f);
+  return GTP_OK;
+}
+
+gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_scale, const float* grad_power,
+                       float* grad_net_load, float* grad_leak_scale) {
+  TRY(need(c, true, true, true, true));
+  if (!net_load_ff || !grad_power || !grad_net_load || !grad_leak_scale)
+    return fail(c, GTP_ERR_INVALID_ARG, "null adjoint argument");
+  HIPCHK(c, hipSetDevice(c->dev));
+  const int64_t NB = c->bins.n_bins;
+  TRY(gate_prep(c, net_load_ff, leak_scale));
+  TRY(ensure(c, c->adj_w, (size_t)NB * 8));
+  TRY(ensure(c, c->adj_c, (size_t)NB * 8));
+  TRY(ensure(c, c->adj_exc, (size_t)NB * 8));
+  TRY(ensure(c, c->adj_wg, (size_t)NB * 16));
+  TRY(ensure(c, c->adj_total, 8));
+  TRY(ensure(c, c->gC, (size_t)std::max<int64_t>(c->n_nets, 1) * 8));
+  TRY(ensure(c, c->gL, (size_t)std::max<int64_t>(c->n_gates, 1) * 8));
+  AdjBinArgs ab;
+  ab.gP = grad_power;
+  ab.c = ptr<double>(c->adj_c);
+  ab.wgtmp = ptr<double>(c->adj_w);
+  ab.n_bins = NB;
+  ab.D = c->bins.D;
+  ab.t_end = c->bins.t_end;
+  LAUNCH(c, "k_adj_bins", k_adj_bins, dim3(grid_for(NB, 256)), dim3(256), 0, ab);
+  TRY(scan_exclusive<double, OpAdd>(c, ptr<double>(c->adj_c), ptr<double>(c->adj_exc), NB, 0.0, OpAdd()));
+  LAUNCH(c, "k_adj_suffix", k_adj_suffix, dim3(grid_for(NB, 256)), dim3(256), 0, (const double*)ptr<double>(c->adj_w), (const double*)ptr<double>(c->adj_c), (const double*)ptr<double>(c->adj_exc), ptr<double2>(c->adj_wg), ptr<double>(c->adj_total), NB);
+  TRY(fill_u64(c, c->gC.p, c->n_nets, 0ull));
+  TRY(fill_u64(c, c->gL.p, c->n_gates, 0ull));
+  if (c->n_blocks > 0) {
+    AdjArgs a;
+    a.ev = ev_view(c);
+    a.plan = ptr<uint2>(c->plan_blk);
+    a.gprep = ptr<GatePrep>(c->gprep);
+    a.gate_out = ptr<int32_t>(c->gate_out);
+    a.lib = lib_view(c);
+    a.lut = lut_args(c);
+    a.bins = c->bins;
+    a.wg = ptr<double2>(c->adj_wg);
+    const double v2 = c->par.vdd * c->par.vdd;
+    a.dsw_rise = (float)(c->par.sw_mode == 0 ? 0.5 * v2 : v2);
+    a.dsw_fall = (float)(c->par.sw_mode == 0 ? 0.5 * v2 : 0.0);
+    a.gC = ptr<double>(c->gC);
+    a.gL = ptr<double>(c->gL);
+    LAUNCH(c, "k_adjoint_events", k_adjoint_events, dim3(grid_for(c->n_blocks, kFwdThreads)), dim3(kFwdThreads), lib_lds_bytes(c), a);
+  }
+  const int64_t n = std::max(c->n_nets, c->n_gates);
+  if (n > 0) {
+    AdjOutArgs o;
+    o.gC = ptr<double>(c->gC);
+    o.gL = ptr<double>(c->gL);
+    o.total = ptr<double>(c->adj_total);
+    o.gate_cell = ptr<int32_t>(c->gate_cell);
+    o.gate_init = ptr<uint32_t>(c->gate_init);
+    o.meta = lib_view(c).meta;
+    o.leak = lib_view(c).leak;
+    o.grad_load = grad_net_load;
+    o.grad_scale = grad_leak_scale;
+    o.n_nets = c->n_nets;
+    o.n_gates = c->n_gates;
+    LAUNCH(c, "k_adj_out", k_adj_out, dim3(grid_for(n, 256)), dim3(256), 0, o);
+  }
+  return GTP_OK;
+}
+
+gtp_status gtp_debug_event_trace(gtp_ctx c, int32_t* state_before, int64_t* bin) {
+  TRY(need(c, true, true, true, true));
+  if (c->n_blocks == 0) return GTP_OK;
+  if (!state_before || !bin) return fail(c, GTP_ERR_INVALID_ARG, "null trace output");
+  HIPCHK(c, hipSetDevice(c->dev));
+  // any loads: the trace does not depend on them; gate_prep needs a net-load array
+  TRY(ensure(c, c->adj_w, (size_t)(c->n_nets + 2) * 4));
+  LAUNCH(c, "k_fill_u64", k_fill_u64, dim3(grid_for((c->n_nets + 1) / 2, 256)), dim3(256), 0, ptr<unsigned long long>(c->adj_w), (c->n_nets + 1) / 2, 0x3f8000003f800000ull);
+  TRY(gate_prep(c, ptr<float>(c->adj_w), nullptr));
+  TraceArgs a;
+  a.ev = ev_view(c);
+  a.plan = ptr<uint2>(c->plan_blk);
+  a.gprep = ptr<GatePrep>(c->gprep);
+  a.lib = lib_view(c);
+  a.lut = lut_args(c);
+  a.bins = c->bins;
+  a.state = state_before;
+  a.bin = bin;
+  LAUNCH(c, "k_event_trace", k_event_trace, dim3(grid_for(c->n_blocks, kFwdThreads)), dim3(kFwdThreads), lib_lds_bytes(c), a);
+  return GTP_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+gtp_status gtp_profile_enable(gtp_ctx c, int enable) {
+  if (!c) return GTP_ERR_INVALID_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_clear(c);
+  c->prof_names.clear();
+  c->prof_on = enable != 0;
+  return GTP_OK;
+}
+
+gtp_status gtp_profile_read(gtp_ctx c, int32_t cap, const char** names, int64_t* launches, double* total_ms,
+                            int32_t* n_out) {
+  if (!c || !n_out || cap < 0 || (cap > 0 && (!names || !launches || !total_ms))) return GTP_ERR_INVALID_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int n = (int)c->prof_names.size();
+  std::vector<double> ms(n, 0.0);
+  std::vector<int64_t> cnt(n, 0);
+  for (const auto& r : c->prof_recs) {
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.id] += t;
+    cnt[r.id] += 1;
+  }
+  const int m = std::min(n, (int)cap);
+  for (int i = 0; i < m; ++i) {
+    names[i] = c->prof_names[i].c_str();
+    launches[i] = cnt[i];
+    total_ms[i] = ms[i];
+  }
+  *n_out = n;
+  return GTP_OK;
+}
+
+}  // extern "C"

@@ -71,3 +71,25 @@ def load_golden(name, sw_mode=0):
         fx = json.load(f)
     prob = build_problem(fx["cells"], fx["gates"], fx["events"], fx["t_end"], fx["bin_ps"], fx["vdd"], sw_mode)
     return prob, fx
+
+
+def to_device_ctx(prob, algo=0, tile_log2=0, validate=True):
+    """Load a synth.Problem into a library Context on cuda:0; returns
+    (ctx, net_load, leak_scale) with the loads and scales on the device."""
+    import torch
+
+    import paper_2609_05960_amd as gtp
+
+    dev = torch.device("cuda", 0)
+    ctx = gtp.Context(0)
+    ctx.load_library(prob.lib)
+    net, ev = prob.net, prob.ev
+    ctx.load_netlist(torch.from_numpy(net.gate_cell).to(dev), torch.from_numpy(net.gate_out_net).to(dev),
+                     torch.from_numpy(net.gate_init.view(np.int32)).to(dev), net.n_nets)
+    tens = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.gate_off, ev.t, ev.pin_bit, ev.slew)]
+    ctx.load_events(*tens, t_end=ev.t_end, validate=validate)
+    ctx.set_params(vdd=prob.vdd, bin_ps=prob.bin_ps, sw_mode=prob.sw_mode)
+    ctx.set_tuning(algo=algo, bins_per_tile_log2=tile_log2)
+    load = torch.from_numpy(net.net_load).to(dev)
+    lam = torch.from_numpy(net.leak_scale).to(dev)
+    return ctx, load, lam
