@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work for the oracle sample")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="only run device copies of this many MiB (to scale HBM byte counters), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
@@ -71,6 +73,15 @@ def main():
     import paper_2609_05960_amd as gtp
 
     dev = torch.device("cuda", 0)
+    if args.calib_copy:
+        n = args.calib_copy << 20
+        a = torch.ones(n // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": n, "copies": 3}))
+        return
     t0 = time.time()
     prob = synth.make_problem(args.config)
     gen_s = time.time() - t0
@@ -175,8 +186,9 @@ def main():
         O = oracle.get()
         counts = np.diff(ev.gate_off)
         cum = np.cumsum(counts)
-        # calibrate on ~2M events, then size the sample for about --cpu-seconds
-        m = int(np.searchsorted(cum, 2_000_000)) + 1
+        # calibrate on ~10% of the events, then size the sample for about --cpu-seconds
+        m = int(np.searchsorted(cum, max(1, N // 10))) + 1
+        m = min(m, G)
         t1 = time.time()
         O.forward(prob, gates=np.arange(m), nthreads=0)
         rate = cum[m - 1] / max(time.time() - t1, 1e-6)
