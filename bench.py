@@ -1,10 +1,11 @@
 """Throughput of the binned power-waveform path on one MI355X.
 
-One step = one forward pass over the whole synthetic trace (gate preparation,
-per-event energies and leakage steps, time-tile accumulation, leakage prefix
-scan, FP32 power), with the events already resident in HBM and the plan
-(which depends only on event times, pins and the bin width) built during
-warm-up. The workload is the 1M-gate, 200M-event, 50 ps-bin configuration;
+One step = one forward pass over the whole synthetic trace (gate parameters,
+per-event state tracking, energies and leakage steps accumulated per time tile,
+leakage prefix scan, FP32 power), with the events already resident in HBM and
+the packed layout (which depends only on event times, pins and the bin width)
+built before the timed region (its build time is reported under "plan").
+The workload is the 1M-gate, 200M-event, 50 ps-bin configuration;
 ``--config`` selects another synthetic configuration.
 
 Prints one JSON line (see the keys below). The per-kernel durations come from
@@ -24,8 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
-EVENT_BYTES = 13           # t int64 + slew float32 + pin/value uint8 read per event
-GATE_BYTES = 32            # prepared gate record read per gate (written once per call by k_gate_prep)
+EVENT_BYTES = 16           # per event: t int64 + slew float32 + pin/value padded to 4 bytes
+EVENT_BYTES_STRICT = 13    # the same with a 1-byte pin/value
+GATE_BYTES = 16            # gate parameter record read per gate
 BIN_BYTES = 4              # FP32 power written per bin
 
 WORKLOADS = {
@@ -101,9 +103,10 @@ def main():
     load = torch.from_numpy(net.net_load).to(dev)
     lam = torch.from_numpy(net.leak_scale).to(dev)
     P = torch.empty(ctx.n_bins, dtype=torch.float32, device=dev)
-    ctx.forward(load, lam, out=P)  # builds the time-tile plan
+    ctx.forward(load, lam, out=P)  # builds the packed layout
     torch.cuda.synchronize()
     plan_s = time.time() - tp
+    plan = ctx.plan_info() if args.algo == 0 else None
     for _ in range(args.warmup):
         ctx.forward(load, lam, out=P)
     torch.cuda.synchronize()
@@ -128,12 +131,21 @@ def main():
 
     kern_avg = {k: dict(launches=n, avg_ms=ms / max(n, 1), total_ms=ms) for k, (n, ms) in kern.items()}
     dom = max(kern_avg, key=lambda k: kern_avg[k]["total_ms"])
-    algo_bytes = {"k_fwd_records": EVENT_BYTES * N, "k_gate_serial": EVENT_BYTES * N + GATE_BYTES * G,
-                  "k_tile_accum": 16 * NB, "k_gate_prep": 24 * G, "k_finalize": 28 * NB}
+    algo_bytes = {"k_fwd_packed": EVENT_BYTES * N, "k_gate_serial": EVENT_BYTES * N + GATE_BYTES * G,
+                  "k_gate_params": 24 * G, "k_gate_prep": 24 * G, "k_finalize": 28 * NB}
     dom_bytes = algo_bytes.get(dom)
     dom_ms = kern_avg[dom]["avg_ms"]
     achieved = dom_bytes / (dom_ms * 1e-3) if dom_bytes else None
     step_bytes = EVENT_BYTES * N + GATE_BYTES * G + BIN_BYTES * NB
+    extra = {}
+    if dom in ("k_fwd_packed", "k_gate_serial"):
+        extra["strict_frac"] = EVENT_BYTES_STRICT * N / (dom_ms * 1e-3) / HBM_PEAK
+    if plan is not None and dom == "k_fwd_packed":
+        # bytes the packed layout actually holds per event: event word + slew,
+        # unit descriptors, group offsets
+        pb = 8 * plan["n_events_packed"] + 8 * 64 * plan["n_groups"] + 8 * plan["n_groups"]
+        extra["packed_bytes_per_event"] = pb / max(N, 1)
+        extra["packed_frac"] = pb / (dom_ms * 1e-3) / HBM_PEAK
 
     out = {
         "metric": "events/s into binned power waveform (fwd, fwd+adjoint); % of HBM roofline",
@@ -154,10 +166,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": (achieved / 1e9) if achieved else None,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK) if achieved else None, "traffic": None,
-                     "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms},
+                     "algorithmic_bytes_per_launch": dom_bytes, "algorithmic_bytes_per_event": EVENT_BYTES,
+                     "avg_launch_ms": dom_ms, **extra},
         "step_hbm_frac": step_bytes / (ms_step * 1e-3) / HBM_PEAK,
         "kernels": kern_avg,
         "plan_s": plan_s,
+        "plan": plan,
         "gen_s": gen_s,
     }
 

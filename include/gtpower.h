@@ -146,10 +146,12 @@ gtp_status gtp_set_params(gtp_ctx ctx, const gtp_params* p);
 gtp_status gtp_num_bins(gtp_ctx ctx, int64_t* n_bins);
 
 /*
- * Execution choices. algo 0: time-tiled path (contributions bucketed by time
- * tile, tiles accumulated in LDS); algo 1: one gate per thread with global
- * atomics (baseline). bins_per_tile_log2 0 = automatic, else 8..13.
- * Both paths give bit-identical waveforms.
+ * Execution choices. algo 0: packed tile-major path (the default: events
+ * regrouped once into time tiles, one workgroup per tile, bins accumulated in
+ * LDS); algo 1: one gate per thread with global atomics (baseline).
+ * bins_per_tile_log2: 0 = automatic, else 2..13 (bins per time tile of the
+ * packed path; the tile's bins and the library image must fit in 160 KB of
+ * LDS). Both paths give bit-identical waveforms.
  */
 typedef struct {
   int32_t algo;
@@ -157,6 +159,21 @@ typedef struct {
 } gtp_tuning;
 gtp_status gtp_set_tuning(gtp_ctx ctx, const gtp_tuning* t);
 gtp_status gtp_get_tuning(gtp_ctx ctx, gtp_tuning* t);
+
+/*
+ * Statistics of the packed layout (builds it if needed, which synchronises):
+ * events packed (those with times in the window), units (runs of at most 16
+ * events of one gate in one time tile), wavefront groups of 64 units, time
+ * tiles, bins per tile (log2), the largest group count of one tile, device
+ * bytes of the packed arrays and the time the last build took (ms).
+ */
+typedef struct {
+  int64_t n_events_packed, n_units, n_groups;
+  int32_t n_tiles, tile_log2, max_tile_groups;
+  int64_t packed_bytes;
+  double pack_ms;
+} gtp_plan_stats;
+gtp_status gtp_plan_info(gtp_ctx ctx, gtp_plan_stats* out);
 
 /*
  * Forward: power_mw[b] (DEVICE, [n_bins], FP32) = binned power for net loads

@@ -26,7 +26,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 SO_PATH = os.path.join(_HERE, "libgtpower.so")
-_SRC = os.path.join(_HERE, "csrc", "gtpower.hip")
+_SRCS = [os.path.join(_HERE, "csrc", "gtpower.hip"), os.path.join(_HERE, "csrc", "gtp_pack.hip")]
 
 HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-shared", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -36,7 +36,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "HIP", 4: "NOT_LOADE
 
 ABI_SYMBOLS = ["gtp_create", "gtp_destroy", "gtp_set_stream", "gtp_last_error", "gtp_sync", "gtp_load_library",
                "gtp_load_netlist", "gtp_load_events", "gtp_bad_event", "gtp_set_params", "gtp_num_bins",
-               "gtp_set_tuning", "gtp_get_tuning", "gtp_forward", "gtp_adjoint", "gtp_debug_event_trace",
+               "gtp_set_tuning", "gtp_get_tuning", "gtp_plan_info", "gtp_forward", "gtp_adjoint", "gtp_debug_event_trace",
                "gtp_device_bytes", "gtp_profile_enable", "gtp_profile_read"]
 
 
@@ -44,7 +44,7 @@ def build(out: Optional[str] = None) -> str:
     """Compile libgtpower.so for gfx950 in-tree with hipcc (always recompiles)."""
     out = out or SO_PATH
     tmp = out + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, _SRC]
+    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, *_SRCS]
     subprocess.check_call(cmd)
     os.replace(tmp, out)
     return out
@@ -78,6 +78,12 @@ class _Tuning(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("bins_per_tile_log2", ctypes.c_int32)]
 
 
+class _PlanStats(ctypes.Structure):
+    _fields_ = [("n_events_packed", ctypes.c_int64), ("n_units", ctypes.c_int64), ("n_groups", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int32), ("tile_log2", ctypes.c_int32), ("max_tile_groups", ctypes.c_int32),
+                ("packed_bytes", ctypes.c_int64), ("pack_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -97,6 +103,7 @@ def load_library(path: Optional[str] = None):
         "gtp_load_netlist": [vp, i64, i64, vp, vp, vp], "gtp_load_events": [vp, ctypes.POINTER(_Events), i32],
         "gtp_set_params": [vp, ctypes.POINTER(_Params)], "gtp_num_bins": [vp, ctypes.POINTER(i64)],
         "gtp_set_tuning": [vp, ctypes.POINTER(_Tuning)], "gtp_get_tuning": [vp, ctypes.POINTER(_Tuning)],
+        "gtp_plan_info": [vp, ctypes.POINTER(_PlanStats)],
         "gtp_forward": [vp, vp, vp, vp], "gtp_adjoint": [vp, vp, vp, vp, vp, vp],
         "gtp_debug_event_trace": [vp, vp, vp],
     }
@@ -232,6 +239,12 @@ class Context:
         tu = _Tuning()
         self._chk(self.L.gtp_get_tuning(self.h, ctypes.byref(tu)))
         return dict(algo=tu.algo, bins_per_tile_log2=tu.bins_per_tile_log2)
+
+    def plan_info(self) -> dict:
+        """Statistics of the packed layout (built on demand; synchronises)."""
+        ps = _PlanStats()
+        self._chk(self.L.gtp_plan_info(self.h, ctypes.byref(ps)))
+        return {k: getattr(ps, k) for k, _ in _PlanStats._fields_}
 
     def device_bytes(self) -> int:
         return self.L.gtp_device_bytes(self.h)

@@ -1,25 +1,31 @@
 // Device side of the binned power-waveform library (gfx950, wave64).
 //
 // Data layout in HBM (all struct-of-arrays):
-//   events   t int64, pin_bit uint8 ((pin << 1) | new value), slew float,
-//            gate-major CSR gate_off int64[G+1] (borrowed from the caller);
+//   events   the caller's gate-major CSR arrays: t int64, pin_bit uint8
+//            ((pin << 1) | new value), slew float, gate_off int64[G+1]
+//            (borrowed), and the library's packed copy of them (built once
+//            per event set and bin width; see gtp_pack.h): per time tile,
+//            "units" of at most 16 consecutive events of one gate, 64 units
+//            per wavefront group, events stored unit-interleaved so that the
+//            k-th events of a group's units are adjacent;
 //   library  per cell a meta record, the (state, dir) -> table map stored as
 //            the table's first quad index, leakage values, slew axis and
-//            reciprocal segment widths (all staged in LDS by every kernel),
-//            and the tables as "quads": for table T and axis cell (i, j) the
-//            four corners (T[i][j], T[i][j+1], T[i+1][j], T[i+1][j+1]) as one
+//            reciprocal segment widths (staged in LDS by every kernel), and
+//            the tables as "quads": for table T and axis cell (i, j) the four
+//            corners (T[i][j], T[i][j+1], T[i+1][j], T[i+1][j+1]) as one
 //            16-byte vector, so an interpolation is one 16-byte gather;
-//   gates    a 32-byte prepared record per gate, rebuilt on every call from
-//            the net loads and leakage scales;
+//   gates    per call, a 16-byte parameter record per gate (load-axis
+//            segment and weight, switching energy, leakage scale);
 //   bins     int64 fixed-point accumulators X (energy) and S (leakage steps).
 //
-// Fixed point. Energies are accumulated as integers in units of 2^-k nW*ps
-// (1 fJ = 1e6 nW*ps) and leakage rates in units of 2^-k nW, so sums are exact
-// and independent of the order of accumulation. The leakage rate of a gate in
-// input state s is quantised once, q = rint(lambda * leak[s] * 2^k) (float),
-// and every input event adds the step q(after) - q(before): per gate the steps
-// telescope exactly, so the rate at any time is exactly the quantised rate of
-// the state held.
+// Fixed point. With E = 2^-m fJ the energy unit and R = 1e6 * 2^-m nW the
+// leakage-rate unit (so that R * 1 ps = E), every contribution is an integer
+// and sums are exact and independent of the order of accumulation. An event
+// energy e (FP32, fJ) becomes e * 2^m exactly (split into two 32-bit halves,
+// see energy_fixed). The leakage rate of a gate in input state s is quantised
+// once, q = rint(lambda * leak[s] * 2^m * 1e-6) (FP32), and every input event
+// adds the step q(after) - q(before): per gate the steps telescope exactly, so
+// the rate at any time is exactly the quantised rate of the state held.
 //
 // Leakage in step form (an exact rewrite of the interval rule of Sec. 2.3,
 // Eq. leakage energy): with R(t) = sum_g q_g(s_g(t)) the total rate, the
@@ -32,13 +38,19 @@
 
 namespace gtp {
 
-constexpr int kLaneEvents = 16;       // consecutive events per lane block
-constexpr int kFwdThreads = 256;      // threads of the event-walking kernels
-constexpr int kSubChunk = kLaneEvents * kFwdThreads;  // events per pass of a workgroup
-constexpr int kTileThreads = 1024;    // threads of the tile accumulation kernel
+constexpr int kLaneEvents = 16;       // events per lane block / per unit (max)
+constexpr int kFwdThreads = 256;      // threads of the gate-major walking kernels
+constexpr int kTileThreads = 512;     // threads of the packed forward kernel
+constexpr int kGroupUnits = 64;       // units per wavefront group (one per lane)
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Packed event word: bits [0, 27) in-tile time (bin_in_tile << r_bits | r),
+// [27, 31) pin (15 marks nothing), bit 31 the new value.
+constexpr int kPinShift = 27;
+constexpr uint32_t kTimeMask = (1u << kPinShift) - 1u;
+constexpr int kMaxPin = 14;
 
 // Per-cell record staged in LDS.
 struct CellMeta {
@@ -60,7 +72,7 @@ struct LibView {
   int32_t lds_words;        // 32-bit words of the LDS image
 };
 
-// Prepared gate record (32 bytes).
+// Prepared gate record (32 bytes), gate-major kernels.
 struct GatePrep {
   int32_t cell;
   uint32_t init;      // bit p = initial value of pin p
@@ -72,6 +84,16 @@ struct GatePrep {
   float dbeta_dc;     // 1 / (L[j+1] - L[j])
 };
 static_assert(sizeof(GatePrep) == 32, "GatePrep is two 16-byte loads");
+
+// Per-gate parameters of the packed forward (16 bytes), indexed by the
+// cell-sorted gate index; esw_fall = esw_rise (sw_mode 0) or 0 (sw_mode 1).
+struct GateParam {
+  float beta;
+  float lam;
+  float esw_rise;
+  uint32_t cell_jq;   // cell << 8 | jq
+};
+static_assert(sizeof(GateParam) == 16, "GateParam is one 16-byte load");
 
 // Unsigned division of a 32-bit value by an invariant divisor (Granlund and
 // Montgomery, "Division by invariant integers using multiplication", PLDI
@@ -125,9 +147,24 @@ __device__ __forceinline__ LdsLib stage_library(const LibView& L, uint32_t* lds)
   return S;
 }
 
-// Quantised leakage rate of a state (units 2^-k nW).
-__device__ __forceinline__ int32_t qrate(float lam, float leak, float scale_k) {
-  return (int32_t)rintf(__fmul_rn(__fmul_rn(lam, leak), scale_k));
+// Quantised leakage rate of a state (units R = 1e6 * 2^-m nW; rate_scale =
+// FP32(2^m * 1e-6)).
+__device__ __forceinline__ int32_t qrate(float lam, float leak, float rate_scale) {
+  return (int32_t)rintf(__fmul_rn(__fmul_rn(lam, leak), rate_scale));
+}
+
+// Energy e (fJ) in units of 2^-40 fJ... generally 2^-m fJ with m = 32 + sh:
+// hi = floor(e * 2^sh), lo = (e * 2^sh - hi) * 2^32. Both steps are exact for
+// |e| < 2^(31-sh) (the fraction has at most 24 significant bits), so the
+// result is e * 2^m truncated toward minus infinity at 2^-m: exact whenever
+// e is a multiple of 2^-m, which holds for every FP32 e >= 2^(23-m).
+__device__ __forceinline__ int64_t energy_fixed(float e, float two_sh) {
+  const float a = __fmul_rn(e, two_sh);
+  const float h = floorf(a);
+  const float f = __fmul_rn(__fsub_rn(a, h), 4294967296.0f);
+  const int32_t hi = (int32_t)h;
+  const uint32_t lo = (uint32_t)f;
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)lo);
 }
 
 // Slew segment i = clamp(#knots <= slew - 1, 0, n-2) and its weight alpha.
@@ -155,16 +192,133 @@ __device__ __forceinline__ float bilerp_dbeta(float4 q, float alpha) {
   return __fmaf_rn(alpha, __fsub_rn(d1, d0), d0);
 }
 
-// Energy contribution of one event as an integer in units of 2^-k nW*ps.
-__device__ __forceinline__ int64_t dyn_fixed(float e_fj, double dyn_scale) {
-  return __double2ll_rn((double)e_fj * dyn_scale);
-}
-
 // Per-event arithmetic shared by every event-walking kernel.
 struct EventOut {
   float e;        // internal + switching energy (fJ)
-  int32_t delta;  // leakage step (units 2^-k nW), 0 for output events
+  int32_t delta;  // leakage step (units R), 0 for output events
   int32_t s;      // input state looked up (before the event's group)
 };
+
+// Constants of the fixed-point conversion, shared by all paths.
+struct FixArgs {
+  float rate_scale;   // FP32(2^m * 1e-6): nW -> R units
+  float two_sh;       // 2^(m-32)
+};
+
+struct EvView {
+  const int64_t* t;
+  const uint8_t* pb;
+  const float* slew;
+  const int64_t* gate_off;
+  int64_t n;        // events
+  int64_t n_gates;
+};
+
+// ---------------------------------------------------------------------------
+// gate-major lane-block walker
+// ---------------------------------------------------------------------------
+// The gate-major event array is cut into lane blocks of kLaneEvents
+// consecutive events. One lane walks one block in order, so the gate state is
+// a running register (each event toggles one pin: the state is the gate's
+// initial bits XOR the parity of the toggles seen so far). A block may hold
+// the tail of one gate and many short gates or a slice of one long gate. The
+// plan gives every block its first gate and the toggle parity that gate
+// carries into the block.
+//
+// Visitor interface:
+//   begin_gate(g, par)  par = parity the gate carries into this block
+//   event(e, t, pin, v, slew, par_group, par_now)
+//   end_gate(g)
+// Events of one gate that share a timestamp form a group; par_group is the
+// parity before the group (Algorithm 1 looks up every event of a group with
+// the state before it), par_now the parity before this event.
+template <class V>
+__device__ __forceinline__ void walk_block(int64_t kb, const EvView& E, const uint2* __restrict__ plan, V& vis) {
+  const int64_t e0 = kb * kLaneEvents;
+  if (e0 >= E.n) return;
+  const int nk = (int)min((int64_t)kLaneEvents, E.n - e0);
+  int64_t tt[kLaneEvents];
+  uint32_t pw[kLaneEvents / 4];
+  float sl[kLaneEvents];
+  if (nk == kLaneEvents) {
+    const longlong2* tp = reinterpret_cast<const longlong2*>(E.t + e0);
+#pragma unroll
+    for (int k = 0; k < kLaneEvents / 2; ++k) {
+      longlong2 v = tp[k];
+      tt[2 * k] = v.x;
+      tt[2 * k + 1] = v.y;
+    }
+    const uint4 p4 = *reinterpret_cast<const uint4*>(E.pb + e0);
+    pw[0] = p4.x; pw[1] = p4.y; pw[2] = p4.z; pw[3] = p4.w;
+    const float4* sp = reinterpret_cast<const float4*>(E.slew + e0);
+#pragma unroll
+    for (int k = 0; k < kLaneEvents / 4; ++k) {
+      float4 v = sp[k];
+      sl[4 * k] = v.x; sl[4 * k + 1] = v.y; sl[4 * k + 2] = v.z; sl[4 * k + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kLaneEvents / 4; ++k) pw[k] = 0;
+#pragma unroll
+    for (int k = 0; k < kLaneEvents; ++k) {
+      if (k < nk) {
+        tt[k] = E.t[e0 + k];
+        pw[k >> 2] |= (uint32_t)E.pb[e0 + k] << (8 * (k & 3));
+        sl[k] = E.slew[e0 + k];
+      } else {
+        tt[k] = 0;
+        sl[k] = 0.f;
+      }
+    }
+  }
+  const uint2 pl = plan[kb];
+  int64_t g = (int64_t)pl.x;
+  uint32_t par = pl.y;
+  int64_t gstart = E.gate_off[g];
+  int64_t next_off = E.gate_off[g + 1];
+  // A timestamp group may straddle the block start: the group-start parity
+  // then excludes the group's earlier events (looked back in memory).
+  uint32_t par_gs = par;
+  int64_t tprev = INT64_MIN;
+  if (e0 > gstart && E.t[e0 - 1] == tt[0]) {
+    uint32_t x = 0;
+    int64_t j = e0 - 1;
+    int guard = 0;
+    while (j >= gstart && E.t[j] == tt[0] && guard < 64) {
+      x ^= 1u << ((E.pb[j] >> 1) & 31);
+      --j;
+      ++guard;
+    }
+    par_gs = par ^ x;
+    tprev = tt[0];
+  }
+  vis.begin_gate(g, par);
+#pragma unroll
+  for (int k = 0; k < kLaneEvents; ++k) {
+    if (k < nk) {
+      const int64_t e = e0 + k;
+      if (e >= next_off) {
+        vis.end_gate(g);
+        while (e >= next_off && g < E.n_gates - 1) {
+          ++g;
+          next_off = E.gate_off[g + 1];
+        }
+        par = 0;
+        tprev = INT64_MIN;
+        vis.begin_gate(g, 0u);
+      }
+      const uint32_t b = (pw[k >> 2] >> (8 * (k & 3))) & 0xffu;
+      const int pin = (int)(b >> 1);
+      const int v = (int)(b & 1u);
+      if (tt[k] != tprev) {
+        par_gs = par;
+        tprev = tt[k];
+      }
+      vis.event(e, tt[k], pin, v, sl[k], par_gs, par);
+      par ^= 1u << (pin & 31);
+    }
+  }
+  vis.end_gate(g);
+}
 
 }  // namespace gtp

@@ -18,111 +18,6 @@
 
 namespace gtp {
 
-struct EvView {
-  const int64_t* t;
-  const uint8_t* pb;
-  const float* slew;
-  const int64_t* gate_off;
-  int64_t n;        // events
-  int64_t n_gates;
-};
-
-// ---------------------------------------------------------------------------
-// lane-block walker
-// ---------------------------------------------------------------------------
-// Visitor interface:
-//   begin_gate(g, par)  par = parity the gate carries into this block
-//   event(e, t, pin, v, slew, par_group, par_now)
-//   end_gate(g)
-template <class V>
-__device__ __forceinline__ void walk_block(int64_t kb, const EvView& E, const uint2* __restrict__ plan, V& vis) {
-  const int64_t e0 = kb * kLaneEvents;
-  if (e0 >= E.n) return;
-  const int nk = (int)min((int64_t)kLaneEvents, E.n - e0);
-  int64_t tt[kLaneEvents];
-  uint32_t pw[kLaneEvents / 4];
-  float sl[kLaneEvents];
-  if (nk == kLaneEvents) {
-    const longlong2* tp = reinterpret_cast<const longlong2*>(E.t + e0);
-#pragma unroll
-    for (int k = 0; k < kLaneEvents / 2; ++k) {
-      longlong2 v = tp[k];
-      tt[2 * k] = v.x;
-      tt[2 * k + 1] = v.y;
-    }
-    const uint4 p4 = *reinterpret_cast<const uint4*>(E.pb + e0);
-    pw[0] = p4.x; pw[1] = p4.y; pw[2] = p4.z; pw[3] = p4.w;
-    const float4* sp = reinterpret_cast<const float4*>(E.slew + e0);
-#pragma unroll
-    for (int k = 0; k < kLaneEvents / 4; ++k) {
-      float4 v = sp[k];
-      sl[4 * k] = v.x; sl[4 * k + 1] = v.y; sl[4 * k + 2] = v.z; sl[4 * k + 3] = v.w;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < kLaneEvents / 4; ++k) pw[k] = 0;
-#pragma unroll
-    for (int k = 0; k < kLaneEvents; ++k) {
-      if (k < nk) {
-        tt[k] = E.t[e0 + k];
-        pw[k >> 2] |= (uint32_t)E.pb[e0 + k] << (8 * (k & 3));
-        sl[k] = E.slew[e0 + k];
-      } else {
-        tt[k] = 0;
-        sl[k] = 0.f;
-      }
-    }
-  }
-  const uint2 pl = plan[kb];
-  int64_t g = (int64_t)pl.x;
-  uint32_t par = pl.y;
-  int64_t gstart = E.gate_off[g];
-  int64_t next_off = E.gate_off[g + 1];
-  // A timestamp group may straddle the block start: the group-start parity
-  // then excludes the group's earlier events (looked back in memory).
-  uint32_t par_gs = par;
-  int64_t tprev = INT64_MIN;
-  if (e0 > gstart && E.t[e0 - 1] == tt[0]) {
-    uint32_t x = 0;
-    int64_t j = e0 - 1;
-    int guard = 0;
-    while (j >= gstart && E.t[j] == tt[0] && guard < 64) {
-      x ^= 1u << ((E.pb[j] >> 1) & 31);
-      --j;
-      ++guard;
-    }
-    par_gs = par ^ x;
-    tprev = tt[0];
-  }
-  vis.begin_gate(g, par);
-#pragma unroll
-  for (int k = 0; k < kLaneEvents; ++k) {
-    if (k < nk) {
-      const int64_t e = e0 + k;
-      if (e >= next_off) {
-        vis.end_gate(g);
-        while (e >= next_off && g < E.n_gates - 1) {
-          ++g;
-          next_off = E.gate_off[g + 1];
-        }
-        par = 0;
-        tprev = INT64_MIN;
-        vis.begin_gate(g, 0u);
-      }
-      const uint32_t b = (pw[k >> 2] >> (8 * (k & 3))) & 0xffu;
-      const int pin = (int)(b >> 1);
-      const int v = (int)(b & 1u);
-      if (tt[k] != tprev) {
-        par_gs = par;
-        tprev = tt[k];
-      }
-      vis.event(e, tt[k], pin, v, sl[k], par_gs, par);
-      par ^= 1u << (pin & 31);
-    }
-  }
-  vis.end_gate(g);
-}
-
 // Lookup and energy of one event (shared by every path so results agree bit
 // for bit). Updates the running quantised leakage rate q_cur.
 struct GateCtx {
@@ -133,7 +28,7 @@ struct GateCtx {
 };
 
 __device__ __forceinline__ void gate_begin(GateCtx& G, const GatePrep* __restrict__ gprep, const LdsLib& L, int64_t g,
-                                           uint32_t par, float scale_k) {
+                                           uint32_t par, float rate_scale) {
   const int4* src = reinterpret_cast<const int4*>(gprep + g);
   int4 a = src[0], b = src[1];
   G.gp.cell = a.x; G.gp.init = (uint32_t)a.y; G.gp.jq = a.z; G.gp.beta = __int_as_float(a.w);
@@ -142,13 +37,14 @@ __device__ __forceinline__ void gate_begin(GateCtx& G, const GatePrep* __restric
   G.cm = L.meta[G.gp.cell];
   G.in_mask = (1u << G.cm.n_in) - 1u;
   const uint32_t s = (G.gp.init ^ par) & G.in_mask;
-  G.q_cur = qrate(G.gp.lam, L.leak[G.cm.leak_off + (int)s], scale_k);
+  G.q_cur = qrate(G.gp.lam, L.leak[G.cm.leak_off + (int)s], rate_scale);
 }
 
 struct LutArgs {
   const float4* __restrict__ quads;
   int32_t n_slew, n_load;
-  float scale_k;
+  float rate_scale;   // FP32(2^m * 1e-6)
+  float two_sh;       // 2^(m-32)
 };
 
 __device__ __forceinline__ EventOut event_energy(GateCtx& G, const LdsLib& L, const LutArgs& A, int pin, int v,
@@ -165,7 +61,7 @@ __device__ __forceinline__ EventOut event_energy(GateCtx& G, const LdsLib& L, co
   int32_t delta = 0;
   if (pin < G.cm.n_in) {
     const uint32_t s_new = (G.gp.init ^ par ^ (1u << pin)) & G.in_mask;
-    const int32_t qn = qrate(G.gp.lam, L.leak[G.cm.leak_off + (int)s_new], A.scale_k);
+    const int32_t qn = qrate(G.gp.lam, L.leak[G.cm.leak_off + (int)s_new], A.rate_scale);
     delta = qn - G.q_cur;
     G.q_cur = qn;
   }
@@ -176,120 +72,185 @@ __device__ __forceinline__ EventOut event_energy(GateCtx& G, const LdsLib& L, co
 }
 
 // ---------------------------------------------------------------------------
-// forward, time-tiled path
+// forward, packed tile-major path
 // ---------------------------------------------------------------------------
-struct FwdArgs {
-  EvView ev;
-  const uint2* plan;
-  const GatePrep* gprep;
+// One workgroup per time tile: the tile's 2^tile_log2 bins (X and S, int64)
+// live in LDS, every wavefront takes whole 64-unit groups of the tile (one
+// unit per lane, see gtp_pack.h) and accumulates with LDS atomics; at the
+// end the tile's bins are stored (each bin belongs to exactly one tile, so
+// no global atomics and no zero fill are needed).
+struct PackedFwdArgs {
+  const uint32_t* w32;
+  const float* slw;
+  const uint2* desc;
+  const int64_t* grp_off;
+  const int32_t* tile_grp;
+  const GateParam* gparam;   // per cell-sorted gate, this call
   LibView lib;
   LutArgs lut;
   BinSpec bins;
-  int64_t group_events;     // events per workgroup (multiple of kSubChunk)
-  const uint32_t* off_gm;   // [n_groups][n_tiles] first record slot
-  uint3* rec;               // records (loc, energy bits, leakage step)
-  int64_t n_rec;
-  int32_t* dbg_state;       // optional per-event trace
-  int64_t* dbg_bin;
-};
-
-struct FwdVisitor {
-  const FwdArgs* A;
-  const LdsLib* L;
-  uint32_t* cursor;
-  GateCtx G;
-  __device__ __forceinline__ void begin_gate(int64_t g, uint32_t par) {
-    gate_begin(G, A->gprep, *L, g, par, A->lut.scale_k);
-  }
-  __device__ __forceinline__ void end_gate(int64_t) {}
-  __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
-                                        uint32_t par) {
-    const EventOut o = event_energy(G, *L, A->lut, pin, v, slew, par_gs, par);
-    const BinSpec& B = A->bins;
-    if (t < 0 || t >= B.t_end) return;  // invalid input: dropped (the plan drops it too)
-    const int64_t b = bin_of(t, B);
-    if (A->dbg_state) {
-      A->dbg_state[e] = o.s;
-      A->dbg_bin[e] = b;
-    }
-    const uint32_t r = (uint32_t)(t - b * B.D);
-    const uint32_t tile = (uint32_t)(b >> B.tile_log2);
-    const uint32_t loc = (((uint32_t)b & ((1u << B.tile_log2) - 1u)) << B.r_bits) | r;
-    const uint32_t pos = atomicAdd(&cursor[tile], 1u);
-    if ((int64_t)pos < A->n_rec) A->rec[pos] = make_uint3(loc, __float_as_uint(o.e), (uint32_t)o.delta);
-  }
-};
-
-__global__ void __launch_bounds__(kFwdThreads) k_fwd_records(FwdArgs a) {
-  extern __shared__ uint32_t lds[];
-  const LdsLib L = stage_library(a.lib, lds);
-  uint32_t* cursor = lds + a.lib.lds_words;
-  const int64_t grp = blockIdx.x;
-  for (int b = threadIdx.x; b < a.bins.n_tiles; b += blockDim.x) cursor[b] = a.off_gm[grp * a.bins.n_tiles + b];
-  __syncthreads();
-  FwdVisitor vis;
-  vis.A = &a;
-  vis.L = &L;
-  vis.cursor = cursor;
-  const int64_t g0 = grp * a.group_events;
-  const int64_t g1 = min(a.ev.n, g0 + a.group_events);
-  for (int64_t sub = g0; sub < g1; sub += kSubChunk) walk_block(sub / kLaneEvents + threadIdx.x, a.ev, a.plan, vis);
-}
-
-// Per tile: accumulate its records into LDS bins, then store the tile.
-struct TileArgs {
-  const uint3* rec;
-  const uint32_t* tile_off;  // [n_tiles + 1]
+  int32_t sw_mode;
   int64_t* X;
   int64_t* S;
-  BinSpec bins;
-  double dyn_scale;          // 2^k * 1e6: fJ -> units of 2^-k nW*ps
+  int32_t* dbg_state;        // optional per-event trace (gate-major index)
+  int64_t* dbg_bin;
+  const int64_t* dsrc;
 };
 
-__global__ void __launch_bounds__(kTileThreads) k_tile_accum(TileArgs a) {
-  extern __shared__ unsigned long long tl[];
-  const int nb = 1 << a.bins.tile_log2;
-  unsigned long long* xs = tl;
-  unsigned long long* ss = tl + nb;
-  for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) tl[i] = 0ull;
+__device__ __forceinline__ size_t packed_bins_word_offset(int32_t lib_words) { return (size_t)((lib_words + 1) & ~1); }
+
+__global__ void __launch_bounds__(kTileThreads) k_fwd_packed(PackedFwdArgs a) {
+  extern __shared__ uint32_t lds[];
+  const LdsLib L = stage_library(a.lib, lds);
+  const BinSpec& B = a.bins;
+  const int nb = 1 << B.tile_log2;
+  unsigned long long* xs = reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.lib.lds_words));
+  unsigned long long* ss = xs + nb;
+  for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) xs[i] = 0ull;
   __syncthreads();
-  const int64_t tile = blockIdx.x;
-  const int64_t r0 = a.tile_off[tile], r1 = a.tile_off[tile + 1];
-  const uint32_t rmask = (1u << a.bins.r_bits) - 1u;
-  const int64_t D = a.bins.D;
-  constexpr int U = 4;
-  int64_t r = r0 + threadIdx.x;
-  for (; r + (U - 1) * kTileThreads < r1; r += U * kTileThreads) {
-    uint3 v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = a.rec[r + u * kTileThreads];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t bl = (v[u].x >> a.bins.r_bits) & (uint32_t)(nb - 1);
-      const int64_t rr = (int64_t)(v[u].x & rmask);
-      const int32_t d = (int32_t)v[u].z;
-      const int64_t x = dyn_fixed(__uint_as_float(v[u].y), a.dyn_scale) + (int64_t)d * (D - rr);
-      atomicAdd(&xs[bl], (unsigned long long)x);
-      if (d != 0) atomicAdd(&ss[bl], (unsigned long long)(int64_t)d);
+  const int32_t tile = blockIdx.x;
+  const int64_t g0 = a.tile_grp[tile], g1 = a.tile_grp[tile + 1];
+  const int lane = (int)(threadIdx.x & 63);
+  const int nwave = (int)(blockDim.x >> 6);
+  const uint32_t rmask = (1u << B.r_bits) - 1u;
+  const int32_t qstride = a.lut.n_load - 1;
+  for (int64_t gi = g0 + (threadIdx.x >> 6); gi < g1; gi += nwave) {
+    const uint2 d = a.desc[gi * kGroupUnits + lane];
+    const bool valid = d.x != 0xffffffffu;
+    const int len = valid ? (int)(d.x >> 28) + 1 : 0;
+    GateParam gp;
+    if (valid) {
+      gp = a.gparam[d.x & 0x0fffffffu];
+    } else {
+      gp.beta = 0.f; gp.lam = 0.f; gp.esw_rise = 0.f; gp.cell_jq = 0u;
+    }
+    const int cell = (int)(gp.cell_jq >> 8);
+    const int jq = (int)(gp.cell_jq & 0xffu);
+    const CellMeta cm = L.meta[cell];
+    const uint32_t in_mask = (1u << cm.n_in) - 1u;
+    const uint32_t st = d.y & 0xffffu;
+    uint32_t par = 0;
+    uint32_t par_gs = ((d.y >> 16) ^ st) & 0xffffu;
+    const float esw_fall = a.sw_mode ? 0.0f : gp.esw_rise;
+    int32_t q_cur = qrate(gp.lam, L.leak[cm.leak_off + (int)(st & in_mask)], a.lut.rate_scale);
+    const float* sax = L.slew + cm.axis_off;
+    const float* sinv = L.slew_inv + cm.axis_off;
+    int64_t off = a.grp_off[gi];
+    uint32_t tprev = 0;
+    for (int kk = 0; kk < kLaneEvents; ++kk) {
+      const bool on = len > kk;
+      const uint64_t m = __ballot(on);
+      if (m == 0) break;
+      if (on) {
+        const int64_t pos = off + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        const uint32_t w = a.w32[pos];
+        const float slew = a.slw[pos];
+        const uint32_t tl = w & kTimeMask;
+        const int pin = (int)((w >> kPinShift) & 15u);
+        const int v = (int)(w >> 31);
+        if (kk > 0 && tl != tprev) par_gs = par;
+        tprev = tl;
+        const uint32_t s = (st ^ par_gs) & in_mask;
+        const int32_t qb = L.map_q[cm.map_off + 2 * (int)s + v];
+        int i;
+        float alpha;
+        slew_segment(sax, sinv, a.lut.n_slew, slew, i, alpha);
+        const float4 q = a.lut.quads[qb + i * qstride + jq];
+        float e = bilerp_quad(q, alpha, gp.beta);
+        if (pin == cm.n_in) e = __fadd_rn(e, v ? gp.esw_rise : esw_fall);
+        int64_t x = energy_fixed(e, a.lut.two_sh);
+        const uint32_t bl = tl >> B.r_bits;
+        if (pin < cm.n_in) {
+          const uint32_t s_new = (st ^ par ^ (1u << pin)) & in_mask;
+          const int32_t qn = qrate(gp.lam, L.leak[cm.leak_off + (int)s_new], a.lut.rate_scale);
+          const int32_t dq = qn - q_cur;
+          q_cur = qn;
+          if (dq != 0) {
+            x += (int64_t)dq * (B.D - (int64_t)(tl & rmask));
+            atomicAdd(&ss[bl], (unsigned long long)(int64_t)dq);
+          }
+        }
+        atomicAdd(&xs[bl], (unsigned long long)x);
+        par ^= 1u << pin;
+        if (a.dbg_state) {
+          const int64_t e_src = a.dsrc[gi * kGroupUnits + lane] + kk;
+          a.dbg_state[e_src] = (int32_t)s;
+          a.dbg_bin[e_src] = ((int64_t)tile << B.tile_log2) + bl;
+        }
+      }
+      off += __popcll(m);
     }
   }
-  for (; r < r1; r += kTileThreads) {
-    const uint3 v = a.rec[r];
-    const uint32_t bl = (v.x >> a.bins.r_bits) & (uint32_t)(nb - 1);
-    const int64_t rr = (int64_t)(v.x & rmask);
-    const int32_t d = (int32_t)v.z;
-    const int64_t x = dyn_fixed(__uint_as_float(v.y), a.dyn_scale) + (int64_t)d * (D - rr);
-    atomicAdd(&xs[bl], (unsigned long long)x);
-    if (d != 0) atomicAdd(&ss[bl], (unsigned long long)(int64_t)d);
-  }
   __syncthreads();
-  const int64_t b0 = tile * nb;
+  const int64_t b0 = (int64_t)tile << B.tile_log2;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    if (b0 + i < a.bins.n_bins) {
+    if (b0 + i < B.n_bins) {
       a.X[b0 + i] = (int64_t)xs[i];
       a.S[b0 + i] = (int64_t)ss[i];
     }
   }
+}
+
+// Per-call gate parameters in cell-sorted order, plus the sum of the gates'
+// quantised initial leakage rates.
+struct GateParamArgs {
+  const int32_t* gperm;      // sorted index -> gate
+  const int32_t* gcell;      // sorted index -> cell
+  const int32_t* gate_out;
+  const uint32_t* gate_init;
+  const float* net_load;
+  const float* leak_scale;   // may be null (all 1)
+  const CellMeta* meta;
+  const float* leak;
+  const float* load;         // [n_cells * n_load]
+  const float* load_inv;
+  int32_t n_load;
+  int64_t n_gates;
+  double vdd;
+  int32_t sw_mode;
+  float rate_scale;
+  float max_scale;
+  GateParam* out;
+  unsigned long long* L0;
+  int32_t* flag;             // bit 0: a leakage scale out of range
+};
+
+__global__ void __launch_bounds__(256) k_gate_params(GateParamArgs a) {
+  __shared__ long long red[256];
+  const int64_t gs = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  long long q0 = 0;
+  if (gs < a.n_gates) {
+    const int32_t g = a.gperm[gs];
+    const int32_t c = a.gcell[gs];
+    const CellMeta cm = a.meta[c];
+    const float C = a.net_load[a.gate_out[g]];
+    float lam = a.leak_scale ? a.leak_scale[g] : 1.0f;
+    if (!(lam >= 0.0f && lam <= a.max_scale)) {
+      atomicOr(a.flag, 1);
+      lam = 0.0f;
+    }
+    const float* la = a.load + (int64_t)c * a.n_load;
+    int j = 0;
+    for (int m = 1; m < a.n_load - 1; ++m) j += (la[m] <= C) ? 1 : 0;
+    const float inv = a.load_inv[(int64_t)c * a.n_load + j];
+    GateParam p;
+    p.beta = __fmul_rn(__fsub_rn(C, la[j]), inv);
+    const double v2 = a.vdd * a.vdd;
+    p.esw_rise = (a.sw_mode == 0) ? (float)(0.5 * (double)C * v2) : (float)((double)C * v2);
+    p.lam = lam;
+    p.cell_jq = ((uint32_t)c << 8) | (uint32_t)j;
+    a.out[gs] = p;
+    const uint32_t s0 = a.gate_init[g] & ((1u << cm.n_in) - 1u);
+    q0 = (long long)qrate(lam, a.leak[cm.leak_off + (int)s0], a.rate_scale);
+  }
+  red[threadIdx.x] = q0;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != 0) atomicAdd(a.L0, (unsigned long long)red[0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -303,7 +264,6 @@ struct SerialArgs {
   BinSpec bins;
   unsigned long long* X;
   unsigned long long* S;
-  double dyn_scale;
 };
 
 __global__ void __launch_bounds__(kFwdThreads) k_gate_serial(SerialArgs a) {
@@ -315,7 +275,7 @@ __global__ void __launch_bounds__(kFwdThreads) k_gate_serial(SerialArgs a) {
   const int64_t e0 = a.ev.gate_off[g], e1 = a.ev.gate_off[g + 1];
   if (e1 <= e0) return;
   GateCtx G;
-  gate_begin(G, a.gprep, L, g, 0u, a.lut.scale_k);
+  gate_begin(G, a.gprep, L, g, 0u, a.lut.rate_scale);
   uint32_t par = 0, par_gs = 0;
   int64_t tprev = INT64_MIN;
   const BinSpec& B = a.bins;
@@ -332,7 +292,7 @@ __global__ void __launch_bounds__(kFwdThreads) k_gate_serial(SerialArgs a) {
     if (t < 0 || t >= B.t_end) continue;
     const int64_t b = bin_of(t, B);
     const int64_t rr = t - b * B.D;
-    const int64_t x = dyn_fixed(o.e, a.dyn_scale) + (int64_t)o.delta * (B.D - rr);
+    const int64_t x = energy_fixed(o.e, a.lut.two_sh) + (int64_t)o.delta * (B.D - rr);
     atomicAdd(&a.X[b], (unsigned long long)x);
     if (o.delta != 0) atomicAdd(&a.S[b], (unsigned long long)(int64_t)o.delta);
   }
@@ -355,7 +315,8 @@ struct PrepArgs {
   int64_t n_gates;
   double vdd;
   int32_t sw_mode;
-  float scale_k;
+  float rate_scale;   // FP32(2^m * 1e-6)
+  float two_sh;       // 2^(m-32)
   float max_scale;
   GatePrep* out;
   unsigned long long* L0;    // sum of quantised initial leakage rates
@@ -396,7 +357,7 @@ __global__ void __launch_bounds__(256) k_gate_prep(PrepArgs a) {
     p.dbeta_dc = inv;
     a.out[g] = p;
     const uint32_t s0 = p.init & ((1u << cm.n_in) - 1u);
-    q0 = (long long)qrate(lam, a.leak[cm.leak_off + (int)s0], a.scale_k);
+    q0 = (long long)qrate(lam, a.leak[cm.leak_off + (int)s0], a.rate_scale);
   }
   red[threadIdx.x] = q0;
   __syncthreads();
@@ -408,7 +369,7 @@ __global__ void __launch_bounds__(256) k_gate_prep(PrepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// finalize: P_b = (X[b] + D * (L0 + sum_{b'<b} S[b'])) * 2^-k * 1e-6 / D
+// finalize: P_b = (X[b] + D * (L0 + sum_{b'<b} S[b'])) * 2^-m / D  (fJ/ps = mW)
 // ---------------------------------------------------------------------------
 struct FinArgs {
   const int64_t* X;
@@ -417,7 +378,7 @@ struct FinArgs {
   const unsigned long long* L0;
   float* P;
   int64_t n_bins, D, t_end;
-  double out_scale;     // 2^-k * 1e-6 / D
+  double out_scale;     // 2^-m / D
 };
 
 __global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
@@ -464,7 +425,7 @@ struct AdjVisitor {
   uint32_t s_cur;
   double acc_c, acc_l;
   __device__ __forceinline__ void begin_gate(int64_t g, uint32_t par) {
-    gate_begin(G, A->gprep, *L, g, par, A->lut.scale_k);
+    gate_begin(G, A->gprep, *L, g, par, A->lut.rate_scale);
     s_cur = (G.gp.init ^ par) & G.in_mask;
     acc_c = 0.0;
     acc_l = 0.0;
@@ -635,7 +596,7 @@ struct TraceVisitor {
   const LdsLib* L;
   GateCtx G;
   __device__ __forceinline__ void begin_gate(int64_t g, uint32_t par) {
-    gate_begin(G, A->gprep, *L, g, par, A->lut.scale_k);
+    gate_begin(G, A->gprep, *L, g, par, A->lut.rate_scale);
   }
   __device__ __forceinline__ void end_gate(int64_t) {}
   __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
@@ -706,42 +667,14 @@ __global__ void __launch_bounds__(256) k_plan_block_carry(const int64_t* gate_of
   plan[kb].y = carry;
 }
 
-// Records per (tile, workgroup group), tile-major, for the placement scan.
-__global__ void __launch_bounds__(256) k_plan_count(const int64_t* t, int64_t n_events, BinSpec bins,
-                                                    int64_t group_events, int64_t n_groups, uint32_t* cnt_tm) {
-  extern __shared__ uint32_t hist[];
-  for (int i = threadIdx.x; i < bins.n_tiles; i += blockDim.x) hist[i] = 0;
-  __syncthreads();
-  const int64_t grp = blockIdx.x;
-  const int64_t e0 = grp * group_events, e1 = min(n_events, e0 + group_events);
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const int64_t tv = t[e];
-    if (tv < 0 || tv >= bins.t_end) continue;
-    const int64_t b = bin_of(tv, bins);
-    atomicAdd(&hist[(uint32_t)(b >> bins.tile_log2)], 1u);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < bins.n_tiles; i += blockDim.x) cnt_tm[(int64_t)i * n_groups + grp] = hist[i];
-}
-
-__global__ void __launch_bounds__(256) k_plan_tile_off(const uint32_t* off_tm, int64_t n_groups, int32_t n_tiles,
-                                                       uint32_t n_rec, uint32_t* tile_off) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_tiles) tile_off[i] = off_tm[i * n_groups];
-  if (i == n_tiles) tile_off[i] = n_rec;
-}
-
-__global__ void __launch_bounds__(256) k_plan_transpose(const uint32_t* off_tm, uint32_t* off_gm, int64_t n_groups,
-                                                        int32_t n_tiles) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_groups * (int64_t)n_tiles) return;
-  const int64_t grp = i / n_tiles, tile = i - grp * n_tiles;
-  off_gm[i] = off_tm[tile * n_groups + grp];
-}
-
 // ---------------------------------------------------------------------------
 // utilities
 // ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;

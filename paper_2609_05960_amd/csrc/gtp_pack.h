@@ -1,0 +1,82 @@
+// Packed event layout (built once per event set and bin width, read by every
+// forward call).
+//
+// The waveform accumulates every event into the bin of its timestamp, so the
+// forward works one time tile (2^tile_log2 consecutive bins) at a time, with
+// the tile's bins privatised in LDS. The caller's events are gate-major; the
+// pack regroups them by tile without losing the per-gate order the state
+// tracking needs:
+//
+//   unit   at most 16 consecutive events (gate-major order) of one gate that
+//          fall in one tile and in one 16-event block of the gate-major
+//          array. Dense gates thus become many full 16-event units (the
+//          "dense gates cut into time segments" of the density split);
+//          sparse gates become short units. A unit carries its gate and the
+//          gate's pin values before its first event and before that event's
+//          timestamp group (carried-in state).
+//   order  units sorted by (tile, gate block, decreasing length); a gate block
+//          is a run of at most 2^14 cell-sorted gates of one cell, so the
+//          units of one wavefront share a cell (table gathers stay in cache)
+//          and have similar lengths (lanes stay busy).
+//   group  64 consecutive units of one tile, one per lane of a wavefront. The
+//          group's events are stored unit-interleaved: event k of every unit
+//          longer than k, in lane order, then event k+1, ... So the k-th
+//          loads of a wavefront are adjacent words.
+//
+// Arrays (device, owned by the ctx):
+//   w32[n]    packed event word (see gtp_device.h): in-tile time, pin, value
+//   slw[n]    slew (FP32)
+//   desc[64 * n_groups]   unit descriptor: x = cell-sorted gate index
+//             (bits 0..27) | (length-1) << 28, y = pin values before the
+//             unit's first event (bits 0..15) | before its timestamp group
+//             (bits 16..31); x = 0xffffffff for an empty lane
+//   dsrc[64 * n_groups]   gate-major index of the unit's first event (for
+//             the per-event debug trace only)
+//   grp_off[n_groups + 1] first event of each group
+//   tile_grp[n_tiles + 1] first group of each tile
+//   gperm[G]  cell-sorted index -> gate;  gcell[G] cell of each sorted index
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "gtp_device.h"
+
+namespace gtp {
+
+constexpr int kGateBlockLog2 = 14;
+
+struct PackIn {
+  EvView ev;                  // gate-major events (device)
+  const uint2* plan_blk;      // gate-major lane-block plan (device)
+  const int32_t* gate_cell;   // [G] (device)
+  const uint32_t* gate_init;  // [G] (device)
+  std::vector<int32_t> h_gate_cell;  // [G] host copy
+  std::vector<int32_t> n_in;         // [n_cells] inputs per cell
+  BinSpec bins;               // tile_log2 and n_tiles set
+  hipStream_t stream;
+};
+
+struct PackOut {
+  uint32_t* w32 = nullptr;
+  float* slw = nullptr;
+  uint2* desc = nullptr;
+  int64_t* dsrc = nullptr;
+  int64_t* grp_off = nullptr;
+  int32_t* tile_grp = nullptr;
+  int32_t* gperm = nullptr;
+  int32_t* gcell = nullptr;
+  int64_t n_events = 0;       // events packed (valid times)
+  int64_t n_units = 0;
+  int64_t n_groups = 0;
+  int64_t bytes = 0;          // device bytes held by the arrays above
+  int32_t max_tile_groups = 0;
+};
+
+// Builds the packed layout on in.stream (synchronises it). Returns
+// hipSuccess or the first HIP error; on error nothing stays allocated.
+hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len);
+void pack_free(PackOut* out);
+
+}  // namespace gtp

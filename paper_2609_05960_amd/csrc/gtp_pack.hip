@@ -1,0 +1,487 @@
+// Builds the packed, tile-major event layout described in gtp_pack.h.
+//
+// Steps (all on the caller's stream):
+//   1. gate order: gates sorted by cell (stable, host), cut into gate blocks
+//      of at most 2^14 gates of one cell;
+//   2. k_pk_units (count pass): every gate-major lane block of 16 events is
+//      walked in order and split into units wherever the gate or the time
+//      tile changes; units per block are counted, then scanned;
+//   3. k_pk_units (emit pass): the same walk writes one record per unit
+//      (first event, gate, length, carried-in pin values) and its sort key
+//      (tile, gate block, 16 - length);
+//   4. radix sort of the unit keys (hipcub, stable);
+//   5. per tile its first unit; 64 units per group; group event counts,
+//      scanned into group offsets;
+//   6. k_pk_fill: one wavefront per group writes the unit descriptors and
+//      copies the units' events into the unit-interleaved order.
+// The pack runs once per event set and bin width; its time is reported apart
+// from the forward.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
+#include "gtp_pack.h"
+
+namespace gtp {
+namespace {
+
+struct UnitRec {
+  int64_t src;   // gate-major index of the first event
+  uint32_t x;    // cell-sorted gate | (len - 1) << 28
+  uint32_t y;    // pin values before the first event | before its group << 16
+};
+
+struct KeySpec {
+  int32_t gb_bits;                // bits of the gate-block field
+  const int32_t* rank;            // gate -> cell-sorted index
+  const int32_t* cell_start;      // [n_cells] first sorted index of the cell
+  const int32_t* gb_base;         // [n_cells] first gate block of the cell
+};
+
+struct UnitArgs {
+  EvView ev;
+  const uint2* plan;
+  const int32_t* gate_cell;
+  const uint32_t* gate_init;
+  BinSpec bins;
+  KeySpec ks;
+  uint32_t* counts;       // count pass: units per lane block
+  const uint32_t* base;   // emit pass: first unit of each lane block
+  uint64_t* keys;
+  uint32_t* vals;
+  UnitRec* recs;
+};
+
+template <bool kEmit>
+struct UnitVisitor {
+  const UnitArgs* A;
+  int64_t kb;
+  uint32_t n = 0;          // units closed in this block
+  uint32_t init = 0;
+  int32_t gs = 0;          // cell-sorted gate index
+  uint32_t gblock = 0;
+  bool open = false;
+  int64_t u_src = 0;
+  int32_t u_len = 0;
+  int64_t u_tile = 0;
+  uint32_t u_st = 0;
+
+  __device__ __forceinline__ void close() {
+    if (!open) return;
+    if (kEmit) {
+      const uint32_t u = A->base[kb] + n;
+      const uint64_t key = ((uint64_t)u_tile << (A->ks.gb_bits + 5)) | ((uint64_t)gblock << 5) |
+                           (uint64_t)(16 - u_len);
+      A->keys[u] = key;
+      A->vals[u] = u;
+      UnitRec r;
+      r.src = u_src;
+      r.x = (uint32_t)gs | ((uint32_t)(u_len - 1) << 28);
+      r.y = u_st;
+      A->recs[u] = r;
+    }
+    ++n;
+    open = false;
+  }
+  __device__ __forceinline__ void begin_gate(int64_t g, uint32_t) {
+    init = A->gate_init[g];
+    const int32_t c = A->gate_cell[g];
+    gs = A->ks.rank[g];
+    gblock = (uint32_t)(A->ks.gb_base[c] + ((gs - A->ks.cell_start[c]) >> kGateBlockLog2));
+    open = false;
+  }
+  __device__ __forceinline__ void end_gate(int64_t) { close(); }
+  __device__ __forceinline__ void event(int64_t e, int64_t t, int, int, float, uint32_t par_gs, uint32_t par) {
+    const BinSpec& B = A->bins;
+    if (t < 0 || t >= B.t_end) {  // outside the window: not packed
+      close();
+      return;
+    }
+    const int64_t tile = bin_of(t, B) >> B.tile_log2;
+    if (open && tile == u_tile) {
+      ++u_len;
+      return;
+    }
+    close();
+    open = true;
+    u_src = e;
+    u_len = 1;
+    u_tile = tile;
+    u_st = ((init ^ par) & 0xffffu) | (((init ^ par_gs) & 0xffffu) << 16);
+  }
+};
+
+template <bool kEmit>
+__global__ void __launch_bounds__(kFwdThreads) k_pk_units(UnitArgs a, int64_t n_blocks) {
+  const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (kb >= n_blocks) return;
+  UnitVisitor<kEmit> vis;
+  vis.A = &a;
+  vis.kb = kb;
+  walk_block(kb, a.ev, a.plan, vis);
+  if (!kEmit) a.counts[kb] = vis.n;
+}
+
+__global__ void __launch_bounds__(256) k_pk_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// First sorted unit of every non-empty tile.
+__global__ void __launch_bounds__(256) k_pk_tile_first(const uint64_t* skey, int64_t nu, int32_t shift,
+                                                       uint32_t* tfirst) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nu) return;
+  const uint64_t t = skey[j] >> shift;
+  if (j == 0 || (skey[j - 1] >> shift) != t) tfirst[t] = (uint32_t)j;
+}
+
+__device__ __forceinline__ int32_t tile_of_group(const int32_t* tile_grp, int32_t n_tiles, int64_t gi) {
+  int32_t lo = 0, hi = n_tiles;  // invariant: tile_grp[lo] <= gi < tile_grp[hi]
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if ((int64_t)tile_grp[mid] <= gi) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256) k_pk_group_len(const int32_t* tile_grp, const uint32_t* tfirst, int32_t n_tiles,
+                                                      const uint32_t* sidx, const UnitRec* recs, int64_t n_groups,
+                                                      int64_t* glen) {
+  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi > n_groups) return;
+  if (gi == n_groups) {
+    glen[gi] = 0;
+    return;
+  }
+  const int32_t k = tile_of_group(tile_grp, n_tiles, gi);
+  const int64_t j0 = (int64_t)tfirst[k] + (gi - tile_grp[k]) * kGroupUnits;
+  const int64_t j1 = min(j0 + kGroupUnits, (int64_t)tfirst[k + 1]);
+  int64_t s = 0;
+  for (int64_t j = j0; j < j1; ++j) s += (int64_t)(recs[sidx[j]].x >> 28) + 1;
+  glen[gi] = s;
+}
+
+struct FillArgs {
+  EvView ev;
+  BinSpec bins;
+  const int32_t* tile_grp;
+  const uint32_t* tfirst;
+  const uint32_t* sidx;
+  const UnitRec* recs;
+  const int64_t* grp_off;
+  int64_t n_groups;
+  uint32_t* w32;
+  float* slw;
+  uint2* desc;
+  int64_t* dsrc;
+};
+
+__global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
+  const int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroupUnits;
+  const int lane = (int)(threadIdx.x & (kGroupUnits - 1));
+  if (gi >= a.n_groups) return;  // whole wavefronts exit together
+  const BinSpec& B = a.bins;
+  const int32_t k = tile_of_group(a.tile_grp, B.n_tiles, gi);
+  const int64_t j = (int64_t)a.tfirst[k] + (gi - a.tile_grp[k]) * kGroupUnits + lane;
+  const bool act = j < (int64_t)a.tfirst[k + 1];
+  UnitRec r{-1, 0xffffffffu, 0u};
+  if (act) r = a.recs[a.sidx[j]];
+  a.desc[gi * kGroupUnits + lane] = make_uint2(r.x, r.y);
+  a.dsrc[gi * kGroupUnits + lane] = r.src;
+  const int len = act ? (int)(r.x >> 28) + 1 : 0;
+  const int64_t tile_t0 = ((int64_t)k << B.tile_log2) * B.D;
+  int64_t off = a.grp_off[gi];
+  for (int kk = 0; kk < kLaneEvents; ++kk) {
+    const bool on = len > kk;
+    const uint64_t m = __ballot(on);
+    if (m == 0) break;
+    if (on) {
+      const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+      const int64_t pos = off + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+      const int64_t e = r.src + kk;
+      const int64_t t = a.ev.t[e];
+      const uint32_t pb = a.ev.pb[e];
+      const int64_t bin = bin_of(t, B);
+      const uint32_t bl = (uint32_t)(bin - ((int64_t)k << B.tile_log2));
+      const uint32_t rr = (uint32_t)(t - bin * B.D);
+      (void)tile_t0;
+      const uint32_t pin = min(pb >> 1, (uint32_t)kMaxPin);
+      a.w32[pos] = (bl << B.r_bits) | rr | (pin << kPinShift) | ((pb & 1u) << 31);
+      a.slw[pos] = a.ev.slew[e];
+    }
+    off += __popcll(m);
+  }
+}
+
+int ceil_log2_u64(uint64_t x) {
+  int l = 0;
+  while ((1ull << l) < x) ++l;
+  return l;
+}
+
+}  // namespace
+
+void pack_free(PackOut* o) {
+  void* ps[] = {o->w32, o->slw, o->desc, o->dsrc, o->grp_off, o->tile_grp, o->gperm, o->gcell};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  *o = PackOut();
+}
+
+hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len) {
+  std::vector<void*> temps;
+  PackOut o;
+  hipError_t st = hipSuccess;
+  const hipStream_t s = in.stream;
+  const int64_t G = in.ev.n_gates, N = in.ev.n;
+  const int32_t n_cells = (int32_t)in.n_in.size();
+  const BinSpec& B = in.bins;
+  const int32_t n_tiles = B.n_tiles;
+  int64_t held = 0;
+
+#define PK(call)                                                                   \
+  do {                                                                             \
+    st = (call);                                                                   \
+    if (st != hipSuccess) {                                                        \
+      snprintf(err, err_len, "pack: %s: %s", #call, hipGetErrorString(st));        \
+      goto fail;                                                                   \
+    }                                                                              \
+  } while (0)
+#define PKLAUNCH(name)                                                             \
+  do {                                                                             \
+    st = hipGetLastError();                                                        \
+    if (st != hipSuccess) {                                                        \
+      snprintf(err, err_len, "pack: launch of %s: %s", name, hipGetErrorString(st)); \
+      goto fail;                                                                   \
+    }                                                                              \
+  } while (0)
+
+  auto tmp = [&](size_t bytes, hipError_t& e) -> void* {
+    void* p = nullptr;
+    e = hipMalloc(&p, std::max<size_t>(bytes, 256));
+    if (e == hipSuccess) temps.push_back(p);
+    return p;
+  };
+  auto own = [&](size_t bytes, hipError_t& e) -> void* {
+    void* p = nullptr;
+    bytes = std::max<size_t>(bytes, 256);
+    e = hipMalloc(&p, bytes);
+    if (e == hipSuccess) held += (int64_t)bytes;
+    return p;
+  };
+
+  {
+    // ---- 1. gate order (host) -------------------------------------------
+    std::vector<int32_t> cnt(n_cells + 1, 0), cell_start(n_cells, 0), gb_base(n_cells, 0);
+    for (int64_t g = 0; g < G; ++g) cnt[in.h_gate_cell[g]]++;
+    int32_t acc = 0, gbacc = 0;
+    for (int32_t c = 0; c < n_cells; ++c) {
+      cell_start[c] = acc;
+      gb_base[c] = gbacc;
+      acc += cnt[c];
+      gbacc += (cnt[c] + (1 << kGateBlockLog2) - 1) >> kGateBlockLog2;
+    }
+    const int32_t n_gb = std::max(gbacc, 1);
+    std::vector<int32_t> rank((size_t)G), perm((size_t)G), pcell((size_t)G);
+    {
+      std::vector<int32_t> cur(cell_start);
+      for (int64_t g = 0; g < G; ++g) {
+        const int32_t c = in.h_gate_cell[g];
+        const int32_t r = cur[c]++;
+        rank[g] = r;
+        perm[r] = (int32_t)g;
+        pcell[r] = c;
+      }
+    }
+    const int gb_bits = ceil_log2_u64((uint64_t)n_gb);
+    const int tile_bits = std::max(1, ceil_log2_u64((uint64_t)n_tiles));
+    const int key_bits = tile_bits + gb_bits + 5;
+    if (key_bits > 64) {
+      snprintf(err, err_len, "pack: sort key of %d bits", key_bits);
+      return hipErrorInvalidValue;
+    }
+    hipError_t e2;
+    int32_t* d_rank = (int32_t*)tmp((size_t)G * 4, e2);
+    PK(e2);
+    int32_t* d_cs = (int32_t*)tmp((size_t)n_cells * 4, e2);
+    PK(e2);
+    int32_t* d_gbb = (int32_t*)tmp((size_t)n_cells * 4, e2);
+    PK(e2);
+    o.gperm = (int32_t*)own((size_t)G * 4, e2);
+    PK(e2);
+    o.gcell = (int32_t*)own((size_t)G * 4, e2);
+    PK(e2);
+    if (G > 0) {
+      PK(hipMemcpyAsync(d_rank, rank.data(), (size_t)G * 4, hipMemcpyHostToDevice, s));
+      PK(hipMemcpyAsync(o.gperm, perm.data(), (size_t)G * 4, hipMemcpyHostToDevice, s));
+      PK(hipMemcpyAsync(o.gcell, pcell.data(), (size_t)G * 4, hipMemcpyHostToDevice, s));
+    }
+    PK(hipMemcpyAsync(d_cs, cell_start.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
+    PK(hipMemcpyAsync(d_gbb, gb_base.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
+
+    // ---- 2-3. units -----------------------------------------------------
+    const int64_t n_blocks = (N + kLaneEvents - 1) / kLaneEvents;
+    UnitArgs ua;
+    ua.ev = in.ev;
+    ua.plan = in.plan_blk;
+    ua.gate_cell = in.gate_cell;
+    ua.gate_init = in.gate_init;
+    ua.bins = B;
+    ua.ks.gb_bits = gb_bits;
+    ua.ks.rank = d_rank;
+    ua.ks.cell_start = d_cs;
+    ua.ks.gb_base = d_gbb;
+    uint32_t* counts = (uint32_t*)tmp((size_t)(n_blocks + 1) * 4, e2);
+    PK(e2);
+    uint32_t* ubase = (uint32_t*)tmp((size_t)(n_blocks + 1) * 4, e2);
+    PK(e2);
+    ua.counts = counts;
+    ua.base = ubase;
+    ua.keys = nullptr;
+    ua.vals = nullptr;
+    ua.recs = nullptr;
+    int64_t NU = 0;
+    if (n_blocks > 0) {
+      const unsigned gridb = (unsigned)((n_blocks + kFwdThreads - 1) / kFwdThreads);
+      hipLaunchKernelGGL((k_pk_units<false>), dim3(gridb), dim3(kFwdThreads), 0, s, ua, n_blocks);
+      PKLAUNCH("k_pk_units<count>");
+      hipLaunchKernelGGL(k_pk_fill_u32, dim3(1), dim3(256), 0, s, counts + n_blocks, (int64_t)1, 0u);
+      PKLAUNCH("k_pk_fill_u32");
+      size_t tb = 0;
+      PK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, counts, ubase, (int)(n_blocks + 1), s));
+      void* tscan = tmp(tb, e2);
+      PK(e2);
+      PK(hipcub::DeviceScan::ExclusiveSum(tscan, tb, counts, ubase, (int)(n_blocks + 1), s));
+      uint32_t tot = 0;
+      PK(hipMemcpyAsync(&tot, ubase + n_blocks, 4, hipMemcpyDeviceToHost, s));
+      PK(hipStreamSynchronize(s));
+      NU = tot;
+    }
+    o.n_units = NU;
+    uint64_t* keys = (uint64_t*)tmp((size_t)NU * 8, e2);
+    PK(e2);
+    uint64_t* skeys = (uint64_t*)tmp((size_t)NU * 8, e2);
+    PK(e2);
+    uint32_t* vals = (uint32_t*)tmp((size_t)NU * 4, e2);
+    PK(e2);
+    uint32_t* sidx = (uint32_t*)tmp((size_t)NU * 4, e2);
+    PK(e2);
+    UnitRec* recs = (UnitRec*)tmp((size_t)NU * sizeof(UnitRec), e2);
+    PK(e2);
+    if (NU > 0) {
+      ua.keys = keys;
+      ua.vals = vals;
+      ua.recs = recs;
+      const unsigned gridb = (unsigned)((n_blocks + kFwdThreads - 1) / kFwdThreads);
+      hipLaunchKernelGGL((k_pk_units<true>), dim3(gridb), dim3(kFwdThreads), 0, s, ua, n_blocks);
+      PKLAUNCH("k_pk_units<emit>");
+      // ---- 4. sort ------------------------------------------------------
+      size_t tb = 0;
+      PK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, skeys, vals, sidx, (int)NU, 0, key_bits, s));
+      void* tsort = tmp(tb, e2);
+      PK(e2);
+      PK(hipcub::DeviceRadixSort::SortPairs(tsort, tb, keys, skeys, vals, sidx, (int)NU, 0, key_bits, s));
+    }
+    // ---- 5. tiles and groups -------------------------------------------
+    uint32_t* tfirst = (uint32_t*)tmp((size_t)(n_tiles + 1) * 4, e2);
+    PK(e2);
+    hipLaunchKernelGGL(k_pk_fill_u32, dim3((unsigned)((n_tiles + 1 + 255) / 256)), dim3(256), 0, s, tfirst,
+                       (int64_t)(n_tiles + 1), (uint32_t)NU);
+    PKLAUNCH("k_pk_fill_u32");
+    if (NU > 0) {
+      hipLaunchKernelGGL(k_pk_tile_first, dim3((unsigned)((NU + 255) / 256)), dim3(256), 0, s, skeys, NU,
+                         gb_bits + 5, tfirst);
+      PKLAUNCH("k_pk_tile_first");
+    }
+    std::vector<uint32_t> htf((size_t)n_tiles + 1);
+    PK(hipMemcpyAsync(htf.data(), tfirst, (size_t)(n_tiles + 1) * 4, hipMemcpyDeviceToHost, s));
+    PK(hipStreamSynchronize(s));
+    for (int32_t k = n_tiles - 1; k >= 0; --k) htf[k] = std::min(htf[k], htf[k + 1]);
+    std::vector<int32_t> htg((size_t)n_tiles + 1);
+    int64_t ng = 0;
+    int32_t maxg = 0;
+    for (int32_t k = 0; k < n_tiles; ++k) {
+      htg[k] = (int32_t)ng;
+      const int64_t gk = ((int64_t)(htf[k + 1] - htf[k]) + kGroupUnits - 1) / kGroupUnits;
+      maxg = std::max<int32_t>(maxg, (int32_t)gk);
+      ng += gk;
+    }
+    htg[n_tiles] = (int32_t)ng;
+    if (ng >= (int64_t)INT32_MAX) {
+      snprintf(err, err_len, "pack: %lld groups", (long long)ng);
+      st = hipErrorInvalidValue;
+      goto fail;
+    }
+    o.n_groups = ng;
+    o.max_tile_groups = maxg;
+    PK(hipMemcpyAsync(tfirst, htf.data(), (size_t)(n_tiles + 1) * 4, hipMemcpyHostToDevice, s));
+    o.tile_grp = (int32_t*)own((size_t)(n_tiles + 1) * 4, e2);
+    PK(e2);
+    PK(hipMemcpyAsync(o.tile_grp, htg.data(), (size_t)(n_tiles + 1) * 4, hipMemcpyHostToDevice, s));
+    int64_t* glen = (int64_t*)tmp((size_t)(ng + 1) * 8, e2);
+    PK(e2);
+    o.grp_off = (int64_t*)own((size_t)(ng + 1) * 8, e2);
+    PK(e2);
+    hipLaunchKernelGGL(k_pk_group_len, dim3((unsigned)((ng + 1 + 255) / 256)), dim3(256), 0, s, o.tile_grp, tfirst,
+                       n_tiles, sidx, recs, ng, glen);
+    PKLAUNCH("k_pk_group_len");
+    {
+      size_t tb = 0;
+      PK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, glen, o.grp_off, (int)(ng + 1), s));
+      void* tscan = tmp(tb, e2);
+      PK(e2);
+      PK(hipcub::DeviceScan::ExclusiveSum(tscan, tb, glen, o.grp_off, (int)(ng + 1), s));
+    }
+    int64_t nev = 0;
+    PK(hipMemcpyAsync(&nev, o.grp_off + ng, 8, hipMemcpyDeviceToHost, s));
+    PK(hipStreamSynchronize(s));
+    o.n_events = nev;
+    // ---- 6. fill --------------------------------------------------------
+    o.w32 = (uint32_t*)own((size_t)nev * 4, e2);
+    PK(e2);
+    o.slw = (float*)own((size_t)nev * 4, e2);
+    PK(e2);
+    o.desc = (uint2*)own((size_t)ng * kGroupUnits * 8, e2);
+    PK(e2);
+    o.dsrc = (int64_t*)own((size_t)ng * kGroupUnits * 8, e2);
+    PK(e2);
+    if (ng > 0) {
+      FillArgs fa;
+      fa.ev = in.ev;
+      fa.bins = B;
+      fa.tile_grp = o.tile_grp;
+      fa.tfirst = tfirst;
+      fa.sidx = sidx;
+      fa.recs = recs;
+      fa.grp_off = o.grp_off;
+      fa.n_groups = ng;
+      fa.w32 = o.w32;
+      fa.slw = o.slw;
+      fa.desc = o.desc;
+      fa.dsrc = o.dsrc;
+      const int64_t threads = ng * kGroupUnits;
+      hipLaunchKernelGGL(k_pk_fill, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, fa);
+      PKLAUNCH("k_pk_fill");
+    }
+    PK(hipStreamSynchronize(s));
+  }
+  for (void* p : temps) (void)hipFree(p);
+  o.bytes = held;
+  *out = o;
+  return hipSuccess;
+
+fail:
+  (void)hipStreamSynchronize(s);
+  (void)hipGetLastError();
+  for (void* p : temps) (void)hipFree(p);
+  pack_free(&o);
+  return st;
+#undef PK
+#undef PKLAUNCH
+}
+
+}  // namespace gtp

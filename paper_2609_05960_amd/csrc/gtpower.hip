@@ -1,20 +1,21 @@
 // Host side of the C ABI declared in include/gtpower.h.
 //
 // Call flow of one forward (all on the ctx stream, asynchronous):
-//   k_gate_prep      per gate: load-axis segment and weight, switching
-//                    energies, leakage scale; sum of initial leakage rates
-//   algo 0 (time-tiled):
-//     k_fwd_records  per workgroup of consecutive lane blocks: every event's
-//                    energy and leakage step, written as a 12-byte record into
-//                    the slot range of its time tile (slots from the plan)
-//     k_tile_accum   per time tile: records accumulated into LDS bins (int64),
-//                    tile stored
+//   algo 0 (packed, tile-major):
+//     k_gate_params  per gate: load-axis segment and weight, switching
+//                    energy, leakage scale (cell-sorted order); sum of the
+//                    initial leakage rates
+//     k_fwd_packed   per time tile: every unit of the tile (see gtp_pack.h)
+//                    walked by one lane, energies and leakage steps
+//                    accumulated into the tile's LDS bins, bins stored
 //   algo 1 (baseline):
+//     k_gate_prep    per gate (gate-major order)
 //     k_gate_serial  one gate per thread, global int64 atomics per event
 //   scan of S, k_finalize -> FP32 power per bin
-// The plan (lane-block gates and carried parities; record slots per time
-// tile) depends only on the event times and pins and on the bin width, so it
-// is built once per gtp_load_events / gtp_set_params.
+// The gate-major lane-block plan (first gate and carried parity of every 16
+// events) is built in gtp_load_events; the packed layout, which depends on the
+// events and the bin width, is built on the first forward after
+// gtp_load_events / gtp_set_params / gtp_set_tuning and reused afterwards.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,6 +29,7 @@
 
 #include "../../include/gtpower.h"
 #include "gtp_kernels.h"
+#include "gtp_pack.h"
 
 using namespace gtp;
 
@@ -53,8 +55,9 @@ struct gtp_ctx_s {
   int32_t n_cells = 0, n_slew = 0, n_load = 0, n_map = 0, n_leak = 0;
   int64_t n_tables = 0;
   int32_t lds_words = 0;
-  int32_t kfix = 16;          // fixed-point exponent
+  int32_t mfix = 40;          // energy unit 2^-mfix fJ (see gtp_device.h)
   std::vector<int32_t> h_nin;
+  std::vector<int32_t> h_gate_cell;  // host copy of the netlist's cells
   DevBuf lib_img;             // meta | map_q | leak | slew | slew_inv
   DevBuf load_axis, load_inv, quads;
 
@@ -74,11 +77,11 @@ struct gtp_ctx_s {
   gtp_params par{};
   BinSpec bins{};
 
-  // tuning + tile plan
+  // tuning + packed layout
   gtp_tuning tun{0, 0};
-  bool tiles_ok = false;
-  int64_t group_events = 0, n_groups = 0;
-  DevBuf cnt_tm, off_tm, off_gm, tile_off, rec;
+  bool pack_ok = false;
+  PackOut pk;
+  double pack_ms = 0.0;
 
   // kernel timing (gtp_profile_enable)
   bool prof_on = false;
@@ -90,7 +93,7 @@ struct gtp_ctx_s {
   hipEvent_t prof_a = nullptr;
 
   // per-call work buffers
-  DevBuf gprep, X, S, exS, L0, flag, first_bad;
+  DevBuf gprep, gparam, X, S, exS, L0, flag, first_bad;
   DevBuf adj_w, adj_c, adj_exc, adj_wg, adj_total, gC, gL;
 };
 
@@ -261,7 +264,8 @@ LutArgs lut_args(gtp_ctx c) {
   A.quads = ptr<float4>(c->quads);
   A.n_slew = c->n_slew;
   A.n_load = c->n_load;
-  A.scale_k = ldexpf(1.0f, c->kfix);
+  A.rate_scale = (float)(std::ldexp(1.0, c->mfix) * 1e-6);
+  A.two_sh = (float)std::ldexp(1.0, c->mfix - 32);
   return A;
 }
 
@@ -320,56 +324,80 @@ gtp_status build_block_plan(gtp_ctx c) {
   return GTP_OK;
 }
 
+// Bins per tile: the largest power of two (at most 2^12) that still gives
+// about two tiles per compute unit (480 or more), and a packed in-tile time
+// of at most 27 bits.
 int auto_tile_log2(int64_t n_bins, int r_bits) {
-  int lb = 12;
-  while (lb > 8 && (n_bins + (1ll << lb) - 1) / (1ll << lb) < 256) --lb;
-  while (lb > 8 && lb + r_bits > 32) --lb;
-  return lb;
+  int lb = 0;
+  while (lb < 12 && (n_bins >> (lb + 1)) >= 480) ++lb;
+  lb = std::max(lb, 4);
+  return std::min(lb, 27 - r_bits);
 }
 
-gtp_status build_tile_plan(gtp_ctx c) {
-  if (c->tiles_ok) return GTP_OK;
-  const int64_t N = c->ev.n_events;
+size_t lib_lds_bytes(gtp_ctx c) { return (size_t)c->lds_words * 4; }
+
+size_t packed_lds_bytes(gtp_ctx c, int tile_log2) {
+  return (size_t)(((c->lds_words + 1) & ~1) * 4) + ((size_t)16 << tile_log2);
+}
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+void drop_pack(gtp_ctx c) {
+  if (c->pk.w32 || c->pk.gperm) {
+    (void)hipStreamSynchronize(c->stream);
+    c->dev_bytes -= c->pk.bytes;
+    pack_free(&c->pk);
+  }
+  c->pack_ok = false;
+}
+
+gtp_status build_pack(gtp_ctx c) {
+  if (c->pack_ok) return GTP_OK;
+  drop_pack(c);
   BinSpec& B = c->bins;
+  if (B.r_bits > 27) return fail(c, GTP_ERR_UNSUPPORTED, "bin width above 2^27 ps");
   int lb = c->tun.bins_per_tile_log2 ? c->tun.bins_per_tile_log2 : auto_tile_log2(B.n_bins, B.r_bits);
-  if (lb < 8 || lb > 13) return fail(c, GTP_ERR_INVALID_ARG, "bins_per_tile_log2 %d outside [8, 13]", lb);
-  if (lb + B.r_bits > 32)
-    return fail(c, GTP_ERR_UNSUPPORTED, "tile of 2^%d bins with %d-bit in-bin offsets exceeds 32 bits", lb, B.r_bits);
-  B.tile_log2 = lb;
+  if (lb + B.r_bits > 27)
+    return fail(c, GTP_ERR_UNSUPPORTED, "tile of 2^%d bins with %d-bit in-bin offsets exceeds 27 bits", lb, B.r_bits);
+  if (packed_lds_bytes(c, lb) > kMaxLds)
+    return fail(c, GTP_ERR_UNSUPPORTED, "tile of 2^%d bins and the library image exceed the LDS", lb);
   const int64_t nt = (B.n_bins + (1ll << lb) - 1) >> lb;
-  if (nt > 8192) return fail(c, GTP_ERR_UNSUPPORTED, "%lld time tiles (max 8192): raise bins_per_tile_log2",
-                             (long long)nt);
+  if (nt >= (int64_t)INT32_MAX / 2) return fail(c, GTP_ERR_UNSUPPORTED, "%lld time tiles", (long long)nt);
+  if (c->ev.n_events >= (int64_t)UINT32_MAX) return fail(c, GTP_ERR_UNSUPPORTED, "2^32 or more events in one trace");
+  if (c->n_gates >= (1ll << 28) - 1) return fail(c, GTP_ERR_UNSUPPORTED, "2^28 or more gates");
+  B.tile_log2 = lb;
   B.n_tiles = (int32_t)nt;
-  if (N >= (int64_t)UINT32_MAX) return fail(c, GTP_ERR_UNSUPPORTED, "more than 2^32-1 events in one trace");
-  // about 16 records per (workgroup, tile) on average
-  int64_t ge = kSubChunk;
-  while (ge < 16 * nt) ge <<= 1;
-  c->group_events = ge;
-  c->n_groups = std::max<int64_t>(1, (N + ge - 1) / ge);
-  const int64_t cells = c->n_groups * nt;
-  if (cells >= (int64_t)INT32_MAX) return fail(c, GTP_ERR_UNSUPPORTED, "placement table too large");
-  TRY(ensure(c, c->cnt_tm, (size_t)cells * 4));
-  TRY(ensure(c, c->off_tm, (size_t)cells * 4 + 8));
-  TRY(ensure(c, c->off_gm, (size_t)cells * 4));
-  TRY(ensure(c, c->tile_off, (size_t)(nt + 1) * 4));
-  TRY(ensure(c, c->rec, (size_t)std::max<int64_t>(N, 1) * sizeof(uint3)));
-  if (N > 0) {
-    LAUNCH(c, "k_plan_count", k_plan_count, dim3((unsigned)c->n_groups), dim3(256), (size_t)nt * 4, c->ev.t_ps, N, B, ge, c->n_groups, ptr<uint32_t>(c->cnt_tm));
-    TRY(scan_exclusive<uint32_t, OpAdd>(c, ptr<uint32_t>(c->cnt_tm), ptr<uint32_t>(c->off_tm), cells, 0u, OpAdd()));
-  } else {
-    TRY(fill_u64(c, c->off_tm.p, (cells + 1) / 2, 0ull));
+  PackIn in;
+  in.ev = ev_view(c);
+  in.plan_blk = ptr<uint2>(c->plan_blk);
+  in.gate_cell = ptr<int32_t>(c->gate_cell);
+  in.gate_init = ptr<uint32_t>(c->gate_init);
+  in.h_gate_cell = c->h_gate_cell;
+  in.n_in = c->h_nin;
+  in.bins = B;
+  in.stream = c->stream;
+  char msg[256] = {0};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  if (e0) (void)hipEventRecord(e0, c->stream);
+  const hipError_t st = pack_events(in, &c->pk, msg, sizeof msg);
+  if (st != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return fail(c, st == hipErrorOutOfMemory ? GTP_ERR_OUT_OF_MEMORY : GTP_ERR_HIP, "%s", msg);
   }
-  // records beyond valid times are dropped, so the total is read back from the scan
-  uint32_t last_off = 0, last_cnt = 0;
-  if (N > 0) {
-    HIPCHK(c, hipMemcpyAsync(&last_off, ptr<uint32_t>(c->off_tm) + cells - 1, 4, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(&last_cnt, ptr<uint32_t>(c->cnt_tm) + cells - 1, 4, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (e0 && e1) {
+    float ms = 0.f;
+    (void)hipEventRecord(e1, c->stream);
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    c->pack_ms = ms;
   }
-  const uint32_t n_rec = last_off + last_cnt;
-  LAUNCH(c, "k_plan_tile_off", k_plan_tile_off, dim3(grid_for(nt + 1, 256)), dim3(256), 0, (const uint32_t*)ptr<uint32_t>(c->off_tm), c->n_groups, (int32_t)nt, n_rec, ptr<uint32_t>(c->tile_off));
-  LAUNCH(c, "k_plan_transpose", k_plan_transpose, dim3(grid_for(cells, 256)), dim3(256), 0, (const uint32_t*)ptr<uint32_t>(c->off_tm), ptr<uint32_t>(c->off_gm), c->n_groups, (int32_t)nt);
-  c->tiles_ok = true;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  c->dev_bytes += c->pk.bytes;
+  c->pack_ok = true;
   return GTP_OK;
 }
 
@@ -393,7 +421,7 @@ gtp_status gate_prep(gtp_ctx c, const float* net_load, const float* leak_scale) 
   a.n_gates = c->n_gates;
   a.vdd = c->par.vdd;
   a.sw_mode = c->par.sw_mode;
-  a.scale_k = ldexpf(1.0f, c->kfix);
+  a.rate_scale = (float)(std::ldexp(1.0, c->mfix) * 1e-6);
   a.max_scale = GTP_MAX_LEAK_SCALE;
   a.out = ptr<GatePrep>(c->gprep);
   a.L0 = ptr<unsigned long long>(c->L0);
@@ -401,8 +429,6 @@ gtp_status gate_prep(gtp_ctx c, const float* net_load, const float* leak_scale) 
   LAUNCH(c, "k_gate_prep", k_gate_prep, dim3(grid_for(c->n_gates, 256)), dim3(256), 0, a);
   return GTP_OK;
 }
-
-size_t lib_lds_bytes(gtp_ctx c) { return (size_t)c->lds_words * 4; }
 
 }  // namespace
 
@@ -431,12 +457,9 @@ gtp_status gtp_create(gtp_ctx* out, int hip_device, void* hip_stream) {
     delete c;
     return GTP_ERR_OUT_OF_MEMORY;
   }
-  // dynamic LDS above the 64 KB default: tiles of up to 2^13 bins (128 KB),
-  // library image plus tile cursors (48 + 32 KB)
-  if (hipFuncSetAttribute((const void*)k_tile_accum, hipFuncAttributeMaxDynamicSharedMemorySize, 16 << 13) !=
-          hipSuccess ||
-      hipFuncSetAttribute((const void*)k_fwd_records, hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024) !=
-          hipSuccess) {
+  // dynamic LDS above the 64 KB default: library image plus a tile of bins
+  if (hipFuncSetAttribute((const void*)k_fwd_packed, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) !=
+      hipSuccess) {
     (void)hipGetLastError();
     delete c;
     return GTP_ERR_HIP;
@@ -453,11 +476,11 @@ gtp_status gtp_destroy(gtp_ctx c) {
   if (!c) return GTP_OK;
   (void)hipSetDevice(c->dev);
   (void)hipStreamSynchronize(c->stream);
+  drop_pack(c);
   DevBuf* all[] = {&c->lib_img, &c->load_axis, &c->load_inv, &c->quads, &c->gate_cell, &c->gate_out,
-                   &c->gate_init, &c->plan_blk, &c->blk_tmp, &c->blk_tmp2, &c->scan_sums, &c->cnt_tm,
-                   &c->off_tm, &c->off_gm, &c->tile_off, &c->rec, &c->gprep, &c->X, &c->S, &c->exS,
-                   &c->L0, &c->flag, &c->first_bad, &c->adj_w, &c->adj_c, &c->adj_exc, &c->adj_wg,
-                   &c->adj_total, &c->gC, &c->gL};
+                   &c->gate_init, &c->plan_blk, &c->blk_tmp, &c->blk_tmp2, &c->scan_sums, &c->gprep, &c->gparam,
+                   &c->X, &c->S, &c->exS, &c->L0, &c->flag, &c->first_bad, &c->adj_w, &c->adj_c, &c->adj_exc,
+                   &c->adj_wg, &c->adj_total, &c->gC, &c->gL};
   for (DevBuf* b : all) release(c, *b);
   prof_clear(c);
   for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
@@ -597,14 +620,15 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
   c->n_tables = lib->n_tables;
   c->lds_words = (int32_t)words;
   c->h_nin.assign(lib->n_inputs, lib->n_inputs + nc);
-  // fixed-point exponent: a quantised rate lambda*leak*2^k must stay below 2^30
-  double top = (double)GTP_MAX_LEAK_SCALE * std::max(leak_max, 1e-3f);
-  int k = (int)std::floor(std::log2((double)(1 << 30) / top));
-  c->kfix = std::max(4, std::min(24, k));
+  // fixed-point exponent m: a quantised rate lambda*leak*2^m*1e-6 must stay
+  // below 2^30; m <= 40 keeps event energies up to 2^23 fJ exact in int64
+  const double top = (double)GTP_MAX_LEAK_SCALE * std::max(leak_max, 1e-3f);
+  const int m = (int)std::floor(std::log2(1073741824.0 * 1e6 / top));
+  c->mfix = std::max(24, std::min(40, m));
   c->lib_ok = true;
   c->net_ok = false;
   c->ev_ok = false;
-  c->tiles_ok = false;
+  drop_pack(c);
   return GTP_OK;
 }
 
@@ -645,11 +669,14 @@ gtp_status gtp_load_netlist(gtp_ctx c, int64_t n_gates, int64_t n_nets, const in
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (bad) return fail(c, GTP_ERR_INVALID_ARG, "a gate names a cell or output net out of range");
   }
+  c->h_gate_cell.resize((size_t)n_gates);
+  if (n_gates > 0)
+    HIPCHK(c, hipMemcpy(c->h_gate_cell.data(), c->gate_cell.p, (size_t)n_gates * 4, hipMemcpyDeviceToHost));
   c->n_gates = n_gates;
   c->n_nets = n_nets;
   c->net_ok = true;
   c->ev_ok = false;
-  c->tiles_ok = false;
+  drop_pack(c);
   return GTP_OK;
 }
 
@@ -673,7 +700,7 @@ gtp_status gtp_load_events(gtp_ctx c, const gtp_events* ev, int validate) {
                 (long long)ends[0], (long long)ends[1]);
   c->ev = *ev;
   c->ev_ok = false;
-  c->tiles_ok = false;
+  drop_pack(c);
   TRY(build_block_plan(c));
   c->ev_ok = true;
   if (c->par_ok && c->bins.t_end != ev->t_end_ps) c->par_ok = false;  // bins depend on t_end
@@ -722,7 +749,7 @@ gtp_status gtp_set_params(gtp_ctx c, const gtp_params* p) {
   B.tile_log2 = 8;
   B.n_tiles = 0;
   c->par_ok = true;
-  c->tiles_ok = false;
+  drop_pack(c);
   return GTP_OK;
 }
 
@@ -736,9 +763,9 @@ gtp_status gtp_num_bins(gtp_ctx c, int64_t* n) {
 gtp_status gtp_set_tuning(gtp_ctx c, const gtp_tuning* t) {
   if (!c || !t) return GTP_ERR_INVALID_ARG;
   if (t->algo < 0 || t->algo > 1) return fail(c, GTP_ERR_INVALID_ARG, "algo %d", t->algo);
-  if (t->bins_per_tile_log2 != 0 && (t->bins_per_tile_log2 < 8 || t->bins_per_tile_log2 > 13))
+  if (t->bins_per_tile_log2 != 0 && (t->bins_per_tile_log2 < 2 || t->bins_per_tile_log2 > 13))
     return fail(c, GTP_ERR_INVALID_ARG, "bins_per_tile_log2 %d", t->bins_per_tile_log2);
-  if (t->bins_per_tile_log2 != c->tun.bins_per_tile_log2) c->tiles_ok = false;
+  if (t->bins_per_tile_log2 != c->tun.bins_per_tile_log2) drop_pack(c);
   c->tun = *t;
   return GTP_OK;
 }
@@ -746,51 +773,118 @@ gtp_status gtp_set_tuning(gtp_ctx c, const gtp_tuning* t) {
 gtp_status gtp_get_tuning(gtp_ctx c, gtp_tuning* t) {
   if (!c || !t) return GTP_ERR_INVALID_ARG;
   *t = c->tun;
-  if (c->tiles_ok && t->bins_per_tile_log2 == 0) t->bins_per_tile_log2 = c->bins.tile_log2;
+  if (c->pack_ok && t->bins_per_tile_log2 == 0) t->bins_per_tile_log2 = c->bins.tile_log2;
   return GTP_OK;
 }
+
+gtp_status gtp_plan_info(gtp_ctx c, gtp_plan_stats* out) {
+  TRY(need(c, true, true, true, true));
+  if (!out) return GTP_ERR_INVALID_ARG;
+  HIPCHK(c, hipSetDevice(c->dev));
+  TRY(build_pack(c));
+  out->n_events_packed = c->pk.n_events;
+  out->n_units = c->pk.n_units;
+  out->n_groups = c->pk.n_groups;
+  out->n_tiles = c->bins.n_tiles;
+  out->tile_log2 = c->bins.tile_log2;
+  out->max_tile_groups = c->pk.max_tile_groups;
+  out->packed_bytes = c->pk.bytes;
+  out->pack_ms = c->pack_ms;
+  return GTP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+gtp_status final_bins(gtp_ctx c, float* power_mw) {
+  const int64_t NB = c->bins.n_bins;
+  TRY(scan_exclusive<int64_t, OpAdd>(c, ptr<int64_t>(c->S), ptr<int64_t>(c->exS), NB, (int64_t)0, OpAdd()));
+  FinArgs f;
+  f.X = ptr<int64_t>(c->X);
+  f.S = ptr<int64_t>(c->S);
+  f.exS = ptr<int64_t>(c->exS);
+  f.L0 = ptr<unsigned long long>(c->L0);
+  f.P = power_mw;
+  f.n_bins = NB;
+  f.D = c->bins.D;
+  f.t_end = c->bins.t_end;
+  f.out_scale = std::ldexp(1.0, -c->mfix) / (double)c->bins.D;
+  LAUNCH(c, "k_finalize", k_finalize, dim3(grid_for(NB, 256)), dim3(256), 0, f);
+  return GTP_OK;
+}
+
+gtp_status gate_params(gtp_ctx c, const float* net_load, const float* leak_scale) {
+  TRY(ensure(c, c->gparam, (size_t)std::max<int64_t>(c->n_gates, 1) * sizeof(GateParam)));
+  TRY(ensure(c, c->L0, 8));
+  TRY(fill_u64(c, c->L0.p, 1, 0ull));
+  if (c->n_gates == 0) return GTP_OK;
+  const LibView L = lib_view(c);
+  GateParamArgs a;
+  a.gperm = c->pk.gperm;
+  a.gcell = c->pk.gcell;
+  a.gate_out = ptr<int32_t>(c->gate_out);
+  a.gate_init = ptr<uint32_t>(c->gate_init);
+  a.net_load = net_load;
+  a.leak_scale = leak_scale;
+  a.meta = L.meta;
+  a.leak = L.leak;
+  a.load = ptr<float>(c->load_axis);
+  a.load_inv = ptr<float>(c->load_inv);
+  a.n_load = c->n_load;
+  a.n_gates = c->n_gates;
+  a.vdd = c->par.vdd;
+  a.sw_mode = c->par.sw_mode;
+  a.rate_scale = (float)(std::ldexp(1.0, c->mfix) * 1e-6);
+  a.max_scale = GTP_MAX_LEAK_SCALE;
+  a.out = ptr<GateParam>(c->gparam);
+  a.L0 = ptr<unsigned long long>(c->L0);
+  a.flag = ptr<int32_t>(c->flag);
+  LAUNCH(c, "k_gate_params", k_gate_params, dim3(grid_for(c->n_gates, 256)), dim3(256), 0, a);
+  return GTP_OK;
+}
+
+// Packed forward into X/S; with dbg_state set, also the per-event trace.
+gtp_status packed_forward(gtp_ctx c, int32_t* dbg_state, int64_t* dbg_bin) {
+  const BinSpec& B = c->bins;
+  PackedFwdArgs a;
+  a.w32 = c->pk.w32;
+  a.slw = c->pk.slw;
+  a.desc = c->pk.desc;
+  a.grp_off = c->pk.grp_off;
+  a.tile_grp = c->pk.tile_grp;
+  a.gparam = ptr<GateParam>(c->gparam);
+  a.lib = lib_view(c);
+  a.lut = lut_args(c);
+  a.bins = B;
+  a.sw_mode = c->par.sw_mode;
+  a.X = ptr<int64_t>(c->X);
+  a.S = ptr<int64_t>(c->S);
+  a.dbg_state = dbg_state;
+  a.dbg_bin = dbg_bin;
+  a.dsrc = c->pk.dsrc;
+  const size_t lds = packed_lds_bytes(c, B.tile_log2);
+  LAUNCH(c, "k_fwd_packed", k_fwd_packed, dim3((unsigned)B.n_tiles), dim3(kTileThreads), lds, a);
+  return GTP_OK;
+}
+}  // namespace
+
+extern "C" {
 
 gtp_status gtp_forward(gtp_ctx c, const float* net_load_ff, const float* leak_scale, float* power_mw) {
   TRY(need(c, true, true, true, true));
   if (!net_load_ff || !power_mw) return fail(c, GTP_ERR_INVALID_ARG, "null forward argument");
   HIPCHK(c, hipSetDevice(c->dev));
   const int64_t NB = c->bins.n_bins;
-  TRY(gate_prep(c, net_load_ff, leak_scale));
   TRY(ensure(c, c->X, (size_t)NB * 8));
   TRY(ensure(c, c->S, (size_t)NB * 8));
   TRY(ensure(c, c->exS, (size_t)NB * 8));
-  const double dyn_scale = std::ldexp(1.0, c->kfix) * 1e6;
   const int64_t N = c->ev.n_events;
   if (c->tun.algo == 0) {
-    TRY(build_tile_plan(c));
-    const BinSpec& B = c->bins;
-    if (N > 0) {
-      FwdArgs a;
-      a.ev = ev_view(c);
-      a.plan = ptr<uint2>(c->plan_blk);
-      a.gprep = ptr<GatePrep>(c->gprep);
-      a.lib = lib_view(c);
-      a.lut = lut_args(c);
-      a.bins = B;
-      a.group_events = c->group_events;
-      a.off_gm = ptr<uint32_t>(c->off_gm);
-      a.rec = ptr<uint3>(c->rec);
-      a.n_rec = N;
-      a.dbg_state = nullptr;
-      a.dbg_bin = nullptr;
-      const size_t lds = lib_lds_bytes(c) + (size_t)B.n_tiles * 4;
-      LAUNCH(c, "k_fwd_records", k_fwd_records, dim3((unsigned)c->n_groups), dim3(kFwdThreads), lds, a);
-    }
-    TileArgs ta;
-    ta.rec = ptr<uint3>(c->rec);
-    ta.tile_off = ptr<uint32_t>(c->tile_off);
-    ta.X = ptr<int64_t>(c->X);
-    ta.S = ptr<int64_t>(c->S);
-    ta.bins = B;
-    ta.dyn_scale = dyn_scale;
-    const size_t lds = (size_t)16 << B.tile_log2;
-    LAUNCH(c, "k_tile_accum", k_tile_accum, dim3((unsigned)B.n_tiles), dim3(kTileThreads), lds, ta);
+    TRY(build_pack(c));
+    TRY(gate_params(c, net_load_ff, leak_scale));
+    TRY(packed_forward(c, nullptr, nullptr));
   } else {
+    TRY(gate_prep(c, net_load_ff, leak_scale));
     TRY(fill_u64(c, c->X.p, NB, 0ull));
     TRY(fill_u64(c, c->S.p, NB, 0ull));
     if (c->n_gates > 0 && N > 0) {
@@ -802,23 +896,10 @@ gtp_status gtp_forward(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       a.bins = c->bins;
       a.X = ptr<unsigned long long>(c->X);
       a.S = ptr<unsigned long long>(c->S);
-      a.dyn_scale = dyn_scale;
       LAUNCH(c, "k_gate_serial", k_gate_serial, dim3(grid_for(c->n_gates, kFwdThreads)), dim3(kFwdThreads), lib_lds_bytes(c), a);
     }
   }
-  TRY(scan_exclusive<int64_t, OpAdd>(c, ptr<int64_t>(c->S), ptr<int64_t>(c->exS), NB, (int64_t)0, OpAdd()));
-  FinArgs f;
-  f.X = ptr<int64_t>(c->X);
-  f.S = ptr<int64_t>(c->S);
-  f.exS = ptr<int64_t>(c->exS);
-  f.L0 = ptr<unsigned long long>(c->L0);
-  f.P = power_mw;
-  f.n_bins = NB;
-  f.D = c->bins.D;
-  f.t_end = c->bins.t_end;
-  f.out_scale = std::ldexp(1.0, -c->kfix) * 1e-6 / (double)c->bins.D;
-  LAUNCH(c, "k_finalize", k_finalize, dim3(grid_for(NB, 256)), dim3(256), 0, f);
-  return GTP_OK;
+  return final_bins(c, power_mw);
 }
 
 gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_scale, const float* grad_power,
@@ -886,12 +967,24 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
 
 gtp_status gtp_debug_event_trace(gtp_ctx c, int32_t* state_before, int64_t* bin) {
   TRY(need(c, true, true, true, true));
-  if (c->n_blocks == 0) return GTP_OK;
+  if (c->ev.n_events == 0) return GTP_OK;
   if (!state_before || !bin) return fail(c, GTP_ERR_INVALID_ARG, "null trace output");
   HIPCHK(c, hipSetDevice(c->dev));
-  // any loads: the trace does not depend on them; gate_prep needs a net-load array
+  const int64_t N = c->ev.n_events;
+  // any loads: the trace does not depend on them; the gate preparation needs a net-load array
   TRY(ensure(c, c->adj_w, (size_t)(c->n_nets + 2) * 4));
-  LAUNCH(c, "k_fill_u64", k_fill_u64, dim3(grid_for((c->n_nets + 1) / 2, 256)), dim3(256), 0, ptr<unsigned long long>(c->adj_w), (c->n_nets + 1) / 2, 0x3f8000003f800000ull);
+  TRY(fill_u64(c, c->adj_w.p, (c->n_nets + 1) / 2 + 1, 0x3f8000003f800000ull));
+  if (c->tun.algo == 0) {
+    // the packed path's own state tracking; events it does not pack keep -1
+    TRY(build_pack(c));
+    LAUNCH(c, "k_fill_i32", k_fill_i32, dim3(grid_for(N, 256)), dim3(256), 0, state_before, N, -1);
+    TRY(fill_u64(c, bin, N, ~0ull));
+    const int64_t NB = c->bins.n_bins;
+    TRY(ensure(c, c->X, (size_t)NB * 8));
+    TRY(ensure(c, c->S, (size_t)NB * 8));
+    TRY(gate_params(c, ptr<float>(c->adj_w), nullptr));
+    return packed_forward(c, state_before, bin);
+  }
   TRY(gate_prep(c, ptr<float>(c->adj_w), nullptr));
   TraceArgs a;
   a.ev = ev_view(c);

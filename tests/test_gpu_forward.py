@@ -1,8 +1,8 @@
 """GPU parity of the forward path against the FP64 oracle, through the C ABI.
 
 Bar: states and bin indices bit-exact; every bin within 1e-5 relative of the
-FP64 waveform; both execution paths (time-tiled, one gate per thread) give
-bit-identical FP32 waveforms (exact int64 fixed-point accumulation).
+FP64 waveform; both execution paths (packed tile-major, one gate per thread)
+give bit-identical FP32 waveforms (exact int64 fixed-point accumulation).
 """
 import numpy as np
 import pytest
@@ -62,7 +62,7 @@ def test_random_small(O, seed):
     check(prob, O)
 
 
-@pytest.mark.parametrize("tile_log2", [8, 9, 13])
+@pytest.mark.parametrize("tile_log2", [2, 4, 8, 9, 13])
 def test_tile_sizes(O, tile_log2):
     prob = synth.make_random_small(21, n_gates=200, n_cells=8, i_max=4, n_events=30000, t_end=200000, bin_ps=10,
                                    p_tie=0.1, n_clock=3)
@@ -121,3 +121,20 @@ def test_run_to_run_identical(O):
     a = run(prob)[0]
     b = run(prob)[0]
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_plan_invariants(O):
+    """Every in-window event is packed exactly once, units hold at most 16
+    events, groups hold at most 64 units, and the packed trace covers every
+    event (checked against the oracle in check())."""
+    prob = synth.make_random_small(41, n_gates=300, n_cells=8, i_max=4, n_events=60000, t_end=500000, bin_ps=50,
+                                   p_tie=0.2, n_clock=4)
+    ctx, load, lam = to_device_ctx(prob, algo=0)
+    info = ctx.plan_info()
+    ctx.close()
+    N = prob.ev.n_events
+    assert info["n_events_packed"] == N
+    assert -(-N // 16) <= info["n_units"] <= N
+    assert -(-info["n_units"] // 64) <= info["n_groups"] <= -(-info["n_units"] // 64) + info["n_tiles"]
+    assert info["n_tiles"] == -(-prob.n_bins // (1 << info["tile_log2"]))
+    check(prob, O)
