@@ -58,6 +58,7 @@ def main():
     ap.add_argument("--config", default="C2", choices=sorted(WORKLOADS))
     ap.add_argument("--algo", type=int, default=0, help="0 time-tiled, 1 one gate per thread")
     ap.add_argument("--tile-log2", type=int, default=0)
+    ap.add_argument("--tile-threads", type=int, default=0, help="threads per tile workgroup (0 = library default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work for the oracle sample")
@@ -99,7 +100,7 @@ def main():
     tp = time.time()
     ctx.load_events(*tens, t_end=ev.t_end, validate=False)
     ctx.set_params(vdd=prob.vdd, bin_ps=prob.bin_ps, sw_mode=prob.sw_mode)
-    ctx.set_tuning(algo=args.algo, bins_per_tile_log2=args.tile_log2)
+    ctx.set_tuning(algo=args.algo, bins_per_tile_log2=args.tile_log2, tile_threads=args.tile_threads)
     load = torch.from_numpy(net.net_load).to(dev)
     lam = torch.from_numpy(net.leak_scale).to(dev)
     P = torch.empty(ctx.n_bins, dtype=torch.float32, device=dev)

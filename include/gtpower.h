@@ -151,11 +151,14 @@ gtp_status gtp_num_bins(gtp_ctx ctx, int64_t* n_bins);
  * LDS); algo 1: one gate per thread with global atomics (baseline).
  * bins_per_tile_log2: 0 = automatic, else 2..13 (bins per time tile of the
  * packed path; the tile's bins and the library image must fit in 160 KB of
- * LDS). Both paths give bit-identical waveforms.
+ * LDS). tile_threads: threads per time-tile workgroup of the packed path,
+ * 0 = automatic, else 256, 512 or 1024. Both paths give bit-identical
+ * waveforms.
  */
 typedef struct {
   int32_t algo;
   int32_t bins_per_tile_log2;
+  int32_t tile_threads;
 } gtp_tuning;
 gtp_status gtp_set_tuning(gtp_ctx ctx, const gtp_tuning* t);
 gtp_status gtp_get_tuning(gtp_ctx ctx, gtp_tuning* t);

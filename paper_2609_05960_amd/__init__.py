@@ -75,7 +75,7 @@ class _Params(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("algo", ctypes.c_int32), ("bins_per_tile_log2", ctypes.c_int32)]
+    _fields_ = [("algo", ctypes.c_int32), ("bins_per_tile_log2", ctypes.c_int32), ("tile_threads", ctypes.c_int32)]
 
 
 class _PlanStats(ctypes.Structure):
@@ -231,14 +231,14 @@ class Context:
         self.n_bins = n.value
         self.vdd, self.bin_ps, self.sw_mode = float(vdd), int(bin_ps), int(sw_mode)
 
-    def set_tuning(self, algo: int = 0, bins_per_tile_log2: int = 0):
-        tu = _Tuning(int(algo), int(bins_per_tile_log2))
+    def set_tuning(self, algo: int = 0, bins_per_tile_log2: int = 0, tile_threads: int = 0):
+        tu = _Tuning(int(algo), int(bins_per_tile_log2), int(tile_threads))
         self._chk(self.L.gtp_set_tuning(self.h, ctypes.byref(tu)))
 
     def get_tuning(self):
         tu = _Tuning()
         self._chk(self.L.gtp_get_tuning(self.h, ctypes.byref(tu)))
-        return dict(algo=tu.algo, bins_per_tile_log2=tu.bins_per_tile_log2)
+        return dict(algo=tu.algo, bins_per_tile_log2=tu.bins_per_tile_log2, tile_threads=tu.tile_threads)
 
     def plan_info(self) -> dict:
         """Statistics of the packed layout (built on demand; synchronises)."""

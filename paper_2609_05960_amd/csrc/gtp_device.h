@@ -40,7 +40,7 @@ namespace gtp {
 
 constexpr int kLaneEvents = 16;       // events per lane block / per unit (max)
 constexpr int kFwdThreads = 256;      // threads of the gate-major walking kernels
-constexpr int kTileThreads = 512;     // threads of the packed forward kernel
+constexpr int kTileThreads = 1024;    // threads of the packed forward kernel (default)
 constexpr int kGroupUnits = 64;       // units per wavefront group (one per lane)
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;

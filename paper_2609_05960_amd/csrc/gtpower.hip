@@ -78,7 +78,7 @@ struct gtp_ctx_s {
   BinSpec bins{};
 
   // tuning + packed layout
-  gtp_tuning tun{0, 0};
+  gtp_tuning tun{0, 0, 0};
   bool pack_ok = false;
   PackOut pk;
   double pack_ms = 0.0;
@@ -342,6 +342,23 @@ size_t packed_lds_bytes(gtp_ctx c, int tile_log2) {
 
 constexpr size_t kMaxLds = 160 * 1024;
 
+template <class K>
+hipError_t lds_limit(K kern) {
+  return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+}
+
+hipError_t set_packed_lds_limits() {
+  hipError_t e = hipSuccess;
+  const hipError_t r[] = {
+      lds_limit(k_fwd_packed<256, 7, true>),   lds_limit(k_fwd_packed<256, 0, true>),
+      lds_limit(k_fwd_packed<256, 7, false>),  lds_limit(k_fwd_packed<256, 0, false>),
+      lds_limit(k_fwd_packed<512, 7, false>),  lds_limit(k_fwd_packed<512, 0, false>),
+      lds_limit(k_fwd_packed<1024, 7, false>), lds_limit(k_fwd_packed<1024, 0, false>)};
+  for (hipError_t x : r)
+    if (x != hipSuccess) e = x;
+  return e;
+}
+
 void drop_pack(gtp_ctx c) {
   if (c->pk.w32 || c->pk.gperm) {
     (void)hipStreamSynchronize(c->stream);
@@ -458,8 +475,7 @@ gtp_status gtp_create(gtp_ctx* out, int hip_device, void* hip_stream) {
     return GTP_ERR_OUT_OF_MEMORY;
   }
   // dynamic LDS above the 64 KB default: library image plus a tile of bins
-  if (hipFuncSetAttribute((const void*)k_fwd_packed, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) !=
-      hipSuccess) {
+  if (set_packed_lds_limits() != hipSuccess) {
     (void)hipGetLastError();
     delete c;
     return GTP_ERR_HIP;
@@ -765,6 +781,8 @@ gtp_status gtp_set_tuning(gtp_ctx c, const gtp_tuning* t) {
   if (t->algo < 0 || t->algo > 1) return fail(c, GTP_ERR_INVALID_ARG, "algo %d", t->algo);
   if (t->bins_per_tile_log2 != 0 && (t->bins_per_tile_log2 < 2 || t->bins_per_tile_log2 > 13))
     return fail(c, GTP_ERR_INVALID_ARG, "bins_per_tile_log2 %d", t->bins_per_tile_log2);
+  if (t->tile_threads != 0 && t->tile_threads != 256 && t->tile_threads != 512 && t->tile_threads != 1024)
+    return fail(c, GTP_ERR_INVALID_ARG, "tile_threads %d (0, 256, 512 or 1024)", t->tile_threads);
   if (t->bins_per_tile_log2 != c->tun.bins_per_tile_log2) drop_pack(c);
   c->tun = *t;
   return GTP_OK;
@@ -774,6 +792,7 @@ gtp_status gtp_get_tuning(gtp_ctx c, gtp_tuning* t) {
   if (!c || !t) return GTP_ERR_INVALID_ARG;
   *t = c->tun;
   if (c->pack_ok && t->bins_per_tile_log2 == 0) t->bins_per_tile_log2 = c->bins.tile_log2;
+  if (t->tile_threads == 0) t->tile_threads = kTileThreads;
   return GTP_OK;
 }
 
@@ -863,8 +882,25 @@ gtp_status packed_forward(gtp_ctx c, int32_t* dbg_state, int64_t* dbg_bin) {
   a.dbg_bin = dbg_bin;
   a.dsrc = c->pk.dsrc;
   const size_t lds = packed_lds_bytes(c, B.tile_log2);
-  LAUNCH(c, "k_fwd_packed", k_fwd_packed, dim3((unsigned)B.n_tiles), dim3(kTileThreads), lds, a);
-  return GTP_OK;
+  const int th = c->tun.tile_threads ? c->tun.tile_threads : kTileThreads;
+  const bool ns7 = c->n_slew == 7;
+  const dim3 grid((unsigned)B.n_tiles);
+  if (dbg_state) {
+    if (ns7) LAUNCH(c, "k_fwd_packed_trace", (k_fwd_packed<256, 7, true>), grid, dim3(256), lds, a);
+    else LAUNCH(c, "k_fwd_packed_trace", (k_fwd_packed<256, 0, true>), grid, dim3(256), lds, a);
+    return GTP_OK;
+  }
+#define GTP_PACKED_CASE(TH)                                                                        \
+  if (th == TH) {                                                                                  \
+    if (ns7) LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, 7, false>), grid, dim3(TH), lds, a);      \
+    else LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, 0, false>), grid, dim3(TH), lds, a);          \
+    return GTP_OK;                                                                                 \
+  }
+  GTP_PACKED_CASE(256)
+  GTP_PACKED_CASE(512)
+  GTP_PACKED_CASE(1024)
+#undef GTP_PACKED_CASE
+  return fail(c, GTP_ERR_INVALID_ARG, "tile_threads %d", th);
 }
 }  // namespace
 
