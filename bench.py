@@ -39,6 +39,34 @@ WORKLOADS = {
 }
 
 
+KERNEL_SOURCES = ("paper_2609_05960_amd/csrc/gtp_kernels.h", "paper_2609_05960_amd/csrc/gtp_device.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the rocprofv3 summaries
+    under profiles/ (a line 'traffic: <kernel> <workload> <bytes> src=<hash>'),
+    or None when no summary matches the current kernel sources."""
+    import glob
+    import re
+    src = kernel_source_hash()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(f) as fh:
+            for line in fh:
+                m = re.match(r"traffic: (\S+) (\S+) (\d+) src=([0-9a-f]+)", line.strip().strip("`"))
+                if m and m.group(1) == kernel and m.group(2) == workload and m.group(4) == src:
+                    return int(m.group(3))
+    return None
+
+
 def cpu_brand() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -166,11 +194,13 @@ def main():
                    "tuning": ctx.get_tuning()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": (achieved / 1e9) if achieved else None,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK) if achieved else None,
+                     "traffic": measured_traffic(dom, args.config),
                      "algorithmic_bytes_per_launch": dom_bytes, "algorithmic_bytes_per_event": EVENT_BYTES,
                      "avg_launch_ms": dom_ms, **extra},
         "step_hbm_frac": step_bytes / (ms_step * 1e-3) / HBM_PEAK,
         "kernels": kern_avg,
+        "kernel_src": kernel_source_hash(),
         "plan_s": plan_s,
         "plan": plan,
         "gen_s": gen_s,

@@ -2,14 +2,15 @@
  * gtpower — C ABI of the MI355X (gfx950) binned power-waveform library.
  *
  * The library turns per-gate toggle-event streams into a time-binned power
- * waveform (the power computation of the paper's Sec. 2.2-2.3 models, fused
- * as in Sec. 4.3 / Algorithm 1): every event gets a state-indexed internal
- * energy lookup (Sec. 4.1: the gate's input state selects a table, which is
- * interpolated bilinearly over input slew x output load, Sec. 2.2), output
- * toggles add switching energy (Eq. switching energy; see gtp_params), the
- * leakage of each held input state is charged for its duration (Eq. leakage
- * energy) and everything is accumulated into fixed-width time bins, an
- * interval being split over the bins it overlaps (Sec. 2.3).
+ * waveform (the power models of the paper's Sec. 2.2 evaluated in time as in
+ * Sec. 2.4, fused as in Sec. 4.3 / Algorithm 1): every event gets a
+ * state-indexed internal energy lookup (Sec. 4.1: the gate's input state
+ * selects a table, which is interpolated bilinearly over input slew x output
+ * load, Sec. 2.2), output toggles add switching energy (Eq. switching energy;
+ * see gtp_params), the leakage of each held input state is charged for its
+ * duration (Eq. leakage energy) and everything is accumulated into
+ * fixed-width time bins, an interval being split over the bins it overlaps
+ * (Sec. 2.4).
  * The adjoint gives d(loss)/d(net load) and d(loss)/d(per-gate leakage
  * scale) for a loss of the binned power.
  *
@@ -135,7 +136,7 @@ int64_t gtp_bad_event(gtp_ctx ctx);
  * n_bins = ceil(t_end / bin_ps); a partial last bin is still divided by
  * bin_ps. sw_mode 0: switching energy 0.5*C*V^2 on every output toggle;
  * sw_mode 1: C*V^2 on an output rise only (the paper's Eq. switching energy).
- * bin_ps in [1, 2^24].
+ * bin_ps in [1, 2^22].
  */
 typedef struct {
   double vdd;
@@ -168,13 +169,17 @@ gtp_status gtp_get_tuning(gtp_ctx ctx, gtp_tuning* t);
  * events packed (those with times in the window), units (runs of at most 16
  * events of one gate in one time tile), wavefront groups of 64 units, time
  * tiles, bins per tile (log2), the largest group count of one tile, device
- * bytes of the packed arrays and the time the last build took (ms).
+ * bytes of the packed arrays, the time the last build took (ms) and the lane
+ * steps (sum over groups of the longest unit: a wavefront spends that many
+ * event steps on a group, so n_events_packed / (64 * lane_steps) is the
+ * fraction of busy lanes).
  */
 typedef struct {
   int64_t n_events_packed, n_units, n_groups;
   int32_t n_tiles, tile_log2, max_tile_groups;
   int64_t packed_bytes;
   double pack_ms;
+  int64_t lane_steps;
 } gtp_plan_stats;
 gtp_status gtp_plan_info(gtp_ctx ctx, gtp_plan_stats* out);
 

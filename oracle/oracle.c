@@ -5,13 +5,13 @@
  * baseline of the benchmark; never by the product library, with which it
  * shares no code.
  *
- * What it computes (paper Sec. 2.2 power models, Sec. 2.3 Naive-D/Naive-L,
+ * What it computes (paper Sec. 2.2 power models, Sec. 2.4 Naive-D/Naive-L,
  * Sec. 4.3 fused kernel, Algorithm 1). For each gate, in time order, one
  * timestamp group at a time (all events of the gate that share a time):
  *   1. leakage of the interval since the previous group at the leakage value
  *      selected by the current input state (state-indexed lookup, Sec. 4.1),
  *      E_leak = p_leak * dt (Eq. leakage energy), split over the time bins it
- *      overlaps in proportion to the overlap (Sec. 2.3, Naive-L);
+ *      overlaps in proportion to the overlap (Sec. 2.4, Naive-L);
  *   2. for every event of the group, the internal energy read from the table
  *      chosen by the state before the group and the event's new value, by
  *      bilinear interpolation at (input slew, output load) (Sec. 2.2), plus

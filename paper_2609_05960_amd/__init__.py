@@ -81,7 +81,7 @@ class _Tuning(ctypes.Structure):
 class _PlanStats(ctypes.Structure):
     _fields_ = [("n_events_packed", ctypes.c_int64), ("n_units", ctypes.c_int64), ("n_groups", ctypes.c_int64),
                 ("n_tiles", ctypes.c_int32), ("tile_log2", ctypes.c_int32), ("max_tile_groups", ctypes.c_int32),
-                ("packed_bytes", ctypes.c_int64), ("pack_ms", ctypes.c_double)]
+                ("packed_bytes", ctypes.c_int64), ("pack_ms", ctypes.c_double), ("lane_steps", ctypes.c_int64)]
 
 
 _lib = None

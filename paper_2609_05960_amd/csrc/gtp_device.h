@@ -27,7 +27,7 @@
 // adds the step q(after) - q(before): per gate the steps telescope exactly, so
 // the rate at any time is exactly the quantised rate of the state held.
 //
-// Leakage in step form (an exact rewrite of the interval rule of Sec. 2.3,
+// Leakage in step form (an exact rewrite of the interval rule of Sec. 2.4,
 // Eq. leakage energy): with R(t) = sum_g q_g(s_g(t)) the total rate, the
 // leakage energy of bin b is  D * R(b*D) + sum over steps d at time t in bin b
 // of d * ((b+1)*D - t).  So each input event contributes its step d to S[b]
@@ -46,10 +46,14 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-// Packed event word: bits [0, 27) in-tile time (bin_in_tile << r_bits | r),
-// [27, 31) pin (15 marks nothing), bit 31 the new value.
+// Packed event word: bits [0, 23) in-tile time (bin_in_tile << r_bits | r),
+// [23, 27) slew-axis segment of the event's slew on its cell's axis (the
+// knots at or below the slew, minus one, clamped to the axis), [27, 31) pin,
+// bit 31 the new value.
+constexpr int kTimeBits = 23;
+constexpr uint32_t kTimeMask = (1u << kTimeBits) - 1u;
+constexpr int kSegShift = 23;
 constexpr int kPinShift = 27;
-constexpr uint32_t kTimeMask = (1u << kPinShift) - 1u;
 constexpr int kMaxPin = 14;
 
 // Per-cell record staged in LDS.
@@ -165,6 +169,13 @@ __device__ __forceinline__ int64_t energy_fixed(float e, float two_sh) {
   const int32_t hi = (int32_t)h;
   const uint32_t lo = (uint32_t)f;
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)lo);
+}
+
+// Slew segment i = clamp(#knots <= slew - 1, 0, n-2).
+__device__ __forceinline__ int slew_seg_index(const float* axis, int n, float slew) {
+  int k = 0;
+  for (int m = 1; m < n - 1; ++m) k += (axis[m] <= slew) ? 1 : 0;
+  return k;
 }
 
 // Slew segment i = clamp(#knots <= slew - 1, 0, n-2) and its weight alpha.

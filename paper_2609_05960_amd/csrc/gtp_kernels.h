@@ -99,23 +99,6 @@ struct PackedFwdArgs {
 
 __device__ __forceinline__ size_t packed_bins_word_offset(int32_t lib_words) { return (size_t)((lib_words + 1) & ~1); }
 
-// Slew segment with the interior knots of a kNS-knot axis held in registers
-// (same result as slew_segment: i = #{m in 1..kNS-2 : knot_m <= slew}).
-template <int kNS>
-struct SlewKnots {
-  float k[kNS > 2 ? kNS - 2 : 1];
-  __device__ __forceinline__ void load(const float* axis) {
-#pragma unroll
-    for (int m = 1; m < kNS - 1; ++m) k[m - 1] = axis[m];
-  }
-  __device__ __forceinline__ int seg(float slew) const {
-    int i = 0;
-#pragma unroll
-    for (int m = 0; m < kNS - 2; ++m) i += (k[m] <= slew) ? 1 : 0;
-    return i;
-  }
-};
-
 // One wavefront group's data in registers: unit descriptor, gate
 // parameters and the lane's events (k-major positions resolved).
 struct GroupRegs {
@@ -137,8 +120,12 @@ __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int
   } else {
     G.gp.beta = 0.f; G.gp.lam = 0.f; G.gp.esw_rise = 0.f; G.gp.cell_jq = 0u;
   }
-  const uint32_t* __restrict__ wp = a.w32 + off;
-  const float* __restrict__ sp = a.slw + off;
+  // the offset is the same on every lane: keep it scalar so the loads use a
+  // scalar base and a 32-bit lane offset
+  const int64_t offu = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(off >> 32)) << 32) |
+                                 (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)off));
+  const uint32_t* __restrict__ wp = a.w32 + offu;
+  const float* __restrict__ sp = a.slw + offu;
   uint32_t o = 0;
   G.kmax = 0;
   // slot kk holds event kk of every lane longer than kk; slots past the
@@ -160,11 +147,95 @@ __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int
   }
 }
 
+// Accumulates one group (already loaded into G) into the tile's LDS bins.
+// Per-event lookups are double-buffered by event parity: while event k is
+// accumulated from buffer k&1, the state, table quad, slew weight and the
+// leakage value after event k+1 load into the other buffer, so no register is
+// reloaded while its previous value is still live.
+template <bool kDebug>
+__device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsLib& L, const GroupRegs& G,
+                                              unsigned long long* xs, unsigned long long* ss, int64_t gi,
+                                              int32_t tile, int lane) {
+  const BinSpec& B = a.bins;
+  const uint32_t rmask = (1u << B.r_bits) - 1u;
+  const int32_t D32 = (int32_t)B.D;
+  const int32_t qstride = a.lut.n_load - 1;
+  const float4* __restrict__ quads = a.lut.quads;
+  const int len = G.len;
+  const GateParam gp = G.gp;
+  const int cell = (int)(gp.cell_jq >> 8);
+  const int jq = (int)(gp.cell_jq & 0xffu);
+  const CellMeta cm = L.meta[cell];
+  const uint32_t in_mask = (1u << cm.n_in) - 1u;
+  const uint32_t st = G.d.y & 0xffffu;
+  const float esw_fall = a.sw_mode ? 0.0f : gp.esw_rise;
+  int32_t q_cur = qrate(gp.lam, L.leak[cm.leak_off + (int)(st & in_mask)], a.lut.rate_scale);
+  const float* sax = L.slew + cm.axis_off;
+  const float* sinv = L.slew_inv + cm.axis_off;
+  const int32_t* mq = L.map_q + cm.map_off;
+  const float* lk = L.leak + cm.leak_off;
+  struct Pre {
+    uint32_t s;      // input state before the event's group
+    float alpha;     // slew weight
+    float4 q;        // table quad
+    float lk_after;  // leakage value of the input state after the event
+  };
+  auto prefetch = [&](int k, uint32_t pgs, uint32_t par_after_k, Pre& P) {
+    const uint32_t w = G.wv[k];
+    const float slew = G.sv[k];
+    P.s = (st ^ pgs) & in_mask;
+    const int v = (int)(w >> 31);
+    const int32_t qb = mq[2 * (int)P.s + v];
+    const int i = (int)((w >> kSegShift) & 15u);  // slew-axis segment (from the pack)
+    P.alpha = __fmul_rn(__fsub_rn(slew, sax[i]), sinv[i]);
+    P.lk_after = lk[(par_after_k ^ st) & in_mask];
+    P.q = quads[(uint32_t)(qb + i * qstride + jq)];
+  };
+  auto pin_bit = [&](int k) -> uint32_t { return 1u << ((G.wv[k] >> kPinShift) & 15u); };
+  uint32_t par = 0;
+  uint32_t par_gs = ((G.d.y >> 16) ^ st) & 0xffffu;
+  Pre pre[2];
+  if (len > 0) prefetch(0, par_gs, pin_bit(0), pre[0]);
+#pragma unroll
+  for (int kk = 0; kk < kLaneEvents; ++kk) {
+    if (kk < G.kmax && len > kk) {
+      const uint32_t w = G.wv[kk];
+      const uint32_t tl = w & kTimeMask;
+      const int pin = (int)((w >> kPinShift) & 15u);
+      const int v = (int)(w >> 31);
+      const uint32_t par_after = par ^ (1u << pin);
+      if (kk + 1 < kLaneEvents && len > kk + 1) {
+        if ((G.wv[kk + 1] & kTimeMask) != tl) par_gs = par_after;
+        prefetch(kk + 1, par_gs, par_after ^ pin_bit(kk + 1), pre[(kk + 1) & 1]);
+      }
+      const Pre& P = pre[kk & 1];
+      float e = bilerp_quad(P.q, P.alpha, gp.beta);
+      if (pin == cm.n_in) e = __fadd_rn(e, v ? gp.esw_rise : esw_fall);
+      int64_t x = energy_fixed(e, a.lut.two_sh);
+      const uint32_t bl = tl >> B.r_bits;
+      // leakage step: an output event leaves the input state (and so the
+      // rate) unchanged, so dq = 0 for it without a branch
+      const int32_t qn = qrate(gp.lam, P.lk_after, a.lut.rate_scale);
+      const int32_t dq = qn - q_cur;
+      q_cur = qn;
+      x += (int64_t)dq * (int64_t)(D32 - (int32_t)(tl & rmask));
+      if (dq != 0) atomicAdd(&ss[bl], (unsigned long long)(int64_t)dq);
+      atomicAdd(&xs[bl], (unsigned long long)x);
+      par = par_after;
+      if (kDebug) {
+        const int64_t e_src = a.dsrc[gi * kGroupUnits + lane] + kk;
+        a.dbg_state[e_src] = (int32_t)P.s;
+        a.dbg_bin[e_src] = ((int64_t)tile << B.tile_log2) + bl;
+      }
+    }
+  }
+}
+
 // Memory-level parallelism: a wavefront works on group i while the loads of
 // group i+1 (gate parameters, events) and the descriptors of group i+2 are in
-// flight, and gathers the table quad of event k+1 before it finishes event k.
-// kNS: knots of every slew axis (0 = any, looked up in LDS per event).
-template <int kThreads, int kNS, bool kDebug>
+// flight. The loop alternates two register buffers, so nothing is copied
+// between groups.
+template <int kThreads, bool kDebug>
 __global__ void __launch_bounds__(kThreads) k_fwd_packed(PackedFwdArgs a) {
   extern __shared__ uint32_t lds[];
   const LdsLib L = stage_library(a.lib, lds);
@@ -177,117 +248,32 @@ __global__ void __launch_bounds__(kThreads) k_fwd_packed(PackedFwdArgs a) {
   const int64_t g1 = a.tile_grp[tile + 1];
   const int lane = (int)(threadIdx.x & 63);
   constexpr int nwave = kThreads / 64;
-  const uint32_t rmask = (1u << B.r_bits) - 1u;
-  const int32_t D32 = (int32_t)B.D;
-  const int32_t qstride = a.lut.n_load - 1;
-  const float4* __restrict__ quads = a.lut.quads;
   int64_t gi = a.tile_grp[tile] + (int64_t)(threadIdx.x >> 6);
-  // pipeline: cur = group gi (loads issued), nxt desc = group gi + nwave
-  GroupRegs cur;
+  GroupRegs ga, gb;
   uint2 dn = make_uint2(0xffffffffu, 0u);
   int64_t offn = 0;
-  if (gi < g1) {
-    const uint2 d0 = a.desc[gi * kGroupUnits + lane];
-    const int64_t off0 = a.grp_off[gi];
-    group_issue(a, d0, off0, cur);
-    if (gi + nwave < g1) {
-      dn = a.desc[(gi + nwave) * kGroupUnits + lane];
-      offn = a.grp_off[gi + nwave];
+  // issue the loads of group g into R and prefetch the descriptor of g + nwave
+  auto issue = [&](int64_t g, GroupRegs& R) {
+    group_issue(a, dn, offn, R);
+    if (g + nwave < g1) {
+      dn = a.desc[(g + nwave) * kGroupUnits + lane];
+      offn = a.grp_off[g + nwave];
     }
+  };
+  if (gi < g1) {
+    dn = a.desc[gi * kGroupUnits + lane];
+    offn = a.grp_off[gi];
+    issue(gi, ga);
   }
   __syncthreads();
   while (gi < g1) {
-    const int64_t gn = gi + nwave;
-    GroupRegs nxt;
-    nxt.len = 0;
-    nxt.kmax = 0;
-    if (gn < g1) {
-      group_issue(a, dn, offn, nxt);
-      if (gn + nwave < g1) {
-        dn = a.desc[(gn + nwave) * kGroupUnits + lane];
-        offn = a.grp_off[gn + nwave];
-      }
-    }
-    // ---- process group gi ----
-    const int len = cur.len;
-    const GateParam gp = cur.gp;
-    const int cell = (int)(gp.cell_jq >> 8);
-    const int jq = (int)(gp.cell_jq & 0xffu);
-    const CellMeta cm = L.meta[cell];
-    const uint32_t in_mask = (1u << cm.n_in) - 1u;
-    const uint32_t st = cur.d.y & 0xffffu;
-    const float esw_fall = a.sw_mode ? 0.0f : gp.esw_rise;
-    int32_t q_cur = qrate(gp.lam, L.leak[cm.leak_off + (int)(st & in_mask)], a.lut.rate_scale);
-    const float* sax = L.slew + cm.axis_off;
-    const float* sinv = L.slew_inv + cm.axis_off;
-    const int32_t* mq = L.map_q + cm.map_off;
-    const float* lk = L.leak + cm.leak_off;
-    SlewKnots<kNS> knots;
-    if (kNS > 0) knots.load(sax);
-    // lookup of an event: state before its group, table quad index, slew weight
-    auto lookup = [&](uint32_t w, float slew, uint32_t pgs, uint32_t& s, uint32_t& qi, float& alpha) {
-      s = (st ^ pgs) & in_mask;
-      const int v = (int)(w >> 31);
-      const int32_t qb = mq[2 * (int)s + v];
-      int i;
-      if (kNS > 0) {
-        i = knots.seg(slew);
-        alpha = __fmul_rn(__fsub_rn(slew, sax[i]), sinv[i]);
-      } else {
-        slew_segment(sax, sinv, a.lut.n_slew, slew, i, alpha);
-      }
-      qi = (uint32_t)(qb + i * qstride + jq);
-    };
-    uint32_t par = 0;
-    uint32_t par_gs = ((cur.d.y >> 16) ^ st) & 0xffffu;
-    uint32_t s_n = 0;
-    float alpha_n = 0.f;
-    float4 q_n = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (len > 0) {
-      uint32_t qi;
-      lookup(cur.wv[0], cur.sv[0], par_gs, s_n, qi, alpha_n);
-      q_n = quads[qi];
-    }
-#pragma unroll
-    for (int kk = 0; kk < kLaneEvents; ++kk) {
-      if (kk < cur.kmax && len > kk) {
-        const uint32_t w = cur.wv[kk];
-        const uint32_t s = s_n;
-        const float alpha = alpha_n;
-        const float4 q = q_n;
-        const uint32_t tl = w & kTimeMask;
-        const int pin = (int)((w >> kPinShift) & 15u);
-        const int v = (int)(w >> 31);
-        const uint32_t par_after = par ^ (1u << pin);
-        if (kk + 1 < kLaneEvents && len > kk + 1) {
-          const uint32_t w1 = cur.wv[kk + 1];
-          if ((w1 & kTimeMask) != tl) par_gs = par_after;
-          uint32_t qi;
-          lookup(w1, cur.sv[kk + 1], par_gs, s_n, qi, alpha_n);
-          q_n = quads[qi];
-        }
-        float e = bilerp_quad(q, alpha, gp.beta);
-        if (pin == cm.n_in) e = __fadd_rn(e, v ? gp.esw_rise : esw_fall);
-        int64_t x = energy_fixed(e, a.lut.two_sh);
-        const uint32_t bl = tl >> B.r_bits;
-        // leakage step: an output event leaves the input state (and so the
-        // rate) unchanged, so dq = 0 for it without a branch
-        const int32_t qn = qrate(gp.lam, lk[(par_after ^ st) & in_mask], a.lut.rate_scale);
-        const int32_t dq = qn - q_cur;
-        q_cur = qn;
-        x += (int64_t)dq * (int64_t)(D32 - (int32_t)(tl & rmask));
-        if (dq != 0) atomicAdd(&ss[bl], (unsigned long long)(int64_t)dq);
-        atomicAdd(&xs[bl], (unsigned long long)x);
-        par = par_after;
-        if (kDebug) {
-          const int64_t e_src = a.dsrc[gi * kGroupUnits + lane] + kk;
-          a.dbg_state[e_src] = (int32_t)s;
-          a.dbg_bin[e_src] = ((int64_t)tile << B.tile_log2) + bl;
-        }
-      }
-    }
-    cur = nxt;
-    gi = gn;
+    if (gi + nwave < g1) issue(gi + nwave, gb);
+    process_group<kDebug>(a, L, ga, xs, ss, gi, tile, lane);
+    gi += nwave;
+    if (gi >= g1) break;
+    if (gi + nwave < g1) issue(gi + nwave, ga);
+    process_group<kDebug>(a, L, gb, xs, ss, gi, tile, lane);
+    gi += nwave;
   }
   __syncthreads();
   const int64_t b0 = (int64_t)tile << B.tile_log2;

@@ -24,7 +24,8 @@
 //          loads of a wavefront are adjacent words.
 //
 // Arrays (device, owned by the ctx):
-//   w32[n]    packed event word (see gtp_device.h): in-tile time, pin, value
+//   w32[n]    packed event word (see gtp_device.h): in-tile time, slew-axis
+//             segment, pin, value
 //   slw[n]    slew (FP32)
 //   desc[64 * n_groups]   unit descriptor: x = cell-sorted gate index
 //             (bits 0..27) | (length-1) << 28, y = pin values before the
@@ -54,6 +55,8 @@ struct PackIn {
   const uint32_t* gate_init;  // [G] (device)
   std::vector<int32_t> h_gate_cell;  // [G] host copy
   std::vector<int32_t> n_in;         // [n_cells] inputs per cell
+  const float* slew_axis;     // [n_cells * n_slew] (device)
+  int32_t n_slew;
   BinSpec bins;               // tile_log2 and n_tiles set
   hipStream_t stream;
 };
@@ -72,6 +75,7 @@ struct PackOut {
   int64_t n_groups = 0;
   int64_t bytes = 0;          // device bytes held by the arrays above
   int32_t max_tile_groups = 0;
+  int64_t lane_steps = 0;     // sum over groups of the longest unit
 };
 
 // Builds the packed layout on in.stream (synchronises it). Returns

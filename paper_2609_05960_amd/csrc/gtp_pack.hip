@@ -148,9 +148,11 @@ __device__ __forceinline__ int32_t tile_of_group(const int32_t* tile_grp, int32_
   return lo;
 }
 
+// Events of each group (for the offsets) and its longest unit (the number of
+// lane steps the group costs a wavefront).
 __global__ void __launch_bounds__(256) k_pk_group_len(const int32_t* tile_grp, const uint32_t* tfirst, int32_t n_tiles,
                                                       const uint32_t* sidx, const UnitRec* recs, int64_t n_groups,
-                                                      int64_t* glen) {
+                                                      int64_t* glen, uint8_t* gmax) {
   const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gi > n_groups) return;
   if (gi == n_groups) {
@@ -161,13 +163,22 @@ __global__ void __launch_bounds__(256) k_pk_group_len(const int32_t* tile_grp, c
   const int64_t j0 = (int64_t)tfirst[k] + (gi - tile_grp[k]) * kGroupUnits;
   const int64_t j1 = min(j0 + kGroupUnits, (int64_t)tfirst[k + 1]);
   int64_t s = 0;
-  for (int64_t j = j0; j < j1; ++j) s += (int64_t)(recs[sidx[j]].x >> 28) + 1;
+  int mx = 0;
+  for (int64_t j = j0; j < j1; ++j) {
+    const int len = (int)(recs[sidx[j]].x >> 28) + 1;
+    s += len;
+    mx = max(mx, len);
+  }
   glen[gi] = s;
+  gmax[gi] = (uint8_t)mx;
 }
 
 struct FillArgs {
   EvView ev;
   BinSpec bins;
+  const float* slew_axis;
+  const int32_t* gcell;
+  int32_t n_slew;
   const int32_t* tile_grp;
   const uint32_t* tfirst;
   const uint32_t* sidx;
@@ -193,7 +204,7 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
   a.desc[gi * kGroupUnits + lane] = make_uint2(r.x, r.y);
   a.dsrc[gi * kGroupUnits + lane] = r.src;
   const int len = act ? (int)(r.x >> 28) + 1 : 0;
-  const int64_t tile_t0 = ((int64_t)k << B.tile_log2) * B.D;
+  const float* axis = a.slew_axis + (int64_t)(act ? a.gcell[r.x & 0x0fffffffu] : 0) * a.n_slew;
   int64_t off = a.grp_off[gi];
   for (int kk = 0; kk < kLaneEvents; ++kk) {
     const bool on = len > kk;
@@ -208,10 +219,11 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
       const int64_t bin = bin_of(t, B);
       const uint32_t bl = (uint32_t)(bin - ((int64_t)k << B.tile_log2));
       const uint32_t rr = (uint32_t)(t - bin * B.D);
-      (void)tile_t0;
       const uint32_t pin = min(pb >> 1, (uint32_t)kMaxPin);
-      a.w32[pos] = (bl << B.r_bits) | rr | (pin << kPinShift) | ((pb & 1u) << 31);
-      a.slw[pos] = a.ev.slew[e];
+      const float slew = a.ev.slew[e];
+      const uint32_t seg = (uint32_t)slew_seg_index(axis, a.n_slew, slew);
+      a.w32[pos] = (bl << B.r_bits) | rr | (seg << kSegShift) | (pin << kPinShift) | ((pb & 1u) << 31);
+      a.slw[pos] = slew;
     }
     off += __popcll(m);
   }
@@ -426,9 +438,19 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     PK(e2);
     o.grp_off = (int64_t*)own((size_t)(ng + 1) * 8, e2);
     PK(e2);
+    uint8_t* gmax = (uint8_t*)tmp((size_t)(ng + 1), e2);
+    PK(e2);
     hipLaunchKernelGGL(k_pk_group_len, dim3((unsigned)((ng + 1 + 255) / 256)), dim3(256), 0, s, o.tile_grp, tfirst,
-                       n_tiles, sidx, recs, ng, glen);
+                       n_tiles, sidx, recs, ng, glen, gmax);
     PKLAUNCH("k_pk_group_len");
+    {
+      std::vector<uint8_t> hm((size_t)ng);
+      if (ng > 0) PK(hipMemcpyAsync(hm.data(), gmax, (size_t)ng, hipMemcpyDeviceToHost, s));
+      PK(hipStreamSynchronize(s));
+      int64_t steps = 0;
+      for (uint8_t m : hm) steps += m;
+      o.lane_steps = steps;
+    }
     {
       size_t tb = 0;
       PK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, glen, o.grp_off, (int)(ng + 1), s));
@@ -453,6 +475,9 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       FillArgs fa;
       fa.ev = in.ev;
       fa.bins = B;
+      fa.slew_axis = in.slew_axis;
+      fa.gcell = o.gcell;
+      fa.n_slew = in.n_slew;
       fa.tile_grp = o.tile_grp;
       fa.tfirst = tfirst;
       fa.sidx = sidx;

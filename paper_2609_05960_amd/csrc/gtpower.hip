@@ -326,12 +326,12 @@ gtp_status build_block_plan(gtp_ctx c) {
 
 // Bins per tile: the largest power of two (at most 2^12) that still gives
 // about two tiles per compute unit (480 or more), and a packed in-tile time
-// of at most 27 bits.
+// of at most kTimeBits bits.
 int auto_tile_log2(int64_t n_bins, int r_bits) {
   int lb = 0;
   while (lb < 12 && (n_bins >> (lb + 1)) >= 480) ++lb;
   lb = std::max(lb, 4);
-  return std::min(lb, 27 - r_bits);
+  return std::min(lb, kTimeBits - r_bits);
 }
 
 size_t lib_lds_bytes(gtp_ctx c) { return (size_t)c->lds_words * 4; }
@@ -349,11 +349,8 @@ hipError_t lds_limit(K kern) {
 
 hipError_t set_packed_lds_limits() {
   hipError_t e = hipSuccess;
-  const hipError_t r[] = {
-      lds_limit(k_fwd_packed<256, 7, true>),   lds_limit(k_fwd_packed<256, 0, true>),
-      lds_limit(k_fwd_packed<256, 7, false>),  lds_limit(k_fwd_packed<256, 0, false>),
-      lds_limit(k_fwd_packed<512, 7, false>),  lds_limit(k_fwd_packed<512, 0, false>),
-      lds_limit(k_fwd_packed<1024, 7, false>), lds_limit(k_fwd_packed<1024, 0, false>)};
+  const hipError_t r[] = {lds_limit(k_fwd_packed<256, true>), lds_limit(k_fwd_packed<256, false>),
+                          lds_limit(k_fwd_packed<512, false>), lds_limit(k_fwd_packed<1024, false>)};
   for (hipError_t x : r)
     if (x != hipSuccess) e = x;
   return e;
@@ -372,10 +369,11 @@ gtp_status build_pack(gtp_ctx c) {
   if (c->pack_ok) return GTP_OK;
   drop_pack(c);
   BinSpec& B = c->bins;
-  if (B.r_bits > 27) return fail(c, GTP_ERR_UNSUPPORTED, "bin width above 2^27 ps");
+  if (B.r_bits > kTimeBits) return fail(c, GTP_ERR_UNSUPPORTED, "bin width above 2^%d ps", kTimeBits);
   int lb = c->tun.bins_per_tile_log2 ? c->tun.bins_per_tile_log2 : auto_tile_log2(B.n_bins, B.r_bits);
-  if (lb + B.r_bits > 27)
-    return fail(c, GTP_ERR_UNSUPPORTED, "tile of 2^%d bins with %d-bit in-bin offsets exceeds 27 bits", lb, B.r_bits);
+  if (lb + B.r_bits > kTimeBits)
+    return fail(c, GTP_ERR_UNSUPPORTED, "tile of 2^%d bins with %d-bit in-bin offsets exceeds %d bits", lb, B.r_bits,
+                kTimeBits);
   if (packed_lds_bytes(c, lb) > kMaxLds)
     return fail(c, GTP_ERR_UNSUPPORTED, "tile of 2^%d bins and the library image exceed the LDS", lb);
   const int64_t nt = (B.n_bins + (1ll << lb) - 1) >> lb;
@@ -391,6 +389,8 @@ gtp_status build_pack(gtp_ctx c) {
   in.gate_init = ptr<uint32_t>(c->gate_init);
   in.h_gate_cell = c->h_gate_cell;
   in.n_in = c->h_nin;
+  in.slew_axis = lib_view(c).slew;
+  in.n_slew = c->n_slew;
   in.bins = B;
   in.stream = c->stream;
   char msg[256] = {0};
@@ -751,7 +751,7 @@ gtp_status gtp_load_events(gtp_ctx c, const gtp_events* ev, int validate) {
 
 gtp_status gtp_set_params(gtp_ctx c, const gtp_params* p) {
   TRY(need(c, false, false, true, false));
-  if (!p || !(p->vdd > 0.0) || !std::isfinite(p->vdd) || p->bin_ps < 1 || p->bin_ps > (1 << 24) ||
+  if (!p || !(p->vdd > 0.0) || !std::isfinite(p->vdd) || p->bin_ps < 1 || p->bin_ps > (1 << 22) ||
       (p->sw_mode != 0 && p->sw_mode != 1))
     return fail(c, GTP_ERR_INVALID_ARG, "bad parameters");
   c->par = *p;
@@ -809,6 +809,7 @@ gtp_status gtp_plan_info(gtp_ctx c, gtp_plan_stats* out) {
   out->max_tile_groups = c->pk.max_tile_groups;
   out->packed_bytes = c->pk.bytes;
   out->pack_ms = c->pack_ms;
+  out->lane_steps = c->pk.lane_steps;
   return GTP_OK;
 }
 
@@ -883,18 +884,15 @@ gtp_status packed_forward(gtp_ctx c, int32_t* dbg_state, int64_t* dbg_bin) {
   a.dsrc = c->pk.dsrc;
   const size_t lds = packed_lds_bytes(c, B.tile_log2);
   const int th = c->tun.tile_threads ? c->tun.tile_threads : kTileThreads;
-  const bool ns7 = c->n_slew == 7;
   const dim3 grid((unsigned)B.n_tiles);
   if (dbg_state) {
-    if (ns7) LAUNCH(c, "k_fwd_packed_trace", (k_fwd_packed<256, 7, true>), grid, dim3(256), lds, a);
-    else LAUNCH(c, "k_fwd_packed_trace", (k_fwd_packed<256, 0, true>), grid, dim3(256), lds, a);
+    LAUNCH(c, "k_fwd_packed_trace", (k_fwd_packed<256, true>), grid, dim3(256), lds, a);
     return GTP_OK;
   }
-#define GTP_PACKED_CASE(TH)                                                                        \
-  if (th == TH) {                                                                                  \
-    if (ns7) LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, 7, false>), grid, dim3(TH), lds, a);      \
-    else LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, 0, false>), grid, dim3(TH), lds, a);          \
-    return GTP_OK;                                                                                 \
+#define GTP_PACKED_CASE(TH)                                                             \
+  if (th == TH) {                                                                       \
+    LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, false>), grid, dim3(TH), lds, a);        \
+    return GTP_OK;                                                                      \
   }
   GTP_PACKED_CASE(256)
   GTP_PACKED_CASE(512)
