@@ -153,13 +153,18 @@ gtp_status gtp_num_bins(gtp_ctx ctx, int64_t* n_bins);
  * bins_per_tile_log2: 0 = automatic, else 2..13 (bins per time tile of the
  * packed path; the tile's bins and the library image must fit in 160 KB of
  * LDS). tile_threads: threads per time-tile workgroup of the packed path,
- * 0 = automatic, else 256, 512 or 1024. Both paths give bit-identical
+ * 0 = automatic, else 256, 512 or 1024. unit_events: longest run of one
+ * gate's events one lane takes (the density split: denser gates are cut into
+ * more runs), 0 = 16, else 1..16. gate_block_log2: gates per sort block of the
+ * packed layout (log2), 0 = 14, else 6..20. Both paths give bit-identical
  * waveforms.
  */
 typedef struct {
   int32_t algo;
   int32_t bins_per_tile_log2;
   int32_t tile_threads;
+  int32_t unit_events;
+  int32_t gate_block_log2;
 } gtp_tuning;
 gtp_status gtp_set_tuning(gtp_ctx ctx, const gtp_tuning* t);
 gtp_status gtp_get_tuning(gtp_ctx ctx, gtp_tuning* t);
@@ -184,6 +189,17 @@ typedef struct {
 gtp_status gtp_plan_info(gtp_ctx ctx, gtp_plan_stats* out);
 
 /*
+ * Autotuner: times the packed forward on the loaded events (and, if a batch
+ * is loaded, the batched forward) for candidate tunings (bins per tile,
+ * threads per tile workgroup, longest run per lane, gate-block size), keeps
+ * the fastest and applies it with gtp_set_tuning. cache_json_path (HOST
+ * string, may be NULL): a JSON file of earlier choices keyed by device and
+ * workload signature; a hit skips the timing, a miss appends the choice.
+ * Synchronises; rebuilds the packed layouts.
+ */
+gtp_status gtp_autotune(gtp_ctx ctx, const char* cache_json_path);
+
+/*
  * Forward: power_mw[b] (DEVICE, [n_bins], FP32) = binned power for net loads
  * net_load_ff (DEVICE, [n_nets]) and leakage scales leak_scale (DEVICE,
  * [n_gates]; NULL = all 1). Accumulation is exact int64 fixed point, so the
@@ -199,6 +215,39 @@ gtp_status gtp_forward(gtp_ctx ctx, const float* net_load_ff, const float* leak_
  */
 gtp_status gtp_adjoint(gtp_ctx ctx, const float* net_load_ff, const float* leak_scale, const float* grad_power,
                        float* grad_net_load, float* grad_leak_scale);
+
+/*
+ * Batched traces: n_traces stimulus traces over the loaded netlist, each a
+ * gtp_events struct of DEVICE pointers, BORROWED as in gtp_load_events (trace
+ * i covers its own window [0, t_end_i)). Requires gtp_set_params (the traces share the
+ * bin width and switching mode) and replaces any earlier batch. validate = 1
+ * checks every event as gtp_load_events does and synchronises; a failure
+ * names the trace in gtp_last_error, and gtp_bad_event gives the event index
+ * within that trace. The packed layouts are built on the first batched call.
+ */
+gtp_status gtp_load_traces(gtp_ctx ctx, int32_t n_traces, const gtp_events* traces, int validate);
+
+/* Total bins of the loaded batch; offsets (HOST, [n_traces + 1], may be NULL)
+ * gets the first bin of every trace in the concatenated output. */
+gtp_status gtp_batch_bins(gtp_ctx ctx, int64_t* total, int64_t* offsets);
+
+/*
+ * Forward of every trace of the batch in one persistent launch: workgroups
+ * take (trace, time tile) work items from a device queue, largest first, so
+ * uneven trace lengths balance. power_mw (DEVICE, [total bins]) gets the
+ * waveforms back to back (trace i from offsets[i]). use_graph = 1 records the
+ * whole call (gate parameters, queue reset, persistent kernel, leakage scan,
+ * finalize) as a HIP graph on its first use and replays it afterwards; it is
+ * recorded again when net_load_ff, leak_scale or power_mw differ from the
+ * recorded pointers or the batch, parameters or tuning change.
+ */
+gtp_status gtp_forward_batched(gtp_ctx ctx, const float* net_load_ff, const float* leak_scale, float* power_mw,
+                               int use_graph);
+
+/* Forward of trace `trace` of the batch alone (its own launches), into
+ * power_mw (DEVICE, [its bins]): the per-trace reference of the batched call. */
+gtp_status gtp_forward_trace(gtp_ctx ctx, int32_t trace, const float* net_load_ff, const float* leak_scale,
+                             float* power_mw);
 
 /*
  * Per-event trace of the state tracking (DEVICE outputs, [n_events]):

@@ -36,7 +36,8 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "HIP", 4: "NOT_LOADE
 
 ABI_SYMBOLS = ["gtp_create", "gtp_destroy", "gtp_set_stream", "gtp_last_error", "gtp_sync", "gtp_load_library",
                "gtp_load_netlist", "gtp_load_events", "gtp_bad_event", "gtp_set_params", "gtp_num_bins",
-               "gtp_set_tuning", "gtp_get_tuning", "gtp_plan_info", "gtp_forward", "gtp_adjoint", "gtp_debug_event_trace",
+               "gtp_set_tuning", "gtp_get_tuning", "gtp_plan_info", "gtp_autotune", "gtp_load_traces",
+               "gtp_batch_bins", "gtp_forward_batched", "gtp_forward_trace", "gtp_forward", "gtp_adjoint", "gtp_debug_event_trace",
                "gtp_device_bytes", "gtp_profile_enable", "gtp_profile_read"]
 
 
@@ -75,7 +76,8 @@ class _Params(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("algo", ctypes.c_int32), ("bins_per_tile_log2", ctypes.c_int32), ("tile_threads", ctypes.c_int32)]
+    _fields_ = [("algo", ctypes.c_int32), ("bins_per_tile_log2", ctypes.c_int32), ("tile_threads", ctypes.c_int32),
+                ("unit_events", ctypes.c_int32), ("gate_block_log2", ctypes.c_int32)]
 
 
 class _PlanStats(ctypes.Structure):
@@ -104,6 +106,11 @@ def load_library(path: Optional[str] = None):
         "gtp_set_params": [vp, ctypes.POINTER(_Params)], "gtp_num_bins": [vp, ctypes.POINTER(i64)],
         "gtp_set_tuning": [vp, ctypes.POINTER(_Tuning)], "gtp_get_tuning": [vp, ctypes.POINTER(_Tuning)],
         "gtp_plan_info": [vp, ctypes.POINTER(_PlanStats)],
+        "gtp_autotune": [vp, ctypes.c_char_p],
+        "gtp_load_traces": [vp, i32, ctypes.POINTER(_Events), i32],
+        "gtp_batch_bins": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "gtp_forward_batched": [vp, vp, vp, vp, i32],
+        "gtp_forward_trace": [vp, i32, vp, vp, vp],
         "gtp_forward": [vp, vp, vp, vp], "gtp_adjoint": [vp, vp, vp, vp, vp, vp],
         "gtp_debug_event_trace": [vp, vp, vp],
     }
@@ -222,23 +229,83 @@ class Context:
             raise err
         self.n_events = t_ps.numel()
         self.t_end = int(t_end)
+        n = ctypes.c_int64()
+        if self.L.gtp_num_bins(self.h, ctypes.byref(n)) == 0:
+            self.n_bins = n.value
 
     def set_params(self, vdd: float = 0.8, bin_ps: int = 50, sw_mode: int = 0):
         p = _Params(float(vdd), int(bin_ps), int(sw_mode))
         self._chk(self.L.gtp_set_params(self.h, ctypes.byref(p)))
-        n = ctypes.c_int64()
-        self._chk(self.L.gtp_num_bins(self.h, ctypes.byref(n)))
-        self.n_bins = n.value
+        self.n_bins = 0
+        if "events" in self._keep:
+            n = ctypes.c_int64()
+            self._chk(self.L.gtp_num_bins(self.h, ctypes.byref(n)))
+            self.n_bins = n.value
         self.vdd, self.bin_ps, self.sw_mode = float(vdd), int(bin_ps), int(sw_mode)
 
-    def set_tuning(self, algo: int = 0, bins_per_tile_log2: int = 0, tile_threads: int = 0):
-        tu = _Tuning(int(algo), int(bins_per_tile_log2), int(tile_threads))
+    def set_tuning(self, algo: int = 0, bins_per_tile_log2: int = 0, tile_threads: int = 0, unit_events: int = 0,
+                   gate_block_log2: int = 0):
+        tu = _Tuning(int(algo), int(bins_per_tile_log2), int(tile_threads), int(unit_events), int(gate_block_log2))
         self._chk(self.L.gtp_set_tuning(self.h, ctypes.byref(tu)))
 
     def get_tuning(self):
         tu = _Tuning()
         self._chk(self.L.gtp_get_tuning(self.h, ctypes.byref(tu)))
-        return dict(algo=tu.algo, bins_per_tile_log2=tu.bins_per_tile_log2, tile_threads=tu.tile_threads)
+        return {k: getattr(tu, k) for k, _ in _Tuning._fields_}
+
+    def autotune(self, cache_path: Optional[str] = None):
+        """Pick the fastest tuning for the loaded events (or batch); see gtp_autotune."""
+        self._chk(self.L.gtp_autotune(self.h, cache_path.encode() if cache_path else None))
+        return self.get_tuning()
+
+    # -- batched traces -------------------------------------------------------
+    def load_traces(self, traces, validate: bool = False):
+        """traces: list of (gate_off, t_ps, pin_bit, slew_ps, t_end) device tensors
+        (borrowed; this object keeps references)."""
+        t = self.torch
+        arr = (_Events * len(traces))()
+        keep = []
+        for i, (go, tp, pb, sl, t_end) in enumerate(traces):
+            for x, dt in ((go, t.int64), (tp, t.int64), (pb, t.uint8), (sl, t.float32)):
+                if x.dtype != dt or not x.is_contiguous() or x.device != self.device:
+                    raise ValueError(f"event tensors must be contiguous {dt} on {self.device}")
+            arr[i].n_events, arr[i].t_end_ps = tp.numel(), int(t_end)
+            arr[i].gate_off, arr[i].t_ps, arr[i].pin_bit, arr[i].slew_ps = (_dptr(go), _dptr(tp), _dptr(pb),
+                                                                            _dptr(sl))
+            keep.append((go, tp, pb, sl))
+        self._keep["traces"] = keep
+        rc = self.L.gtp_load_traces(self.h, len(traces), arr, 1 if validate else 0)
+        if rc != 0:
+            err = GtpError(rc, self.L.gtp_last_error(self.h).decode())
+            err.bad_event = self.L.gtp_bad_event(self.h)
+            raise err
+        self.n_traces = len(traces)
+
+    def batch_bins(self):
+        """(total bins, offsets[n_traces + 1]) of the concatenated batched output."""
+        tot = ctypes.c_int64()
+        offs = (ctypes.c_int64 * (self.n_traces + 1))()
+        self._chk(self.L.gtp_batch_bins(self.h, ctypes.byref(tot), offs))
+        return tot.value, np.array(offs[:], dtype=np.int64)
+
+    def forward_batched(self, net_load, leak_scale=None, out=None, use_graph: bool = False):
+        net_load = self._vec(net_load, self.n_nets, "net_load")
+        leak_scale = self._vec(leak_scale, self.n_gates, "leak_scale")
+        if out is None:
+            tot, _ = self.batch_bins()
+            out = self.torch.empty(tot, dtype=self.torch.float32, device=self.device)
+        self._chk(self.L.gtp_forward_batched(self.h, _dptr(net_load), _dptr(leak_scale), _dptr(out),
+                                             1 if use_graph else 0))
+        return out
+
+    def forward_trace(self, i: int, net_load, leak_scale=None, out=None):
+        net_load = self._vec(net_load, self.n_nets, "net_load")
+        leak_scale = self._vec(leak_scale, self.n_gates, "leak_scale")
+        if out is None:
+            _, offs = self.batch_bins()
+            out = self.torch.empty(int(offs[i + 1] - offs[i]), dtype=self.torch.float32, device=self.device)
+        self._chk(self.L.gtp_forward_trace(self.h, int(i), _dptr(net_load), _dptr(leak_scale), _dptr(out)))
+        return out
 
     def plan_info(self) -> dict:
         """Statistics of the packed layout (built on demand; synchronises)."""

@@ -231,20 +231,18 @@ __device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsL
   }
 }
 
-// Memory-level parallelism: a wavefront works on group i while the loads of
-// group i+1 (gate parameters, events) and the descriptors of group i+2 are in
-// flight. The loop alternates two register buffers, so nothing is copied
-// between groups.
+// One time tile of one trace: the tile's bins are zeroed in LDS, every
+// wavefront takes whole groups of the tile, and the bins are stored at the
+// end (each bin belongs to exactly one tile). Memory-level parallelism: a
+// wavefront works on group i while the loads of group i+1 (gate parameters,
+// events) and the descriptors of group i+2 are in flight; the loop alternates
+// two register buffers, so nothing is copied between groups.
 template <int kThreads, bool kDebug>
-__global__ void __launch_bounds__(kThreads) k_fwd_packed(PackedFwdArgs a) {
-  extern __shared__ uint32_t lds[];
-  const LdsLib L = stage_library(a.lib, lds);
+__device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsLib& L, unsigned long long* xs,
+                                              unsigned long long* ss, int32_t tile) {
   const BinSpec& B = a.bins;
   const int nb = 1 << B.tile_log2;
-  unsigned long long* xs = reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.lib.lds_words));
-  unsigned long long* ss = xs + nb;
   for (int i = threadIdx.x; i < 2 * nb; i += kThreads) xs[i] = 0ull;
-  const int32_t tile = blockIdx.x;
   const int64_t g1 = a.tile_grp[tile + 1];
   const int lane = (int)(threadIdx.x & 63);
   constexpr int nwave = kThreads / 64;
@@ -282,6 +280,70 @@ __global__ void __launch_bounds__(kThreads) k_fwd_packed(PackedFwdArgs a) {
       a.X[b0 + i] = (int64_t)xs[i];
       a.S[b0 + i] = (int64_t)ss[i];
     }
+  }
+}
+
+// One workgroup per time tile of a single trace.
+template <int kThreads, bool kDebug>
+__global__ void __launch_bounds__(kThreads) k_fwd_packed(PackedFwdArgs a) {
+  extern __shared__ uint32_t lds[];
+  const LdsLib L = stage_library(a.lib, lds);
+  unsigned long long* xs = reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.lib.lds_words));
+  unsigned long long* ss = xs + (1 << a.bins.tile_log2);
+  fwd_tile_body<kThreads, kDebug>(a, L, xs, ss, (int32_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// batched traces: one persistent launch over all (trace, tile) work items
+// ---------------------------------------------------------------------------
+struct TraceDev {
+  const uint32_t* w32;
+  const float* slw;
+  const uint2* desc;
+  const int64_t* grp_off;
+  const int32_t* tile_grp;
+  BinSpec bins;
+  int64_t bin_off;   // first bin of the trace in the concatenated bins
+};
+
+struct BatchFwdArgs {
+  PackedFwdArgs base;          // shared fields: gate parameters, library, LUT, switching mode
+  const TraceDev* traces;
+  const int2* items;           // (trace, tile), largest first
+  int64_t n_items;
+  unsigned long long* queue;   // next item (zeroed before the launch)
+  int64_t* X;                  // concatenated bins
+  int64_t* S;
+};
+
+// Workgroups stay resident and take work items from the queue until it is
+// empty; every workgroup ends once it draws an index past the last item.
+template <int kThreads>
+__global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
+  extern __shared__ uint32_t lds[];
+  __shared__ long long item_sh;
+  const LdsLib L = stage_library(a.base.lib, lds);
+  for (;;) {
+    __syncthreads();  // the previous item is done with item_sh and the LDS bins
+    if (threadIdx.x == 0) item_sh = (long long)atomicAdd(a.queue, 1ull);
+    __syncthreads();
+    const long long it = item_sh;
+    if (it >= a.n_items) break;
+    const int2 w = a.items[it];
+    const TraceDev T = a.traces[w.x];
+    PackedFwdArgs p = a.base;
+    p.w32 = T.w32;
+    p.slw = T.slw;
+    p.desc = T.desc;
+    p.grp_off = T.grp_off;
+    p.tile_grp = T.tile_grp;
+    p.bins = T.bins;
+    p.X = a.X + T.bin_off;
+    p.S = a.S + T.bin_off;
+    unsigned long long* xs =
+        reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.base.lib.lds_words));
+    unsigned long long* ss = xs + (1 << T.bins.tile_log2);
+    fwd_tile_body<kThreads, false>(p, L, xs, ss, w.y);
   }
 }
 
@@ -482,6 +544,45 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
   if (b == a.n_bins - 1 && a.n_bins * a.D != a.t_end) {
     const int64_t w = a.t_end - b * a.D;
     E = a.X[b] - a.S[b] * (a.n_bins * a.D - a.t_end) + w * R;
+  } else {
+    E = a.X[b] + a.D * R;
+  }
+  a.P[b] = (float)((double)E * a.out_scale);
+}
+
+// Finalize of concatenated traces: the leakage prefix restarts at every
+// trace (exS is the exclusive prefix over the concatenation).
+struct FinTrace {
+  int64_t bin_off, n_bins, t_end;
+};
+
+struct FinBatchArgs {
+  const int64_t* X;
+  const int64_t* S;
+  const int64_t* exS;
+  const unsigned long long* L0;
+  const FinTrace* traces;
+  int32_t n_traces;
+  float* P;
+  int64_t total_bins, D;
+  double out_scale;
+};
+
+__global__ void __launch_bounds__(256) k_finalize_batched(FinBatchArgs a) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.total_bins) return;
+  int32_t lo = 0, hi = a.n_traces;  // last trace starting at or before b
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (a.traces[mid].bin_off <= b) lo = mid; else hi = mid;
+  }
+  const FinTrace T = a.traces[lo];
+  const int64_t bl = b - T.bin_off;
+  const int64_t R = (int64_t)*a.L0 + a.exS[b] - a.exS[T.bin_off];
+  int64_t E;
+  if (bl == T.n_bins - 1 && T.n_bins * a.D != T.t_end) {
+    const int64_t w = T.t_end - bl * a.D;
+    E = a.X[b] - a.S[b] * (T.n_bins * a.D - T.t_end) + w * R;
   } else {
     E = a.X[b] + a.D * R;
   }

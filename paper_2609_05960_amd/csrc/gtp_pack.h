@@ -46,7 +46,7 @@
 
 namespace gtp {
 
-constexpr int kGateBlockLog2 = 14;
+constexpr int kGateBlockLog2 = 14;   // default gate-block size (log2)
 
 struct PackIn {
   EvView ev;                  // gate-major events (device)
@@ -57,6 +57,8 @@ struct PackIn {
   std::vector<int32_t> n_in;         // [n_cells] inputs per cell
   const float* slew_axis;     // [n_cells * n_slew] (device)
   int32_t n_slew;
+  int32_t unit_events = kLaneEvents;          // longest unit, 1..16
+  int32_t gate_block_log2 = kGateBlockLog2;   // gates per gate block (log2)
   BinSpec bins;               // tile_log2 and n_tiles set
   hipStream_t stream;
 };

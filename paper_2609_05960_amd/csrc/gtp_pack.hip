@@ -2,7 +2,7 @@
 //
 // Steps (all on the caller's stream):
 //   1. gate order: gates sorted by cell (stable, host), cut into gate blocks
-//      of at most 2^14 gates of one cell;
+//      of at most 2^gate_block_log2 gates of one cell;
 //   2. k_pk_units (count pass): every gate-major lane block of 16 events is
 //      walked in order and split into units wherever the gate or the time
 //      tile changes; units per block are counted, then scanned;
@@ -36,6 +36,8 @@ struct UnitRec {
 
 struct KeySpec {
   int32_t gb_bits;                // bits of the gate-block field
+  int32_t gb_log2;                // gates per gate block (log2)
+  int32_t unit_cap;               // longest unit
   const int32_t* rank;            // gate -> cell-sorted index
   const int32_t* cell_start;      // [n_cells] first sorted index of the cell
   const int32_t* gb_base;         // [n_cells] first gate block of the cell
@@ -90,7 +92,7 @@ struct UnitVisitor {
     init = A->gate_init[g];
     const int32_t c = A->gate_cell[g];
     gs = A->ks.rank[g];
-    gblock = (uint32_t)(A->ks.gb_base[c] + ((gs - A->ks.cell_start[c]) >> kGateBlockLog2));
+    gblock = (uint32_t)(A->ks.gb_base[c] + ((gs - A->ks.cell_start[c]) >> A->ks.gb_log2));
     open = false;
   }
   __device__ __forceinline__ void end_gate(int64_t) { close(); }
@@ -101,7 +103,7 @@ struct UnitVisitor {
       return;
     }
     const int64_t tile = bin_of(t, B) >> B.tile_log2;
-    if (open && tile == u_tile) {
+    if (open && tile == u_tile && u_len < A->ks.unit_cap) {
       ++u_len;
       return;
     }
@@ -295,7 +297,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       cell_start[c] = acc;
       gb_base[c] = gbacc;
       acc += cnt[c];
-      gbacc += (cnt[c] + (1 << kGateBlockLog2) - 1) >> kGateBlockLog2;
+      gbacc += (cnt[c] + (1 << in.gate_block_log2) - 1) >> in.gate_block_log2;
     }
     const int32_t n_gb = std::max(gbacc, 1);
     std::vector<int32_t> rank((size_t)G), perm((size_t)G), pcell((size_t)G);
@@ -344,6 +346,8 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     ua.gate_init = in.gate_init;
     ua.bins = B;
     ua.ks.gb_bits = gb_bits;
+    ua.ks.gb_log2 = in.gate_block_log2;
+    ua.ks.unit_cap = in.unit_events;
     ua.ks.rank = d_rank;
     ua.ks.cell_start = d_cs;
     ua.ks.gb_base = d_gbb;

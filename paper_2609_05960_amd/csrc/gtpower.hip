@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <fstream>
+#include <sstream>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -44,6 +46,7 @@ struct DevBuf {
 
 struct gtp_ctx_s {
   int dev = 0;
+  int n_cu = 256;
   hipStream_t stream = nullptr;
   std::string err;
   int64_t bad_event = -1;
@@ -77,8 +80,29 @@ struct gtp_ctx_s {
   gtp_params par{};
   BinSpec bins{};
 
+  // batched traces
+  struct BatchTrace {
+    gtp_events ev{};
+    int64_t n_blocks = 0;
+    DevBuf plan;
+    BinSpec bins{};
+    PackOut pk;
+    double pack_ms = 0.0;
+    int64_t bin_off = 0;
+  };
+  std::vector<BatchTrace> batch;
+  bool batch_packed = false;
+  int64_t batch_total_bins = 0;
+  int64_t batch_items = 0;
+  DevBuf b_tab, b_items, b_queue, b_fin, b_X, b_S, b_exS;
+  DevBuf tun_in, tun_out;  // autotuner inputs and output
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* gkey[3] = {nullptr, nullptr, nullptr};
+
   // tuning + packed layout
-  gtp_tuning tun{0, 0, 0};
+  gtp_tuning tun{0, 0, 0, 0, 0};
   bool pack_ok = false;
   PackOut pk;
   double pack_ms = 0.0;
@@ -308,21 +332,25 @@ gtp_status need(gtp_ctx c, bool lib, bool net, bool ev, bool par) {
 // ----------------------------------------------------------------------------
 // plan
 // ----------------------------------------------------------------------------
-gtp_status build_block_plan(gtp_ctx c) {
-  const int64_t N = c->ev.n_events;
-  c->n_blocks = (N + kLaneEvents - 1) / kLaneEvents;
-  if (c->n_blocks == 0) return GTP_OK;
-  TRY(ensure(c, c->plan_blk, (size_t)c->n_blocks * sizeof(uint2)));
-  TRY(ensure(c, c->blk_tmp, (size_t)c->n_blocks * sizeof(uint32_t)));
-  TRY(ensure(c, c->blk_tmp2, (size_t)c->n_blocks * sizeof(uint32_t)));
-  uint2* plan = ptr<uint2>(c->plan_blk);
-  LAUNCH(c, "k_plan_block_gate", k_plan_block_gate, dim3(grid_for(c->n_blocks, 256)), dim3(256), 0, c->ev.gate_off, c->n_gates, N, plan, c->n_blocks);
-  LAUNCH(c, "k_plan_block_xor", k_plan_block_xor, dim3(grid_for(c->n_blocks, 256)), dim3(256), 0, c->ev.pin_bit, N, ptr<uint32_t>(c->blk_tmp), c->n_blocks);
-  TRY(scan_exclusive<uint32_t, OpXor>(c, ptr<uint32_t>(c->blk_tmp), ptr<uint32_t>(c->blk_tmp2), c->n_blocks, 0u,
+// Gate-major lane-block plan of an event set: first gate of every 16 events
+// and the toggle parity that gate carries into the block.
+gtp_status block_plan_for(gtp_ctx c, const gtp_events& ev, DevBuf& plan_buf, int64_t& n_blocks) {
+  const int64_t N = ev.n_events;
+  n_blocks = (N + kLaneEvents - 1) / kLaneEvents;
+  if (n_blocks == 0) return GTP_OK;
+  TRY(ensure(c, plan_buf, (size_t)n_blocks * sizeof(uint2)));
+  TRY(ensure(c, c->blk_tmp, (size_t)n_blocks * sizeof(uint32_t)));
+  TRY(ensure(c, c->blk_tmp2, (size_t)n_blocks * sizeof(uint32_t)));
+  uint2* plan = ptr<uint2>(plan_buf);
+  LAUNCH(c, "k_plan_block_gate", k_plan_block_gate, dim3(grid_for(n_blocks, 256)), dim3(256), 0, ev.gate_off, c->n_gates, N, plan, n_blocks);
+  LAUNCH(c, "k_plan_block_xor", k_plan_block_xor, dim3(grid_for(n_blocks, 256)), dim3(256), 0, ev.pin_bit, N, ptr<uint32_t>(c->blk_tmp), n_blocks);
+  TRY(scan_exclusive<uint32_t, OpXor>(c, ptr<uint32_t>(c->blk_tmp), ptr<uint32_t>(c->blk_tmp2), n_blocks, 0u,
                                       OpXor()));
-  LAUNCH(c, "k_plan_block_carry", k_plan_block_carry, dim3(grid_for(c->n_blocks, 256)), dim3(256), 0, c->ev.gate_off, c->ev.pin_bit, (const uint32_t*)ptr<uint32_t>(c->blk_tmp2), plan, c->n_blocks);
+  LAUNCH(c, "k_plan_block_carry", k_plan_block_carry, dim3(grid_for(n_blocks, 256)), dim3(256), 0, ev.gate_off, ev.pin_bit, (const uint32_t*)ptr<uint32_t>(c->blk_tmp2), plan, n_blocks);
   return GTP_OK;
 }
+
+gtp_status build_block_plan(gtp_ctx c) { return block_plan_for(c, c->ev, c->plan_blk, c->n_blocks); }
 
 // Bins per tile: the largest power of two (at most 2^12) that still gives
 // about two tiles per compute unit (480 or more), and a packed in-tile time
@@ -342,19 +370,30 @@ size_t packed_lds_bytes(gtp_ctx c, int tile_log2) {
 
 constexpr size_t kMaxLds = 160 * 1024;
 
+// static LDS of the batched kernel (its work-item slot), kept out of the
+// dynamic budget
+constexpr size_t kBatchStaticLds = 64;
+
 template <class K>
-hipError_t lds_limit(K kern) {
-  return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+hipError_t lds_limit(K kern, size_t static_lds = 0) {
+  return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(kMaxLds - static_lds));
 }
 
 hipError_t set_packed_lds_limits() {
   hipError_t e = hipSuccess;
-  const hipError_t r[] = {lds_limit(k_fwd_packed<256, true>), lds_limit(k_fwd_packed<256, false>),
-                          lds_limit(k_fwd_packed<512, false>), lds_limit(k_fwd_packed<1024, false>)};
+  const hipError_t r[] = {lds_limit(k_fwd_packed<256, true>),  lds_limit(k_fwd_packed<256, false>),
+                          lds_limit(k_fwd_packed<512, false>), lds_limit(k_fwd_packed<1024, false>),
+                          lds_limit(k_fwd_batched<256>, kBatchStaticLds), lds_limit(k_fwd_batched<512>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<1024>, kBatchStaticLds)};
   for (hipError_t x : r)
     if (x != hipSuccess) e = x;
   return e;
 }
+
+void drop_graph(gtp_ctx c);
+void drop_batch_packs(gtp_ctx c);
+void drop_batch(gtp_ctx c);
 
 void drop_pack(gtp_ctx c) {
   if (c->pk.w32 || c->pk.gperm) {
@@ -365,10 +404,30 @@ void drop_pack(gtp_ctx c) {
   c->pack_ok = false;
 }
 
-gtp_status build_pack(gtp_ctx c) {
-  if (c->pack_ok) return GTP_OK;
-  drop_pack(c);
-  BinSpec& B = c->bins;
+EvView ev_view_of(gtp_ctx c, const gtp_events& ev) {
+  EvView E;
+  E.t = ev.t_ps;
+  E.pb = ev.pin_bit;
+  E.slew = ev.slew_ps;
+  E.gate_off = ev.gate_off;
+  E.n = ev.n_events;
+  E.n_gates = c->n_gates;
+  return E;
+}
+
+// Bin layout of an event window under the ctx parameters.
+BinSpec bins_for(gtp_ctx c, int64_t t_end) {
+  BinSpec B = c->bins;
+  B.t_end = t_end;
+  B.n_bins = (t_end + B.D - 1) / B.D;
+  B.t32 = (t_end <= ((int64_t)1 << 32)) ? 1 : 0;
+  B.n_tiles = 0;
+  return B;
+}
+
+// Packed layout of one event set (plan_buf: its gate-major lane-block plan);
+// sets B.tile_log2 / B.n_tiles.
+gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, BinSpec& B, PackOut& pk, double& pack_ms) {
   if (B.r_bits > kTimeBits) return fail(c, GTP_ERR_UNSUPPORTED, "bin width above 2^%d ps", kTimeBits);
   int lb = c->tun.bins_per_tile_log2 ? c->tun.bins_per_tile_log2 : auto_tile_log2(B.n_bins, B.r_bits);
   if (lb + B.r_bits > kTimeBits)
@@ -378,19 +437,21 @@ gtp_status build_pack(gtp_ctx c) {
     return fail(c, GTP_ERR_UNSUPPORTED, "tile of 2^%d bins and the library image exceed the LDS", lb);
   const int64_t nt = (B.n_bins + (1ll << lb) - 1) >> lb;
   if (nt >= (int64_t)INT32_MAX / 2) return fail(c, GTP_ERR_UNSUPPORTED, "%lld time tiles", (long long)nt);
-  if (c->ev.n_events >= (int64_t)UINT32_MAX) return fail(c, GTP_ERR_UNSUPPORTED, "2^32 or more events in one trace");
+  if (ev.n_events >= (int64_t)UINT32_MAX) return fail(c, GTP_ERR_UNSUPPORTED, "2^32 or more events in one trace");
   if (c->n_gates >= (1ll << 28) - 1) return fail(c, GTP_ERR_UNSUPPORTED, "2^28 or more gates");
   B.tile_log2 = lb;
   B.n_tiles = (int32_t)nt;
   PackIn in;
-  in.ev = ev_view(c);
-  in.plan_blk = ptr<uint2>(c->plan_blk);
+  in.ev = ev_view_of(c, ev);
+  in.plan_blk = reinterpret_cast<const uint2*>(plan_buf.p);
   in.gate_cell = ptr<int32_t>(c->gate_cell);
   in.gate_init = ptr<uint32_t>(c->gate_init);
   in.h_gate_cell = c->h_gate_cell;
   in.n_in = c->h_nin;
   in.slew_axis = lib_view(c).slew;
   in.n_slew = c->n_slew;
+  in.unit_events = c->tun.unit_events ? c->tun.unit_events : kLaneEvents;
+  in.gate_block_log2 = c->tun.gate_block_log2 ? c->tun.gate_block_log2 : kGateBlockLog2;
   in.bins = B;
   in.stream = c->stream;
   char msg[256] = {0};
@@ -398,7 +459,7 @@ gtp_status build_pack(gtp_ctx c) {
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   if (e0) (void)hipEventRecord(e0, c->stream);
-  const hipError_t st = pack_events(in, &c->pk, msg, sizeof msg);
+  const hipError_t st = pack_events(in, &pk, msg, sizeof msg);
   if (st != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -409,11 +470,18 @@ gtp_status build_pack(gtp_ctx c) {
     (void)hipEventRecord(e1, c->stream);
     (void)hipEventSynchronize(e1);
     (void)hipEventElapsedTime(&ms, e0, e1);
-    c->pack_ms = ms;
+    pack_ms = ms;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  c->dev_bytes += c->pk.bytes;
+  c->dev_bytes += pk.bytes;
+  return GTP_OK;
+}
+
+gtp_status build_pack(gtp_ctx c) {
+  if (c->pack_ok) return GTP_OK;
+  drop_pack(c);
+  TRY(pack_for(c, c->ev, c->plan_blk, c->bins, c->pk, c->pack_ms));
   c->pack_ok = true;
   return GTP_OK;
 }
@@ -465,6 +533,12 @@ gtp_status gtp_create(gtp_ctx* out, int hip_device, void* hip_stream) {
   gtp_ctx c = new (std::nothrow) gtp_ctx_s();
   if (!c) return GTP_ERR_OUT_OF_MEMORY;
   c->dev = hip_device;
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
+      c->n_cu = cus;
+    (void)hipGetLastError();
+  }
   c->stream = (hipStream_t)hip_stream;
   if (hipSetDevice(hip_device) != hipSuccess) {
     delete c;
@@ -493,10 +567,13 @@ gtp_status gtp_destroy(gtp_ctx c) {
   (void)hipSetDevice(c->dev);
   (void)hipStreamSynchronize(c->stream);
   drop_pack(c);
+  drop_batch(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   DevBuf* all[] = {&c->lib_img, &c->load_axis, &c->load_inv, &c->quads, &c->gate_cell, &c->gate_out,
                    &c->gate_init, &c->plan_blk, &c->blk_tmp, &c->blk_tmp2, &c->scan_sums, &c->gprep, &c->gparam,
                    &c->X, &c->S, &c->exS, &c->L0, &c->flag, &c->first_bad, &c->adj_w, &c->adj_c, &c->adj_exc,
-                   &c->adj_wg, &c->adj_total, &c->gC, &c->gL};
+                   &c->adj_wg, &c->adj_total, &c->gC, &c->gL, &c->b_tab, &c->b_items, &c->b_queue,
+                   &c->b_fin, &c->b_X, &c->b_S, &c->b_exS, &c->tun_in, &c->tun_out};
   for (DevBuf* b : all) release(c, *b);
   prof_clear(c);
   for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
@@ -645,6 +722,7 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
   c->net_ok = false;
   c->ev_ok = false;
   drop_pack(c);
+  drop_batch(c);
   return GTP_OK;
 }
 
@@ -656,6 +734,54 @@ __global__ void k_check_netlist(const int32_t* cell, const int32_t* out, int64_t
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   if (cell[g] < 0 || cell[g] >= n_cells || out[g] < 0 || (int64_t)out[g] >= n_nets) atomicOr(bad, 1);
+}
+// Checks every event of ev (synchronises); the first offending event in
+// gate-major order sets c->bad_event and the status.
+gtp_status validate_events(gtp_ctx c, const gtp_events& ev, const DevBuf& plan, int64_t n_blocks) {
+  if (n_blocks == 0) return GTP_OK;
+  TRY(fill_u64(c, c->first_bad.p, 1, ~0ull));
+  ValArgs a;
+  a.ev = ev_view_of(c, ev);
+  a.plan = reinterpret_cast<const uint2*>(plan.p);
+  a.gate_cell = ptr<int32_t>(c->gate_cell);
+  a.gate_init = ptr<uint32_t>(c->gate_init);
+  a.meta = lib_view(c).meta;
+  a.t_end = ev.t_end_ps;
+  a.first = ptr<unsigned long long>(c->first_bad);
+  LAUNCH(c, "k_validate", k_validate, dim3(grid_for(n_blocks, kFwdThreads)), dim3(kFwdThreads), 0, a);
+  unsigned long long key = 0;
+  HIPCHK(c, hipMemcpyAsync(&key, c->first_bad.p, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (key != ~0ull) {
+    const int code = (int)(key & 7);
+    c->bad_event = (int64_t)(key >> 3);
+    static const char* what[] = {"", "time outside [0, t_end)", "time decreases within its gate",
+                                 "pin above the output pin", "pin repeated at one timestamp", "not a toggle"};
+    const gtp_status st = (code == 1 || code == 3) ? GTP_ERR_EVENT_RANGE
+                          : (code == 5)            ? GTP_ERR_NOT_TOGGLE
+                                                   : GTP_ERR_EVENT_ORDER;
+    return fail(c, st, "event %lld: %s", (long long)c->bad_event, what[code]);
+  }
+  return GTP_OK;
+}
+
+// Checks a caller's event descriptor against the netlist (synchronises).
+gtp_status check_event_desc(gtp_ctx c, const gtp_events* ev) {
+  if (!ev || ev->n_events < 0 || ev->t_end_ps <= 0) return fail(c, GTP_ERR_INVALID_ARG, "bad event descriptor");
+  if (!ev->gate_off) return fail(c, GTP_ERR_INVALID_ARG, "null gate_off");
+  if (ev->n_events > 0 && (!ev->t_ps || !ev->pin_bit || !ev->slew_ps))
+    return fail(c, GTP_ERR_INVALID_ARG, "null event array");
+  if (((uintptr_t)ev->t_ps | (uintptr_t)ev->pin_bit | (uintptr_t)ev->slew_ps) & 15)
+    return fail(c, GTP_ERR_INVALID_ARG, "event arrays must be 16-byte aligned");
+  if (c->n_gates == 0 && ev->n_events > 0) return fail(c, GTP_ERR_INVALID_ARG, "events without gates");
+  int64_t ends[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(&ends[0], ev->gate_off, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&ends[1], ev->gate_off + c->n_gates, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (ends[0] != 0 || ends[1] != ev->n_events)
+    return fail(c, GTP_ERR_INVALID_ARG, "gate_off must start at 0 and end at n_events (%lld, %lld)",
+                (long long)ends[0], (long long)ends[1]);
+  return GTP_OK;
 }
 }  // namespace
 
@@ -693,6 +819,7 @@ gtp_status gtp_load_netlist(gtp_ctx c, int64_t n_gates, int64_t n_nets, const in
   c->net_ok = true;
   c->ev_ok = false;
   drop_pack(c);
+  drop_batch(c);
   return GTP_OK;
 }
 
@@ -700,72 +827,38 @@ gtp_status gtp_load_events(gtp_ctx c, const gtp_events* ev, int validate) {
   TRY(need(c, true, true, false, false));
   HIPCHK(c, hipSetDevice(c->dev));
   c->bad_event = -1;
-  if (!ev || ev->n_events < 0 || ev->t_end_ps <= 0) return fail(c, GTP_ERR_INVALID_ARG, "bad event descriptor");
-  if (!ev->gate_off) return fail(c, GTP_ERR_INVALID_ARG, "null gate_off");
-  if (ev->n_events > 0 && (!ev->t_ps || !ev->pin_bit || !ev->slew_ps))
-    return fail(c, GTP_ERR_INVALID_ARG, "null event array");
-  if (((uintptr_t)ev->t_ps | (uintptr_t)ev->pin_bit | (uintptr_t)ev->slew_ps) & 15)
-    return fail(c, GTP_ERR_INVALID_ARG, "event arrays must be 16-byte aligned");
-  if (c->n_gates == 0 && ev->n_events > 0) return fail(c, GTP_ERR_INVALID_ARG, "events without gates");
-  int64_t ends[2] = {0, 0};
-  HIPCHK(c, hipMemcpyAsync(&ends[0], ev->gate_off, 8, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(&ends[1], ev->gate_off + c->n_gates, 8, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (ends[0] != 0 || ends[1] != ev->n_events)
-    return fail(c, GTP_ERR_INVALID_ARG, "gate_off must start at 0 and end at n_events (%lld, %lld)",
-                (long long)ends[0], (long long)ends[1]);
+  TRY(check_event_desc(c, ev));
   c->ev = *ev;
   c->ev_ok = false;
   drop_pack(c);
   TRY(build_block_plan(c));
   c->ev_ok = true;
-  if (c->par_ok && c->bins.t_end != ev->t_end_ps) c->par_ok = false;  // bins depend on t_end
-  if (validate && c->n_blocks > 0) {
-    TRY(fill_u64(c, c->first_bad.p, 1, ~0ull));
-    ValArgs a;
-    a.ev = ev_view(c);
-    a.plan = ptr<uint2>(c->plan_blk);
-    a.gate_cell = ptr<int32_t>(c->gate_cell);
-    a.gate_init = ptr<uint32_t>(c->gate_init);
-    a.meta = lib_view(c).meta;
-    a.t_end = ev->t_end_ps;
-    a.first = ptr<unsigned long long>(c->first_bad);
-    LAUNCH(c, "k_validate", k_validate, dim3(grid_for(c->n_blocks, kFwdThreads)), dim3(kFwdThreads), 0, a);
-    unsigned long long key = 0;
-    HIPCHK(c, hipMemcpyAsync(&key, c->first_bad.p, 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (key != ~0ull) {
-      const int code = (int)(key & 7);
-      c->bad_event = (int64_t)(key >> 3);
+  if (c->par_ok) c->bins = bins_for(c, ev->t_end_ps);  // bins depend on t_end
+  if (validate) {
+    const gtp_status st = validate_events(c, *ev, c->plan_blk, c->n_blocks);
+    if (st != GTP_OK) {
       c->ev_ok = false;
-      static const char* what[] = {"", "time outside [0, t_end)", "time decreases within its gate",
-                                   "pin above the output pin", "pin repeated at one timestamp", "not a toggle"};
-      const gtp_status st = (code == 1 || code == 3) ? GTP_ERR_EVENT_RANGE
-                            : (code == 5)            ? GTP_ERR_NOT_TOGGLE
-                                                     : GTP_ERR_EVENT_ORDER;
-      return fail(c, st, "event %lld: %s", (long long)c->bad_event, what[code]);
+      return st;
     }
   }
   return GTP_OK;
 }
 
 gtp_status gtp_set_params(gtp_ctx c, const gtp_params* p) {
-  TRY(need(c, false, false, true, false));
+  TRY(need(c, true, false, false, false));
   if (!p || !(p->vdd > 0.0) || !std::isfinite(p->vdd) || p->bin_ps < 1 || p->bin_ps > (1 << 22) ||
       (p->sw_mode != 0 && p->sw_mode != 1))
     return fail(c, GTP_ERR_INVALID_ARG, "bad parameters");
   c->par = *p;
   BinSpec& B = c->bins;
   B.D = p->bin_ps;
-  B.t_end = c->ev.t_end_ps;
-  B.n_bins = (B.t_end + B.D - 1) / B.D;
-  B.t32 = (B.t_end <= ((int64_t)1 << 32)) ? 1 : 0;
   B.div = make_div32((uint32_t)B.D);
   B.r_bits = ceil_log2((uint64_t)B.D);
   B.tile_log2 = 8;
-  B.n_tiles = 0;
+  B = bins_for(c, c->ev_ok ? c->ev.t_end_ps : 1);
   c->par_ok = true;
   drop_pack(c);
+  drop_batch_packs(c);
   return GTP_OK;
 }
 
@@ -783,7 +876,16 @@ gtp_status gtp_set_tuning(gtp_ctx c, const gtp_tuning* t) {
     return fail(c, GTP_ERR_INVALID_ARG, "bins_per_tile_log2 %d", t->bins_per_tile_log2);
   if (t->tile_threads != 0 && t->tile_threads != 256 && t->tile_threads != 512 && t->tile_threads != 1024)
     return fail(c, GTP_ERR_INVALID_ARG, "tile_threads %d (0, 256, 512 or 1024)", t->tile_threads);
-  if (t->bins_per_tile_log2 != c->tun.bins_per_tile_log2) drop_pack(c);
+  if (t->unit_events < 0 || t->unit_events > kLaneEvents)
+    return fail(c, GTP_ERR_INVALID_ARG, "unit_events %d (0..%d)", t->unit_events, kLaneEvents);
+  if (t->gate_block_log2 != 0 && (t->gate_block_log2 < 6 || t->gate_block_log2 > 20))
+    return fail(c, GTP_ERR_INVALID_ARG, "gate_block_log2 %d (0 or 6..20)", t->gate_block_log2);
+  if (t->bins_per_tile_log2 != c->tun.bins_per_tile_log2 || t->unit_events != c->tun.unit_events ||
+      t->gate_block_log2 != c->tun.gate_block_log2) {
+    drop_pack(c);
+    drop_batch_packs(c);
+  }
+  if (t->tile_threads != c->tun.tile_threads) drop_graph(c);
   c->tun = *t;
   return GTP_OK;
 }
@@ -793,6 +895,8 @@ gtp_status gtp_get_tuning(gtp_ctx c, gtp_tuning* t) {
   *t = c->tun;
   if (c->pack_ok && t->bins_per_tile_log2 == 0) t->bins_per_tile_log2 = c->bins.tile_log2;
   if (t->tile_threads == 0) t->tile_threads = kTileThreads;
+  if (t->unit_events == 0) t->unit_events = kLaneEvents;
+  if (t->gate_block_log2 == 0) t->gate_block_log2 = kGateBlockLog2;
   return GTP_OK;
 }
 
@@ -833,15 +937,15 @@ gtp_status final_bins(gtp_ctx c, float* power_mw) {
   return GTP_OK;
 }
 
-gtp_status gate_params(gtp_ctx c, const float* net_load, const float* leak_scale) {
+gtp_status gate_params_for(gtp_ctx c, const PackOut& pk, const float* net_load, const float* leak_scale) {
   TRY(ensure(c, c->gparam, (size_t)std::max<int64_t>(c->n_gates, 1) * sizeof(GateParam)));
   TRY(ensure(c, c->L0, 8));
   TRY(fill_u64(c, c->L0.p, 1, 0ull));
   if (c->n_gates == 0) return GTP_OK;
   const LibView L = lib_view(c);
   GateParamArgs a;
-  a.gperm = c->pk.gperm;
-  a.gcell = c->pk.gcell;
+  a.gperm = pk.gperm;
+  a.gcell = pk.gcell;
   a.gate_out = ptr<int32_t>(c->gate_out);
   a.gate_init = ptr<uint32_t>(c->gate_init);
   a.net_load = net_load;
@@ -863,27 +967,42 @@ gtp_status gate_params(gtp_ctx c, const float* net_load, const float* leak_scale
   return GTP_OK;
 }
 
-// Packed forward into X/S; with dbg_state set, also the per-event trace.
-gtp_status packed_forward(gtp_ctx c, int32_t* dbg_state, int64_t* dbg_bin) {
-  const BinSpec& B = c->bins;
-  PackedFwdArgs a;
-  a.w32 = c->pk.w32;
-  a.slw = c->pk.slw;
-  a.desc = c->pk.desc;
-  a.grp_off = c->pk.grp_off;
-  a.tile_grp = c->pk.tile_grp;
+gtp_status gate_params(gtp_ctx c, const float* net_load, const float* leak_scale) {
+  return gate_params_for(c, c->pk, net_load, leak_scale);
+}
+
+// Fields of the packed forward shared by every trace.
+PackedFwdArgs packed_common(gtp_ctx c) {
+  PackedFwdArgs a{};
   a.gparam = ptr<GateParam>(c->gparam);
   a.lib = lib_view(c);
   a.lut = lut_args(c);
-  a.bins = B;
   a.sw_mode = c->par.sw_mode;
-  a.X = ptr<int64_t>(c->X);
-  a.S = ptr<int64_t>(c->S);
+  a.dbg_state = nullptr;
+  a.dbg_bin = nullptr;
+  return a;
+}
+
+int tile_threads(gtp_ctx c) { return c->tun.tile_threads ? c->tun.tile_threads : kTileThreads; }
+
+// Packed forward of one trace into X/S; with dbg_state set, also the
+// per-event trace.
+gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, int64_t* X, int64_t* S,
+                              int32_t* dbg_state, int64_t* dbg_bin) {
+  PackedFwdArgs a = packed_common(c);
+  a.w32 = pk.w32;
+  a.slw = pk.slw;
+  a.desc = pk.desc;
+  a.grp_off = pk.grp_off;
+  a.tile_grp = pk.tile_grp;
+  a.bins = B;
+  a.X = X;
+  a.S = S;
   a.dbg_state = dbg_state;
   a.dbg_bin = dbg_bin;
-  a.dsrc = c->pk.dsrc;
+  a.dsrc = pk.dsrc;
   const size_t lds = packed_lds_bytes(c, B.tile_log2);
-  const int th = c->tun.tile_threads ? c->tun.tile_threads : kTileThreads;
+  const int th = tile_threads(c);
   const dim3 grid((unsigned)B.n_tiles);
   if (dbg_state) {
     LAUNCH(c, "k_fwd_packed_trace", (k_fwd_packed<256, true>), grid, dim3(256), lds, a);
@@ -899,6 +1018,183 @@ gtp_status packed_forward(gtp_ctx c, int32_t* dbg_state, int64_t* dbg_bin) {
   GTP_PACKED_CASE(1024)
 #undef GTP_PACKED_CASE
   return fail(c, GTP_ERR_INVALID_ARG, "tile_threads %d", th);
+}
+
+gtp_status packed_forward(gtp_ctx c, int32_t* dbg_state, int64_t* dbg_bin) {
+  return packed_forward_for(c, c->pk, c->bins, ptr<int64_t>(c->X), ptr<int64_t>(c->S), dbg_state, dbg_bin);
+}
+
+// ---------------------------------------------------------------------------
+// batched traces
+// ---------------------------------------------------------------------------
+void drop_graph(gtp_ctx c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->gkey[0] = c->gkey[1] = c->gkey[2] = nullptr;
+}
+
+void drop_batch_packs(gtp_ctx c) {
+  drop_graph(c);
+  if (c->batch_packed) (void)hipStreamSynchronize(c->stream);
+  for (auto& t : c->batch) {
+    if (t.pk.w32 || t.pk.gperm) {
+      c->dev_bytes -= t.pk.bytes;
+      pack_free(&t.pk);
+    }
+  }
+  c->batch_packed = false;
+}
+
+void drop_batch(gtp_ctx c) {
+  drop_batch_packs(c);
+  for (auto& t : c->batch) release(c, t.plan);
+  c->batch.clear();
+  c->batch_total_bins = 0;
+  c->batch_items = 0;
+}
+
+// Packs every trace with one bin-per-tile choice, builds the trace table, the
+// work items (largest first) and the finalize table.
+gtp_status build_batch(gtp_ctx c) {
+  if (c->batch_packed) return GTP_OK;
+  drop_batch_packs(c);
+  const int32_t nt = (int32_t)c->batch.size();
+  // one tile size for all traces (the queue balances uneven traces)
+  const BinSpec B0 = c->bins;
+  const int lb = c->tun.bins_per_tile_log2 ? c->tun.bins_per_tile_log2
+                                           : std::min(12, std::max(2, kTimeBits - B0.r_bits));
+  if (packed_lds_bytes(c, lb) + kBatchStaticLds > kMaxLds)
+    return fail(c, GTP_ERR_UNSUPPORTED, "tile of 2^%d bins and the library image exceed the LDS", lb);
+  gtp_tuning saved = c->tun;
+  c->tun.bins_per_tile_log2 = lb;
+  std::vector<TraceDev> tab((size_t)nt);
+  std::vector<FinTrace> fin((size_t)nt);
+  std::vector<std::pair<int64_t, int2>> items;
+  int64_t off = 0;
+  for (int32_t i = 0; i < nt; ++i) {
+    auto& t = c->batch[i];
+    t.bins = bins_for(c, t.ev.t_end_ps);
+    const gtp_status st = pack_for(c, t.ev, t.plan, t.bins, t.pk, t.pack_ms);
+    if (st != GTP_OK) {
+      c->tun = saved;
+      return st;
+    }
+    t.bin_off = off;
+    tab[i] = TraceDev{t.pk.w32, t.pk.slw, t.pk.desc, t.pk.grp_off, t.pk.tile_grp, t.bins, off};
+    fin[i] = FinTrace{off, t.bins.n_bins, t.bins.t_end};
+    off += t.bins.n_bins;
+    // events per tile, for the largest-first order
+    const int32_t ntile = t.bins.n_tiles;
+    std::vector<int32_t> tg((size_t)ntile + 1);
+    HIPCHK(c, hipMemcpy(tg.data(), t.pk.tile_grp, (size_t)(ntile + 1) * 4, hipMemcpyDeviceToHost));
+    std::vector<int64_t> go((size_t)t.pk.n_groups + 1);
+    HIPCHK(c, hipMemcpy(go.data(), t.pk.grp_off, (size_t)(t.pk.n_groups + 1) * 8, hipMemcpyDeviceToHost));
+    for (int32_t k = 0; k < ntile; ++k) items.push_back({go[tg[k + 1]] - go[tg[k]], make_int2(i, k)});
+  }
+  c->tun = saved;
+  std::stable_sort(items.begin(), items.end(),
+                   [](const std::pair<int64_t, int2>& x, const std::pair<int64_t, int2>& y) { return x.first > y.first; });
+  std::vector<int2> it(items.size());
+  for (size_t j = 0; j < items.size(); ++j) it[j] = items[j].second;
+  c->batch_total_bins = off;
+  c->batch_items = (int64_t)it.size();
+  TRY(ensure(c, c->b_tab, tab.size() * sizeof(TraceDev)));
+  TRY(ensure(c, c->b_fin, fin.size() * sizeof(FinTrace)));
+  TRY(ensure(c, c->b_items, std::max<size_t>(it.size(), 1) * sizeof(int2)));
+  TRY(ensure(c, c->b_queue, 256));
+  if (nt > 0) {
+    HIPCHK(c, hipMemcpy(c->b_tab.p, tab.data(), tab.size() * sizeof(TraceDev), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->b_fin.p, fin.data(), fin.size() * sizeof(FinTrace), hipMemcpyHostToDevice));
+  }
+  if (!it.empty()) HIPCHK(c, hipMemcpy(c->b_items.p, it.data(), it.size() * sizeof(int2), hipMemcpyHostToDevice));
+  const int64_t NB = std::max<int64_t>(off, 1);
+  TRY(ensure(c, c->b_X, (size_t)NB * 8));
+  TRY(ensure(c, c->b_S, (size_t)NB * 8));
+  TRY(ensure(c, c->b_exS, (size_t)NB * 8));
+  TRY(ensure(c, c->scan_sums, (size_t)((NB + kScanTile - 1) / kScanTile) * 8 + 8));
+  TRY(ensure(c, c->gparam, (size_t)std::max<int64_t>(c->n_gates, 1) * sizeof(GateParam)));
+  TRY(ensure(c, c->L0, 8));
+  c->batch_packed = true;
+  return GTP_OK;
+}
+
+// Every launch of a batched forward (no allocation, no synchronisation: safe
+// to record in a graph).
+gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_scale, float* power_mw) {
+  TRY(gate_params_for(c, c->batch[0].pk, net_load, leak_scale));
+  TRY(fill_u64(c, c->b_queue.p, 1, 0ull));
+  const int lb = c->batch[0].bins.tile_log2;
+  if (c->batch_items > 0) {
+    BatchFwdArgs a;
+    a.base = packed_common(c);
+    a.traces = ptr<TraceDev>(c->b_tab);
+    a.items = ptr<int2>(c->b_items);
+    a.n_items = c->batch_items;
+    a.queue = ptr<unsigned long long>(c->b_queue);
+    a.X = ptr<int64_t>(c->b_X);
+    a.S = ptr<int64_t>(c->b_S);
+    const size_t lds = packed_lds_bytes(c, lb);
+    const int th = tile_threads(c);
+    // resident workgroups: as many as fit (LDS-limited), at most one per item
+    int per_cu = (int)std::max<size_t>(1, kMaxLds / lds);
+    per_cu = std::min(per_cu, 2048 / th);
+    const int64_t wgs = std::min<int64_t>(c->batch_items, (int64_t)c->n_cu * per_cu);
+    const dim3 grid((unsigned)wgs);
+#define GTP_BATCH_CASE(TH)                                                              \
+  if (th == TH) {                                                                       \
+    LAUNCH(c, "k_fwd_batched", (k_fwd_batched<TH>), grid, dim3(TH), lds, a);             \
+  }
+    GTP_BATCH_CASE(256)
+    GTP_BATCH_CASE(512)
+    GTP_BATCH_CASE(1024)
+#undef GTP_BATCH_CASE
+  }
+  const int64_t NB = c->batch_total_bins;
+  TRY(scan_exclusive<int64_t, OpAdd>(c, ptr<int64_t>(c->b_S), ptr<int64_t>(c->b_exS), NB, (int64_t)0, OpAdd()));
+  FinBatchArgs f;
+  f.X = ptr<int64_t>(c->b_X);
+  f.S = ptr<int64_t>(c->b_S);
+  f.exS = ptr<int64_t>(c->b_exS);
+  f.L0 = ptr<unsigned long long>(c->L0);
+  f.traces = ptr<FinTrace>(c->b_fin);
+  f.n_traces = (int32_t)c->batch.size();
+  f.P = power_mw;
+  f.total_bins = NB;
+  f.D = c->bins.D;
+  f.out_scale = std::ldexp(1.0, -c->mfix) / (double)c->bins.D;
+  if (NB > 0) LAUNCH(c, "k_finalize_batched", k_finalize_batched, dim3(grid_for(NB, 256)), dim3(256), 0, f);
+  return GTP_OK;
+}
+
+// Records batched_enqueue into a graph on a private capture stream.
+gtp_status capture_batched(gtp_ctx c, const float* net_load, const float* leak_scale, float* power_mw) {
+  drop_graph(c);
+  if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipStream_t saved = c->stream;
+  const bool prof = c->prof_on;
+  c->prof_on = false;
+  c->stream = c->cap_stream;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  gtp_status st = GTP_OK;
+  if (e == hipSuccess) st = batched_enqueue(c, net_load, leak_scale, power_mw);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = (e == hipSuccess) ? hipStreamEndCapture(c->cap_stream, &g) : e;
+  c->stream = saved;
+  c->prof_on = prof;
+  if (e != hipSuccess || e2 != hipSuccess || st != GTP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    if (st != GTP_OK) return st;
+    return fail(c, GTP_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  c->graph = g;
+  HIPCHK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+  c->gkey[0] = net_load;
+  c->gkey[1] = leak_scale;
+  c->gkey[2] = power_mw;
+  return GTP_OK;
 }
 }  // namespace
 
@@ -934,6 +1230,213 @@ gtp_status gtp_forward(gtp_ctx c, const float* net_load_ff, const float* leak_sc
     }
   }
   return final_bins(c, power_mw);
+}
+
+gtp_status gtp_load_traces(gtp_ctx c, int32_t n_traces, const gtp_events* traces, int validate) {
+  TRY(need(c, true, true, false, true));
+  HIPCHK(c, hipSetDevice(c->dev));
+  c->bad_event = -1;
+  if (n_traces < 1 || !traces) return fail(c, GTP_ERR_INVALID_ARG, "need at least one trace");
+  drop_batch(c);
+  c->batch.resize((size_t)n_traces);
+  for (int32_t i = 0; i < n_traces; ++i) {
+    auto& t = c->batch[i];
+    gtp_status st = check_event_desc(c, &traces[i]);
+    if (st == GTP_OK) {
+      t.ev = traces[i];
+      st = block_plan_for(c, t.ev, t.plan, t.n_blocks);
+    }
+    if (st == GTP_OK && validate) st = validate_events(c, t.ev, t.plan, t.n_blocks);
+    if (st != GTP_OK) {
+      const std::string m = c->err;
+      drop_batch(c);
+      return fail(c, st, "trace %d: %s", (int)i, m.c_str());
+    }
+  }
+  return GTP_OK;
+}
+
+gtp_status gtp_batch_bins(gtp_ctx c, int64_t* total, int64_t* offsets) {
+  TRY(need(c, true, true, false, true));
+  if (c->batch.empty()) return fail(c, GTP_ERR_NOT_LOADED, "no batch loaded");
+  if (!total) return GTP_ERR_INVALID_ARG;
+  int64_t off = 0;
+  for (size_t i = 0; i < c->batch.size(); ++i) {
+    if (offsets) offsets[i] = off;
+    off += bins_for(c, c->batch[i].ev.t_end_ps).n_bins;
+  }
+  if (offsets) offsets[c->batch.size()] = off;
+  *total = off;
+  return GTP_OK;
+}
+
+gtp_status gtp_forward_batched(gtp_ctx c, const float* net_load_ff, const float* leak_scale, float* power_mw,
+                               int use_graph) {
+  TRY(need(c, true, true, false, true));
+  if (c->batch.empty()) return fail(c, GTP_ERR_NOT_LOADED, "no batch loaded");
+  if (!net_load_ff || !power_mw) return fail(c, GTP_ERR_INVALID_ARG, "null forward argument");
+  HIPCHK(c, hipSetDevice(c->dev));
+  TRY(build_batch(c));
+  if (!use_graph) return batched_enqueue(c, net_load_ff, leak_scale, power_mw);
+  if (!c->gexec || c->gkey[0] != net_load_ff || c->gkey[1] != leak_scale || c->gkey[2] != power_mw)
+    TRY(capture_batched(c, net_load_ff, leak_scale, power_mw));
+  prof_begin(c, "graph_forward_batched");
+  HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+  prof_end(c);
+  return GTP_OK;
+}
+
+gtp_status gtp_forward_trace(gtp_ctx c, int32_t trace, const float* net_load_ff, const float* leak_scale,
+                             float* power_mw) {
+  TRY(need(c, true, true, false, true));
+  if (trace < 0 || trace >= (int32_t)c->batch.size()) return fail(c, GTP_ERR_INVALID_ARG, "trace %d", (int)trace);
+  if (!net_load_ff || !power_mw) return fail(c, GTP_ERR_INVALID_ARG, "null forward argument");
+  HIPCHK(c, hipSetDevice(c->dev));
+  TRY(build_batch(c));
+  const auto& t = c->batch[trace];
+  const int64_t NB = t.bins.n_bins;
+  TRY(ensure(c, c->X, (size_t)NB * 8));
+  TRY(ensure(c, c->S, (size_t)NB * 8));
+  TRY(ensure(c, c->exS, (size_t)NB * 8));
+  TRY(gate_params_for(c, t.pk, net_load_ff, leak_scale));
+  TRY(packed_forward_for(c, t.pk, t.bins, ptr<int64_t>(c->X), ptr<int64_t>(c->S), nullptr, nullptr));
+  TRY(scan_exclusive<int64_t, OpAdd>(c, ptr<int64_t>(c->S), ptr<int64_t>(c->exS), NB, (int64_t)0, OpAdd()));
+  FinArgs f;
+  f.X = ptr<int64_t>(c->X);
+  f.S = ptr<int64_t>(c->S);
+  f.exS = ptr<int64_t>(c->exS);
+  f.L0 = ptr<unsigned long long>(c->L0);
+  f.P = power_mw;
+  f.n_bins = NB;
+  f.D = t.bins.D;
+  f.t_end = t.bins.t_end;
+  f.out_scale = std::ldexp(1.0, -c->mfix) / (double)t.bins.D;
+  LAUNCH(c, "k_finalize", k_finalize, dim3(grid_for(NB, 256)), dim3(256), 0, f);
+  return GTP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Signature of the loaded workload for the autotune cache.
+std::string tune_key(gtp_ctx c) {
+  hipDeviceProp_t pr;
+  std::string dev = "gpu";
+  if (hipGetDeviceProperties(&pr, c->dev) == hipSuccess) dev = pr.gcnArchName;
+  (void)hipGetLastError();
+  int64_t nev = 0, nb = 0;
+  if (!c->batch.empty()) {
+    for (auto& t : c->batch) {
+      nev += t.ev.n_events;
+      nb += bins_for(c, t.ev.t_end_ps).n_bins;
+    }
+  } else {
+    nev = c->ev.n_events;
+    nb = c->bins.n_bins;
+  }
+  std::ostringstream k;
+  k << dev << "/cu" << c->n_cu << "/g" << c->n_gates << "/c" << c->n_cells << "/e" << nev << "/b" << nb << "/d"
+    << c->bins.D << "/t" << c->batch.size();
+  return k.str();
+}
+
+bool tune_cache_lookup(const char* path, const std::string& key, gtp_tuning* t) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line;
+  const std::string pat = "\"key\": \"" + key + "\"";
+  while (std::getline(f, line)) {
+    if (line.find(pat) == std::string::npos) continue;
+    gtp_tuning r{0, 0, 0, 0, 0};
+    auto field = [&](const char* name, int32_t* v) {
+      const std::string n = std::string("\"") + name + "\": ";
+      const size_t p = line.find(n);
+      if (p == std::string::npos) return false;
+      *v = (int32_t)std::strtol(line.c_str() + p + n.size(), nullptr, 10);
+      return true;
+    };
+    if (field("algo", &r.algo) && field("bins_per_tile_log2", &r.bins_per_tile_log2) &&
+        field("tile_threads", &r.tile_threads) && field("unit_events", &r.unit_events) &&
+        field("gate_block_log2", &r.gate_block_log2)) {
+      *t = r;
+      return true;
+    }
+  }
+  return false;
+}
+
+void tune_cache_append(const char* path, const std::string& key, const gtp_tuning& t, double ms) {
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << "{\"key\": \"" << key << "\", \"algo\": " << t.algo << ", \"bins_per_tile_log2\": " << t.bins_per_tile_log2
+    << ", \"tile_threads\": " << t.tile_threads << ", \"unit_events\": " << t.unit_events
+    << ", \"gate_block_log2\": " << t.gate_block_log2 << ", \"ms\": " << ms << "}\n";
+}
+}  // namespace
+
+extern "C" {
+
+gtp_status gtp_autotune(gtp_ctx c, const char* cache_json_path) {
+  TRY(need(c, true, true, false, true));
+  const bool batched = !c->batch.empty();
+  if (!batched && !c->ev_ok) return fail(c, GTP_ERR_NOT_LOADED, "no events or batch loaded");
+  HIPCHK(c, hipSetDevice(c->dev));
+  const std::string key = tune_key(c);
+  gtp_tuning cached;
+  if (tune_cache_lookup(cache_json_path, key, &cached)) return gtp_set_tuning(c, &cached);
+  // inputs: unit loads, unit scales; output sized for the workload
+  int64_t nb = c->bins.n_bins;
+  if (batched) TRY(gtp_batch_bins(c, &nb, nullptr));
+  TRY(ensure(c, c->tun_in, (size_t)(c->n_nets + 2) * 4));
+  TRY(fill_u64(c, c->tun_in.p, (c->n_nets + 2) / 2, 0x3f8000003f800000ull));
+  TRY(ensure(c, c->tun_out, (size_t)std::max<int64_t>(nb, 1) * 4));
+  const float* load = ptr<float>(c->tun_in);
+  float* out = ptr<float>(c->tun_out);
+  auto run = [&]() -> gtp_status {
+    if (batched) return gtp_forward_batched(c, load, nullptr, out, 0);
+    return gtp_forward(c, load, nullptr, out);
+  };
+  const bool prof = c->prof_on;
+  c->prof_on = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  gtp_tuning best{0, 0, 0, 0, 0};
+  double best_ms = 1e30;
+  const int tiles[] = {11, 12, 13};
+  const int threads[] = {512, 1024};
+  const int units[] = {8, 16};
+  const int gblocks[] = {12, 14};
+  for (int tl : tiles)
+    for (int un : units)
+      for (int gbl : gblocks)
+        for (int th : threads) {
+          gtp_tuning t{0, tl, th, un, gbl};
+          if (gtp_set_tuning(c, &t) != GTP_OK) continue;
+          if (run() != GTP_OK || hipStreamSynchronize(c->stream) != hipSuccess) {  // builds the layout
+            (void)hipGetLastError();
+            continue;
+          }
+          const int reps = 3;
+          (void)hipEventRecord(e0, c->stream);
+          gtp_status st = GTP_OK;
+          for (int r = 0; r < reps && st == GTP_OK; ++r) st = run();
+          (void)hipEventRecord(e1, c->stream);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (st == GTP_OK && ms / reps < best_ms) {
+            best_ms = ms / reps;
+            best = t;
+          }
+        }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->prof_on = prof;
+  if (best_ms >= 1e30) return fail(c, GTP_ERR_UNSUPPORTED, "no candidate tuning ran");
+  TRY(gtp_set_tuning(c, &best));
+  tune_cache_append(cache_json_path, key, best, best_ms);
+  return GTP_OK;
 }
 
 gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_scale, const float* grad_power,

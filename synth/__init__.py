@@ -214,6 +214,32 @@ def make_problem(name: str = "C1", scale: float = 1.0, p_tie: float = 0.0, **ove
     return Problem(lib, net, ev, vdd=0.8, bin_ps=cfg["bin_ps"], sw_mode=0, name=name)
 
 
+def make_batch(n_traces: int = 64, cycles=(10_000, 1_000_000), events_per_cycle: int = 500, n_gates: int = 200_000,
+               n_cells: int = 32, i_max: int = 4, t_clk: int = 1000, bin_ps: int = 50, seed: int = 4,
+               p_tie: float = 0.0):
+    """Batched workload: one netlist and n_traces stimulus traces of uneven
+    length. Trace i runs N_cyc,i cycles, N_cyc,i drawn uniformly from `cycles`
+    (counter stream 4, index i), with events_per_cycle * N_cyc,i events whose
+    per-gate counts follow lognormal(0, 2) weights redrawn per trace; no clock
+    gates. Returns (library, netlist, [Events], bin_ps)."""
+    L = _load()
+    lib = make_library(seed, n_cells, i_max, load_range=(0.5, 50.0))
+    net = make_netlist(seed, lib, n_gates, load_range=(0.5, 50.0))
+    draws = np.zeros(n_traces, np.uint64)
+    _check(L.synth_draws(ctypes.c_uint64(seed), ctypes.c_uint64(4), ctypes.c_uint64(0), ctypes.c_int64(n_traces),
+                         _p(draws)), "draws")
+    lo, hi = int(cycles[0]), int(cycles[1])
+    traces = []
+    for i in range(n_traces):
+        n_cyc = lo + int(draws[i] % np.uint64(hi - lo + 1))
+        t_end = n_cyc * t_clk
+        total = events_per_cycle * n_cyc
+        tseed = seed * 1_000_003 + i + 1
+        counts, is_clock = make_counts(tseed, n_gates, 0, 0, "lognormal", 0.0, 2.0, total, t_end)
+        traces.append(make_events(tseed, lib, net, counts, is_clock, t_end, t_clk, p_tie=p_tie))
+    return lib, net, traces, bin_ps
+
+
 def make_random_small(seed: int, n_gates: int = 20, n_cells: int = 4, i_max: int = 3, n_events: int = 400,
                       t_end: int = 5000, bin_ps: int = 100, p_tie: float = 0.2, n_clock: int = 0,
                       dist: str = "lognormal", n_slew: int = 7, n_load: int = 7, vdd: float = 0.8,
