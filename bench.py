@@ -78,6 +78,66 @@ def cpu_brand() -> str:
     return platform.processor()
 
 
+def bench_batched(args, gtp, torch, dev):
+    """Many stimulus traces of uneven length over one netlist: the batched
+    forward (one persistent launch, replayed from a HIP graph) against one
+    forward per trace, same traces, same GPU."""
+    import synth
+    t0 = time.time()
+    lib, net, traces, bin_ps = synth.make_batch(n_traces=args.batch_traces, cycles=tuple(args.batch_cycles))
+    gen_s = time.time() - t0
+    n_ev = sum(ev.n_events for ev in traces)
+    ctx = gtp.Context(0)
+    ctx.load_library(lib)
+    ctx.load_netlist(torch.from_numpy(net.gate_cell).to(dev), torch.from_numpy(net.gate_out_net).to(dev),
+                     torch.from_numpy(net.gate_init.view(np.int32)).to(dev), net.n_nets)
+    ctx.set_params(vdd=0.8, bin_ps=bin_ps)
+    tr = [tuple(torch.from_numpy(a).to(dev) for a in (ev.gate_off, ev.t, ev.pin_bit, ev.slew)) + (ev.t_end,)
+          for ev in traces]
+    ctx.load_traces(tr)
+    load = torch.from_numpy(net.net_load).to(dev)
+    lam = torch.from_numpy(net.leak_scale).to(dev)
+    tot, offs = ctx.batch_bins()
+    P = torch.empty(tot, dtype=torch.float32, device=dev)
+    tp = time.time()
+    ctx.forward_batched(load, lam, out=P, use_graph=True)  # packs every trace, records the graph
+    torch.cuda.synchronize()
+    plan_s = time.time() - tp
+    outs = [P[int(offs[i]):int(offs[i + 1])] for i in range(len(traces))]
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, steps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    def per_trace():
+        for i in range(len(traces)):
+            ctx.forward_trace(i, load, lam, out=outs[i])
+
+    steps = max(2, min(args.steps, 10))
+    ms_graph = timed(lambda: ctx.forward_batched(load, lam, out=P, use_graph=True), steps)
+    ms_eager = timed(lambda: ctx.forward_batched(load, lam, out=P, use_graph=False), steps)
+    ms_seq = timed(per_trace, steps)
+    ctx.close()
+    lens = [ev.t_end // 1000 for ev in traces]
+    return {"workload": f"{len(traces)} traces over one {net.n_gates}-gate, {lib.n_cells}-cell netlist, "
+                        f"{args.batch_cycles[0]}-{args.batch_cycles[1]} cycles of 1 ns each (drawn), "
+                        f"500 events per cycle, lognormal(0,2) per-gate counts, {bin_ps} ps bins",
+            "n_events": n_ev, "n_bins": int(tot), "cycles_min": int(min(lens)), "cycles_max": int(max(lens)),
+            "value": n_ev / (ms_graph * 1e-3), "unit": "events/s", "ms_per_step": ms_graph,
+            "eager_ms_per_step": ms_eager,
+            "per_trace": {"value": n_ev / (ms_seq * 1e-3), "ms_per_step": ms_seq, "launches_per_step": 4 * len(traces)},
+            "speedup_vs_per_trace": ms_seq / ms_graph, "plan_s": plan_s, "gen_s": gen_s}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +150,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work for the oracle sample")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-trace comparison")
+    ap.add_argument("--batch-traces", type=int, default=64)
+    ap.add_argument("--batch-cycles", type=int, nargs=2, default=[1000, 20000],
+                    help="range of cycles per trace of the batched comparison")
+    ap.add_argument("--autotune", default=None, help="autotune cache file (JSON lines); tune before timing")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only run device copies of this many MiB (to scale HBM byte counters), then exit")
     args = ap.parse_args()
@@ -132,6 +197,8 @@ def main():
     load = torch.from_numpy(net.net_load).to(dev)
     lam = torch.from_numpy(net.leak_scale).to(dev)
     P = torch.empty(ctx.n_bins, dtype=torch.float32, device=dev)
+    if args.autotune:
+        ctx.autotune(args.autotune)
     ctx.forward(load, lam, out=P)  # builds the packed layout
     torch.cuda.synchronize()
     plan_s = time.time() - tp
@@ -224,6 +291,10 @@ def main():
         torch.cuda.synchronize()
         ms_fa = e0.elapsed_time(e1) / args.steps
         out["fwd_adjoint"] = {"value": N / (ms_fa * 1e-3), "unit": "events/s", "ms_per_step": ms_fa}
+
+    # ---- batched traces: one persistent graph launch vs per-trace launches --
+    if not args.no_batched:
+        out["batched"] = bench_batched(args, gtp, torch, dev)
 
     # ---- CPU oracle on a bounded sample ------------------------------------
     if not args.no_cpu:
