@@ -237,9 +237,10 @@ def main():
     if dom in ("k_fwd_packed", "k_gate_serial"):
         extra["strict_frac"] = EVENT_BYTES_STRICT * N / (dom_ms * 1e-3) / HBM_PEAK
     if plan is not None and dom == "k_fwd_packed":
-        # bytes the packed layout actually holds per event: event word + slew,
+        # bytes the packed layout actually holds per event: event word, table row
+        # and slew weight,
         # unit descriptors, group offsets
-        pb = 8 * plan["n_events_packed"] + 8 * 64 * plan["n_groups"] + 8 * plan["n_groups"]
+        pb = 12 * plan["n_events_packed"] + 8 * 64 * plan["n_groups"] + 8 * plan["n_groups"]
         extra["packed_bytes_per_event"] = pb / max(N, 1)
         extra["packed_frac"] = pb / (dom_ms * 1e-3) / HBM_PEAK
 
@@ -282,6 +283,7 @@ def main():
             gP.copy_(torch.softmax(beta * P, dim=0))
             ctx.adjoint(load, lam, gP)
         torch.cuda.synchronize()
+        ctx.profile(True)
         e0.record(stream)
         for _ in range(args.steps):
             ctx.forward(load, lam, out=P)
@@ -289,8 +291,11 @@ def main():
             ctx.adjoint(load, lam, gP)
         e1.record(stream)
         torch.cuda.synchronize()
+        kern_fa = ctx.profile_read()
+        ctx.profile(False)
         ms_fa = e0.elapsed_time(e1) / args.steps
-        out["fwd_adjoint"] = {"value": N / (ms_fa * 1e-3), "unit": "events/s", "ms_per_step": ms_fa}
+        out["fwd_adjoint"] = {"value": N / (ms_fa * 1e-3), "unit": "events/s", "ms_per_step": ms_fa,
+                              "kernels": {k: dict(launches=n, avg_ms=ms / max(n, 1)) for k, (n, ms) in kern_fa.items()}}
 
     # ---- batched traces: one persistent graph launch vs per-trace launches --
     if not args.no_batched:

@@ -46,14 +46,23 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-// Packed event word: bits [0, 23) in-tile time (bin_in_tile << r_bits | r),
-// [23, 27) slew-axis segment of the event's slew on its cell's axis (the
-// knots at or below the slew, minus one, clamped to the axis), [27, 31) pin,
-// bit 31 the new value.
+// Packed event record (three 32-bit words, built once per event set, bin
+// width and library; everything in it is independent of the per-call loads
+// and leakage scales):
+//   word  bits [0, 23) in-tile time (bin_in_tile << r_bits | r), [23, 31)
+//         the gate's input state after the event (the leakage state held
+//         from the event on);
+//   row   bits [0, 30) the quad index of the event's table row at its slew
+//         segment, i.e. map(state before the timestamp group, new value) +
+//         segment * (n_load - 1), to which the gate's load segment is added;
+//         bit 30 set for an output event, bit 31 the new value;
+//   alpha the slew weight (slew - S[i]) / (S[i+1] - S[i]) in FP32, rounded
+//         as the gate-major kernels round it.
 constexpr int kTimeBits = 23;
 constexpr uint32_t kTimeMask = (1u << kTimeBits) - 1u;
-constexpr int kSegShift = 23;
-constexpr int kPinShift = 27;
+constexpr int kStateShift = 23;
+constexpr uint32_t kRowMask = (1u << 30) - 1u;
+constexpr int kOutBit = 30;
 constexpr int kMaxPin = 14;
 
 // Per-cell record staged in LDS.

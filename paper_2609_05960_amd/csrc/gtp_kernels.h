@@ -80,8 +80,9 @@ __device__ __forceinline__ EventOut event_energy(GateCtx& G, const LdsLib& L, co
 // end the tile's bins are stored (each bin belongs to exactly one tile, so
 // no global atomics and no zero fill are needed).
 struct PackedFwdArgs {
-  const uint32_t* w32;
-  const float* slw;
+  const uint32_t* w32;       // event words
+  const uint32_t* row;       // table rows
+  const float* alpha;        // slew weights
   const uint2* desc;
   const int64_t* grp_off;
   const int32_t* tile_grp;
@@ -92,30 +93,34 @@ struct PackedFwdArgs {
   int32_t sw_mode;
   int64_t* X;
   int64_t* S;
-  int32_t* dbg_state;        // optional per-event trace (gate-major index)
-  int64_t* dbg_bin;
-  const int64_t* dsrc;
 };
 
 __device__ __forceinline__ size_t packed_bins_word_offset(int32_t lib_words) { return (size_t)((lib_words + 1) & ~1); }
 
 // One wavefront group's data in registers: unit descriptor, gate
-// parameters and the lane's events (k-major positions resolved).
+// parameters and the lane's event records (k-major positions resolved).
+template <int kS>
 struct GroupRegs {
   uint2 d;
   GateParam gp;
   int len;
   int kmax;
-  uint32_t wv[kLaneEvents];
-  float sv[kLaneEvents];
+  uint32_t wv[kS];
+  uint32_t rv[kS];
+  float av[kS];
 };
 
-// Issue every load of group gi (descriptor and offset already loaded).
-__device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int64_t off, GroupRegs& G) {
+// Issue every load of one group (descriptor and offset already loaded).
+// With mine false the lane's length still counts for the positions of the
+// other lanes, but its own loads are skipped.
+// kS is the longest unit the layout holds (its unit_events), 8 or 16.
+template <int kS>
+__device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int64_t off, GroupRegs<kS>& G,
+                                            bool mine = true) {
   G.d = d;
   const bool valid = d.x != 0xffffffffu;
   G.len = valid ? (int)(d.x >> 28) + 1 : 0;
-  if (valid) {
+  if (valid && mine) {
     G.gp = a.gparam[d.x & 0x0fffffffu];
   } else {
     G.gp.beta = 0.f; G.gp.lam = 0.f; G.gp.esw_rise = 0.f; G.gp.cell_jq = 0u;
@@ -125,108 +130,80 @@ __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int
   const int64_t offu = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(off >> 32)) << 32) |
                                  (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)off));
   const uint32_t* __restrict__ wp = a.w32 + offu;
-  const float* __restrict__ sp = a.slw + offu;
+  const uint32_t* __restrict__ rp = a.row + offu;
+  const float* __restrict__ ap = a.alpha + offu;
   uint32_t o = 0;
   G.kmax = 0;
   // slot kk holds event kk of every lane longer than kk; slots past the
   // longest unit are skipped by a wave-uniform branch
 #pragma unroll
-  for (int kk = 0; kk < kLaneEvents; ++kk) {
+  for (int kk = 0; kk < kS; ++kk) {
     const bool on = G.len > kk;
     const uint64_t m = __ballot(on);
     if (m != 0) {
       G.kmax = kk + 1;
-      if (on) {
+      if (on && mine) {
         const uint32_t r =
             o + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         G.wv[kk] = wp[r];
-        G.sv[kk] = sp[r];
+        G.rv[kk] = rp[r];
+        G.av[kk] = ap[r];
       }
       o += (uint32_t)__popcll(m);
     }
   }
 }
 
-// Accumulates one group (already loaded into G) into the tile's LDS bins.
-// Per-event lookups are double-buffered by event parity: while event k is
-// accumulated from buffer k&1, the state, table quad, slew weight and the
-// leakage value after event k+1 load into the other buffer, so no register is
-// reloaded while its previous value is still live.
-template <bool kDebug>
-__device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsLib& L, const GroupRegs& G,
-                                              unsigned long long* xs, unsigned long long* ss, int64_t gi,
-                                              int32_t tile, int lane) {
+// The table quads of every event of a loaded group, gathered in one burst.
+// Vector-memory loads complete in issue order, so the burst is issued before
+// the next group's loads: the quads then arrive after an L2 latency instead
+// of waiting behind the next group's HBM loads.
+template <int kS>
+struct GroupQuads {
+  float4 q[kS];
+};
+
+template <int kS>
+__device__ __forceinline__ void group_quads(const PackedFwdArgs& a, const GroupRegs<kS>& G, GroupQuads<kS>& Q) {
+  const uint32_t jq = G.gp.cell_jq & 0xffu;
+#pragma unroll
+  for (int kk = 0; kk < kS; ++kk)
+    if (kk < G.kmax && G.len > kk) Q.q[kk] = a.lut.quads[(G.rv[kk] & kRowMask) + jq];
+}
+
+// Accumulates one group (loaded into G, its quads into Q) into the tile's
+// LDS bins.
+template <int kS>
+__device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsLib& L, const GroupRegs<kS>& G,
+                                              const GroupQuads<kS>& Q, unsigned long long* xs,
+                                              unsigned long long* ss) {
   const BinSpec& B = a.bins;
   const uint32_t rmask = (1u << B.r_bits) - 1u;
   const int32_t D32 = (int32_t)B.D;
-  const int32_t qstride = a.lut.n_load - 1;
-  const float4* __restrict__ quads = a.lut.quads;
   const int len = G.len;
   const GateParam gp = G.gp;
-  const int cell = (int)(gp.cell_jq >> 8);
-  const int jq = (int)(gp.cell_jq & 0xffu);
-  const CellMeta cm = L.meta[cell];
-  const uint32_t in_mask = (1u << cm.n_in) - 1u;
-  const uint32_t st = G.d.y & 0xffffu;
+  const CellMeta cm = L.meta[gp.cell_jq >> 8];
   const float esw_fall = a.sw_mode ? 0.0f : gp.esw_rise;
-  int32_t q_cur = qrate(gp.lam, L.leak[cm.leak_off + (int)(st & in_mask)], a.lut.rate_scale);
-  const float* sax = L.slew + cm.axis_off;
-  const float* sinv = L.slew_inv + cm.axis_off;
-  const int32_t* mq = L.map_q + cm.map_off;
   const float* lk = L.leak + cm.leak_off;
-  struct Pre {
-    uint32_t s;      // input state before the event's group
-    float alpha;     // slew weight
-    float4 q;        // table quad
-    float lk_after;  // leakage value of the input state after the event
-  };
-  auto prefetch = [&](int k, uint32_t pgs, uint32_t par_after_k, Pre& P) {
-    const uint32_t w = G.wv[k];
-    const float slew = G.sv[k];
-    P.s = (st ^ pgs) & in_mask;
-    const int v = (int)(w >> 31);
-    const int32_t qb = mq[2 * (int)P.s + v];
-    const int i = (int)((w >> kSegShift) & 15u);  // slew-axis segment (from the pack)
-    P.alpha = __fmul_rn(__fsub_rn(slew, sax[i]), sinv[i]);
-    P.lk_after = lk[(par_after_k ^ st) & in_mask];
-    P.q = quads[(uint32_t)(qb + i * qstride + jq)];
-  };
-  auto pin_bit = [&](int k) -> uint32_t { return 1u << ((G.wv[k] >> kPinShift) & 15u); };
-  uint32_t par = 0;
-  uint32_t par_gs = ((G.d.y >> 16) ^ st) & 0xffffu;
-  Pre pre[2];
-  if (len > 0) prefetch(0, par_gs, pin_bit(0), pre[0]);
+  int32_t q_cur = qrate(gp.lam, lk[G.d.y & ((1u << cm.n_in) - 1u)], a.lut.rate_scale);
 #pragma unroll
-  for (int kk = 0; kk < kLaneEvents; ++kk) {
+  for (int kk = 0; kk < kS; ++kk) {
     if (kk < G.kmax && len > kk) {
       const uint32_t w = G.wv[kk];
-      const uint32_t tl = w & kTimeMask;
-      const int pin = (int)((w >> kPinShift) & 15u);
-      const int v = (int)(w >> 31);
-      const uint32_t par_after = par ^ (1u << pin);
-      if (kk + 1 < kLaneEvents && len > kk + 1) {
-        if ((G.wv[kk + 1] & kTimeMask) != tl) par_gs = par_after;
-        prefetch(kk + 1, par_gs, par_after ^ pin_bit(kk + 1), pre[(kk + 1) & 1]);
-      }
-      const Pre& P = pre[kk & 1];
-      float e = bilerp_quad(P.q, P.alpha, gp.beta);
-      if (pin == cm.n_in) e = __fadd_rn(e, v ? gp.esw_rise : esw_fall);
+      const uint32_t rv = G.rv[kk];
+      float e = bilerp_quad(Q.q[kk], G.av[kk], gp.beta);
+      if (rv & (1u << kOutBit)) e = __fadd_rn(e, (rv >> 31) ? gp.esw_rise : esw_fall);
       int64_t x = energy_fixed(e, a.lut.two_sh);
+      const uint32_t tl = w & kTimeMask;
       const uint32_t bl = tl >> B.r_bits;
       // leakage step: an output event leaves the input state (and so the
       // rate) unchanged, so dq = 0 for it without a branch
-      const int32_t qn = qrate(gp.lam, P.lk_after, a.lut.rate_scale);
+      const int32_t qn = qrate(gp.lam, lk[w >> kStateShift], a.lut.rate_scale);
       const int32_t dq = qn - q_cur;
       q_cur = qn;
       x += (int64_t)dq * (int64_t)(D32 - (int32_t)(tl & rmask));
       if (dq != 0) atomicAdd(&ss[bl], (unsigned long long)(int64_t)dq);
       atomicAdd(&xs[bl], (unsigned long long)x);
-      par = par_after;
-      if (kDebug) {
-        const int64_t e_src = a.dsrc[gi * kGroupUnits + lane] + kk;
-        a.dbg_state[e_src] = (int32_t)P.s;
-        a.dbg_bin[e_src] = ((int64_t)tile << B.tile_log2) + bl;
-      }
     }
   }
 }
@@ -234,10 +211,11 @@ __device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsL
 // One time tile of one trace: the tile's bins are zeroed in LDS, every
 // wavefront takes whole groups of the tile, and the bins are stored at the
 // end (each bin belongs to exactly one tile). Memory-level parallelism: a
-// wavefront works on group i while the loads of group i+1 (gate parameters,
-// events) and the descriptors of group i+2 are in flight; the loop alternates
-// two register buffers, so nothing is copied between groups.
-template <int kThreads, bool kDebug>
+// wavefront issues the table gathers of group i, then the loads of group i+1
+// (gate parameters, events) and the descriptors of group i+2, then works on
+// group i; the loop alternates two register buffers, so nothing is copied
+// between groups.
+template <int kThreads, int kS>
 __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsLib& L, unsigned long long* xs,
                                               unsigned long long* ss, int32_t tile) {
   const BinSpec& B = a.bins;
@@ -247,11 +225,11 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
   const int lane = (int)(threadIdx.x & 63);
   constexpr int nwave = kThreads / 64;
   int64_t gi = a.tile_grp[tile] + (int64_t)(threadIdx.x >> 6);
-  GroupRegs ga, gb;
+  GroupRegs<kS> ga, gb;
   uint2 dn = make_uint2(0xffffffffu, 0u);
   int64_t offn = 0;
   // issue the loads of group g into R and prefetch the descriptor of g + nwave
-  auto issue = [&](int64_t g, GroupRegs& R) {
+  auto issue = [&](int64_t g, GroupRegs<kS>& R) {
     group_issue(a, dn, offn, R);
     if (g + nwave < g1) {
       dn = a.desc[(g + nwave) * kGroupUnits + lane];
@@ -264,13 +242,20 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
     issue(gi, ga);
   }
   __syncthreads();
+  GroupQuads<kS> Q;
   while (gi < g1) {
+    group_quads(a, ga, Q);
+    __builtin_amdgcn_sched_barrier(0);
     if (gi + nwave < g1) issue(gi + nwave, gb);
-    process_group<kDebug>(a, L, ga, xs, ss, gi, tile, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    process_group(a, L, ga, Q, xs, ss);
     gi += nwave;
     if (gi >= g1) break;
+    group_quads(a, gb, Q);
+    __builtin_amdgcn_sched_barrier(0);
     if (gi + nwave < g1) issue(gi + nwave, ga);
-    process_group<kDebug>(a, L, gb, xs, ss, gi, tile, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    process_group(a, L, gb, Q, xs, ss);
     gi += nwave;
   }
   __syncthreads();
@@ -284,13 +269,13 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
 }
 
 // One workgroup per time tile of a single trace.
-template <int kThreads, bool kDebug>
+template <int kThreads, int kS>
 __global__ void __launch_bounds__(kThreads) k_fwd_packed(PackedFwdArgs a) {
   extern __shared__ uint32_t lds[];
   const LdsLib L = stage_library(a.lib, lds);
   unsigned long long* xs = reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.lib.lds_words));
   unsigned long long* ss = xs + (1 << a.bins.tile_log2);
-  fwd_tile_body<kThreads, kDebug>(a, L, xs, ss, (int32_t)blockIdx.x);
+  fwd_tile_body<kThreads, kS>(a, L, xs, ss, (int32_t)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -298,7 +283,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd_packed(PackedFwdArgs a) {
 // ---------------------------------------------------------------------------
 struct TraceDev {
   const uint32_t* w32;
-  const float* slw;
+  const uint32_t* row;
+  const float* alpha;
   const uint2* desc;
   const int64_t* grp_off;
   const int32_t* tile_grp;
@@ -318,7 +304,7 @@ struct BatchFwdArgs {
 
 // Workgroups stay resident and take work items from the queue until it is
 // empty; every workgroup ends once it draws an index past the last item.
-template <int kThreads>
+template <int kThreads, int kS>
 __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ long long item_sh;
@@ -333,7 +319,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
     const TraceDev T = a.traces[w.x];
     PackedFwdArgs p = a.base;
     p.w32 = T.w32;
-    p.slw = T.slw;
+    p.row = T.row;
+    p.alpha = T.alpha;
     p.desc = T.desc;
     p.grp_off = T.grp_off;
     p.tile_grp = T.tile_grp;
@@ -343,7 +330,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
     unsigned long long* xs =
         reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.base.lib.lds_words));
     unsigned long long* ss = xs + (1 << T.bins.tile_log2);
-    fwd_tile_body<kThreads, false>(p, L, xs, ss, w.y);
+    fwd_tile_body<kThreads, kS>(p, L, xs, ss, w.y);
   }
 }
 
@@ -716,6 +703,212 @@ __global__ void __launch_bounds__(256) k_adj_out(AdjOutArgs a) {
     const double base = (double)a.leak[cm.leak_off + (int)s0] * *a.total;
     a.grad_scale[i] = (float)(1e-6 * (base + a.gL[i]));
   }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint, packed layout: one workgroup per (gate block, tile range) item
+// ---------------------------------------------------------------------------
+// The gates of one gate block accumulate their two gradients in LDS (FP32
+// per unit); at the end the item stores them, with plain coalesced stores, as
+// its own row of a partial table, and the output kernel sums a gate's rows
+// in FP64. An item is a run of entries, each one group of the packed layout
+// restricted to the lanes (units) of the item's gate block: a group on the
+// boundary of two gate blocks appears in both blocks' entries with
+// complementary lane ranges. Each event reads its bin's (w_b, G_b) from the
+// bin table; one tile's window of it stays in cache while the item walks the
+// tile.
+struct AdjItem {
+  int32_t gb;       // gate block
+  int32_t e0, e1;   // entries [e0, e1)
+  int32_t pad;
+  int64_t row;      // first element of the item's row in the partial table
+};
+
+struct AdjPackedArgs {
+  PackedFwdArgs f;            // events, descriptors, gate parameters, library
+  const int4* entries;        // (group, tile, first lane, end lane)
+  const AdjItem* items;
+  const int32_t* gb_start;    // [n_gb + 1] first sorted gate of each gate block
+  float2* part;               // partial table: per item and gate (load, leakage)
+  const float* load_inv;      // [n_cells * n_load]
+  int32_t n_load;
+  int32_t last_w;             // width of the last bin (ps)
+  const float2* wg;           // [n_bins] (w_b, G_b)
+  float dsw_rise, dsw_fall;
+};
+
+// One entry's group (loaded into G): per event, the load gradient gains
+// w_b * dE/dC and, for an input event, the leakage gradient gains the step of
+// the cell leakage times the integral of w from the event to the window end.
+// Lookups are double-buffered by event parity as in the forward.
+template <int kS>
+__device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const LdsLib& L, const GroupRegs<kS>& G,
+                                                  bool mine, int32_t tile, int32_t gs0, float* acc_c,
+                                                  float* acc_l) {
+  const BinSpec& B = a.f.bins;
+  const uint32_t rmask = (1u << B.r_bits) - 1u;
+  const int32_t D32 = (int32_t)B.D;
+  const float4* __restrict__ quads = a.f.lut.quads;
+  const int len = mine ? G.len : 0;
+  const GateParam gp = G.gp;
+  const int cell = (int)(gp.cell_jq >> 8);
+  const int jq = (int)(gp.cell_jq & 0xffu);
+  const CellMeta cm = L.meta[cell];
+  const float dbdc = len > 0 ? a.load_inv[cell * a.n_load + jq] : 0.f;
+  const float* lk = L.leak + cm.leak_off;
+  const int64_t tile_b0 = (int64_t)tile << B.tile_log2;
+  float lk_cur = lk[G.d.y & ((1u << cm.n_in) - 1u)];
+  struct Pre {
+    float4 q;        // table quad
+    float lk_after;  // leakage value of the input state after the event
+    float2 wg;       // the bin's (w_b, G_b)
+  };
+  auto prefetch = [&](int k, Pre& P) {
+    const uint32_t w = G.wv[k];
+    P.q = quads[(G.rv[k] & kRowMask) + (uint32_t)jq];
+    P.lk_after = lk[w >> kStateShift];
+    P.wg = a.wg[tile_b0 + (int64_t)((w & kTimeMask) >> B.r_bits)];
+  };
+  float ac = 0.f, al = 0.f;
+  Pre pre[2];
+  if (len > 0) prefetch(0, pre[0]);
+#pragma unroll
+  for (int kk = 0; kk < kS; ++kk) {
+    if (kk < G.kmax && len > kk) {
+      const uint32_t w = G.wv[kk];
+      const uint32_t rv = G.rv[kk];
+      if (kk + 1 < kS && len > kk + 1) prefetch(kk + 1, pre[(kk + 1) & 1]);
+      const Pre& P = pre[kk & 1];
+      float dedc = __fmul_rn(bilerp_dbeta(P.q, G.av[kk]), dbdc);
+      if (rv & (1u << kOutBit)) dedc = __fadd_rn(dedc, (rv >> 31) ? a.dsw_rise : a.dsw_fall);
+      ac = __fmaf_rn(P.wg.x, dedc, ac);
+      // an output event leaves the input state unchanged: step 0, no branch
+      const uint32_t tl = w & kTimeMask;
+      const int64_t b = tile_b0 + (int64_t)(tl >> B.r_bits);
+      const int32_t width = (b == B.n_bins - 1) ? a.last_w : D32;
+      const float tail = (float)(width - (int32_t)(tl & rmask));
+      al = __fmaf_rn(__fsub_rn(P.lk_after, lk_cur), __fmaf_rn(P.wg.x, tail, P.wg.y), al);
+      lk_cur = P.lk_after;
+    }
+  }
+  if (len > 0) {
+    const int32_t li = (int32_t)(G.d.x & 0x0fffffffu) - gs0;
+    if (ac != 0.f) atomicAdd(&acc_c[li], ac);
+    if (al != 0.f) atomicAdd(&acc_l[li], al);
+  }
+}
+
+template <int kThreads, int kS>
+__global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
+  extern __shared__ uint32_t lds[];
+  const LdsLib L = stage_library(a.f.lib, lds);
+  const AdjItem it = a.items[blockIdx.x];
+  const int32_t gs0 = a.gb_start[it.gb];
+  const int32_t ng = a.gb_start[it.gb + 1] - gs0;
+  float* acc_c = reinterpret_cast<float*>(lds + a.f.lib.lds_words);
+  float* acc_l = acc_c + ng;
+  for (int i = threadIdx.x; i < 2 * ng; i += kThreads) acc_c[i] = 0.f;
+  const int lane = (int)(threadIdx.x & 63);
+  constexpr int nwave = kThreads / 64;
+  const int64_t e1 = it.e1;
+  // wave-uniform entry index: the entry loads go through the scalar unit
+  int64_t e = it.e0 + (int64_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  GroupRegs<kS> ga, gb;
+  bool ma = false, mb = false;
+  int32_t ta = 0, tb = 0;
+  // loads run ahead of the wavefront's work: the entry two groups ahead, its
+  // descriptor and offset one group ahead, the events of the next group
+  int4 en2 = make_int4(0, 0, 0, 0);    // entry of group e + 2 nwave
+  int4 en1 = make_int4(0, 0, 0, 0);    // entry of group e + nwave
+  uint2 dn = make_uint2(0xffffffffu, 0u);
+  int64_t offn = 0;
+  auto issue = [&](int64_t en, GroupRegs<kS>& R, bool& m, int32_t& t) {
+    m = lane >= (en1.z & 0xff) && lane < (en1.z >> 8);
+    t = en1.y;
+    group_issue(a.f, dn, offn, R, m);
+    en1 = en2;
+    if (en + nwave < e1) {
+      dn = a.f.desc[(int64_t)en1.x * kGroupUnits + lane];
+      offn = a.f.grp_off[en1.x];
+    }
+    if (en + 2 * nwave < e1) en2 = a.entries[en + 2 * nwave];
+  };
+  if (e < e1) {
+    en1 = a.entries[e];
+    dn = a.f.desc[(int64_t)en1.x * kGroupUnits + lane];
+    offn = a.f.grp_off[en1.x];
+    if (e + nwave < e1) en2 = a.entries[e + nwave];
+    issue(e, ga, ma, ta);
+  }
+  __syncthreads();
+  while (e < e1) {
+    if (e + nwave < e1) issue(e + nwave, gb, mb, tb);
+    adj_process_group(a, L, ga, ma, ta, gs0, acc_c, acc_l);
+    e += nwave;
+    if (e >= e1) break;
+    if (e + nwave < e1) issue(e + nwave, ga, ma, ta);
+    adj_process_group(a, L, gb, mb, tb, gs0, acc_c, acc_l);
+    e += nwave;
+  }
+  __syncthreads();
+  float2* prow = a.part + it.row;
+  for (int i = threadIdx.x; i < ng; i += kThreads) prow[i] = make_float2(acc_c[i], acc_l[i]);
+}
+
+// (w_b, G_b) in FP32 for the packed adjoint.
+__global__ void __launch_bounds__(256) k_adj_suffix_f(const double* w, const double* c, const double* exc, float2* wg,
+                                                      double* total, int64_t n_bins) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_bins) return;
+  const double tot = exc[n_bins - 1] + c[n_bins - 1];
+  wg[b] = make_float2((float)w[b], (float)(tot - (exc[b] + c[b])));
+  if (b == 0) *total = tot;
+}
+
+// Gradient outputs from the partial table: a sorted gate sums its block's
+// rows (one per item of the block) in FP64, adds its load gradient to its
+// output net (grad_load zeroed first) and writes its leakage-scale gradient
+// (plus the initial-state leakage times the integral of the bin weights over
+// the window).
+struct AdjOutSortedArgs {
+  const float2* part;
+  const int64_t* gb_row;      // [n_gb] first element of the block's rows
+  const int32_t* gb_rows;     // [n_gb] rows (items) of the block
+  const int32_t* gb_start;    // [n_gb + 1]
+  int32_t n_gb;
+  const double* total;
+  const int32_t* gperm;
+  const int32_t* gcell;
+  const int32_t* gate_out;
+  const uint32_t* gate_init;
+  const CellMeta* meta;
+  const float* leak;
+  float* grad_load;
+  float* grad_scale;
+  int64_t n_gates;
+};
+
+__global__ void __launch_bounds__(256) k_adj_out_sorted(AdjOutSortedArgs a) {
+  const int64_t gs = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gs >= a.n_gates) return;
+  int32_t lo = 0, hi = a.n_gb;  // gate block holding gs: gb_start[lo] <= gs < gb_start[hi]
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (a.gb_start[mid] <= gs) lo = mid; else hi = mid;
+  }
+  const int64_t ng = a.gb_start[lo + 1] - a.gb_start[lo];
+  const float2* p = a.part + a.gb_row[lo] + (gs - a.gb_start[lo]);
+  double gc = 0.0, gl = 0.0;
+  for (int32_t j = 0; j < a.gb_rows[lo]; ++j) {
+    const float2 v = p[j * ng];
+    gc += (double)v.x;
+    gl += (double)v.y;
+  }
+  const int32_t g = a.gperm[gs];
+  const CellMeta cm = a.meta[a.gcell[gs]];
+  const uint32_t s0 = a.gate_init[g] & ((1u << cm.n_in) - 1u);
+  a.grad_scale[g] = (float)(1e-6 * ((double)a.leak[cm.leak_off + (int)s0] * *a.total + gl));
+  if (gc != 0.0) atomicAdd(&a.grad_load[a.gate_out[g]], (float)gc);
 }
 
 // ---------------------------------------------------------------------------

@@ -24,9 +24,10 @@
 //          loads of a wavefront are adjacent words.
 //
 // Arrays (device, owned by the ctx):
-//   w32[n]    packed event word (see gtp_device.h): in-tile time, slew-axis
-//             segment, pin, value
-//   slw[n]    slew (FP32)
+//   w32[n]    event word (see gtp_device.h): in-tile time, input state
+//             after the event
+//   row[n]    table row of the event at its slew segment, output flag, value
+//   alpha[n]  slew weight (FP32)
 //   desc[64 * n_groups]   unit descriptor: x = cell-sorted gate index
 //             (bits 0..27) | (length-1) << 28, y = pin values before the
 //             unit's first event (bits 0..15) | before its timestamp group
@@ -55,17 +56,19 @@ struct PackIn {
   const uint32_t* gate_init;  // [G] (device)
   std::vector<int32_t> h_gate_cell;  // [G] host copy
   std::vector<int32_t> n_in;         // [n_cells] inputs per cell
-  const float* slew_axis;     // [n_cells * n_slew] (device)
-  int32_t n_slew;
+  LibView lib;                // library image (device pointers)
   int32_t unit_events = kLaneEvents;          // longest unit, 1..16
   int32_t gate_block_log2 = kGateBlockLog2;   // gates per gate block (log2)
   BinSpec bins;               // tile_log2 and n_tiles set
   hipStream_t stream;
+  int32_t* dbg_state = nullptr;   // optional [n_events] gate-major: state before the event's group
+  int64_t* dbg_bin = nullptr;     // optional [n_events] gate-major: bin of the event
 };
 
 struct PackOut {
   uint32_t* w32 = nullptr;
-  float* slw = nullptr;
+  uint32_t* row = nullptr;
+  float* alpha = nullptr;
   uint2* desc = nullptr;
   int64_t* dsrc = nullptr;
   int64_t* grp_off = nullptr;
@@ -78,6 +81,16 @@ struct PackOut {
   int64_t bytes = 0;          // device bytes held by the arrays above
   int32_t max_tile_groups = 0;
   int64_t lane_steps = 0;     // sum over groups of the longest unit
+  // gate-block view (the adjoint's work decomposition): sorted units of
+  // region r = tile * n_gb + gate block are [reg_first[r], reg_first[r+1])
+  // (indices over all sorted units; tile k's units start at tfirst[k], its
+  // j-th unit is lane j % 64 of group tile_grp[k] + j / 64)
+  uint32_t* reg_first = nullptr;   // [n_tiles * n_gb + 1] (device)
+  uint32_t* tfirst = nullptr;      // [n_tiles + 1] (device)
+  int32_t n_gb = 0;
+  int32_t gb_log2 = 0;
+  std::vector<int32_t> h_gb_start;     // [n_gb + 1] first sorted gate of each gate block
+  std::vector<int64_t> h_reg_events;   // [n_tiles * n_gb] events per region
 };
 
 // Builds the packed layout on in.stream (synchronises it). Returns

@@ -141,6 +141,33 @@ __global__ void __launch_bounds__(256) k_pk_tile_first(const uint64_t* skey, int
   if (j == 0 || (skey[j - 1] >> shift) != t) tfirst[t] = (uint32_t)j;
 }
 
+// First sorted unit of every non-empty (tile, gate block) region.
+__global__ void __launch_bounds__(256) k_pk_region_first(const uint64_t* skey, int64_t nu, int32_t gb_bits, int32_t n_gb,
+                                                         uint32_t* rfirst) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nu) return;
+  auto region = [&](uint64_t k) -> int64_t {
+    return (int64_t)(k >> (gb_bits + 5)) * n_gb + (int64_t)((k >> 5) & ((1ull << gb_bits) - 1ull));
+  };
+  const int64_t r = region(skey[j]);
+  if (j == 0 || region(skey[j - 1]) != r) rfirst[r] = (uint32_t)j;
+}
+
+// Event count of every sorted unit (for the per-region event counts).
+__global__ void __launch_bounds__(256) k_pk_sorted_len(const uint32_t* sidx, const UnitRec* recs, int64_t nu,
+                                                       uint32_t* slen) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > nu) return;
+  slen[j] = (j < nu) ? (recs[sidx[j]].x >> 28) + 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_pk_region_events(const uint64_t* uoff, const uint32_t* rfirst, int64_t n_reg,
+                                                          int64_t* rev) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_reg) return;
+  rev[r] = (int64_t)(uoff[rfirst[r + 1]] - uoff[rfirst[r]]);
+}
+
 __device__ __forceinline__ int32_t tile_of_group(const int32_t* tile_grp, int32_t n_tiles, int64_t gi) {
   int32_t lo = 0, hi = n_tiles;  // invariant: tile_grp[lo] <= gi < tile_grp[hi]
   while (hi - lo > 1) {
@@ -178,9 +205,8 @@ __global__ void __launch_bounds__(256) k_pk_group_len(const int32_t* tile_grp, c
 struct FillArgs {
   EvView ev;
   BinSpec bins;
-  const float* slew_axis;
+  LibView lib;                // device pointers of the library image
   const int32_t* gcell;
-  int32_t n_slew;
   const int32_t* tile_grp;
   const uint32_t* tfirst;
   const uint32_t* sidx;
@@ -188,11 +214,20 @@ struct FillArgs {
   const int64_t* grp_off;
   int64_t n_groups;
   uint32_t* w32;
-  float* slw;
+  uint32_t* row;
+  float* alpha;
   uint2* desc;
   int64_t* dsrc;
+  int32_t* dbg_state;         // optional, gate-major: state before the event's group
+  int64_t* dbg_bin;           // optional, gate-major: bin of the event
 };
 
+// One wavefront per group: the unit descriptors, and every event's record in
+// the unit-interleaved order. The lane of a unit tracks its gate's pin values
+// from the carried-in values, as the gate-major walk does: the table is
+// selected by the input state before the event's timestamp group, the
+// leakage state after the event is the input state once the event's pin has
+// toggled.
 __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
   const int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroupUnits;
   const int lane = (int)(threadIdx.x & (kGroupUnits - 1));
@@ -206,7 +241,14 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
   a.desc[gi * kGroupUnits + lane] = make_uint2(r.x, r.y);
   a.dsrc[gi * kGroupUnits + lane] = r.src;
   const int len = act ? (int)(r.x >> 28) + 1 : 0;
-  const float* axis = a.slew_axis + (int64_t)(act ? a.gcell[r.x & 0x0fffffffu] : 0) * a.n_slew;
+  const CellMeta cm = a.lib.meta[act ? a.gcell[r.x & 0x0fffffffu] : 0];
+  const uint32_t in_mask = (1u << cm.n_in) - 1u;
+  const float* axis = a.lib.slew + cm.axis_off;
+  const float* inv = a.lib.slew_inv + cm.axis_off;
+  const int32_t qstride = a.lib.n_load - 1;
+  uint32_t cur = r.y & 0xffffu;   // pin values before the unit's first event
+  uint32_t gsv = r.y >> 16;       // pin values before that event's timestamp group
+  int64_t tprev = 0;
   int64_t off = a.grp_off[gi];
   for (int kk = 0; kk < kLaneEvents; ++kk) {
     const bool on = len > kk;
@@ -218,14 +260,26 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
       const int64_t e = r.src + kk;
       const int64_t t = a.ev.t[e];
       const uint32_t pb = a.ev.pb[e];
+      if (kk > 0 && t != tprev) gsv = cur;
+      tprev = t;
+      const uint32_t pin = min(pb >> 1, (uint32_t)kMaxPin);
+      const uint32_t v = pb & 1u;
+      const uint32_t st = gsv & in_mask;
+      cur ^= 1u << pin;
       const int64_t bin = bin_of(t, B);
       const uint32_t bl = (uint32_t)(bin - ((int64_t)k << B.tile_log2));
       const uint32_t rr = (uint32_t)(t - bin * B.D);
-      const uint32_t pin = min(pb >> 1, (uint32_t)kMaxPin);
-      const float slew = a.ev.slew[e];
-      const uint32_t seg = (uint32_t)slew_seg_index(axis, a.n_slew, slew);
-      a.w32[pos] = (bl << B.r_bits) | rr | (seg << kSegShift) | (pin << kPinShift) | ((pb & 1u) << 31);
-      a.slw[pos] = slew;
+      int i;
+      float al;
+      slew_segment(axis, inv, a.lib.n_slew, a.ev.slew[e], i, al);
+      const uint32_t q = (uint32_t)(a.lib.map_q[cm.map_off + 2 * (int)st + (int)v] + i * qstride);
+      a.w32[pos] = (bl << B.r_bits) | rr | ((cur & in_mask) << kStateShift);
+      a.row[pos] = q | ((pin == (uint32_t)cm.n_in ? 1u : 0u) << kOutBit) | (v << 31);
+      a.alpha[pos] = al;
+      if (a.dbg_state) {
+        a.dbg_state[e] = (int32_t)st;
+        a.dbg_bin[e] = bin;
+      }
     }
     off += __popcll(m);
   }
@@ -240,7 +294,7 @@ int ceil_log2_u64(uint64_t x) {
 }  // namespace
 
 void pack_free(PackOut* o) {
-  void* ps[] = {o->w32, o->slw, o->desc, o->dsrc, o->grp_off, o->tile_grp, o->gperm, o->gcell};
+  void* ps[] = {o->w32, o->row, o->alpha, o->desc, o->dsrc, o->grp_off, o->tile_grp, o->gperm, o->gcell, o->reg_first, o->tfirst};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   *o = PackOut();
@@ -300,6 +354,12 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       gbacc += (cnt[c] + (1 << in.gate_block_log2) - 1) >> in.gate_block_log2;
     }
     const int32_t n_gb = std::max(gbacc, 1);
+    o.n_gb = n_gb;
+    o.gb_log2 = in.gate_block_log2;
+    o.h_gb_start.assign((size_t)n_gb + 1, (int32_t)G);
+    for (int32_t c = 0; c < n_cells; ++c)
+      for (int32_t b = 0; gb_base[c] + b < (c + 1 < n_cells ? gb_base[c + 1] : gbacc); ++b)
+        o.h_gb_start[gb_base[c] + b] = cell_start[c] + (b << in.gate_block_log2);
     std::vector<int32_t> rank((size_t)G), perm((size_t)G), pcell((size_t)G);
     {
       std::vector<int32_t> cur(cell_start);
@@ -403,8 +463,9 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       PK(hipcub::DeviceRadixSort::SortPairs(tsort, tb, keys, skeys, vals, sidx, (int)NU, 0, key_bits, s));
     }
     // ---- 5. tiles and groups -------------------------------------------
-    uint32_t* tfirst = (uint32_t*)tmp((size_t)(n_tiles + 1) * 4, e2);
+    uint32_t* tfirst = (uint32_t*)own((size_t)(n_tiles + 1) * 4, e2);
     PK(e2);
+    o.tfirst = tfirst;
     hipLaunchKernelGGL(k_pk_fill_u32, dim3((unsigned)((n_tiles + 1 + 255) / 256)), dim3(256), 0, s, tfirst,
                        (int64_t)(n_tiles + 1), (uint32_t)NU);
     PKLAUNCH("k_pk_fill_u32");
@@ -466,10 +527,53 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     PK(hipMemcpyAsync(&nev, o.grp_off + ng, 8, hipMemcpyDeviceToHost, s));
     PK(hipStreamSynchronize(s));
     o.n_events = nev;
+    // ---- 5b. gate-block regions -------------------------------------------
+    {
+      const int64_t n_reg = (int64_t)n_tiles * n_gb;
+      o.reg_first = (uint32_t*)own((size_t)(n_reg + 1) * 4, e2);
+      PK(e2);
+      hipLaunchKernelGGL(k_pk_fill_u32, dim3((unsigned)((n_reg + 1 + 255) / 256)), dim3(256), 0, s, o.reg_first,
+                         n_reg + 1, (uint32_t)NU);
+      PKLAUNCH("k_pk_fill_u32");
+      if (NU > 0) {
+        hipLaunchKernelGGL(k_pk_region_first, dim3((unsigned)((NU + 255) / 256)), dim3(256), 0, s, skeys, NU, gb_bits,
+                           n_gb, o.reg_first);
+        PKLAUNCH("k_pk_region_first");
+      }
+      std::vector<uint32_t> hrf((size_t)n_reg + 1);
+      PK(hipMemcpyAsync(hrf.data(), o.reg_first, (size_t)(n_reg + 1) * 4, hipMemcpyDeviceToHost, s));
+      PK(hipStreamSynchronize(s));
+      for (int64_t r = n_reg - 1; r >= 0; --r) hrf[r] = std::min(hrf[r], hrf[r + 1]);
+      PK(hipMemcpyAsync(o.reg_first, hrf.data(), (size_t)(n_reg + 1) * 4, hipMemcpyHostToDevice, s));
+      uint32_t* slen = (uint32_t*)tmp((size_t)(NU + 1) * 4, e2);
+      PK(e2);
+      uint64_t* uoff = (uint64_t*)tmp((size_t)(NU + 1) * 8, e2);
+      PK(e2);
+      int64_t* rev = (int64_t*)tmp((size_t)std::max<int64_t>(n_reg, 1) * 8, e2);
+      PK(e2);
+      hipLaunchKernelGGL(k_pk_sorted_len, dim3((unsigned)((NU + 1 + 255) / 256)), dim3(256), 0, s, sidx, recs, NU, slen);
+      PKLAUNCH("k_pk_sorted_len");
+      size_t tb = 0;
+      PK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, slen, uoff, (int)(NU + 1), s));
+      void* tscan = tmp(tb, e2);
+      PK(e2);
+      PK(hipcub::DeviceScan::ExclusiveSum(tscan, tb, slen, uoff, (int)(NU + 1), s));
+      if (n_reg > 0) {
+        hipLaunchKernelGGL(k_pk_region_events, dim3((unsigned)((n_reg + 255) / 256)), dim3(256), 0, s, uoff, o.reg_first,
+                           n_reg, rev);
+        PKLAUNCH("k_pk_region_events");
+      }
+      o.h_reg_events.resize((size_t)n_reg);
+      if (n_reg > 0)
+        PK(hipMemcpyAsync(o.h_reg_events.data(), rev, (size_t)n_reg * 8, hipMemcpyDeviceToHost, s));
+      PK(hipStreamSynchronize(s));
+    }
     // ---- 6. fill --------------------------------------------------------
     o.w32 = (uint32_t*)own((size_t)nev * 4, e2);
     PK(e2);
-    o.slw = (float*)own((size_t)nev * 4, e2);
+    o.row = (uint32_t*)own((size_t)nev * 4, e2);
+    PK(e2);
+    o.alpha = (float*)own((size_t)nev * 4, e2);
     PK(e2);
     o.desc = (uint2*)own((size_t)ng * kGroupUnits * 8, e2);
     PK(e2);
@@ -479,9 +583,8 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       FillArgs fa;
       fa.ev = in.ev;
       fa.bins = B;
-      fa.slew_axis = in.slew_axis;
+      fa.lib = in.lib;
       fa.gcell = o.gcell;
-      fa.n_slew = in.n_slew;
       fa.tile_grp = o.tile_grp;
       fa.tfirst = tfirst;
       fa.sidx = sidx;
@@ -489,7 +592,10 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       fa.grp_off = o.grp_off;
       fa.n_groups = ng;
       fa.w32 = o.w32;
-      fa.slw = o.slw;
+      fa.row = o.row;
+      fa.alpha = o.alpha;
+      fa.dbg_state = in.dbg_state;
+      fa.dbg_bin = in.dbg_bin;
       fa.desc = o.desc;
       fa.dsrc = o.dsrc;
       const int64_t threads = ng * kGroupUnits;

@@ -119,6 +119,12 @@ struct gtp_ctx_s {
   // per-call work buffers
   DevBuf gprep, gparam, X, S, exS, L0, flag, first_bad;
   DevBuf adj_w, adj_c, adj_exc, adj_wg, adj_total, gC, gL;
+
+  // packed adjoint work items (built from the pack's region tables)
+  bool adj_ok = false;
+  int64_t adj_n_items = 0;
+  int32_t adj_max_gb = 0;   // gates in the largest gate block
+  DevBuf adj_items, adj_entries, adj_gbs, adj_gbrow, adj_gbrows, adj_part;
 };
 
 namespace {
@@ -369,6 +375,13 @@ size_t packed_lds_bytes(gtp_ctx c, int tile_log2) {
 }
 
 constexpr size_t kMaxLds = 160 * 1024;
+// Longest unit of the packed layout by default; kernels hold a group's events
+// in registers, 8 or 16 slots per lane. With 16 slots, workgroups of at most
+// 512 threads (the registers of 1024 threads do not fit).
+constexpr int kDefaultUnitEvents = 8;
+int threads_for_slots(int th, int slots) { return (slots == 16 && th > 512) ? 512 : th; }
+int unit_events_of(gtp_ctx c) { return c->tun.unit_events ? c->tun.unit_events : kDefaultUnitEvents; }
+int slots_of(gtp_ctx c) { return unit_events_of(c) <= 8 ? 8 : 16; }
 
 // static LDS of the batched kernel (its work-item slot), kept out of the
 // dynamic budget
@@ -382,10 +395,18 @@ hipError_t lds_limit(K kern, size_t static_lds = 0) {
 
 hipError_t set_packed_lds_limits() {
   hipError_t e = hipSuccess;
-  const hipError_t r[] = {lds_limit(k_fwd_packed<256, true>),  lds_limit(k_fwd_packed<256, false>),
-                          lds_limit(k_fwd_packed<512, false>), lds_limit(k_fwd_packed<1024, false>),
-                          lds_limit(k_fwd_batched<256>, kBatchStaticLds), lds_limit(k_fwd_batched<512>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<1024>, kBatchStaticLds)};
+  const hipError_t r[] = {lds_limit(k_fwd_packed<256, 8>),
+                          lds_limit(k_fwd_packed<512, 8>),
+                          lds_limit(k_fwd_packed<1024, 8>),
+                          lds_limit(k_fwd_packed<256, 16>),
+                          lds_limit(k_fwd_packed<512, 16>),
+                          lds_limit(k_fwd_batched<256, 8>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<512, 8>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<1024, 8>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<256, 16>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<512, 16>, kBatchStaticLds),
+                          lds_limit(k_adjoint_packed<1024, 8>),
+                          lds_limit(k_adjoint_packed<512, 16>)};
   for (hipError_t x : r)
     if (x != hipSuccess) e = x;
   return e;
@@ -402,6 +423,7 @@ void drop_pack(gtp_ctx c) {
     pack_free(&c->pk);
   }
   c->pack_ok = false;
+  c->adj_ok = false;
 }
 
 EvView ev_view_of(gtp_ctx c, const gtp_events& ev) {
@@ -427,7 +449,8 @@ BinSpec bins_for(gtp_ctx c, int64_t t_end) {
 
 // Packed layout of one event set (plan_buf: its gate-major lane-block plan);
 // sets B.tile_log2 / B.n_tiles.
-gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, BinSpec& B, PackOut& pk, double& pack_ms) {
+gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, BinSpec& B, PackOut& pk, double& pack_ms,
+                    int32_t* dbg_state = nullptr, int64_t* dbg_bin = nullptr) {
   if (B.r_bits > kTimeBits) return fail(c, GTP_ERR_UNSUPPORTED, "bin width above 2^%d ps", kTimeBits);
   int lb = c->tun.bins_per_tile_log2 ? c->tun.bins_per_tile_log2 : auto_tile_log2(B.n_bins, B.r_bits);
   if (lb + B.r_bits > kTimeBits)
@@ -448,9 +471,10 @@ gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, Bin
   in.gate_init = ptr<uint32_t>(c->gate_init);
   in.h_gate_cell = c->h_gate_cell;
   in.n_in = c->h_nin;
-  in.slew_axis = lib_view(c).slew;
-  in.n_slew = c->n_slew;
-  in.unit_events = c->tun.unit_events ? c->tun.unit_events : kLaneEvents;
+  in.lib = lib_view(c);
+  in.dbg_state = dbg_state;
+  in.dbg_bin = dbg_bin;
+  in.unit_events = unit_events_of(c);
   in.gate_block_log2 = c->tun.gate_block_log2 ? c->tun.gate_block_log2 : kGateBlockLog2;
   in.bins = B;
   in.stream = c->stream;
@@ -483,6 +507,94 @@ gtp_status build_pack(gtp_ctx c) {
   drop_pack(c);
   TRY(pack_for(c, c->ev, c->plan_blk, c->bins, c->pk, c->pack_ms));
   c->pack_ok = true;
+  return GTP_OK;
+}
+
+// LDS of the packed adjoint: the staged library, then two FP32 accumulators
+// per gate of the largest gate block.
+size_t adj_lds_bytes(gtp_ctx c, int32_t max_gb) { return lib_lds_bytes(c) + (size_t)max_gb * 8; }
+
+// Work items of the packed adjoint. Entries list, gate block by gate block
+// and tile by tile, the groups holding the block's units with the lane range
+// of those units; an item is a run of one block's entries covering whole
+// tiles and about total / (3 * CUs) events, and items run largest first.
+gtp_status adj_plan(gtp_ctx c) {
+  if (c->adj_ok) return GTP_OK;
+  const PackOut& pk = c->pk;
+  const int32_t n_gb = pk.n_gb, n_tiles = c->bins.n_tiles;
+  const int64_t n_reg = (int64_t)n_tiles * n_gb;
+  if (pk.n_groups >= ((int64_t)1 << 31)) return fail(c, GTP_ERR_UNSUPPORTED, "too many groups for the adjoint");
+  std::vector<uint32_t> rf((size_t)n_reg + 1), tf((size_t)n_tiles + 1);
+  std::vector<int32_t> tg((size_t)n_tiles + 1);
+  HIPCHK(c, hipMemcpyAsync(rf.data(), pk.reg_first, rf.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(tf.data(), pk.tfirst, tf.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(tg.data(), pk.tile_grp, tg.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int32_t max_gb = 0;
+  for (int32_t g = 0; g < n_gb; ++g) max_gb = std::max(max_gb, pk.h_gb_start[g + 1] - pk.h_gb_start[g]);
+  int64_t total = 0;
+  for (int64_t e : pk.h_reg_events) total += e;
+  const int64_t target = std::max<int64_t>(total / (3 * (int64_t)std::max(c->n_cu, 1)), 2048);
+  struct Item { int64_t ev; int32_t gb; int64_t e0, e1; };
+  std::vector<Item> items;
+  std::vector<int4> ent;
+  for (int32_t g = 0; g < n_gb; ++g) {
+    int64_t acc = 0, e0 = (int64_t)ent.size();
+    for (int32_t k = 0; k < n_tiles; ++k) {
+      const int64_t r = (int64_t)k * n_gb + g;
+      const int64_t j0 = rf[r], j1 = rf[r + 1];
+      if (j0 >= j1) continue;
+      const int64_t t0 = tf[k];
+      for (int64_t q = (j0 - t0) / kGroupUnits; q <= (j1 - 1 - t0) / kGroupUnits; ++q) {
+        const int64_t u0 = t0 + q * kGroupUnits;
+        const int lo = (int)std::max<int64_t>(j0 - u0, 0), hi = (int)std::min<int64_t>(j1 - u0, kGroupUnits);
+        ent.push_back(make_int4((int32_t)(tg[k] + q), k, lo | (hi << 8), 0));
+      }
+      acc += pk.h_reg_events[(size_t)r];
+      if (acc >= target) {
+        items.push_back({acc, g, e0, (int64_t)ent.size()});
+        acc = 0;
+        e0 = (int64_t)ent.size();
+      }
+    }
+    if ((int64_t)ent.size() > e0) items.push_back({acc, g, e0, (int64_t)ent.size()});
+  }
+  if ((int64_t)ent.size() >= ((int64_t)1 << 31)) return fail(c, GTP_ERR_UNSUPPORTED, "too many adjoint entries");
+  // rows of the partial table: a block's items get consecutive rows
+  std::vector<int64_t> gb_row((size_t)n_gb, 0);
+  std::vector<int32_t> gb_rows((size_t)n_gb, 0);
+  std::vector<AdjItem> h(std::max<size_t>(items.size(), 1));
+  int64_t rows = 0;
+  for (size_t i = 0; i < items.size(); ++i) {
+    const int32_t g = items[i].gb;
+    const int64_t ng = pk.h_gb_start[g + 1] - pk.h_gb_start[g];
+    if (gb_rows[g] == 0) gb_row[g] = rows;
+    h[i] = AdjItem{g, (int32_t)items[i].e0, (int32_t)items[i].e1, 0, gb_row[g] + gb_rows[g] * ng};
+    gb_rows[g]++;
+    rows += ng;
+  }
+  std::vector<int32_t> order(items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return items[a].ev > items[b].ev; });
+  std::vector<AdjItem> hs(h.size());
+  for (size_t i = 0; i < order.size(); ++i) hs[i] = h[order[i]];
+  if (ent.empty()) ent.push_back(make_int4(0, 0, 0, 0));
+  TRY(ensure(c, c->adj_items, hs.size() * sizeof(AdjItem)));
+  TRY(ensure(c, c->adj_entries, ent.size() * sizeof(int4)));
+  TRY(ensure(c, c->adj_gbs, pk.h_gb_start.size() * 4));
+  TRY(ensure(c, c->adj_gbrow, gb_row.size() * 8));
+  TRY(ensure(c, c->adj_gbrows, gb_rows.size() * 4));
+  TRY(ensure(c, c->adj_part, (size_t)std::max<int64_t>(rows, 1) * 8));
+  HIPCHK(c, hipMemcpyAsync(c->adj_items.p, hs.data(), hs.size() * sizeof(AdjItem), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->adj_entries.p, ent.data(), ent.size() * sizeof(int4), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->adj_gbs.p, pk.h_gb_start.data(), pk.h_gb_start.size() * 4, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->adj_gbrow.p, gb_row.data(), gb_row.size() * 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->adj_gbrows.p, gb_rows.data(), gb_rows.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->adj_n_items = (int64_t)items.size();
+  c->adj_max_gb = max_gb;
+  c->adj_ok = true;
   return GTP_OK;
 }
 
@@ -572,7 +684,7 @@ gtp_status gtp_destroy(gtp_ctx c) {
   DevBuf* all[] = {&c->lib_img, &c->load_axis, &c->load_inv, &c->quads, &c->gate_cell, &c->gate_out,
                    &c->gate_init, &c->plan_blk, &c->blk_tmp, &c->blk_tmp2, &c->scan_sums, &c->gprep, &c->gparam,
                    &c->X, &c->S, &c->exS, &c->L0, &c->flag, &c->first_bad, &c->adj_w, &c->adj_c, &c->adj_exc,
-                   &c->adj_wg, &c->adj_total, &c->gC, &c->gL, &c->b_tab, &c->b_items, &c->b_queue,
+                   &c->adj_wg, &c->adj_total, &c->gC, &c->gL, &c->adj_items, &c->adj_entries, &c->adj_gbs, &c->adj_gbrow, &c->adj_gbrows, &c->adj_part, &c->b_tab, &c->b_items, &c->b_queue,
                    &c->b_fin, &c->b_X, &c->b_S, &c->b_exS, &c->tun_in, &c->tun_out};
   for (DevBuf* b : all) release(c, *b);
   prof_clear(c);
@@ -895,7 +1007,7 @@ gtp_status gtp_get_tuning(gtp_ctx c, gtp_tuning* t) {
   *t = c->tun;
   if (c->pack_ok && t->bins_per_tile_log2 == 0) t->bins_per_tile_log2 = c->bins.tile_log2;
   if (t->tile_threads == 0) t->tile_threads = kTileThreads;
-  if (t->unit_events == 0) t->unit_events = kLaneEvents;
+  if (t->unit_events == 0) t->unit_events = kDefaultUnitEvents;
   if (t->gate_block_log2 == 0) t->gate_block_log2 = kGateBlockLog2;
   return GTP_OK;
 }
@@ -978,50 +1090,43 @@ PackedFwdArgs packed_common(gtp_ctx c) {
   a.lib = lib_view(c);
   a.lut = lut_args(c);
   a.sw_mode = c->par.sw_mode;
-  a.dbg_state = nullptr;
-  a.dbg_bin = nullptr;
   return a;
 }
 
 int tile_threads(gtp_ctx c) { return c->tun.tile_threads ? c->tun.tile_threads : kTileThreads; }
 
-// Packed forward of one trace into X/S; with dbg_state set, also the
-// per-event trace.
-gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, int64_t* X, int64_t* S,
-                              int32_t* dbg_state, int64_t* dbg_bin) {
+// Packed forward of one trace into X/S.
+gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, int64_t* X, int64_t* S) {
   PackedFwdArgs a = packed_common(c);
   a.w32 = pk.w32;
-  a.slw = pk.slw;
+  a.row = pk.row;
+  a.alpha = pk.alpha;
   a.desc = pk.desc;
   a.grp_off = pk.grp_off;
   a.tile_grp = pk.tile_grp;
   a.bins = B;
   a.X = X;
   a.S = S;
-  a.dbg_state = dbg_state;
-  a.dbg_bin = dbg_bin;
-  a.dsrc = pk.dsrc;
   const size_t lds = packed_lds_bytes(c, B.tile_log2);
-  const int th = tile_threads(c);
+  const int sl = slots_of(c);
+  const int th = threads_for_slots(tile_threads(c), sl);
   const dim3 grid((unsigned)B.n_tiles);
-  if (dbg_state) {
-    LAUNCH(c, "k_fwd_packed_trace", (k_fwd_packed<256, true>), grid, dim3(256), lds, a);
-    return GTP_OK;
+#define GTP_PACKED_CASE(TH, SL)                                                     \
+  if (th == TH && sl == SL) {                                                       \
+    LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, SL>), grid, dim3(TH), lds, a);      \
+    return GTP_OK;                                                                  \
   }
-#define GTP_PACKED_CASE(TH)                                                             \
-  if (th == TH) {                                                                       \
-    LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, false>), grid, dim3(TH), lds, a);        \
-    return GTP_OK;                                                                      \
-  }
-  GTP_PACKED_CASE(256)
-  GTP_PACKED_CASE(512)
-  GTP_PACKED_CASE(1024)
+  GTP_PACKED_CASE(256, 8)
+  GTP_PACKED_CASE(512, 8)
+  GTP_PACKED_CASE(1024, 8)
+  GTP_PACKED_CASE(256, 16)
+  GTP_PACKED_CASE(512, 16)
 #undef GTP_PACKED_CASE
   return fail(c, GTP_ERR_INVALID_ARG, "tile_threads %d", th);
 }
 
-gtp_status packed_forward(gtp_ctx c, int32_t* dbg_state, int64_t* dbg_bin) {
-  return packed_forward_for(c, c->pk, c->bins, ptr<int64_t>(c->X), ptr<int64_t>(c->S), dbg_state, dbg_bin);
+gtp_status packed_forward(gtp_ctx c) {
+  return packed_forward_for(c, c->pk, c->bins, ptr<int64_t>(c->X), ptr<int64_t>(c->S));
 }
 
 // ---------------------------------------------------------------------------
@@ -1082,7 +1187,7 @@ gtp_status build_batch(gtp_ctx c) {
       return st;
     }
     t.bin_off = off;
-    tab[i] = TraceDev{t.pk.w32, t.pk.slw, t.pk.desc, t.pk.grp_off, t.pk.tile_grp, t.bins, off};
+    tab[i] = TraceDev{t.pk.w32, t.pk.row, t.pk.alpha, t.pk.desc, t.pk.grp_off, t.pk.tile_grp, t.bins, off};
     fin[i] = FinTrace{off, t.bins.n_bins, t.bins.t_end};
     off += t.bins.n_bins;
     // events per tile, for the largest-first order
@@ -1136,19 +1241,22 @@ gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_s
     a.X = ptr<int64_t>(c->b_X);
     a.S = ptr<int64_t>(c->b_S);
     const size_t lds = packed_lds_bytes(c, lb);
-    const int th = tile_threads(c);
+    const int sl = slots_of(c);
+    const int th = threads_for_slots(tile_threads(c), sl);
     // resident workgroups: as many as fit (LDS-limited), at most one per item
     int per_cu = (int)std::max<size_t>(1, kMaxLds / lds);
     per_cu = std::min(per_cu, 2048 / th);
     const int64_t wgs = std::min<int64_t>(c->batch_items, (int64_t)c->n_cu * per_cu);
     const dim3 grid((unsigned)wgs);
-#define GTP_BATCH_CASE(TH)                                                              \
-  if (th == TH) {                                                                       \
-    LAUNCH(c, "k_fwd_batched", (k_fwd_batched<TH>), grid, dim3(TH), lds, a);             \
+#define GTP_BATCH_CASE(TH, SL)                                                          \
+  if (th == TH && sl == SL) {                                                           \
+    LAUNCH(c, "k_fwd_batched", (k_fwd_batched<TH, SL>), grid, dim3(TH), lds, a);         \
   }
-    GTP_BATCH_CASE(256)
-    GTP_BATCH_CASE(512)
-    GTP_BATCH_CASE(1024)
+    GTP_BATCH_CASE(256, 8)
+    GTP_BATCH_CASE(512, 8)
+    GTP_BATCH_CASE(1024, 8)
+    GTP_BATCH_CASE(256, 16)
+    GTP_BATCH_CASE(512, 16)
 #undef GTP_BATCH_CASE
   }
   const int64_t NB = c->batch_total_bins;
@@ -1212,7 +1320,7 @@ gtp_status gtp_forward(gtp_ctx c, const float* net_load_ff, const float* leak_sc
   if (c->tun.algo == 0) {
     TRY(build_pack(c));
     TRY(gate_params(c, net_load_ff, leak_scale));
-    TRY(packed_forward(c, nullptr, nullptr));
+    TRY(packed_forward(c));
   } else {
     TRY(gate_prep(c, net_load_ff, leak_scale));
     TRY(fill_u64(c, c->X.p, NB, 0ull));
@@ -1299,7 +1407,7 @@ gtp_status gtp_forward_trace(gtp_ctx c, int32_t trace, const float* net_load_ff,
   TRY(ensure(c, c->S, (size_t)NB * 8));
   TRY(ensure(c, c->exS, (size_t)NB * 8));
   TRY(gate_params_for(c, t.pk, net_load_ff, leak_scale));
-  TRY(packed_forward_for(c, t.pk, t.bins, ptr<int64_t>(c->X), ptr<int64_t>(c->S), nullptr, nullptr));
+  TRY(packed_forward_for(c, t.pk, t.bins, ptr<int64_t>(c->X), ptr<int64_t>(c->S)));
   TRY(scan_exclusive<int64_t, OpAdd>(c, ptr<int64_t>(c->S), ptr<int64_t>(c->exS), NB, (int64_t)0, OpAdd()));
   FinArgs f;
   f.X = ptr<int64_t>(c->X);
@@ -1446,13 +1554,18 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
     return fail(c, GTP_ERR_INVALID_ARG, "null adjoint argument");
   HIPCHK(c, hipSetDevice(c->dev));
   const int64_t NB = c->bins.n_bins;
-  TRY(gate_prep(c, net_load_ff, leak_scale));
+  bool packed = c->tun.algo == 0;
+  if (packed) {
+    TRY(build_pack(c));
+    TRY(adj_plan(c));
+    packed = adj_lds_bytes(c, c->adj_max_gb) <= kMaxLds;  // else the gate-major kernel
+  }
   TRY(ensure(c, c->adj_w, (size_t)NB * 8));
   TRY(ensure(c, c->adj_c, (size_t)NB * 8));
   TRY(ensure(c, c->adj_exc, (size_t)NB * 8));
   TRY(ensure(c, c->adj_wg, (size_t)NB * 16));
   TRY(ensure(c, c->adj_total, 8));
-  TRY(ensure(c, c->gC, (size_t)std::max<int64_t>(c->n_nets, 1) * 8));
+  TRY(ensure(c, c->gC, (size_t)std::max<int64_t>(std::max(c->n_nets, c->n_gates), 1) * 8));
   TRY(ensure(c, c->gL, (size_t)std::max<int64_t>(c->n_gates, 1) * 8));
   AdjBinArgs ab;
   ab.gP = grad_power;
@@ -1463,7 +1576,69 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
   ab.t_end = c->bins.t_end;
   LAUNCH(c, "k_adj_bins", k_adj_bins, dim3(grid_for(NB, 256)), dim3(256), 0, ab);
   TRY(scan_exclusive<double, OpAdd>(c, ptr<double>(c->adj_c), ptr<double>(c->adj_exc), NB, 0.0, OpAdd()));
+  const double v2 = c->par.vdd * c->par.vdd;
+  const float dsw_rise = (float)(c->par.sw_mode == 0 ? 0.5 * v2 : v2);
+  const float dsw_fall = (float)(c->par.sw_mode == 0 ? 0.5 * v2 : 0.0);
+  if (packed) {
+    LAUNCH(c, "k_adj_suffix_f", k_adj_suffix_f, dim3(grid_for(NB, 256)), dim3(256), 0,
+           (const double*)ptr<double>(c->adj_w), (const double*)ptr<double>(c->adj_c),
+           (const double*)ptr<double>(c->adj_exc), ptr<float2>(c->adj_wg), ptr<double>(c->adj_total), NB);
+    TRY(gate_params(c, net_load_ff, leak_scale));
+    if (c->adj_n_items > 0) {
+      const PackOut& pk = c->pk;
+      AdjPackedArgs a;
+      a.f = packed_common(c);
+      a.f.w32 = pk.w32;
+      a.f.row = pk.row;
+      a.f.alpha = pk.alpha;
+      a.f.desc = pk.desc;
+      a.f.grp_off = pk.grp_off;
+      a.f.tile_grp = pk.tile_grp;
+      a.f.bins = c->bins;
+      a.entries = ptr<int4>(c->adj_entries);
+      a.items = ptr<AdjItem>(c->adj_items);
+      a.gb_start = ptr<int32_t>(c->adj_gbs);
+      a.part = ptr<float2>(c->adj_part);
+      a.load_inv = ptr<float>(c->load_inv);
+      a.n_load = c->n_load;
+      a.last_w = (int32_t)(c->bins.t_end - (c->bins.n_bins - 1) * c->bins.D);
+      a.wg = ptr<float2>(c->adj_wg);
+      a.dsw_rise = dsw_rise;
+      a.dsw_fall = dsw_fall;
+      if (slots_of(c) == 8) {
+        LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<1024, 8>), dim3((unsigned)c->adj_n_items), dim3(1024),
+               adj_lds_bytes(c, c->adj_max_gb), a);
+      } else {
+        LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<512, 16>), dim3((unsigned)c->adj_n_items), dim3(512),
+               adj_lds_bytes(c, c->adj_max_gb), a);
+      }
+    }
+    if (c->n_nets > 0)
+      LAUNCH(c, "k_fill_i32", k_fill_i32, dim3(grid_for(c->n_nets, 256)), dim3(256), 0, (int32_t*)grad_net_load,
+             c->n_nets, 0);
+    if (c->n_gates > 0) {
+      AdjOutSortedArgs o;
+      o.part = ptr<float2>(c->adj_part);
+      o.gb_row = ptr<int64_t>(c->adj_gbrow);
+      o.gb_rows = ptr<int32_t>(c->adj_gbrows);
+      o.gb_start = ptr<int32_t>(c->adj_gbs);
+      o.n_gb = c->pk.n_gb;
+      o.total = ptr<double>(c->adj_total);
+      o.gperm = c->pk.gperm;
+      o.gcell = c->pk.gcell;
+      o.gate_out = ptr<int32_t>(c->gate_out);
+      o.gate_init = ptr<uint32_t>(c->gate_init);
+      o.meta = lib_view(c).meta;
+      o.leak = lib_view(c).leak;
+      o.grad_load = grad_net_load;
+      o.grad_scale = grad_leak_scale;
+      o.n_gates = c->n_gates;
+      LAUNCH(c, "k_adj_out_sorted", k_adj_out_sorted, dim3(grid_for(c->n_gates, 256)), dim3(256), 0, o);
+    }
+    return GTP_OK;
+  }
   LAUNCH(c, "k_adj_suffix", k_adj_suffix, dim3(grid_for(NB, 256)), dim3(256), 0, (const double*)ptr<double>(c->adj_w), (const double*)ptr<double>(c->adj_c), (const double*)ptr<double>(c->adj_exc), ptr<double2>(c->adj_wg), ptr<double>(c->adj_total), NB);
+  TRY(gate_prep(c, net_load_ff, leak_scale));
   TRY(fill_u64(c, c->gC.p, c->n_nets, 0ull));
   TRY(fill_u64(c, c->gL.p, c->n_gates, 0ull));
   if (c->n_blocks > 0) {
@@ -1476,9 +1651,8 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
     a.lut = lut_args(c);
     a.bins = c->bins;
     a.wg = ptr<double2>(c->adj_wg);
-    const double v2 = c->par.vdd * c->par.vdd;
-    a.dsw_rise = (float)(c->par.sw_mode == 0 ? 0.5 * v2 : v2);
-    a.dsw_fall = (float)(c->par.sw_mode == 0 ? 0.5 * v2 : 0.0);
+    a.dsw_rise = dsw_rise;
+    a.dsw_fall = dsw_fall;
     a.gC = ptr<double>(c->gC);
     a.gL = ptr<double>(c->gL);
     LAUNCH(c, "k_adjoint_events", k_adjoint_events, dim3(grid_for(c->n_blocks, kFwdThreads)), dim3(kFwdThreads), lib_lds_bytes(c), a);
@@ -1512,15 +1686,15 @@ gtp_status gtp_debug_event_trace(gtp_ctx c, int32_t* state_before, int64_t* bin)
   TRY(ensure(c, c->adj_w, (size_t)(c->n_nets + 2) * 4));
   TRY(fill_u64(c, c->adj_w.p, (c->n_nets + 1) / 2 + 1, 0x3f8000003f800000ull));
   if (c->tun.algo == 0) {
-    // the packed path's own state tracking; events it does not pack keep -1
-    TRY(build_pack(c));
+    // the packed path's own state tracking, done once when the layout is
+    // built: the layout is rebuilt with the trace written alongside; events
+    // it does not pack keep -1
     LAUNCH(c, "k_fill_i32", k_fill_i32, dim3(grid_for(N, 256)), dim3(256), 0, state_before, N, -1);
     TRY(fill_u64(c, bin, N, ~0ull));
-    const int64_t NB = c->bins.n_bins;
-    TRY(ensure(c, c->X, (size_t)NB * 8));
-    TRY(ensure(c, c->S, (size_t)NB * 8));
-    TRY(gate_params(c, ptr<float>(c->adj_w), nullptr));
-    return packed_forward(c, state_before, bin);
+    drop_pack(c);
+    TRY(pack_for(c, c->ev, c->plan_blk, c->bins, c->pk, c->pack_ms, state_before, bin));
+    c->pack_ok = true;
+    return GTP_OK;
   }
   TRY(gate_prep(c, ptr<float>(c->adj_w), nullptr));
   TraceArgs a;

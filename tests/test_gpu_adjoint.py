@@ -23,9 +23,11 @@ def O():
     return oracle.get()
 
 
-def gpu_adjoint(prob, gP, algo=0):
+def gpu_adjoint(prob, gP, algo=0, **tuning):
     import torch
     ctx, load, lam = to_device_ctx(prob, algo=algo)
+    if tuning:
+        ctx.set_tuning(algo=algo, **tuning)
     gl, gs = ctx.adjoint(load, lam, torch.from_numpy(np.asarray(gP, np.float32)).to(load.device))
     out = gl.cpu().numpy().astype(np.float64), gs.cpu().numpy().astype(np.float64)
     ctx.close()
@@ -38,8 +40,9 @@ def close(a, b, what):
     assert err <= TOL * max(scale, 1e-30), f"{what}: max abs err {err:.3e} vs scale {scale:.3e}"
 
 
+@pytest.mark.parametrize("algo", [0, 1])
 @pytest.mark.parametrize("seed", [1, 2, 3, 4, 5, 6])
-def test_random_vs_oracle(O, seed):
+def test_random_vs_oracle(O, seed, algo):
     rng = np.random.default_rng(100 + seed)
     prob = synth.make_random_small(seed, n_gates=int(rng.integers(5, 120)), n_cells=int(rng.integers(1, 8)),
                                    i_max=int(rng.integers(1, 5)), n_events=int(rng.integers(100, 30000)),
@@ -47,7 +50,7 @@ def test_random_vs_oracle(O, seed):
                                    p_tie=float(rng.choice([0.0, 0.3])), n_clock=int(rng.integers(0, 3)))
     gP = rng.normal(size=prob.n_bins)  # signed weights: no cancellation hides a wrong term
     gl64, gs64 = O.adjoint(prob, gP)
-    gl, gs = gpu_adjoint(prob, gP)
+    gl, gs = gpu_adjoint(prob, gP, algo=algo)
     drv = prob.net.gate_out_net
     close(gl[drv], gl64[drv], "d/d load")
     close(gs, gs64, "d/d leak scale")
@@ -94,6 +97,20 @@ def test_adjoint_workload_scaled(O):
     _, gP = oracle.lse_loss_grad(P64, beta)
     gl64, gs64 = O.adjoint(prob, gP)
     gl, gs = gpu_adjoint(prob, gP)
+    drv = prob.net.gate_out_net
+    close(gl[drv], gl64[drv], "d/d load")
+    close(gs, gs64, "d/d leak scale")
+
+
+@pytest.mark.parametrize("tl,ue,gb", [(4, 16, 6), (2, 5, 6), (9, 8, 14)])
+def test_packed_decompositions(O, tl, ue, gb):
+    """Small tiles and gate blocks: many work items, groups shared by two gate
+    blocks, regions of one unit; every decomposition matches the oracle."""
+    prob = synth.make_random_small(91, n_gates=300, n_cells=3, i_max=4, n_events=40000, t_end=300000, bin_ps=50,
+                                   p_tie=0.2, n_clock=2)
+    gP = np.random.default_rng(5).normal(size=prob.n_bins)
+    gl64, gs64 = O.adjoint(prob, gP)
+    gl, gs = gpu_adjoint(prob, gP, algo=0, bins_per_tile_log2=tl, unit_events=ue, gate_block_log2=gb)
     drv = prob.net.gate_out_net
     close(gl[drv], gl64[drv], "d/d load")
     close(gs, gs64, "d/d leak scale")
