@@ -83,6 +83,7 @@ struct LibView {
   const float4* quads;      // [n_tables * (n_slew-1) * (n_load-1)]
   int32_t n_cells, n_slew, n_load, n_map, n_leak;
   int32_t lds_words;        // 32-bit words of the LDS image
+  int32_t lds_words_ml;     // words of its meta + leakage prefix
 };
 
 // Prepared gate record (32 bytes), gate-major kernels.
@@ -138,7 +139,7 @@ __device__ __forceinline__ int64_t bin_of(int64_t t, const BinSpec& B) {
   return t / B.D;
 }
 
-// LDS image of the library: meta | map_q | leak | slew | slew_inv (words).
+// LDS image of the library: meta | leak | map_q | slew | slew_inv (words).
 struct LdsLib {
   const CellMeta* meta;
   const int32_t* map_q;
@@ -153,10 +154,24 @@ __device__ __forceinline__ LdsLib stage_library(const LibView& L, uint32_t* lds)
   for (int w = threadIdx.x; w < L.lds_words; w += blockDim.x) lds[w] = src[w];
   LdsLib S;
   S.meta = reinterpret_cast<const CellMeta*>(lds);
-  S.map_q = reinterpret_cast<const int32_t*>(lds + 4 * L.n_cells);
-  S.leak = reinterpret_cast<const float*>(lds + 4 * L.n_cells + L.n_map);
+  S.leak = reinterpret_cast<const float*>(lds + 4 * L.n_cells);
+  S.map_q = reinterpret_cast<const int32_t*>(lds + 4 * L.n_cells + L.n_leak);
   S.slew = reinterpret_cast<const float*>(lds + 4 * L.n_cells + L.n_map + L.n_leak);
   S.slew_inv = S.slew + L.n_cells * L.n_slew;
+  return S;
+}
+
+// Only the cell records and leakage values (the prefix of the image): all the
+// packed kernels read from the library.
+__device__ __forceinline__ LdsLib stage_library_ml(const LibView& L, uint32_t* lds) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(L.meta);
+  for (int w = threadIdx.x; w < L.lds_words_ml; w += blockDim.x) lds[w] = src[w];
+  LdsLib S;
+  S.meta = reinterpret_cast<const CellMeta*>(lds);
+  S.leak = reinterpret_cast<const float*>(lds + 4 * L.n_cells);
+  S.map_q = nullptr;
+  S.slew = nullptr;
+  S.slew_inv = nullptr;
   return S;
 }
 

@@ -93,9 +93,16 @@ struct PackedFwdArgs {
   int32_t sw_mode;
   int64_t* X;
   int64_t* S;
+  const int4* phases;        // table phases (null: every quad from global memory)
+  const int32_t* ph_off;
 };
 
-__device__ __forceinline__ size_t packed_bins_word_offset(int32_t lib_words) { return (size_t)((lib_words + 1) & ~1); }
+// LDS of the packed kernels: the library's meta + leakage prefix, then the
+// tile's bins (two int64 per bin), then two table slots of kSlotQuads quads.
+constexpr int kSlotQuads = 2048;
+__device__ __host__ __forceinline__ size_t packed_bins_word_offset(int32_t lib_words) {
+  return (size_t)((lib_words + 3) & ~3);
+}
 
 // One wavefront group's data in registers: unit descriptor, gate
 // parameters and the lane's event records (k-major positions resolved).
@@ -154,51 +161,58 @@ __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int
   }
 }
 
-// The table quads of every event of a loaded group, gathered in one burst.
-// Vector-memory loads complete in issue order, so the burst is issued before
-// the next group's loads: the quads then arrive after an L2 latency instead
-// of waiting behind the next group's HBM loads.
-template <int kS>
-struct GroupQuads {
-  float4 q[kS];
-};
-
-template <int kS>
-__device__ __forceinline__ void group_quads(const PackedFwdArgs& a, const GroupRegs<kS>& G, GroupQuads<kS>& Q) {
-  const uint32_t jq = G.gp.cell_jq & 0xffu;
-#pragma unroll
-  for (int kk = 0; kk < kS; ++kk)
-    if (kk < G.kmax && G.len > kk) Q.q[kk] = a.lut.quads[(G.rv[kk] & kRowMask) + jq];
+// Table quad of a lane's event: from the phase's LDS slot when the quad lies
+// in its range [lo, lo + n), else from global memory.
+__device__ __forceinline__ float4 quad_at(const float4* __restrict__ quads, const float4* slot, uint32_t lo,
+                                          uint32_t n, uint32_t qi) {
+  const uint32_t li = qi - lo;
+  if (li < n) return slot[li];
+  return quads[qi];
 }
 
-// Accumulates one group (loaded into G, its quads into Q) into the tile's
-// LDS bins.
+// Accumulates one group (loaded into G) into the tile's LDS bins. The table
+// quad and the leakage value after event k+1 load into one buffer while event
+// k is accumulated from the other.
 template <int kS>
 __device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsLib& L, const GroupRegs<kS>& G,
-                                              const GroupQuads<kS>& Q, unsigned long long* xs,
-                                              unsigned long long* ss) {
+                                              unsigned long long* xs, unsigned long long* ss, const float4* slot,
+                                              uint32_t lo, uint32_t n) {
   const BinSpec& B = a.bins;
   const uint32_t rmask = (1u << B.r_bits) - 1u;
   const int32_t D32 = (int32_t)B.D;
+  const float4* __restrict__ quads = a.lut.quads;
   const int len = G.len;
   const GateParam gp = G.gp;
+  const uint32_t jq = gp.cell_jq & 0xffu;
   const CellMeta cm = L.meta[gp.cell_jq >> 8];
   const float esw_fall = a.sw_mode ? 0.0f : gp.esw_rise;
   const float* lk = L.leak + cm.leak_off;
   int32_t q_cur = qrate(gp.lam, lk[G.d.y & ((1u << cm.n_in) - 1u)], a.lut.rate_scale);
+  struct Pre {
+    float4 q;        // table quad
+    float lk_after;  // leakage value of the input state after the event
+  };
+  auto prefetch = [&](int k, Pre& P) {
+    P.q = quad_at(quads, slot, lo, n, (G.rv[k] & kRowMask) + jq);
+    P.lk_after = lk[G.wv[k] >> kStateShift];
+  };
+  Pre pre[2];
+  if (len > 0) prefetch(0, pre[0]);
 #pragma unroll
   for (int kk = 0; kk < kS; ++kk) {
     if (kk < G.kmax && len > kk) {
       const uint32_t w = G.wv[kk];
       const uint32_t rv = G.rv[kk];
-      float e = bilerp_quad(Q.q[kk], G.av[kk], gp.beta);
+      if (kk + 1 < kS && len > kk + 1) prefetch(kk + 1, pre[(kk + 1) & 1]);
+      const Pre& P = pre[kk & 1];
+      float e = bilerp_quad(P.q, G.av[kk], gp.beta);
       if (rv & (1u << kOutBit)) e = __fadd_rn(e, (rv >> 31) ? gp.esw_rise : esw_fall);
       int64_t x = energy_fixed(e, a.lut.two_sh);
       const uint32_t tl = w & kTimeMask;
       const uint32_t bl = tl >> B.r_bits;
       // leakage step: an output event leaves the input state (and so the
       // rate) unchanged, so dq = 0 for it without a branch
-      const int32_t qn = qrate(gp.lam, lk[w >> kStateShift], a.lut.rate_scale);
+      const int32_t qn = qrate(gp.lam, P.lk_after, a.lut.rate_scale);
       const int32_t dq = qn - q_cur;
       q_cur = qn;
       x += (int64_t)dq * (int64_t)(D32 - (int32_t)(tl & rmask));
@@ -208,23 +222,98 @@ __device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsL
   }
 }
 
+// Table-phase state of one workgroup (see fwd_tile_body).
+struct PhaseState {
+  int32_t ph, ph1;     // current phase, end of the tile's phases
+  int64_t ge;          // end group of the current phase
+  uint32_t lo, n;      // its quad range
+};
+
+__device__ __forceinline__ void phase_enter(const PackedFwdArgs& a, PhaseState& P, int64_t g0) {
+  const int4 Q = a.phases[P.ph];
+  P.ge = g0 + Q.x;
+  P.lo = (uint32_t)Q.y;
+  P.n = (uint32_t)Q.z;
+}
+
+// Quads [lo, lo + n) of the table array into an LDS slot, by direct
+// global-to-LDS loads: wavefront w copies 64-quad chunks w, w + nwave, ...
+// (a lane past n re-reads the last quad; the slot holds whole chunks). The
+// copy completes at the issuing wavefront's next vmcnt(0) wait.
+template <int kThreads>
+__device__ __forceinline__ void slot_fill(const float4* __restrict__ quads, uint32_t lo, uint32_t n, float4* slot) {
+  constexpr int nwave = kThreads / 64;
+  const int lane = (int)(threadIdx.x & 63);
+  const int chunks = (int)((n + 63) >> 6);
+  for (int c = (int)(threadIdx.x >> 6); c < chunks; c += nwave) {
+    const uint32_t i = min((uint32_t)(c * 64 + lane), n - 1u);
+    __builtin_amdgcn_global_load_lds((const void*)(quads + lo + i),
+                                     (__attribute__((address_space(3))) void*)(slot + c * 64), 16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+// Boundary ph -> ph + 1, taken by every wavefront: wait for this wavefront's
+// share of the next phase's quads, one barrier (after it the slot is whole
+// and the previous phase's slot is free), then the following phase's quads
+// start loading into that free slot.
+template <int kThreads>
+__device__ __forceinline__ void phase_advance(const PackedFwdArgs& a, PhaseState& P, float4* slots, int64_t g0) {
+  wait_vmem();
+  __syncthreads();
+  ++P.ph;
+  phase_enter(a, P, g0);
+  if (P.ph + 1 < P.ph1) {
+    const int4 Q = a.phases[P.ph + 1];
+    slot_fill<kThreads>(a.lut.quads, (uint32_t)Q.y, (uint32_t)Q.z, slots + ((P.ph + 1) & 1) * kSlotQuads);
+  }
+}
+
 // One time tile of one trace: the tile's bins are zeroed in LDS, every
 // wavefront takes whole groups of the tile, and the bins are stored at the
 // end (each bin belongs to exactly one tile). Memory-level parallelism: a
-// wavefront issues the table gathers of group i, then the loads of group i+1
-// (gate parameters, events) and the descriptors of group i+2, then works on
-// group i; the loop alternates two register buffers, so nothing is copied
-// between groups.
+// wavefront works on group i while the loads of group i+1 (gate parameters,
+// events) and the descriptors of group i+2 are in flight; the loop alternates
+// two register buffers, so nothing is copied between groups.
+//
+// Table phases (slots non-null and the tile has phases): the tile's groups
+// are cut into phases whose cells' table quads fit one LDS slot. Phase p reads
+// slot p & 1; while it runs, phase p+1's quads load straight into the other
+// slot, and one barrier at the boundary separates the phases. Every
+// wavefront crosses every boundary once, in order, whether or not it has
+// groups in a phase.
 template <int kThreads, int kS>
 __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsLib& L, unsigned long long* xs,
-                                              unsigned long long* ss, int32_t tile) {
+                                              unsigned long long* ss, int32_t tile, float4* slots) {
   const BinSpec& B = a.bins;
   const int nb = 1 << B.tile_log2;
   for (int i = threadIdx.x; i < 2 * nb; i += kThreads) xs[i] = 0ull;
+  const int64_t g0 = a.tile_grp[tile];
   const int64_t g1 = a.tile_grp[tile + 1];
   const int lane = (int)(threadIdx.x & 63);
   constexpr int nwave = kThreads / 64;
-  int64_t gi = a.tile_grp[tile] + (int64_t)(threadIdx.x >> 6);
+  int64_t gi = g0 + (int64_t)(threadIdx.x >> 6);
+  // ---- table phases
+  PhaseState P;
+  P.ph = 0;
+  P.ph1 = 0;
+  if (slots && a.phases) {
+    P.ph = a.ph_off[tile];
+    P.ph1 = a.ph_off[tile + 1];
+  }
+  P.ge = g1;
+  P.lo = 0;
+  P.n = 0;
+  if (P.ph < P.ph1) {
+    phase_enter(a, P, g0);
+    slot_fill<kThreads>(a.lut.quads, P.lo, P.n, slots + (P.ph & 1) * kSlotQuads);
+    wait_vmem();  // the first phase's slot is whole at the barrier below
+    if (P.ph + 1 < P.ph1) {
+      const int4 Q = a.phases[P.ph + 1];
+      slot_fill<kThreads>(a.lut.quads, (uint32_t)Q.y, (uint32_t)Q.z, slots + ((P.ph + 1) & 1) * kSlotQuads);
+    }
+  }
   GroupRegs<kS> ga, gb;
   uint2 dn = make_uint2(0xffffffffu, 0u);
   int64_t offn = 0;
@@ -242,22 +331,18 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
     issue(gi, ga);
   }
   __syncthreads();
-  GroupQuads<kS> Q;
   while (gi < g1) {
-    group_quads(a, ga, Q);
-    __builtin_amdgcn_sched_barrier(0);
+    while (gi >= P.ge) phase_advance<kThreads>(a, P, slots, g0);
     if (gi + nwave < g1) issue(gi + nwave, gb);
-    __builtin_amdgcn_sched_barrier(0);
-    process_group(a, L, ga, Q, xs, ss);
+    process_group(a, L, ga, xs, ss, slots + (P.ph & 1) * kSlotQuads, P.lo, P.n);
     gi += nwave;
     if (gi >= g1) break;
-    group_quads(a, gb, Q);
-    __builtin_amdgcn_sched_barrier(0);
+    while (gi >= P.ge) phase_advance<kThreads>(a, P, slots, g0);
     if (gi + nwave < g1) issue(gi + nwave, ga);
-    __builtin_amdgcn_sched_barrier(0);
-    process_group(a, L, gb, Q, xs, ss);
+    process_group(a, L, gb, xs, ss, slots + (P.ph & 1) * kSlotQuads, P.lo, P.n);
     gi += nwave;
   }
+  while (P.ph + 1 < P.ph1) phase_advance<kThreads>(a, P, slots, g0);  // boundaries after this wavefront's last group
   __syncthreads();
   const int64_t b0 = (int64_t)tile << B.tile_log2;
   for (int i = threadIdx.x; i < nb; i += kThreads) {
@@ -272,10 +357,11 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
 template <int kThreads, int kS>
 __global__ void __launch_bounds__(kThreads) k_fwd_packed(PackedFwdArgs a) {
   extern __shared__ uint32_t lds[];
-  const LdsLib L = stage_library(a.lib, lds);
-  unsigned long long* xs = reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.lib.lds_words));
+  const LdsLib L = stage_library_ml(a.lib, lds);
+  unsigned long long* xs = reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.lib.lds_words_ml));
   unsigned long long* ss = xs + (1 << a.bins.tile_log2);
-  fwd_tile_body<kThreads, kS>(a, L, xs, ss, (int32_t)blockIdx.x);
+  float4* slots = a.phases ? reinterpret_cast<float4*>(ss + (1 << a.bins.tile_log2)) : nullptr;
+  fwd_tile_body<kThreads, kS>(a, L, xs, ss, (int32_t)blockIdx.x, slots);
 }
 
 // ---------------------------------------------------------------------------
@@ -285,6 +371,8 @@ struct TraceDev {
   const uint32_t* w32;
   const uint32_t* row;
   const float* alpha;
+  const int4* phases;
+  const int32_t* ph_off;
   const uint2* desc;
   const int64_t* grp_off;
   const int32_t* tile_grp;
@@ -308,12 +396,16 @@ template <int kThreads, int kS>
 __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ long long item_sh;
-  const LdsLib L = stage_library(a.base.lib, lds);
+  const LdsLib L = stage_library_ml(a.base.lib, lds);
   for (;;) {
     __syncthreads();  // the previous item is done with item_sh and the LDS bins
     if (threadIdx.x == 0) item_sh = (long long)atomicAdd(a.queue, 1ull);
     __syncthreads();
-    const long long it = item_sh;
+    // the item index is the same on every lane: make it scalar, so the
+    // trace record and everything derived from it stay in scalar registers
+    const long long it0 = item_sh;
+    const long long it = (long long)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(it0 >> 32)) << 32) |
+                                     (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)it0));
     if (it >= a.n_items) break;
     const int2 w = a.items[it];
     const TraceDev T = a.traces[w.x];
@@ -327,10 +419,13 @@ __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
     p.bins = T.bins;
     p.X = a.X + T.bin_off;
     p.S = a.S + T.bin_off;
+    p.phases = T.phases;
+    p.ph_off = T.ph_off;
     unsigned long long* xs =
-        reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.base.lib.lds_words));
+        reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.base.lib.lds_words_ml));
     unsigned long long* ss = xs + (1 << T.bins.tile_log2);
-    fwd_tile_body<kThreads, kS>(p, L, xs, ss, w.y);
+    float4* slots = T.phases ? reinterpret_cast<float4*>(ss + (1 << T.bins.tile_log2)) : nullptr;
+    fwd_tile_body<kThreads, kS>(p, L, xs, ss, w.y, slots);
   }
 }
 
@@ -720,8 +815,10 @@ __global__ void __launch_bounds__(256) k_adj_out(AdjOutArgs a) {
 struct AdjItem {
   int32_t gb;       // gate block
   int32_t e0, e1;   // entries [e0, e1)
-  int32_t pad;
+  int32_t q_lo;     // table quads [q_lo, q_lo + q_n) staged in LDS (the block's cell)
   int64_t row;      // first element of the item's row in the partial table
+  int32_t q_n;
+  int32_t pad;
 };
 
 struct AdjPackedArgs {
@@ -735,6 +832,7 @@ struct AdjPackedArgs {
   int32_t last_w;             // width of the last bin (ps)
   const float2* wg;           // [n_bins] (w_b, G_b)
   float dsw_rise, dsw_fall;
+  int32_t slot_quads;         // LDS table room (quads)
 };
 
 // One entry's group (loaded into G): per event, the load gradient gains
@@ -743,8 +841,8 @@ struct AdjPackedArgs {
 // Lookups are double-buffered by event parity as in the forward.
 template <int kS>
 __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const LdsLib& L, const GroupRegs<kS>& G,
-                                                  bool mine, int32_t tile, int32_t gs0, float* acc_c,
-                                                  float* acc_l) {
+                                                  bool mine, int32_t tile, int32_t gs0, float* acc_c, float* acc_l,
+                                                  const float4* tab, uint32_t q_lo, uint32_t q_n) {
   const BinSpec& B = a.f.bins;
   const uint32_t rmask = (1u << B.r_bits) - 1u;
   const int32_t D32 = (int32_t)B.D;
@@ -765,7 +863,12 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
   };
   auto prefetch = [&](int k, Pre& P) {
     const uint32_t w = G.wv[k];
-    P.q = quads[(G.rv[k] & kRowMask) + (uint32_t)jq];
+    const uint32_t qi = (G.rv[k] & kRowMask) + (uint32_t)jq;
+    if (qi - q_lo < q_n) {
+      P.q = tab[qi - q_lo];
+    } else {
+      P.q = quads[qi];
+    }
     P.lk_after = lk[w >> kStateShift];
     P.wg = a.wg[tile_b0 + (int64_t)((w & kTimeMask) >> B.r_bits)];
   };
@@ -801,11 +904,13 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
 template <int kThreads, int kS>
 __global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
   extern __shared__ uint32_t lds[];
-  const LdsLib L = stage_library(a.f.lib, lds);
+  const LdsLib L = stage_library_ml(a.f.lib, lds);
   const AdjItem it = a.items[blockIdx.x];
   const int32_t gs0 = a.gb_start[it.gb];
   const int32_t ng = a.gb_start[it.gb + 1] - gs0;
-  float* acc_c = reinterpret_cast<float*>(lds + a.f.lib.lds_words);
+  float4* tab = reinterpret_cast<float4*>(lds + packed_bins_word_offset(a.f.lib.lds_words_ml));
+  for (int i = threadIdx.x; i < it.q_n; i += kThreads) tab[i] = a.f.lut.quads[(uint32_t)it.q_lo + (uint32_t)i];
+  float* acc_c = reinterpret_cast<float*>(tab + a.slot_quads);
   float* acc_l = acc_c + ng;
   for (int i = threadIdx.x; i < 2 * ng; i += kThreads) acc_c[i] = 0.f;
   const int lane = (int)(threadIdx.x & 63);
@@ -843,11 +948,11 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
   __syncthreads();
   while (e < e1) {
     if (e + nwave < e1) issue(e + nwave, gb, mb, tb);
-    adj_process_group(a, L, ga, ma, ta, gs0, acc_c, acc_l);
+    adj_process_group(a, L, ga, ma, ta, gs0, acc_c, acc_l, tab, (uint32_t)it.q_lo, (uint32_t)it.q_n);
     e += nwave;
     if (e >= e1) break;
     if (e + nwave < e1) issue(e + nwave, ga, ma, ta);
-    adj_process_group(a, L, gb, mb, tb, gs0, acc_c, acc_l);
+    adj_process_group(a, L, gb, mb, tb, gs0, acc_c, acc_l, tab, (uint32_t)it.q_lo, (uint32_t)it.q_n);
     e += nwave;
   }
   __syncthreads();

@@ -14,10 +14,12 @@
 //          sparse gates become short units. A unit carries its gate and the
 //          gate's pin values before its first event and before that event's
 //          timestamp group (carried-in state).
-//   order  units sorted by (tile, gate block, decreasing length); a gate block
-//          is a run of at most 2^14 cell-sorted gates of one cell, so the
-//          units of one wavefront share a cell (table gathers stay in cache)
-//          and have similar lengths (lanes stay busy).
+//   order  units sorted by (tile, gate block, decreasing length, gate); a
+//          gate block is a run of at most 2^14 cell-sorted gates of one cell,
+//          so the units of one wavefront share a cell (table gathers stay in
+//          cache), have similar lengths (lanes stay busy) and, within a
+//          length, increasing gates (the per-unit gate-record loads of a
+//          wavefront touch fewer cache lines).
 //   group  64 consecutive units of one tile, one per lane of a wavefront. The
 //          group's events are stored unit-interleaved: event k of every unit
 //          longer than k, in lane order, then event k+1, ... So the k-th
@@ -63,6 +65,8 @@ struct PackIn {
   hipStream_t stream;
   int32_t* dbg_state = nullptr;   // optional [n_events] gate-major: state before the event's group
   int64_t* dbg_bin = nullptr;     // optional [n_events] gate-major: bin of the event
+  std::vector<int32_t> cq_lo, cq_hi;  // [n_cells] quad index range of each cell's tables
+  int32_t slot_quads = 0;         // quads one LDS table slot holds (0: no phases)
 };
 
 struct PackOut {
@@ -90,7 +94,14 @@ struct PackOut {
   int32_t n_gb = 0;
   int32_t gb_log2 = 0;
   std::vector<int32_t> h_gb_start;     // [n_gb + 1] first sorted gate of each gate block
+  std::vector<int32_t> h_gb_cell;      // [n_gb] cell of each gate block
   std::vector<int64_t> h_reg_events;   // [n_tiles * n_gb] events per region
+  // table phases of the forward: tile k's groups split into runs whose
+  // cells' table quads [lo, lo + n) fit one LDS slot; phase p of tile k is
+  // phases[ph_off[k] + p] = (end group, lo, n, -), runs cover the tile's groups
+  int4* phases = nullptr;
+  int32_t* ph_off = nullptr;       // [n_tiles + 1]
+  int64_t n_phases = 0;
 };
 
 // Builds the packed layout on in.stream (synchronises it). Returns

@@ -8,7 +8,7 @@
 //      tile changes; units per block are counted, then scanned;
 //   3. k_pk_units (emit pass): the same walk writes one record per unit
 //      (first event, gate, length, carried-in pin values) and its sort key
-//      (tile, gate block, 16 - length);
+//      (tile, gate block, 16 - length, gate within the block);
 //   4. radix sort of the unit keys (hipcub, stable);
 //   5. per tile its first unit; 64 units per group; group event counts,
 //      scanned into group offsets;
@@ -65,6 +65,7 @@ struct UnitVisitor {
   uint32_t init = 0;
   int32_t gs = 0;          // cell-sorted gate index
   uint32_t gblock = 0;
+  uint32_t gin = 0;        // index of the gate within its gate block
   bool open = false;
   int64_t u_src = 0;
   int32_t u_len = 0;
@@ -75,8 +76,11 @@ struct UnitVisitor {
     if (!open) return;
     if (kEmit) {
       const uint32_t u = A->base[kb] + n;
-      const uint64_t key = ((uint64_t)u_tile << (A->ks.gb_bits + 5)) | ((uint64_t)gblock << 5) |
-                           (uint64_t)(16 - u_len);
+      // (tile, gate block, 16 - length, gate within the block): lanes of one
+      // length class read neighbouring gate records
+      const uint64_t key = ((uint64_t)u_tile << (A->ks.gb_bits + 5 + A->ks.gb_log2)) |
+                           ((uint64_t)gblock << (5 + A->ks.gb_log2)) | ((uint64_t)(16 - u_len) << A->ks.gb_log2) |
+                           (uint64_t)gin;
       A->keys[u] = key;
       A->vals[u] = u;
       UnitRec r;
@@ -93,6 +97,7 @@ struct UnitVisitor {
     const int32_t c = A->gate_cell[g];
     gs = A->ks.rank[g];
     gblock = (uint32_t)(A->ks.gb_base[c] + ((gs - A->ks.cell_start[c]) >> A->ks.gb_log2));
+    gin = (uint32_t)(gs - A->ks.cell_start[c]) & ((1u << A->ks.gb_log2) - 1u);
     open = false;
   }
   __device__ __forceinline__ void end_gate(int64_t) { close(); }
@@ -142,12 +147,12 @@ __global__ void __launch_bounds__(256) k_pk_tile_first(const uint64_t* skey, int
 }
 
 // First sorted unit of every non-empty (tile, gate block) region.
-__global__ void __launch_bounds__(256) k_pk_region_first(const uint64_t* skey, int64_t nu, int32_t gb_bits, int32_t n_gb,
-                                                         uint32_t* rfirst) {
+__global__ void __launch_bounds__(256) k_pk_region_first(const uint64_t* skey, int64_t nu, int32_t gb_bits, int32_t low,
+                                                         int32_t n_gb, uint32_t* rfirst) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nu) return;
   auto region = [&](uint64_t k) -> int64_t {
-    return (int64_t)(k >> (gb_bits + 5)) * n_gb + (int64_t)((k >> 5) & ((1ull << gb_bits) - 1ull));
+    return (int64_t)(k >> (gb_bits + low)) * n_gb + (int64_t)((k >> low) & ((1ull << gb_bits) - 1ull));
   };
   const int64_t r = region(skey[j]);
   if (j == 0 || region(skey[j - 1]) != r) rfirst[r] = (uint32_t)j;
@@ -285,6 +290,26 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
   }
 }
 
+// First and last cell among a group's units (-1 for an empty group); the
+// lanes of a group are in gate-block order, so cells do not decrease.
+__global__ void __launch_bounds__(256) k_pk_group_cells(const uint2* desc, const int32_t* gcell, int64_t n_groups,
+                                                        int2* cells) {
+  const int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroupUnits;
+  const int lane = (int)(threadIdx.x & (kGroupUnits - 1));
+  if (gi >= n_groups) return;
+  const uint2 d = desc[gi * kGroupUnits + lane];
+  const bool v = d.x != 0xffffffffu;
+  const uint64_t m = __ballot(v);
+  if (m == 0) {
+    if (lane == 0) cells[gi] = make_int2(-1, -1);
+    return;
+  }
+  const int first = __ffsll((unsigned long long)m) - 1;
+  const int last = 63 - __clzll((long long)m);
+  if (lane == first) cells[gi].x = gcell[d.x & 0x0fffffffu];
+  if (lane == last) cells[gi].y = gcell[d.x & 0x0fffffffu];
+}
+
 int ceil_log2_u64(uint64_t x) {
   int l = 0;
   while ((1ull << l) < x) ++l;
@@ -294,7 +319,8 @@ int ceil_log2_u64(uint64_t x) {
 }  // namespace
 
 void pack_free(PackOut* o) {
-  void* ps[] = {o->w32, o->row, o->alpha, o->desc, o->dsrc, o->grp_off, o->tile_grp, o->gperm, o->gcell, o->reg_first, o->tfirst};
+  void* ps[] = {o->w32,  o->row,   o->alpha,     o->desc,  o->dsrc,   o->grp_off, o->tile_grp,
+                o->gperm, o->gcell, o->reg_first, o->tfirst, o->phases, o->ph_off};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   *o = PackOut();
@@ -357,9 +383,12 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     o.n_gb = n_gb;
     o.gb_log2 = in.gate_block_log2;
     o.h_gb_start.assign((size_t)n_gb + 1, (int32_t)G);
+    o.h_gb_cell.assign((size_t)n_gb, 0);
     for (int32_t c = 0; c < n_cells; ++c)
-      for (int32_t b = 0; gb_base[c] + b < (c + 1 < n_cells ? gb_base[c + 1] : gbacc); ++b)
+      for (int32_t b = 0; gb_base[c] + b < (c + 1 < n_cells ? gb_base[c + 1] : gbacc); ++b) {
         o.h_gb_start[gb_base[c] + b] = cell_start[c] + (b << in.gate_block_log2);
+        o.h_gb_cell[gb_base[c] + b] = c;
+      }
     std::vector<int32_t> rank((size_t)G), perm((size_t)G), pcell((size_t)G);
     {
       std::vector<int32_t> cur(cell_start);
@@ -373,7 +402,8 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     }
     const int gb_bits = ceil_log2_u64((uint64_t)n_gb);
     const int tile_bits = std::max(1, ceil_log2_u64((uint64_t)n_tiles));
-    const int key_bits = tile_bits + gb_bits + 5;
+    const int low = 5 + in.gate_block_log2;   // length and gate-within-block fields
+    const int key_bits = tile_bits + gb_bits + low;
     if (key_bits > 64) {
       snprintf(err, err_len, "pack: sort key of %d bits", key_bits);
       return hipErrorInvalidValue;
@@ -471,7 +501,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     PKLAUNCH("k_pk_fill_u32");
     if (NU > 0) {
       hipLaunchKernelGGL(k_pk_tile_first, dim3((unsigned)((NU + 255) / 256)), dim3(256), 0, s, skeys, NU,
-                         gb_bits + 5, tfirst);
+                         gb_bits + low, tfirst);
       PKLAUNCH("k_pk_tile_first");
     }
     std::vector<uint32_t> htf((size_t)n_tiles + 1);
@@ -537,7 +567,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       PKLAUNCH("k_pk_fill_u32");
       if (NU > 0) {
         hipLaunchKernelGGL(k_pk_region_first, dim3((unsigned)((NU + 255) / 256)), dim3(256), 0, s, skeys, NU, gb_bits,
-                           n_gb, o.reg_first);
+                           low, n_gb, o.reg_first);
         PKLAUNCH("k_pk_region_first");
       }
       std::vector<uint32_t> hrf((size_t)n_reg + 1);
@@ -603,6 +633,65 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       PKLAUNCH("k_pk_fill");
     }
     PK(hipStreamSynchronize(s));
+    // ---- 7. table phases ------------------------------------------------
+    if (in.slot_quads > 0 && ng > 0) {
+      int2* gc = (int2*)tmp((size_t)ng * 8, e2);
+      PK(e2);
+      const int64_t threads = ng * kGroupUnits;
+      hipLaunchKernelGGL(k_pk_group_cells, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, o.desc, o.gcell,
+                         ng, gc);
+      PKLAUNCH("k_pk_group_cells");
+      std::vector<int2> hgc((size_t)ng);
+      std::vector<int32_t> htg((size_t)n_tiles + 1);
+      PK(hipMemcpyAsync(hgc.data(), gc, (size_t)ng * 8, hipMemcpyDeviceToHost, s));
+      PK(hipMemcpyAsync(htg.data(), o.tile_grp, (size_t)(n_tiles + 1) * 4, hipMemcpyDeviceToHost, s));
+      PK(hipStreamSynchronize(s));
+      const int64_t cap = in.slot_quads;
+      std::vector<int4> ph;
+      std::vector<int32_t> poff((size_t)n_tiles + 1, 0);
+      for (int32_t k = 0; k < n_tiles; ++k) {
+        poff[k] = (int32_t)ph.size();
+        int64_t g = htg[k];
+        const int64_t g1 = htg[k + 1];
+        while (g < g1) {
+          // a phase starts at group g and grows while the union of its
+          // groups' cell table ranges fits the slot
+          int64_t lo = INT64_MAX, hi = INT64_MIN;
+          int64_t e = g;
+          for (; e < g1; ++e) {
+            const int2 cc = hgc[(size_t)e];
+            if (cc.x < 0) continue;
+            const int64_t l = std::min(in.cq_lo[cc.x], in.cq_lo[cc.y]), h = std::max(in.cq_hi[cc.x], in.cq_hi[cc.y]);
+            const int64_t nl = std::min(lo, l), nh = std::max(hi, h);
+            if (e > g && nh - nl > cap) break;
+            lo = nl;
+            hi = nh;
+          }
+          if (lo == INT64_MAX) {  // only empty groups: nothing to stage
+            lo = 0;
+            hi = 0;
+          }
+          // a single group whose cells exceed the slot keeps its first cell's
+          // tables (the other lanes read the tables from global memory)
+          if (hi - lo > cap) {
+            const int2 cc = hgc[(size_t)g];
+            lo = in.cq_lo[cc.x];
+            hi = std::min<int64_t>(in.cq_hi[cc.x], lo + cap);
+          }
+          ph.push_back(make_int4((int32_t)(e - htg[k]), (int32_t)lo, (int32_t)(hi - lo), 0));
+          g = e;
+        }
+      }
+      poff[n_tiles] = (int32_t)ph.size();
+      o.n_phases = (int64_t)ph.size();
+      o.phases = (int4*)own(std::max<size_t>(ph.size(), 1) * sizeof(int4), e2);
+      PK(e2);
+      o.ph_off = (int32_t*)own((size_t)(n_tiles + 1) * 4, e2);
+      PK(e2);
+      if (!ph.empty()) PK(hipMemcpyAsync(o.phases, ph.data(), ph.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+      PK(hipMemcpyAsync(o.ph_off, poff.data(), poff.size() * 4, hipMemcpyHostToDevice, s));
+      PK(hipStreamSynchronize(s));
+    }
   }
   for (void* p : temps) (void)hipFree(p);
   o.bytes = held;

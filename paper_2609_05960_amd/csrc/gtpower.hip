@@ -60,8 +60,9 @@ struct gtp_ctx_s {
   int32_t lds_words = 0;
   int32_t mfix = 40;          // energy unit 2^-mfix fJ (see gtp_device.h)
   std::vector<int32_t> h_nin;
+  std::vector<int32_t> h_cq_lo, h_cq_hi;   // per cell: quad index range of its tables
   std::vector<int32_t> h_gate_cell;  // host copy of the netlist's cells
-  DevBuf lib_img;             // meta | map_q | leak | slew | slew_inv
+  DevBuf lib_img;             // meta | leak | map_q | slew | slew_inv
   DevBuf load_axis, load_inv, quads;
 
   // netlist
@@ -275,8 +276,8 @@ LibView lib_view(gtp_ctx c) {
   LibView L;
   const uint32_t* img = ptr<uint32_t>(c->lib_img);
   L.meta = reinterpret_cast<const CellMeta*>(img);
-  L.map_q = reinterpret_cast<const int32_t*>(img + 4 * c->n_cells);
-  L.leak = reinterpret_cast<const float*>(img + 4 * c->n_cells + c->n_map);
+  L.leak = reinterpret_cast<const float*>(img + 4 * c->n_cells);
+  L.map_q = reinterpret_cast<const int32_t*>(img + 4 * c->n_cells + c->n_leak);
   L.slew = reinterpret_cast<const float*>(img + 4 * c->n_cells + c->n_map + c->n_leak);
   L.slew_inv = L.slew + c->n_cells * c->n_slew;
   L.quads = ptr<float4>(c->quads);
@@ -286,6 +287,7 @@ LibView lib_view(gtp_ctx c) {
   L.n_map = c->n_map;
   L.n_leak = c->n_leak;
   L.lds_words = c->lds_words;
+  L.lds_words_ml = 4 * c->n_cells + c->n_leak;
   return L;
 }
 
@@ -370,11 +372,14 @@ int auto_tile_log2(int64_t n_bins, int r_bits) {
 
 size_t lib_lds_bytes(gtp_ctx c) { return (size_t)c->lds_words * 4; }
 
-size_t packed_lds_bytes(gtp_ctx c, int tile_log2) {
-  return (size_t)(((c->lds_words + 1) & ~1) * 4) + ((size_t)16 << tile_log2);
-}
+// LDS of the packed kernels: the library's meta + leakage prefix (rounded to
+// 16 bytes), a tile of bins, and for the forward with table phases two slots.
+size_t ml_lds_bytes(gtp_ctx c) { return packed_bins_word_offset(4 * c->n_cells + c->n_leak) * 4; }
+size_t packed_lds_bytes(gtp_ctx c, int tile_log2) { return ml_lds_bytes(c) + ((size_t)16 << tile_log2); }
+constexpr size_t kSlotBytes = 2 * (size_t)kSlotQuads * 16;
 
 constexpr size_t kMaxLds = 160 * 1024;
+bool slots_fit(gtp_ctx c, int tile_log2) { return packed_lds_bytes(c, tile_log2) + kSlotBytes <= kMaxLds; }
 // Longest unit of the packed layout by default; kernels hold a group's events
 // in registers, 8 or 16 slots per lane. With 16 slots, workgroups of at most
 // 512 threads (the registers of 1024 threads do not fit).
@@ -386,6 +391,9 @@ int slots_of(gtp_ctx c) { return unit_events_of(c) <= 8 ? 8 : 16; }
 // static LDS of the batched kernel (its work-item slot), kept out of the
 // dynamic budget
 constexpr size_t kBatchStaticLds = 64;
+bool batch_slots_fit(gtp_ctx c, int tile_log2) {
+  return packed_lds_bytes(c, tile_log2) + kSlotBytes + kBatchStaticLds <= kMaxLds;
+}
 
 template <class K>
 hipError_t lds_limit(K kern, size_t static_lds = 0) {
@@ -474,6 +482,9 @@ gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, Bin
   in.lib = lib_view(c);
   in.dbg_state = dbg_state;
   in.dbg_bin = dbg_bin;
+  in.cq_lo = c->h_cq_lo;
+  in.cq_hi = c->h_cq_hi;
+  in.slot_quads = kSlotQuads;
   in.unit_events = unit_events_of(c);
   in.gate_block_log2 = c->tun.gate_block_log2 ? c->tun.gate_block_log2 : kGateBlockLog2;
   in.bins = B;
@@ -512,7 +523,16 @@ gtp_status build_pack(gtp_ctx c) {
 
 // LDS of the packed adjoint: the staged library, then two FP32 accumulators
 // per gate of the largest gate block.
-size_t adj_lds_bytes(gtp_ctx c, int32_t max_gb) { return lib_lds_bytes(c) + (size_t)max_gb * 8; }
+// LDS of the packed adjoint: the library prefix, one cell's table quads (as
+// many as fit, at most one slot), two FP32 accumulators per gate of the
+// largest gate block.
+int32_t adj_slot_quads(gtp_ctx c, int32_t max_gb) {
+  const int64_t room = (int64_t)kMaxLds - (int64_t)ml_lds_bytes(c) - 8 * (int64_t)max_gb;
+  return (int32_t)std::max<int64_t>(0, std::min<int64_t>(room / 16, kSlotQuads));
+}
+size_t adj_lds_bytes(gtp_ctx c, int32_t max_gb) {
+  return ml_lds_bytes(c) + 16 * (size_t)adj_slot_quads(c, max_gb) + (size_t)max_gb * 8;
+}
 
 // Work items of the packed adjoint. Entries list, gate block by gate block
 // and tile by tile, the groups holding the block's units with the lane range
@@ -569,7 +589,9 @@ gtp_status adj_plan(gtp_ctx c) {
     const int32_t g = items[i].gb;
     const int64_t ng = pk.h_gb_start[g + 1] - pk.h_gb_start[g];
     if (gb_rows[g] == 0) gb_row[g] = rows;
-    h[i] = AdjItem{g, (int32_t)items[i].e0, (int32_t)items[i].e1, 0, gb_row[g] + gb_rows[g] * ng};
+    const int32_t cell = pk.h_gb_cell[g];
+    const int32_t qn = std::min(c->h_cq_hi[cell] - c->h_cq_lo[cell], adj_slot_quads(c, max_gb));
+    h[i] = AdjItem{g, (int32_t)items[i].e0, (int32_t)items[i].e1, c->h_cq_lo[cell], gb_row[g] + gb_rows[g] * ng, qn, 0};
     gb_rows[g]++;
     rows += ng;
   }
@@ -734,6 +756,7 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
   const int64_t Q = (int64_t)(ns - 1) * (nl - 1);
   if (lib->n_tables * Q >= (int64_t)INT32_MAX) return fail(c, GTP_ERR_UNSUPPORTED, "tables too large");
   std::vector<CellMeta> meta(nc);
+  std::vector<int32_t> cq_lo(nc), cq_hi(nc);   // quads of each cell's tables
   std::vector<int32_t> mapq;
   std::vector<float> leak;
   float leak_max = 0.f;
@@ -754,12 +777,17 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
     meta[cc].map_off = (int32_t)mapq.size();
     meta[cc].leak_off = (int32_t)leak.size();
     meta[cc].axis_off = cc * ns;
+    int64_t t_lo = INT64_MAX, t_hi = -1;
     for (int64_t e = 0; e < 2 * nst; ++e) {
       const int64_t k = lib->state_to_table[mb + e];
       if (k < 0 || tb + k >= lib->n_tables)
         return fail(c, GTP_ERR_INVALID_ARG, "cell %d: table id %lld out of range", cc, (long long)k);
       mapq.push_back((int32_t)((tb + k) * Q));
+      t_lo = std::min(t_lo, tb + k);
+      t_hi = std::max(t_hi, tb + k);
     }
+    cq_lo[cc] = (int32_t)(t_lo * Q);
+    cq_hi[cc] = (int32_t)((t_hi + 1) * Q);
     for (int64_t s = 0; s < nst; ++s) {
       const float v = lib->leak_nw[lbs + s];
       if (!(v >= 0.f) || !std::isfinite(v)) return fail(c, GTP_ERR_INVALID_ARG, "cell %d: bad leakage value", cc);
@@ -777,8 +805,8 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
                 (long long)(words * 4));
   std::vector<uint32_t> img((size_t)words);
   memcpy(img.data(), meta.data(), sizeof(CellMeta) * nc);
-  memcpy(img.data() + 4 * nc, mapq.data(), 4 * (size_t)n_map);
-  memcpy(img.data() + 4 * nc + n_map, leak.data(), 4 * (size_t)n_leak);
+  memcpy(img.data() + 4 * nc, leak.data(), 4 * (size_t)n_leak);
+  memcpy(img.data() + 4 * nc + n_leak, mapq.data(), 4 * (size_t)n_map);
   float* slew = reinterpret_cast<float*>(img.data() + 4 * nc + n_map + n_leak);
   float* slew_inv = slew + (size_t)nc * ns;
   std::vector<float> load((size_t)nc * nl), load_inv((size_t)nc * nl, 0.f);
@@ -825,6 +853,8 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
   c->n_tables = lib->n_tables;
   c->lds_words = (int32_t)words;
   c->h_nin.assign(lib->n_inputs, lib->n_inputs + nc);
+  c->h_cq_lo = cq_lo;
+  c->h_cq_hi = cq_hi;
   // fixed-point exponent m: a quantised rate lambda*leak*2^m*1e-6 must stay
   // below 2^30; m <= 40 keeps event energies up to 2^23 fJ exact in int64
   const double top = (double)GTP_MAX_LEAK_SCALE * std::max(leak_max, 1e-3f);
@@ -1107,7 +1137,10 @@ gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, in
   a.bins = B;
   a.X = X;
   a.S = S;
-  const size_t lds = packed_lds_bytes(c, B.tile_log2);
+  const bool ph = pk.phases && slots_fit(c, B.tile_log2);
+  a.phases = ph ? pk.phases : nullptr;
+  a.ph_off = ph ? pk.ph_off : nullptr;
+  const size_t lds = packed_lds_bytes(c, B.tile_log2) + (ph ? kSlotBytes : 0);
   const int sl = slots_of(c);
   const int th = threads_for_slots(tile_threads(c), sl);
   const dim3 grid((unsigned)B.n_tiles);
@@ -1187,7 +1220,10 @@ gtp_status build_batch(gtp_ctx c) {
       return st;
     }
     t.bin_off = off;
-    tab[i] = TraceDev{t.pk.w32, t.pk.row, t.pk.alpha, t.pk.desc, t.pk.grp_off, t.pk.tile_grp, t.bins, off};
+    const bool ph = t.pk.phases && batch_slots_fit(c, lb);
+    tab[i] = TraceDev{t.pk.w32,          t.pk.row,  t.pk.alpha,      ph ? t.pk.phases : nullptr,
+                      ph ? t.pk.ph_off : nullptr, t.pk.desc, t.pk.grp_off, t.pk.tile_grp,
+                      t.bins,            off};
     fin[i] = FinTrace{off, t.bins.n_bins, t.bins.t_end};
     off += t.bins.n_bins;
     // events per tile, for the largest-first order
@@ -1240,7 +1276,7 @@ gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_s
     a.queue = ptr<unsigned long long>(c->b_queue);
     a.X = ptr<int64_t>(c->b_X);
     a.S = ptr<int64_t>(c->b_S);
-    const size_t lds = packed_lds_bytes(c, lb);
+    const size_t lds = packed_lds_bytes(c, lb) + (batch_slots_fit(c, lb) ? kSlotBytes : 0);
     const int sl = slots_of(c);
     const int th = threads_for_slots(tile_threads(c), sl);
     // resident workgroups: as many as fit (LDS-limited), at most one per item
@@ -1605,6 +1641,7 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       a.wg = ptr<float2>(c->adj_wg);
       a.dsw_rise = dsw_rise;
       a.dsw_fall = dsw_fall;
+      a.slot_quads = adj_slot_quads(c, c->adj_max_gb);
       if (slots_of(c) == 8) {
         LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<1024, 8>), dim3((unsigned)c->adj_n_items), dim3(1024),
                adj_lds_bytes(c, c->adj_max_gb), a);
