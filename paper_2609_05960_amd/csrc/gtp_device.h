@@ -78,12 +78,14 @@ struct LibView {
   const CellMeta* meta;     // [n_cells]
   const int32_t* map_q;     // [n_map] first quad index of the table
   const float* leak;        // [n_leak]
+  const float* load;        // [n_cells * n_load]
+  const float* load_inv;    // [n_cells * n_load]
   const float* slew;        // [n_cells * n_slew]
   const float* slew_inv;    // [n_cells * n_slew] 1/(S[i+1]-S[i]) (last unused)
   const float4* quads;      // [n_tables * (n_slew-1) * (n_load-1)]
   int32_t n_cells, n_slew, n_load, n_map, n_leak;
   int32_t lds_words;        // 32-bit words of the LDS image
-  int32_t lds_words_ml;     // words of its meta + leakage prefix
+  int32_t lds_words_ml;     // words of its meta, leakage and load-axis prefix
 };
 
 // Prepared gate record (32 bytes), gate-major kernels.
@@ -99,15 +101,16 @@ struct GatePrep {
 };
 static_assert(sizeof(GatePrep) == 32, "GatePrep is two 16-byte loads");
 
-// Per-gate parameters of the packed forward (16 bytes), indexed by the
-// cell-sorted gate index; esw_fall = esw_rise (sw_mode 0) or 0 (sw_mode 1).
+// Per-call gate record of the packed kernels (8 bytes), indexed by the
+// cell-sorted gate index: the load of the gate's output net and its leakage
+// scale. The load-axis segment, its weight and the switching energies follow
+// from the load and the cell (unit_lut), which keeps the record, gathered
+// once per unit, to half a 16-byte vector.
 struct GateParam {
-  float beta;
+  float C;
   float lam;
-  float esw_rise;
-  uint32_t cell_jq;   // cell << 8 | jq
 };
-static_assert(sizeof(GateParam) == 16, "GateParam is one 16-byte load");
+static_assert(sizeof(GateParam) == 8, "GateParam is one 8-byte load");
 
 // Unsigned division of a 32-bit value by an invariant divisor (Granlund and
 // Montgomery, "Division by invariant integers using multiplication", PLDI
@@ -139,11 +142,14 @@ __device__ __forceinline__ int64_t bin_of(int64_t t, const BinSpec& B) {
   return t / B.D;
 }
 
-// LDS image of the library: meta | leak | map_q | slew | slew_inv (words).
+// LDS image of the library: meta | leak | load | load_inv | map_q | slew |
+// slew_inv (words).
 struct LdsLib {
   const CellMeta* meta;
   const int32_t* map_q;
   const float* leak;
+  const float* load;       // [n_cells * n_load] load axes
+  const float* load_inv;   // [n_cells * n_load] 1/(L[j+1]-L[j]) (last unused)
   const float* slew;
   const float* slew_inv;
 };
@@ -152,27 +158,59 @@ __device__ __forceinline__ LdsLib stage_library(const LibView& L, uint32_t* lds)
   // the image is contiguous in global memory in the same order: copy words
   const uint32_t* src = reinterpret_cast<const uint32_t*>(L.meta);
   for (int w = threadIdx.x; w < L.lds_words; w += blockDim.x) lds[w] = src[w];
+  const int32_t nl = L.n_cells * L.n_load;
   LdsLib S;
   S.meta = reinterpret_cast<const CellMeta*>(lds);
   S.leak = reinterpret_cast<const float*>(lds + 4 * L.n_cells);
-  S.map_q = reinterpret_cast<const int32_t*>(lds + 4 * L.n_cells + L.n_leak);
-  S.slew = reinterpret_cast<const float*>(lds + 4 * L.n_cells + L.n_map + L.n_leak);
+  S.load = S.leak + L.n_leak;
+  S.load_inv = S.load + nl;
+  S.map_q = reinterpret_cast<const int32_t*>(S.load_inv + nl);
+  S.slew = reinterpret_cast<const float*>(S.map_q + L.n_map);
   S.slew_inv = S.slew + L.n_cells * L.n_slew;
   return S;
 }
 
-// Only the cell records and leakage values (the prefix of the image): all the
-// packed kernels read from the library.
+// Only the prefix of the image (cell records, leakage values, load axes):
+// all the packed kernels read from the library.
 __device__ __forceinline__ LdsLib stage_library_ml(const LibView& L, uint32_t* lds) {
   const uint32_t* src = reinterpret_cast<const uint32_t*>(L.meta);
   for (int w = threadIdx.x; w < L.lds_words_ml; w += blockDim.x) lds[w] = src[w];
+  const int32_t nl = L.n_cells * L.n_load;
   LdsLib S;
   S.meta = reinterpret_cast<const CellMeta*>(lds);
   S.leak = reinterpret_cast<const float*>(lds + 4 * L.n_cells);
+  S.load = S.leak + L.n_leak;
+  S.load_inv = S.load + nl;
   S.map_q = nullptr;
   S.slew = nullptr;
   S.slew_inv = nullptr;
   return S;
+}
+
+// What a unit's gate needs for its events, from its output load C and cell:
+// the load-axis segment j = clamp(#knots <= C - 1, 0, n_load - 2), its weight
+// beta, d(beta)/dC, and the switching energies of an output rise and fall
+// (sw_mode 0: 0.5 C V^2 on both; 1: C V^2 on a rise only). Rounded exactly
+// as the gate-major kernels round them.
+struct UnitLut {
+  uint32_t jq;
+  float beta;
+  float dbdc;
+  float esw_rise, esw_fall;
+};
+
+__device__ __forceinline__ UnitLut unit_lut(const LdsLib& L, int32_t n_load, int cell, float C, double v2,
+                                            int32_t sw_mode) {
+  const float* la = L.load + cell * n_load;
+  int j = 0;
+  for (int m = 1; m < n_load - 1; ++m) j += (la[m] <= C) ? 1 : 0;
+  UnitLut u;
+  u.jq = (uint32_t)j;
+  u.dbdc = L.load_inv[cell * n_load + j];
+  u.beta = __fmul_rn(__fsub_rn(C, la[j]), u.dbdc);
+  u.esw_rise = (sw_mode == 0) ? (float)(0.5 * (double)C * v2) : (float)((double)C * v2);
+  u.esw_fall = sw_mode ? 0.0f : u.esw_rise;
+  return u;
 }
 
 // Quantised leakage rate of a state (units R = 1e6 * 2^-m nW; rate_scale =

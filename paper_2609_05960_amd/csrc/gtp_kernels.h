@@ -91,6 +91,7 @@ struct PackedFwdArgs {
   LutArgs lut;
   BinSpec bins;
   int32_t sw_mode;
+  double v2;                 // Vdd^2
   int64_t* X;
   int64_t* S;
   const int4* phases;        // table phases (null: every quad from global memory)
@@ -130,7 +131,8 @@ __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int
   if (valid && mine) {
     G.gp = a.gparam[d.x & 0x0fffffffu];
   } else {
-    G.gp.beta = 0.f; G.gp.lam = 0.f; G.gp.esw_rise = 0.f; G.gp.cell_jq = 0u;
+    G.gp.C = 0.f;
+    G.gp.lam = 0.f;
   }
   // the offset is the same on every lane: keep it scalar so the loads use a
   // scalar base and a 32-bit lane offset
@@ -183,9 +185,10 @@ __device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsL
   const float4* __restrict__ quads = a.lut.quads;
   const int len = G.len;
   const GateParam gp = G.gp;
-  const uint32_t jq = gp.cell_jq & 0xffu;
-  const CellMeta cm = L.meta[gp.cell_jq >> 8];
-  const float esw_fall = a.sw_mode ? 0.0f : gp.esw_rise;
+  const int cell = (int)(G.d.y >> 16);
+  const UnitLut u = unit_lut(L, a.lut.n_load, cell, gp.C, a.v2, a.sw_mode);
+  const uint32_t jq = u.jq;
+  const CellMeta cm = L.meta[cell];
   const float* lk = L.leak + cm.leak_off;
   int32_t q_cur = qrate(gp.lam, lk[G.d.y & ((1u << cm.n_in) - 1u)], a.lut.rate_scale);
   struct Pre {
@@ -205,8 +208,8 @@ __device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsL
       const uint32_t rv = G.rv[kk];
       if (kk + 1 < kS && len > kk + 1) prefetch(kk + 1, pre[(kk + 1) & 1]);
       const Pre& P = pre[kk & 1];
-      float e = bilerp_quad(P.q, G.av[kk], gp.beta);
-      if (rv & (1u << kOutBit)) e = __fadd_rn(e, (rv >> 31) ? gp.esw_rise : esw_fall);
+      float e = bilerp_quad(P.q, G.av[kk], u.beta);
+      if (rv & (1u << kOutBit)) e = __fadd_rn(e, (rv >> 31) ? u.esw_rise : u.esw_fall);
       int64_t x = energy_fixed(e, a.lut.two_sh);
       const uint32_t tl = w & kTimeMask;
       const uint32_t bl = tl >> B.r_bits;
@@ -429,8 +432,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
   }
 }
 
-// Per-call gate parameters in cell-sorted order, plus the sum of the gates'
-// quantised initial leakage rates.
+// Per-call gate records (output load, leakage scale) in cell-sorted order,
+// plus the sum of the gates' quantised initial leakage rates.
 struct GateParamArgs {
   const int32_t* gperm;      // sorted index -> gate
   const int32_t* gcell;      // sorted index -> cell
@@ -440,12 +443,7 @@ struct GateParamArgs {
   const float* leak_scale;   // may be null (all 1)
   const CellMeta* meta;
   const float* leak;
-  const float* load;         // [n_cells * n_load]
-  const float* load_inv;
-  int32_t n_load;
   int64_t n_gates;
-  double vdd;
-  int32_t sw_mode;
   float rate_scale;
   float max_scale;
   GateParam* out;
@@ -467,16 +465,9 @@ __global__ void __launch_bounds__(256) k_gate_params(GateParamArgs a) {
       atomicOr(a.flag, 1);
       lam = 0.0f;
     }
-    const float* la = a.load + (int64_t)c * a.n_load;
-    int j = 0;
-    for (int m = 1; m < a.n_load - 1; ++m) j += (la[m] <= C) ? 1 : 0;
-    const float inv = a.load_inv[(int64_t)c * a.n_load + j];
     GateParam p;
-    p.beta = __fmul_rn(__fsub_rn(C, la[j]), inv);
-    const double v2 = a.vdd * a.vdd;
-    p.esw_rise = (a.sw_mode == 0) ? (float)(0.5 * (double)C * v2) : (float)((double)C * v2);
+    p.C = C;
     p.lam = lam;
-    p.cell_jq = ((uint32_t)c << 8) | (uint32_t)j;
     a.out[gs] = p;
     const uint32_t s0 = a.gate_init[g] & ((1u << cm.n_in) - 1u);
     q0 = (long long)qrate(lam, a.leak[cm.leak_off + (int)s0], a.rate_scale);
@@ -827,8 +818,6 @@ struct AdjPackedArgs {
   const AdjItem* items;
   const int32_t* gb_start;    // [n_gb + 1] first sorted gate of each gate block
   float2* part;               // partial table: per item and gate (load, leakage)
-  const float* load_inv;      // [n_cells * n_load]
-  int32_t n_load;
   int32_t last_w;             // width of the last bin (ps)
   const float2* wg;           // [n_bins] (w_b, G_b)
   float dsw_rise, dsw_fall;
@@ -849,10 +838,11 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
   const float4* __restrict__ quads = a.f.lut.quads;
   const int len = mine ? G.len : 0;
   const GateParam gp = G.gp;
-  const int cell = (int)(gp.cell_jq >> 8);
-  const int jq = (int)(gp.cell_jq & 0xffu);
+  const int cell = (int)(G.d.y >> 16);
+  const UnitLut u = unit_lut(L, a.f.lut.n_load, cell, gp.C, a.f.v2, a.f.sw_mode);
+  const uint32_t jq = u.jq;
   const CellMeta cm = L.meta[cell];
-  const float dbdc = len > 0 ? a.load_inv[cell * a.n_load + jq] : 0.f;
+  const float dbdc = len > 0 ? u.dbdc : 0.f;
   const float* lk = L.leak + cm.leak_off;
   const int64_t tile_b0 = (int64_t)tile << B.tile_log2;
   float lk_cur = lk[G.d.y & ((1u << cm.n_in) - 1u)];

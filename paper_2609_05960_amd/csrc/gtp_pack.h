@@ -32,8 +32,8 @@
 //   alpha[n]  slew weight (FP32)
 //   desc[64 * n_groups]   unit descriptor: x = cell-sorted gate index
 //             (bits 0..27) | (length-1) << 28, y = pin values before the
-//             unit's first event (bits 0..15) | before its timestamp group
-//             (bits 16..31); x = 0xffffffff for an empty lane
+//             unit's first event (bits 0..15) | the gate's cell << 16;
+//             x = 0xffffffff for an empty lane
 //   dsrc[64 * n_groups]   gate-major index of the unit's first event (for
 //             the per-event debug trace only)
 //   grp_off[n_groups + 1] first event of each group

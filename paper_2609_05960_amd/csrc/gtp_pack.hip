@@ -243,10 +243,12 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
   const bool act = j < (int64_t)a.tfirst[k + 1];
   UnitRec r{-1, 0xffffffffu, 0u};
   if (act) r = a.recs[a.sidx[j]];
-  a.desc[gi * kGroupUnits + lane] = make_uint2(r.x, r.y);
+  const int cell = act ? a.gcell[r.x & 0x0fffffffu] : 0;
+  // descriptor: y = pin values before the unit's first event | cell << 16
+  a.desc[gi * kGroupUnits + lane] = make_uint2(r.x, (r.y & 0xffffu) | ((uint32_t)cell << 16));
   a.dsrc[gi * kGroupUnits + lane] = r.src;
   const int len = act ? (int)(r.x >> 28) + 1 : 0;
-  const CellMeta cm = a.lib.meta[act ? a.gcell[r.x & 0x0fffffffu] : 0];
+  const CellMeta cm = a.lib.meta[cell];
   const uint32_t in_mask = (1u << cm.n_in) - 1u;
   const float* axis = a.lib.slew + cm.axis_off;
   const float* inv = a.lib.slew_inv + cm.axis_off;

@@ -276,9 +276,12 @@ LibView lib_view(gtp_ctx c) {
   LibView L;
   const uint32_t* img = ptr<uint32_t>(c->lib_img);
   L.meta = reinterpret_cast<const CellMeta*>(img);
+  const int32_t nl = c->n_cells * c->n_load;
   L.leak = reinterpret_cast<const float*>(img + 4 * c->n_cells);
-  L.map_q = reinterpret_cast<const int32_t*>(img + 4 * c->n_cells + c->n_leak);
-  L.slew = reinterpret_cast<const float*>(img + 4 * c->n_cells + c->n_map + c->n_leak);
+  L.load = L.leak + c->n_leak;
+  L.load_inv = L.load + nl;
+  L.map_q = reinterpret_cast<const int32_t*>(L.load_inv + nl);
+  L.slew = reinterpret_cast<const float*>(L.map_q + c->n_map);
   L.slew_inv = L.slew + c->n_cells * c->n_slew;
   L.quads = ptr<float4>(c->quads);
   L.n_cells = c->n_cells;
@@ -287,7 +290,7 @@ LibView lib_view(gtp_ctx c) {
   L.n_map = c->n_map;
   L.n_leak = c->n_leak;
   L.lds_words = c->lds_words;
-  L.lds_words_ml = 4 * c->n_cells + c->n_leak;
+  L.lds_words_ml = 4 * c->n_cells + c->n_leak + 2 * nl;
   return L;
 }
 
@@ -374,7 +377,9 @@ size_t lib_lds_bytes(gtp_ctx c) { return (size_t)c->lds_words * 4; }
 
 // LDS of the packed kernels: the library's meta + leakage prefix (rounded to
 // 16 bytes), a tile of bins, and for the forward with table phases two slots.
-size_t ml_lds_bytes(gtp_ctx c) { return packed_bins_word_offset(4 * c->n_cells + c->n_leak) * 4; }
+size_t ml_lds_bytes(gtp_ctx c) {
+  return packed_bins_word_offset(4 * c->n_cells + c->n_leak + 2 * c->n_cells * c->n_load) * 4;
+}
 size_t packed_lds_bytes(gtp_ctx c, int tile_log2) { return ml_lds_bytes(c) + ((size_t)16 << tile_log2); }
 constexpr size_t kSlotBytes = 2 * (size_t)kSlotQuads * 16;
 
@@ -799,15 +804,17 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
     if (!std::isfinite(lib->tables_fj[i])) return fail(c, GTP_ERR_INVALID_ARG, "non-finite table entry %lld",
                                                        (long long)i);
   const int32_t n_map = (int32_t)mapq.size(), n_leak = (int32_t)leak.size();
-  const int64_t words = 4ll * nc + n_map + n_leak + 2ll * nc * ns;
+  const int64_t words = 4ll * nc + n_leak + 2ll * nc * nl + n_map + 2ll * nc * ns;
   if (words * 4 > 48 * 1024)
     return fail(c, GTP_ERR_UNSUPPORTED, "library image of %lld bytes exceeds the 48 KB LDS budget",
                 (long long)(words * 4));
   std::vector<uint32_t> img((size_t)words);
   memcpy(img.data(), meta.data(), sizeof(CellMeta) * nc);
   memcpy(img.data() + 4 * nc, leak.data(), 4 * (size_t)n_leak);
-  memcpy(img.data() + 4 * nc + n_leak, mapq.data(), 4 * (size_t)n_map);
-  float* slew = reinterpret_cast<float*>(img.data() + 4 * nc + n_map + n_leak);
+  float* load_img = reinterpret_cast<float*>(img.data() + 4 * nc + n_leak);
+  float* load_inv_img = load_img + (size_t)nc * nl;
+  memcpy(load_inv_img + (size_t)nc * nl, mapq.data(), 4 * (size_t)n_map);
+  float* slew = reinterpret_cast<float*>(load_inv_img + (size_t)nc * nl + n_map);
   float* slew_inv = slew + (size_t)nc * ns;
   std::vector<float> load((size_t)nc * nl), load_inv((size_t)nc * nl, 0.f);
   for (int cc = 0; cc < nc; ++cc) {
@@ -824,6 +831,8 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
                        : 0.f;
     }
   }
+  std::copy(load.begin(), load.end(), load_img);
+  std::copy(load_inv.begin(), load_inv.end(), load_inv_img);
   // quads: (T[i][j], T[i][j+1], T[i+1][j], T[i+1][j+1]) per table and axis cell
   std::vector<float> quads((size_t)(lib->n_tables * Q * 4));
   for (int64_t T = 0; T < lib->n_tables; ++T) {
@@ -1094,12 +1103,7 @@ gtp_status gate_params_for(gtp_ctx c, const PackOut& pk, const float* net_load, 
   a.leak_scale = leak_scale;
   a.meta = L.meta;
   a.leak = L.leak;
-  a.load = ptr<float>(c->load_axis);
-  a.load_inv = ptr<float>(c->load_inv);
-  a.n_load = c->n_load;
   a.n_gates = c->n_gates;
-  a.vdd = c->par.vdd;
-  a.sw_mode = c->par.sw_mode;
   a.rate_scale = (float)(std::ldexp(1.0, c->mfix) * 1e-6);
   a.max_scale = GTP_MAX_LEAK_SCALE;
   a.out = ptr<GateParam>(c->gparam);
@@ -1120,6 +1124,7 @@ PackedFwdArgs packed_common(gtp_ctx c) {
   a.lib = lib_view(c);
   a.lut = lut_args(c);
   a.sw_mode = c->par.sw_mode;
+  a.v2 = c->par.vdd * c->par.vdd;
   return a;
 }
 
@@ -1635,8 +1640,6 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       a.items = ptr<AdjItem>(c->adj_items);
       a.gb_start = ptr<int32_t>(c->adj_gbs);
       a.part = ptr<float2>(c->adj_part);
-      a.load_inv = ptr<float>(c->load_inv);
-      a.n_load = c->n_load;
       a.last_w = (int32_t)(c->bins.t_end - (c->bins.n_bins - 1) * c->bins.D);
       a.wg = ptr<float2>(c->adj_wg);
       a.dsw_rise = dsw_rise;
