@@ -164,12 +164,24 @@ __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int
 }
 
 // Table quad of a lane's event: from the phase's LDS slot when the quad lies
-// in its range [lo, lo + n), else from global memory.
-__device__ __forceinline__ float4 quad_at(const float4* __restrict__ quads, const float4* slot, uint32_t lo,
+// in its range [lo, lo + n), else from global memory. The slot read is
+// unconditional (clamped index) through an LDS pointer and the global read is
+// predicated, so the two stay an LDS and a global load rather than being
+// merged into one flat load.
+// (The fallback is a non-temporal load: it differs from the slot load, so the
+// optimiser cannot sink the two into one load through a selected pointer.)
+typedef float quad_vec __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) quad_vec lds_float4;
+
+__device__ __forceinline__ const lds_float4* lds_ptr(const float4* p) { return (const lds_float4*)p; }
+
+__device__ __forceinline__ float4 quad_at(const float4* __restrict__ quads, const lds_float4* slot, uint32_t lo,
                                           uint32_t n, uint32_t qi) {
   const uint32_t li = qi - lo;
-  if (li < n) return slot[li];
-  return quads[qi];
+  const bool in = li < n;
+  quad_vec v = slot[in ? li : 0u];
+  if (!in) v = __builtin_nontemporal_load(reinterpret_cast<const quad_vec*>(quads) + qi);
+  return make_float4(v.x, v.y, v.z, v.w);
 }
 
 // Accumulates one group (loaded into G) into the tile's LDS bins. The table
@@ -177,7 +189,7 @@ __device__ __forceinline__ float4 quad_at(const float4* __restrict__ quads, cons
 // k is accumulated from the other.
 template <int kS>
 __device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsLib& L, const GroupRegs<kS>& G,
-                                              unsigned long long* xs, unsigned long long* ss, const float4* slot,
+                                              unsigned long long* xs, unsigned long long* ss, const lds_float4* slot,
                                               uint32_t lo, uint32_t n) {
   const BinSpec& B = a.bins;
   const uint32_t rmask = (1u << B.r_bits) - 1u;
@@ -292,6 +304,9 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
   const BinSpec& B = a.bins;
   const int nb = 1 << B.tile_log2;
   for (int i = threadIdx.x; i < 2 * nb; i += kThreads) xs[i] = 0ull;
+  // without phases every quad comes from global memory; the slot reads of
+  // quad_at then touch the bins (any valid LDS address) and are discarded
+  float4* const lds_slots = slots ? slots : reinterpret_cast<float4*>(xs);
   const int64_t g0 = a.tile_grp[tile];
   const int64_t g1 = a.tile_grp[tile + 1];
   const int lane = (int)(threadIdx.x & 63);
@@ -337,12 +352,12 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
   while (gi < g1) {
     while (gi >= P.ge) phase_advance<kThreads>(a, P, slots, g0);
     if (gi + nwave < g1) issue(gi + nwave, gb);
-    process_group(a, L, ga, xs, ss, slots + (P.ph & 1) * kSlotQuads, P.lo, P.n);
+    process_group(a, L, ga, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * kSlotQuads), P.lo, P.n);
     gi += nwave;
     if (gi >= g1) break;
     while (gi >= P.ge) phase_advance<kThreads>(a, P, slots, g0);
     if (gi + nwave < g1) issue(gi + nwave, ga);
-    process_group(a, L, gb, xs, ss, slots + (P.ph & 1) * kSlotQuads, P.lo, P.n);
+    process_group(a, L, gb, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * kSlotQuads), P.lo, P.n);
     gi += nwave;
   }
   while (P.ph + 1 < P.ph1) phase_advance<kThreads>(a, P, slots, g0);  // boundaries after this wavefront's last group
@@ -853,12 +868,7 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
   };
   auto prefetch = [&](int k, Pre& P) {
     const uint32_t w = G.wv[k];
-    const uint32_t qi = (G.rv[k] & kRowMask) + (uint32_t)jq;
-    if (qi - q_lo < q_n) {
-      P.q = tab[qi - q_lo];
-    } else {
-      P.q = quads[qi];
-    }
+    P.q = quad_at(quads, lds_ptr(tab), q_lo, q_n, (G.rv[k] & kRowMask) + (uint32_t)jq);
     P.lk_after = lk[w >> kStateShift];
     P.wg = a.wg[tile_b0 + (int64_t)((w & kTimeMask) >> B.r_bits)];
   };
