@@ -39,7 +39,11 @@ WORKLOADS = {
 }
 
 
-KERNEL_SOURCES = ("paper_2609_05960_amd/csrc/gtp_kernels.h", "paper_2609_05960_amd/csrc/gtp_device.h")
+# sources that decide a kernel's memory traffic: the kernels, the packed
+# layout and the host's launch configuration
+KERNEL_SOURCES = ("paper_2609_05960_amd/csrc/gtp_kernels.h", "paper_2609_05960_amd/csrc/gtp_device.h",
+                  "paper_2609_05960_amd/csrc/gtp_pack.h", "paper_2609_05960_amd/csrc/gtp_pack.hip",
+                  "paper_2609_05960_amd/csrc/gtpower.hip")
 
 
 def kernel_source_hash() -> str:
