@@ -822,7 +822,7 @@ struct AdjItem {
   int32_t gb;       // gate block
   int32_t e0, e1;   // entries [e0, e1)
   int32_t q_lo;     // table quads [q_lo, q_lo + q_n) staged in LDS (the block's cell)
-  int64_t row;      // first element of the item's row in the partial table
+  int64_t row;      // first element of the item's row in the partial table (-1: padding, no work)
   int32_t q_n;
   int32_t pad;
 };
@@ -904,8 +904,9 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
 template <int kThreads, int kS>
 __global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
   extern __shared__ uint32_t lds[];
-  const LdsLib L = stage_library_ml(a.f.lib, lds);
   const AdjItem it = a.items[blockIdx.x];
+  if (it.row < 0) return;  // padding item (the whole workgroup leaves)
+  const LdsLib L = stage_library_ml(a.f.lib, lds);
   const int32_t gs0 = a.gb_start[it.gb];
   const int32_t ng = a.gb_start[it.gb + 1] - gs0;
   float4* tab = reinterpret_cast<float4*>(lds + packed_bins_word_offset(a.f.lib.lds_words_ml));

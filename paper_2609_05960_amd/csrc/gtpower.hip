@@ -389,6 +389,7 @@ bool slots_fit(gtp_ctx c, int tile_log2) { return packed_lds_bytes(c, tile_log2)
 // in registers, 8 or 16 slots per lane. With 16 slots, workgroups of at most
 // 512 threads (the registers of 1024 threads do not fit).
 constexpr int kDefaultUnitEvents = 8;
+constexpr int kXcds = 8;   // XCDs of the MI355X: workgroup i runs on XCD i % 8
 int threads_for_slots(int th, int slots) { return (slots == 16 && th > 512) ? 512 : th; }
 int unit_events_of(gtp_ctx c) { return c->tun.unit_events ? c->tun.unit_events : kDefaultUnitEvents; }
 int slots_of(gtp_ctx c) { return unit_events_of(c) <= 8 ? 8 : 16; }
@@ -541,8 +542,8 @@ size_t adj_lds_bytes(gtp_ctx c, int32_t max_gb) {
 
 // Work items of the packed adjoint. Entries list, gate block by gate block
 // and tile by tile, the groups holding the block's units with the lane range
-// of those units; an item is a run of one block's entries covering whole
-// tiles and about total / (3 * CUs) events, and items run largest first.
+// of those units; an item is one block's entries over one of the tile ranges
+// shared by all blocks (about three items per CU in all).
 gtp_status adj_plan(gtp_ctx c) {
   if (c->adj_ok) return GTP_OK;
   const PackOut& pk = c->pk;
@@ -559,30 +560,39 @@ gtp_status adj_plan(gtp_ctx c) {
   for (int32_t g = 0; g < n_gb; ++g) max_gb = std::max(max_gb, pk.h_gb_start[g + 1] - pk.h_gb_start[g]);
   int64_t total = 0;
   for (int64_t e : pk.h_reg_events) total += e;
-  const int64_t target = std::max<int64_t>(total / (3 * (int64_t)std::max(c->n_cu, 1)), 2048);
-  struct Item { int64_t ev; int32_t gb; int64_t e0, e1; };
+  // tile ranges shared by every gate block, about three items per CU in all
+  int32_t active_gb = 0;
+  for (int32_t g = 0; g < n_gb; ++g) {
+    int64_t e = 0;
+    for (int32_t k = 0; k < n_tiles; ++k) e += pk.h_reg_events[(size_t)k * n_gb + g];
+    if (e > 0) ++active_gb;
+  }
+  const int64_t want = 3 * (int64_t)std::max(c->n_cu, 1);
+  int64_t nr = (want + std::max(active_gb, 1) - 1) / std::max(active_gb, 1);
+  nr = (nr + kXcds - 1) / kXcds * kXcds;  // a multiple of the XCD count
+  const int32_t n_rng = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n_tiles, nr));
+  const int32_t rng_tiles = (n_tiles + n_rng - 1) / n_rng;
+  struct Item { int64_t ev; int32_t gb, rng; int64_t e0, e1; };
   std::vector<Item> items;
   std::vector<int4> ent;
   for (int32_t g = 0; g < n_gb; ++g) {
-    int64_t acc = 0, e0 = (int64_t)ent.size();
-    for (int32_t k = 0; k < n_tiles; ++k) {
-      const int64_t r = (int64_t)k * n_gb + g;
-      const int64_t j0 = rf[r], j1 = rf[r + 1];
-      if (j0 >= j1) continue;
-      const int64_t t0 = tf[k];
-      for (int64_t q = (j0 - t0) / kGroupUnits; q <= (j1 - 1 - t0) / kGroupUnits; ++q) {
-        const int64_t u0 = t0 + q * kGroupUnits;
-        const int lo = (int)std::max<int64_t>(j0 - u0, 0), hi = (int)std::min<int64_t>(j1 - u0, kGroupUnits);
-        ent.push_back(make_int4((int32_t)(tg[k] + q), k, lo | (hi << 8), 0));
+    for (int32_t k0 = 0; k0 < n_tiles; k0 += rng_tiles) {
+      const int64_t e0 = (int64_t)ent.size();
+      int64_t acc = 0;
+      for (int32_t k = k0; k < std::min(n_tiles, k0 + rng_tiles); ++k) {
+        const int64_t r = (int64_t)k * n_gb + g;
+        const int64_t j0 = rf[r], j1 = rf[r + 1];
+        if (j0 >= j1) continue;
+        const int64_t t0 = tf[k];
+        for (int64_t q = (j0 - t0) / kGroupUnits; q <= (j1 - 1 - t0) / kGroupUnits; ++q) {
+          const int64_t u0 = t0 + q * kGroupUnits;
+          const int lo = (int)std::max<int64_t>(j0 - u0, 0), hi = (int)std::min<int64_t>(j1 - u0, kGroupUnits);
+          ent.push_back(make_int4((int32_t)(tg[k] + q), k, lo | (hi << 8), 0));
+        }
+        acc += pk.h_reg_events[(size_t)r];
       }
-      acc += pk.h_reg_events[(size_t)r];
-      if (acc >= target) {
-        items.push_back({acc, g, e0, (int64_t)ent.size()});
-        acc = 0;
-        e0 = (int64_t)ent.size();
-      }
+      if ((int64_t)ent.size() > e0) items.push_back({acc, g, k0 / rng_tiles, e0, (int64_t)ent.size()});
     }
-    if ((int64_t)ent.size() > e0) items.push_back({acc, g, e0, (int64_t)ent.size()});
   }
   if ((int64_t)ent.size() >= ((int64_t)1 << 31)) return fail(c, GTP_ERR_UNSUPPORTED, "too many adjoint entries");
   // rows of the partial table: a block's items get consecutive rows
@@ -600,11 +610,27 @@ gtp_status adj_plan(gtp_ctx c) {
     gb_rows[g]++;
     rows += ng;
   }
-  std::vector<int32_t> order(items.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return items[a].ev > items[b].ev; });
-  std::vector<AdjItem> hs(h.size());
-  for (size_t i = 0; i < order.size(); ++i) hs[i] = h[order[i]];
+  // launch order: workgroup i runs on XCD i % kXcds, and tile range r is
+  // given to XCD r % kXcds, taken range by range (largest items first within
+  // a range): the items resident on one XCD read the bin weights of about one
+  // tile range, which then stays in that XCD's L2. Empty items pad the
+  // interleave where one XCD has fewer items than another.
+  std::vector<std::vector<int32_t>> per((size_t)kXcds);
+  for (size_t i = 0; i < items.size(); ++i) per[(size_t)(items[i].rng % kXcds)].push_back((int32_t)i);
+  size_t longest = 0;
+  for (auto& v : per) {
+    std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) {
+      if (items[a].rng != items[b].rng) return items[a].rng < items[b].rng;
+      return items[a].ev > items[b].ev;
+    });
+    longest = std::max(longest, v.size());
+  }
+  const AdjItem pad{0, 0, 0, 0, -1, 0, 0};
+  std::vector<AdjItem> hs;
+  for (size_t j = 0; j < longest; ++j)
+    for (int x = 0; x < kXcds; ++x) hs.push_back(j < per[(size_t)x].size() ? h[(size_t)per[(size_t)x][j]] : pad);
+  while (!hs.empty() && hs.back().row < 0) hs.pop_back();
+  if (hs.empty()) hs.push_back(pad);
   if (ent.empty()) ent.push_back(make_int4(0, 0, 0, 0));
   TRY(ensure(c, c->adj_items, hs.size() * sizeof(AdjItem)));
   TRY(ensure(c, c->adj_entries, ent.size() * sizeof(int4)));
@@ -619,7 +645,7 @@ gtp_status adj_plan(gtp_ctx c) {
   HIPCHK(c, hipMemcpyAsync(c->adj_gbrow.p, gb_row.data(), gb_row.size() * 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->adj_gbrows.p, gb_rows.data(), gb_rows.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  c->adj_n_items = (int64_t)items.size();
+  c->adj_n_items = items.empty() ? 0 : (int64_t)hs.size();
   c->adj_max_gb = max_gb;
   c->adj_ok = true;
   return GTP_OK;
