@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="shrink gates, cycles and events of the workload together (comparison runs only)")
     ap.add_argument("--algo", type=int, default=0, help="0 time-tiled, 1 one gate per thread")
     ap.add_argument("--tile-log2", type=int, default=0)
     ap.add_argument("--tile-threads", type=int, default=0, help="threads per tile workgroup (0 = library default)")
@@ -183,7 +185,7 @@ def main():
         print(json.dumps({"calib_copy_bytes": n, "copies": 3}))
         return
     t0 = time.time()
-    prob = synth.make_problem(args.config)
+    prob = synth.make_problem(args.config, scale=args.scale)
     gen_s = time.time() - t0
     print(f"# generated {args.config}: {prob.ev.n_events} events, {prob.net.n_gates} gates, {prob.n_bins} bins "
           f"in {gen_s:.1f} s", file=sys.stderr, flush=True)
@@ -261,7 +263,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "n_gates": G, "n_events": N,
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}"
+                               + (f" (scaled by {args.scale})" if args.scale != 1.0 else ""), "n_gates": G, "n_events": N,
                    "n_bins": NB, "bin_ps": prob.bin_ps, "t_end_ps": ev.t_end, "algo": args.algo,
                    "tuning": ctx.get_tuning()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": (achieved / 1e9) if achieved else None,
