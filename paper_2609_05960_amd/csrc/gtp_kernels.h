@@ -96,11 +96,12 @@ struct PackedFwdArgs {
   int64_t* S;
   const int4* phases;        // table phases (null: every quad from global memory)
   const int32_t* ph_off;
+  int32_t slot_quads;        // quads of one LDS table slot
 };
 
 // LDS of the packed kernels: the library's meta + leakage prefix, then the
-// tile's bins (two int64 per bin), then two table slots of kSlotQuads quads.
-constexpr int kSlotQuads = 2048;
+// tile's bins (two int64 per bin), then two table slots of slot_quads quads
+// (as many as the remaining LDS holds, a multiple of 64).
 __device__ __host__ __forceinline__ size_t packed_bins_word_offset(int32_t lib_words) {
   return (size_t)((lib_words + 3) & ~3);
 }
@@ -281,7 +282,7 @@ __device__ __forceinline__ void phase_advance(const PackedFwdArgs& a, PhaseState
   phase_enter(a, P, g0);
   if (P.ph + 1 < P.ph1) {
     const int4 Q = a.phases[P.ph + 1];
-    slot_fill<kThreads>(a.lut.quads, (uint32_t)Q.y, (uint32_t)Q.z, slots + ((P.ph + 1) & 1) * kSlotQuads);
+    slot_fill<kThreads>(a.lut.quads, (uint32_t)Q.y, (uint32_t)Q.z, slots + ((P.ph + 1) & 1) * a.slot_quads);
   }
 }
 
@@ -325,11 +326,11 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
   P.n = 0;
   if (P.ph < P.ph1) {
     phase_enter(a, P, g0);
-    slot_fill<kThreads>(a.lut.quads, P.lo, P.n, slots + (P.ph & 1) * kSlotQuads);
+    slot_fill<kThreads>(a.lut.quads, P.lo, P.n, slots + (P.ph & 1) * a.slot_quads);
     wait_vmem();  // the first phase's slot is whole at the barrier below
     if (P.ph + 1 < P.ph1) {
       const int4 Q = a.phases[P.ph + 1];
-      slot_fill<kThreads>(a.lut.quads, (uint32_t)Q.y, (uint32_t)Q.z, slots + ((P.ph + 1) & 1) * kSlotQuads);
+      slot_fill<kThreads>(a.lut.quads, (uint32_t)Q.y, (uint32_t)Q.z, slots + ((P.ph + 1) & 1) * a.slot_quads);
     }
   }
   GroupRegs<kS> ga, gb;
@@ -352,12 +353,12 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
   while (gi < g1) {
     while (gi >= P.ge) phase_advance<kThreads>(a, P, slots, g0);
     if (gi + nwave < g1) issue(gi + nwave, gb);
-    process_group(a, L, ga, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * kSlotQuads), P.lo, P.n);
+    process_group(a, L, ga, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * a.slot_quads), P.lo, P.n);
     gi += nwave;
     if (gi >= g1) break;
     while (gi >= P.ge) phase_advance<kThreads>(a, P, slots, g0);
     if (gi + nwave < g1) issue(gi + nwave, ga);
-    process_group(a, L, gb, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * kSlotQuads), P.lo, P.n);
+    process_group(a, L, gb, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * a.slot_quads), P.lo, P.n);
     gi += nwave;
   }
   while (P.ph + 1 < P.ph1) phase_advance<kThreads>(a, P, slots, g0);  // boundaries after this wavefront's last group
@@ -391,6 +392,7 @@ struct TraceDev {
   const float* alpha;
   const int4* phases;
   const int32_t* ph_off;
+  int32_t slot_quads;
   const uint2* desc;
   const int64_t* grp_off;
   const int32_t* tile_grp;
@@ -439,6 +441,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
     p.S = a.S + T.bin_off;
     p.phases = T.phases;
     p.ph_off = T.ph_off;
+    p.slot_quads = T.slot_quads;
     unsigned long long* xs =
         reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.base.lib.lds_words_ml));
     unsigned long long* ss = xs + (1 << T.bins.tile_log2);

@@ -102,6 +102,7 @@ struct PackOut {
   int4* phases = nullptr;
   int32_t* ph_off = nullptr;       // [n_tiles + 1]
   int64_t n_phases = 0;
+  int32_t slot_quads = 0;          // slot capacity the phases were cut for
 };
 
 // Builds the packed layout on in.stream (synchronises it). Returns

@@ -686,6 +686,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       }
       poff[n_tiles] = (int32_t)ph.size();
       o.n_phases = (int64_t)ph.size();
+      o.slot_quads = in.slot_quads;
       o.phases = (int4*)own(std::max<size_t>(ph.size(), 1) * sizeof(int4), e2);
       PK(e2);
       o.ph_off = (int32_t*)own((size_t)(n_tiles + 1) * 4, e2);

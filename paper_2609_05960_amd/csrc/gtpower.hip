@@ -363,12 +363,15 @@ gtp_status block_plan_for(gtp_ctx c, const gtp_events& ev, DevBuf& plan_buf, int
 
 gtp_status build_block_plan(gtp_ctx c) { return block_plan_for(c, c->ev, c->plan_blk, c->n_blocks); }
 
-// Bins per tile: the largest power of two (at most 2^12) that still gives
-// about two tiles per compute unit (480 or more), and a packed in-tile time
-// of at most kTimeBits bits.
-int auto_tile_log2(int64_t n_bins, int r_bits) {
+// Bins per tile: the largest power of two (at most 2^12) that still gives at
+// least three tiles for every four compute units, and a packed in-tile time
+// of at most kTimeBits bits. Larger tiles cut fewer units and table phases;
+// one tile per compute unit already keeps the chip busy (one 1024-thread
+// workgroup fills a compute unit).
+int auto_tile_log2(int64_t n_bins, int r_bits, int n_cu) {
+  const int64_t min_tiles = std::max<int64_t>(1, 3 * (int64_t)n_cu / 4);
   int lb = 0;
-  while (lb < 12 && (n_bins >> (lb + 1)) >= 480) ++lb;
+  while (lb < 12 && (n_bins >> (lb + 1)) >= min_tiles) ++lb;
   lb = std::max(lb, 4);
   return std::min(lb, kTimeBits - r_bits);
 }
@@ -381,10 +384,23 @@ size_t ml_lds_bytes(gtp_ctx c) {
   return packed_bins_word_offset(4 * c->n_cells + c->n_leak + 2 * c->n_cells * c->n_load) * 4;
 }
 size_t packed_lds_bytes(gtp_ctx c, int tile_log2) { return ml_lds_bytes(c) + ((size_t)16 << tile_log2); }
-constexpr size_t kSlotBytes = 2 * (size_t)kSlotQuads * 16;
-
 constexpr size_t kMaxLds = 160 * 1024;
-bool slots_fit(gtp_ctx c, int tile_log2) { return packed_lds_bytes(c, tile_log2) + kSlotBytes <= kMaxLds; }
+
+// static LDS of the batched kernel (its work-item slot), kept out of the
+// dynamic budget
+constexpr size_t kBatchStaticLds = 64;
+
+// Quads of one table slot for tiles of 2^tile_log2 bins: two slots fill what
+// the bins and the library prefix leave of the LDS (the batched kernel's
+// static slot included), a multiple of 64 quads, at most 4096; 0 (no table
+// phases) below 256.
+constexpr int32_t kMaxSlotQuads = 4096;
+int32_t slot_quads_for(gtp_ctx c, int tile_log2) {
+  const int64_t room = (int64_t)kMaxLds - (int64_t)kBatchStaticLds - (int64_t)packed_lds_bytes(c, tile_log2);
+  const int64_t q = std::min<int64_t>(room / 32 / 64 * 64, kMaxSlotQuads);
+  return q >= 256 ? (int32_t)q : 0;
+}
+size_t slot_bytes(int32_t slot_quads) { return 2 * (size_t)slot_quads * 16; }
 // Longest unit of the packed layout by default; kernels hold a group's events
 // in registers, 8 or 16 slots per lane. With 16 slots, workgroups of at most
 // 512 threads (the registers of 1024 threads do not fit).
@@ -394,12 +410,6 @@ int threads_for_slots(int th, int slots) { return (slots == 16 && th > 512) ? 51
 int unit_events_of(gtp_ctx c) { return c->tun.unit_events ? c->tun.unit_events : kDefaultUnitEvents; }
 int slots_of(gtp_ctx c) { return unit_events_of(c) <= 8 ? 8 : 16; }
 
-// static LDS of the batched kernel (its work-item slot), kept out of the
-// dynamic budget
-constexpr size_t kBatchStaticLds = 64;
-bool batch_slots_fit(gtp_ctx c, int tile_log2) {
-  return packed_lds_bytes(c, tile_log2) + kSlotBytes + kBatchStaticLds <= kMaxLds;
-}
 
 template <class K>
 hipError_t lds_limit(K kern, size_t static_lds = 0) {
@@ -466,7 +476,7 @@ BinSpec bins_for(gtp_ctx c, int64_t t_end) {
 gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, BinSpec& B, PackOut& pk, double& pack_ms,
                     int32_t* dbg_state = nullptr, int64_t* dbg_bin = nullptr) {
   if (B.r_bits > kTimeBits) return fail(c, GTP_ERR_UNSUPPORTED, "bin width above 2^%d ps", kTimeBits);
-  int lb = c->tun.bins_per_tile_log2 ? c->tun.bins_per_tile_log2 : auto_tile_log2(B.n_bins, B.r_bits);
+  int lb = c->tun.bins_per_tile_log2 ? c->tun.bins_per_tile_log2 : auto_tile_log2(B.n_bins, B.r_bits, c->n_cu);
   if (lb + B.r_bits > kTimeBits)
     return fail(c, GTP_ERR_UNSUPPORTED, "tile of 2^%d bins with %d-bit in-bin offsets exceeds %d bits", lb, B.r_bits,
                 kTimeBits);
@@ -490,7 +500,7 @@ gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, Bin
   in.dbg_bin = dbg_bin;
   in.cq_lo = c->h_cq_lo;
   in.cq_hi = c->h_cq_hi;
-  in.slot_quads = kSlotQuads;
+  in.slot_quads = slot_quads_for(c, lb);
   in.unit_events = unit_events_of(c);
   in.gate_block_log2 = c->tun.gate_block_log2 ? c->tun.gate_block_log2 : kGateBlockLog2;
   in.bins = B;
@@ -534,7 +544,7 @@ gtp_status build_pack(gtp_ctx c) {
 // largest gate block.
 int32_t adj_slot_quads(gtp_ctx c, int32_t max_gb) {
   const int64_t room = (int64_t)kMaxLds - (int64_t)ml_lds_bytes(c) - 8 * (int64_t)max_gb;
-  return (int32_t)std::max<int64_t>(0, std::min<int64_t>(room / 16, kSlotQuads));
+  return (int32_t)std::max<int64_t>(0, std::min<int64_t>(room / 16, kMaxSlotQuads));
 }
 size_t adj_lds_bytes(gtp_ctx c, int32_t max_gb) {
   return ml_lds_bytes(c) + 16 * (size_t)adj_slot_quads(c, max_gb) + (size_t)max_gb * 8;
@@ -1168,10 +1178,11 @@ gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, in
   a.bins = B;
   a.X = X;
   a.S = S;
-  const bool ph = pk.phases && slots_fit(c, B.tile_log2);
+  const bool ph = pk.phases && pk.slot_quads > 0;
   a.phases = ph ? pk.phases : nullptr;
   a.ph_off = ph ? pk.ph_off : nullptr;
-  const size_t lds = packed_lds_bytes(c, B.tile_log2) + (ph ? kSlotBytes : 0);
+  a.slot_quads = ph ? pk.slot_quads : 0;
+  const size_t lds = packed_lds_bytes(c, B.tile_log2) + (ph ? slot_bytes(pk.slot_quads) : 0);
   const int sl = slots_of(c);
   const int th = threads_for_slots(tile_threads(c), sl);
   const dim3 grid((unsigned)B.n_tiles);
@@ -1251,10 +1262,18 @@ gtp_status build_batch(gtp_ctx c) {
       return st;
     }
     t.bin_off = off;
-    const bool ph = t.pk.phases && batch_slots_fit(c, lb);
-    tab[i] = TraceDev{t.pk.w32,          t.pk.row,  t.pk.alpha,      ph ? t.pk.phases : nullptr,
-                      ph ? t.pk.ph_off : nullptr, t.pk.desc, t.pk.grp_off, t.pk.tile_grp,
-                      t.bins,            off};
+    const bool ph = t.pk.phases && t.pk.slot_quads > 0;
+    tab[i] = TraceDev{t.pk.w32,
+                      t.pk.row,
+                      t.pk.alpha,
+                      ph ? t.pk.phases : nullptr,
+                      ph ? t.pk.ph_off : nullptr,
+                      ph ? t.pk.slot_quads : 0,
+                      t.pk.desc,
+                      t.pk.grp_off,
+                      t.pk.tile_grp,
+                      t.bins,
+                      off};
     fin[i] = FinTrace{off, t.bins.n_bins, t.bins.t_end};
     off += t.bins.n_bins;
     // events per tile, for the largest-first order
@@ -1307,7 +1326,10 @@ gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_s
     a.queue = ptr<unsigned long long>(c->b_queue);
     a.X = ptr<int64_t>(c->b_X);
     a.S = ptr<int64_t>(c->b_S);
-    const size_t lds = packed_lds_bytes(c, lb) + (batch_slots_fit(c, lb) ? kSlotBytes : 0);
+    int32_t sq = 0;  // every trace's pack has the same slot size (same tile size)
+    for (auto& t : c->batch)
+      if (t.pk.phases) sq = std::max(sq, t.pk.slot_quads);
+    const size_t lds = packed_lds_bytes(c, lb) + slot_bytes(sq);
     const int sl = slots_of(c);
     const int th = threads_for_slots(tile_threads(c), sl);
     // resident workgroups: as many as fit (LDS-limited), at most one per item
