@@ -97,13 +97,18 @@ struct PackedFwdArgs {
   const int4* phases;        // table phases (null: every quad from global memory)
   const int32_t* ph_off;
   int32_t slot_quads;        // quads of one LDS table slot
+  long long* tile_tot;       // non-null: S gets the within-tile exclusive prefix of
+                             // the steps and tile_tot[tile] their total
 };
 
 // LDS of the packed kernels: the library's meta + leakage prefix, then the
 // tile's bins (two int64 per bin), then two table slots of slot_quads quads
 // (as many as the remaining LDS holds, a multiple of 64).
+// (36 words between the library prefix and the bins: the in-tile prefix scan's
+// wavefront sums)
+constexpr int kScanScratchWords = 36;
 __device__ __host__ __forceinline__ size_t packed_bins_word_offset(int32_t lib_words) {
-  return (size_t)((lib_words + 3) & ~3);
+  return (size_t)((lib_words + 3) & ~3) + kScanScratchWords;
 }
 
 // One wavefront group's data in registers: unit descriptor, gate
@@ -363,6 +368,40 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
   }
   while (P.ph + 1 < P.ph1) phase_advance<kThreads>(a, P, slots, g0);  // boundaries after this wavefront's last group
   __syncthreads();
+  if (a.tile_tot) {
+    // exclusive prefix of the tile's steps, in place: thread i takes a run of
+    // consecutive bins, the runs' sums are scanned over the wavefronts
+    long long* ws = reinterpret_cast<long long*>(xs) - kScanScratchWords / 2;
+    const int per = (nb + kThreads - 1) / kThreads;
+    const int i0 = min((int)threadIdx.x * per, nb), i1 = min(i0 + per, nb);
+    long long sum = 0;
+    for (int i = i0; i < i1; ++i) sum += (long long)ss[i];
+    long long inc = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+      const long long t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    const int wave = (int)(threadIdx.x >> 6);
+    if (lane == 63) ws[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long acc = 0;
+      for (int w = 0; w < nwave; ++w) {
+        const long long t = ws[w];
+        ws[w] = acc;
+        acc += t;
+      }
+      a.tile_tot[tile] = acc;
+    }
+    __syncthreads();
+    long long run = ws[wave] + inc - sum;
+    for (int i = i0; i < i1; ++i) {
+      const long long v = (long long)ss[i];
+      ss[i] = (unsigned long long)run;
+      run += v;
+    }
+    __syncthreads();
+  }
   const int64_t b0 = (int64_t)tile << B.tile_log2;
   for (int i = threadIdx.x; i < nb; i += kThreads) {
     if (b0 + i < B.n_bins) {
@@ -451,12 +490,13 @@ __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
 }
 
 // Per-call gate records (output load, leakage scale) in cell-sorted order,
-// plus the sum of the gates' quantised initial leakage rates.
+// plus each block's sum of its gates' quantised initial leakage rates
+// (l0_part[block]; their total is L0, summed by the kernel that needs it).
 struct GateParamArgs {
-  const int32_t* gperm;      // sorted index -> gate
+  const int32_t* gperm;      // sorted index -> gate (for the caller's leakage scales)
   const int32_t* gcell;      // sorted index -> cell
-  const int32_t* gate_out;
-  const uint32_t* gate_init;
+  const int32_t* gout;       // sorted index -> output net
+  const uint32_t* ginit;     // sorted index -> initial pin values
   const float* net_load;
   const float* leak_scale;   // may be null (all 1)
   const CellMeta* meta;
@@ -465,7 +505,7 @@ struct GateParamArgs {
   float rate_scale;
   float max_scale;
   GateParam* out;
-  unsigned long long* L0;
+  long long* l0_part;        // [blocks]
   int32_t* flag;             // bit 0: a leakage scale out of range
 };
 
@@ -474,11 +514,10 @@ __global__ void __launch_bounds__(256) k_gate_params(GateParamArgs a) {
   const int64_t gs = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   long long q0 = 0;
   if (gs < a.n_gates) {
-    const int32_t g = a.gperm[gs];
     const int32_t c = a.gcell[gs];
     const CellMeta cm = a.meta[c];
-    const float C = a.net_load[a.gate_out[g]];
-    float lam = a.leak_scale ? a.leak_scale[g] : 1.0f;
+    const float C = a.net_load[a.gout[gs]];
+    float lam = a.leak_scale ? a.leak_scale[a.gperm[gs]] : 1.0f;
     if (!(lam >= 0.0f && lam <= a.max_scale)) {
       atomicOr(a.flag, 1);
       lam = 0.0f;
@@ -487,7 +526,7 @@ __global__ void __launch_bounds__(256) k_gate_params(GateParamArgs a) {
     p.C = C;
     p.lam = lam;
     a.out[gs] = p;
-    const uint32_t s0 = a.gate_init[g] & ((1u << cm.n_in) - 1u);
+    const uint32_t s0 = a.ginit[gs] & ((1u << cm.n_in) - 1u);
     q0 = (long long)qrate(lam, a.leak[cm.leak_off + (int)s0], a.rate_scale);
   }
   red[threadIdx.x] = q0;
@@ -496,7 +535,95 @@ __global__ void __launch_bounds__(256) k_gate_params(GateParamArgs a) {
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && red[0] != 0) atomicAdd(a.L0, (unsigned long long)red[0]);
+  if (threadIdx.x == 0) a.l0_part[blockIdx.x] = red[0];
+}
+
+// Sum of n partials (one workgroup of 1024 threads) into *out.
+__global__ void __launch_bounds__(1024) k_sum_parts(const long long* part, int64_t n, unsigned long long* out) {
+  __shared__ long long red[1024];
+  long long v = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) v += part[i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = (unsigned long long)red[0];
+}
+
+// Leakage rate at every tile start (one workgroup of 1024 threads):
+// base[k] = L0 + sum of the tile totals of the steps before tile k, with L0
+// the sum of the gate-record kernel's partials.
+__global__ void __launch_bounds__(1024) k_tile_base(const long long* l0_part, int64_t n_part, const long long* tot,
+                                                    int64_t n_tiles, long long* base) {
+  __shared__ long long red[1024];
+  __shared__ long long ws[17];
+  long long v = 0;
+  for (int64_t i = threadIdx.x; i < n_part; i += 1024) v += l0_part[i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  long long carry = red[0];  // L0
+  const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+  for (int64_t c0 = 0; c0 < n_tiles; c0 += 1024) {
+    const int64_t i = c0 + threadIdx.x;
+    const long long x = i < n_tiles ? tot[i] : 0;
+    long long inc = x;  // inclusive scan within the wavefront
+    for (int o = 1; o < 64; o <<= 1) {
+      const long long t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    if (lane == 63) ws[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long acc = 0;
+      for (int w = 0; w < 16; ++w) {
+        const long long t = ws[w];
+        ws[w] = acc;
+        acc += t;
+      }
+      ws[16] = acc;
+    }
+    __syncthreads();
+    if (i < n_tiles) base[i] = carry + ws[wave] + inc - x;
+    carry += ws[16];
+    __syncthreads();
+  }
+}
+
+// Power of every bin from the packed forward's per-tile output: X, the
+// within-tile exclusive prefix of the leakage steps (exS), the rate at each
+// tile start (base) and the tile totals (for the step sum of a partial last
+// bin, whose later bins in the tile hold no events).
+struct FinTileArgs {
+  const int64_t* X;
+  const int64_t* exS;
+  const long long* base;
+  const long long* tot;
+  float* P;
+  int64_t n_bins, D, t_end;
+  int32_t tile_log2;
+  double out_scale;     // 2^-m / D
+};
+
+__global__ void __launch_bounds__(256) k_finalize_tiles(FinTileArgs a) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.n_bins) return;
+  const int64_t k = b >> a.tile_log2;
+  const int64_t R = (int64_t)a.base[k] + a.exS[b];
+  int64_t E;
+  if (b == a.n_bins - 1 && a.n_bins * a.D != a.t_end) {
+    const int64_t w = a.t_end - b * a.D;
+    const int64_t S = (int64_t)a.tot[k] - a.exS[b];
+    E = a.X[b] - S * (a.n_bins * a.D - a.t_end) + w * R;
+  } else {
+    E = a.X[b] + a.D * R;
+  }
+  a.P[b] = (float)((double)E * a.out_scale);
 }
 
 // ---------------------------------------------------------------------------

@@ -38,7 +38,8 @@
 //             the per-event debug trace only)
 //   grp_off[n_groups + 1] first event of each group
 //   tile_grp[n_tiles + 1] first group of each tile
-//   gperm[G]  cell-sorted index -> gate;  gcell[G] cell of each sorted index
+//   gperm[G]  cell-sorted index -> gate;  gcell[G] cell of each sorted index;
+//   gout[G], ginit[G]  output net and initial pin values in sorted order
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -55,6 +56,7 @@ struct PackIn {
   EvView ev;                  // gate-major events (device)
   const uint2* plan_blk;      // gate-major lane-block plan (device)
   const int32_t* gate_cell;   // [G] (device)
+  const int32_t* gate_out;    // [G] (device)
   const uint32_t* gate_init;  // [G] (device)
   std::vector<int32_t> h_gate_cell;  // [G] host copy
   std::vector<int32_t> n_in;         // [n_cells] inputs per cell
@@ -79,6 +81,8 @@ struct PackOut {
   int32_t* tile_grp = nullptr;
   int32_t* gperm = nullptr;
   int32_t* gcell = nullptr;
+  int32_t* gout = nullptr;     // [G] output net of each cell-sorted gate
+  uint32_t* ginit = nullptr;   // [G] initial pin values of each cell-sorted gate
   int64_t n_events = 0;       // events packed (valid times)
   int64_t n_units = 0;
   int64_t n_groups = 0;

@@ -312,6 +312,18 @@ __global__ void __launch_bounds__(256) k_pk_group_cells(const uint2* desc, const
   if (lane == last) cells[gi].y = gcell[d.x & 0x0fffffffu];
 }
 
+// Output nets and initial pin values in cell-sorted gate order (the per-call
+// gate records then read them contiguously).
+__global__ void __launch_bounds__(256) k_pk_gate_sorted(const int32_t* gperm, const int32_t* gate_out,
+                                                        const uint32_t* gate_init, int64_t n_gates, int32_t* gout,
+                                                        uint32_t* ginit) {
+  const int64_t gs = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gs >= n_gates) return;
+  const int32_t g = gperm[gs];
+  gout[gs] = gate_out[g];
+  ginit[gs] = gate_init[g];
+}
+
 int ceil_log2_u64(uint64_t x) {
   int l = 0;
   while ((1ull << l) < x) ++l;
@@ -321,8 +333,8 @@ int ceil_log2_u64(uint64_t x) {
 }  // namespace
 
 void pack_free(PackOut* o) {
-  void* ps[] = {o->w32,  o->row,   o->alpha,     o->desc,  o->dsrc,   o->grp_off, o->tile_grp,
-                o->gperm, o->gcell, o->reg_first, o->tfirst, o->phases, o->ph_off};
+  void* ps[] = {o->w32,   o->row,   o->alpha, o->desc,      o->dsrc,   o->grp_off, o->tile_grp, o->gperm,
+                o->gcell, o->gout, o->ginit, o->reg_first, o->tfirst, o->phases, o->ph_off};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   *o = PackOut();
@@ -421,10 +433,17 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     PK(e2);
     o.gcell = (int32_t*)own((size_t)G * 4, e2);
     PK(e2);
+    o.gout = (int32_t*)own((size_t)G * 4, e2);
+    PK(e2);
+    o.ginit = (uint32_t*)own((size_t)G * 4, e2);
+    PK(e2);
     if (G > 0) {
       PK(hipMemcpyAsync(d_rank, rank.data(), (size_t)G * 4, hipMemcpyHostToDevice, s));
       PK(hipMemcpyAsync(o.gperm, perm.data(), (size_t)G * 4, hipMemcpyHostToDevice, s));
       PK(hipMemcpyAsync(o.gcell, pcell.data(), (size_t)G * 4, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_pk_gate_sorted, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, s, o.gperm, in.gate_out,
+                         in.gate_init, (int64_t)G, o.gout, o.ginit);
+      PKLAUNCH("k_pk_gate_sorted");
     }
     PK(hipMemcpyAsync(d_cs, cell_start.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
     PK(hipMemcpyAsync(d_gbb, gb_base.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));

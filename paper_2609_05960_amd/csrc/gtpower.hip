@@ -119,6 +119,7 @@ struct gtp_ctx_s {
 
   // per-call work buffers
   DevBuf gprep, gparam, X, S, exS, L0, flag, first_bad;
+  DevBuf l0_part, tile_tot, tile_base;   // packed forward: leakage-rate partials and tile sums
   DevBuf adj_w, adj_c, adj_exc, adj_wg, adj_total, gC, gL;
 
   // packed adjoint work items (built from the pack's region tables)
@@ -493,6 +494,7 @@ gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, Bin
   in.plan_blk = reinterpret_cast<const uint2*>(plan_buf.p);
   in.gate_cell = ptr<int32_t>(c->gate_cell);
   in.gate_init = ptr<uint32_t>(c->gate_init);
+  in.gate_out = ptr<int32_t>(c->gate_out);
   in.h_gate_cell = c->h_gate_cell;
   in.n_in = c->h_nin;
   in.lib = lib_view(c);
@@ -745,7 +747,7 @@ gtp_status gtp_destroy(gtp_ctx c) {
   drop_batch(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   DevBuf* all[] = {&c->lib_img, &c->load_axis, &c->load_inv, &c->quads, &c->gate_cell, &c->gate_out,
-                   &c->gate_init, &c->plan_blk, &c->blk_tmp, &c->blk_tmp2, &c->scan_sums, &c->gprep, &c->gparam,
+                   &c->gate_init, &c->plan_blk, &c->blk_tmp, &c->blk_tmp2, &c->scan_sums, &c->gprep, &c->gparam, &c->l0_part, &c->tile_tot, &c->tile_base,
                    &c->X, &c->S, &c->exS, &c->L0, &c->flag, &c->first_bad, &c->adj_w, &c->adj_c, &c->adj_exc,
                    &c->adj_wg, &c->adj_total, &c->gC, &c->gL, &c->adj_items, &c->adj_entries, &c->adj_gbs, &c->adj_gbrow, &c->adj_gbrows, &c->adj_part, &c->b_tab, &c->b_items, &c->b_queue,
                    &c->b_fin, &c->b_X, &c->b_S, &c->b_exS, &c->tun_in, &c->tun_out};
@@ -1124,17 +1126,19 @@ gtp_status final_bins(gtp_ctx c, float* power_mw) {
   return GTP_OK;
 }
 
+// Per-call gate records in the pack's gate order, and the per-block partial
+// sums of the initial leakage rates (l0_part).
 gtp_status gate_params_for(gtp_ctx c, const PackOut& pk, const float* net_load, const float* leak_scale) {
   TRY(ensure(c, c->gparam, (size_t)std::max<int64_t>(c->n_gates, 1) * sizeof(GateParam)));
-  TRY(ensure(c, c->L0, 8));
-  TRY(fill_u64(c, c->L0.p, 1, 0ull));
-  if (c->n_gates == 0) return GTP_OK;
+  const int64_t nb = std::max<int64_t>(grid_for(c->n_gates, 256), 1);
+  TRY(ensure(c, c->l0_part, (size_t)nb * 8));
+  if (c->n_gates == 0) return fill_u64(c, c->l0_part.p, 1, 0ull);
   const LibView L = lib_view(c);
   GateParamArgs a;
   a.gperm = pk.gperm;
   a.gcell = pk.gcell;
-  a.gate_out = ptr<int32_t>(c->gate_out);
-  a.gate_init = ptr<uint32_t>(c->gate_init);
+  a.gout = pk.gout;
+  a.ginit = pk.ginit;
   a.net_load = net_load;
   a.leak_scale = leak_scale;
   a.meta = L.meta;
@@ -1143,9 +1147,19 @@ gtp_status gate_params_for(gtp_ctx c, const PackOut& pk, const float* net_load, 
   a.rate_scale = (float)(std::ldexp(1.0, c->mfix) * 1e-6);
   a.max_scale = GTP_MAX_LEAK_SCALE;
   a.out = ptr<GateParam>(c->gparam);
-  a.L0 = ptr<unsigned long long>(c->L0);
+  a.l0_part = ptr<long long>(c->l0_part);
   a.flag = ptr<int32_t>(c->flag);
   LAUNCH(c, "k_gate_params", k_gate_params, dim3(grid_for(c->n_gates, 256)), dim3(256), 0, a);
+  return GTP_OK;
+}
+
+int64_t l0_parts(gtp_ctx c) { return std::max<int64_t>(grid_for(c->n_gates, 256), 1); }
+
+// L0 (the initial leakage rate) as one value, from the gate records' partials.
+gtp_status sum_l0(gtp_ctx c) {
+  TRY(ensure(c, c->L0, 8));
+  LAUNCH(c, "k_sum_parts", k_sum_parts, dim3(1), dim3(1024), 0, (const long long*)ptr<long long>(c->l0_part),
+         l0_parts(c), ptr<unsigned long long>(c->L0));
   return GTP_OK;
 }
 
@@ -1167,8 +1181,10 @@ PackedFwdArgs packed_common(gtp_ctx c) {
 int tile_threads(gtp_ctx c) { return c->tun.tile_threads ? c->tun.tile_threads : kTileThreads; }
 
 // Packed forward of one trace into X/S.
-gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, int64_t* X, int64_t* S) {
+gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, int64_t* X, int64_t* S,
+                              long long* tile_tot = nullptr) {
   PackedFwdArgs a = packed_common(c);
+  a.tile_tot = tile_tot;
   a.w32 = pk.w32;
   a.row = pk.row;
   a.alpha = pk.alpha;
@@ -1200,8 +1216,34 @@ gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, in
   return fail(c, GTP_ERR_INVALID_ARG, "tile_threads %d", th);
 }
 
-gtp_status packed_forward(gtp_ctx c) {
-  return packed_forward_for(c, c->pk, c->bins, ptr<int64_t>(c->X), ptr<int64_t>(c->S));
+// The whole packed forward of one trace (gate records already computed):
+// the tile kernel leaves X, the within-tile prefix of the steps and the tile
+// totals; one small kernel turns the totals into the rate at every tile
+// start, one more gives the power.
+gtp_status packed_power(gtp_ctx c, const PackOut& pk, const BinSpec& B, float* power_mw) {
+  const int64_t NB = B.n_bins;
+  TRY(ensure(c, c->X, (size_t)std::max<int64_t>(NB, 1) * 8));
+  TRY(ensure(c, c->S, (size_t)std::max<int64_t>(NB, 1) * 8));
+  TRY(ensure(c, c->tile_tot, (size_t)std::max(B.n_tiles, 1) * 8));
+  TRY(ensure(c, c->tile_base, (size_t)std::max(B.n_tiles, 1) * 8));
+  TRY(packed_forward_for(c, pk, B, ptr<int64_t>(c->X), ptr<int64_t>(c->S), ptr<long long>(c->tile_tot)));
+  LAUNCH(c, "k_tile_base", k_tile_base, dim3(1), dim3(1024), 0, (const long long*)ptr<long long>(c->l0_part),
+         l0_parts(c), (const long long*)ptr<long long>(c->tile_tot), (int64_t)B.n_tiles,
+         ptr<long long>(c->tile_base));
+  if (NB == 0) return GTP_OK;
+  FinTileArgs f;
+  f.X = ptr<int64_t>(c->X);
+  f.exS = ptr<int64_t>(c->S);
+  f.base = ptr<long long>(c->tile_base);
+  f.tot = ptr<long long>(c->tile_tot);
+  f.P = power_mw;
+  f.n_bins = NB;
+  f.D = B.D;
+  f.t_end = B.t_end;
+  f.tile_log2 = B.tile_log2;
+  f.out_scale = std::ldexp(1.0, -c->mfix) / (double)B.D;
+  LAUNCH(c, "k_finalize_tiles", k_finalize_tiles, dim3(grid_for(NB, 256)), dim3(256), 0, f);
+  return GTP_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1307,6 +1349,7 @@ gtp_status build_batch(gtp_ctx c) {
   TRY(ensure(c, c->scan_sums, (size_t)((NB + kScanTile - 1) / kScanTile) * 8 + 8));
   TRY(ensure(c, c->gparam, (size_t)std::max<int64_t>(c->n_gates, 1) * sizeof(GateParam)));
   TRY(ensure(c, c->L0, 8));
+  TRY(ensure(c, c->l0_part, (size_t)l0_parts(c) * 8));
   c->batch_packed = true;
   return GTP_OK;
 }
@@ -1315,6 +1358,7 @@ gtp_status build_batch(gtp_ctx c) {
 // to record in a graph).
 gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_scale, float* power_mw) {
   TRY(gate_params_for(c, c->batch[0].pk, net_load, leak_scale));
+  TRY(sum_l0(c));
   TRY(fill_u64(c, c->b_queue.p, 1, 0ull));
   const int lb = c->batch[0].bins.tile_log2;
   if (c->batch_items > 0) {
@@ -1409,7 +1453,7 @@ gtp_status gtp_forward(gtp_ctx c, const float* net_load_ff, const float* leak_sc
   if (c->tun.algo == 0) {
     TRY(build_pack(c));
     TRY(gate_params(c, net_load_ff, leak_scale));
-    TRY(packed_forward(c));
+    return packed_power(c, c->pk, c->bins, power_mw);
   } else {
     TRY(gate_prep(c, net_load_ff, leak_scale));
     TRY(fill_u64(c, c->X.p, NB, 0ull));
@@ -1496,20 +1540,7 @@ gtp_status gtp_forward_trace(gtp_ctx c, int32_t trace, const float* net_load_ff,
   TRY(ensure(c, c->S, (size_t)NB * 8));
   TRY(ensure(c, c->exS, (size_t)NB * 8));
   TRY(gate_params_for(c, t.pk, net_load_ff, leak_scale));
-  TRY(packed_forward_for(c, t.pk, t.bins, ptr<int64_t>(c->X), ptr<int64_t>(c->S)));
-  TRY(scan_exclusive<int64_t, OpAdd>(c, ptr<int64_t>(c->S), ptr<int64_t>(c->exS), NB, (int64_t)0, OpAdd()));
-  FinArgs f;
-  f.X = ptr<int64_t>(c->X);
-  f.S = ptr<int64_t>(c->S);
-  f.exS = ptr<int64_t>(c->exS);
-  f.L0 = ptr<unsigned long long>(c->L0);
-  f.P = power_mw;
-  f.n_bins = NB;
-  f.D = t.bins.D;
-  f.t_end = t.bins.t_end;
-  f.out_scale = std::ldexp(1.0, -c->mfix) / (double)t.bins.D;
-  LAUNCH(c, "k_finalize", k_finalize, dim3(grid_for(NB, 256)), dim3(256), 0, f);
-  return GTP_OK;
+  return packed_power(c, t.pk, t.bins, power_mw);
 }
 
 }  // extern "C"
