@@ -1103,7 +1103,8 @@ __global__ void __launch_bounds__(256) k_adj_suffix_f(const double* w, const dou
 
 // Gradient outputs from the partial table: a sorted gate sums its block's
 // rows (one per item of the block) in FP64, adds its load gradient to its
-// output net (grad_load zeroed first) and writes its leakage-scale gradient
+// output net (grad_load zeroed first; a plain store when every net has at most
+// one driver) and writes its leakage-scale gradient
 // (plus the initial-state leakage times the integral of the bin weights over
 // the window).
 struct AdjOutSortedArgs {
@@ -1122,6 +1123,7 @@ struct AdjOutSortedArgs {
   float* grad_load;
   float* grad_scale;
   int64_t n_gates;
+  int32_t unique_out;         // 1: no net has two drivers (plain stores)
 };
 
 __global__ void __launch_bounds__(256) k_adj_out_sorted(AdjOutSortedArgs a) {
@@ -1144,7 +1146,11 @@ __global__ void __launch_bounds__(256) k_adj_out_sorted(AdjOutSortedArgs a) {
   const CellMeta cm = a.meta[a.gcell[gs]];
   const uint32_t s0 = a.gate_init[g] & ((1u << cm.n_in) - 1u);
   a.grad_scale[g] = (float)(1e-6 * ((double)a.leak[cm.leak_off + (int)s0] * *a.total + gl));
-  if (gc != 0.0) atomicAdd(&a.grad_load[a.gate_out[g]], (float)gc);
+  if (a.unique_out) {
+    a.grad_load[a.gate_out[g]] = (float)gc;
+  } else if (gc != 0.0) {
+    atomicAdd(&a.grad_load[a.gate_out[g]], (float)gc);
+  }
 }
 
 // ---------------------------------------------------------------------------

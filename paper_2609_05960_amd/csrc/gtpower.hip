@@ -68,6 +68,7 @@ struct gtp_ctx_s {
   // netlist
   bool net_ok = false;
   int64_t n_gates = 0, n_nets = 0;
+  bool unique_out = true;   // no net has two driving gates
   DevBuf gate_cell, gate_out, gate_init;
 
   // events
@@ -1003,6 +1004,21 @@ gtp_status gtp_load_netlist(gtp_ctx c, int64_t n_gates, int64_t n_nets, const in
   c->h_gate_cell.resize((size_t)n_gates);
   if (n_gates > 0)
     HIPCHK(c, hipMemcpy(c->h_gate_cell.data(), c->gate_cell.p, (size_t)n_gates * 4, hipMemcpyDeviceToHost));
+  {
+    // at most one driving gate per net: the adjoint then stores each gate's
+    // load gradient into its net instead of adding it atomically
+    std::vector<int32_t> out((size_t)n_gates);
+    if (n_gates > 0) HIPCHK(c, hipMemcpy(out.data(), c->gate_out.p, (size_t)n_gates * 4, hipMemcpyDeviceToHost));
+    std::vector<uint8_t> seen((size_t)std::max<int64_t>(n_nets, 1), 0);
+    c->unique_out = true;
+    for (int32_t o : out) {
+      if (seen[(size_t)o]) {
+        c->unique_out = false;
+        break;
+      }
+      seen[(size_t)o] = 1;
+    }
+  }
   c->n_gates = n_gates;
   c->n_nets = n_nets;
   c->net_ok = true;
@@ -1752,6 +1768,7 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       o.grad_load = grad_net_load;
       o.grad_scale = grad_leak_scale;
       o.n_gates = c->n_gates;
+      o.unique_out = c->unique_out ? 1 : 0;
       LAUNCH(c, "k_adj_out_sorted", k_adj_out_sorted, dim3(grid_for(c->n_gates, 256)), dim3(256), 0, o);
     }
     return GTP_OK;

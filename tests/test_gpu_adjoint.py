@@ -114,3 +114,20 @@ def test_packed_decompositions(O, tl, ue, gb):
     drv = prob.net.gate_out_net
     close(gl[drv], gl64[drv], "d/d load")
     close(gs, gs64, "d/d leak scale")
+
+
+@pytest.mark.parametrize("algo", [0, 1])
+def test_shared_output_net(O, algo):
+    """Two gates driving one net: the net's load gradient is the sum of both
+    gates' terms (the adjoint's atomic path; unique drivers take plain stores)."""
+    prob = synth.make_random_small(23, n_gates=40, n_cells=4, i_max=3, n_events=8000, t_end=100000, bin_ps=50,
+                                   p_tie=0.1, n_clock=1)
+    out = prob.net.gate_out_net
+    out[1] = out[0]
+    out[7] = out[0]
+    gP = np.random.default_rng(9).normal(size=prob.n_bins)
+    gl64, gs64 = O.adjoint(prob, gP)
+    gl, gs = gpu_adjoint(prob, gP, algo=algo)
+    drv = np.unique(out)
+    close(gl[drv], gl64[drv], "d/d load")
+    close(gs, gs64, "d/d leak scale")
