@@ -134,12 +134,10 @@ __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int
   G.d = d;
   const bool valid = d.x != 0xffffffffu;
   G.len = valid ? (int)(d.x >> 28) + 1 : 0;
-  if (valid && mine) {
-    G.gp = a.gparam[d.x & 0x0fffffffu];
-  } else {
-    G.gp.C = 0.f;
-    G.gp.lam = 0.f;
-  }
+  // no else branch: a lane without a unit (len 0) gathers record 0 and never
+  // uses it, and nothing reads the loaded registers before the group is
+  // processed (a select on them would wait for the load right here)
+  if (mine) G.gp = a.gparam[valid ? (d.x & 0x0fffffffu) : 0u];
   // the offset is the same on every lane: keep it scalar so the loads use a
   // scalar base and a 32-bit lane offset
   const int64_t offu = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(off >> 32)) << 32) |
@@ -190,10 +188,20 @@ __device__ __forceinline__ float4 quad_at(const float4* __restrict__ quads, cons
   return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// Table quad of a lane's event when the phase's slot holds every quad its
+// groups read (index clamped into the slot, so a stray index stays in LDS;
+// n is at least 1 whenever a group of the phase holds an event).
+__device__ __forceinline__ float4 quad_slot(const lds_float4* slot, uint32_t lo, uint32_t n, uint32_t qi) {
+  const quad_vec v = slot[min(qi - lo, n - 1u)];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // Accumulates one group (loaded into G) into the tile's LDS bins. The table
 // quad and the leakage value after event k+1 load into one buffer while event
-// k is accumulated from the other.
-template <int kS>
+// k is accumulated from the other. With kSlotOnly every quad comes from the
+// slot and the function issues no global load, so the next group's loads
+// stay in flight while this group is accumulated.
+template <int kS, bool kSlotOnly>
 __device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsLib& L, const GroupRegs<kS>& G,
                                               unsigned long long* xs, unsigned long long* ss, const lds_float4* slot,
                                               uint32_t lo, uint32_t n) {
@@ -214,7 +222,8 @@ __device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsL
     float lk_after;  // leakage value of the input state after the event
   };
   auto prefetch = [&](int k, Pre& P) {
-    P.q = quad_at(quads, slot, lo, n, (G.rv[k] & kRowMask) + jq);
+    const uint32_t qi = (G.rv[k] & kRowMask) + jq;
+    P.q = kSlotOnly ? quad_slot(slot, lo, n, qi) : quad_at(quads, slot, lo, n, qi);
     P.lk_after = lk[G.wv[k] >> kStateShift];
   };
   Pre pre[2];
@@ -304,7 +313,7 @@ __device__ __forceinline__ void phase_advance(const PackedFwdArgs& a, PhaseState
 // slot, and one barrier at the boundary separates the phases. Every
 // wavefront crosses every boundary once, in order, whether or not it has
 // groups in a phase.
-template <int kThreads, int kS>
+template <int kThreads, int kS, bool kSlotOnly>
 __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsLib& L, unsigned long long* xs,
                                               unsigned long long* ss, int32_t tile, float4* slots) {
   const BinSpec& B = a.bins;
@@ -342,28 +351,40 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
   uint2 dn = make_uint2(0xffffffffu, 0u);
   int64_t offn = 0;
   // issue the loads of group g into R and prefetch the descriptor of g + nwave
-  auto issue = [&](int64_t g, GroupRegs<kS>& R) {
-    group_issue(a, dn, offn, R);
-    if (g + nwave < g1) {
-      dn = a.desc[(g + nwave) * kGroupUnits + lane];
-      offn = a.grp_off[g + nwave];
-    }
+  // the descriptor and offset of group g: unconditional loads, clamped to
+  // the tile's last group (a conditional load would make the compiler copy
+  // the register at the join, and the copy waits for the load)
+  auto load_desc = [&](int64_t g) {
+    const int64_t gn = min(g, g1 - 1);
+    dn = a.desc[gn * kGroupUnits + lane];
+    offn = a.grp_off[gn];
   };
   if (gi < g1) {
-    dn = a.desc[gi * kGroupUnits + lane];
-    offn = a.grp_off[gi];
-    issue(gi, ga);
+    load_desc(gi);
+    wait_vmem();
+    group_issue(a, dn, offn, ga);
+    load_desc(gi + nwave);
   }
   __syncthreads();
+  // Each step first waits for everything this wavefront has loaded (the
+  // current group's records and the next descriptor, issued one group ago),
+  // then issues the next group's loads and accumulates the current group.
+  // An explicit wait here keeps the compiler from placing its own: it cannot
+  // count the group's loads (their number varies), so any wait it derived
+  // inside the accumulation would drain the next group's loads as well.
   while (gi < g1) {
     while (gi >= P.ge) phase_advance<kThreads>(a, P, slots, g0);
-    if (gi + nwave < g1) issue(gi + nwave, gb);
-    process_group(a, L, ga, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * a.slot_quads), P.lo, P.n);
+    wait_vmem();
+    if (gi + nwave < g1) group_issue(a, dn, offn, gb);
+    load_desc(gi + 2 * nwave);
+    process_group<kS, kSlotOnly>(a, L, ga, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * a.slot_quads), P.lo, P.n);
     gi += nwave;
     if (gi >= g1) break;
     while (gi >= P.ge) phase_advance<kThreads>(a, P, slots, g0);
-    if (gi + nwave < g1) issue(gi + nwave, ga);
-    process_group(a, L, gb, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * a.slot_quads), P.lo, P.n);
+    wait_vmem();
+    if (gi + nwave < g1) group_issue(a, dn, offn, ga);
+    load_desc(gi + 2 * nwave);
+    process_group<kS, kSlotOnly>(a, L, gb, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * a.slot_quads), P.lo, P.n);
     gi += nwave;
   }
   while (P.ph + 1 < P.ph1) phase_advance<kThreads>(a, P, slots, g0);  // boundaries after this wavefront's last group
@@ -411,15 +432,16 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
   }
 }
 
-// One workgroup per time tile of a single trace.
-template <int kThreads, int kS>
+// One workgroup per time tile of a single trace. kSlotOnly: every table phase
+// holds all the quads of its groups (the host launches it only then).
+template <int kThreads, int kS, bool kSlotOnly>
 __global__ void __launch_bounds__(kThreads) k_fwd_packed(PackedFwdArgs a) {
   extern __shared__ uint32_t lds[];
   const LdsLib L = stage_library_ml(a.lib, lds);
   unsigned long long* xs = reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.lib.lds_words_ml));
   unsigned long long* ss = xs + (1 << a.bins.tile_log2);
   float4* slots = a.phases ? reinterpret_cast<float4*>(ss + (1 << a.bins.tile_log2)) : nullptr;
-  fwd_tile_body<kThreads, kS>(a, L, xs, ss, (int32_t)blockIdx.x, slots);
+  fwd_tile_body<kThreads, kS, kSlotOnly>(a, L, xs, ss, (int32_t)blockIdx.x, slots);
 }
 
 // ---------------------------------------------------------------------------
@@ -451,7 +473,8 @@ struct BatchFwdArgs {
 
 // Workgroups stay resident and take work items from the queue until it is
 // empty; every workgroup ends once it draws an index past the last item.
-template <int kThreads, int kS>
+// kSlotOnly: every trace has table phases that hold all their groups' quads.
+template <int kThreads, int kS, bool kSlotOnly>
 __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ long long item_sh;
@@ -485,7 +508,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
         reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.base.lib.lds_words_ml));
     unsigned long long* ss = xs + (1 << T.bins.tile_log2);
     float4* slots = T.phases ? reinterpret_cast<float4*>(ss + (1 << T.bins.tile_log2)) : nullptr;
-    fwd_tile_body<kThreads, kS>(p, L, xs, ss, w.y, slots);
+    fwd_tile_body<kThreads, kS, kSlotOnly>(p, L, xs, ss, w.y, slots);
   }
 }
 

@@ -102,10 +102,13 @@ struct PackOut {
   std::vector<int64_t> h_reg_events;   // [n_tiles * n_gb] events per region
   // table phases of the forward: tile k's groups split into runs whose
   // cells' table quads [lo, lo + n) fit one LDS slot; phase p of tile k is
-  // phases[ph_off[k] + p] = (end group, lo, n, -), runs cover the tile's groups
+  // phases[ph_off[k] + p] = (end group, lo, n, full), runs cover the tile's
+  // groups; full = 1 when [lo, lo + n) holds every quad the phase's groups
+  // read (0 only for a group whose cells alone exceed the slot)
   int4* phases = nullptr;
   int32_t* ph_off = nullptr;       // [n_tiles + 1]
   int64_t n_phases = 0;
+  int32_t phases_full = 0;         // 1: every phase is full
   int32_t slot_quads = 0;          // slot capacity the phases were cut for
 };
 

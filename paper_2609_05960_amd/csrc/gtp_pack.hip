@@ -670,6 +670,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       const int64_t cap = in.slot_quads;
       std::vector<int4> ph;
       std::vector<int32_t> poff((size_t)n_tiles + 1, 0);
+      bool all_full = true;
       for (int32_t k = 0; k < n_tiles; ++k) {
         poff[k] = (int32_t)ph.size();
         int64_t g = htg[k];
@@ -694,17 +695,21 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
           }
           // a single group whose cells exceed the slot keeps its first cell's
           // tables (the other lanes read the tables from global memory)
+          int32_t full = 1;
           if (hi - lo > cap) {
             const int2 cc = hgc[(size_t)g];
             lo = in.cq_lo[cc.x];
             hi = std::min<int64_t>(in.cq_hi[cc.x], lo + cap);
+            full = 0;
+            all_full = false;
           }
-          ph.push_back(make_int4((int32_t)(e - htg[k]), (int32_t)lo, (int32_t)(hi - lo), 0));
+          ph.push_back(make_int4((int32_t)(e - htg[k]), (int32_t)lo, (int32_t)(hi - lo), full));
           g = e;
         }
       }
       poff[n_tiles] = (int32_t)ph.size();
       o.n_phases = (int64_t)ph.size();
+      o.phases_full = all_full ? 1 : 0;
       o.slot_quads = in.slot_quads;
       o.phases = (int4*)own(std::max<size_t>(ph.size(), 1) * sizeof(int4), e2);
       PK(e2);

@@ -421,16 +421,26 @@ hipError_t lds_limit(K kern, size_t static_lds = 0) {
 
 hipError_t set_packed_lds_limits() {
   hipError_t e = hipSuccess;
-  const hipError_t r[] = {lds_limit(k_fwd_packed<256, 8>),
-                          lds_limit(k_fwd_packed<512, 8>),
-                          lds_limit(k_fwd_packed<1024, 8>),
-                          lds_limit(k_fwd_packed<256, 16>),
-                          lds_limit(k_fwd_packed<512, 16>),
-                          lds_limit(k_fwd_batched<256, 8>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<512, 8>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<1024, 8>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<256, 16>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<512, 16>, kBatchStaticLds),
+  const hipError_t r[] = {lds_limit(k_fwd_packed<256, 8, false>),
+                          lds_limit(k_fwd_packed<512, 8, false>),
+                          lds_limit(k_fwd_packed<1024, 8, false>),
+                          lds_limit(k_fwd_packed<256, 16, false>),
+                          lds_limit(k_fwd_packed<512, 16, false>),
+                          lds_limit(k_fwd_packed<256, 8, true>),
+                          lds_limit(k_fwd_packed<512, 8, true>),
+                          lds_limit(k_fwd_packed<1024, 8, true>),
+                          lds_limit(k_fwd_packed<256, 16, true>),
+                          lds_limit(k_fwd_packed<512, 16, true>),
+                          lds_limit(k_fwd_batched<256, 8, false>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<512, 8, false>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<1024, 8, false>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<256, 16, false>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<512, 16, false>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<256, 8, true>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<512, 8, true>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<1024, 8, true>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<256, 16, true>, kBatchStaticLds),
+                          lds_limit(k_fwd_batched<512, 16, true>, kBatchStaticLds),
                           lds_limit(k_adjoint_packed<1024, 8>),
                           lds_limit(k_adjoint_packed<512, 16>)};
   for (hipError_t x : r)
@@ -1218,10 +1228,15 @@ gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, in
   const int sl = slots_of(c);
   const int th = threads_for_slots(tile_threads(c), sl);
   const dim3 grid((unsigned)B.n_tiles);
-#define GTP_PACKED_CASE(TH, SL)                                                     \
-  if (th == TH && sl == SL) {                                                       \
-    LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, SL>), grid, dim3(TH), lds, a);      \
-    return GTP_OK;                                                                  \
+  // every quad from the LDS slots when every phase holds all its groups' quads
+  const bool so = ph && pk.phases_full;
+#define GTP_PACKED_CASE(TH, SL)                                                            \
+  if (th == TH && sl == SL) {                                                              \
+    if (so)                                                                                \
+      LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, SL, true>), grid, dim3(TH), lds, a);     \
+    else                                                                                   \
+      LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, SL, false>), grid, dim3(TH), lds, a);    \
+    return GTP_OK;                                                                         \
   }
   GTP_PACKED_CASE(256, 8)
   GTP_PACKED_CASE(512, 8)
@@ -1387,8 +1402,11 @@ gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_s
     a.X = ptr<int64_t>(c->b_X);
     a.S = ptr<int64_t>(c->b_S);
     int32_t sq = 0;  // every trace's pack has the same slot size (same tile size)
-    for (auto& t : c->batch)
+    bool so = true;  // every trace's phases hold all their groups' quads
+    for (auto& t : c->batch) {
       if (t.pk.phases) sq = std::max(sq, t.pk.slot_quads);
+      so = so && t.pk.phases && t.pk.slot_quads > 0 && t.pk.phases_full;
+    }
     const size_t lds = packed_lds_bytes(c, lb) + slot_bytes(sq);
     const int sl = slots_of(c);
     const int th = threads_for_slots(tile_threads(c), sl);
@@ -1397,9 +1415,12 @@ gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_s
     per_cu = std::min(per_cu, 2048 / th);
     const int64_t wgs = std::min<int64_t>(c->batch_items, (int64_t)c->n_cu * per_cu);
     const dim3 grid((unsigned)wgs);
-#define GTP_BATCH_CASE(TH, SL)                                                          \
-  if (th == TH && sl == SL) {                                                           \
-    LAUNCH(c, "k_fwd_batched", (k_fwd_batched<TH, SL>), grid, dim3(TH), lds, a);         \
+#define GTP_BATCH_CASE(TH, SL)                                                                \
+  if (th == TH && sl == SL) {                                                                 \
+    if (so)                                                                                   \
+      LAUNCH(c, "k_fwd_batched", (k_fwd_batched<TH, SL, true>), grid, dim3(TH), lds, a);      \
+    else                                                                                      \
+      LAUNCH(c, "k_fwd_batched", (k_fwd_batched<TH, SL, false>), grid, dim3(TH), lds, a);     \
   }
     GTP_BATCH_CASE(256, 8)
     GTP_BATCH_CASE(512, 8)
