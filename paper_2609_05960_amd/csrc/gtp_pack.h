@@ -68,6 +68,10 @@ struct PackIn {
   int32_t* dbg_state = nullptr;   // optional [n_events] gate-major: state before the event's group
   int64_t* dbg_bin = nullptr;     // optional [n_events] gate-major: bin of the event
   std::vector<int32_t> cq_lo, cq_hi;  // [n_cells] quad index range of each cell's tables
+  // optional [G] gate weights: a cell's gates are ordered by decreasing
+  // weight (empty: by this trace's event counts). Traces that share gate
+  // records must share the order, so a batch passes one set of weights.
+  std::vector<int64_t> gate_weight;
   int32_t slot_quads = 0;         // quads one LDS table slot holds (0: no phases)
 };
 

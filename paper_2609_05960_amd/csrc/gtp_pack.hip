@@ -324,6 +324,32 @@ __global__ void __launch_bounds__(256) k_pk_gate_sorted(const int32_t* gperm, co
   ginit[gs] = gate_init[g];
 }
 
+// Sort key of gate g for the cell-sorted gate order: cell, then decreasing
+// weight (its event count unless weights are given; capped at 2^20 - 1),
+// then the gate index (n_cells < 2^16, gates < 2^28).
+constexpr int64_t kWeightCap = (1 << 20) - 1;
+__global__ void __launch_bounds__(256) k_pk_gate_keys(const int32_t* gate_cell, const int64_t* gate_off,
+                                                      const int64_t* weight, int64_t n_gates, uint64_t* keys) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_gates) return;
+  const int64_t w = weight ? weight[g] : gate_off[g + 1] - gate_off[g];
+  const uint64_t wq = (uint64_t)(kWeightCap - min(max(w, (int64_t)0), kWeightCap));
+  keys[g] = ((uint64_t)(uint32_t)gate_cell[g] << 48) | (wq << 28) | (uint64_t)g;
+}
+
+// The sorted keys as the permutation (sorted index -> gate), its inverse and
+// each sorted gate's cell.
+__global__ void __launch_bounds__(256) k_pk_gate_order(const uint64_t* skeys, int64_t n_gates, int32_t* perm,
+                                                       int32_t* rank, int32_t* pcell) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_gates) return;
+  const uint64_t k = skeys[r];
+  const int32_t g = (int32_t)(k & ((1u << 28) - 1u));
+  perm[r] = g;
+  rank[g] = (int32_t)r;
+  pcell[r] = (int32_t)(k >> 48);
+}
+
 int ceil_log2_u64(uint64_t x) {
   int l = 0;
   while ((1ull << l) < x) ++l;
@@ -403,16 +429,9 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
         o.h_gb_start[gb_base[c] + b] = cell_start[c] + (b << in.gate_block_log2);
         o.h_gb_cell[gb_base[c] + b] = c;
       }
-    std::vector<int32_t> rank((size_t)G), perm((size_t)G), pcell((size_t)G);
-    {
-      std::vector<int32_t> cur(cell_start);
-      for (int64_t g = 0; g < G; ++g) {
-        const int32_t c = in.h_gate_cell[g];
-        const int32_t r = cur[c]++;
-        rank[g] = r;
-        perm[r] = (int32_t)g;
-        pcell[r] = c;
-      }
+    if (n_cells >= (1 << 16) || G >= (1ll << 28)) {
+      snprintf(err, err_len, "pack: %d cells, %lld gates", n_cells, (long long)G);
+      return hipErrorInvalidValue;
     }
     const int gb_bits = ceil_log2_u64((uint64_t)n_gb);
     const int tile_bits = std::max(1, ceil_log2_u64((uint64_t)n_tiles));
@@ -438,9 +457,30 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     o.ginit = (uint32_t*)own((size_t)G * 4, e2);
     PK(e2);
     if (G > 0) {
-      PK(hipMemcpyAsync(d_rank, rank.data(), (size_t)G * 4, hipMemcpyHostToDevice, s));
-      PK(hipMemcpyAsync(o.gperm, perm.data(), (size_t)G * 4, hipMemcpyHostToDevice, s));
-      PK(hipMemcpyAsync(o.gcell, pcell.data(), (size_t)G * 4, hipMemcpyHostToDevice, s));
+      // Gates in cell order and, within a cell, by decreasing event count (or
+      // the given weights; ties by gate index): the gates active in most time
+      // tiles sit together, so the gate records one wavefront gathers share
+      // cache lines.
+      uint64_t* gk = (uint64_t*)tmp((size_t)G * 8, e2);
+      PK(e2);
+      uint64_t* gks = (uint64_t*)tmp((size_t)G * 8, e2);
+      PK(e2);
+      int64_t* d_wt = nullptr;
+      if ((int64_t)in.gate_weight.size() == G) {
+        d_wt = (int64_t*)tmp((size_t)G * 8, e2);
+        PK(e2);
+        PK(hipMemcpyAsync(d_wt, in.gate_weight.data(), (size_t)G * 8, hipMemcpyHostToDevice, s));
+      }
+      const dim3 gg((unsigned)((G + 255) / 256));
+      hipLaunchKernelGGL(k_pk_gate_keys, gg, dim3(256), 0, s, in.gate_cell, in.ev.gate_off, d_wt, (int64_t)G, gk);
+      PKLAUNCH("k_pk_gate_keys");
+      size_t tb = 0;
+      PK(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, gk, gks, (int)G, 0, 64, s));
+      void* tsort = tmp(tb, e2);
+      PK(e2);
+      PK(hipcub::DeviceRadixSort::SortKeys(tsort, tb, gk, gks, (int)G, 0, 64, s));
+      hipLaunchKernelGGL(k_pk_gate_order, gg, dim3(256), 0, s, gks, (int64_t)G, o.gperm, d_rank, o.gcell);
+      PKLAUNCH("k_pk_gate_order");
       hipLaunchKernelGGL(k_pk_gate_sorted, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, s, o.gperm, in.gate_out,
                          in.gate_init, (int64_t)G, o.gout, o.ginit);
       PKLAUNCH("k_pk_gate_sorted");

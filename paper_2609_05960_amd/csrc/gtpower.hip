@@ -486,7 +486,8 @@ BinSpec bins_for(gtp_ctx c, int64_t t_end) {
 // Packed layout of one event set (plan_buf: its gate-major lane-block plan);
 // sets B.tile_log2 / B.n_tiles.
 gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, BinSpec& B, PackOut& pk, double& pack_ms,
-                    int32_t* dbg_state = nullptr, int64_t* dbg_bin = nullptr) {
+                    int32_t* dbg_state = nullptr, int64_t* dbg_bin = nullptr,
+                    const std::vector<int64_t>* gate_weight = nullptr) {
   if (B.r_bits > kTimeBits) return fail(c, GTP_ERR_UNSUPPORTED, "bin width above 2^%d ps", kTimeBits);
   int lb = c->tun.bins_per_tile_log2 ? c->tun.bins_per_tile_log2 : auto_tile_log2(B.n_bins, B.r_bits, c->n_cu);
   if (lb + B.r_bits > kTimeBits)
@@ -513,6 +514,7 @@ gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, Bin
   in.dbg_bin = dbg_bin;
   in.cq_lo = c->h_cq_lo;
   in.cq_hi = c->h_cq_hi;
+  if (gate_weight) in.gate_weight = *gate_weight;
   in.slot_quads = slot_quads_for(c, lb);
   in.unit_events = unit_events_of(c);
   in.gate_block_log2 = c->tun.gate_block_log2 ? c->tun.gate_block_log2 : kGateBlockLog2;
@@ -1320,6 +1322,16 @@ gtp_status build_batch(gtp_ctx c) {
                                            : std::min(12, std::max(2, kTimeBits - B0.r_bits));
   if (packed_lds_bytes(c, lb) + kBatchStaticLds > kMaxLds)
     return fail(c, GTP_ERR_UNSUPPORTED, "tile of 2^%d bins and the library image exceed the LDS", lb);
+  // the traces share one set of gate records, so one gate order: by events
+  // over all traces
+  std::vector<int64_t> wt((size_t)c->n_gates, 0);
+  if (c->n_gates > 0) {
+    std::vector<int64_t> go((size_t)c->n_gates + 1);
+    for (int32_t i = 0; i < nt; ++i) {
+      HIPCHK(c, hipMemcpy(go.data(), c->batch[i].ev.gate_off, go.size() * 8, hipMemcpyDeviceToHost));
+      for (int64_t g = 0; g < c->n_gates; ++g) wt[g] += go[g + 1] - go[g];
+    }
+  }
   gtp_tuning saved = c->tun;
   c->tun.bins_per_tile_log2 = lb;
   std::vector<TraceDev> tab((size_t)nt);
@@ -1329,7 +1341,7 @@ gtp_status build_batch(gtp_ctx c) {
   for (int32_t i = 0; i < nt; ++i) {
     auto& t = c->batch[i];
     t.bins = bins_for(c, t.ev.t_end_ps);
-    const gtp_status st = pack_for(c, t.ev, t.plan, t.bins, t.pk, t.pack_ms);
+    const gtp_status st = pack_for(c, t.ev, t.plan, t.bins, t.pk, t.pack_ms, nullptr, nullptr, &wt);
     if (st != GTP_OK) {
       c->tun = saved;
       return st;
