@@ -52,7 +52,8 @@ typedef enum {
   GTP_ERR_EVENT_RANGE = 6,   /* time outside [0, t_end) or pin above the output pin */
   GTP_ERR_NOT_TOGGLE = 7,    /* an event sets a pin to the value it already holds */
   GTP_ERR_UNSUPPORTED = 8,   /* valid input outside the sizes this build handles */
-  GTP_ERR_SCALE_RANGE = 9    /* a leakage scale is negative, not finite or above GTP_MAX_LEAK_SCALE */
+  GTP_ERR_SCALE_RANGE = 9,   /* a leakage scale is negative, not finite or above GTP_MAX_LEAK_SCALE */
+  GTP_ERR_LOAD_RANGE = 10    /* a net load is negative, not finite or above 4x the library's largest load knot */
 } gtp_status;
 
 /* Leakage scales must lie in [0, GTP_MAX_LEAK_SCALE]; the fixed-point range of
@@ -68,8 +69,36 @@ gtp_status gtp_set_stream(gtp_ctx ctx, void* hip_stream);
 /* Message for the last non-OK status on ctx (never NULL; "" if none). */
 const char* gtp_last_error(gtp_ctx ctx);
 /* Wait for the ctx stream; report a condition flagged by kernels since the
- * last check (GTP_ERR_SCALE_RANGE) or a HIP error. */
+ * last check (GTP_ERR_LOAD_RANGE, GTP_ERR_SCALE_RANGE) or a HIP error. */
 gtp_status gtp_sync(gtp_ctx ctx);
+
+/*
+ * Fixed-point range of the bin accumulators (host only, no device work).
+ * Bin energies are accumulated as exact integers in units of 2^-m fJ (the
+ * leakage rate in units of 1e6 * 2^-m nW, so a rate unit held for 1 ps is one
+ * energy unit); m is chosen per event set and bin width as the largest
+ * m <= 40 with
+ *   2^m * (max_bin_events * event_energy_fj + bin_ps * leak_rate_fj_per_ps) < 2^62
+ *   2^m * 1e-6 * leak_value_nw < 2^30   (a quantised rate fits 30 bits)
+ * where event_energy_fj bounds |energy| of one event, leak_rate_fj_per_ps the
+ * total leakage rate and leak_value_nw one gate's scaled leakage value. With
+ * that m no bin and no rate can wrap. Returns GTP_ERR_UNSUPPORTED when m would
+ * fall below 30 (the quantised leakage rates would then miss the 1e-5
+ * relative budget of the waveform, whose readings are Sec. 2.4's overlap rule
+ * and Eq. leakage energy), GTP_ERR_INVALID_ARG for negative or non-finite
+ * inputs. gtp_forward applies it with bounds taken from the library (largest
+ * table entry, slew and load extrapolation factors), the netlist (the sum of
+ * every gate's largest leakage value at the largest scale) and the packed
+ * events (most events in one bin).
+ */
+typedef struct {
+  int64_t max_bin_events;
+  int64_t bin_ps;
+  double event_energy_fj;
+  double leak_rate_fj_per_ps;
+  double leak_value_nw;
+} gtp_range;
+gtp_status gtp_fixed_point_bits(const gtp_range* r, int32_t* m);
 
 /*
  * Cell library (HOST pointers, copied). For cell c with I = n_inputs[c]
@@ -103,7 +132,13 @@ gtp_status gtp_load_library(gtp_ctx ctx, const gtp_library* lib);
 /*
  * Netlist (DEVICE pointers, copied): gate g is an instance of cell
  * gate_cell[g] driving net gate_out_net[g]; bit p of gate_init_bits[g] is the
- * initial value of pin p (inputs 0..I-1, output I). Requires a library.
+ * initial value of pin p (inputs 0..I-1, output I), i.e. the gate state of
+ * Sec. 2.1 (the vector of the values on all pins of a gate) at time 0; the
+ * switching energy of Eq. switching energy charges the load of the output
+ * net. Requires a library. Errors: INVALID_ARG for a cell or net index out of
+ * range (checked on the device, synchronises) or a null array, NOT_LOADED
+ * without a library. Any failure leaves the ctx with no netlist and no events
+ * (the previous ones are dropped).
  */
 gtp_status gtp_load_netlist(gtp_ctx ctx, int64_t n_gates, int64_t n_nets, const int32_t* gate_cell,
                             const int32_t* gate_out_net, const uint32_t* gate_init_bits);
@@ -112,8 +147,10 @@ gtp_status gtp_load_netlist(gtp_ctx ctx, int64_t n_gates, int64_t n_nets, const 
  * Toggle events (DEVICE pointers, BORROWED), gate-major: the events of gate g
  * are [gate_off[g], gate_off[g+1]), sorted by time (events of one gate that
  * share a time form a group and may come in any order within it).
- * pin_bit = (pin << 1) | new_value; every event toggles its pin.
- * Window [0, t_end); every t in it.
+ * pin_bit = (pin << 1) | new_value; every event toggles its pin: the
+ * value-timestamp pairs of Sec. 2.1, merged over the pins of a gate (the
+ * per-gate activity the framework of Sec. 5 hands to the GPU).
+ * Window [0, t_end); every t in it. Arrays 16-byte aligned.
  */
 typedef struct {
   int64_t n_events, t_end_ps;
@@ -156,7 +193,7 @@ gtp_status gtp_num_bins(gtp_ctx ctx, int64_t* n_bins);
  * 0 = automatic, else 256, 512 or 1024. unit_events: longest run of one
  * gate's events one lane takes (the density split: denser gates are cut into
  * more runs), 0 = 16, else 1..16. gate_block_log2: gates per sort block of the
- * packed layout (log2), 0 = 14, else 6..20. Both paths give bit-identical
+ * packed layout (log2), 0 = 13, else 6..20. Both paths give bit-identical
  * waveforms.
  */
 typedef struct {
@@ -189,8 +226,9 @@ typedef struct {
 gtp_status gtp_plan_info(gtp_ctx ctx, gtp_plan_stats* out);
 
 /*
- * Autotuner: times the packed forward on the loaded events (and, if a batch
- * is loaded, the batched forward) for candidate tunings (bins per tile,
+ * Autotuner (the paper tunes its partition parameters per workload, Sec. 4.2
+ * and Sec. 6.5): times the packed forward on the loaded events (and, if a
+ * batch is loaded, the batched forward) for candidate tunings (bins per tile,
  * threads per tile workgroup, longest run per lane, gate-block size), keeps
  * the fastest and applies it with gtp_set_tuning. cache_json_path (HOST
  * string, may be NULL): a JSON file of earlier choices keyed by device and
@@ -202,13 +240,27 @@ gtp_status gtp_autotune(gtp_ctx ctx, const char* cache_json_path);
 /*
  * Forward: power_mw[b] (DEVICE, [n_bins], FP32) = binned power for net loads
  * net_load_ff (DEVICE, [n_nets]) and leakage scales leak_scale (DEVICE,
- * [n_gates]; NULL = all 1). Accumulation is exact int64 fixed point, so the
- * result does not depend on the execution order.
+ * [n_gates]; NULL = all 1). Per event the internal energy of the table the
+ * state before the event's timestamp group selects (Sec. 4.1), interpolated
+ * at (slew, load) (Sec. 2.2), plus switching energy on output events (Eq.
+ * switching energy, see sw_mode); leakage of every held state for its
+ * duration split over the bins it overlaps (Sec. 2.4, Eq. leakage energy);
+ * the per-timestamp order of Algorithm 1 (look up every event of a group with
+ * the state before it, then apply the group). Accumulation is exact int64
+ * fixed point (gtp_fixed_point_bits), so the result does not depend on the
+ * execution order. Loads must lie in [0, 4 x the largest load knot], scales
+ * in [0, GTP_MAX_LEAK_SCALE] (else GTP_ERR_LOAD_RANGE / _SCALE_RANGE at the
+ * next gtp_sync, the value used as 0). The first call after new events or
+ * parameters builds the packed layout (synchronises; gtp_plan_info reports
+ * its time); power_mw must hold n_bins floats.
  */
 gtp_status gtp_forward(gtp_ctx ctx, const float* net_load_ff, const float* leak_scale, float* power_mw);
 
 /*
- * Adjoint: given grad_power[b] = dL/dP_b (DEVICE, [n_bins]) writes
+ * Adjoint (no counterpart in the paper: the gradient of a loss of the
+ * forward's waveform, through the interpolation of Sec. 2.2, Eq. switching
+ * energy and Eq. leakage energy): given grad_power[b] = dL/dP_b (DEVICE,
+ * [n_bins]) writes
  * grad_net_load[n] = dL/d(net_load_ff[n]) (DEVICE, [n_nets]; nets no gate
  * drives get 0) and grad_leak_scale[g] = dL/d(leak_scale[g]) (DEVICE,
  * [n_gates]). Event times and states are not differentiated.
@@ -232,9 +284,12 @@ gtp_status gtp_load_traces(gtp_ctx ctx, int32_t n_traces, const gtp_events* trac
 gtp_status gtp_batch_bins(gtp_ctx ctx, int64_t* total, int64_t* offsets);
 
 /*
- * Forward of every trace of the batch in one persistent launch: workgroups
- * take (trace, time tile) work items from a device queue, largest first, so
- * uneven trace lengths balance. power_mw (DEVICE, [total bins]) gets the
+ * Forward of every trace of the batch in one persistent launch (the chunk
+ * loop of Sec. 5 processes event chunks one after another with the same
+ * kernel; here all traces share one launch): workgroups take (trace, time
+ * tile) work items from a device queue, largest first, so uneven trace
+ * lengths balance. The traces share one fixed-point exponent (the smallest
+ * any trace needs). power_mw (DEVICE, [total bins]) gets the
  * waveforms back to back (trace i from offsets[i]). use_graph = 1 records the
  * whole call (gate parameters, queue reset, persistent kernel, leakage scan,
  * finalize) as a HIP graph on its first use and replays it afterwards; it is

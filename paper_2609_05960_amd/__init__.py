@@ -32,13 +32,13 @@ HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-shared", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "HIP", 4: "NOT_LOADED", 5: "EVENT_ORDER",
-          6: "EVENT_RANGE", 7: "NOT_TOGGLE", 8: "UNSUPPORTED", 9: "SCALE_RANGE"}
+          6: "EVENT_RANGE", 7: "NOT_TOGGLE", 8: "UNSUPPORTED", 9: "SCALE_RANGE", 10: "LOAD_RANGE"}
 
 ABI_SYMBOLS = ["gtp_create", "gtp_destroy", "gtp_set_stream", "gtp_last_error", "gtp_sync", "gtp_load_library",
                "gtp_load_netlist", "gtp_load_events", "gtp_bad_event", "gtp_set_params", "gtp_num_bins",
                "gtp_set_tuning", "gtp_get_tuning", "gtp_plan_info", "gtp_autotune", "gtp_load_traces",
                "gtp_batch_bins", "gtp_forward_batched", "gtp_forward_trace", "gtp_forward", "gtp_adjoint", "gtp_debug_event_trace",
-               "gtp_device_bytes", "gtp_profile_enable", "gtp_profile_read"]
+               "gtp_device_bytes", "gtp_profile_enable", "gtp_profile_read", "gtp_fixed_point_bits"]
 
 
 def build(out: Optional[str] = None) -> str:
@@ -86,6 +86,24 @@ class _PlanStats(ctypes.Structure):
                 ("packed_bytes", ctypes.c_int64), ("pack_ms", ctypes.c_double), ("lane_steps", ctypes.c_int64)]
 
 
+class _Range(ctypes.Structure):
+    _fields_ = [("max_bin_events", ctypes.c_int64), ("bin_ps", ctypes.c_int64), ("event_energy_fj", ctypes.c_double),
+                ("leak_rate_fj_per_ps", ctypes.c_double), ("leak_value_nw", ctypes.c_double)]
+
+
+def fixed_point_bits(max_bin_events: int, bin_ps: int, event_energy_fj: float, leak_rate_fj_per_ps: float,
+                     leak_value_nw: float) -> int:
+    """Fixed-point exponent m the library uses for these bounds (gtp_fixed_point_bits)."""
+    L = load_library()
+    r = _Range(int(max_bin_events), int(bin_ps), float(event_energy_fj), float(leak_rate_fj_per_ps),
+               float(leak_value_nw))
+    m = ctypes.c_int32()
+    rc = L.gtp_fixed_point_bits(ctypes.byref(r), ctypes.byref(m))
+    if rc != 0:
+        raise GtpError(rc, "fixed-point range")
+    return m.value
+
+
 _lib = None
 
 
@@ -113,6 +131,7 @@ def load_library(path: Optional[str] = None):
         "gtp_forward_trace": [vp, i32, vp, vp, vp],
         "gtp_forward": [vp, vp, vp, vp], "gtp_adjoint": [vp, vp, vp, vp, vp, vp],
         "gtp_debug_event_trace": [vp, vp, vp],
+        "gtp_fixed_point_bits": [ctypes.POINTER(_Range), ctypes.POINTER(ctypes.c_int32)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -291,9 +310,8 @@ class Context:
     def forward_batched(self, net_load, leak_scale=None, out=None, use_graph: bool = False):
         net_load = self._vec(net_load, self.n_nets, "net_load")
         leak_scale = self._vec(leak_scale, self.n_gates, "leak_scale")
-        if out is None:
-            tot, _ = self.batch_bins()
-            out = self.torch.empty(tot, dtype=self.torch.float32, device=self.device)
+        tot, _ = self.batch_bins()
+        out = self._out(out, tot)
         self._chk(self.L.gtp_forward_batched(self.h, _dptr(net_load), _dptr(leak_scale), _dptr(out),
                                              1 if use_graph else 0))
         return out
@@ -301,9 +319,8 @@ class Context:
     def forward_trace(self, i: int, net_load, leak_scale=None, out=None):
         net_load = self._vec(net_load, self.n_nets, "net_load")
         leak_scale = self._vec(leak_scale, self.n_gates, "leak_scale")
-        if out is None:
-            _, offs = self.batch_bins()
-            out = self.torch.empty(int(offs[i + 1] - offs[i]), dtype=self.torch.float32, device=self.device)
+        _, offs = self.batch_bins()
+        out = self._out(out, int(offs[i + 1] - offs[i]))
         self._chk(self.L.gtp_forward_trace(self.h, int(i), _dptr(net_load), _dptr(leak_scale), _dptr(out)))
         return out
 
@@ -339,11 +356,18 @@ class Context:
             raise ValueError(f"{name} must be a contiguous float32 tensor of {n} elements on {self.device}")
         return x
 
+    def _out(self, out, n):
+        t = self.torch
+        if out is None:
+            return t.empty(n, dtype=t.float32, device=self.device)
+        if out.dtype != t.float32 or out.device != self.device or not out.is_contiguous() or out.numel() < n:
+            raise ValueError(f"out must be a contiguous float32 tensor of at least {n} elements on {self.device}")
+        return out
+
     def forward(self, net_load, leak_scale=None, out=None):
         net_load = self._vec(net_load, self.n_nets, "net_load")
         leak_scale = self._vec(leak_scale, self.n_gates, "leak_scale")
-        if out is None:
-            out = self.torch.empty(self.n_bins, dtype=self.torch.float32, device=self.device)
+        out = self._out(out, self.n_bins)
         self._chk(self.L.gtp_forward(self.h, _dptr(net_load), _dptr(leak_scale), _dptr(out)))
         return out
 
@@ -408,4 +432,4 @@ def peak_power_loss(P, beta: float):
 
 
 __all__ = ["Context", "GtpError", "binned_power", "peak_power_loss", "build", "load_library", "SO_PATH",
-           "ABI_SYMBOLS"]
+           "ABI_SYMBOLS", "fixed_point_bits"]

@@ -527,9 +527,10 @@ struct GateParamArgs {
   int64_t n_gates;
   float rate_scale;
   float max_scale;
+  float load_cap;            // loads must lie in [0, load_cap]
   GateParam* out;
   long long* l0_part;        // [blocks]
-  int32_t* flag;             // bit 0: a leakage scale out of range
+  int32_t* flag;             // bit 0: a leakage scale out of range; bit 1: a load out of range
 };
 
 __global__ void __launch_bounds__(256) k_gate_params(GateParamArgs a) {
@@ -539,7 +540,11 @@ __global__ void __launch_bounds__(256) k_gate_params(GateParamArgs a) {
   if (gs < a.n_gates) {
     const int32_t c = a.gcell[gs];
     const CellMeta cm = a.meta[c];
-    const float C = a.net_load[a.gout[gs]];
+    float C = a.net_load[a.gout[gs]];
+    if (!(C >= 0.0f && C <= a.load_cap)) {  // keeps every energy inside the fixed-point range
+      atomicOr(a.flag, 2);
+      C = 0.0f;
+    }
     float lam = a.leak_scale ? a.leak_scale[a.gperm[gs]] : 1.0f;
     if (!(lam >= 0.0f && lam <= a.max_scale)) {
       atomicOr(a.flag, 1);
@@ -714,6 +719,7 @@ struct PrepArgs {
   float rate_scale;   // FP32(2^m * 1e-6)
   float two_sh;       // 2^(m-32)
   float max_scale;
+  float load_cap;     // loads must lie in [0, load_cap]
   GatePrep* out;
   unsigned long long* L0;    // sum of quantised initial leakage rates
   int32_t* flag;             // bit 0: a leakage scale out of range
@@ -726,7 +732,11 @@ __global__ void __launch_bounds__(256) k_gate_prep(PrepArgs a) {
   if (g < a.n_gates) {
     const int32_t c = a.gate_cell[g];
     const CellMeta cm = a.meta[c];
-    const float C = a.net_load[a.gate_out[g]];
+    float C = a.net_load[a.gate_out[g]];
+    if (!(C >= 0.0f && C <= a.load_cap)) {
+      atomicOr(a.flag, 2);
+      C = 0.0f;
+    }
     float lam = a.leak_scale ? a.leak_scale[g] : 1.0f;
     if (!(lam >= 0.0f && lam <= a.max_scale)) {
       atomicOr(a.flag, 1);
@@ -963,9 +973,9 @@ __global__ void __launch_bounds__(256) k_adj_out(AdjOutArgs a) {
 // adjoint, packed layout: one workgroup per (gate block, tile range) item
 // ---------------------------------------------------------------------------
 // The gates of one gate block accumulate their two gradients in LDS (FP32
-// per unit); at the end the item stores them, with plain coalesced stores, as
-// its own row of a partial table, and the output kernel sums a gate's rows
-// in FP64. An item is a run of entries, each one group of the packed layout
+// sums over a unit's events, FP64 accumulators per gate); at the end the item
+// stores them, with plain coalesced stores, as its own row of a partial
+// table, and the output kernel sums a gate's rows in FP64. An item is a run of entries, each one group of the packed layout
 // restricted to the lanes (units) of the item's gate block: a group on the
 // boundary of two gate blocks appears in both blocks' entries with
 // complementary lane ranges. Each event reads its bin's (w_b, G_b) from the
@@ -985,20 +995,32 @@ struct AdjPackedArgs {
   const int4* entries;        // (group, tile, first lane, end lane)
   const AdjItem* items;
   const int32_t* gb_start;    // [n_gb + 1] first sorted gate of each gate block
-  float2* part;               // partial table: per item and gate (load, leakage)
+  double2* part;              // partial table: per item and gate (load, leakage)
   int32_t last_w;             // width of the last bin (ps)
-  const float2* wg;           // [n_bins] (w_b, G_b)
+  const float2* wg;           // [n_bins] (w_b, Gt_b): Gt_b = integral of w from the end of bin b to the end of its tile
+  const double* gtile;        // [n_tiles] integral of w from the end of tile k to the end of the window
   float dsw_rise, dsw_fall;
   int32_t slot_quads;         // LDS table room (quads)
 };
 
+// Relaxed FP64 add to LDS (one ds_add_f64).
+__device__ __forceinline__ void lds_add_f64(double* p, double v) {
+  (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // One entry's group (loaded into G): per event, the load gradient gains
 // w_b * dE/dC and, for an input event, the leakage gradient gains the step of
 // the cell leakage times the integral of w from the event to the window end.
+// That integral is split at the end of the event's tile: the part inside the
+// tile (w_b * (end_b - t) + Gt_b) is summed per event in FP32, the part after
+// the tile is the same for every event of the unit, so the unit adds its net
+// leakage step times it once, in FP64 (the steps of a gate telescope, so the
+// FP32 terms stay as small as the tile's share of the integral). The unit's
+// sums go into FP64 LDS accumulators of its gate.
 // Lookups are double-buffered by event parity as in the forward.
 template <int kS>
 __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const LdsLib& L, const GroupRegs<kS>& G,
-                                                  bool mine, int32_t tile, int32_t gs0, float* acc_c, float* acc_l,
+                                                  bool mine, int32_t tile, int32_t gs0, double* acc_c, double* acc_l,
                                                   const float4* tab, uint32_t q_lo, uint32_t q_n) {
   const BinSpec& B = a.f.bins;
   const uint32_t rmask = (1u << B.r_bits) - 1u;
@@ -1014,6 +1036,7 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
   const float* lk = L.leak + cm.leak_off;
   const int64_t tile_b0 = (int64_t)tile << B.tile_log2;
   float lk_cur = lk[G.d.y & ((1u << cm.n_in) - 1u)];
+  const float lk_first = lk_cur;
   struct Pre {
     float4 q;        // table quad
     float lk_after;  // leakage value of the input state after the event
@@ -1049,8 +1072,9 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
   }
   if (len > 0) {
     const int32_t li = (int32_t)(G.d.x & 0x0fffffffu) - gs0;
-    if (ac != 0.f) atomicAdd(&acc_c[li], ac);
-    if (al != 0.f) atomicAdd(&acc_l[li], al);
+    const double dl = (double)al + ((double)lk_cur - (double)lk_first) * a.gtile[tile];
+    if (ac != 0.f) lds_add_f64(&acc_c[li], (double)ac);
+    if (dl != 0.0) lds_add_f64(&acc_l[li], dl);
   }
 }
 
@@ -1064,9 +1088,9 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
   const int32_t ng = a.gb_start[it.gb + 1] - gs0;
   float4* tab = reinterpret_cast<float4*>(lds + packed_bins_word_offset(a.f.lib.lds_words_ml));
   for (int i = threadIdx.x; i < it.q_n; i += kThreads) tab[i] = a.f.lut.quads[(uint32_t)it.q_lo + (uint32_t)i];
-  float* acc_c = reinterpret_cast<float*>(tab + a.slot_quads);
-  float* acc_l = acc_c + ng;
-  for (int i = threadIdx.x; i < 2 * ng; i += kThreads) acc_c[i] = 0.f;
+  double* acc_c = reinterpret_cast<double*>(tab + a.slot_quads);
+  double* acc_l = acc_c + ng;
+  for (int i = threadIdx.x; i < 2 * ng; i += kThreads) acc_c[i] = 0.0;
   const int lane = (int)(threadIdx.x & 63);
   constexpr int nwave = kThreads / 64;
   const int64_t e1 = it.e1;
@@ -1110,17 +1134,26 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
     e += nwave;
   }
   __syncthreads();
-  float2* prow = a.part + it.row;
-  for (int i = threadIdx.x; i < ng; i += kThreads) prow[i] = make_float2(acc_c[i], acc_l[i]);
+  double2* prow = a.part + it.row;
+  for (int i = threadIdx.x; i < ng; i += kThreads) prow[i] = make_double2(acc_c[i], acc_l[i]);
 }
 
-// (w_b, G_b) in FP32 for the packed adjoint.
-__global__ void __launch_bounds__(256) k_adj_suffix_f(const double* w, const double* c, const double* exc, float2* wg,
-                                                      double* total, int64_t n_bins) {
+// Bin weights of the packed adjoint: (w_b, Gt_b) in FP32 with Gt_b the
+// integral of w from the end of bin b to the end of its tile, and per tile
+// the integral from the tile's end to the window end (FP64). G_b (the
+// integral from the end of bin b to the window end) is Gt_b + gtile[tile].
+__global__ void __launch_bounds__(256) k_adj_suffix_tiles(const double* w, const double* c, const double* exc,
+                                                          float2* wg, double* gtile, double* total, int64_t n_bins,
+                                                          int32_t tile_log2) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n_bins) return;
   const double tot = exc[n_bins - 1] + c[n_bins - 1];
-  wg[b] = make_float2((float)w[b], (float)(tot - (exc[b] + c[b])));
+  const int64_t k = b >> tile_log2;
+  const int64_t e = min(((k + 1) << tile_log2), n_bins) - 1;   // last bin of the tile
+  const double g_end = tot - (exc[e] + c[e]);
+  const double g_b = tot - (exc[b] + c[b]);
+  wg[b] = make_float2((float)w[b], (float)(g_b - g_end));
+  if (b == e) gtile[k] = g_end;
   if (b == 0) *total = tot;
 }
 
@@ -1131,7 +1164,7 @@ __global__ void __launch_bounds__(256) k_adj_suffix_f(const double* w, const dou
 // (plus the initial-state leakage times the integral of the bin weights over
 // the window).
 struct AdjOutSortedArgs {
-  const float2* part;
+  const double2* part;
   const int64_t* gb_row;      // [n_gb] first element of the block's rows
   const int32_t* gb_rows;     // [n_gb] rows (items) of the block
   const int32_t* gb_start;    // [n_gb + 1]
@@ -1158,12 +1191,12 @@ __global__ void __launch_bounds__(256) k_adj_out_sorted(AdjOutSortedArgs a) {
     if (a.gb_start[mid] <= gs) lo = mid; else hi = mid;
   }
   const int64_t ng = a.gb_start[lo + 1] - a.gb_start[lo];
-  const float2* p = a.part + a.gb_row[lo] + (gs - a.gb_start[lo]);
+  const double2* p = a.part + a.gb_row[lo] + (gs - a.gb_start[lo]);
   double gc = 0.0, gl = 0.0;
   for (int32_t j = 0; j < a.gb_rows[lo]; ++j) {
-    const float2 v = p[j * ng];
-    gc += (double)v.x;
-    gl += (double)v.y;
+    const double2 v = p[j * ng];
+    gc += v.x;
+    gl += v.y;
   }
   const int32_t g = a.gperm[gs];
   const CellMeta cm = a.meta[a.gcell[gs]];

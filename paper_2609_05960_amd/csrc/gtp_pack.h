@@ -15,7 +15,7 @@
 //          gate's pin values before its first event and before that event's
 //          timestamp group (carried-in state).
 //   order  units sorted by (tile, gate block, decreasing length, gate); a
-//          gate block is a run of at most 2^14 cell-sorted gates of one cell,
+//          gate block is a run of at most 2^13 (tunable) cell-sorted gates of one cell,
 //          so the units of one wavefront share a cell (table gathers stay in
 //          cache), have similar lengths (lanes stay busy) and, within a
 //          length, increasing gates (the per-unit gate-record loads of a
@@ -50,7 +50,7 @@
 
 namespace gtp {
 
-constexpr int kGateBlockLog2 = 14;   // default gate-block size (log2)
+constexpr int kGateBlockLog2 = 13;   // default gate-block size (log2): the adjoint holds 16 B per gate of a block in LDS
 
 struct PackIn {
   EvView ev;                  // gate-major events (device)
@@ -114,6 +114,11 @@ struct PackOut {
   int64_t n_phases = 0;
   int32_t phases_full = 0;         // 1: every phase is full
   int32_t slot_quads = 0;          // slot capacity the phases were cut for
+  // bounds for the fixed-point range (independent of the tuning): the most
+  // events in one bin and the largest |1 - alpha| + |alpha| of a slew weight
+  int64_t max_bin_events = 0;
+  float alpha_span = 1.0f;
+  int32_t mfix = 0;                // fixed-point exponent chosen for this layout (set by the ctx)
 };
 
 // Builds the packed layout on in.stream (synchronises it). Returns

@@ -225,6 +225,7 @@ struct FillArgs {
   int64_t* dsrc;
   int32_t* dbg_state;         // optional, gate-major: state before the event's group
   int64_t* dbg_bin;           // optional, gate-major: bin of the event
+  int32_t* alpha_span;        // max over events of |1 - alpha| + |alpha| (FP32 bits; positive floats order as ints)
 };
 
 // One wavefront per group: the unit descriptors, and every event's record in
@@ -257,6 +258,7 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
   uint32_t gsv = r.y >> 16;       // pin values before that event's timestamp group
   int64_t tprev = 0;
   int64_t off = a.grp_off[gi];
+  float span = 1.0f;   // |1 - alpha| + |alpha| of the lane's events (1 inside the axis)
   for (int kk = 0; kk < kLaneEvents; ++kk) {
     const bool on = len > kk;
     const uint64_t m = __ballot(on);
@@ -283,6 +285,7 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
       a.w32[pos] = (bl << B.r_bits) | rr | ((cur & in_mask) << kStateShift);
       a.row[pos] = q | ((pin == (uint32_t)cm.n_in ? 1u : 0u) << kOutBit) | (v << 31);
       a.alpha[pos] = al;
+      span = fmaxf(span, fabsf(1.0f - al) + fabsf(al));
       if (a.dbg_state) {
         a.dbg_state[e] = (int32_t)st;
         a.dbg_bin[e] = bin;
@@ -290,6 +293,29 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
     }
     off += __popcll(m);
   }
+  for (int o = 32; o > 0; o >>= 1) span = fmaxf(span, __shfl_xor(span, o, 64));
+  if (lane == 0) atomicMax(a.alpha_span, __float_as_int(span));
+}
+
+// Largest number of events in one bin: one workgroup per tile counts the
+// tile's packed events per bin in LDS (the in-tile bin is in the event
+// word), then one atomic max per tile.
+__global__ void __launch_bounds__(256) k_pk_bin_max(const uint32_t* w32, const int64_t* grp_off,
+                                                    const int32_t* tile_grp, int32_t tile_log2, int32_t r_bits,
+                                                    int32_t* out) {
+  extern __shared__ int32_t hist[];
+  const int nb = 1 << tile_log2;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int32_t k = blockIdx.x;
+  const int64_t e0 = grp_off[tile_grp[k]], e1 = grp_off[tile_grp[k + 1]];
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+    atomicAdd(&hist[(w32[e] & kTimeMask) >> r_bits], 1);
+  __syncthreads();
+  int mx = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) mx = max(mx, hist[i]);
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(out, mx);
 }
 
 // First and last cell among a group's units (-1 for an empty group); the
@@ -660,6 +686,12 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       PK(hipStreamSynchronize(s));
     }
     // ---- 6. fill --------------------------------------------------------
+    int32_t* d_bounds = (int32_t*)tmp(2 * sizeof(int32_t), e2);   // [alpha span bits, max events per bin]
+    PK(e2);
+    {
+      const int32_t init[2] = {__builtin_bit_cast(int32_t, 1.0f), 0};
+      PK(hipMemcpyAsync(d_bounds, init, sizeof init, hipMemcpyHostToDevice, s));
+    }
     o.w32 = (uint32_t*)own((size_t)nev * 4, e2);
     PK(e2);
     o.row = (uint32_t*)own((size_t)nev * 4, e2);
@@ -689,11 +721,21 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       fa.dbg_bin = in.dbg_bin;
       fa.desc = o.desc;
       fa.dsrc = o.dsrc;
+      fa.alpha_span = d_bounds;
       const int64_t threads = ng * kGroupUnits;
       hipLaunchKernelGGL(k_pk_fill, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, fa);
       PKLAUNCH("k_pk_fill");
+      hipLaunchKernelGGL(k_pk_bin_max, dim3((unsigned)n_tiles), dim3(256), (size_t)4 << B.tile_log2, s, o.w32,
+                         o.grp_off, o.tile_grp, B.tile_log2, B.r_bits, d_bounds + 1);
+      PKLAUNCH("k_pk_bin_max");
     }
-    PK(hipStreamSynchronize(s));
+    {
+      int32_t hb[2] = {0, 0};
+      PK(hipMemcpyAsync(hb, d_bounds, sizeof hb, hipMemcpyDeviceToHost, s));
+      PK(hipStreamSynchronize(s));
+      o.alpha_span = __builtin_bit_cast(float, hb[0]);
+      o.max_bin_events = hb[1];
+    }
     // ---- 7. table phases ------------------------------------------------
     if (in.slot_quads > 0 && ng > 0) {
       int2* gc = (int2*)tmp((size_t)ng * 8, e2);

@@ -47,6 +47,7 @@ struct DevBuf {
 struct gtp_ctx_s {
   int dev = 0;
   int n_cu = 256;
+  size_t dev_total = 0;       // device memory (bytes); no single buffer can exceed it
   hipStream_t stream = nullptr;
   std::string err;
   int64_t bad_event = -1;
@@ -58,7 +59,11 @@ struct gtp_ctx_s {
   int32_t n_cells = 0, n_slew = 0, n_load = 0, n_map = 0, n_leak = 0;
   int64_t n_tables = 0;
   int32_t lds_words = 0;
-  int32_t mfix = 40;          // energy unit 2^-mfix fJ (see gtp_device.h)
+  // fixed-point range inputs (see choose_mfix): largest |table entry|, the
+  // largest leakage value, the load limit and the largest |1-beta|+|beta| a
+  // load within [0, load_cap] gives on any cell's load axis
+  double lib_tmax = 0.0, lib_leak_max = 0.0, load_cap = 0.0, beta_span = 1.0;
+  std::vector<double> h_leak_max;    // [n_cells] largest leakage value of the cell
   std::vector<int32_t> h_nin;
   std::vector<int32_t> h_cq_lo, h_cq_hi;   // per cell: quad index range of its tables
   std::vector<int32_t> h_gate_cell;  // host copy of the netlist's cells
@@ -69,6 +74,7 @@ struct gtp_ctx_s {
   bool net_ok = false;
   int64_t n_gates = 0, n_nets = 0;
   bool unique_out = true;   // no net has two driving gates
+  double r_bound = 0.0;     // bound on the total leakage rate (fJ/ps) for scales up to GTP_MAX_LEAK_SCALE
   DevBuf gate_cell, gate_out, gate_init;
 
   // events
@@ -121,7 +127,7 @@ struct gtp_ctx_s {
   // per-call work buffers
   DevBuf gprep, gparam, X, S, exS, L0, flag, first_bad;
   DevBuf l0_part, tile_tot, tile_base;   // packed forward: leakage-rate partials and tile sums
-  DevBuf adj_w, adj_c, adj_exc, adj_wg, adj_total, gC, gL;
+  DevBuf adj_w, adj_c, adj_exc, adj_wg, adj_gtile, adj_total, gC, gL;
 
   // packed adjoint work items (built from the pack's region tables)
   bool adj_ok = false;
@@ -216,10 +222,18 @@ void prof_clear(gtp_ctx c) {
     prof_end((c));                                                        \
   } while (0)
 
+void drop_graph(gtp_ctx c);
+
 gtp_status ensure(gtp_ctx c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.bytes >= bytes) return GTP_OK;
+  if (c->dev_total > 0 && bytes > c->dev_total)
+    return fail(c, GTP_ERR_OUT_OF_MEMORY, "a buffer of %zu bytes exceeds the device memory (%zu bytes)", bytes,
+                c->dev_total);
   if (b.p) {
+    // a recorded graph may hold this buffer's address: it is recorded again
+    // on its next use
+    drop_graph(c);
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(b.p);
     c->dev_bytes -= (int64_t)b.bytes;
@@ -296,13 +310,22 @@ LibView lib_view(gtp_ctx c) {
   return L;
 }
 
-LutArgs lut_args(gtp_ctx c) {
+float rate_scale_of(int32_t m) { return (float)(std::ldexp(1.0, m) * 1e-6); }
+
+// Exponent for kernels whose fixed-point values are not used (the adjoint
+// and per-event trace of the gate-major path read only the gate state and the
+// interpolation weights).
+constexpr int32_t kAnyMfix = 32;
+constexpr int32_t kMaxMfix = 40;   // energy unit 2^-40 fJ at most
+constexpr int32_t kMinMfix = 30;   // below this the quantised leakage rates lose the 1e-5 budget
+
+LutArgs lut_args(gtp_ctx c, int32_t m) {
   LutArgs A;
   A.quads = ptr<float4>(c->quads);
   A.n_slew = c->n_slew;
   A.n_load = c->n_load;
-  A.rate_scale = (float)(std::ldexp(1.0, c->mfix) * 1e-6);
-  A.two_sh = (float)std::ldexp(1.0, c->mfix - 32);
+  A.rate_scale = rate_scale_of(m);
+  A.two_sh = (float)std::ldexp(1.0, m - 32);
   return A;
 }
 
@@ -448,7 +471,6 @@ hipError_t set_packed_lds_limits() {
   return e;
 }
 
-void drop_graph(gtp_ctx c);
 void drop_batch_packs(gtp_ctx c);
 void drop_batch(gtp_ctx c);
 
@@ -481,6 +503,29 @@ BinSpec bins_for(gtp_ctx c, int64_t t_end) {
   B.t32 = (t_end <= ((int64_t)1 << 32)) ? 1 : 0;
   B.n_tiles = 0;
   return B;
+}
+
+// Fixed-point exponent of a packed event set: the largest m <= 40 for which no
+// bin can overflow (gtp_fixed_point_bits). Bounds: per event |energy| <=
+// max|T| * (|1-alpha|+|alpha|)_max * (|1-beta|+|beta|)_max + load_cap * V^2
+// (loads are limited to [0, load_cap] by the gate-record kernels), per bin at
+// most max_bin_events events, and a total leakage rate below r_bound.
+gtp_status choose_mfix(gtp_ctx c, const PackOut& pk, int64_t bin_ps, int32_t* m) {
+  gtp_range r;
+  r.max_bin_events = pk.max_bin_events;
+  r.bin_ps = bin_ps;
+  const double v2 = c->par.vdd * c->par.vdd;
+  r.event_energy_fj = c->lib_tmax * (double)pk.alpha_span * c->beta_span +
+                      c->load_cap * v2 * (c->par.sw_mode ? 1.0 : 0.5);
+  r.leak_rate_fj_per_ps = c->r_bound;
+  r.leak_value_nw = (double)GTP_MAX_LEAK_SCALE * c->lib_leak_max;
+  const gtp_status st = gtp_fixed_point_bits(&r, m);
+  if (st != GTP_OK)
+    return fail(c, st,
+                "bins of %lld ps with up to %lld events each exceed the fixed-point range (event energy bound %.3g fJ, "
+                "leakage rate bound %.3g fJ/ps)",
+                (long long)bin_ps, (long long)pk.max_bin_events, r.event_energy_fj, r.leak_rate_fj_per_ps);
+  return GTP_OK;
 }
 
 // Packed layout of one event set (plan_buf: its gate-major lane-block plan);
@@ -541,6 +586,12 @@ gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, Bin
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   c->dev_bytes += pk.bytes;
+  const gtp_status ms = choose_mfix(c, pk, B.D, &pk.mfix);
+  if (ms != GTP_OK) {
+    c->dev_bytes -= pk.bytes;
+    pack_free(&pk);
+    return ms;
+  }
   return GTP_OK;
 }
 
@@ -552,17 +603,16 @@ gtp_status build_pack(gtp_ctx c) {
   return GTP_OK;
 }
 
-// LDS of the packed adjoint: the staged library, then two FP32 accumulators
-// per gate of the largest gate block.
 // LDS of the packed adjoint: the library prefix, one cell's table quads (as
-// many as fit, at most one slot), two FP32 accumulators per gate of the
+// many as fit, at most one slot), two FP64 accumulators per gate of the
 // largest gate block.
+constexpr int64_t kAdjAccBytes = 16;   // per gate: load and leakage-scale gradient (FP64)
 int32_t adj_slot_quads(gtp_ctx c, int32_t max_gb) {
-  const int64_t room = (int64_t)kMaxLds - (int64_t)ml_lds_bytes(c) - 8 * (int64_t)max_gb;
+  const int64_t room = (int64_t)kMaxLds - (int64_t)ml_lds_bytes(c) - kAdjAccBytes * (int64_t)max_gb;
   return (int32_t)std::max<int64_t>(0, std::min<int64_t>(room / 16, kMaxSlotQuads));
 }
 size_t adj_lds_bytes(gtp_ctx c, int32_t max_gb) {
-  return ml_lds_bytes(c) + 16 * (size_t)adj_slot_quads(c, max_gb) + (size_t)max_gb * 8;
+  return ml_lds_bytes(c) + 16 * (size_t)adj_slot_quads(c, max_gb) + (size_t)max_gb * kAdjAccBytes;
 }
 
 // Work items of the packed adjoint. Entries list, gate block by gate block
@@ -662,7 +712,7 @@ gtp_status adj_plan(gtp_ctx c) {
   TRY(ensure(c, c->adj_gbs, pk.h_gb_start.size() * 4));
   TRY(ensure(c, c->adj_gbrow, gb_row.size() * 8));
   TRY(ensure(c, c->adj_gbrows, gb_rows.size() * 4));
-  TRY(ensure(c, c->adj_part, (size_t)std::max<int64_t>(rows, 1) * 8));
+  TRY(ensure(c, c->adj_part, (size_t)std::max<int64_t>(rows, 1) * sizeof(double2)));
   HIPCHK(c, hipMemcpyAsync(c->adj_items.p, hs.data(), hs.size() * sizeof(AdjItem), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->adj_entries.p, ent.data(), ent.size() * sizeof(int4), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->adj_gbs.p, pk.h_gb_start.data(), pk.h_gb_start.size() * 4, hipMemcpyHostToDevice,
@@ -676,7 +726,7 @@ gtp_status adj_plan(gtp_ctx c) {
   return GTP_OK;
 }
 
-gtp_status gate_prep(gtp_ctx c, const float* net_load, const float* leak_scale) {
+gtp_status gate_prep(gtp_ctx c, const float* net_load, const float* leak_scale, int32_t m) {
   TRY(ensure(c, c->gprep, (size_t)std::max<int64_t>(c->n_gates, 1) * sizeof(GatePrep)));
   TRY(ensure(c, c->L0, 8));
   TRY(fill_u64(c, c->L0.p, 1, 0ull));
@@ -696,8 +746,9 @@ gtp_status gate_prep(gtp_ctx c, const float* net_load, const float* leak_scale) 
   a.n_gates = c->n_gates;
   a.vdd = c->par.vdd;
   a.sw_mode = c->par.sw_mode;
-  a.rate_scale = (float)(std::ldexp(1.0, c->mfix) * 1e-6);
+  a.rate_scale = rate_scale_of(m);
   a.max_scale = GTP_MAX_LEAK_SCALE;
+  a.load_cap = (float)c->load_cap;
   a.out = ptr<GatePrep>(c->gprep);
   a.L0 = ptr<unsigned long long>(c->L0);
   a.flag = ptr<int32_t>(c->flag);
@@ -711,6 +762,23 @@ gtp_status gate_prep(gtp_ctx c, const float* net_load, const float* leak_scale) 
 // C ABI
 // ============================================================================
 extern "C" {
+
+gtp_status gtp_fixed_point_bits(const gtp_range* r, int32_t* m_out) {
+  if (!r || !m_out || r->max_bin_events < 0 || r->bin_ps < 1 || !(r->event_energy_fj >= 0.0) ||
+      !(r->leak_rate_fj_per_ps >= 0.0) || !(r->leak_value_nw >= 0.0) || !std::isfinite(r->event_energy_fj) ||
+      !std::isfinite(r->leak_rate_fj_per_ps) || !std::isfinite(r->leak_value_nw))
+    return GTP_ERR_INVALID_ARG;
+  const double bound = (double)r->max_bin_events * r->event_energy_fj + (double)r->bin_ps * r->leak_rate_fj_per_ps;
+  int m = kMaxMfix;
+  // the largest m with 2^m * bound < 2^62 (2x margin for the sum of the
+  // terms and the FP64 evaluation) and a quantised rate below 2^30
+  while (m >= kMinMfix && (std::ldexp(bound, m) >= std::ldexp(1.0, 62) ||
+                           std::ldexp(r->leak_value_nw * 1e-6, m) >= std::ldexp(1.0, 30)))
+    --m;
+  if (m < kMinMfix) return GTP_ERR_UNSUPPORTED;
+  *m_out = m;
+  return GTP_OK;
+}
 
 gtp_status gtp_create(gtp_ctx* out, int hip_device, void* hip_stream) {
   if (!out) return GTP_ERR_INVALID_ARG;
@@ -727,6 +795,8 @@ gtp_status gtp_create(gtp_ctx* out, int hip_device, void* hip_stream) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
       c->n_cu = cus;
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, hip_device) == hipSuccess) c->dev_total = pr.totalGlobalMem;
     (void)hipGetLastError();
   }
   c->stream = (hipStream_t)hip_stream;
@@ -762,7 +832,7 @@ gtp_status gtp_destroy(gtp_ctx c) {
   DevBuf* all[] = {&c->lib_img, &c->load_axis, &c->load_inv, &c->quads, &c->gate_cell, &c->gate_out,
                    &c->gate_init, &c->plan_blk, &c->blk_tmp, &c->blk_tmp2, &c->scan_sums, &c->gprep, &c->gparam, &c->l0_part, &c->tile_tot, &c->tile_base,
                    &c->X, &c->S, &c->exS, &c->L0, &c->flag, &c->first_bad, &c->adj_w, &c->adj_c, &c->adj_exc,
-                   &c->adj_wg, &c->adj_total, &c->gC, &c->gL, &c->adj_items, &c->adj_entries, &c->adj_gbs, &c->adj_gbrow, &c->adj_gbrows, &c->adj_part, &c->b_tab, &c->b_items, &c->b_queue,
+                   &c->adj_wg, &c->adj_gtile, &c->adj_total, &c->gC, &c->gL, &c->adj_items, &c->adj_entries, &c->adj_gbs, &c->adj_gbrow, &c->adj_gbrows, &c->adj_part, &c->b_tab, &c->b_items, &c->b_queue,
                    &c->b_fin, &c->b_X, &c->b_S, &c->b_exS, &c->tun_in, &c->tun_out};
   for (DevBuf* b : all) release(c, *b);
   prof_clear(c);
@@ -792,6 +862,9 @@ gtp_status gtp_sync(gtp_ctx c) {
   if (flag) {
     fill_u64(c, c->flag.p, 1, 0ull);
     (void)hipStreamSynchronize(c->stream);
+    if (flag & 2)
+      return fail(c, GTP_ERR_LOAD_RANGE, "a net load was negative, not finite or above %g fF (used as 0)",
+                  c->load_cap);
     return fail(c, GTP_ERR_SCALE_RANGE, "a leakage scale was negative, not finite or above %g (used as 0)",
                 (double)GTP_MAX_LEAK_SCALE);
   }
@@ -915,11 +988,33 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
   c->h_nin.assign(lib->n_inputs, lib->n_inputs + nc);
   c->h_cq_lo = cq_lo;
   c->h_cq_hi = cq_hi;
-  // fixed-point exponent m: a quantised rate lambda*leak*2^m*1e-6 must stay
-  // below 2^30; m <= 40 keeps event energies up to 2^23 fJ exact in int64
-  const double top = (double)GTP_MAX_LEAK_SCALE * std::max(leak_max, 1e-3f);
-  const int m = (int)std::floor(std::log2(1073741824.0 * 1e6 / top));
-  c->mfix = std::max(24, std::min(40, m));
+  // inputs of the fixed-point range (choose_mfix): largest |table entry|,
+  // largest leakage value, the load limit (4x the largest load knot) and the
+  // largest |1-beta|+|beta| of a load in [0, load_cap] (at one of the two
+  // ends: beta is affine in the load on each axis segment)
+  {
+    double tmax = 0.0, lmax_axis = 0.0, span = 1.0;
+    for (int64_t i = 0; i < lib->n_tables * ns * nl; ++i) tmax = std::max(tmax, std::fabs((double)lib->tables_fj[i]));
+    for (int cc = 0; cc < nc; ++cc) lmax_axis = std::max(lmax_axis, (double)lib->load_axis_ff[cc * nl + nl - 1]);
+    const double cap = 4.0 * std::max(lmax_axis, 1e-3);
+    for (int cc = 0; cc < nc; ++cc) {
+      const float* la = lib->load_axis_ff + cc * nl;
+      for (double C : {0.0, cap}) {
+        int j = 0;
+        for (int m = 1; m < nl - 1; ++m) j += ((double)la[m] <= C) ? 1 : 0;
+        const double b = (C - la[j]) / ((double)la[j + 1] - la[j]);
+        span = std::max(span, std::fabs(1.0 - b) + std::fabs(b));
+      }
+    }
+    c->lib_tmax = tmax;
+    c->lib_leak_max = leak_max;
+    c->load_cap = cap;
+    c->beta_span = span;
+    c->h_leak_max.assign((size_t)nc, 0.0);
+    for (int cc = 0; cc < nc; ++cc)
+      for (int64_t st = 0; st < (1ll << lib->n_inputs[cc]); ++st)
+        c->h_leak_max[cc] = std::max(c->h_leak_max[cc], (double)lib->leak_nw[lib->leak_base[cc] + st]);
+  }
   c->lib_ok = true;
   c->net_ok = false;
   c->ev_ok = false;
@@ -997,6 +1092,16 @@ gtp_status gtp_load_netlist(gtp_ctx c, int64_t n_gates, int64_t n_nets, const in
     return fail(c, GTP_ERR_INVALID_ARG, "n_gates=%lld n_nets=%lld", (long long)n_gates, (long long)n_nets);
   if (n_gates > 0 && (!gate_cell || !gate_out_net || !gate_init_bits))
     return fail(c, GTP_ERR_INVALID_ARG, "null netlist array");
+  // from here on the old netlist is being replaced: until the new one is
+  // checked and committed, the ctx holds none (a failed load leaves the
+  // netlist, the events and every layout unloaded)
+  c->net_ok = false;
+  c->ev_ok = false;
+  drop_pack(c);
+  drop_batch(c);
+  c->n_gates = 0;
+  c->n_nets = 0;
+  c->h_gate_cell.clear();
   TRY(ensure(c, c->gate_cell, (size_t)n_gates * 4));
   TRY(ensure(c, c->gate_out, (size_t)n_gates * 4));
   TRY(ensure(c, c->gate_init, (size_t)n_gates * 4));
@@ -1030,6 +1135,11 @@ gtp_status gtp_load_netlist(gtp_ctx c, int64_t n_gates, int64_t n_nets, const in
       }
       seen[(size_t)o] = 1;
     }
+  }
+  {
+    double r = 0.0;
+    for (int32_t cc : c->h_gate_cell) r += c->h_leak_max[(size_t)cc];
+    c->r_bound = (double)GTP_MAX_LEAK_SCALE * r * 1e-6;
   }
   c->n_gates = n_gates;
   c->n_nets = n_nets;
@@ -1137,7 +1247,7 @@ gtp_status gtp_plan_info(gtp_ctx c, gtp_plan_stats* out) {
 }  // extern "C"
 
 namespace {
-gtp_status final_bins(gtp_ctx c, float* power_mw) {
+gtp_status final_bins(gtp_ctx c, float* power_mw, int32_t m) {
   const int64_t NB = c->bins.n_bins;
   TRY(scan_exclusive<int64_t, OpAdd>(c, ptr<int64_t>(c->S), ptr<int64_t>(c->exS), NB, (int64_t)0, OpAdd()));
   FinArgs f;
@@ -1149,7 +1259,7 @@ gtp_status final_bins(gtp_ctx c, float* power_mw) {
   f.n_bins = NB;
   f.D = c->bins.D;
   f.t_end = c->bins.t_end;
-  f.out_scale = std::ldexp(1.0, -c->mfix) / (double)c->bins.D;
+  f.out_scale = std::ldexp(1.0, -m) / (double)c->bins.D;
   LAUNCH(c, "k_finalize", k_finalize, dim3(grid_for(NB, 256)), dim3(256), 0, f);
   return GTP_OK;
 }
@@ -1172,8 +1282,9 @@ gtp_status gate_params_for(gtp_ctx c, const PackOut& pk, const float* net_load, 
   a.meta = L.meta;
   a.leak = L.leak;
   a.n_gates = c->n_gates;
-  a.rate_scale = (float)(std::ldexp(1.0, c->mfix) * 1e-6);
+  a.rate_scale = rate_scale_of(pk.mfix);
   a.max_scale = GTP_MAX_LEAK_SCALE;
+  a.load_cap = (float)c->load_cap;
   a.out = ptr<GateParam>(c->gparam);
   a.l0_part = ptr<long long>(c->l0_part);
   a.flag = ptr<int32_t>(c->flag);
@@ -1196,11 +1307,11 @@ gtp_status gate_params(gtp_ctx c, const float* net_load, const float* leak_scale
 }
 
 // Fields of the packed forward shared by every trace.
-PackedFwdArgs packed_common(gtp_ctx c) {
+PackedFwdArgs packed_common(gtp_ctx c, int32_t m) {
   PackedFwdArgs a{};
   a.gparam = ptr<GateParam>(c->gparam);
   a.lib = lib_view(c);
-  a.lut = lut_args(c);
+  a.lut = lut_args(c, m);
   a.sw_mode = c->par.sw_mode;
   a.v2 = c->par.vdd * c->par.vdd;
   return a;
@@ -1211,7 +1322,7 @@ int tile_threads(gtp_ctx c) { return c->tun.tile_threads ? c->tun.tile_threads :
 // Packed forward of one trace into X/S.
 gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, int64_t* X, int64_t* S,
                               long long* tile_tot = nullptr) {
-  PackedFwdArgs a = packed_common(c);
+  PackedFwdArgs a = packed_common(c, pk.mfix);
   a.tile_tot = tile_tot;
   a.w32 = pk.w32;
   a.row = pk.row;
@@ -1274,7 +1385,7 @@ gtp_status packed_power(gtp_ctx c, const PackOut& pk, const BinSpec& B, float* p
   f.D = B.D;
   f.t_end = B.t_end;
   f.tile_log2 = B.tile_log2;
-  f.out_scale = std::ldexp(1.0, -c->mfix) / (double)B.D;
+  f.out_scale = std::ldexp(1.0, -pk.mfix) / (double)B.D;
   LAUNCH(c, "k_finalize_tiles", k_finalize_tiles, dim3(grid_for(NB, 256)), dim3(256), 0, f);
   return GTP_OK;
 }
@@ -1370,6 +1481,13 @@ gtp_status build_batch(gtp_ctx c) {
     for (int32_t k = 0; k < ntile; ++k) items.push_back({go[tg[k + 1]] - go[tg[k]], make_int2(i, k)});
   }
   c->tun = saved;
+  // one fixed-point exponent for the batch (the traces share the gate
+  // records): the smallest any trace needs
+  {
+    int32_t m = kMaxMfix;
+    for (auto& t : c->batch) m = std::min(m, t.pk.mfix);
+    for (auto& t : c->batch) t.pk.mfix = m;
+  }
   std::stable_sort(items.begin(), items.end(),
                    [](const std::pair<int64_t, int2>& x, const std::pair<int64_t, int2>& y) { return x.first > y.first; });
   std::vector<int2> it(items.size());
@@ -1406,7 +1524,7 @@ gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_s
   const int lb = c->batch[0].bins.tile_log2;
   if (c->batch_items > 0) {
     BatchFwdArgs a;
-    a.base = packed_common(c);
+    a.base = packed_common(c, c->batch[0].pk.mfix);
     a.traces = ptr<TraceDev>(c->b_tab);
     a.items = ptr<int2>(c->b_items);
     a.n_items = c->batch_items;
@@ -1453,7 +1571,7 @@ gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_s
   f.P = power_mw;
   f.total_bins = NB;
   f.D = c->bins.D;
-  f.out_scale = std::ldexp(1.0, -c->mfix) / (double)c->bins.D;
+  f.out_scale = std::ldexp(1.0, -c->batch[0].pk.mfix) / (double)c->bins.D;
   if (NB > 0) LAUNCH(c, "k_finalize_batched", k_finalize_batched, dim3(grid_for(NB, 256)), dim3(256), 0, f);
   return GTP_OK;
 }
@@ -1499,12 +1617,15 @@ gtp_status gtp_forward(gtp_ctx c, const float* net_load_ff, const float* leak_sc
   TRY(ensure(c, c->S, (size_t)NB * 8));
   TRY(ensure(c, c->exS, (size_t)NB * 8));
   const int64_t N = c->ev.n_events;
+  // the packed layout also fixes the fixed-point exponent of this event set,
+  // which the one-gate-per-thread path uses too (so both give the same bits)
+  TRY(build_pack(c));
+  const int32_t m = c->pk.mfix;
   if (c->tun.algo == 0) {
-    TRY(build_pack(c));
     TRY(gate_params(c, net_load_ff, leak_scale));
     return packed_power(c, c->pk, c->bins, power_mw);
   } else {
-    TRY(gate_prep(c, net_load_ff, leak_scale));
+    TRY(gate_prep(c, net_load_ff, leak_scale, m));
     TRY(fill_u64(c, c->X.p, NB, 0ull));
     TRY(fill_u64(c, c->S.p, NB, 0ull));
     if (c->n_gates > 0 && N > 0) {
@@ -1512,14 +1633,14 @@ gtp_status gtp_forward(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       a.ev = ev_view(c);
       a.gprep = ptr<GatePrep>(c->gprep);
       a.lib = lib_view(c);
-      a.lut = lut_args(c);
+      a.lut = lut_args(c, m);
       a.bins = c->bins;
       a.X = ptr<unsigned long long>(c->X);
       a.S = ptr<unsigned long long>(c->S);
       LAUNCH(c, "k_gate_serial", k_gate_serial, dim3(grid_for(c->n_gates, kFwdThreads)), dim3(kFwdThreads), lib_lds_bytes(c), a);
     }
   }
-  return final_bins(c, power_mw);
+  return final_bins(c, power_mw, m);
 }
 
 gtp_status gtp_load_traces(gtp_ctx c, int32_t n_traces, const gtp_events* traces, int validate) {
@@ -1683,7 +1804,7 @@ gtp_status gtp_autotune(gtp_ctx c, const char* cache_json_path) {
   const int tiles[] = {11, 12, 13};
   const int threads[] = {512, 1024};
   const int units[] = {8, 16};
-  const int gblocks[] = {12, 14};
+  const int gblocks[] = {12, 13};
   for (int tl : tiles)
     for (int un : units)
       for (int gbl : gblocks)
@@ -1749,14 +1870,16 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
   const float dsw_rise = (float)(c->par.sw_mode == 0 ? 0.5 * v2 : v2);
   const float dsw_fall = (float)(c->par.sw_mode == 0 ? 0.5 * v2 : 0.0);
   if (packed) {
-    LAUNCH(c, "k_adj_suffix_f", k_adj_suffix_f, dim3(grid_for(NB, 256)), dim3(256), 0,
+    TRY(ensure(c, c->adj_gtile, (size_t)std::max(c->bins.n_tiles, 1) * 8));
+    LAUNCH(c, "k_adj_suffix_tiles", k_adj_suffix_tiles, dim3(grid_for(NB, 256)), dim3(256), 0,
            (const double*)ptr<double>(c->adj_w), (const double*)ptr<double>(c->adj_c),
-           (const double*)ptr<double>(c->adj_exc), ptr<float2>(c->adj_wg), ptr<double>(c->adj_total), NB);
+           (const double*)ptr<double>(c->adj_exc), ptr<float2>(c->adj_wg), ptr<double>(c->adj_gtile),
+           ptr<double>(c->adj_total), NB, (int32_t)c->bins.tile_log2);
     TRY(gate_params(c, net_load_ff, leak_scale));
     if (c->adj_n_items > 0) {
       const PackOut& pk = c->pk;
       AdjPackedArgs a;
-      a.f = packed_common(c);
+      a.f = packed_common(c, pk.mfix);
       a.f.w32 = pk.w32;
       a.f.row = pk.row;
       a.f.alpha = pk.alpha;
@@ -1767,9 +1890,10 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       a.entries = ptr<int4>(c->adj_entries);
       a.items = ptr<AdjItem>(c->adj_items);
       a.gb_start = ptr<int32_t>(c->adj_gbs);
-      a.part = ptr<float2>(c->adj_part);
+      a.part = ptr<double2>(c->adj_part);
       a.last_w = (int32_t)(c->bins.t_end - (c->bins.n_bins - 1) * c->bins.D);
       a.wg = ptr<float2>(c->adj_wg);
+      a.gtile = ptr<double>(c->adj_gtile);
       a.dsw_rise = dsw_rise;
       a.dsw_fall = dsw_fall;
       a.slot_quads = adj_slot_quads(c, c->adj_max_gb);
@@ -1786,7 +1910,7 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
              c->n_nets, 0);
     if (c->n_gates > 0) {
       AdjOutSortedArgs o;
-      o.part = ptr<float2>(c->adj_part);
+      o.part = ptr<double2>(c->adj_part);
       o.gb_row = ptr<int64_t>(c->adj_gbrow);
       o.gb_rows = ptr<int32_t>(c->adj_gbrows);
       o.gb_start = ptr<int32_t>(c->adj_gbs);
@@ -1807,7 +1931,7 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
     return GTP_OK;
   }
   LAUNCH(c, "k_adj_suffix", k_adj_suffix, dim3(grid_for(NB, 256)), dim3(256), 0, (const double*)ptr<double>(c->adj_w), (const double*)ptr<double>(c->adj_c), (const double*)ptr<double>(c->adj_exc), ptr<double2>(c->adj_wg), ptr<double>(c->adj_total), NB);
-  TRY(gate_prep(c, net_load_ff, leak_scale));
+  TRY(gate_prep(c, net_load_ff, leak_scale, kAnyMfix));
   TRY(fill_u64(c, c->gC.p, c->n_nets, 0ull));
   TRY(fill_u64(c, c->gL.p, c->n_gates, 0ull));
   if (c->n_blocks > 0) {
@@ -1817,7 +1941,7 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
     a.gprep = ptr<GatePrep>(c->gprep);
     a.gate_out = ptr<int32_t>(c->gate_out);
     a.lib = lib_view(c);
-    a.lut = lut_args(c);
+    a.lut = lut_args(c, kAnyMfix);
     a.bins = c->bins;
     a.wg = ptr<double2>(c->adj_wg);
     a.dsw_rise = dsw_rise;
@@ -1865,13 +1989,13 @@ gtp_status gtp_debug_event_trace(gtp_ctx c, int32_t* state_before, int64_t* bin)
     c->pack_ok = true;
     return GTP_OK;
   }
-  TRY(gate_prep(c, ptr<float>(c->adj_w), nullptr));
+  TRY(gate_prep(c, ptr<float>(c->adj_w), nullptr, kAnyMfix));
   TraceArgs a;
   a.ev = ev_view(c);
   a.plan = ptr<uint2>(c->plan_blk);
   a.gprep = ptr<GatePrep>(c->gprep);
   a.lib = lib_view(c);
-  a.lut = lut_args(c);
+  a.lut = lut_args(c, kAnyMfix);
   a.bins = c->bins;
   a.state = state_before;
   a.bin = bin;

@@ -41,3 +41,25 @@ def test_null_and_no_device_errors():
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(RuntimeError):
         gtp.load_library(str(tmp_path / "nope.so"))
+
+
+def test_fixed_point_bits():
+    """Host-side range check of the bin accumulators: the largest m <= 40 with
+    2^m * bound < 2^62 and 2^m * 1e-6 * leak < 2^30, UNSUPPORTED below 30."""
+    f = gtp.fixed_point_bits
+    # 1M gates at 50 ps bins: the finest unit
+    assert f(300, 50, 500.0, 800.0, 800.0) == 40
+    for n, D, e, r, lk in ((10 ** 6, 1 << 22, 430.0, 800.0, 800.0), (5 * 10 ** 5, 1 << 22, 430.0, 6.4e-3, 800.0),
+                           (1, 1, 1.0, 1.0, 1.0e4)):
+        m = f(n, D, e, r, lk)
+        bound = n * e + D * r
+        assert 30 <= m <= 40
+        assert 2.0 ** m * bound < 2.0 ** 62 and 2.0 ** m * 1e-6 * lk < 2.0 ** 30
+        if m < 40:   # maximal: one more bit would break a bound
+            assert 2.0 ** (m + 1) * bound >= 2.0 ** 62 or 2.0 ** (m + 1) * 1e-6 * lk >= 2.0 ** 30
+    with pytest.raises(gtp.GtpError) as ei:
+        f(10 ** 9, 1 << 22, 1.0e4, 1.0e4, 800.0)
+    assert ei.value.status == "UNSUPPORTED"
+    with pytest.raises(gtp.GtpError) as ei:
+        f(-1, 50, 1.0, 1.0, 1.0)
+    assert ei.value.status == "INVALID_ARG"

@@ -35,9 +35,12 @@ def gpu_adjoint(prob, gP, algo=0, **tuning):
 
 
 def close(a, b, what):
-    scale = np.abs(b).max()
-    err = np.abs(a - b).max()
-    assert err <= TOL * max(scale, 1e-30), f"{what}: max abs err {err:.3e} vs scale {scale:.3e}"
+    """Per-element bar: |a - b| <= TOL * max(|b|, 1e-3 * max|b|)."""
+    bar = TOL * np.maximum(np.abs(b), 1e-3 * np.abs(b).max())
+    bar = np.maximum(bar, 1e-300)
+    r = np.abs(a - b) / bar
+    i = int(r.argmax())
+    assert r[i] <= 1.0, f"{what}: element {i}: {a[i]:.9e} vs {b[i]:.9e} ({r[i]:.2f} x the bar)"
 
 
 @pytest.mark.parametrize("algo", [0, 1])

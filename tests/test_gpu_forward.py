@@ -138,3 +138,17 @@ def test_plan_invariants(O):
     assert -(-info["n_units"] // 64) <= info["n_groups"] <= -(-info["n_units"] // 64) + info["n_tiles"]
     assert info["n_tiles"] == -(-prob.n_bins // (1 << info["tile_log2"]))
     check(prob, O)
+
+
+def test_wide_bins_fixed_point_range(O):
+    """Bins of 2^22 ps holding 10^6 events each (about 10^7 fJ per bin, beyond
+    the 2^23 fJ an energy unit of 2^-40 fJ allows in int64): the library picks
+    a coarser unit from its range bounds, and every bin still matches the
+    oracle within 1e-5 (a wrapped accumulator would be off by 2^63 units)."""
+    lib = synth.make_library(12, 4, 4)
+    net = synth.make_netlist(12, lib, 16)
+    counts = np.full(16, 125000, np.int64)
+    ev = synth.make_events(12, lib, net, counts, np.zeros(16, np.uint8), 1 << 23, 1000, p_tie=0.1)
+    prob = synth.Problem(lib, net, ev, vdd=0.8, bin_ps=1 << 22)
+    P, P64 = check(prob, O)
+    assert (P64 * prob.bin_ps).max() > 2.0 ** 23   # the per-bin energy the unit 2^-40 fJ cannot hold

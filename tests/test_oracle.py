@@ -417,3 +417,24 @@ def test_planted_mistakes_are_caught(tmp_path, plant):
         except (AssertionError, oracle.OracleError):
             failed.append(pin.__name__)
     assert failed, f"planted mistake '{PLANTS[plant]}' passed every pin"
+
+
+def test_adjoint_fd_protocol_scaled_workload(O):
+    """The oracle's analytic gradient of the smooth peak-power loss against
+    central finite differences of its own FP64 forward, with the adjoint
+    workload's protocol (100 nets: 50 uniform, 50 by |gradient|, h = 1e-3 fF,
+    knots skipped; 100 leakage scales, h = 1e-3 relative) on the 1M-gate,
+    1e8-event recipe at 1/100 scale. Bar: 1e-6 x max(|g_fd|, 1e-3 max|g_fd|)
+    (FP64 on both sides; the GPU's bar is 1e-4)."""
+    from _fd import fd_errors, fd_load, fd_scale, sample_gates, sample_nets
+    prob = synth.make_problem("C5", scale=0.01)
+    P64 = O.power(prob)
+    beta = 1.0 / (0.05 * P64.mean())
+    _, gP = oracle.lse_loss_grad(P64, beta)
+    gl, gs = O.adjoint(prob, gP)
+    rng = np.random.default_rng(7)
+    nets = sample_nets(prob, gl, rng)
+    gates = sample_gates(prob, gs, rng)
+    assert len(nets) >= 80 and len(gates) >= 80
+    assert fd_errors(gl[nets], fd_load(O, prob, P64, beta, nets), tol=1e-6) <= 1.0
+    assert fd_errors(gs[gates], fd_scale(O, prob, P64, beta, gates), tol=1e-6) <= 1.0
