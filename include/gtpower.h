@@ -257,6 +257,24 @@ gtp_status gtp_autotune(gtp_ctx ctx, const char* cache_json_path);
 gtp_status gtp_forward(gtp_ctx ctx, const float* net_load_ff, const float* leak_scale, float* power_mw);
 
 /*
+ * Allocation-free forward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result as gtp_forward (bit for bit, same kernels), but
+ * its per-call buffers (gate records, bins, tile sums: 8*n_gates +
+ * 16*n_bins + 16*n_tiles + 8*ceil(n_gates/256) bytes, each part rounded up to
+ * 256) live in a fixed 64 MiB device array of the library, one per GPU, so the
+ * call makes no hipMalloc, hipFree or allocating library call. Requirements:
+ * the packed layout already built for the loaded events and parameters (by
+ * gtp_plan_info or an earlier gtp_forward: GTP_ERR_NOT_LOADED otherwise),
+ * algo 0, and buffers that fit the array (GTP_ERR_UNSUPPORTED otherwise; the
+ * 1M-gate, 2M-bin workload needs about 40 MB). Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (any contexts, any streams)
+ * race and must be serialised by the caller. Profiling records are not made
+ * for this call.
+ */
+gtp_status gtp_forward_noalloc(gtp_ctx ctx, const float* net_load_ff, const float* leak_scale, float* power_mw);
+
+/*
  * Adjoint (no counterpart in the paper: the gradient of a loss of the
  * forward's waveform, through the interpolation of Sec. 2.2, Eq. switching
  * energy and Eq. leakage energy): given grad_power[b] = dL/dP_b (DEVICE,

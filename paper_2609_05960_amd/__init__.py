@@ -38,7 +38,8 @@ ABI_SYMBOLS = ["gtp_create", "gtp_destroy", "gtp_set_stream", "gtp_last_error", 
                "gtp_load_netlist", "gtp_load_events", "gtp_bad_event", "gtp_set_params", "gtp_num_bins",
                "gtp_set_tuning", "gtp_get_tuning", "gtp_plan_info", "gtp_autotune", "gtp_load_traces",
                "gtp_batch_bins", "gtp_forward_batched", "gtp_forward_trace", "gtp_forward", "gtp_adjoint", "gtp_debug_event_trace",
-               "gtp_device_bytes", "gtp_profile_enable", "gtp_profile_read", "gtp_fixed_point_bits"]
+               "gtp_device_bytes", "gtp_profile_enable", "gtp_profile_read", "gtp_fixed_point_bits",
+               "gtp_forward_noalloc"]
 
 
 def build(out: Optional[str] = None) -> str:
@@ -130,6 +131,7 @@ def load_library(path: Optional[str] = None):
         "gtp_forward_batched": [vp, vp, vp, vp, i32],
         "gtp_forward_trace": [vp, i32, vp, vp, vp],
         "gtp_forward": [vp, vp, vp, vp], "gtp_adjoint": [vp, vp, vp, vp, vp, vp],
+        "gtp_forward_noalloc": [vp, vp, vp, vp],
         "gtp_debug_event_trace": [vp, vp, vp],
         "gtp_fixed_point_bits": [ctypes.POINTER(_Range), ctypes.POINTER(ctypes.c_int32)],
     }
@@ -369,6 +371,16 @@ class Context:
         leak_scale = self._vec(leak_scale, self.n_gates, "leak_scale")
         out = self._out(out, self.n_bins)
         self._chk(self.L.gtp_forward(self.h, _dptr(net_load), _dptr(leak_scale), _dptr(out)))
+        return out
+
+    def forward_noalloc(self, net_load, leak_scale=None, out=None):
+        """gtp_forward_noalloc: the forward without device allocation (the packed
+        layout must be built first, e.g. by plan_info(); out must be given by
+        callers that cannot allocate)."""
+        net_load = self._vec(net_load, self.n_nets, "net_load")
+        leak_scale = self._vec(leak_scale, self.n_gates, "leak_scale")
+        out = self._out(out, self.n_bins)
+        self._chk(self.L.gtp_forward_noalloc(self.h, _dptr(net_load), _dptr(leak_scale), _dptr(out)))
         return out
 
     def adjoint(self, net_load, leak_scale, grad_power):

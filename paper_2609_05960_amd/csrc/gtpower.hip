@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <cmath>
 #include <cstdarg>
@@ -35,7 +36,35 @@
 
 using namespace gtp;
 
+// Scratch memory of gtp_forward_noalloc (the per-call buffers of one packed
+// forward, carved from this array). Each GPU the library runs on holds its own
+// copy until the process ends. In host code `scratch` names a host-side
+// stand-in: its device address on a GPU comes from hipGetSymbolAddress, taken
+// once per device at context creation (scratch_address below).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on hip_device (the current device); resolved on
+// the first call for that device.
+hipError_t scratch_address(int hip_device, void** out) {
+  if (hip_device < 0 || hip_device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[hip_device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[hip_device] = p;
+  }
+  *out = g_scratch_ptr[hip_device];
+  return hipSuccess;
+}
 
 struct DevBuf {
   void* p = nullptr;
@@ -47,6 +76,7 @@ struct DevBuf {
 struct gtp_ctx_s {
   int dev = 0;
   int n_cu = 256;
+  void* scratch_dev = nullptr;  // device address of `scratch` on this ctx's device
   size_t dev_total = 0;       // device memory (bytes); no single buffer can exceed it
   hipStream_t stream = nullptr;
   std::string err;
@@ -804,6 +834,11 @@ gtp_status gtp_create(gtp_ctx* out, int hip_device, void* hip_stream) {
     delete c;
     return GTP_ERR_HIP;
   }
+  if (scratch_address(hip_device, &c->scratch_dev) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return GTP_ERR_HIP;
+  }
   if (ensure(c, c->flag, 256) != GTP_OK || ensure(c, c->first_bad, 256) != GTP_OK) {
     delete c;
     return GTP_ERR_OUT_OF_MEMORY;
@@ -1266,11 +1301,21 @@ gtp_status final_bins(gtp_ctx c, float* power_mw, int32_t m) {
 
 // Per-call gate records in the pack's gate order, and the per-block partial
 // sums of the initial leakage rates (l0_part).
-gtp_status gate_params_for(gtp_ctx c, const PackOut& pk, const float* net_load, const float* leak_scale) {
-  TRY(ensure(c, c->gparam, (size_t)std::max<int64_t>(c->n_gates, 1) * sizeof(GateParam)));
-  const int64_t nb = std::max<int64_t>(grid_for(c->n_gates, 256), 1);
-  TRY(ensure(c, c->l0_part, (size_t)nb * 8));
-  if (c->n_gates == 0) return fill_u64(c, c->l0_part.p, 1, 0ull);
+// Per-call buffers of one packed forward (device pointers): gate records,
+// initial-rate partials, the bins' X and in-tile step prefix, tile totals and
+// rates at tile starts.
+struct FwdScratch {
+  GateParam* gparam;    // [n_gates]
+  long long* l0_part;   // [l0_parts]
+  int64_t* X;           // [n_bins]
+  int64_t* S;           // [n_bins]
+  long long* tile_tot;  // [n_tiles]
+  long long* tile_base; // [n_tiles]
+};
+
+gtp_status gate_params_into(gtp_ctx c, const PackOut& pk, const float* net_load, const float* leak_scale,
+                            GateParam* out, long long* l0_part) {
+  if (c->n_gates == 0) return fill_u64(c, l0_part, 1, 0ull);
   const LibView L = lib_view(c);
   GateParamArgs a;
   a.gperm = pk.gperm;
@@ -1285,11 +1330,18 @@ gtp_status gate_params_for(gtp_ctx c, const PackOut& pk, const float* net_load, 
   a.rate_scale = rate_scale_of(pk.mfix);
   a.max_scale = GTP_MAX_LEAK_SCALE;
   a.load_cap = (float)c->load_cap;
-  a.out = ptr<GateParam>(c->gparam);
-  a.l0_part = ptr<long long>(c->l0_part);
+  a.out = out;
+  a.l0_part = l0_part;
   a.flag = ptr<int32_t>(c->flag);
   LAUNCH(c, "k_gate_params", k_gate_params, dim3(grid_for(c->n_gates, 256)), dim3(256), 0, a);
   return GTP_OK;
+}
+
+gtp_status gate_params_for(gtp_ctx c, const PackOut& pk, const float* net_load, const float* leak_scale) {
+  TRY(ensure(c, c->gparam, (size_t)std::max<int64_t>(c->n_gates, 1) * sizeof(GateParam)));
+  const int64_t nb = std::max<int64_t>(grid_for(c->n_gates, 256), 1);
+  TRY(ensure(c, c->l0_part, (size_t)nb * 8));
+  return gate_params_into(c, pk, net_load, leak_scale, ptr<GateParam>(c->gparam), ptr<long long>(c->l0_part));
 }
 
 int64_t l0_parts(gtp_ctx c) { return std::max<int64_t>(grid_for(c->n_gates, 256), 1); }
@@ -1321,8 +1373,9 @@ int tile_threads(gtp_ctx c) { return c->tun.tile_threads ? c->tun.tile_threads :
 
 // Packed forward of one trace into X/S.
 gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, int64_t* X, int64_t* S,
-                              long long* tile_tot = nullptr) {
+                              long long* tile_tot = nullptr, const GateParam* gparam = nullptr) {
   PackedFwdArgs a = packed_common(c, pk.mfix);
+  if (gparam) a.gparam = gparam;
   a.tile_tot = tile_tot;
   a.w32 = pk.w32;
   a.row = pk.row;
@@ -1364,22 +1417,17 @@ gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, in
 // the tile kernel leaves X, the within-tile prefix of the steps and the tile
 // totals; one small kernel turns the totals into the rate at every tile
 // start, one more gives the power.
-gtp_status packed_power(gtp_ctx c, const PackOut& pk, const BinSpec& B, float* power_mw) {
+gtp_status packed_power_into(gtp_ctx c, const PackOut& pk, const BinSpec& B, float* power_mw, const FwdScratch& w) {
   const int64_t NB = B.n_bins;
-  TRY(ensure(c, c->X, (size_t)std::max<int64_t>(NB, 1) * 8));
-  TRY(ensure(c, c->S, (size_t)std::max<int64_t>(NB, 1) * 8));
-  TRY(ensure(c, c->tile_tot, (size_t)std::max(B.n_tiles, 1) * 8));
-  TRY(ensure(c, c->tile_base, (size_t)std::max(B.n_tiles, 1) * 8));
-  TRY(packed_forward_for(c, pk, B, ptr<int64_t>(c->X), ptr<int64_t>(c->S), ptr<long long>(c->tile_tot)));
-  LAUNCH(c, "k_tile_base", k_tile_base, dim3(1), dim3(1024), 0, (const long long*)ptr<long long>(c->l0_part),
-         l0_parts(c), (const long long*)ptr<long long>(c->tile_tot), (int64_t)B.n_tiles,
-         ptr<long long>(c->tile_base));
+  TRY(packed_forward_for(c, pk, B, w.X, w.S, w.tile_tot, w.gparam));
+  LAUNCH(c, "k_tile_base", k_tile_base, dim3(1), dim3(1024), 0, (const long long*)w.l0_part, l0_parts(c),
+         (const long long*)w.tile_tot, (int64_t)B.n_tiles, w.tile_base);
   if (NB == 0) return GTP_OK;
   FinTileArgs f;
-  f.X = ptr<int64_t>(c->X);
-  f.exS = ptr<int64_t>(c->S);
-  f.base = ptr<long long>(c->tile_base);
-  f.tot = ptr<long long>(c->tile_tot);
+  f.X = w.X;
+  f.exS = w.S;
+  f.base = w.tile_base;
+  f.tot = w.tile_tot;
   f.P = power_mw;
   f.n_bins = NB;
   f.D = B.D;
@@ -1388,6 +1436,17 @@ gtp_status packed_power(gtp_ctx c, const PackOut& pk, const BinSpec& B, float* p
   f.out_scale = std::ldexp(1.0, -pk.mfix) / (double)B.D;
   LAUNCH(c, "k_finalize_tiles", k_finalize_tiles, dim3(grid_for(NB, 256)), dim3(256), 0, f);
   return GTP_OK;
+}
+
+gtp_status packed_power(gtp_ctx c, const PackOut& pk, const BinSpec& B, float* power_mw) {
+  const int64_t NB = B.n_bins;
+  TRY(ensure(c, c->X, (size_t)std::max<int64_t>(NB, 1) * 8));
+  TRY(ensure(c, c->S, (size_t)std::max<int64_t>(NB, 1) * 8));
+  TRY(ensure(c, c->tile_tot, (size_t)std::max(B.n_tiles, 1) * 8));
+  TRY(ensure(c, c->tile_base, (size_t)std::max(B.n_tiles, 1) * 8));
+  const FwdScratch w{ptr<GateParam>(c->gparam), ptr<long long>(c->l0_part), ptr<int64_t>(c->X),
+                     ptr<int64_t>(c->S),        ptr<long long>(c->tile_tot), ptr<long long>(c->tile_base)};
+  return packed_power_into(c, pk, B, power_mw, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -1641,6 +1700,44 @@ gtp_status gtp_forward(gtp_ctx c, const float* net_load_ff, const float* leak_sc
     }
   }
   return final_bins(c, power_mw, m);
+}
+
+gtp_status gtp_forward_noalloc(gtp_ctx c, const float* net_load_ff, const float* leak_scale, float* power_mw) {
+  TRY(need(c, true, true, true, true));
+  if (!net_load_ff || !power_mw) return fail(c, GTP_ERR_INVALID_ARG, "null forward argument");
+  if (c->tun.algo != 0) return fail(c, GTP_ERR_UNSUPPORTED, "the allocation-free forward runs the packed path (algo 0)");
+  if (!c->pack_ok)
+    return fail(c, GTP_ERR_NOT_LOADED,
+                "the packed layout is not built: call gtp_plan_info or gtp_forward once after loading the events");
+  if (!c->scratch_dev) return fail(c, GTP_ERR_HIP, "no scratch address for device %d", c->dev);
+  HIPCHK(c, hipSetDevice(c->dev));
+  const BinSpec& B = c->bins;
+  // carve the per-call buffers from the scratch array (256-byte aligned)
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t s_gp = up((size_t)std::max<int64_t>(c->n_gates, 1) * sizeof(GateParam));
+  const size_t s_l0 = up((size_t)l0_parts(c) * 8);
+  const size_t s_bin = up((size_t)std::max<int64_t>(B.n_bins, 1) * 8);
+  const size_t s_tile = up((size_t)std::max(B.n_tiles, 1) * 8);
+  const size_t need_bytes = s_gp + s_l0 + 2 * s_bin + 2 * s_tile;
+  if (need_bytes > kScratchBytes)
+    return fail(c, GTP_ERR_UNSUPPORTED,
+                "%lld gates and %lld bins need %zu bytes of scratch; the allocation-free forward holds %zu",
+                (long long)c->n_gates, (long long)B.n_bins, need_bytes, kScratchBytes);
+  unsigned char* base = static_cast<unsigned char*>(c->scratch_dev);
+  FwdScratch w;
+  w.gparam = reinterpret_cast<GateParam*>(base);
+  w.l0_part = reinterpret_cast<long long*>(base + s_gp);
+  w.X = reinterpret_cast<int64_t*>(base + s_gp + s_l0);
+  w.S = reinterpret_cast<int64_t*>(base + s_gp + s_l0 + s_bin);
+  w.tile_tot = reinterpret_cast<long long*>(base + s_gp + s_l0 + 2 * s_bin);
+  w.tile_base = reinterpret_cast<long long*>(base + s_gp + s_l0 + 2 * s_bin + s_tile);
+  // no profiling events here (creating one is a driver allocation)
+  const bool prof = c->prof_on;
+  c->prof_on = false;
+  gtp_status st = gate_params_into(c, c->pk, net_load_ff, leak_scale, w.gparam, w.l0_part);
+  if (st == GTP_OK) st = packed_power_into(c, c->pk, B, power_mw, w);
+  c->prof_on = prof;
+  return st;
 }
 
 gtp_status gtp_load_traces(gtp_ctx c, int32_t n_traces, const gtp_events* traces, int validate) {
