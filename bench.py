@@ -42,6 +42,7 @@ WORKLOADS = {
 # sources that decide a kernel's memory traffic: the kernels, the packed
 # layout and the host's launch configuration
 KERNEL_SOURCES = ("paper_2609_05960_amd/csrc/gtp_kernels.h", "paper_2609_05960_amd/csrc/gtp_device.h",
+                  "paper_2609_05960_amd/csrc/gtp_scan.h",
                   "paper_2609_05960_amd/csrc/gtp_pack.h", "paper_2609_05960_amd/csrc/gtp_pack.hip",
                   "paper_2609_05960_amd/csrc/gtpower.hip")
 
@@ -281,6 +282,29 @@ def main():
         "gen_s": gen_s,
     }
 
+    # ---- events -> waveform: plan, packed layout and forward together -------
+    # (the layout is rebuilt every step: gtp_load_events drops it, the forward
+    # rebuilds it; the builder waits on the host, so the step is timed with
+    # the host clock around device-synchronised steps)
+    if args.algo == 0:
+        e2w_steps = max(2, min(args.steps, 5))
+        times = []
+        for it in range(e2w_steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.load_events(*tens, t_end=ev.t_end, validate=False)
+            ctx.forward(load, lam, out=P)
+            torch.cuda.synchronize()
+            if it > 0:   # the first step also grows the builder's workspace
+                times.append(time.perf_counter() - t0)
+        ms_e2w = 1e3 * sum(times) / len(times)
+        pk = ctx.plan_info()
+        out_e2w = {"value": N / (ms_e2w * 1e-3), "unit": "events/s", "ms_per_step": ms_e2w, "steps": e2w_steps,
+                   "pack_ms": pk["pack_ms"],
+                   "frac": EVENT_BYTES * N / (ms_e2w * 1e-3) / HBM_PEAK,
+                   "note": "events in the caller's gate-major layout to FP32 waveform: lane-block plan, packed "
+                           "layout (partition, carried-in state, per-event state, table rows, slew weights) and "
+                           "the forward, every step"}
     # ---- forward + adjoint -------------------------------------------------
     if not args.no_adjoint:
         beta = float(1.0 / (0.05 * P.double().mean().item()))
@@ -308,6 +332,8 @@ def main():
         out["fwd_adjoint"] = {"value": N / (ms_fa * 1e-3), "unit": "events/s", "ms_per_step": ms_fa,
                               "kernels": {k: dict(launches=n, avg_ms=ms / max(n, 1)) for k, (n, ms) in kern_fa.items()}}
 
+    if args.algo == 0:
+        out["events_to_waveform"] = out_e2w
     # ---- batched traces: one persistent graph launch vs per-trace launches --
     if not args.no_batched:
         out["batched"] = bench_batched(args, gtp, torch, dev)

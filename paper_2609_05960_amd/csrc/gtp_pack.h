@@ -34,8 +34,6 @@
 //             (bits 0..27) | (length-1) << 28, y = pin values before the
 //             unit's first event (bits 0..15) | the gate's cell << 16;
 //             x = 0xffffffff for an empty lane
-//   dsrc[64 * n_groups]   gate-major index of the unit's first event (for
-//             the per-event debug trace only)
 //   grp_off[n_groups + 1] first event of each group
 //   tile_grp[n_tiles + 1] first group of each tile
 //   gperm[G]  cell-sorted index -> gate;  gcell[G] cell of each sorted index;
@@ -51,6 +49,13 @@
 namespace gtp {
 
 constexpr int kGateBlockLog2 = 13;   // default gate-block size (log2): the adjoint holds 16 B per gate of a block in LDS
+
+// Device memory the pack takes its temporaries from (grown on demand, kept
+// by the caller between packs, freed by the caller).
+struct Workspace {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
 
 struct PackIn {
   EvView ev;                  // gate-major events (device)
@@ -73,6 +78,7 @@ struct PackIn {
   // records must share the order, so a batch passes one set of weights.
   std::vector<int64_t> gate_weight;
   int32_t slot_quads = 0;         // quads one LDS table slot holds (0: no phases)
+  Workspace* ws = nullptr;        // [2] temporaries (caller-owned)
 };
 
 struct PackOut {
@@ -80,7 +86,6 @@ struct PackOut {
   uint32_t* row = nullptr;
   float* alpha = nullptr;
   uint2* desc = nullptr;
-  int64_t* dsrc = nullptr;
   int64_t* grp_off = nullptr;
   int32_t* tile_grp = nullptr;
   int32_t* gperm = nullptr;

@@ -1,29 +1,39 @@
 // Builds the packed, tile-major event layout described in gtp_pack.h.
 //
-// Steps (all on the caller's stream):
-//   1. gate order: gates sorted by cell (stable, host), cut into gate blocks
-//      of at most 2^gate_block_log2 gates of one cell;
+// Steps (all on the caller's stream; the host waits twice, for the number of
+// units and the number of groups, which size the arrays, and once at the end
+// for the statistics):
+//   1. gate order: gates sorted by (cell, decreasing event count, gate) with
+//      a device radix sort of 64-bit keys; gate blocks of at most
+//      2^gate_block_log2 gates of one cell;
 //   2. k_pk_units (count pass): every gate-major lane block of 16 events is
 //      walked in order and split into units wherever the gate or the time
-//      tile changes; units per block are counted, then scanned;
+//      tile changes; units per block, exclusive scan;
 //   3. k_pk_units (emit pass): the same walk writes one record per unit
 //      (first event, gate, length, carried-in pin values) and its sort key
 //      (tile, gate block, 16 - length, gate within the block);
-//   4. radix sort of the unit keys (hipcub, stable);
-//   5. per tile its first unit; 64 units per group; group event counts,
-//      scanned into group offsets;
-//   6. k_pk_fill: one wavefront per group writes the unit descriptors and
-//      copies the units' events into the unit-interleaved order.
-// The pack runs once per event set and bin width; its time is reported apart
-// from the forward.
+//   4. device radix sort of the unit keys (stable);
+//   5. k_pk_tile_first + suffix minimum: each tile's first unit; groups of 64
+//      units per tile, scanned into tile_grp;
+//   6. k_pk_group_len: per group its events and longest unit (from the sorted
+//      keys), per unit its length; scans into group and unit event offsets;
+//      per (tile, gate block) region its first unit and events;
+//   7. k_pk_fill: one workgroup per tile, one wavefront per group: the unit
+//      descriptors and every event's record in the unit-interleaved order;
+//   8. k_pk_bin_max (most events in one bin), k_pk_group_cells +
+//      k_pk_phases + k_pk_phase_copy (the table phases of every tile).
+// Temporaries live in a workspace the caller keeps between packs; the pack
+// runs once per event set and bin width, its time is reported apart from the
+// forward.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <cstdio>
 #include <vector>
 
 #include "gtp_pack.h"
+#include "gtp_scan.h"
 
 namespace gtp {
 namespace {
@@ -137,7 +147,12 @@ __global__ void __launch_bounds__(256) k_pk_fill_u32(uint32_t* p, int64_t n, uin
   if (i < n) p[i] = v;
 }
 
-// First sorted unit of every non-empty tile.
+__global__ void __launch_bounds__(256) k_pk_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// First sorted unit of every non-empty tile (others keep their fill value).
 __global__ void __launch_bounds__(256) k_pk_tile_first(const uint64_t* skey, int64_t nu, int32_t shift,
                                                        uint32_t* tfirst) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -158,12 +173,82 @@ __global__ void __launch_bounds__(256) k_pk_region_first(const uint64_t* skey, i
   if (j == 0 || region(skey[j - 1]) != r) rfirst[r] = (uint32_t)j;
 }
 
-// Event count of every sorted unit (for the per-region event counts).
-__global__ void __launch_bounds__(256) k_pk_sorted_len(const uint32_t* sidx, const UnitRec* recs, int64_t nu,
-                                                       uint32_t* slen) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j > nu) return;
-  slen[j] = (j < nu) ? (recs[sidx[j]].x >> 28) + 1u : 0u;
+// In place, p[i] = min(p[i], p[i+1], ..., p[n-1]) (one workgroup of 1024
+// threads, chunks of 1024 from the end): fills the entries of empty tiles and
+// regions with the first unit of the next non-empty one.
+__global__ void __launch_bounds__(1024) k_pk_suffix_min(uint32_t* p, int64_t n) {
+  __shared__ uint32_t wmin[16];
+  __shared__ uint32_t carry_sh;
+  const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+  uint32_t carry = 0xffffffffu;
+  for (int64_t end = n; end > 0; end -= 1024) {
+    // element end - 1 - threadIdx.x: thread 0 holds the last element
+    const int64_t i = end - 1 - (int64_t)threadIdx.x;
+    uint32_t v = i >= 0 ? p[i] : 0xffffffffu;
+    // inclusive min over threads 0..threadIdx.x (= elements i..end-1)
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(v, o, 64);
+      if (lane >= o) v = min(v, t);
+    }
+    if (lane == 63) wmin[wave] = v;
+    __syncthreads();
+    uint32_t pre = carry;
+    for (int w = 0; w < wave; ++w) pre = min(pre, wmin[w]);
+    v = min(v, pre);
+    if (i >= 0) p[i] = v;
+    if (threadIdx.x == 1023) carry_sh = v;
+    __syncthreads();
+    carry = carry_sh;
+    __syncthreads();
+  }
+}
+
+// Groups of every tile: ceil(units / 64).
+__global__ void __launch_bounds__(256) k_pk_tile_groups(const uint32_t* tfirst, int32_t n_tiles, uint32_t* gk) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > n_tiles) return;
+  gk[k] = (k < n_tiles) ? (tfirst[k + 1] - tfirst[k] + kGroupUnits - 1) / kGroupUnits : 0u;
+}
+
+// Length of a unit from its sort key (16 - length is the field below the
+// gate within the block).
+__device__ __forceinline__ uint32_t key_len(uint64_t key, int32_t gb_log2) {
+  return 16u - (uint32_t)((key >> gb_log2) & 31u);
+}
+
+// One workgroup per tile, one wavefront per group: the group's events
+// (glen), its longest unit (gmax, the lane steps it costs a wavefront) and
+// every unit's length (slen, for the per-region event counts).
+__global__ void __launch_bounds__(256) k_pk_group_len(const uint32_t* tile_grp, const uint32_t* tfirst,
+                                                      const uint64_t* skey, int32_t gb_log2, int64_t* glen,
+                                                      uint32_t* slen, unsigned long long* lane_steps,
+                                                      uint32_t* max_tile_groups) {
+  const int32_t k = blockIdx.x;
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t g0 = tile_grp[k], g1 = tile_grp[k + 1];
+  const int64_t j1 = tfirst[k + 1];
+  unsigned long long steps = 0;
+  for (int64_t g = g0 + (threadIdx.x >> 6); g < g1; g += blockDim.x >> 6) {
+    const int64_t j = tfirst[k] + (g - g0) * kGroupUnits + lane;
+    const uint32_t len = j < j1 ? key_len(skey[j], gb_log2) : 0u;
+    if (j < j1) slen[j] = len;
+    uint32_t s = len, mx = len;
+    for (int o = 32; o > 0; o >>= 1) {
+      s += __shfl_xor(s, o, 64);
+      mx = max(mx, __shfl_xor(mx, o, 64));
+    }
+    if (lane == 0) {
+      glen[g] = s;
+      steps += mx;
+    }
+  }
+  if (lane == 0 && steps) atomicAdd(lane_steps, steps);
+  if (threadIdx.x == 0) atomicMax(max_tile_groups, (uint32_t)(g1 - g0));
+}
+
+__global__ void __launch_bounds__(256) k_widen_u32(const uint32_t* in, int64_t n, uint64_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
 }
 
 __global__ void __launch_bounds__(256) k_pk_region_events(const uint64_t* uoff, const uint32_t* rfirst, int64_t n_reg,
@@ -173,125 +258,108 @@ __global__ void __launch_bounds__(256) k_pk_region_events(const uint64_t* uoff, 
   rev[r] = (int64_t)(uoff[rfirst[r + 1]] - uoff[rfirst[r]]);
 }
 
-__device__ __forceinline__ int32_t tile_of_group(const int32_t* tile_grp, int32_t n_tiles, int64_t gi) {
-  int32_t lo = 0, hi = n_tiles;  // invariant: tile_grp[lo] <= gi < tile_grp[hi]
-  while (hi - lo > 1) {
-    const int32_t mid = (lo + hi) >> 1;
-    if ((int64_t)tile_grp[mid] <= gi) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-// Events of each group (for the offsets) and its longest unit (the number of
-// lane steps the group costs a wavefront).
-__global__ void __launch_bounds__(256) k_pk_group_len(const int32_t* tile_grp, const uint32_t* tfirst, int32_t n_tiles,
-                                                      const uint32_t* sidx, const UnitRec* recs, int64_t n_groups,
-                                                      int64_t* glen, uint8_t* gmax) {
-  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gi > n_groups) return;
-  if (gi == n_groups) {
-    glen[gi] = 0;
-    return;
-  }
-  const int32_t k = tile_of_group(tile_grp, n_tiles, gi);
-  const int64_t j0 = (int64_t)tfirst[k] + (gi - tile_grp[k]) * kGroupUnits;
-  const int64_t j1 = min(j0 + kGroupUnits, (int64_t)tfirst[k + 1]);
-  int64_t s = 0;
-  int mx = 0;
-  for (int64_t j = j0; j < j1; ++j) {
-    const int len = (int)(recs[sidx[j]].x >> 28) + 1;
-    s += len;
-    mx = max(mx, len);
-  }
-  glen[gi] = s;
-  gmax[gi] = (uint8_t)mx;
-}
-
 struct FillArgs {
   EvView ev;
   BinSpec bins;
   LibView lib;                // device pointers of the library image
   const int32_t* gcell;
-  const int32_t* tile_grp;
+  const uint32_t* tile_grp;
   const uint32_t* tfirst;
   const uint32_t* sidx;
   const UnitRec* recs;
   const int64_t* grp_off;
-  int64_t n_groups;
   uint32_t* w32;
   uint32_t* row;
   float* alpha;
   uint2* desc;
-  int64_t* dsrc;
   int32_t* dbg_state;         // optional, gate-major: state before the event's group
   int64_t* dbg_bin;           // optional, gate-major: bin of the event
   int32_t* alpha_span;        // max over events of |1 - alpha| + |alpha| (FP32 bits; positive floats order as ints)
 };
 
-// One wavefront per group: the unit descriptors, and every event's record in
-// the unit-interleaved order. The lane of a unit tracks its gate's pin values
-// from the carried-in values, as the gate-major walk does: the table is
-// selected by the input state before the event's timestamp group, the
-// leakage state after the event is the input state once the event's pin has
-// toggled.
+// One workgroup per tile, one wavefront per group of the tile, one lane per
+// unit: the unit descriptor, and every event's record in the unit-interleaved
+// order. The lane tracks its gate's pin values from the carried-in values, as
+// the gate-major walk does: the table is selected by the input state before
+// the event's timestamp group, the leakage state after the event is the input
+// state once the event's pin has toggled. All of a unit's event loads are
+// issued before any is used (the unit's events are scattered over the
+// gate-major array, so the loads are latency-bound), and the library's map
+// and axes are read from LDS.
+template <int kS>
 __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
-  const int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroupUnits;
-  const int lane = (int)(threadIdx.x & (kGroupUnits - 1));
-  if (gi >= a.n_groups) return;  // whole wavefronts exit together
+  extern __shared__ uint32_t lds[];
+  const LdsLib L = stage_library(a.lib, lds);
+  __syncthreads();
   const BinSpec& B = a.bins;
-  const int32_t k = tile_of_group(a.tile_grp, B.n_tiles, gi);
-  const int64_t j = (int64_t)a.tfirst[k] + (gi - a.tile_grp[k]) * kGroupUnits + lane;
-  const bool act = j < (int64_t)a.tfirst[k + 1];
-  UnitRec r{-1, 0xffffffffu, 0u};
-  if (act) r = a.recs[a.sidx[j]];
-  const int cell = act ? a.gcell[r.x & 0x0fffffffu] : 0;
-  // descriptor: y = pin values before the unit's first event | cell << 16
-  a.desc[gi * kGroupUnits + lane] = make_uint2(r.x, (r.y & 0xffffu) | ((uint32_t)cell << 16));
-  a.dsrc[gi * kGroupUnits + lane] = r.src;
-  const int len = act ? (int)(r.x >> 28) + 1 : 0;
-  const CellMeta cm = a.lib.meta[cell];
-  const uint32_t in_mask = (1u << cm.n_in) - 1u;
-  const float* axis = a.lib.slew + cm.axis_off;
-  const float* inv = a.lib.slew_inv + cm.axis_off;
+  const int32_t k = blockIdx.x;
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t g0 = a.tile_grp[k], g1 = a.tile_grp[k + 1];
+  const int64_t jend = a.tfirst[k + 1];
   const int32_t qstride = a.lib.n_load - 1;
-  uint32_t cur = r.y & 0xffffu;   // pin values before the unit's first event
-  uint32_t gsv = r.y >> 16;       // pin values before that event's timestamp group
-  int64_t tprev = 0;
-  int64_t off = a.grp_off[gi];
   float span = 1.0f;   // |1 - alpha| + |alpha| of the lane's events (1 inside the axis)
-  for (int kk = 0; kk < kLaneEvents; ++kk) {
-    const bool on = len > kk;
-    const uint64_t m = __ballot(on);
-    if (m == 0) break;
-    if (on) {
-      const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
-      const int64_t pos = off + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-      const int64_t e = r.src + kk;
-      const int64_t t = a.ev.t[e];
-      const uint32_t pb = a.ev.pb[e];
-      if (kk > 0 && t != tprev) gsv = cur;
-      tprev = t;
-      const uint32_t pin = min(pb >> 1, (uint32_t)kMaxPin);
-      const uint32_t v = pb & 1u;
-      const uint32_t st = gsv & in_mask;
-      cur ^= 1u << pin;
-      const int64_t bin = bin_of(t, B);
-      const uint32_t bl = (uint32_t)(bin - ((int64_t)k << B.tile_log2));
-      const uint32_t rr = (uint32_t)(t - bin * B.D);
-      int i;
-      float al;
-      slew_segment(axis, inv, a.lib.n_slew, a.ev.slew[e], i, al);
-      const uint32_t q = (uint32_t)(a.lib.map_q[cm.map_off + 2 * (int)st + (int)v] + i * qstride);
-      a.w32[pos] = (bl << B.r_bits) | rr | ((cur & in_mask) << kStateShift);
-      a.row[pos] = q | ((pin == (uint32_t)cm.n_in ? 1u : 0u) << kOutBit) | (v << 31);
-      a.alpha[pos] = al;
-      span = fmaxf(span, fabsf(1.0f - al) + fabsf(al));
-      if (a.dbg_state) {
-        a.dbg_state[e] = (int32_t)st;
-        a.dbg_bin[e] = bin;
+  for (int64_t gi = g0 + (threadIdx.x >> 6); gi < g1; gi += blockDim.x >> 6) {
+    const int64_t j = (int64_t)a.tfirst[k] + (gi - g0) * kGroupUnits + lane;
+    const bool act = j < jend;
+    UnitRec r{0, 0xffffffffu, 0u};
+    if (act) r = a.recs[a.sidx[j]];
+    const int cell = act ? a.gcell[r.x & 0x0fffffffu] : 0;
+    // descriptor: y = pin values before the unit's first event | cell << 16
+    a.desc[gi * kGroupUnits + lane] = make_uint2(r.x, (r.y & 0xffffu) | ((uint32_t)cell << 16));
+    const int len = act ? (int)(r.x >> 28) + 1 : 0;
+    int64_t tt[kS];
+    uint32_t pb[kS];
+    float sl[kS];
+#pragma unroll
+    for (int kk = 0; kk < kS; ++kk) {
+      if (kk < len) {
+        tt[kk] = a.ev.t[r.src + kk];
+        pb[kk] = a.ev.pb[r.src + kk];
+        sl[kk] = a.ev.slew[r.src + kk];
       }
     }
-    off += __popcll(m);
+    const CellMeta cm = L.meta[cell];
+    const uint32_t in_mask = (1u << cm.n_in) - 1u;
+    const float* axis = L.slew + cm.axis_off;
+    const float* inv = L.slew_inv + cm.axis_off;
+    uint32_t cur = r.y & 0xffffu;   // pin values before the unit's first event
+    uint32_t gsv = r.y >> 16;       // pin values before that event's timestamp group
+    int64_t tprev = 0;
+    int64_t off = a.grp_off[gi];
+#pragma unroll
+    for (int kk = 0; kk < kS; ++kk) {
+      const bool on = len > kk;
+      const uint64_t m = __ballot(on);
+      if (m == 0) break;
+      if (on) {
+        const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+        const int64_t pos = off + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+        const int64_t t = tt[kk];
+        if (kk > 0 && t != tprev) gsv = cur;
+        tprev = t;
+        const uint32_t pin = min(pb[kk] >> 1, (uint32_t)kMaxPin);
+        const uint32_t v = pb[kk] & 1u;
+        const uint32_t st = gsv & in_mask;
+        cur ^= 1u << pin;
+        const int64_t bin = bin_of(t, B);
+        const uint32_t bl = (uint32_t)(bin - ((int64_t)k << B.tile_log2));
+        const uint32_t rr = (uint32_t)(t - bin * B.D);
+        int i;
+        float al;
+        slew_segment(axis, inv, a.lib.n_slew, sl[kk], i, al);
+        const uint32_t q = (uint32_t)(L.map_q[cm.map_off + 2 * (int)st + (int)v] + i * qstride);
+        a.w32[pos] = (bl << B.r_bits) | rr | ((cur & in_mask) << kStateShift);
+        a.row[pos] = q | ((pin == (uint32_t)cm.n_in ? 1u : 0u) << kOutBit) | (v << 31);
+        a.alpha[pos] = al;
+        span = fmaxf(span, fabsf(1.0f - al) + fabsf(al));
+        if (a.dbg_state) {
+          const int64_t e = r.src + kk;
+          a.dbg_state[e] = (int32_t)st;
+          a.dbg_bin[e] = bin;
+        }
+      }
+      off += __popcll(m);
+    }
   }
   for (int o = 32; o > 0; o >>= 1) span = fmaxf(span, __shfl_xor(span, o, 64));
   if (lane == 0) atomicMax(a.alpha_span, __float_as_int(span));
@@ -299,9 +367,9 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
 
 // Largest number of events in one bin: one workgroup per tile counts the
 // tile's packed events per bin in LDS (the in-tile bin is in the event
-// word), then one atomic max per tile.
+// word), then one atomic max per wavefront.
 __global__ void __launch_bounds__(256) k_pk_bin_max(const uint32_t* w32, const int64_t* grp_off,
-                                                    const int32_t* tile_grp, int32_t tile_log2, int32_t r_bits,
+                                                    const uint32_t* tile_grp, int32_t tile_log2, int32_t r_bits,
                                                     int32_t* out) {
   extern __shared__ int32_t hist[];
   const int nb = 1 << tile_log2;
@@ -320,8 +388,7 @@ __global__ void __launch_bounds__(256) k_pk_bin_max(const uint32_t* w32, const i
 
 // First and last cell among a group's units (-1 for an empty group); the
 // lanes of a group are in gate-block order, so cells do not decrease.
-__global__ void __launch_bounds__(256) k_pk_group_cells(const uint2* desc, const int32_t* gcell, int64_t n_groups,
-                                                        int2* cells) {
+__global__ void __launch_bounds__(256) k_pk_group_cells(const uint2* desc, int64_t n_groups, int2* cells) {
   const int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroupUnits;
   const int lane = (int)(threadIdx.x & (kGroupUnits - 1));
   if (gi >= n_groups) return;
@@ -334,8 +401,81 @@ __global__ void __launch_bounds__(256) k_pk_group_cells(const uint2* desc, const
   }
   const int first = __ffsll((unsigned long long)m) - 1;
   const int last = 63 - __clzll((long long)m);
-  if (lane == first) cells[gi].x = gcell[d.x & 0x0fffffffu];
-  if (lane == last) cells[gi].y = gcell[d.x & 0x0fffffffu];
+  if (lane == first) cells[gi].x = (int)(d.y >> 16);
+  if (lane == last) cells[gi].y = (int)(d.y >> 16);
+}
+
+// Table phases of one tile (one wavefront per tile, the decisions taken in
+// lockstep by every lane): a phase starts at a group and grows while the
+// union of its groups' cell table ranges [cq_lo, cq_hi) fits the slot; a
+// single group whose cells exceed the slot keeps its first cell's quads
+// (full = 0: the other lanes read global memory). Phases are written at the
+// tile's first group index (a tile has at most as many phases as groups) and
+// counted in n_ph; k_pk_phase_copy compacts them.
+constexpr int kPhaseChunk = 2048;   // groups staged in LDS at a time
+__global__ void __launch_bounds__(64) k_pk_phases(const int2* gcells, const uint32_t* tile_grp, const int32_t* cq_lo,
+                                                  const int32_t* cq_hi, int32_t n_cells, int64_t cap, int4* ph_tmp,
+                                                  uint32_t* n_ph, int32_t* all_full) {
+  __shared__ int2 cc_sh[kPhaseChunk];
+  const int32_t k = blockIdx.x;
+  const int64_t g0 = tile_grp[k], g1 = tile_grp[k + 1];
+  bool staged = false;   // cc_sh holds groups [cbase, cbase + kPhaseChunk)
+  int64_t cbase = 0;
+  // cells of group e (an out-of-range cell counts as an empty group)
+  auto cells_of = [&](int64_t e) -> int2 {
+    if (!staged || e < cbase || e >= cbase + kPhaseChunk) {
+      __syncthreads();
+      staged = true;
+      cbase = e;
+      for (int i = threadIdx.x; i < kPhaseChunk; i += 64)
+        cc_sh[i] = (e + i < g1) ? gcells[e + i] : make_int2(-1, -1);
+      __syncthreads();
+    }
+    const int2 cc = cc_sh[e - cbase];
+    return (cc.x >= 0 && cc.x < n_cells && cc.y >= cc.x && cc.y < n_cells) ? cc : make_int2(-1, -1);
+  };
+  uint32_t np = 0;
+  int32_t full_all = 1;
+  int64_t g = g0;
+  while (g < g1) {
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    int64_t e = g;
+    for (; e < g1; ++e) {
+      const int2 cc = cells_of(e);
+      if (cc.x < 0) continue;
+      const int64_t l = min(cq_lo[cc.x], cq_lo[cc.y]), h = max(cq_hi[cc.x], cq_hi[cc.y]);
+      const int64_t nl = min(lo, l), nh = max(hi, h);
+      if (e > g && nh - nl > cap) break;
+      lo = nl;
+      hi = nh;
+    }
+    if (lo == INT64_MAX) {  // only empty groups: nothing to stage
+      lo = 0;
+      hi = 0;
+    }
+    int32_t full = 1;
+    if (hi - lo > cap) {  // group g alone exceeds the slot (so it is not empty)
+      const int2 cc = cells_of(g);
+      lo = cc.x >= 0 ? cq_lo[cc.x] : 0;
+      hi = cc.x >= 0 ? min((int64_t)cq_hi[cc.x], lo + cap) : 0;
+      full = 0;
+      full_all = 0;
+    }
+    if (threadIdx.x == 0) ph_tmp[g0 + np] = make_int4((int32_t)(e - g0), (int32_t)lo, (int32_t)(hi - lo), full);
+    ++np;
+    g = e;
+  }
+  if (threadIdx.x == 0) {
+    n_ph[k] = np;
+    if (!full_all) atomicAnd(all_full, 0);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_pk_phase_copy(const int4* ph_tmp, const uint32_t* tile_grp,
+                                                       const uint32_t* ph_off, int32_t n_tiles, int4* phases) {
+  const int32_t k = blockIdx.x;
+  const uint32_t n = ph_off[k + 1] - ph_off[k];
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) phases[ph_off[k] + i] = ph_tmp[tile_grp[k] + i];
 }
 
 // Output nets and initial pin values in cell-sorted gate order (the per-call
@@ -382,18 +522,50 @@ int ceil_log2_u64(uint64_t x) {
   return l;
 }
 
+// Bump allocator over the caller's workspace (256-byte aligned pieces).
+struct Bump {
+  char* base;
+  size_t cap, used = 0;
+  template <class T>
+  T* take(size_t count) {
+    const size_t bytes = (std::max<size_t>(count, 1) * sizeof(T) + 255) & ~(size_t)255;
+    if (used + bytes > cap) return nullptr;
+    T* p = reinterpret_cast<T*>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
+size_t align256(size_t b) { return (std::max<size_t>(b, 1) + 255) & ~(size_t)255; }
+
+// Exclusive scan (add) of n items with the three-pass scan kernels; sums
+// holds ceil(n / kScanTile) items.
+template <class T>
+void scan_add(const T* in, T* out, T* sums, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL((k_scan_tiles<T, OpAdd>), dim3((unsigned)nt), dim3(kScanThreads), 0, s, in, out, sums, n, (T)0,
+                     OpAdd());
+  if (nt > 1) {
+    hipLaunchKernelGGL((k_scan_sums<T, OpAdd>), dim3(1), dim3(kScanThreads), 0, s, sums, nt, (T)0, OpAdd());
+    hipLaunchKernelGGL((k_scan_add<T, OpAdd>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out,
+                       (const T*)sums, n, OpAdd());
+  }
+}
+
+int64_t scan_sums_items(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
 }  // namespace
 
 void pack_free(PackOut* o) {
-  void* ps[] = {o->w32,   o->row,   o->alpha, o->desc,      o->dsrc,   o->grp_off, o->tile_grp, o->gperm,
-                o->gcell, o->gout, o->ginit, o->reg_first, o->tfirst, o->phases, o->ph_off};
+  void* ps[] = {o->w32,   o->row,  o->alpha, o->desc,      o->grp_off, o->tile_grp, o->gperm,
+                o->gcell, o->gout, o->ginit, o->reg_first, o->tfirst,  o->phases,   o->ph_off};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   *o = PackOut();
 }
 
 hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len) {
-  std::vector<void*> temps;
   PackOut o;
   hipError_t st = hipSuccess;
   const hipStream_t s = in.stream;
@@ -402,6 +574,8 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
   const BinSpec& B = in.bins;
   const int32_t n_tiles = B.n_tiles;
   int64_t held = 0;
+  Workspace* ws = in.ws;         // gate order and unit counts
+  Workspace* ws2b = in.ws + 1;   // units, sort, offsets, phases
 
 #define PK(call)                                                                   \
   do {                                                                             \
@@ -420,12 +594,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     }                                                                              \
   } while (0)
 
-  auto tmp = [&](size_t bytes, hipError_t& e) -> void* {
-    void* p = nullptr;
-    e = hipMalloc(&p, std::max<size_t>(bytes, 256));
-    if (e == hipSuccess) temps.push_back(p);
-    return p;
-  };
+  // owned output arrays
   auto own = [&](size_t bytes, hipError_t& e) -> void* {
     void* p = nullptr;
     bytes = std::max<size_t>(bytes, 256);
@@ -433,9 +602,26 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     if (e == hipSuccess) held += (int64_t)bytes;
     return p;
   };
+  // grows a workspace to at least `bytes` (after the stream is idle: no
+  // earlier use of the old buffer is pending)
+  auto reserve = [&](Workspace* w, size_t bytes) -> hipError_t {
+    if (w->bytes >= bytes) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (w->p) (void)hipFree(w->p);
+    w->p = nullptr;
+    w->bytes = 0;
+    e = hipMalloc(&w->p, bytes);
+    if (e != hipSuccess) {
+      w->p = nullptr;
+      return e;
+    }
+    w->bytes = bytes;
+    return hipSuccess;
+  };
 
   {
-    // ---- 1. gate order (host) -------------------------------------------
+    // ---- 1. gate order ------------------------------------------------------
     std::vector<int32_t> cnt(n_cells + 1, 0), cell_start(n_cells, 0), gb_base(n_cells, 0);
     for (int64_t g = 0; g < G; ++g) cnt[in.h_gate_cell[g]]++;
     int32_t acc = 0, gbacc = 0;
@@ -467,13 +653,8 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       snprintf(err, err_len, "pack: sort key of %d bits", key_bits);
       return hipErrorInvalidValue;
     }
+    const int64_t n_blocks = (N + kLaneEvents - 1) / kLaneEvents;
     hipError_t e2;
-    int32_t* d_rank = (int32_t*)tmp((size_t)G * 4, e2);
-    PK(e2);
-    int32_t* d_cs = (int32_t*)tmp((size_t)n_cells * 4, e2);
-    PK(e2);
-    int32_t* d_gbb = (int32_t*)tmp((size_t)n_cells * 4, e2);
-    PK(e2);
     o.gperm = (int32_t*)own((size_t)G * 4, e2);
     PK(e2);
     o.gcell = (int32_t*)own((size_t)G * 4, e2);
@@ -482,40 +663,48 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     PK(e2);
     o.ginit = (uint32_t*)own((size_t)G * 4, e2);
     PK(e2);
+
+    // workspace, phase 1: gate sort and unit counts (sized before the unit count is known)
+    size_t gsort_tmp = 0;
+    if (G > 0)
+      PK(rocprim::radix_sort_keys(nullptr, gsort_tmp, (uint64_t*)nullptr, (uint64_t*)nullptr, (int64_t)G, 0,
+                                  48 + std::max(1, ceil_log2_u64((uint64_t)n_cells)), s));
+    const size_t ws1 = align256((size_t)G * 4) + 2 * align256((size_t)n_cells * 4) + 3 * align256((size_t)G * 8) +
+                       align256(gsort_tmp) + 2 * align256((size_t)(n_blocks + 1) * 4) +
+                       align256((size_t)scan_sums_items(n_blocks + 1) * 4) + align256(64);
+    PK(reserve(ws, ws1));
+    Bump wb{(char*)ws->p, ws->bytes};
+    int32_t* d_rank = wb.take<int32_t>((size_t)G);
+    int32_t* d_cs = wb.take<int32_t>((size_t)n_cells);
+    int32_t* d_gbb = wb.take<int32_t>((size_t)n_cells);
+    uint32_t* counts = wb.take<uint32_t>((size_t)n_blocks + 1);
+    uint32_t* ubase = wb.take<uint32_t>((size_t)n_blocks + 1);
+    uint32_t* usums = wb.take<uint32_t>((size_t)scan_sums_items(n_blocks + 1));
+    uint32_t* d_nu = wb.take<uint32_t>(16);
     if (G > 0) {
-      // Gates in cell order and, within a cell, by decreasing event count (or
-      // the given weights; ties by gate index): the gates active in most time
-      // tiles sit together, so the gate records one wavefront gathers share
-      // cache lines.
-      uint64_t* gk = (uint64_t*)tmp((size_t)G * 8, e2);
-      PK(e2);
-      uint64_t* gks = (uint64_t*)tmp((size_t)G * 8, e2);
-      PK(e2);
-      int64_t* d_wt = nullptr;
-      if ((int64_t)in.gate_weight.size() == G) {
-        d_wt = (int64_t*)tmp((size_t)G * 8, e2);
-        PK(e2);
-        PK(hipMemcpyAsync(d_wt, in.gate_weight.data(), (size_t)G * 8, hipMemcpyHostToDevice, s));
-      }
+      uint64_t* gk = wb.take<uint64_t>((size_t)G);
+      uint64_t* gks = wb.take<uint64_t>((size_t)G);
+      int64_t* d_wt = wb.take<int64_t>((size_t)G);
+      void* tsort = wb.take<char>(gsort_tmp);
+      const bool wt = (int64_t)in.gate_weight.size() == G;
+      if (wt) PK(hipMemcpyAsync(d_wt, in.gate_weight.data(), (size_t)G * 8, hipMemcpyHostToDevice, s));
       const dim3 gg((unsigned)((G + 255) / 256));
-      hipLaunchKernelGGL(k_pk_gate_keys, gg, dim3(256), 0, s, in.gate_cell, in.ev.gate_off, d_wt, (int64_t)G, gk);
+      hipLaunchKernelGGL(k_pk_gate_keys, gg, dim3(256), 0, s, in.gate_cell, in.ev.gate_off,
+                         wt ? (const int64_t*)d_wt : nullptr, (int64_t)G, gk);
       PKLAUNCH("k_pk_gate_keys");
-      size_t tb = 0;
-      PK(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, gk, gks, (int)G, 0, 64, s));
-      void* tsort = tmp(tb, e2);
-      PK(e2);
-      PK(hipcub::DeviceRadixSort::SortKeys(tsort, tb, gk, gks, (int)G, 0, 64, s));
+      size_t tb = gsort_tmp;
+      PK(rocprim::radix_sort_keys(tsort, tb, gk, gks, (int64_t)G, 0,
+                                  48 + std::max(1, ceil_log2_u64((uint64_t)n_cells)), s));
       hipLaunchKernelGGL(k_pk_gate_order, gg, dim3(256), 0, s, gks, (int64_t)G, o.gperm, d_rank, o.gcell);
       PKLAUNCH("k_pk_gate_order");
-      hipLaunchKernelGGL(k_pk_gate_sorted, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, s, o.gperm, in.gate_out,
-                         in.gate_init, (int64_t)G, o.gout, o.ginit);
+      hipLaunchKernelGGL(k_pk_gate_sorted, gg, dim3(256), 0, s, o.gperm, in.gate_out, in.gate_init, (int64_t)G, o.gout,
+                         o.ginit);
       PKLAUNCH("k_pk_gate_sorted");
     }
     PK(hipMemcpyAsync(d_cs, cell_start.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
     PK(hipMemcpyAsync(d_gbb, gb_base.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
 
-    // ---- 2-3. units -----------------------------------------------------
-    const int64_t n_blocks = (N + kLaneEvents - 1) / kLaneEvents;
+    // ---- 2. unit counts ----------------------------------------------------
     UnitArgs ua;
     ua.ev = in.ev;
     ua.plan = in.plan_blk;
@@ -528,10 +717,6 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     ua.ks.rank = d_rank;
     ua.ks.cell_start = d_cs;
     ua.ks.gb_base = d_gbb;
-    uint32_t* counts = (uint32_t*)tmp((size_t)(n_blocks + 1) * 4, e2);
-    PK(e2);
-    uint32_t* ubase = (uint32_t*)tmp((size_t)(n_blocks + 1) * 4, e2);
-    PK(e2);
     ua.counts = counts;
     ua.base = ubase;
     ua.keys = nullptr;
@@ -544,27 +729,62 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       PKLAUNCH("k_pk_units<count>");
       hipLaunchKernelGGL(k_pk_fill_u32, dim3(1), dim3(256), 0, s, counts + n_blocks, (int64_t)1, 0u);
       PKLAUNCH("k_pk_fill_u32");
-      size_t tb = 0;
-      PK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, counts, ubase, (int)(n_blocks + 1), s));
-      void* tscan = tmp(tb, e2);
-      PK(e2);
-      PK(hipcub::DeviceScan::ExclusiveSum(tscan, tb, counts, ubase, (int)(n_blocks + 1), s));
+      scan_add<uint32_t>(counts, ubase, usums, n_blocks + 1, s);
+      PKLAUNCH("scan of unit counts");
       uint32_t tot = 0;
       PK(hipMemcpyAsync(&tot, ubase + n_blocks, 4, hipMemcpyDeviceToHost, s));
       PK(hipStreamSynchronize(s));
       NU = tot;
     }
     o.n_units = NU;
-    uint64_t* keys = (uint64_t*)tmp((size_t)NU * 8, e2);
-    PK(e2);
-    uint64_t* skeys = (uint64_t*)tmp((size_t)NU * 8, e2);
-    PK(e2);
-    uint32_t* vals = (uint32_t*)tmp((size_t)NU * 4, e2);
-    PK(e2);
-    uint32_t* sidx = (uint32_t*)tmp((size_t)NU * 4, e2);
-    PK(e2);
-    UnitRec* recs = (UnitRec*)tmp((size_t)NU * sizeof(UnitRec), e2);
-    PK(e2);
+    const int64_t n_reg = (int64_t)n_tiles * n_gb;
+
+    // workspace, phase 2 (a second buffer: the first one's pieces stay in use)
+    size_t usort_tmp = 0;
+    if (NU > 0)
+      PK(rocprim::radix_sort_pairs(nullptr, usort_tmp, (uint64_t*)nullptr, (uint64_t*)nullptr, (uint32_t*)nullptr,
+                                   (uint32_t*)nullptr, (int64_t)NU, 0, key_bits, s));
+    const int64_t ng_max = NU / kGroupUnits + n_tiles + 1;   // groups per tile: ceil(units / 64)
+    const size_t ws2 = 2 * align256((size_t)NU * 8) + 2 * align256((size_t)NU * 4) +
+                       align256((size_t)NU * sizeof(UnitRec)) + align256(usort_tmp) +
+                       align256((size_t)(n_tiles + 1) * 4) + align256((size_t)scan_sums_items(n_tiles + 1) * 4) +
+                       align256((size_t)(ng_max + 1) * 8) + align256((size_t)scan_sums_items(ng_max + 1) * 8) +
+                       align256((size_t)(NU + 1) * 4) + align256((size_t)(NU + 1) * 8) +
+                       align256((size_t)scan_sums_items(NU + 1) * 8) + align256((size_t)std::max<int64_t>(n_reg, 1) * 8) +
+                       align256((size_t)ng_max * 8) + align256((size_t)ng_max * sizeof(int4)) +
+                       align256((size_t)(n_tiles + 1) * 4) + align256((size_t)scan_sums_items(n_tiles + 1) * 4) +
+                       align256((size_t)n_cells * 8) + 4096;
+    PK(reserve(ws2b, ws2));
+    Bump wc{(char*)ws2b->p, ws2b->bytes};
+    uint64_t* keys = wc.take<uint64_t>((size_t)NU);
+    uint64_t* skeys = wc.take<uint64_t>((size_t)NU);
+    uint32_t* vals = wc.take<uint32_t>((size_t)NU);
+    uint32_t* sidx = wc.take<uint32_t>((size_t)NU);
+    UnitRec* recs = wc.take<UnitRec>((size_t)NU);
+    void* tsortu = wc.take<char>(usort_tmp);
+    uint32_t* gk = wc.take<uint32_t>((size_t)n_tiles + 1);
+    uint32_t* tsums = wc.take<uint32_t>((size_t)scan_sums_items(n_tiles + 1));
+    int64_t* glen = wc.take<int64_t>((size_t)ng_max + 1);
+    int64_t* gsums = wc.take<int64_t>((size_t)scan_sums_items(ng_max + 1));
+    uint32_t* slen = wc.take<uint32_t>((size_t)NU + 1);
+    uint64_t* uoff = wc.take<uint64_t>((size_t)NU + 1);
+    uint64_t* usums2 = wc.take<uint64_t>((size_t)scan_sums_items(NU + 1));
+    int64_t* rev = wc.take<int64_t>((size_t)std::max<int64_t>(n_reg, 1));
+    int2* gcells = wc.take<int2>((size_t)ng_max);
+    int4* ph_tmp = wc.take<int4>((size_t)ng_max);
+    uint32_t* nph = wc.take<uint32_t>((size_t)n_tiles + 1);
+    uint32_t* psums = wc.take<uint32_t>((size_t)scan_sums_items(n_tiles + 1));
+    if (!psums) {
+      snprintf(err, err_len, "pack: workspace of %zu bytes too small", ws2b->bytes);
+      st = hipErrorOutOfMemory;
+      goto fail;
+    }
+    // d_nu[0..]: alpha span bits, max events per bin, lane steps (u64 at 2..3),
+    // max tile groups, all-phases-full flag
+    {
+      const int32_t init[8] = {__builtin_bit_cast(int32_t, 1.0f), 0, 0, 0, 0, 1, 0, 0};
+      PK(hipMemcpyAsync(d_nu, init, sizeof init, hipMemcpyHostToDevice, s));
+    }
     if (NU > 0) {
       ua.keys = keys;
       ua.vals = vals;
@@ -572,135 +792,90 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       const unsigned gridb = (unsigned)((n_blocks + kFwdThreads - 1) / kFwdThreads);
       hipLaunchKernelGGL((k_pk_units<true>), dim3(gridb), dim3(kFwdThreads), 0, s, ua, n_blocks);
       PKLAUNCH("k_pk_units<emit>");
-      // ---- 4. sort ------------------------------------------------------
-      size_t tb = 0;
-      PK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, skeys, vals, sidx, (int)NU, 0, key_bits, s));
-      void* tsort = tmp(tb, e2);
-      PK(e2);
-      PK(hipcub::DeviceRadixSort::SortPairs(tsort, tb, keys, skeys, vals, sidx, (int)NU, 0, key_bits, s));
+      // ---- 4. sort --------------------------------------------------------
+      size_t tb = usort_tmp;
+      PK(rocprim::radix_sort_pairs(tsortu, tb, keys, skeys, vals, sidx, (int64_t)NU, 0, key_bits, s));
     }
     // ---- 5. tiles and groups -------------------------------------------
-    uint32_t* tfirst = (uint32_t*)own((size_t)(n_tiles + 1) * 4, e2);
+    o.tfirst = (uint32_t*)own((size_t)(n_tiles + 1) * 4, e2);
     PK(e2);
-    o.tfirst = tfirst;
-    hipLaunchKernelGGL(k_pk_fill_u32, dim3((unsigned)((n_tiles + 1 + 255) / 256)), dim3(256), 0, s, tfirst,
+    o.tile_grp = (int32_t*)own((size_t)(n_tiles + 1) * 4, e2);
+    PK(e2);
+    hipLaunchKernelGGL(k_pk_fill_u32, dim3((unsigned)((n_tiles + 1 + 255) / 256)), dim3(256), 0, s, o.tfirst,
                        (int64_t)(n_tiles + 1), (uint32_t)NU);
     PKLAUNCH("k_pk_fill_u32");
     if (NU > 0) {
       hipLaunchKernelGGL(k_pk_tile_first, dim3((unsigned)((NU + 255) / 256)), dim3(256), 0, s, skeys, NU,
-                         gb_bits + low, tfirst);
+                         gb_bits + low, o.tfirst);
       PKLAUNCH("k_pk_tile_first");
     }
-    std::vector<uint32_t> htf((size_t)n_tiles + 1);
-    PK(hipMemcpyAsync(htf.data(), tfirst, (size_t)(n_tiles + 1) * 4, hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_pk_suffix_min, dim3(1), dim3(1024), 0, s, o.tfirst, (int64_t)(n_tiles + 1));
+    PKLAUNCH("k_pk_suffix_min");
+    hipLaunchKernelGGL(k_pk_tile_groups, dim3((unsigned)((n_tiles + 1 + 255) / 256)), dim3(256), 0, s,
+                       (const uint32_t*)o.tfirst, n_tiles, gk);
+    PKLAUNCH("k_pk_tile_groups");
+    scan_add<uint32_t>(gk, (uint32_t*)o.tile_grp, tsums, n_tiles + 1, s);
+    PKLAUNCH("scan of tile groups");
+    uint32_t ngu = 0;
+    PK(hipMemcpyAsync(&ngu, o.tile_grp + n_tiles, 4, hipMemcpyDeviceToHost, s));
     PK(hipStreamSynchronize(s));
-    for (int32_t k = n_tiles - 1; k >= 0; --k) htf[k] = std::min(htf[k], htf[k + 1]);
-    std::vector<int32_t> htg((size_t)n_tiles + 1);
-    int64_t ng = 0;
-    int32_t maxg = 0;
-    for (int32_t k = 0; k < n_tiles; ++k) {
-      htg[k] = (int32_t)ng;
-      const int64_t gk = ((int64_t)(htf[k + 1] - htf[k]) + kGroupUnits - 1) / kGroupUnits;
-      maxg = std::max<int32_t>(maxg, (int32_t)gk);
-      ng += gk;
-    }
-    htg[n_tiles] = (int32_t)ng;
-    if (ng >= (int64_t)INT32_MAX) {
+    const int64_t ng = ngu;
+    if (ng >= (int64_t)INT32_MAX || ng > ng_max) {
       snprintf(err, err_len, "pack: %lld groups", (long long)ng);
       st = hipErrorInvalidValue;
       goto fail;
     }
     o.n_groups = ng;
-    o.max_tile_groups = maxg;
-    PK(hipMemcpyAsync(tfirst, htf.data(), (size_t)(n_tiles + 1) * 4, hipMemcpyHostToDevice, s));
-    o.tile_grp = (int32_t*)own((size_t)(n_tiles + 1) * 4, e2);
-    PK(e2);
-    PK(hipMemcpyAsync(o.tile_grp, htg.data(), (size_t)(n_tiles + 1) * 4, hipMemcpyHostToDevice, s));
-    int64_t* glen = (int64_t*)tmp((size_t)(ng + 1) * 8, e2);
-    PK(e2);
+    // ---- 6. group and unit lengths, offsets, regions ------------------------
     o.grp_off = (int64_t*)own((size_t)(ng + 1) * 8, e2);
     PK(e2);
-    uint8_t* gmax = (uint8_t*)tmp((size_t)(ng + 1), e2);
-    PK(e2);
-    hipLaunchKernelGGL(k_pk_group_len, dim3((unsigned)((ng + 1 + 255) / 256)), dim3(256), 0, s, o.tile_grp, tfirst,
-                       n_tiles, sidx, recs, ng, glen, gmax);
+    hipLaunchKernelGGL(k_pk_fill_u64, dim3(1), dim3(256), 0, s, (uint64_t*)(glen + ng), (int64_t)1, (uint64_t)0);
+    PKLAUNCH("k_pk_fill_u64");
+    hipLaunchKernelGGL(k_pk_fill_u32, dim3(1), dim3(256), 0, s, slen + NU, (int64_t)1, 0u);
+    PKLAUNCH("k_pk_fill_u32");
+    hipLaunchKernelGGL(k_pk_group_len, dim3((unsigned)n_tiles), dim3(256), 0, s, (const uint32_t*)o.tile_grp,
+                       (const uint32_t*)o.tfirst, (const uint64_t*)skeys, (int32_t)in.gate_block_log2, glen, slen,
+                       (unsigned long long*)(d_nu + 2), d_nu + 4);
     PKLAUNCH("k_pk_group_len");
+    scan_add<int64_t>(glen, o.grp_off, gsums, ng + 1, s);
+    PKLAUNCH("scan of group events");
     {
-      std::vector<uint8_t> hm((size_t)ng);
-      if (ng > 0) PK(hipMemcpyAsync(hm.data(), gmax, (size_t)ng, hipMemcpyDeviceToHost, s));
-      PK(hipStreamSynchronize(s));
-      int64_t steps = 0;
-      for (uint8_t m : hm) steps += m;
-      o.lane_steps = steps;
+      // unit lengths as 64-bit for the offsets
+      const int64_t n1 = NU + 1;
+      // widen slen into uoff, then scan in place through usums2
+      hipLaunchKernelGGL(k_widen_u32, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, (const uint32_t*)slen, n1,
+                         uoff);
+      PKLAUNCH("k_widen_u32");
+      scan_add<uint64_t>(uoff, uoff, usums2, n1, s);
+      PKLAUNCH("scan of unit events");
     }
-    {
-      size_t tb = 0;
-      PK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, glen, o.grp_off, (int)(ng + 1), s));
-      void* tscan = tmp(tb, e2);
-      PK(e2);
-      PK(hipcub::DeviceScan::ExclusiveSum(tscan, tb, glen, o.grp_off, (int)(ng + 1), s));
-    }
-    int64_t nev = 0;
-    PK(hipMemcpyAsync(&nev, o.grp_off + ng, 8, hipMemcpyDeviceToHost, s));
-    PK(hipStreamSynchronize(s));
-    o.n_events = nev;
-    // ---- 5b. gate-block regions -------------------------------------------
-    {
-      const int64_t n_reg = (int64_t)n_tiles * n_gb;
-      o.reg_first = (uint32_t*)own((size_t)(n_reg + 1) * 4, e2);
-      PK(e2);
-      hipLaunchKernelGGL(k_pk_fill_u32, dim3((unsigned)((n_reg + 1 + 255) / 256)), dim3(256), 0, s, o.reg_first,
-                         n_reg + 1, (uint32_t)NU);
-      PKLAUNCH("k_pk_fill_u32");
-      if (NU > 0) {
-        hipLaunchKernelGGL(k_pk_region_first, dim3((unsigned)((NU + 255) / 256)), dim3(256), 0, s, skeys, NU, gb_bits,
-                           low, n_gb, o.reg_first);
-        PKLAUNCH("k_pk_region_first");
-      }
-      std::vector<uint32_t> hrf((size_t)n_reg + 1);
-      PK(hipMemcpyAsync(hrf.data(), o.reg_first, (size_t)(n_reg + 1) * 4, hipMemcpyDeviceToHost, s));
-      PK(hipStreamSynchronize(s));
-      for (int64_t r = n_reg - 1; r >= 0; --r) hrf[r] = std::min(hrf[r], hrf[r + 1]);
-      PK(hipMemcpyAsync(o.reg_first, hrf.data(), (size_t)(n_reg + 1) * 4, hipMemcpyHostToDevice, s));
-      uint32_t* slen = (uint32_t*)tmp((size_t)(NU + 1) * 4, e2);
-      PK(e2);
-      uint64_t* uoff = (uint64_t*)tmp((size_t)(NU + 1) * 8, e2);
-      PK(e2);
-      int64_t* rev = (int64_t*)tmp((size_t)std::max<int64_t>(n_reg, 1) * 8, e2);
-      PK(e2);
-      hipLaunchKernelGGL(k_pk_sorted_len, dim3((unsigned)((NU + 1 + 255) / 256)), dim3(256), 0, s, sidx, recs, NU, slen);
-      PKLAUNCH("k_pk_sorted_len");
-      size_t tb = 0;
-      PK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, slen, uoff, (int)(NU + 1), s));
-      void* tscan = tmp(tb, e2);
-      PK(e2);
-      PK(hipcub::DeviceScan::ExclusiveSum(tscan, tb, slen, uoff, (int)(NU + 1), s));
-      if (n_reg > 0) {
-        hipLaunchKernelGGL(k_pk_region_events, dim3((unsigned)((n_reg + 255) / 256)), dim3(256), 0, s, uoff, o.reg_first,
-                           n_reg, rev);
-        PKLAUNCH("k_pk_region_events");
-      }
-      o.h_reg_events.resize((size_t)n_reg);
-      if (n_reg > 0)
-        PK(hipMemcpyAsync(o.h_reg_events.data(), rev, (size_t)n_reg * 8, hipMemcpyDeviceToHost, s));
-      PK(hipStreamSynchronize(s));
-    }
-    // ---- 6. fill --------------------------------------------------------
-    int32_t* d_bounds = (int32_t*)tmp(2 * sizeof(int32_t), e2);   // [alpha span bits, max events per bin]
+    o.reg_first = (uint32_t*)own((size_t)(n_reg + 1) * 4, e2);
     PK(e2);
-    {
-      const int32_t init[2] = {__builtin_bit_cast(int32_t, 1.0f), 0};
-      PK(hipMemcpyAsync(d_bounds, init, sizeof init, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_pk_fill_u32, dim3((unsigned)((n_reg + 1 + 255) / 256)), dim3(256), 0, s, o.reg_first,
+                       n_reg + 1, (uint32_t)NU);
+    PKLAUNCH("k_pk_fill_u32");
+    if (NU > 0) {
+      hipLaunchKernelGGL(k_pk_region_first, dim3((unsigned)((NU + 255) / 256)), dim3(256), 0, s, skeys, NU, gb_bits,
+                         low, n_gb, o.reg_first);
+      PKLAUNCH("k_pk_region_first");
     }
-    o.w32 = (uint32_t*)own((size_t)nev * 4, e2);
+    hipLaunchKernelGGL(k_pk_suffix_min, dim3(1), dim3(1024), 0, s, o.reg_first, n_reg + 1);
+    PKLAUNCH("k_pk_suffix_min");
+    if (n_reg > 0) {
+      hipLaunchKernelGGL(k_pk_region_events, dim3((unsigned)((n_reg + 255) / 256)), dim3(256), 0, s,
+                         (const uint64_t*)uoff, (const uint32_t*)o.reg_first, n_reg, rev);
+      PKLAUNCH("k_pk_region_events");
+    }
+    // ---- 7. fill --------------------------------------------------------
+    // every event may be packed (events outside the window are not: the
+    // arrays keep room for them)
+    o.w32 = (uint32_t*)own((size_t)N * 4, e2);
     PK(e2);
-    o.row = (uint32_t*)own((size_t)nev * 4, e2);
+    o.row = (uint32_t*)own((size_t)N * 4, e2);
     PK(e2);
-    o.alpha = (float*)own((size_t)nev * 4, e2);
+    o.alpha = (float*)own((size_t)N * 4, e2);
     PK(e2);
     o.desc = (uint2*)own((size_t)ng * kGroupUnits * 8, e2);
-    PK(e2);
-    o.dsrc = (int64_t*)own((size_t)ng * kGroupUnits * 8, e2);
     PK(e2);
     if (ng > 0) {
       FillArgs fa;
@@ -708,101 +883,79 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       fa.bins = B;
       fa.lib = in.lib;
       fa.gcell = o.gcell;
-      fa.tile_grp = o.tile_grp;
-      fa.tfirst = tfirst;
+      fa.tile_grp = (const uint32_t*)o.tile_grp;
+      fa.tfirst = o.tfirst;
       fa.sidx = sidx;
       fa.recs = recs;
       fa.grp_off = o.grp_off;
-      fa.n_groups = ng;
       fa.w32 = o.w32;
       fa.row = o.row;
       fa.alpha = o.alpha;
       fa.dbg_state = in.dbg_state;
       fa.dbg_bin = in.dbg_bin;
       fa.desc = o.desc;
-      fa.dsrc = o.dsrc;
-      fa.alpha_span = d_bounds;
-      const int64_t threads = ng * kGroupUnits;
-      hipLaunchKernelGGL(k_pk_fill, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, fa);
+      fa.alpha_span = (int32_t*)d_nu;
+      const size_t lds = (size_t)in.lib.lds_words * 4;
+      if (in.unit_events <= 8)
+        hipLaunchKernelGGL(k_pk_fill<8>, dim3((unsigned)n_tiles), dim3(256), lds, s, fa);
+      else
+        hipLaunchKernelGGL(k_pk_fill<16>, dim3((unsigned)n_tiles), dim3(256), lds, s, fa);
       PKLAUNCH("k_pk_fill");
       hipLaunchKernelGGL(k_pk_bin_max, dim3((unsigned)n_tiles), dim3(256), (size_t)4 << B.tile_log2, s, o.w32,
-                         o.grp_off, o.tile_grp, B.tile_log2, B.r_bits, d_bounds + 1);
+                         o.grp_off, (const uint32_t*)o.tile_grp, B.tile_log2, B.r_bits, (int32_t*)d_nu + 1);
       PKLAUNCH("k_pk_bin_max");
     }
-    {
-      int32_t hb[2] = {0, 0};
-      PK(hipMemcpyAsync(hb, d_bounds, sizeof hb, hipMemcpyDeviceToHost, s));
-      PK(hipStreamSynchronize(s));
-      o.alpha_span = __builtin_bit_cast(float, hb[0]);
-      o.max_bin_events = hb[1];
-    }
-    // ---- 7. table phases ------------------------------------------------
+    // ---- 8. table phases --------------------------------------------------
     if (in.slot_quads > 0 && ng > 0) {
-      int2* gc = (int2*)tmp((size_t)ng * 8, e2);
-      PK(e2);
-      const int64_t threads = ng * kGroupUnits;
-      hipLaunchKernelGGL(k_pk_group_cells, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, o.desc, o.gcell,
-                         ng, gc);
-      PKLAUNCH("k_pk_group_cells");
-      std::vector<int2> hgc((size_t)ng);
-      std::vector<int32_t> htg((size_t)n_tiles + 1);
-      PK(hipMemcpyAsync(hgc.data(), gc, (size_t)ng * 8, hipMemcpyDeviceToHost, s));
-      PK(hipMemcpyAsync(htg.data(), o.tile_grp, (size_t)(n_tiles + 1) * 4, hipMemcpyDeviceToHost, s));
-      PK(hipStreamSynchronize(s));
-      const int64_t cap = in.slot_quads;
-      std::vector<int4> ph;
-      std::vector<int32_t> poff((size_t)n_tiles + 1, 0);
-      bool all_full = true;
-      for (int32_t k = 0; k < n_tiles; ++k) {
-        poff[k] = (int32_t)ph.size();
-        int64_t g = htg[k];
-        const int64_t g1 = htg[k + 1];
-        while (g < g1) {
-          // a phase starts at group g and grows while the union of its
-          // groups' cell table ranges fits the slot
-          int64_t lo = INT64_MAX, hi = INT64_MIN;
-          int64_t e = g;
-          for (; e < g1; ++e) {
-            const int2 cc = hgc[(size_t)e];
-            if (cc.x < 0) continue;
-            const int64_t l = std::min(in.cq_lo[cc.x], in.cq_lo[cc.y]), h = std::max(in.cq_hi[cc.x], in.cq_hi[cc.y]);
-            const int64_t nl = std::min(lo, l), nh = std::max(hi, h);
-            if (e > g && nh - nl > cap) break;
-            lo = nl;
-            hi = nh;
-          }
-          if (lo == INT64_MAX) {  // only empty groups: nothing to stage
-            lo = 0;
-            hi = 0;
-          }
-          // a single group whose cells exceed the slot keeps its first cell's
-          // tables (the other lanes read the tables from global memory)
-          int32_t full = 1;
-          if (hi - lo > cap) {
-            const int2 cc = hgc[(size_t)g];
-            lo = in.cq_lo[cc.x];
-            hi = std::min<int64_t>(in.cq_hi[cc.x], lo + cap);
-            full = 0;
-            all_full = false;
-          }
-          ph.push_back(make_int4((int32_t)(e - htg[k]), (int32_t)lo, (int32_t)(hi - lo), full));
-          g = e;
-        }
-      }
-      poff[n_tiles] = (int32_t)ph.size();
-      o.n_phases = (int64_t)ph.size();
-      o.phases_full = all_full ? 1 : 0;
-      o.slot_quads = in.slot_quads;
-      o.phases = (int4*)own(std::max<size_t>(ph.size(), 1) * sizeof(int4), e2);
+      o.phases = (int4*)own((size_t)ng * sizeof(int4), e2);
       PK(e2);
       o.ph_off = (int32_t*)own((size_t)(n_tiles + 1) * 4, e2);
       PK(e2);
-      if (!ph.empty()) PK(hipMemcpyAsync(o.phases, ph.data(), ph.size() * sizeof(int4), hipMemcpyHostToDevice, s));
-      PK(hipMemcpyAsync(o.ph_off, poff.data(), poff.size() * 4, hipMemcpyHostToDevice, s));
+      int32_t* d_cq = (int32_t*)wc.take<int32_t>(2 * (size_t)n_cells);
+      if (!d_cq) {
+        snprintf(err, err_len, "pack: workspace of %zu bytes too small", ws2b->bytes);
+        st = hipErrorOutOfMemory;
+        goto fail;
+      }
+      PK(hipMemcpyAsync(d_cq, in.cq_lo.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
+      PK(hipMemcpyAsync(d_cq + n_cells, in.cq_hi.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
+      const int64_t threads = ng * kGroupUnits;
+      hipLaunchKernelGGL(k_pk_group_cells, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, o.desc, ng,
+                         gcells);
+      PKLAUNCH("k_pk_group_cells");
+      hipLaunchKernelGGL(k_pk_phases, dim3((unsigned)n_tiles), dim3(64), 0, s, (const int2*)gcells,
+                         (const uint32_t*)o.tile_grp, (const int32_t*)d_cq, (const int32_t*)(d_cq + n_cells), n_cells,
+                         (int64_t)in.slot_quads, ph_tmp, nph, (int32_t*)d_nu + 5);
+      PKLAUNCH("k_pk_phases");
+      hipLaunchKernelGGL(k_pk_fill_u32, dim3(1), dim3(256), 0, s, nph + n_tiles, (int64_t)1, 0u);
+      PKLAUNCH("k_pk_fill_u32");
+      scan_add<uint32_t>(nph, (uint32_t*)o.ph_off, psums, n_tiles + 1, s);
+      PKLAUNCH("scan of phase counts");
+      hipLaunchKernelGGL(k_pk_phase_copy, dim3((unsigned)n_tiles), dim3(256), 0, s, (const int4*)ph_tmp,
+                         (const uint32_t*)o.tile_grp, (const uint32_t*)o.ph_off, n_tiles, o.phases);
+      PKLAUNCH("k_pk_phase_copy");
+      o.slot_quads = in.slot_quads;
+    }
+    // ---- statistics back to the host (one wait) -----------------------------
+    {
+      uint32_t hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      uint64_t nev = 0;
+      uint32_t nphase = 0;
+      PK(hipMemcpyAsync(hs, d_nu, sizeof hs, hipMemcpyDeviceToHost, s));
+      PK(hipMemcpyAsync(&nev, uoff + NU, 8, hipMemcpyDeviceToHost, s));
+      if (o.ph_off) PK(hipMemcpyAsync(&nphase, o.ph_off + n_tiles, 4, hipMemcpyDeviceToHost, s));
+      o.h_reg_events.resize((size_t)n_reg);
+      if (n_reg > 0) PK(hipMemcpyAsync(o.h_reg_events.data(), rev, (size_t)n_reg * 8, hipMemcpyDeviceToHost, s));
       PK(hipStreamSynchronize(s));
+      o.alpha_span = __builtin_bit_cast(float, hs[0]);
+      o.max_bin_events = hs[1];
+      o.lane_steps = (int64_t)((uint64_t)hs[2] | ((uint64_t)hs[3] << 32));
+      o.max_tile_groups = (int32_t)hs[4];
+      o.phases_full = o.ph_off ? (int32_t)hs[5] : 0;
+      o.n_events = (int64_t)nev;
+      o.n_phases = nphase;
     }
   }
-  for (void* p : temps) (void)hipFree(p);
   o.bytes = held;
   *out = o;
   return hipSuccess;
@@ -810,7 +963,6 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
 fail:
   (void)hipStreamSynchronize(s);
   (void)hipGetLastError();
-  for (void* p : temps) (void)hipFree(p);
   pack_free(&o);
   return st;
 #undef PK

@@ -144,6 +144,7 @@ struct gtp_ctx_s {
   bool pack_ok = false;
   PackOut pk;
   double pack_ms = 0.0;
+  Workspace pk_ws[2];   // the pack's temporaries, kept between packs
 
   // kernel timing (gtp_profile_enable)
   bool prof_on = false;
@@ -595,12 +596,15 @@ gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, Bin
   in.gate_block_log2 = c->tun.gate_block_log2 ? c->tun.gate_block_log2 : kGateBlockLog2;
   in.bins = B;
   in.stream = c->stream;
+  in.ws = c->pk_ws;
+  const size_t ws_before = c->pk_ws[0].bytes + c->pk_ws[1].bytes;
   char msg[256] = {0};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   if (e0) (void)hipEventRecord(e0, c->stream);
   const hipError_t st = pack_events(in, &pk, msg, sizeof msg);
+  c->dev_bytes += (int64_t)(c->pk_ws[0].bytes + c->pk_ws[1].bytes) - (int64_t)ws_before;
   if (st != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -863,6 +867,8 @@ gtp_status gtp_destroy(gtp_ctx c) {
   (void)hipStreamSynchronize(c->stream);
   drop_pack(c);
   drop_batch(c);
+  for (Workspace& w : c->pk_ws)
+    if (w.p) (void)hipFree(w.p);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   DevBuf* all[] = {&c->lib_img, &c->load_axis, &c->load_inv, &c->quads, &c->gate_cell, &c->gate_out,
                    &c->gate_init, &c->plan_blk, &c->blk_tmp, &c->blk_tmp2, &c->scan_sums, &c->gprep, &c->gparam, &c->l0_part, &c->tile_tot, &c->tile_base,
