@@ -41,7 +41,7 @@ class _Problem(ctypes.Structure):
         ("n_events", ctypes.c_int64), ("gate_off", ctypes.c_void_p), ("t", ctypes.c_void_p),
         ("pin_bit", ctypes.c_void_p), ("slew", ctypes.c_void_p),
         ("t_end", ctypes.c_int64), ("bin_ps", ctypes.c_int64), ("vdd", ctypes.c_double),
-        ("sw_mode", ctypes.c_int32),
+        ("sw_mode", ctypes.c_int32), ("state_all_pins", ctypes.c_int32), ("glitch_clk", ctypes.c_int64),
     ]
 
 
@@ -75,6 +75,8 @@ class Oracle:
         L.orc_adjoint.argtypes = [ctypes.POINTER(_Problem), ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int]
         L.orc_validate.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(ctypes.c_int64)]
+        L.orc_gate_report.argtypes = [ctypes.POINTER(_Problem), ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_int]
         L.orc_bilerp.restype = ctypes.c_double
         L.orc_bilerp.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_double]
@@ -113,6 +115,8 @@ class Oracle:
         P.n_gates, P.n_nets = net.n_gates, net.n_nets
         P.n_events = ev.n_events
         P.t_end, P.bin_ps, P.vdd, P.sw_mode = ev.t_end, prob.bin_ps, prob.vdd, prob.sw_mode
+        P.state_all_pins = int(getattr(prob, "state_all_pins", 0))
+        P.glitch_clk = int(getattr(prob, "glitch_clk", 0))
         return P, keep
 
     # -- API ---------------------------------------------------------------
@@ -127,7 +131,7 @@ class Oracle:
         nb = self.num_bins(prob)
         b1 = nb if b1 is None else b1
         E = np.zeros(max(0, b1 - b0), np.float64)
-        tot = np.zeros(3, np.float64)
+        tot = np.zeros(4, np.float64)
         gl = None if gates is None else np.ascontiguousarray(gates, np.int64)
         bad = ctypes.c_int64(-1)
         rc = self.lib.orc_forward(ctypes.byref(P), b0, b1, leak_mode, None if gl is None else gl.ctypes.data,
@@ -150,6 +154,17 @@ class Oracle:
         if rc != OK:
             raise OracleError(rc, bad.value)
         return st, b
+
+    def gate_report(self, prob, net_load=None, leak_scale=None, nthreads: int = 0):
+        """(per-gate energies [n_gates, 4] in fJ: leakage, internal, switching,
+        glitch; t_max = latest event time, -1 without events)."""
+        P, keep = self._arrays(prob, net_load, leak_scale)
+        ge = np.zeros((prob.net.n_gates, 4), np.float64)
+        tm = ctypes.c_int64(-1)
+        rc = self.lib.orc_gate_report(ctypes.byref(P), ge.ctypes.data, ctypes.byref(tm), nthreads)
+        if rc != OK:
+            raise OracleError(rc)
+        return ge, tm.value
 
     def validate(self, prob):
         P, keep = self._arrays(prob)

@@ -20,10 +20,23 @@
  *   3. the group's events are applied to the gate state.
  * After the last group the leakage runs to the end of the window.
  *
+ * Glitch power (optional, glitch_clk > 0; Sec. 2.2 Glitch Power, the
+ * clock-cycle detection of Sec. 2.4 and Sec. 4.3 GlitchDetectUpdate, Eq.
+ * glitch scaling ratio): per pin, a counter of the pin's events in the
+ * current clock cycle (reset when the pin's cycle changes). An event that is
+ * not its pin's first in the cycle is a glitch event: its dynamic energy
+ * (internal + switching) is scaled by r = min(1, (2 pw / (rSlew + fSlew))^2),
+ * pw = time since the pin's previous event, rSlew + fSlew = the slews of that
+ * event and this one (a rise and a fall: the pin toggles), and is counted as
+ * glitch energy (the waveform gets the scaled energy, the internal and
+ * switching totals nothing).
+ *
  * Readings where the paper is silent (also listed in the design doc):
  *   - switching energy: 0.5*C*V^2 on every output toggle (sw_mode 0), or the
  *     paper's C*V^2 on an output rise only (sw_mode 1, Eq. switching energy);
- *   - state index over input pins only, bit p = value of input pin p;
+ *   - state index over the input pins, bit p = value of input pin p
+ *     (state_all_pins = 1: over all pins, bit I = the output, the SIPL index of
+ *     Sec. 4.1 over every pin of the cell);
  *   - table direction = the event's own new value (1 = rise);
  *   - bins are half-open [b*D, (b+1)*D); a partial last bin is still divided
  *     by D; events must lie in [0, t_end);
@@ -182,12 +195,58 @@ static void add_leak(const orc_problem* P, acc_t* A, int64_t t0, int64_t t1, dou
   }
 }
 
-/* Evaluate one gate (Algorithm 1 order). trace arrays may be NULL. */
+/* Per-pin state of the clock-cycle glitch detection. */
+typedef struct {
+  int64_t cyc;      /* clock cycle of the pin's last event (-1: none yet) */
+  int64_t last_t;   /* time of the pin's last event */
+  float last_slew;  /* slew of the pin's last event */
+  int cnt;          /* events of the pin in cycle cyc */
+} pin_glitch;
+
+/* GlitchDetectUpdate for one event of a pin at time t with slew `slew`:
+ * returns the glitch scaling ratio r > 0 when the event is not the pin's
+ * first in its clock cycle, else -1 (a regular event). */
+static double glitch_update(const orc_problem* P, pin_glitch* s, int64_t t, float slew) {
+  const int64_t cyc = t / P->glitch_clk;
+  if (s->cyc != cyc) {
+    s->cyc = cyc;
+    s->cnt = 0;
+  }
+  s->cnt += 1;
+  double r = -1.0;
+  if (s->cnt > 1) {
+    const double pw = (double)(t - s->last_t);
+#if ORC_PLANT == 11
+    const double q = pw / ((double)slew + (double)s->last_slew); /* planted: dropped factor 2 */
+#else
+    const double q = 2.0 * pw / ((double)slew + (double)s->last_slew);
+#endif
+    r = q * q < 1.0 ? q * q : 1.0;
+  }
+  s->last_t = t;
+  s->last_slew = slew;
+  return r;
+}
+
+/* Evaluate one gate (Algorithm 1 order). trace arrays may be NULL.
+ * tot: [E_int, E_sw, E_leak, E_gl] of the gate are added to it. */
 static int eval_gate(const orc_problem* P, int64_t g, acc_t* A, double* tot, int32_t* st_before,
                      int64_t* bin_out, int64_t* bad) {
   const int32_t c = P->gate_cell[g];
   const int32_t I = P->n_inputs[c];
-  const uint32_t smask = (1u << I) - 1u;
+  /* the state index: input pins, or all pins (bit I = output) */
+#if ORC_PLANT == 13
+  const uint32_t smask = (1u << I) - 1u; /* planted: the output pin left out of an all-pin state */
+#else
+  const uint32_t smask = P->state_all_pins ? (1u << (I + 1)) - 1u : (1u << I) - 1u;
+#endif
+  pin_glitch pg[32];
+  for (int p = 0; p < 32; ++p) {
+    pg[p].cyc = -1;
+    pg[p].last_t = 0;
+    pg[p].last_slew = 0.f;
+    pg[p].cnt = 0;
+  }
   const double C = P->net_load[P->gate_out_net[g]];
   const double lam = P->leak_scale ? P->leak_scale[g] : 1.0;
   const float* lk = P->leak + P->leak_base[c];
@@ -248,9 +307,19 @@ static int eval_gate(const orc_problem* P, int64_t g, acc_t* A, double* tot, int
       const double ei = orc_bilerp(P, c, k, (double)P->slew[q], C);
       const double es = (p == I) ? sw_energy(P, C, v) : 0.0;
       const int64_t b = bin_of(P, t);
-      acc_add(A, b, ei + es);
-      tot[0] += ei;
-      tot[1] += es;
+      const double r = P->glitch_clk > 0 ? glitch_update(P, &pg[p], t, P->slew[q]) : -1.0;
+      if (r > 0.0) {
+#if ORC_PLANT == 12
+        acc_add(A, b, ei + es); /* planted: glitch energy not scaled in the waveform */
+#else
+        acc_add(A, b, r * (ei + es));
+#endif
+        tot[3] += r * (ei + es);
+      } else {
+        acc_add(A, b, ei + es);
+        tot[0] += ei;
+        tot[1] += es;
+      }
       if (st_before) st_before[q] = (int32_t)sl;
       if (bin_out) bin_out[q] = b;
     }
@@ -280,7 +349,7 @@ int orc_forward(const orc_problem* P, int64_t b0, int64_t b1, int leak_mode, con
   int nt = nthreads > 0 ? nthreads : orc_max_threads();
   if (nt < 1) nt = 1;
   memset(E, 0, sizeof(double) * (size_t)nb);
-  double tot_all[3] = {0, 0, 0};
+  double tot_all[4] = {0, 0, 0, 0};
   int status = ORC_OK;
   int64_t bad = -1;
 #pragma omp parallel num_threads(nt)
@@ -289,7 +358,7 @@ int orc_forward(const orc_problem* P, int64_t b0, int64_t b1, int leak_mode, con
     A.b0 = b0; A.b1 = b1; A.mode = leak_mode;
     A.E = (double*)calloc((size_t)(nb > 0 ? nb : 1), sizeof(double));
     A.diff = (double*)calloc((size_t)nb + 1, sizeof(double));
-    double tot[3] = {0, 0, 0};
+    double tot[4] = {0, 0, 0, 0};
     int st = (A.E && A.diff) ? ORC_OK : ORC_ERR_INVALID_ARG;
     int64_t mybad = -1;
 #pragma omp for schedule(dynamic, 64)
@@ -308,12 +377,12 @@ int orc_forward(const orc_problem* P, int64_t b0, int64_t b1, int leak_mode, con
       if (st != ORC_OK && status == ORC_OK) { status = st; bad = mybad; }
       if (A.E)
         for (int64_t b = 0; b < nb; ++b) E[b] += A.E[b];
-      for (int q = 0; q < 3; ++q) tot_all[q] += tot[q];
+      for (int q = 0; q < 4; ++q) tot_all[q] += tot[q];
     }
     free(A.E);
     free(A.diff);
   }
-  if (totals) { totals[0] = tot_all[0]; totals[1] = tot_all[1]; totals[2] = tot_all[2]; }
+  if (totals) { totals[0] = tot_all[0]; totals[1] = tot_all[1]; totals[2] = tot_all[2]; totals[3] = tot_all[3]; }
   if (bad_event) *bad_event = bad;
   return status;
 }
@@ -323,7 +392,7 @@ int orc_event_trace(const orc_problem* P, int32_t* state_before, int64_t* bin, i
   acc_t A;
   double dummy = 0;
   A.b0 = 0; A.b1 = 0; A.mode = 0; A.E = &dummy; A.diff = NULL;
-  double tot[3] = {0, 0, 0};
+  double tot[4] = {0, 0, 0, 0};
   for (int64_t g = 0; g < P->n_gates; ++g) {
     int64_t bad = -1;
     int st = eval_gate(P, g, &A, tot, state_before, bin, &bad);
@@ -332,11 +401,37 @@ int orc_event_trace(const orc_problem* P, int32_t* state_before, int64_t* bin, i
   return ORC_OK;
 }
 
+int orc_gate_report(const orc_problem* P, double* gate_e, int64_t* t_max, int nthreads) {
+  if (!P || !gate_e || !t_max) return ORC_ERR_INVALID_ARG;
+  int nt = nthreads > 0 ? nthreads : orc_max_threads();
+  int status = ORC_OK;
+  int64_t tm = -1;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nt) reduction(max : tm)
+  for (int64_t g = 0; g < P->n_gates; ++g) {
+    acc_t A;
+    double dummy = 0;
+    A.b0 = 0; A.b1 = 0; A.mode = 0; A.E = &dummy; A.diff = NULL;
+    double tot[4] = {0, 0, 0, 0};
+    int64_t bad = -1;
+    if (eval_gate(P, g, &A, tot, NULL, NULL, &bad) != ORC_OK) {
+#pragma omp critical
+      status = ORC_ERR_INVALID_ARG;
+    }
+    gate_e[4 * g + 0] = tot[2];
+    gate_e[4 * g + 1] = tot[0];
+    gate_e[4 * g + 2] = tot[1];
+    gate_e[4 * g + 3] = tot[3];
+    if (P->gate_off[g + 1] > P->gate_off[g] && P->t[P->gate_off[g + 1] - 1] > tm) tm = P->t[P->gate_off[g + 1] - 1];
+  }
+  *t_max = tm;
+  return status;
+}
+
 int orc_validate(const orc_problem* P, int64_t* bad_event) {
   acc_t A;
   double dummy = 0;
   A.b0 = 0; A.b1 = 0; A.mode = 0; A.E = &dummy; A.diff = NULL;
-  double tot[3] = {0, 0, 0};
+  double tot[4] = {0, 0, 0, 0};
   for (int64_t g = 0; g < P->n_gates; ++g) {
     int64_t bad = -1;
     int st = eval_gate(P, g, &A, tot, NULL, NULL, &bad);
@@ -398,12 +493,19 @@ int orc_adjoint(const orc_problem* P, const double* gP, int leak_mode, double* g
   for (int64_t g = 0; g < P->n_gates; ++g) {
     const int32_t c = P->gate_cell[g];
     const int32_t I = P->n_inputs[c];
-    const uint32_t smask = (1u << I) - 1u;
+    const uint32_t smask = P->state_all_pins ? (1u << (I + 1)) - 1u : (1u << I) - 1u;
     const double C = P->net_load[P->gate_out_net[g]];
     const float* lk = P->leak + P->leak_base[c];
     uint32_t vals = P->gate_init[g] & ((1u << (I + 1)) - 1u);
     int64_t t_prev = 0;
     double dC = 0, dl = 0;
+    pin_glitch pg[32];
+    for (int p = 0; p < 32; ++p) {
+      pg[p].cyc = -1;
+      pg[p].last_t = 0;
+      pg[p].last_slew = 0.f;
+      pg[p].cnt = 0;
+    }
     int64_t e = P->gate_off[g];
     const int64_t e_end = P->gate_off[g + 1];
     while (e < e_end) {
@@ -418,6 +520,10 @@ int orc_adjoint(const orc_problem* P, const double* gP, int leak_mode, double* g
         const int32_t k = P->state_to_table[P->map_base[c] + 2 * (int64_t)s + v];
         double d = bilerp_dload(P, c, k, (double)P->slew[q], C);
         if (p == I) d += sw_energy_dC(P, v);
+        if (P->glitch_clk > 0) {
+          const double r = glitch_update(P, &pg[p], t, P->slew[q]);
+          if (r > 0.0) d *= r;
+        }
         dC += gP[b] / D * d;
       }
       for (int64_t q = e; q < e2; ++q) {

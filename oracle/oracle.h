@@ -55,6 +55,8 @@ typedef struct {
   int64_t t_end, bin_ps;
   double vdd;
   int32_t sw_mode;               /* 0: 0.5*C*V^2 per output toggle; 1: C*V^2 per output rise */
+  int32_t state_all_pins;        /* 0: state index over the input pins (2^I); 1: over all pins, bit I = output (2^(I+1)) */
+  int64_t glitch_clk;            /* clock period (ps) of the glitch detection; 0: no glitch analysis */
 } orc_problem;
 
 /* Number of bins: ceil(t_end / bin_ps). */
@@ -69,9 +71,11 @@ double orc_bilerp(const orc_problem* P, int32_t c, int32_t k, double slew, doubl
  * leak_mode 0: leakage of every interval added bin by bin (direct);
  * leak_mode 1: fully covered bins via a difference array (same values).
  * gates: optional subset (NULL = all gates). totals (may be NULL) receives
- * [sum E_int, sum E_sw, sum E_leak] over [0, t_end) for the gate set,
- * independent of the bin window. nthreads <= 0 uses all threads.
- * Returns ORC_* status; on error *bad_event (if not NULL) holds an event.
+ * [sum E_int, sum E_sw, sum E_leak, sum E_gl] over [0, t_end) for the gate
+ * set, independent of the bin window (with glitch analysis on, the scaled
+ * energy of a glitch event is counted in E_gl only). nthreads <= 0 uses all
+ * threads. Returns ORC_* status; on error *bad_event (if not NULL) holds an
+ * event.
  */
 int orc_forward(const orc_problem* P, int64_t b0, int64_t b1, int leak_mode, const int64_t* gates,
                 int64_t n_gate_list, double* E, double* totals, int nthreads, int64_t* bad_event);
@@ -87,6 +91,14 @@ int orc_event_trace(const orc_problem* P, int32_t* state_before, int64_t* bin, i
  */
 int orc_adjoint(const orc_problem* P, const double* gP, int leak_mode, double* grad_load, double* grad_scale,
                 int nthreads);
+
+/*
+ * Per-gate report: gate_e[4*g + k] = energy (fJ) of gate g over [0, t_end),
+ * k = 0 leakage, 1 internal, 2 switching, 3 glitch; *t_max = the latest event
+ * time (the horizon of the paper's average power p = E / t_max), -1 without
+ * events.
+ */
+int orc_gate_report(const orc_problem* P, double* gate_e, int64_t* t_max, int nthreads);
 
 /* Validation only: first offending event in gate-major order. */
 int orc_validate(const orc_problem* P, int64_t* bad_event);

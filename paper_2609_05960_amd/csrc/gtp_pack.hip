@@ -16,12 +16,13 @@
 //   5. k_pk_tile_first + suffix minimum: each tile's first unit; groups of 64
 //      units per tile, scanned into tile_grp;
 //   6. k_pk_group_len: per group its events and longest unit (from the sorted
-//      keys), per unit its length; scans into group and unit event offsets;
-//      per (tile, gate block) region its first unit and events;
+//      keys), scanned into group offsets; per (tile, gate block) region its
+//      events and first unit;
 //   7. k_pk_fill: one workgroup per tile, one wavefront per group: the unit
-//      descriptors and every event's record in the unit-interleaved order;
-//   8. k_pk_bin_max (most events in one bin), k_pk_group_cells +
-//      k_pk_phases + k_pk_phase_copy (the table phases of every tile).
+//      descriptors and every event's record in the unit-interleaved order,
+//      and the most events in one bin (LDS histogram of the tile);
+//   8. k_pk_group_cells + k_pk_phases + k_pk_phase_copy (the table phases of
+//      every tile).
 // Temporaries live in a workspace the caller keeps between packs; the pack
 // runs once per event set and bin width, its time is reported apart from the
 // forward.
@@ -217,21 +218,24 @@ __device__ __forceinline__ uint32_t key_len(uint64_t key, int32_t gb_log2) {
 }
 
 // One workgroup per tile, one wavefront per group: the group's events
-// (glen), its longest unit (gmax, the lane steps it costs a wavefront) and
-// every unit's length (slen, for the per-region event counts).
+// (glen), its longest unit (gmax, the lane steps it costs a wavefront), and the
+// events of every (tile, gate block) region (rev, zeroed before; a group spans
+// few regions, each summed over its lanes and added once).
 __global__ void __launch_bounds__(256) k_pk_group_len(const uint32_t* tile_grp, const uint32_t* tfirst,
-                                                      const uint64_t* skey, int32_t gb_log2, int64_t* glen,
-                                                      uint32_t* slen, unsigned long long* lane_steps,
-                                                      uint32_t* max_tile_groups) {
+                                                      const uint64_t* skey, int32_t gb_log2, int32_t gb_bits,
+                                                      int32_t n_gb, int64_t* glen, unsigned long long* rev,
+                                                      unsigned long long* lane_steps, uint32_t* max_tile_groups) {
   const int32_t k = blockIdx.x;
   const int lane = (int)(threadIdx.x & 63);
   const int64_t g0 = tile_grp[k], g1 = tile_grp[k + 1];
   const int64_t j1 = tfirst[k + 1];
+  const int low = 5 + gb_log2;
   unsigned long long steps = 0;
   for (int64_t g = g0 + (threadIdx.x >> 6); g < g1; g += blockDim.x >> 6) {
     const int64_t j = tfirst[k] + (g - g0) * kGroupUnits + lane;
-    const uint32_t len = j < j1 ? key_len(skey[j], gb_log2) : 0u;
-    if (j < j1) slen[j] = len;
+    const bool act = j < j1;
+    const uint64_t key = act ? skey[j] : 0ull;
+    const uint32_t len = act ? key_len(key, gb_log2) : 0u;
     uint32_t s = len, mx = len;
     for (int o = 32; o > 0; o >>= 1) {
       s += __shfl_xor(s, o, 64);
@@ -241,21 +245,22 @@ __global__ void __launch_bounds__(256) k_pk_group_len(const uint32_t* tile_grp, 
       glen[g] = s;
       steps += mx;
     }
+    // region events: one pass per distinct region among the active lanes
+    const int64_t reg = (int64_t)k * n_gb + (int64_t)((key >> low) & ((1ull << gb_bits) - 1ull));
+    uint64_t todo = __ballot(act);
+    while (todo) {
+      const int first = __ffsll((unsigned long long)todo) - 1;
+      const int64_t r0 = __shfl(reg, first, 64);
+      const bool mine = act && reg == r0;
+      const uint64_t m = __ballot(mine);
+      uint32_t v = mine ? len : 0u;
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == first) atomicAdd(&rev[r0], (unsigned long long)v);
+      todo &= ~m;
+    }
   }
   if (lane == 0 && steps) atomicAdd(lane_steps, steps);
   if (threadIdx.x == 0) atomicMax(max_tile_groups, (uint32_t)(g1 - g0));
-}
-
-__global__ void __launch_bounds__(256) k_widen_u32(const uint32_t* in, int64_t n, uint64_t* out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = in[i];
-}
-
-__global__ void __launch_bounds__(256) k_pk_region_events(const uint64_t* uoff, const uint32_t* rfirst, int64_t n_reg,
-                                                          int64_t* rev) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_reg) return;
-  rev[r] = (int64_t)(uoff[rfirst[r + 1]] - uoff[rfirst[r]]);
 }
 
 struct FillArgs {
@@ -275,6 +280,7 @@ struct FillArgs {
   int32_t* dbg_state;         // optional, gate-major: state before the event's group
   int64_t* dbg_bin;           // optional, gate-major: bin of the event
   int32_t* alpha_span;        // max over events of |1 - alpha| + |alpha| (FP32 bits; positive floats order as ints)
+  int32_t* max_bin;           // most events in one bin
 };
 
 // One workgroup per tile, one wavefront per group of the tile, one lane per
@@ -290,8 +296,10 @@ template <int kS>
 __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
   extern __shared__ uint32_t lds[];
   const LdsLib L = stage_library(a.lib, lds);
-  __syncthreads();
+  int32_t* hist = reinterpret_cast<int32_t*>(lds + ((a.lib.lds_words + 3) & ~3));   // events per bin of the tile
   const BinSpec& B = a.bins;
+  for (int i = threadIdx.x; i < (1 << B.tile_log2); i += blockDim.x) hist[i] = 0;
+  __syncthreads();
   const int32_t k = blockIdx.x;
   const int lane = (int)(threadIdx.x & 63);
   const int64_t g0 = a.tile_grp[k], g1 = a.tile_grp[k + 1];
@@ -348,6 +356,7 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
         float al;
         slew_segment(axis, inv, a.lib.n_slew, sl[kk], i, al);
         const uint32_t q = (uint32_t)(L.map_q[cm.map_off + 2 * (int)st + (int)v] + i * qstride);
+        atomicAdd(&hist[bl], 1);
         a.w32[pos] = (bl << B.r_bits) | rr | ((cur & in_mask) << kStateShift);
         a.row[pos] = q | ((pin == (uint32_t)cm.n_in ? 1u : 0u) << kOutBit) | (v << 31);
         a.alpha[pos] = al;
@@ -363,27 +372,11 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
   }
   for (int o = 32; o > 0; o >>= 1) span = fmaxf(span, __shfl_xor(span, o, 64));
   if (lane == 0) atomicMax(a.alpha_span, __float_as_int(span));
-}
-
-// Largest number of events in one bin: one workgroup per tile counts the
-// tile's packed events per bin in LDS (the in-tile bin is in the event
-// word), then one atomic max per wavefront.
-__global__ void __launch_bounds__(256) k_pk_bin_max(const uint32_t* w32, const int64_t* grp_off,
-                                                    const uint32_t* tile_grp, int32_t tile_log2, int32_t r_bits,
-                                                    int32_t* out) {
-  extern __shared__ int32_t hist[];
-  const int nb = 1 << tile_log2;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
-  __syncthreads();
-  const int32_t k = blockIdx.x;
-  const int64_t e0 = grp_off[tile_grp[k]], e1 = grp_off[tile_grp[k + 1]];
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-    atomicAdd(&hist[(w32[e] & kTimeMask) >> r_bits], 1);
   __syncthreads();
   int mx = 0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) mx = max(mx, hist[i]);
+  for (int i = threadIdx.x; i < (1 << B.tile_log2); i += blockDim.x) mx = max(mx, hist[i]);
   for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
-  if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(out, mx);
+  if (lane == 0 && mx > 0) atomicMax(a.max_bin, mx);
 }
 
 // First and last cell among a group's units (-1 for an empty group); the
@@ -749,8 +742,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
                        align256((size_t)NU * sizeof(UnitRec)) + align256(usort_tmp) +
                        align256((size_t)(n_tiles + 1) * 4) + align256((size_t)scan_sums_items(n_tiles + 1) * 4) +
                        align256((size_t)(ng_max + 1) * 8) + align256((size_t)scan_sums_items(ng_max + 1) * 8) +
-                       align256((size_t)(NU + 1) * 4) + align256((size_t)(NU + 1) * 8) +
-                       align256((size_t)scan_sums_items(NU + 1) * 8) + align256((size_t)std::max<int64_t>(n_reg, 1) * 8) +
+                       align256((size_t)std::max<int64_t>(n_reg, 1) * 8) +
                        align256((size_t)ng_max * 8) + align256((size_t)ng_max * sizeof(int4)) +
                        align256((size_t)(n_tiles + 1) * 4) + align256((size_t)scan_sums_items(n_tiles + 1) * 4) +
                        align256((size_t)n_cells * 8) + 4096;
@@ -766,9 +758,6 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     uint32_t* tsums = wc.take<uint32_t>((size_t)scan_sums_items(n_tiles + 1));
     int64_t* glen = wc.take<int64_t>((size_t)ng_max + 1);
     int64_t* gsums = wc.take<int64_t>((size_t)scan_sums_items(ng_max + 1));
-    uint32_t* slen = wc.take<uint32_t>((size_t)NU + 1);
-    uint64_t* uoff = wc.take<uint64_t>((size_t)NU + 1);
-    uint64_t* usums2 = wc.take<uint64_t>((size_t)scan_sums_items(NU + 1));
     int64_t* rev = wc.take<int64_t>((size_t)std::max<int64_t>(n_reg, 1));
     int2* gcells = wc.take<int2>((size_t)ng_max);
     int4* ph_tmp = wc.take<int4>((size_t)ng_max);
@@ -831,24 +820,17 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     PK(e2);
     hipLaunchKernelGGL(k_pk_fill_u64, dim3(1), dim3(256), 0, s, (uint64_t*)(glen + ng), (int64_t)1, (uint64_t)0);
     PKLAUNCH("k_pk_fill_u64");
-    hipLaunchKernelGGL(k_pk_fill_u32, dim3(1), dim3(256), 0, s, slen + NU, (int64_t)1, 0u);
-    PKLAUNCH("k_pk_fill_u32");
+    if (n_reg > 0) {
+      hipLaunchKernelGGL(k_pk_fill_u64, dim3((unsigned)((n_reg + 255) / 256)), dim3(256), 0, s, (uint64_t*)rev, n_reg,
+                         (uint64_t)0);
+      PKLAUNCH("k_pk_fill_u64");
+    }
     hipLaunchKernelGGL(k_pk_group_len, dim3((unsigned)n_tiles), dim3(256), 0, s, (const uint32_t*)o.tile_grp,
-                       (const uint32_t*)o.tfirst, (const uint64_t*)skeys, (int32_t)in.gate_block_log2, glen, slen,
-                       (unsigned long long*)(d_nu + 2), d_nu + 4);
+                       (const uint32_t*)o.tfirst, (const uint64_t*)skeys, (int32_t)in.gate_block_log2, (int32_t)gb_bits,
+                       n_gb, glen, (unsigned long long*)rev, (unsigned long long*)(d_nu + 2), d_nu + 4);
     PKLAUNCH("k_pk_group_len");
     scan_add<int64_t>(glen, o.grp_off, gsums, ng + 1, s);
     PKLAUNCH("scan of group events");
-    {
-      // unit lengths as 64-bit for the offsets
-      const int64_t n1 = NU + 1;
-      // widen slen into uoff, then scan in place through usums2
-      hipLaunchKernelGGL(k_widen_u32, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, (const uint32_t*)slen, n1,
-                         uoff);
-      PKLAUNCH("k_widen_u32");
-      scan_add<uint64_t>(uoff, uoff, usums2, n1, s);
-      PKLAUNCH("scan of unit events");
-    }
     o.reg_first = (uint32_t*)own((size_t)(n_reg + 1) * 4, e2);
     PK(e2);
     hipLaunchKernelGGL(k_pk_fill_u32, dim3((unsigned)((n_reg + 1 + 255) / 256)), dim3(256), 0, s, o.reg_first,
@@ -861,11 +843,6 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     }
     hipLaunchKernelGGL(k_pk_suffix_min, dim3(1), dim3(1024), 0, s, o.reg_first, n_reg + 1);
     PKLAUNCH("k_pk_suffix_min");
-    if (n_reg > 0) {
-      hipLaunchKernelGGL(k_pk_region_events, dim3((unsigned)((n_reg + 255) / 256)), dim3(256), 0, s,
-                         (const uint64_t*)uoff, (const uint32_t*)o.reg_first, n_reg, rev);
-      PKLAUNCH("k_pk_region_events");
-    }
     // ---- 7. fill --------------------------------------------------------
     // every event may be packed (events outside the window are not: the
     // arrays keep room for them)
@@ -895,15 +872,16 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       fa.dbg_bin = in.dbg_bin;
       fa.desc = o.desc;
       fa.alpha_span = (int32_t*)d_nu;
-      const size_t lds = (size_t)in.lib.lds_words * 4;
-      if (in.unit_events <= 8)
+      fa.max_bin = (int32_t*)d_nu + 1;
+      const size_t lds = (size_t)((in.lib.lds_words + 3) & ~3) * 4 + ((size_t)4 << B.tile_log2);
+      if (in.unit_events <= 8) {
+        PK(hipFuncSetAttribute((const void*)k_pk_fill<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         hipLaunchKernelGGL(k_pk_fill<8>, dim3((unsigned)n_tiles), dim3(256), lds, s, fa);
-      else
+      } else {
+        PK(hipFuncSetAttribute((const void*)k_pk_fill<16>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         hipLaunchKernelGGL(k_pk_fill<16>, dim3((unsigned)n_tiles), dim3(256), lds, s, fa);
+      }
       PKLAUNCH("k_pk_fill");
-      hipLaunchKernelGGL(k_pk_bin_max, dim3((unsigned)n_tiles), dim3(256), (size_t)4 << B.tile_log2, s, o.w32,
-                         o.grp_off, (const uint32_t*)o.tile_grp, B.tile_log2, B.r_bits, (int32_t*)d_nu + 1);
-      PKLAUNCH("k_pk_bin_max");
     }
     // ---- 8. table phases --------------------------------------------------
     if (in.slot_quads > 0 && ng > 0) {
@@ -942,7 +920,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       uint64_t nev = 0;
       uint32_t nphase = 0;
       PK(hipMemcpyAsync(hs, d_nu, sizeof hs, hipMemcpyDeviceToHost, s));
-      PK(hipMemcpyAsync(&nev, uoff + NU, 8, hipMemcpyDeviceToHost, s));
+      PK(hipMemcpyAsync(&nev, o.grp_off + ng, 8, hipMemcpyDeviceToHost, s));
       if (o.ph_off) PK(hipMemcpyAsync(&nphase, o.ph_off + n_tiles, 4, hipMemcpyDeviceToHost, s));
       o.h_reg_events.resize((size_t)n_reg);
       if (n_reg > 0) PK(hipMemcpyAsync(o.h_reg_events.data(), rev, (size_t)n_reg * 8, hipMemcpyDeviceToHost, s));

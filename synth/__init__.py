@@ -94,6 +94,8 @@ class Problem:
     bin_ps: int
     sw_mode: int = 0
     name: str = ""
+    state_all_pins: int = 0     # 1: state index over every pin (bit I = output); the library then holds 2^(I+1) states
+    glitch_clk: int = 0         # clock period of the glitch detection (ps); 0: off
 
     @property
     def n_bins(self) -> int:

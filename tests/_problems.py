@@ -70,6 +70,7 @@ def load_golden(name, sw_mode=0):
     with open(os.path.join(GOLDEN, name)) as f:
         fx = json.load(f)
     prob = build_problem(fx["cells"], fx["gates"], fx["events"], fx["t_end"], fx["bin_ps"], fx["vdd"], sw_mode)
+    prob.glitch_clk = int(fx.get("glitch_clk", 0))
     return prob, fx
 
 

@@ -57,12 +57,29 @@ def pin_golden_b(O):
     E, tot = O.forward(prob, return_totals=True)
     np.testing.assert_allclose(E, exp["bins_fj"], rtol=1e-12, atol=1e-15)
     c = exp["components_fj"]
-    np.testing.assert_allclose(tot, [c["int"], c["sw"], c["leak"]], rtol=1e-12)
+    np.testing.assert_allclose(tot[:3], [c["int"], c["sw"], c["leak"]], rtol=1e-12)
+    assert tot[3] == 0.0
     st, b = O.event_trace(prob)
     assert st.tolist() == exp["state_before"] and b.tolist() == exp["bin"]
     gl, gs = O.adjoint(prob, np.ones(prob.n_bins))
     assert abs(gl[prob.net.gate_out_net[0]] - exp["grad_unit_g"]["load"]) < 1e-13
     assert abs(gs[0] - exp["grad_unit_g"]["leak_scale"]) < 1e-15
+
+
+def pin_golden_c(O):
+    """Hand-computed glitch waveform and per-gate components (fixture example_c)."""
+    prob, fx = load_golden("example_c.json")
+    exp = fx["expect"]
+    E, tot = O.forward(prob, return_totals=True)
+    np.testing.assert_allclose(E, exp["bins_fj"], rtol=1e-12, atol=1e-15)
+    c = exp["components_fj"]
+    np.testing.assert_allclose(tot, [c["int"], c["sw"], c["leak"], c["gl"]], rtol=1e-12)
+    assert abs(E.sum() - exp["total_fj"]) < 1e-12
+    GE, tmax = O.gate_report(prob)
+    np.testing.assert_allclose(GE[0], [c["leak"], c["int"], c["sw"], c["gl"]], rtol=1e-12)
+    assert tmax == exp["t_max"]
+    prob.glitch_clk = 0
+    np.testing.assert_allclose(O.forward(prob), exp["no_glitch_bins_fj"], rtol=1e-12, atol=1e-15)
 
 
 def pin_bin_index(O):
@@ -156,15 +173,22 @@ def pin_leakage_closed_form(O):
         assert abs(P[10] - 1e-6 * rate * 50 / 100) < 1e-13 * rate
 
 
-def _bruteforce_bins(prob):
-    """Plain-definition waveform: dynamic energy of every event in its bin, and
-    leakage integrated picosecond by picosecond at the state given by toggle
-    parity (init bit XOR number of events on the pin at or before t).
-    Interpolation by a library linear interpolator on the float32 tables."""
+def _bruteforce(prob):
+    """Plain-definition waveform and per-gate energies: dynamic energy of every
+    event in its bin, and leakage integrated picosecond by picosecond at the
+    state given by toggle parity (init bit XOR number of events on the pin at
+    or before t). Interpolation by a library linear interpolator on the
+    float32 tables. Glitches (prob.glitch_clk > 0): an event is a glitch when
+    its pin's previous event lies in the same clock cycle; its dynamic energy
+    is scaled by min(1, (2 * gap / (sum of the two slews))^2) and counted as
+    glitch energy. Returns (bins [n_bins], per-gate [G, 4] = leak, int, sw, gl)."""
     lib, net, ev = prob.lib, prob.net, prob.ev
     nb = prob.n_bins
     E = np.zeros(nb)
+    GE = np.zeros((net.n_gates, 4))
     ns, nl = lib.n_slew, lib.n_load
+    allp = int(getattr(prob, "state_all_pins", 0))
+    T = int(getattr(prob, "glitch_clk", 0))
     for g in range(net.n_gates):
         c = int(net.gate_cell[g])
         I = int(lib.n_inputs[c])
@@ -174,11 +198,12 @@ def _bruteforce_bins(prob):
         ts = ev.t[o0:o1]
         pins = ev.pin_bit[o0:o1] >> 1
         vals = ev.pin_bit[o0:o1] & 1
+        sl = ev.slew[o0:o1].astype(np.float64)
         init = int(net.gate_init[g])
 
         def state_at(t, strict):
             s = 0
-            for p in range(I):
+            for p in range(I + allp):
                 m = (ts < t) if strict else (ts <= t)
                 n = int(np.count_nonzero(m & (pins == p)))
                 s |= (((init >> p) & 1) ^ (n & 1)) << p
@@ -190,28 +215,80 @@ def _bruteforce_bins(prob):
             t = int(ts[q])
             s = state_at(t, strict=True)  # state before the event's timestamp
             k = int(lib.state_to_table[lib.map_base[c] + 2 * s + int(vals[q])])
-            T = lib.tables[(lib.table_base[c] + k) * ns * nl:(lib.table_base[c] + k + 1) * ns * nl]
-            rgi = RegularGridInterpolator((sa, la), T.reshape(ns, nl).astype(float), method="linear",
+            Tab = lib.tables[(lib.table_base[c] + k) * ns * nl:(lib.table_base[c] + k + 1) * ns * nl]
+            rgi = RegularGridInterpolator((sa, la), Tab.reshape(ns, nl).astype(float), method="linear",
                                           bounds_error=False, fill_value=None)
-            e = rgi([[float(ev.slew[o0 + q]), C]])[0]
+            ei = rgi([[float(ev.slew[o0 + q]), C]])[0]
+            es = 0.0
             if pins[q] == I:
-                e += (0.5 * C * prob.vdd ** 2) if prob.sw_mode == 0 else (C * prob.vdd ** 2 * vals[q])
-            E[t // prob.bin_ps] += e
+                es = (0.5 * C * prob.vdd ** 2) if prob.sw_mode == 0 else (C * prob.vdd ** 2 * vals[q])
+            r = -1.0
+            if T > 0:
+                prev = [j for j in range(q) if pins[j] == pins[q]]
+                if prev and ts[prev[-1]] // T == t // T:
+                    j = prev[-1]
+                    r = min(1.0, (2.0 * (t - int(ts[j])) / (sl[q] + sl[j])) ** 2)
+            if r > 0:
+                E[t // prob.bin_ps] += r * (ei + es)
+                GE[g, 3] += r * (ei + es)
+            else:
+                E[t // prob.bin_ps] += ei + es
+                GE[g, 1] += ei
+                GE[g, 2] += es
         for t in range(ev.t_end):
             s = state_at(t, strict=False)
-            E[t // prob.bin_ps] += lam * float(lib.leak[lib.leak_base[c] + s]) * 1e-6
-    return E
+            e = lam * float(lib.leak[lib.leak_base[c] + s]) * 1e-6
+            E[t // prob.bin_ps] += e
+            GE[g, 0] += e
+    return E, GE
+
+
+def _bruteforce_bins(prob):
+    return _bruteforce(prob)[0]
+
+
+def all_pin_library(lib, seed=0):
+    """The library re-indexed over every pin (bit I = the output): the output
+    value selects a different table and scales the leakage, so the state the
+    output holds matters."""
+    rng = np.random.default_rng(seed)
+    map_base, s2t, leak_base, leak = [], [], [], []
+    for c in range(lib.n_cells):
+        I = int(lib.n_inputs[c])
+        n_tab = 2 << I   # the cell's tables, one per (input state, direction)
+        map_base.append(len(s2t))
+        leak_base.append(len(leak))
+        for s in range(2 << I):
+            si, out = s & ((1 << I) - 1), s >> I
+            for d in range(2):
+                k = int(lib.state_to_table[lib.map_base[c] + 2 * si + d])
+                s2t.append(k if out == 0 else (k + 1) % n_tab)
+            leak.append(float(lib.leak[lib.leak_base[c] + si]) * (1.0 + out * float(rng.uniform(0.2, 1.0))))
+    return synth.Library(lib.n_cells, lib.n_slew, lib.n_load, lib.n_inputs, lib.slew_axis, lib.load_axis,
+                         np.array(map_base, np.int64), np.array(s2t, np.int16), lib.table_base, lib.tables,
+                         np.array(leak_base, np.int64), np.array(leak, np.float32))
 
 
 def pin_bruteforce_random(O):
-    """Random tiny problems (ties included) against the brute-force definition."""
+    """Random tiny problems (ties included) against the brute-force definition:
+    the waveform and the per-gate report, with and without glitch detection,
+    state over the inputs or over every pin."""
     for seed in (1, 2, 3):
-        prob = synth.make_random_small(seed, n_gates=6, n_cells=3, i_max=3, n_events=60, t_end=700, bin_ps=70,
-                                       p_tie=0.3)
-        Ebf = _bruteforce_bins(prob)
-        for mode in (0, 1):
-            E = O.forward(prob, leak_mode=mode)
-            np.testing.assert_allclose(E, Ebf, rtol=1e-9, atol=1e-12)
+        for allp, T in ((0, 0), (0, 100), (1, 0), (1, 150)):
+            prob = synth.make_random_small(seed, n_gates=6, n_cells=3, i_max=3, n_events=60, t_end=700, bin_ps=70,
+                                           p_tie=0.3)
+            if allp:
+                prob.lib = all_pin_library(prob.lib, seed)
+            prob.state_all_pins, prob.glitch_clk = allp, T
+            Ebf, GEbf = _bruteforce(prob)
+            for mode in (0, 1):
+                E = O.forward(prob, leak_mode=mode)
+                np.testing.assert_allclose(E, Ebf, rtol=1e-9, atol=1e-12)
+            GE, tmax = O.gate_report(prob)
+            np.testing.assert_allclose(GE, GEbf, rtol=1e-9, atol=1e-12)
+            assert tmax == int(prob.ev.t.max())
+            if T:
+                assert GEbf[:, 3].sum() > 0, "the case holds glitches"
 
 
 def pin_state_enumeration(O):
@@ -302,7 +379,7 @@ def pin_euler_identity(O):
     assert abs(lhs - rhs) < 1e-9 * max(1.0, abs(rhs))
 
 
-PINS = [pin_golden_a, pin_golden_b, pin_bin_index, pin_interp, pin_switching, pin_leakage_closed_form,
+PINS = [pin_golden_a, pin_golden_b, pin_golden_c, pin_bin_index, pin_interp, pin_switching, pin_leakage_closed_form,
         pin_bruteforce_random, pin_state_enumeration, pin_energy_invariant, pin_adjoint_fd, pin_euler_identity]
 
 
@@ -403,7 +480,8 @@ def O_free_validate(prob):
 
 PLANTS = {1: "intermediate state in a group", 2: "transposed table", 3: "switching 2x", 4: "leak after-state",
           5: "rounded bin", 6: "tail leakage dropped", 7: "wrong direction table", 9: "switching term dropped in grad",
-          10: "partial bins dropped in grad"}
+          10: "partial bins dropped in grad", 11: "glitch ratio without the factor 2",
+          12: "glitch energy unscaled in the waveform", 13: "output left out of an all-pin state"}
 
 
 @pytest.mark.parametrize("plant", sorted(PLANTS), ids=[PLANTS[k] for k in sorted(PLANTS)])
