@@ -101,18 +101,59 @@ typedef struct {
 gtp_status gtp_fixed_point_bits(const gtp_range* r, int32_t* m);
 
 /*
+ * Expansion of state patterns with don't-care pins into a per-state array
+ * (host only, no device work, no context): Sec. 4.1, SIPL, where a pattern
+ * that fixes only some pins applies to every state that agrees with it on
+ * those pins, filled by enumerating the assignments of its don't-care pins.
+ * Pattern k matches state s when (s & care[k]) == (value[k] & care[k]) (bit p
+ * = pin p); out[s] = item[k] of the first pattern in array order that matches
+ * s, default_item when none does (the paper assumes patterns that do not
+ * overlap; first-match is the reading for those that do).
+ *   n_pins      pins of the state index, 0..16 (the direct-array limit
+ *               the paper uses); out has 2^n_pins entries (HOST, written)
+ *   care, value, item   n_patterns >= 0 entries each (HOST, read)
+ * Errors: GTP_ERR_INVALID_ARG for n_pins outside 0..16, a null array, or a
+ * care bit at or above n_pins (out is then unspecified).
+ */
+gtp_status gtp_expand_when(int32_t n_pins, int32_t n_patterns, const uint32_t* care, const uint32_t* value,
+                           const int32_t* item, int32_t default_item, int32_t* out);
+
+/*
  * Cell library (HOST pointers, copied). For cell c with I = n_inputs[c]
  * input pins (pins 0..I-1; the output is pin I):
  *   state s = sum_p value(p) * 2^p over the input pins (Sec. 4.1, the
- *   state-indexed lookup: bit p = input pin p);
+ *   state-indexed lookup: bit p = input pin p), or, with all_pin_state = 1,
+ *   over every pin of the cell (bit I = the output; 2^(I+1) states, Sec. 4.1
+ *   indexes the array by all of the cell's pins);
  *   state_to_table[map_base[c] + 2*s + dir] = local table id k of the cell
  *   for an event with new value dir (1 = rise) at input state s;
  *   table k: tables_fj[((table_base[c] + k) * n_slew + i) * n_load + j] = energy
  *   at slew_axis_ps[c*n_slew + i], load_axis_ff[c*n_load + j];
  *   leak_nw[leak_base[c] + s] = leakage power at state s.
- * Axes strictly increasing; n_slew, n_load in [2, 16]; I in [1, 8];
- * leakage values finite and >= 0; every table id in range.
- * Local table ids may be shared by several (state, dir) pairs.
+ * Axes strictly increasing; n_slew, n_load in [2, 16]; leakage values
+ * finite and >= 0; every table id in range. Local table ids may be shared by
+ * several (state, dir) pairs. A cell given by these per-state arrays has at
+ * most 8 state pins (I in [1, 8], I + 1 <= 8 with all_pin_state).
+ *
+ * State patterns (Sec. 4.1, optional: n_tpat NULL means none). A cell c with
+ * n_tpat[c] > 0 is given by Liberty-style `when` patterns instead (its
+ * map_base and leak_base entries are then ignored), with I in [1, 31] (the
+ * I + 1 pin values fit 32 bits):
+ *   table pattern k (0 <= k < n_tpat[c]) is entry i = tpat_base[c] + k of
+ *   tpat_care / tpat_value (bit p = pin p of the state index) and selects
+ *   local tables tpat_table[2*i + dir]; it matches state s when
+ *   (s & care) == (value & care) (pins outside care are don't-cares);
+ *   leakage pattern k (0 <= k < n_lpat[c]) is entry i = lpat_base[c] + k of
+ *   lpat_care / lpat_value with value lpat_leak_nw[i].
+ * A state takes the first matching pattern of each list. Each list holds 1 to
+ * 256 patterns and its last pattern has care = 0 (the cell's default, the
+ * Liberty group without a `when`), so every state matches. Care bits lie
+ * below the cell's state-pin count. The library expands the patterns of a
+ * cell with at most 16 state pins into per-state arrays (the expansion of
+ * gtp_expand_when; on chip for at most 8 state pins, in device memory above)
+ * and scans the patterns of wider cells in order at every lookup (the
+ * fallback of Sec. 4.1 for cells with more than 16 pins). Either way the
+ * result equals the first-match scan.
  */
 typedef struct {
   int32_t n_cells, n_slew, n_load;
@@ -126,6 +167,18 @@ typedef struct {
   const int64_t* leak_base;     /* [n_cells] */
   const float* leak_nw;
   int64_t n_map, n_tables, n_leak; /* lengths of state_to_table, tables (in tables), leak_nw */
+  int32_t all_pin_state;           /* 0: state over the input pins; 1: over every pin (output = bit I) */
+  const int32_t* n_tpat;           /* [n_cells] or NULL: table patterns per cell (0: per-state arrays) */
+  const int64_t* tpat_base;        /* [n_cells] */
+  const uint32_t* tpat_care;       /* [n_tpat_total] */
+  const uint32_t* tpat_value;      /* [n_tpat_total] */
+  const int16_t* tpat_table;       /* [2 * n_tpat_total]: local table id (fall, rise) */
+  const int32_t* n_lpat;           /* [n_cells] leakage patterns per cell */
+  const int64_t* lpat_base;        /* [n_cells] */
+  const uint32_t* lpat_care;       /* [n_lpat_total] */
+  const uint32_t* lpat_value;      /* [n_lpat_total] */
+  const float* lpat_leak_nw;       /* [n_lpat_total] */
+  int64_t n_tpat_total, n_lpat_total;
 } gtp_library;
 gtp_status gtp_load_library(gtp_ctx ctx, const gtp_library* lib);
 
@@ -174,10 +227,18 @@ int64_t gtp_bad_event(gtp_ctx ctx);
  * bin_ps. sw_mode 0: switching energy 0.5*C*V^2 on every output toggle;
  * sw_mode 1: C*V^2 on an output rise only (the paper's Eq. switching energy).
  * bin_ps in [1, 2^22].
+ * glitch_clk_ps > 0 turns on the clock-cycle glitch detection (Sec. 2.4,
+ * Sec. 4.3): an event that is not its pin's first in its clock cycle
+ * [k*glitch_clk_ps, (k+1)*glitch_clk_ps) is a glitch event; its internal plus
+ * switching energy is scaled by r = min(1, (2*pw / (rSlew + fSlew))^2) (Eq.
+ * glitch scaling ratio; pw = time since the pin's previous event, the slews
+ * those of that event and this one) and counted as glitch energy. The
+ * waveform then carries the scaled energy. 0 = off.
  */
 typedef struct {
   double vdd;
   int64_t bin_ps;
+  int64_t glitch_clk_ps;
   int32_t sw_mode;
 } gtp_params;
 gtp_status gtp_set_params(gtp_ctx ctx, const gtp_params* p);
@@ -321,6 +382,26 @@ gtp_status gtp_forward_batched(gtp_ctx ctx, const float* net_load_ff, const floa
  * power_mw (DEVICE, [its bins]): the per-trace reference of the batched call. */
 gtp_status gtp_forward_trace(gtp_ctx ctx, int32_t trace, const float* net_load_ff, const float* leak_scale,
                              float* power_mw);
+
+/*
+ * Per-gate power report (Sec. 4.4 reduces per-gate leakage, internal,
+ * switching and glitch power; Sec. 5 reports them per gate and for the
+ * design, with the waveform's peak): for the loaded events and parameters,
+ *   gate_energy_fj (DEVICE, [n_gates * 4], FP64): gate g's energy over the
+ *     window [0, t_end) as (leakage, internal, switching, glitch) at
+ *     [4*g .. 4*g+3]; a glitch event's scaled energy counts as glitch only;
+ *   totals (HOST, [12]): [0..3] the design sums of the four components (fJ),
+ *     [4] t_max = the latest event time (ps; -1 without events), [5] the
+ *     largest value of power_mw (mW; NaN if power_mw is NULL), [6..9] the
+ *     paper's average powers p = E / t_max of the four components (Eq.
+ *     average power; mW, NaN when t_max <= 0), [10] the average total power
+ *     over the window (sum of the components / t_end, mW), [11] t_end (ps).
+ * power_mw (DEVICE, [n_bins], may be NULL): a waveform from gtp_forward, for
+ * the peak. Energies are the FP32 per-event values the forward uses, summed
+ * in FP64 per gate. Synchronises.
+ */
+gtp_status gtp_gate_report(gtp_ctx ctx, const float* net_load_ff, const float* leak_scale, const float* power_mw,
+                           double* gate_energy_fj, double* totals);
 
 /*
  * Per-event trace of the state tracking (DEVICE outputs, [n_events]):

@@ -42,7 +42,15 @@ class _Problem(ctypes.Structure):
         ("pin_bit", ctypes.c_void_p), ("slew", ctypes.c_void_p),
         ("t_end", ctypes.c_int64), ("bin_ps", ctypes.c_int64), ("vdd", ctypes.c_double),
         ("sw_mode", ctypes.c_int32), ("state_all_pins", ctypes.c_int32), ("glitch_clk", ctypes.c_int64),
+        ("n_tpat", ctypes.c_void_p), ("tpat_base", ctypes.c_void_p), ("tpat_care", ctypes.c_void_p),
+        ("tpat_value", ctypes.c_void_p), ("tpat_table", ctypes.c_void_p), ("n_lpat", ctypes.c_void_p),
+        ("lpat_base", ctypes.c_void_p), ("lpat_care", ctypes.c_void_p), ("lpat_value", ctypes.c_void_p),
+        ("lpat_leak", ctypes.c_void_p),
     ]
+
+_PATTERNS = (("n_tpat", np.int32), ("tpat_base", np.int64), ("tpat_care", np.uint32), ("tpat_value", np.uint32),
+             ("tpat_table", np.int16), ("n_lpat", np.int32), ("lpat_base", np.int64), ("lpat_care", np.uint32),
+             ("lpat_value", np.uint32), ("lpat_leak", np.float32))
 
 
 def build(force: bool = True, plant: int = 0, out: Optional[str] = None) -> str:
@@ -83,6 +91,8 @@ class Oracle:
         L.orc_num_bins.restype = ctypes.c_int64
         L.orc_num_bins.argtypes = [ctypes.POINTER(_Problem)]
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_pattern_scan.restype = ctypes.c_int64
+        L.orc_pattern_scan.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
 
     # -- marshalling -------------------------------------------------------
     @staticmethod
@@ -108,6 +118,9 @@ class Oracle:
             pin_bit=np.ascontiguousarray(ev.pin_bit, np.uint8),
             slew=np.ascontiguousarray(ev.slew, np.float32),
         )
+        if getattr(lib, "n_tpat", None) is not None:
+            for name, dt in _PATTERNS:
+                keep[name] = np.ascontiguousarray(getattr(lib, name), dt)
         P = _Problem()
         P.n_cells, P.n_slew, P.n_load = lib.n_cells, lib.n_slew, lib.n_load
         for k, a in keep.items():
@@ -187,6 +200,12 @@ class Oracle:
     def bilerp(self, prob, cell: int, table: int, slew: float, load: float) -> float:
         P, keep = self._arrays(prob)
         return self.lib.orc_bilerp(ctypes.byref(P), cell, table, slew, load)
+
+    def pattern_scan(self, care, value, s: int) -> int:
+        """First pattern whose care pins agree with state s, -1 if none."""
+        care = np.ascontiguousarray(care, np.uint32)
+        value = np.ascontiguousarray(value, np.uint32)
+        return int(self.lib.orc_pattern_scan(len(care), care.ctypes.data, value.ctypes.data, int(s)))
 
     def max_threads(self) -> int:
         return self.lib.orc_max_threads()

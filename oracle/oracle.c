@@ -141,6 +141,51 @@ static double sw_energy_dC(const orc_problem* P, int v) {
 #endif
 }
 
+/* mask of the n low bits, n in 0..32 */
+static uint32_t low_bits(int n) { return n >= 32 ? 0xffffffffu : (1u << n) - 1u; }
+
+int64_t orc_pattern_scan(int64_t n, const uint32_t* care, const uint32_t* value, uint32_t s) {
+  for (int64_t k = 0; k < n; ++k) {
+#if ORC_PLANT == 14
+    if ((s & care[k]) == value[k]) return k; /* planted: value bits outside care compared too */
+#else
+    if ((s & care[k]) == (value[k] & care[k])) return k;
+#endif
+  }
+  return -1;
+}
+
+static int patterned(const orc_problem* P, int32_t c) { return P->n_tpat && P->n_tpat[c] > 0; }
+
+/* local table id of cell c for state s and new value dir: the per-state
+ * array, or the first matching table pattern */
+static int32_t table_id(const orc_problem* P, int32_t c, uint32_t s, int dir) {
+  if (!patterned(P, c)) return P->state_to_table[P->map_base[c] + 2 * (int64_t)s + dir];
+  const int64_t b = P->tpat_base[c];
+  const int64_t k = orc_pattern_scan(P->n_tpat[c], P->tpat_care + b, P->tpat_value + b, s);
+  return P->tpat_table[2 * (b + k) + dir];
+}
+
+/* leakage value (nW) of cell c at state s */
+static double leak_value(const orc_problem* P, int32_t c, uint32_t s) {
+  if (!patterned(P, c)) return (double)P->leak[P->leak_base[c] + s];
+  const int64_t b = P->lpat_base[c];
+  const int64_t k = orc_pattern_scan(P->n_lpat[c], P->lpat_care + b, P->lpat_value + b, s);
+  return (double)P->lpat_leak[b + k];
+}
+
+/* every pattern list non-empty and ending in a care = 0 pattern */
+static int check_patterns(const orc_problem* P) {
+  if (!P->n_tpat) return ORC_OK;
+  for (int32_t c = 0; c < P->n_cells; ++c) {
+    if (!patterned(P, c)) continue;
+    if (!P->n_lpat || P->n_lpat[c] < 1) return ORC_ERR_INVALID_ARG;
+    if (P->tpat_care[P->tpat_base[c] + P->n_tpat[c] - 1] != 0u) return ORC_ERR_INVALID_ARG;
+    if (P->lpat_care[P->lpat_base[c] + P->n_lpat[c] - 1] != 0u) return ORC_ERR_INVALID_ARG;
+  }
+  return ORC_OK;
+}
+
 static int64_t bin_of(const orc_problem* P, int64_t t) {
 #if ORC_PLANT == 5
   return (t + P->bin_ps / 2) / P->bin_ps; /* planted: rounds instead of floor */
@@ -236,9 +281,9 @@ static int eval_gate(const orc_problem* P, int64_t g, acc_t* A, double* tot, int
   const int32_t I = P->n_inputs[c];
   /* the state index: input pins, or all pins (bit I = output) */
 #if ORC_PLANT == 13
-  const uint32_t smask = (1u << I) - 1u; /* planted: the output pin left out of an all-pin state */
+  const uint32_t smask = low_bits(I); /* planted: the output pin left out of an all-pin state */
 #else
-  const uint32_t smask = P->state_all_pins ? (1u << (I + 1)) - 1u : (1u << I) - 1u;
+  const uint32_t smask = low_bits(P->state_all_pins ? I + 1 : I);
 #endif
   pin_glitch pg[32];
   for (int p = 0; p < 32; ++p) {
@@ -249,8 +294,7 @@ static int eval_gate(const orc_problem* P, int64_t g, acc_t* A, double* tot, int
   }
   const double C = P->net_load[P->gate_out_net[g]];
   const double lam = P->leak_scale ? P->leak_scale[g] : 1.0;
-  const float* lk = P->leak + P->leak_base[c];
-  uint32_t vals = P->gate_init[g] & ((1u << (I + 1)) - 1u);
+  uint32_t vals = P->gate_init[g] & low_bits(I + 1);
   int64_t t_prev = 0;
   const int64_t e_end = P->gate_off[g + 1];
   int64_t e = P->gate_off[g];
@@ -270,13 +314,13 @@ static int eval_gate(const orc_problem* P, int64_t g, acc_t* A, double* tot, int
         int p = P->pin_bit[q] >> 1, v = P->pin_bit[q] & 1;
         v2 = (v2 & ~(1u << p)) | ((uint32_t)v << p);
       }
-      double r = lam * lk[v2 & smask];
+      double r = lam * leak_value(P, c, v2 & smask);
       add_leak(P, A, t_prev, t, r);
       tot[2] += r * 1e-6 * (double)(t - t_prev);
     }
 #else
     {
-      double r = lam * lk[s];
+      double r = lam * leak_value(P, c, s);
       add_leak(P, A, t_prev, t, r);
       tot[2] += r * 1e-6 * (double)(t - t_prev);
     }
@@ -303,7 +347,7 @@ static int eval_gate(const orc_problem* P, int64_t g, acc_t* A, double* tot, int
 #else
       const int dir = v;
 #endif
-      const int32_t k = P->state_to_table[P->map_base[c] + 2 * (int64_t)sl + dir];
+      const int32_t k = table_id(P, c, sl, dir);
       const double ei = orc_bilerp(P, c, k, (double)P->slew[q], C);
       const double es = (p == I) ? sw_energy(P, C, v) : 0.0;
       const int64_t b = bin_of(P, t);
@@ -333,7 +377,7 @@ static int eval_gate(const orc_problem* P, int64_t g, acc_t* A, double* tot, int
   }
 #if ORC_PLANT != 6
   {
-    double r = lam * lk[vals & smask];
+    double r = lam * leak_value(P, c, vals & smask);
     add_leak(P, A, t_prev, P->t_end, r);
     tot[2] += r * 1e-6 * (double)(P->t_end - t_prev);
   }
@@ -344,6 +388,7 @@ static int eval_gate(const orc_problem* P, int64_t g, acc_t* A, double* tot, int
 int orc_forward(const orc_problem* P, int64_t b0, int64_t b1, int leak_mode, const int64_t* gates,
                 int64_t n_gate_list, double* E, double* totals, int nthreads, int64_t* bad_event) {
   if (!P || !E || b0 < 0 || b1 < b0 || b1 > orc_num_bins(P) || P->bin_ps <= 0) return ORC_ERR_INVALID_ARG;
+  if (check_patterns(P) != ORC_OK) return ORC_ERR_INVALID_ARG;
   const int64_t nb = b1 - b0;
   const int64_t ng = gates ? n_gate_list : P->n_gates;
   int nt = nthreads > 0 ? nthreads : orc_max_threads();
@@ -388,7 +433,7 @@ int orc_forward(const orc_problem* P, int64_t b0, int64_t b1, int leak_mode, con
 }
 
 int orc_event_trace(const orc_problem* P, int32_t* state_before, int64_t* bin, int64_t* bad_event) {
-  if (!P || !state_before || !bin) return ORC_ERR_INVALID_ARG;
+  if (!P || !state_before || !bin || check_patterns(P) != ORC_OK) return ORC_ERR_INVALID_ARG;
   acc_t A;
   double dummy = 0;
   A.b0 = 0; A.b1 = 0; A.mode = 0; A.E = &dummy; A.diff = NULL;
@@ -402,7 +447,7 @@ int orc_event_trace(const orc_problem* P, int32_t* state_before, int64_t* bin, i
 }
 
 int orc_gate_report(const orc_problem* P, double* gate_e, int64_t* t_max, int nthreads) {
-  if (!P || !gate_e || !t_max) return ORC_ERR_INVALID_ARG;
+  if (!P || !gate_e || !t_max || check_patterns(P) != ORC_OK) return ORC_ERR_INVALID_ARG;
   int nt = nthreads > 0 ? nthreads : orc_max_threads();
   int status = ORC_OK;
   int64_t tm = -1;
@@ -428,6 +473,7 @@ int orc_gate_report(const orc_problem* P, double* gate_e, int64_t* t_max, int nt
 }
 
 int orc_validate(const orc_problem* P, int64_t* bad_event) {
+  if (!P || check_patterns(P) != ORC_OK) return ORC_ERR_INVALID_ARG;
   acc_t A;
   double dummy = 0;
   A.b0 = 0; A.b1 = 0; A.mode = 0; A.E = &dummy; A.diff = NULL;
@@ -476,7 +522,7 @@ static double interval_gsum(const orc_problem* P, const double* PG, const double
 
 int orc_adjoint(const orc_problem* P, const double* gP, int leak_mode, double* grad_load, double* grad_scale,
                 int nthreads) {
-  if (!P || !gP || !grad_load || !grad_scale) return ORC_ERR_INVALID_ARG;
+  if (!P || !gP || !grad_load || !grad_scale || check_patterns(P) != ORC_OK) return ORC_ERR_INVALID_ARG;
   const int64_t nb = orc_num_bins(P);
   const double D = (double)P->bin_ps;
   double* PG = (double*)malloc(sizeof(double) * (size_t)(nb + 1));
@@ -493,10 +539,9 @@ int orc_adjoint(const orc_problem* P, const double* gP, int leak_mode, double* g
   for (int64_t g = 0; g < P->n_gates; ++g) {
     const int32_t c = P->gate_cell[g];
     const int32_t I = P->n_inputs[c];
-    const uint32_t smask = P->state_all_pins ? (1u << (I + 1)) - 1u : (1u << I) - 1u;
+    const uint32_t smask = low_bits(P->state_all_pins ? I + 1 : I);
     const double C = P->net_load[P->gate_out_net[g]];
-    const float* lk = P->leak + P->leak_base[c];
-    uint32_t vals = P->gate_init[g] & ((1u << (I + 1)) - 1u);
+    uint32_t vals = P->gate_init[g] & low_bits(I + 1);
     int64_t t_prev = 0;
     double dC = 0, dl = 0;
     pin_glitch pg[32];
@@ -513,11 +558,11 @@ int orc_adjoint(const orc_problem* P, const double* gP, int leak_mode, double* g
       int64_t e2 = e + 1;
       while (e2 < e_end && P->t[e2] == t) ++e2;
       const uint32_t s = vals & smask;
-      dl += lk[s] * 1e-6 * interval_gsum(P, PG, gP, nb, leak_mode, t_prev, t);
+      dl += leak_value(P, c, s) * 1e-6 * interval_gsum(P, PG, gP, nb, leak_mode, t_prev, t);
       const int64_t b = t / P->bin_ps;
       for (int64_t q = e; q < e2; ++q) {
         const int p = P->pin_bit[q] >> 1, v = P->pin_bit[q] & 1;
-        const int32_t k = P->state_to_table[P->map_base[c] + 2 * (int64_t)s + v];
+        const int32_t k = table_id(P, c, s, v);
         double d = bilerp_dload(P, c, k, (double)P->slew[q], C);
         if (p == I) d += sw_energy_dC(P, v);
         if (P->glitch_clk > 0) {
@@ -533,7 +578,7 @@ int orc_adjoint(const orc_problem* P, const double* gP, int leak_mode, double* g
       t_prev = t;
       e = e2;
     }
-    dl += lk[vals & smask] * 1e-6 * interval_gsum(P, PG, gP, nb, leak_mode, t_prev, P->t_end);
+    dl += leak_value(P, c, vals & smask) * 1e-6 * interval_gsum(P, PG, gP, nb, leak_mode, t_prev, P->t_end);
     gC[g] = dC;
     grad_scale[g] = dl;
   }

@@ -57,7 +57,30 @@ typedef struct {
   int32_t sw_mode;               /* 0: 0.5*C*V^2 per output toggle; 1: C*V^2 per output rise */
   int32_t state_all_pins;        /* 0: state index over the input pins (2^I); 1: over all pins, bit I = output (2^(I+1)) */
   int64_t glitch_clk;            /* clock period (ps) of the glitch detection; 0: no glitch analysis */
+  /* state patterns (Sec. 4.1). A cell with n_tpat[c] > 0 takes its tables and
+   * leakage values from patterns instead of the per-state arrays above. Table
+   * pattern k of cell c is entry tpat_base[c] + k of tpat_care / tpat_value
+   * (bit p = pin p; it matches a state that agrees with value on every pin
+   * whose care bit is set) with tables tpat_table[2*(tpat_base[c]+k) + dir];
+   * leakage pattern k is entry lpat_base[c] + k of lpat_care / lpat_value /
+   * lpat_leak. A state takes its first matching pattern, scanned in order;
+   * the last pattern of each list must have care = 0 (the default item, so
+   * every state matches one). NULL n_tpat: no patterned cell. */
+  const int32_t* n_tpat;
+  const int64_t* tpat_base;
+  const uint32_t* tpat_care;
+  const uint32_t* tpat_value;
+  const int16_t* tpat_table;
+  const int32_t* n_lpat;
+  const int64_t* lpat_base;
+  const uint32_t* lpat_care;
+  const uint32_t* lpat_value;
+  const float* lpat_leak;
 } orc_problem;
+
+/* First pattern k in 0..n-1 whose care pins agree with state s (Sec. 4.1,
+ * the pattern traversal that SIPL replaces), -1 when none does. */
+int64_t orc_pattern_scan(int64_t n, const uint32_t* care, const uint32_t* value, uint32_t s);
 
 /* Number of bins: ceil(t_end / bin_ps). */
 int64_t orc_num_bins(const orc_problem* P);

@@ -39,7 +39,7 @@ ABI_SYMBOLS = ["gtp_create", "gtp_destroy", "gtp_set_stream", "gtp_last_error", 
                "gtp_set_tuning", "gtp_get_tuning", "gtp_plan_info", "gtp_autotune", "gtp_load_traces",
                "gtp_batch_bins", "gtp_forward_batched", "gtp_forward_trace", "gtp_forward", "gtp_adjoint", "gtp_debug_event_trace",
                "gtp_device_bytes", "gtp_profile_enable", "gtp_profile_read", "gtp_fixed_point_bits",
-               "gtp_forward_noalloc"]
+               "gtp_forward_noalloc", "gtp_gate_report", "gtp_expand_when"]
 
 
 def build(out: Optional[str] = None) -> str:
@@ -64,7 +64,18 @@ class _Library(ctypes.Structure):
                 ("n_inputs", ctypes.c_void_p), ("slew_axis_ps", ctypes.c_void_p), ("load_axis_ff", ctypes.c_void_p),
                 ("map_base", ctypes.c_void_p), ("state_to_table", ctypes.c_void_p), ("table_base", ctypes.c_void_p),
                 ("tables_fj", ctypes.c_void_p), ("leak_base", ctypes.c_void_p), ("leak_nw", ctypes.c_void_p),
-                ("n_map", ctypes.c_int64), ("n_tables", ctypes.c_int64), ("n_leak", ctypes.c_int64)]
+                ("n_map", ctypes.c_int64), ("n_tables", ctypes.c_int64), ("n_leak", ctypes.c_int64),
+                ("all_pin_state", ctypes.c_int32),
+                ("n_tpat", ctypes.c_void_p), ("tpat_base", ctypes.c_void_p), ("tpat_care", ctypes.c_void_p),
+                ("tpat_value", ctypes.c_void_p), ("tpat_table", ctypes.c_void_p), ("n_lpat", ctypes.c_void_p),
+                ("lpat_base", ctypes.c_void_p), ("lpat_care", ctypes.c_void_p), ("lpat_value", ctypes.c_void_p),
+                ("lpat_leak_nw", ctypes.c_void_p), ("n_tpat_total", ctypes.c_int64), ("n_lpat_total", ctypes.c_int64)]
+
+# state-pattern fields of a library object (all optional; n_tpat None: none)
+_PATTERN_FIELDS = (("n_tpat", np.int32), ("tpat_base", np.int64), ("tpat_care", np.uint32),
+                   ("tpat_value", np.uint32), ("tpat_table", np.int16), ("n_lpat", np.int32),
+                   ("lpat_base", np.int64), ("lpat_care", np.uint32), ("lpat_value", np.uint32),
+                   ("lpat_leak", np.float32))
 
 
 class _Events(ctypes.Structure):
@@ -73,7 +84,8 @@ class _Events(ctypes.Structure):
 
 
 class _Params(ctypes.Structure):
-    _fields_ = [("vdd", ctypes.c_double), ("bin_ps", ctypes.c_int64), ("sw_mode", ctypes.c_int32)]
+    _fields_ = [("vdd", ctypes.c_double), ("bin_ps", ctypes.c_int64), ("glitch_clk_ps", ctypes.c_int64),
+                ("sw_mode", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):
@@ -105,6 +117,26 @@ def fixed_point_bits(max_bin_events: int, bin_ps: int, event_energy_fj: float, l
     return m.value
 
 
+def expand_when(n_pins: int, care, value, item, default_item: int) -> np.ndarray:
+    """Per-state item array of state patterns with don't-care pins
+    (gtp_expand_when): entry s holds the item of the first pattern whose
+    care bits agree with s, default_item where none does."""
+    L = load_library()
+    care = np.ascontiguousarray(care, np.uint32)
+    value = np.ascontiguousarray(value, np.uint32)
+    item = np.ascontiguousarray(item, np.int32)
+    if not (care.shape == value.shape == item.shape) or care.ndim != 1:
+        raise ValueError("care, value and item must be 1-D arrays of one length")
+    if not 0 <= int(n_pins) <= 16:
+        raise ValueError("n_pins must lie in 0..16")
+    out = np.empty(1 << int(n_pins), np.int32)
+    rc = L.gtp_expand_when(int(n_pins), len(care), care.ctypes.data, value.ctypes.data, item.ctypes.data,
+                           int(default_item), out.ctypes.data)
+    if rc != 0:
+        raise GtpError(rc, "state-pattern expansion")
+    return out
+
+
 _lib = None
 
 
@@ -132,8 +164,10 @@ def load_library(path: Optional[str] = None):
         "gtp_forward_trace": [vp, i32, vp, vp, vp],
         "gtp_forward": [vp, vp, vp, vp], "gtp_adjoint": [vp, vp, vp, vp, vp, vp],
         "gtp_forward_noalloc": [vp, vp, vp, vp],
+        "gtp_gate_report": [vp, vp, vp, vp, vp, vp],
         "gtp_debug_event_trace": [vp, vp, vp],
         "gtp_fixed_point_bits": [ctypes.POINTER(_Range), ctypes.POINTER(ctypes.c_int32)],
+        "gtp_expand_when": [i32, i32, vp, vp, vp, i32, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -205,10 +239,14 @@ class Context:
         self._chk(self.L.gtp_sync(self.h))
 
     # -- loading ------------------------------------------------------------
-    def load_library(self, lib):
+    def load_library(self, lib, all_pin_state: int = 0):
         """lib: object with n_cells, n_slew, n_load and host arrays n_inputs,
         slew_axis, load_axis, map_base, state_to_table, table_base, tables,
-        leak_base, leak (the layout of include/gtpower.h gtp_library)."""
+        leak_base, leak (the layout of include/gtpower.h gtp_library), and
+        optionally the state patterns n_tpat, tpat_base, tpat_care,
+        tpat_value, tpat_table, n_lpat, lpat_base, lpat_care, lpat_value,
+        lpat_leak (n_tpat None or absent: none); all_pin_state = 1: its
+        states cover every pin (bit I = the output)."""
         arrs = dict(n_inputs=_np(lib.n_inputs, np.int32), slew=_np(lib.slew_axis, np.float32),
                     load=_np(lib.load_axis, np.float32), map_base=_np(lib.map_base, np.int64),
                     s2t=_np(lib.state_to_table, np.int16), table_base=_np(lib.table_base, np.int64),
@@ -222,6 +260,16 @@ class Context:
         S.n_map = arrs["s2t"].size
         S.n_tables = arrs["tables"].size // (S.n_slew * S.n_load)
         S.n_leak = arrs["leak"].size
+        S.all_pin_state = int(all_pin_state)
+        if getattr(lib, "n_tpat", None) is not None:
+            for name, dt in _PATTERN_FIELDS:
+                arrs[name] = _np(getattr(lib, name), dt)
+            for name in ("n_tpat", "tpat_base", "tpat_care", "tpat_value", "tpat_table", "n_lpat", "lpat_base",
+                         "lpat_care", "lpat_value"):
+                setattr(S, name, arrs[name].ctypes.data)
+            S.lpat_leak_nw = arrs["lpat_leak"].ctypes.data
+            S.n_tpat_total = arrs["tpat_care"].size
+            S.n_lpat_total = arrs["lpat_care"].size
         self._chk(self.L.gtp_load_library(self.h, ctypes.byref(S)))
 
     def load_netlist(self, gate_cell, gate_out_net, gate_init, n_nets: int):
@@ -254,15 +302,15 @@ class Context:
         if self.L.gtp_num_bins(self.h, ctypes.byref(n)) == 0:
             self.n_bins = n.value
 
-    def set_params(self, vdd: float = 0.8, bin_ps: int = 50, sw_mode: int = 0):
-        p = _Params(float(vdd), int(bin_ps), int(sw_mode))
+    def set_params(self, vdd: float = 0.8, bin_ps: int = 50, sw_mode: int = 0, glitch_clk_ps: int = 0):
+        p = _Params(float(vdd), int(bin_ps), int(glitch_clk_ps), int(sw_mode))
         self._chk(self.L.gtp_set_params(self.h, ctypes.byref(p)))
         self.n_bins = 0
         if "events" in self._keep:
             n = ctypes.c_int64()
             self._chk(self.L.gtp_num_bins(self.h, ctypes.byref(n)))
             self.n_bins = n.value
-        self.vdd, self.bin_ps, self.sw_mode = float(vdd), int(bin_ps), int(sw_mode)
+        self.vdd, self.bin_ps, self.sw_mode, self.glitch_clk_ps = float(vdd), int(bin_ps), int(sw_mode), int(glitch_clk_ps)
 
     def set_tuning(self, algo: int = 0, bins_per_tile_log2: int = 0, tile_threads: int = 0, unit_events: int = 0,
                    gate_block_log2: int = 0):
@@ -394,6 +442,25 @@ class Context:
                                      _dptr(gs)))
         return gl, gs
 
+    def report(self, net_load, leak_scale=None, power=None):
+        """gtp_gate_report: per-gate energies [n_gates, 4] (FP64 fJ: leakage,
+        internal, switching, glitch) and the design summary (totals, latest
+        event time, peak of `power`, the paper's averages E / t_max and the
+        window average)."""
+        net_load = self._vec(net_load, self.n_nets, "net_load")
+        leak_scale = self._vec(leak_scale, self.n_gates, "leak_scale")
+        if power is not None:
+            power = self._vec(power, self.n_bins, "power")
+        t = self.torch
+        ge = t.empty((self.n_gates, 4), dtype=t.float64, device=self.device)
+        tot = (ctypes.c_double * 12)()
+        self._chk(self.L.gtp_gate_report(self.h, _dptr(net_load), _dptr(leak_scale), _dptr(power), _dptr(ge),
+                                         ctypes.cast(tot, ctypes.c_void_p)))
+        v = list(tot)
+        keys = ("leak", "int", "sw", "gl")
+        return ge, {"energy_fj": dict(zip(keys, v[0:4])), "t_max_ps": v[4], "peak_mw": v[5],
+                    "avg_mw_tmax": dict(zip(keys, v[6:10])), "avg_mw_window": v[10], "t_end_ps": v[11]}
+
     def event_trace(self):
         t = self.torch
         st = t.empty(self.n_events, dtype=t.int32, device=self.device)
@@ -444,4 +511,4 @@ def peak_power_loss(P, beta: float):
 
 
 __all__ = ["Context", "GtpError", "binned_power", "peak_power_loss", "build", "load_library", "SO_PATH",
-           "ABI_SYMBOLS", "fixed_point_bits"]
+           "ABI_SYMBOLS", "fixed_point_bits", "expand_when"]

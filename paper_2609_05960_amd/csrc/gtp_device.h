@@ -50,28 +50,72 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 // width and library; everything in it is independent of the per-call loads
 // and leakage scales):
 //   word  bits [0, 23) in-tile time (bin_in_tile << r_bits | r), [23, 31)
-//         the gate's input state after the event (the leakage state held
-//         from the event on);
+//         the leakage entry of the gate's state after the event, relative to
+//         the cell's first (the state itself for a kCellDirect cell, its
+//         leakage item for a wider one): the leakage held from the event on;
 //   row   bits [0, 30) the quad index of the event's table row at its slew
 //         segment, i.e. map(state before the timestamp group, new value) +
 //         segment * (n_load - 1), to which the gate's load segment is added;
 //         bit 30 set for an output event, bit 31 the new value;
 //   alpha the slew weight (slew - S[i]) / (S[i+1] - S[i]) in FP32, rounded
 //         as the gate-major kernels round it.
+// With glitch detection on, a fourth word per event holds its energy factor
+// (the glitch scaling ratio of a glitch event, 1 otherwise).
 constexpr int kTimeBits = 23;
 constexpr uint32_t kTimeMask = (1u << kTimeBits) - 1u;
 constexpr int kStateShift = 23;
 constexpr uint32_t kRowMask = (1u << 30) - 1u;
 constexpr int kOutBit = 30;
-constexpr int kMaxPin = 14;
 
-// Per-cell record staged in LDS.
+// Per-cell record staged in LDS. How a state selects the cell's table and
+// leakage value (Sec. 4.1):
+//   kCellDirect  a per-state array in the LDS image (at most 8 state pins):
+//                entry (s, dir) at map_off + 2*s + dir, leakage at leak_off + s;
+//   kCellSipl    per-state item arrays in device memory (9..16 state pins):
+//                item k = sipl[t_sipl + s] (tables), sipl[l_sipl + s]
+//                (leakage), entry (k, dir) at map_off + 2*k + dir, leakage
+//                at leak_off + k;
+//   kCellScan    the state patterns themselves (more than 16 state pins): k
+//                = the first pattern whose care pins agree with s, scanned
+//                in device memory, then as kCellSipl.
+constexpr int kCellDirect = 0, kCellSipl = 1, kCellScan = 2;
 struct CellMeta {
-  int32_t n_in;      // input pins I (output pin = I)
-  int32_t map_off;   // first map entry: entry (s, dir) at map_off + 2*s + dir
-  int32_t leak_off;  // first leakage value: state s at leak_off + s
+  int16_t n_in;      // input pins I (output pin = I)
+  int16_t mode;      // kCellDirect, kCellSipl or kCellScan
+  int32_t map_off;   // first map entry
+  int32_t leak_off;  // first leakage value
   int32_t axis_off;  // first slew knot: c * n_slew
 };
+static_assert(sizeof(CellMeta) == 16, "CellMeta is four LDS words");
+
+// Device-memory record of a cell with more than 8 state pins.
+struct WideCell {
+  int32_t t_first, t_n;   // its table patterns: pat[t_first .. t_first + t_n)
+  int32_t l_first, l_n;   // its leakage patterns
+  int64_t t_sipl, l_sipl; // kCellSipl: first entry of its per-state item arrays
+};
+
+struct WideView {
+  const WideCell* cell;   // [n_cells] (entries of kCellDirect cells unused)
+  const uint2* pat;       // (care, value) of every pattern
+  const uint8_t* sipl;    // per-state item arrays
+};
+
+// Item of state s in one of a wide cell's lists: the per-state array, or the
+// first pattern whose care pins agree with s (the last pattern of a list has
+// care = 0, so the scan always ends on a match).
+__device__ __forceinline__ int32_t wide_item(const WideView& W, int cell, int mode, uint32_t s, bool leak) {
+  const WideCell& w = W.cell[cell];
+  if (mode == kCellSipl) return (int32_t)W.sipl[(leak ? w.l_sipl : w.t_sipl) + (int64_t)s];
+  const int32_t first = leak ? w.l_first : w.t_first, n = leak ? w.l_n : w.t_n;
+  int32_t k = 0;
+#pragma nounroll
+  for (; k < n - 1; ++k) {
+    const uint2 p = W.pat[first + k];
+    if (((s ^ p.y) & p.x) == 0u) break;
+  }
+  return k;
+}
 
 // Library as the kernels see it (device pointers into one ctx-owned buffer).
 struct LibView {
@@ -86,7 +130,15 @@ struct LibView {
   int32_t n_cells, n_slew, n_load, n_map, n_leak;
   int32_t lds_words;        // 32-bit words of the LDS image
   int32_t lds_words_ml;     // words of its meta, leakage and load-axis prefix
+  int32_t all_pins;         // 1: the state index covers every pin (bit n_in = the output), else the inputs
+  WideView wide;            // cells with more than 8 state pins
 };
+
+// Mask of the pins the state index covers: the inputs, or every pin.
+__device__ __host__ __forceinline__ uint32_t state_mask(int32_t n_in, int32_t all_pins) {
+  const int32_t n = n_in + all_pins;
+  return n >= 32 ? 0xffffffffu : (1u << n) - 1u;
+}
 
 // Prepared gate record (32 bytes), gate-major kernels.
 struct GatePrep {
@@ -145,6 +197,8 @@ __device__ __forceinline__ int64_t bin_of(int64_t t, const BinSpec& B) {
 // LDS image of the library: meta | leak | load | load_inv | map_q | slew |
 // slew_inv (words).
 struct LdsLib {
+  int32_t all_pins;        // as LibView::all_pins
+  WideView wide;           // as LibView::wide (device memory)
   const CellMeta* meta;
   const int32_t* map_q;
   const float* leak;
@@ -160,6 +214,8 @@ __device__ __forceinline__ LdsLib stage_library(const LibView& L, uint32_t* lds)
   for (int w = threadIdx.x; w < L.lds_words; w += blockDim.x) lds[w] = src[w];
   const int32_t nl = L.n_cells * L.n_load;
   LdsLib S;
+  S.all_pins = L.all_pins;
+  S.wide = L.wide;
   S.meta = reinterpret_cast<const CellMeta*>(lds);
   S.leak = reinterpret_cast<const float*>(lds + 4 * L.n_cells);
   S.load = S.leak + L.n_leak;
@@ -177,6 +233,8 @@ __device__ __forceinline__ LdsLib stage_library_ml(const LibView& L, uint32_t* l
   for (int w = threadIdx.x; w < L.lds_words_ml; w += blockDim.x) lds[w] = src[w];
   const int32_t nl = L.n_cells * L.n_load;
   LdsLib S;
+  S.all_pins = L.all_pins;
+  S.wide = L.wide;
   S.meta = reinterpret_cast<const CellMeta*>(lds);
   S.leak = reinterpret_cast<const float*>(lds + 4 * L.n_cells);
   S.load = S.leak + L.n_leak;
@@ -185,6 +243,28 @@ __device__ __forceinline__ LdsLib stage_library_ml(const LibView& L, uint32_t* l
   S.slew = nullptr;
   S.slew_inv = nullptr;
   return S;
+}
+
+// Map entry of (state s, new value v) and leakage entry of state s for a
+// cell (Lib: LibView or LdsLib; s masked to the cell's state pins).
+__device__ __forceinline__ int32_t map_entry_w(const WideView& W, const CellMeta& cm, int cell, uint32_t s,
+                                               uint32_t v) {
+  const int32_t k = cm.mode == kCellDirect ? (int32_t)s : wide_item(W, cell, cm.mode, s, false);
+  return cm.map_off + 2 * k + (int32_t)v;
+}
+__device__ __forceinline__ int32_t leak_item_w(const WideView& W, const CellMeta& cm, int cell, uint32_t s) {
+  return cm.mode == kCellDirect ? (int32_t)s : wide_item(W, cell, cm.mode, s, true);
+}
+__device__ __forceinline__ int32_t leak_entry_w(const WideView& W, const CellMeta& cm, int cell, uint32_t s) {
+  return cm.leak_off + leak_item_w(W, cm, cell, s);
+}
+template <class Lib>
+__device__ __forceinline__ int32_t map_entry(const Lib& L, const CellMeta& cm, int cell, uint32_t s, uint32_t v) {
+  return map_entry_w(L.wide, cm, cell, s, v);
+}
+template <class Lib>
+__device__ __forceinline__ int32_t leak_entry(const Lib& L, const CellMeta& cm, int cell, uint32_t s) {
+  return leak_entry_w(L.wide, cm, cell, s);
 }
 
 // What a unit's gate needs for its events, from its output load C and cell:
@@ -247,6 +327,28 @@ __device__ __forceinline__ void slew_segment(const float* axis, const float* inv
   for (int m = 1; m < n - 1; ++m) k += (axis[m] <= slew) ? 1 : 0;
   i = k;
   alpha = __fmul_rn(__fsub_rn(slew, axis[k]), inv[k]);
+}
+
+// Glitch scaling ratio of event e (Sec. 2.4 clock-cycle detection, Eq.
+// glitch scaling ratio): the event is a glitch when its pin's previous event
+// in the gate's time order lies in the same clock cycle of length clk;
+// then r = min(1, (2 pw / (s_prev + s))^2) with pw the time since that event
+// and s_prev, s the two slews (FP32), else -1 (a regular event). Searches the
+// gate's earlier events (gate-major array, first event gstart) back to the
+// start of the cycle.
+__device__ __forceinline__ float glitch_ratio(const int64_t* __restrict__ t, const uint8_t* __restrict__ pb,
+                                              const float* __restrict__ slew, int64_t gstart, int64_t e, int64_t te,
+                                              int pin, float se, int64_t clk) {
+  const int64_t c0 = (te / clk) * clk;   // start of the event's clock cycle
+  for (int64_t j = e - 1; j >= gstart; --j) {
+    const int64_t tj = t[j];
+    if (tj < c0) break;
+    if ((int)(pb[j] >> 1) == pin) {
+      const float q = __fdiv_rn(__fmul_rn(2.0f, (float)(te - tj)), __fadd_rn(slew[j], se));
+      return fminf(1.0f, __fmul_rn(q, q));
+    }
+  }
+  return -1.0f;
 }
 
 // Bilinear interpolation on a quad (c00, c01, c10, c11) = (T[i][j], T[i][j+1],

@@ -24,7 +24,8 @@ namespace gtp {
 struct GateCtx {
   GatePrep gp;
   CellMeta cm;
-  uint32_t in_mask;
+  uint32_t in_mask;     // the pins of the state index (inputs, or every pin)
+  int32_t n_state;      // pins below n_state change the state (n_in or n_in + 1)
   int32_t q_cur;
 };
 
@@ -36,9 +37,10 @@ __device__ __forceinline__ void gate_begin(GateCtx& G, const GatePrep* __restric
   G.gp.esw_rise = __int_as_float(b.x); G.gp.esw_fall = __int_as_float(b.y);
   G.gp.lam = __int_as_float(b.z); G.gp.dbeta_dc = __int_as_float(b.w);
   G.cm = L.meta[G.gp.cell];
-  G.in_mask = (1u << G.cm.n_in) - 1u;
+  G.in_mask = state_mask(G.cm.n_in, L.all_pins);
+  G.n_state = G.cm.n_in + L.all_pins;
   const uint32_t s = (G.gp.init ^ par) & G.in_mask;
-  G.q_cur = qrate(G.gp.lam, L.leak[G.cm.leak_off + (int)s], rate_scale);
+  G.q_cur = qrate(G.gp.lam, L.leak[leak_entry(L, G.cm, G.gp.cell, s)], rate_scale);
 }
 
 struct LutArgs {
@@ -52,7 +54,7 @@ __device__ __forceinline__ EventOut event_energy(GateCtx& G, const LdsLib& L, co
                                                  float slew, uint32_t par_gs, uint32_t par) {
   EventOut o;
   const uint32_t s = (G.gp.init ^ par_gs) & G.in_mask;
-  const int32_t qb = L.map_q[G.cm.map_off + 2 * (int)s + v];
+  const int32_t qb = L.map_q[map_entry(L, G.cm, G.gp.cell, s, (uint32_t)v)];
   int i;
   float alpha;
   slew_segment(L.slew + G.cm.axis_off, L.slew_inv + G.cm.axis_off, A.n_slew, slew, i, alpha);
@@ -60,9 +62,9 @@ __device__ __forceinline__ EventOut event_energy(GateCtx& G, const LdsLib& L, co
   float e = bilerp_quad(q, alpha, G.gp.beta);
   if (pin == G.cm.n_in) e = __fadd_rn(e, v ? G.gp.esw_rise : G.gp.esw_fall);
   int32_t delta = 0;
-  if (pin < G.cm.n_in) {
+  if (pin < G.n_state) {
     const uint32_t s_new = (G.gp.init ^ par ^ (1u << pin)) & G.in_mask;
-    const int32_t qn = qrate(G.gp.lam, L.leak[G.cm.leak_off + (int)s_new], A.rate_scale);
+    const int32_t qn = qrate(G.gp.lam, L.leak[leak_entry(L, G.cm, G.gp.cell, s_new)], A.rate_scale);
     delta = qn - G.q_cur;
     G.q_cur = qn;
   }
@@ -100,6 +102,7 @@ struct PackedFwdArgs {
   int32_t slot_quads;        // quads of one LDS table slot
   long long* tile_tot;       // non-null: S gets the within-tile exclusive prefix of
                              // the steps and tile_tot[tile] their total
+  const float* rgl;          // per packed event its energy factor (glitch detection on), else null
 };
 
 // LDS of the packed kernels: the library's meta + leakage prefix, then the
@@ -123,13 +126,15 @@ struct GroupRegs {
   uint32_t wv[kS];
   uint32_t rv[kS];
   float av[kS];
+  float gv[kS];   // energy factors (glitch detection on only)
 };
 
 // Issue every load of one group (descriptor and offset already loaded).
 // With mine false the lane's length still counts for the positions of the
 // other lanes, but its own loads are skipped.
-// kS is the longest unit the layout holds (its unit_events), 8 or 16.
-template <int kS>
+// kS is the longest unit the layout holds (its unit_events), 8 or 16; kGl:
+// the events' energy factors are loaded too (glitch detection on).
+template <int kS, bool kGl>
 __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int64_t off, GroupRegs<kS>& G,
                                             bool mine = true) {
   G.d = d;
@@ -162,6 +167,7 @@ __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int
         G.wv[kk] = wp[r];
         G.rv[kk] = rp[r];
         G.av[kk] = ap[r];
+        if (kGl) G.gv[kk] = a.rgl[offu + r];
       }
       o += (uint32_t)__popcll(m);
     }
@@ -202,7 +208,7 @@ __device__ __forceinline__ float4 quad_slot(const lds_float4* slot, uint32_t lo,
 // k is accumulated from the other. With kSlotOnly every quad comes from the
 // slot and the function issues no global load, so the next group's loads
 // stay in flight while this group is accumulated.
-template <int kS, bool kSlotOnly>
+template <int kS, bool kSlotOnly, bool kGl>
 __device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsLib& L, const GroupRegs<kS>& G,
                                               unsigned long long* xs, unsigned long long* ss, const lds_float4* slot,
                                               uint32_t lo, uint32_t n) {
@@ -217,7 +223,9 @@ __device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsL
   const uint32_t jq = u.jq;
   const CellMeta cm = L.meta[cell];
   const float* lk = L.leak + cm.leak_off;
-  int32_t q_cur = qrate(gp.lam, lk[G.d.y & ((1u << cm.n_in) - 1u)], a.lut.rate_scale);
+  // desc.y low half: the pin values (a kCellDirect cell, masked to its state)
+  // or the leakage item (wider cells, below 256) before the unit
+  int32_t q_cur = qrate(gp.lam, lk[G.d.y & 0xffffu & state_mask(cm.n_in, L.all_pins)], a.lut.rate_scale);
   struct Pre {
     float4 q;        // table quad
     float lk_after;  // leakage value of the input state after the event
@@ -238,6 +246,7 @@ __device__ __forceinline__ void process_group(const PackedFwdArgs& a, const LdsL
       const Pre& P = pre[kk & 1];
       float e = bilerp_quad(P.q, G.av[kk], u.beta);
       if (rv & (1u << kOutBit)) e = __fadd_rn(e, (rv >> 31) ? u.esw_rise : u.esw_fall);
+      if (kGl) e = __fmul_rn(e, G.gv[kk]);
       int64_t x = energy_fixed(e, a.lut.two_sh);
       const uint32_t tl = w & kTimeMask;
       const uint32_t bl = tl >> B.r_bits;
@@ -314,7 +323,7 @@ __device__ __forceinline__ void phase_advance(const PackedFwdArgs& a, PhaseState
 // slot, and one barrier at the boundary separates the phases. Every
 // wavefront crosses every boundary once, in order, whether or not it has
 // groups in a phase.
-template <int kThreads, int kS, bool kSlotOnly>
+template <int kThreads, int kS, bool kSlotOnly, bool kGl>
 __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsLib& L, unsigned long long* xs,
                                               unsigned long long* ss, int32_t tile, float4* slots) {
   const BinSpec& B = a.bins;
@@ -363,7 +372,7 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
   if (gi < g1) {
     load_desc(gi);
     wait_vmem();
-    group_issue(a, dn, offn, ga);
+    group_issue<kS, kGl>(a, dn, offn, ga);
     load_desc(gi + nwave);
   }
   __syncthreads();
@@ -376,16 +385,16 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
   while (gi < g1) {
     while (gi >= P.ge) phase_advance<kThreads>(a, P, slots, g0);
     wait_vmem();
-    if (gi + nwave < g1) group_issue(a, dn, offn, gb);
+    if (gi + nwave < g1) group_issue<kS, kGl>(a, dn, offn, gb);
     load_desc(gi + 2 * nwave);
-    process_group<kS, kSlotOnly>(a, L, ga, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * a.slot_quads), P.lo, P.n);
+    process_group<kS, kSlotOnly, kGl>(a, L, ga, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * a.slot_quads), P.lo, P.n);
     gi += nwave;
     if (gi >= g1) break;
     while (gi >= P.ge) phase_advance<kThreads>(a, P, slots, g0);
     wait_vmem();
-    if (gi + nwave < g1) group_issue(a, dn, offn, ga);
+    if (gi + nwave < g1) group_issue<kS, kGl>(a, dn, offn, ga);
     load_desc(gi + 2 * nwave);
-    process_group<kS, kSlotOnly>(a, L, gb, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * a.slot_quads), P.lo, P.n);
+    process_group<kS, kSlotOnly, kGl>(a, L, gb, xs, ss, lds_ptr(lds_slots + (P.ph & 1) * a.slot_quads), P.lo, P.n);
     gi += nwave;
   }
   while (P.ph + 1 < P.ph1) phase_advance<kThreads>(a, P, slots, g0);  // boundaries after this wavefront's last group
@@ -434,15 +443,16 @@ __device__ __forceinline__ void fwd_tile_body(const PackedFwdArgs& a, const LdsL
 }
 
 // One workgroup per time tile of a single trace. kSlotOnly: every table phase
-// holds all the quads of its groups (the host launches it only then).
-template <int kThreads, int kS, bool kSlotOnly>
+// holds all the quads of its groups (the host launches it only then); kGl:
+// glitch detection on (each event's energy times its factor).
+template <int kThreads, int kS, bool kSlotOnly, bool kGl>
 __global__ void __launch_bounds__(kThreads) k_fwd_packed(PackedFwdArgs a) {
   extern __shared__ uint32_t lds[];
   const LdsLib L = stage_library_ml(a.lib, lds);
   unsigned long long* xs = reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.lib.lds_words_ml));
   unsigned long long* ss = xs + (1 << a.bins.tile_log2);
   float4* slots = a.phases ? reinterpret_cast<float4*>(ss + (1 << a.bins.tile_log2)) : nullptr;
-  fwd_tile_body<kThreads, kS, kSlotOnly>(a, L, xs, ss, (int32_t)blockIdx.x, slots);
+  fwd_tile_body<kThreads, kS, kSlotOnly, kGl>(a, L, xs, ss, (int32_t)blockIdx.x, slots);
 }
 
 // ---------------------------------------------------------------------------
@@ -452,6 +462,7 @@ struct TraceDev {
   const uint32_t* w32;
   const uint32_t* row;
   const float* alpha;
+  const float* rgl;
   const int4* phases;
   const int32_t* ph_off;
   int32_t slot_quads;
@@ -475,7 +486,7 @@ struct BatchFwdArgs {
 // Workgroups stay resident and take work items from the queue until it is
 // empty; every workgroup ends once it draws an index past the last item.
 // kSlotOnly: every trace has table phases that hold all their groups' quads.
-template <int kThreads, int kS, bool kSlotOnly>
+template <int kThreads, int kS, bool kSlotOnly, bool kGl>
 __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ long long item_sh;
@@ -496,6 +507,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
     p.w32 = T.w32;
     p.row = T.row;
     p.alpha = T.alpha;
+    p.rgl = T.rgl;
     p.desc = T.desc;
     p.grp_off = T.grp_off;
     p.tile_grp = T.tile_grp;
@@ -509,7 +521,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
         reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.base.lib.lds_words_ml));
     unsigned long long* ss = xs + (1 << T.bins.tile_log2);
     float4* slots = T.phases ? reinterpret_cast<float4*>(ss + (1 << T.bins.tile_log2)) : nullptr;
-    fwd_tile_body<kThreads, kS, kSlotOnly>(p, L, xs, ss, w.y, slots);
+    fwd_tile_body<kThreads, kS, kSlotOnly, kGl>(p, L, xs, ss, w.y, slots);
   }
 }
 
@@ -525,10 +537,12 @@ struct GateParamArgs {
   const float* leak_scale;   // may be null (all 1)
   const CellMeta* meta;
   const float* leak;
+  WideView wide;             // cells with more than 8 state pins
   int64_t n_gates;
   float rate_scale;
   float max_scale;
   float load_cap;            // loads must lie in [0, load_cap]
+  int32_t all_pins;          // state index over every pin
   GateParam* out;
   long long* l0_part;        // [blocks]
   int32_t* flag;             // bit 0: a leakage scale out of range; bit 1: a load out of range
@@ -555,8 +569,8 @@ __global__ void __launch_bounds__(256) k_gate_params(GateParamArgs a) {
     p.C = C;
     p.lam = lam;
     a.out[gs] = p;
-    const uint32_t s0 = a.ginit[gs] & ((1u << cm.n_in) - 1u);
-    q0 = (long long)qrate(lam, a.leak[cm.leak_off + (int)s0], a.rate_scale);
+    const uint32_t s0 = a.ginit[gs] & state_mask(cm.n_in, a.all_pins);
+    q0 = (long long)qrate(lam, a.leak[leak_entry_w(a.wide, cm, c, s0)], a.rate_scale);
   }
   red[threadIdx.x] = q0;
   __syncthreads();
@@ -664,6 +678,7 @@ struct SerialArgs {
   LibView lib;
   LutArgs lut;
   BinSpec bins;
+  int64_t glitch_clk;   // > 0: glitch detection with this clock period
   unsigned long long* X;
   unsigned long long* S;
 };
@@ -689,9 +704,13 @@ __global__ void __launch_bounds__(kFwdThreads) k_gate_serial(SerialArgs a) {
       par_gs = par;
       tprev = t;
     }
-    const EventOut o = event_energy(G, L, a.lut, pin, v, a.ev.slew[e], par_gs, par);
+    EventOut o = event_energy(G, L, a.lut, pin, v, a.ev.slew[e], par_gs, par);
     par ^= 1u << (pin & 31);
     if (t < 0 || t >= B.t_end) continue;
+    if (a.glitch_clk > 0) {
+      const float r = glitch_ratio(a.ev.t, a.ev.pb, a.ev.slew, e0, e, t, pin, a.ev.slew[e], a.glitch_clk);
+      o.e = __fmul_rn(o.e, r > 0.f ? r : 1.0f);
+    }
     const int64_t b = bin_of(t, B);
     const int64_t rr = t - b * B.D;
     const int64_t x = energy_fixed(o.e, a.lut.two_sh) + (int64_t)o.delta * (B.D - rr);
@@ -711,6 +730,7 @@ struct PrepArgs {
   const float* leak_scale;   // may be null (all 1)
   const CellMeta* meta;
   const float* leak;
+  WideView wide;             // cells with more than 8 state pins
   const float* load;         // [n_cells * n_load]
   const float* load_inv;
   int32_t n_load;
@@ -721,6 +741,7 @@ struct PrepArgs {
   float two_sh;       // 2^(m-32)
   float max_scale;
   float load_cap;     // loads must lie in [0, load_cap]
+  int32_t all_pins;   // state index over every pin
   GatePrep* out;
   unsigned long long* L0;    // sum of quantised initial leakage rates
   int32_t* flag;             // bit 0: a leakage scale out of range
@@ -763,8 +784,8 @@ __global__ void __launch_bounds__(256) k_gate_prep(PrepArgs a) {
     p.lam = lam;
     p.dbeta_dc = inv;
     a.out[g] = p;
-    const uint32_t s0 = p.init & ((1u << cm.n_in) - 1u);
-    q0 = (long long)qrate(lam, a.leak[cm.leak_off + (int)s0], a.rate_scale);
+    const uint32_t s0 = p.init & state_mask(cm.n_in, a.all_pins);
+    q0 = (long long)qrate(lam, a.leak[leak_entry_w(a.wide, cm, c, s0)], a.rate_scale);
   }
   red[threadIdx.x] = q0;
   __syncthreads();
@@ -860,6 +881,7 @@ struct AdjArgs {
   BinSpec bins;
   const double2* wg;   // [n_bins] (w_b, G_b)
   float dsw_rise, dsw_fall;  // d(switching energy)/dC
+  int64_t glitch_clk;  // > 0: glitch detection with this clock period
   double* gC;          // [n_nets]
   double* gL;          // [n_gates] (sum of d * integral, without the 1e-6)
 };
@@ -869,10 +891,12 @@ struct AdjVisitor {
   const LdsLib* L;
   GateCtx G;
   uint32_t s_cur;
+  int64_t g_cur;
   double acc_c, acc_l;
   __device__ __forceinline__ void begin_gate(int64_t g, uint32_t par) {
     gate_begin(G, A->gprep, *L, g, par, A->lut.rate_scale);
     s_cur = (G.gp.init ^ par) & G.in_mask;
+    g_cur = g;
     acc_c = 0.0;
     acc_l = 0.0;
   }
@@ -882,27 +906,32 @@ struct AdjVisitor {
     acc_c = 0.0;
     acc_l = 0.0;
   }
-  __device__ __forceinline__ void event(int64_t, int64_t t, int pin, int v, float slew, uint32_t par_gs,
+  __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
                                         uint32_t par) {
     const BinSpec& B = A->bins;
     const uint32_t s_new = (G.gp.init ^ par ^ (1u << (pin & 31))) & G.in_mask;
     if (t < 0 || t >= B.t_end) {  // invalid input: dropped, state still tracked
-      if (pin < G.cm.n_in) s_cur = s_new;
+      if (pin < G.n_state) s_cur = s_new;
       return;
     }
     const int64_t b = bin_of(t, B);
     const double2 wg = A->wg[b];
     const uint32_t s = (G.gp.init ^ par_gs) & G.in_mask;
-    const int32_t qb = L->map_q[G.cm.map_off + 2 * (int)s + v];
+    const int32_t qb = L->map_q[map_entry(*L, G.cm, G.gp.cell, s, (uint32_t)v)];
     int i;
     float alpha;
     slew_segment(L->slew + G.cm.axis_off, L->slew_inv + G.cm.axis_off, A->lut.n_slew, slew, i, alpha);
     const float4 q = A->lut.quads[qb + i * (A->lut.n_load - 1) + G.gp.jq];
     float dedc = __fmul_rn(bilerp_dbeta(q, alpha), G.gp.dbeta_dc);
     if (pin == G.cm.n_in) dedc = __fadd_rn(dedc, v ? A->dsw_rise : A->dsw_fall);
+    if (A->glitch_clk > 0) {
+      const float r = glitch_ratio(A->ev.t, A->ev.pb, A->ev.slew, A->ev.gate_off[g_cur], e, t, pin, slew, A->glitch_clk);
+      if (r > 0.f) dedc = __fmul_rn(dedc, r);
+    }
     acc_c += wg.x * (double)dedc;
-    if (pin < G.cm.n_in) {
-      const double d = (double)L->leak[G.cm.leak_off + (int)s_new] - (double)L->leak[G.cm.leak_off + (int)s_cur];
+    if (pin < G.n_state) {
+      const double d = (double)L->leak[leak_entry(*L, G.cm, G.gp.cell, s_new)] -
+                       (double)L->leak[leak_entry(*L, G.cm, G.gp.cell, s_cur)];
       const int64_t end_b = min((b + 1) * B.D, B.t_end);
       acc_l += d * (wg.x * (double)(end_b - t) + wg.y);
       s_cur = s_new;
@@ -954,18 +983,21 @@ struct AdjOutArgs {
   const uint32_t* gate_init;
   const CellMeta* meta;
   const float* leak;
+  WideView wide;             // cells with more than 8 state pins
   float* grad_load;
   float* grad_scale;
   int64_t n_nets, n_gates;
+  int32_t all_pins;
 };
 
 __global__ void __launch_bounds__(256) k_adj_out(AdjOutArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < a.n_nets) a.grad_load[i] = (float)a.gC[i];
   if (i < a.n_gates) {
-    const CellMeta cm = a.meta[a.gate_cell[i]];
-    const uint32_t s0 = a.gate_init[i] & ((1u << cm.n_in) - 1u);
-    const double base = (double)a.leak[cm.leak_off + (int)s0] * *a.total;
+    const int32_t c = a.gate_cell[i];
+    const CellMeta cm = a.meta[c];
+    const uint32_t s0 = a.gate_init[i] & state_mask(cm.n_in, a.all_pins);
+    const double base = (double)a.leak[leak_entry_w(a.wide, cm, c, s0)] * *a.total;
     a.grad_scale[i] = (float)(1e-6 * (base + a.gL[i]));
   }
 }
@@ -1019,7 +1051,7 @@ __device__ __forceinline__ void lds_add_f64(double* p, double v) {
 // FP32 terms stay as small as the tile's share of the integral). The unit's
 // sums go into FP64 LDS accumulators of its gate.
 // Lookups are double-buffered by event parity as in the forward.
-template <int kS>
+template <int kS, bool kGl>
 __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const LdsLib& L, const GroupRegs<kS>& G,
                                                   bool mine, int32_t tile, int32_t gs0, double* acc_c, double* acc_l,
                                                   const float4* tab, uint32_t q_lo, uint32_t q_n) {
@@ -1036,7 +1068,7 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
   const float dbdc = len > 0 ? u.dbdc : 0.f;
   const float* lk = L.leak + cm.leak_off;
   const int64_t tile_b0 = (int64_t)tile << B.tile_log2;
-  float lk_cur = lk[G.d.y & ((1u << cm.n_in) - 1u)];
+  float lk_cur = lk[G.d.y & 0xffffu & state_mask(cm.n_in, L.all_pins)];
   const float lk_first = lk_cur;
   struct Pre {
     float4 q;        // table quad
@@ -1061,6 +1093,7 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
       const Pre& P = pre[kk & 1];
       float dedc = __fmul_rn(bilerp_dbeta(P.q, G.av[kk]), dbdc);
       if (rv & (1u << kOutBit)) dedc = __fadd_rn(dedc, (rv >> 31) ? a.dsw_rise : a.dsw_fall);
+      if (kGl) dedc = __fmul_rn(dedc, G.gv[kk]);
       ac = __fmaf_rn(P.wg.x, dedc, ac);
       // an output event leaves the input state unchanged: step 0, no branch
       const uint32_t tl = w & kTimeMask;
@@ -1079,7 +1112,7 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
   }
 }
 
-template <int kThreads, int kS>
+template <int kThreads, int kS, bool kGl>
 __global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
   extern __shared__ uint32_t lds[];
   const AdjItem it = a.items[blockIdx.x];
@@ -1109,7 +1142,7 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
   auto issue = [&](int64_t en, GroupRegs<kS>& R, bool& m, int32_t& t) {
     m = lane >= (en1.z & 0xff) && lane < (en1.z >> 8);
     t = en1.y;
-    group_issue(a.f, dn, offn, R, m);
+    group_issue<kS, kGl>(a.f, dn, offn, R, m);
     en1 = en2;
     if (en + nwave < e1) {
       dn = a.f.desc[(int64_t)en1.x * kGroupUnits + lane];
@@ -1127,11 +1160,11 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
   __syncthreads();
   while (e < e1) {
     if (e + nwave < e1) issue(e + nwave, gb, mb, tb);
-    adj_process_group(a, L, ga, ma, ta, gs0, acc_c, acc_l, tab, (uint32_t)it.q_lo, (uint32_t)it.q_n);
+    adj_process_group<kS, kGl>(a, L, ga, ma, ta, gs0, acc_c, acc_l, tab, (uint32_t)it.q_lo, (uint32_t)it.q_n);
     e += nwave;
     if (e >= e1) break;
     if (e + nwave < e1) issue(e + nwave, ga, ma, ta);
-    adj_process_group(a, L, gb, mb, tb, gs0, acc_c, acc_l, tab, (uint32_t)it.q_lo, (uint32_t)it.q_n);
+    adj_process_group<kS, kGl>(a, L, gb, mb, tb, gs0, acc_c, acc_l, tab, (uint32_t)it.q_lo, (uint32_t)it.q_n);
     e += nwave;
   }
   __syncthreads();
@@ -1177,10 +1210,12 @@ struct AdjOutSortedArgs {
   const uint32_t* gate_init;
   const CellMeta* meta;
   const float* leak;
+  WideView wide;             // cells with more than 8 state pins
   float* grad_load;
   float* grad_scale;
   int64_t n_gates;
   int32_t unique_out;         // 1: no net has two drivers (plain stores)
+  int32_t all_pins;
 };
 
 __global__ void __launch_bounds__(256) k_adj_out_sorted(AdjOutSortedArgs a) {
@@ -1200,14 +1235,202 @@ __global__ void __launch_bounds__(256) k_adj_out_sorted(AdjOutSortedArgs a) {
     gl += v.y;
   }
   const int32_t g = a.gperm[gs];
-  const CellMeta cm = a.meta[a.gcell[gs]];
-  const uint32_t s0 = a.gate_init[g] & ((1u << cm.n_in) - 1u);
-  a.grad_scale[g] = (float)(1e-6 * ((double)a.leak[cm.leak_off + (int)s0] * *a.total + gl));
+  const int32_t c = a.gcell[gs];
+  const CellMeta cm = a.meta[c];
+  const uint32_t s0 = a.gate_init[g] & state_mask(cm.n_in, a.all_pins);
+  a.grad_scale[g] = (float)(1e-6 * ((double)a.leak[leak_entry_w(a.wide, cm, c, s0)] * *a.total + gl));
   if (a.unique_out) {
     a.grad_load[a.gate_out[g]] = (float)gc;
   } else if (gc != 0.0) {
     atomicAdd(&a.grad_load[a.gate_out[g]], (float)gc);
   }
+}
+
+// ---------------------------------------------------------------------------
+// per-gate report: leakage, internal, switching and glitch energy per gate
+// ---------------------------------------------------------------------------
+// Gate-major walk (one lane per 16-event block, as the other gate-major
+// kernels). Per gate the lane sums, in FP64, the FP32 energies the forward
+// uses: internal and switching energy of regular events, the scaled energy of
+// glitch events, and the leakage steps d * (t_end - t) (nW ps; the finalize
+// kernel adds the initial state's leakage over the window and scales by the
+// gate's lambda and 1e-6). A gate entirely inside one lane's block is stored
+// with plain stores; the part of a gate that continues into or out of the
+// block is added atomically, after the lanes of a wavefront that hold the same
+// gate (consecutive lanes) have combined their parts. This is the paper's
+// per-gate two-phase reduction (Sec. 4.4) with the first phase in registers.
+struct ReportArgs {
+  EvView ev;
+  const uint2* plan;
+  const GatePrep* gprep;
+  LibView lib;
+  LutArgs lut;
+  BinSpec bins;
+  int64_t glitch_clk;          // > 0: glitch detection with this clock period
+  double* ge;                  // [n_gates * 4]: leak (steps, nW ps), int, sw, gl (fJ); zeroed before
+  unsigned long long* t_max;   // latest event time in the window (atomic max; zeroed before)
+};
+
+struct RepVisitor {
+  const ReportArgs* A;
+  const LdsLib* L;
+  GateCtx G;
+  int64_t e_lo, e_hi;          // the block's events [e_lo, e_hi)
+  int64_t g;
+  bool spans_in;
+  uint32_t s_cur;
+  double acc[4];
+  int64_t ga = -1, gb = -1;    // gate continuing into / only out of the block
+  double va[4], vb[4];
+  int64_t tmax = -1;
+  __device__ __forceinline__ void begin_gate(int64_t gg, uint32_t par) {
+    gate_begin(G, A->gprep, *L, gg, par, A->lut.rate_scale);
+    s_cur = (G.gp.init ^ par) & G.in_mask;
+    g = gg;
+    spans_in = A->ev.gate_off[gg] < e_lo;
+    acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
+  }
+  __device__ __forceinline__ void end_gate(int64_t gg) {
+    const bool spans_out = A->ev.gate_off[gg + 1] > e_hi;
+    if (!spans_in && !spans_out) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) A->ge[4 * gg + k] = acc[k];
+    } else if (spans_in) {
+      ga = gg;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) va[k] = acc[k];
+    } else {
+      gb = gg;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) vb[k] = acc[k];
+    }
+    spans_in = false;
+  }
+  __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
+                                        uint32_t par) {
+    const BinSpec& B = A->bins;
+    const uint32_t s_new = (G.gp.init ^ par ^ (1u << (pin & 31))) & G.in_mask;
+    if (t < 0 || t >= B.t_end) {  // invalid input: dropped, state still tracked
+      if (pin < G.n_state) s_cur = s_new;
+      return;
+    }
+    tmax = max(tmax, t);
+    const uint32_t s = (G.gp.init ^ par_gs) & G.in_mask;
+    const int32_t qb = L->map_q[map_entry(*L, G.cm, G.gp.cell, s, (uint32_t)v)];
+    int i;
+    float alpha;
+    slew_segment(L->slew + G.cm.axis_off, L->slew_inv + G.cm.axis_off, A->lut.n_slew, slew, i, alpha);
+    const float4 q = A->lut.quads[qb + i * (A->lut.n_load - 1) + G.gp.jq];
+    const float ei = bilerp_quad(q, alpha, G.gp.beta);
+    const float es = (pin == G.cm.n_in) ? (v ? G.gp.esw_rise : G.gp.esw_fall) : 0.0f;
+    const float r = A->glitch_clk > 0
+                        ? glitch_ratio(A->ev.t, A->ev.pb, A->ev.slew, A->ev.gate_off[g], e, t, pin, slew, A->glitch_clk)
+                        : -1.0f;
+    if (r > 0.f) {
+      acc[3] += (double)__fmul_rn(pin == G.cm.n_in ? __fadd_rn(ei, es) : ei, r);
+    } else {
+      acc[1] += (double)ei;
+      acc[2] += (double)es;
+    }
+    if (pin < G.n_state) {
+      acc[0] += ((double)L->leak[leak_entry(*L, G.cm, G.gp.cell, s_new)] -
+                 (double)L->leak[leak_entry(*L, G.cm, G.gp.cell, s_cur)]) *
+                (double)(B.t_end - t);
+      s_cur = s_new;
+    }
+  }
+};
+
+// Sum over consecutive lanes holding the same key (keys do not decrease over
+// the lanes that hold one; -1: no value), then the last lane of each run adds
+// the sums to the gate's entries.
+__device__ __forceinline__ void report_flush(double* ge, int64_t key, double* v) {
+  const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t ku = __shfl_up(key, o, 64);
+    double up[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) up[k] = __shfl_up(v[k], o, 64);
+    if (lane >= o && ku == key) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] += up[k];
+    }
+  }
+  const int64_t kd = __shfl_down(key, 1, 64);
+  const bool last = (lane == 63) || kd != key;
+  if (key >= 0 && last) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (v[k] != 0.0) unsafeAtomicAdd(&ge[4 * key + k], v[k]);
+  }
+}
+
+__global__ void __launch_bounds__(kFwdThreads) k_gate_report(ReportArgs a) {
+  extern __shared__ uint32_t lds[];
+  const LdsLib L = stage_library(a.lib, lds);
+  __syncthreads();
+  RepVisitor vis;
+  vis.A = &a;
+  vis.L = &L;
+  const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  vis.e_lo = kb * kLaneEvents;
+  vis.e_hi = min(vis.e_lo + kLaneEvents, a.ev.n);
+  vis.spans_in = false;
+  walk_block(kb, a.ev, a.plan, vis);
+  // every lane of the wavefront takes part in the combines (lanes past the
+  // last block hold no value)
+  report_flush(a.ge, vis.ga, vis.va);
+  report_flush(a.ge, vis.gb, vis.vb);
+  int64_t tm = vis.tmax;
+  for (int o = 32; o > 0; o >>= 1) tm = max(tm, (int64_t)__shfl_xor(tm, o, 64));
+  if ((threadIdx.x & 63) == 0 && tm >= 0) atomicMax(a.t_max, (unsigned long long)tm);
+}
+
+// Per gate: leakage energy = lambda * 1e-6 * (leak[s0] * t_end + the summed
+// steps), then the design totals (per block, FP64 atomics into tot[4]).
+__global__ void __launch_bounds__(256) k_report_finalize(const GatePrep* gprep, const CellMeta* meta,
+                                                         const float* leak, WideView wide, int32_t all_pins,
+                                                         int64_t n_gates, int64_t t_end, double* ge, double* tot) {
+  __shared__ double red[4][256];
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (g < n_gates) {
+    const GatePrep p = gprep[g];
+    const CellMeta cm = meta[p.cell];
+    const uint32_t s0 = p.init & state_mask(cm.n_in, all_pins);
+    const double el =
+        (double)p.lam * 1e-6 * ((double)leak[leak_entry_w(wide, cm, p.cell, s0)] * (double)t_end + ge[4 * g]);
+    ge[4 * g] = el;
+    v[0] = el;
+    v[1] = ge[4 * g + 1];
+    v[2] = ge[4 * g + 2];
+    v[3] = ge[4 * g + 3];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) unsafeAtomicAdd(&tot[threadIdx.x], red[threadIdx.x][0]);
+}
+
+// Largest bin power (one float per bin; order-preserving integer image of
+// the FP32 value for the atomic max).
+__device__ __forceinline__ uint32_t float_key(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__global__ void __launch_bounds__(256) k_peak(const float* P, int64_t n, uint32_t* out) {
+  uint32_t m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    m = max(m, float_key(P[i]));
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -1245,7 +1468,7 @@ struct ValVisitor {
     else {
       // same pin earlier in this timestamp group (a valid group has at most n_in + 1 events)
       int64_t j = e - 1;
-      for (int k = 0; k < 17 && j >= gstart && A->ev.t[j] == t; ++k, --j)
+      for (int k = 0; k < 33 && j >= gstart && A->ev.t[j] == t; ++k, --j)
         if ((A->ev.pb[j] >> 1) == pin) { code = 4; break; }
       if (code == 0 && (int)(((init ^ par) >> pin) & 1u) == v) code = 5;
     }

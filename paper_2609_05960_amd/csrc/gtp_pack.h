@@ -30,6 +30,8 @@
 //             after the event
 //   row[n]    table row of the event at its slew segment, output flag, value
 //   alpha[n]  slew weight (FP32)
+//   rgl[n]    energy factor (glitch detection on only): the glitch scaling
+//             ratio of a glitch event, 1 for a regular event
 //   desc[64 * n_groups]   unit descriptor: x = cell-sorted gate index
 //             (bits 0..27) | (length-1) << 28, y = pin values before the
 //             unit's first event (bits 0..15) | the gate's cell << 16;
@@ -79,12 +81,15 @@ struct PackIn {
   std::vector<int64_t> gate_weight;
   int32_t slot_quads = 0;         // quads one LDS table slot holds (0: no phases)
   Workspace* ws = nullptr;        // [2] temporaries (caller-owned)
+  int64_t glitch_clk = 0;         // > 0: per-event glitch factors for this clock period
+  bool wide_cells = false;        // some cell has more than 8 state pins (its units carry every pin value)
 };
 
 struct PackOut {
   uint32_t* w32 = nullptr;
   uint32_t* row = nullptr;
   float* alpha = nullptr;
+  float* rgl = nullptr;       // energy factor per event (glitch detection on), else null
   uint2* desc = nullptr;
   int64_t* grp_off = nullptr;
   int32_t* tile_grp = nullptr;

@@ -21,7 +21,7 @@
 //   7. k_pk_fill: one workgroup per tile, one wavefront per group: the unit
 //      descriptors and every event's record in the unit-interleaved order,
 //      and the most events in one bin (LDS histogram of the tile);
-//   8. k_pk_group_cells + k_pk_phases + k_pk_phase_copy (the table phases of
+//   8. k_pk_group_quads + k_pk_phases + k_pk_phase_copy (the table phases of
 //      every tile).
 // Temporaries live in a workspace the caller keeps between packs; the pack
 // runs once per event set and bin width, its time is reported apart from the
@@ -66,6 +66,7 @@ struct UnitArgs {
   uint64_t* keys;
   uint32_t* vals;
   UnitRec* recs;
+  uint2* upins;           // emit pass, optional: every pin value before each unit's first event and its group
 };
 
 template <bool kEmit>
@@ -82,6 +83,7 @@ struct UnitVisitor {
   int32_t u_len = 0;
   int64_t u_tile = 0;
   uint32_t u_st = 0;
+  uint2 u_pins{0u, 0u};
 
   __device__ __forceinline__ void close() {
     if (!open) return;
@@ -99,6 +101,7 @@ struct UnitVisitor {
       r.x = (uint32_t)gs | ((uint32_t)(u_len - 1) << 28);
       r.y = u_st;
       A->recs[u] = r;
+      if (A->upins) A->upins[u] = u_pins;
     }
     ++n;
     open = false;
@@ -129,6 +132,7 @@ struct UnitVisitor {
     u_len = 1;
     u_tile = tile;
     u_st = ((init ^ par) & 0xffffu) | (((init ^ par_gs) & 0xffffu) << 16);
+    u_pins = make_uint2(init ^ par, init ^ par_gs);
   }
 };
 
@@ -281,7 +285,18 @@ struct FillArgs {
   int64_t* dbg_bin;           // optional, gate-major: bin of the event
   int32_t* alpha_span;        // max over events of |1 - alpha| + |alpha| (FP32 bits; positive floats order as ints)
   int32_t* max_bin;           // most events in one bin
+  const int32_t* gperm;       // cell-sorted index -> gate
+  int64_t glitch_clk;         // > 0: glitch detection with this clock period
+  float* rgl;                 // energy factor per event (glitch detection on)
+  const uint2* upins;         // per unit, all pin values (set when some cell has more than 8 state pins)
 };
+
+// Table item of state st and leakage item of state sl of a cell with more
+// than 8 state pins (kept out of line: rare, and it would stop the event loop
+// of k_pk_fill from unrolling).
+__device__ __noinline__ uint2 wide_items(WideView W, int cell, int mode, uint32_t st, uint32_t sl) {
+  return make_uint2((uint32_t)wide_item(W, cell, mode, st, false), (uint32_t)wide_item(W, cell, mode, sl, true));
+}
 
 // One workgroup per tile, one wavefront per group of the tile, one lane per
 // unit: the unit descriptor, and every event's record in the unit-interleaved
@@ -312,8 +327,19 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
     UnitRec r{0, 0xffffffffu, 0u};
     if (act) r = a.recs[a.sidx[j]];
     const int cell = act ? a.gcell[r.x & 0x0fffffffu] : 0;
-    // descriptor: y = pin values before the unit's first event | cell << 16
-    a.desc[gi * kGroupUnits + lane] = make_uint2(r.x, (r.y & 0xffffu) | ((uint32_t)cell << 16));
+    uint32_t cur = r.y & 0xffffu;   // pin values before the unit's first event
+    uint32_t gsv = r.y >> 16;       // pin values before that event's timestamp group
+    if (a.upins && act) {
+      const uint2 up = a.upins[a.sidx[j]];
+      cur = up.x;
+      gsv = up.y;
+    }
+    const CellMeta cm = L.meta[cell];
+    const uint32_t in_mask = state_mask(cm.n_in, L.all_pins);   // pins of the state index
+    // descriptor: y = the leakage state before the unit's first event (its
+    // pin values for a kCellDirect cell, else its leakage item) | cell << 16
+    const uint32_t lk0 = cm.mode == kCellDirect ? (cur & 0xffffu) : wide_items(L.wide, cell, cm.mode, 0u, cur & in_mask).y;
+    a.desc[gi * kGroupUnits + lane] = make_uint2(r.x, lk0 | ((uint32_t)cell << 16));
     const int len = act ? (int)(r.x >> 28) + 1 : 0;
     int64_t tt[kS];
     uint32_t pb[kS];
@@ -326,12 +352,9 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
         sl[kk] = a.ev.slew[r.src + kk];
       }
     }
-    const CellMeta cm = L.meta[cell];
-    const uint32_t in_mask = (1u << cm.n_in) - 1u;
+    const int64_t gstart = (a.glitch_clk > 0 && act) ? a.ev.gate_off[a.gperm[r.x & 0x0fffffffu]] : 0;
     const float* axis = L.slew + cm.axis_off;
     const float* inv = L.slew_inv + cm.axis_off;
-    uint32_t cur = r.y & 0xffffu;   // pin values before the unit's first event
-    uint32_t gsv = r.y >> 16;       // pin values before that event's timestamp group
     int64_t tprev = 0;
     int64_t off = a.grp_off[gi];
 #pragma unroll
@@ -345,7 +368,7 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
         const int64_t t = tt[kk];
         if (kk > 0 && t != tprev) gsv = cur;
         tprev = t;
-        const uint32_t pin = min(pb[kk] >> 1, (uint32_t)kMaxPin);
+        const uint32_t pin = (pb[kk] >> 1) & 31u;
         const uint32_t v = pb[kk] & 1u;
         const uint32_t st = gsv & in_mask;
         cur ^= 1u << pin;
@@ -355,11 +378,22 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
         int i;
         float al;
         slew_segment(axis, inv, a.lib.n_slew, sl[kk], i, al);
-        const uint32_t q = (uint32_t)(L.map_q[cm.map_off + 2 * (int)st + (int)v] + i * qstride);
+        uint32_t ti = st, li = cur & in_mask;   // table and leakage entries relative to the cell's first
+        if (cm.mode != kCellDirect) {
+          const uint2 w = wide_items(L.wide, cell, cm.mode, st, li);
+          ti = w.x;
+          li = w.y;
+        }
+        const uint32_t q = (uint32_t)(L.map_q[cm.map_off + 2 * (int)ti + (int)v] + i * qstride);
         atomicAdd(&hist[bl], 1);
-        a.w32[pos] = (bl << B.r_bits) | rr | ((cur & in_mask) << kStateShift);
+        a.w32[pos] = (bl << B.r_bits) | rr | (li << kStateShift);
         a.row[pos] = q | ((pin == (uint32_t)cm.n_in ? 1u : 0u) << kOutBit) | (v << 31);
         a.alpha[pos] = al;
+        if (a.glitch_clk > 0) {
+          const float rg = glitch_ratio(a.ev.t, a.ev.pb, a.ev.slew, gstart, r.src + kk, t, (int)(pb[kk] >> 1), sl[kk],
+                                        a.glitch_clk);
+          a.rgl[pos] = rg > 0.f ? rg : 1.0f;
+        }
         span = fmaxf(span, fabsf(1.0f - al) + fabsf(al));
         if (a.dbg_state) {
           const int64_t e = r.src + kk;
@@ -379,23 +413,30 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
   if (lane == 0 && mx > 0) atomicMax(a.max_bin, mx);
 }
 
-// First and last cell among a group's units (-1 for an empty group); the
-// lanes of a group are in gate-block order, so cells do not decrease.
-__global__ void __launch_bounds__(256) k_pk_group_cells(const uint2* desc, int64_t n_groups, int2* cells) {
+// Quad range of a group: the union of its units' cell table ranges
+// [cq_lo, cq_hi) (the table ranges of cells need not follow the cell order),
+// and the range of its first unit's cell: (lo, hi, first lo, first hi), all
+// -1 for an empty group.
+__global__ void __launch_bounds__(256) k_pk_group_quads(const uint2* desc, int64_t n_groups, const int32_t* cq_lo,
+                                                        const int32_t* cq_hi, int32_t n_cells, int4* gq) {
   const int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroupUnits;
   const int lane = (int)(threadIdx.x & (kGroupUnits - 1));
   if (gi >= n_groups) return;
   const uint2 d = desc[gi * kGroupUnits + lane];
-  const bool v = d.x != 0xffffffffu;
+  const int cell = (int)(d.y >> 16);
+  const bool v = d.x != 0xffffffffu && cell < n_cells;
   const uint64_t m = __ballot(v);
   if (m == 0) {
-    if (lane == 0) cells[gi] = make_int2(-1, -1);
+    if (lane == 0) gq[gi] = make_int4(-1, -1, -1, -1);
     return;
   }
+  int32_t lo = v ? cq_lo[cell] : INT32_MAX, hi = v ? cq_hi[cell] : INT32_MIN;
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o, 64));
+    hi = max(hi, __shfl_xor(hi, o, 64));
+  }
   const int first = __ffsll((unsigned long long)m) - 1;
-  const int last = 63 - __clzll((long long)m);
-  if (lane == first) cells[gi].x = (int)(d.y >> 16);
-  if (lane == last) cells[gi].y = (int)(d.y >> 16);
+  if (lane == first) gq[gi] = make_int4(lo, hi, cq_lo[cell], cq_hi[cell]);
 }
 
 // Table phases of one tile (one wavefront per tile, the decisions taken in
@@ -406,26 +447,25 @@ __global__ void __launch_bounds__(256) k_pk_group_cells(const uint2* desc, int64
 // tile's first group index (a tile has at most as many phases as groups) and
 // counted in n_ph; k_pk_phase_copy compacts them.
 constexpr int kPhaseChunk = 2048;   // groups staged in LDS at a time
-__global__ void __launch_bounds__(64) k_pk_phases(const int2* gcells, const uint32_t* tile_grp, const int32_t* cq_lo,
-                                                  const int32_t* cq_hi, int32_t n_cells, int64_t cap, int4* ph_tmp,
-                                                  uint32_t* n_ph, int32_t* all_full) {
-  __shared__ int2 cc_sh[kPhaseChunk];
+__global__ void __launch_bounds__(64) k_pk_phases(const int4* gq, const uint32_t* tile_grp, int64_t cap,
+                                                  int4* ph_tmp, uint32_t* n_ph, int32_t* all_full) {
+  __shared__ int4 cc_sh[kPhaseChunk];
   const int32_t k = blockIdx.x;
   const int64_t g0 = tile_grp[k], g1 = tile_grp[k + 1];
   bool staged = false;   // cc_sh holds groups [cbase, cbase + kPhaseChunk)
   int64_t cbase = 0;
-  // cells of group e (an out-of-range cell counts as an empty group)
-  auto cells_of = [&](int64_t e) -> int2 {
+  // quad ranges of group e (an inconsistent range counts as an empty group)
+  auto quads_of = [&](int64_t e) -> int4 {
     if (!staged || e < cbase || e >= cbase + kPhaseChunk) {
       __syncthreads();
       staged = true;
       cbase = e;
       for (int i = threadIdx.x; i < kPhaseChunk; i += 64)
-        cc_sh[i] = (e + i < g1) ? gcells[e + i] : make_int2(-1, -1);
+        cc_sh[i] = (e + i < g1) ? gq[e + i] : make_int4(-1, -1, -1, -1);
       __syncthreads();
     }
-    const int2 cc = cc_sh[e - cbase];
-    return (cc.x >= 0 && cc.x < n_cells && cc.y >= cc.x && cc.y < n_cells) ? cc : make_int2(-1, -1);
+    const int4 r = cc_sh[e - cbase];
+    return (r.x >= 0 && r.y >= r.x && r.z >= r.x && r.w >= r.z && r.w <= r.y) ? r : make_int4(-1, -1, -1, -1);
   };
   uint32_t np = 0;
   int32_t full_all = 1;
@@ -434,10 +474,9 @@ __global__ void __launch_bounds__(64) k_pk_phases(const int2* gcells, const uint
     int64_t lo = INT64_MAX, hi = INT64_MIN;
     int64_t e = g;
     for (; e < g1; ++e) {
-      const int2 cc = cells_of(e);
-      if (cc.x < 0) continue;
-      const int64_t l = min(cq_lo[cc.x], cq_lo[cc.y]), h = max(cq_hi[cc.x], cq_hi[cc.y]);
-      const int64_t nl = min(lo, l), nh = max(hi, h);
+      const int4 r = quads_of(e);
+      if (r.x < 0) continue;
+      const int64_t nl = min(lo, (int64_t)r.x), nh = max(hi, (int64_t)r.y);
       if (e > g && nh - nl > cap) break;
       lo = nl;
       hi = nh;
@@ -448,9 +487,9 @@ __global__ void __launch_bounds__(64) k_pk_phases(const int2* gcells, const uint
     }
     int32_t full = 1;
     if (hi - lo > cap) {  // group g alone exceeds the slot (so it is not empty)
-      const int2 cc = cells_of(g);
-      lo = cc.x >= 0 ? cq_lo[cc.x] : 0;
-      hi = cc.x >= 0 ? min((int64_t)cq_hi[cc.x], lo + cap) : 0;
+      const int4 r = quads_of(g);
+      lo = r.x >= 0 ? r.z : 0;
+      hi = r.x >= 0 ? min((int64_t)r.w, lo + cap) : 0;
       full = 0;
       full_all = 0;
     }
@@ -551,8 +590,8 @@ int64_t scan_sums_items(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1;
 }  // namespace
 
 void pack_free(PackOut* o) {
-  void* ps[] = {o->w32,   o->row,  o->alpha, o->desc,      o->grp_off, o->tile_grp, o->gperm,
-                o->gcell, o->gout, o->ginit, o->reg_first, o->tfirst,  o->phases,   o->ph_off};
+  void* ps[] = {o->w32,  o->row,  o->alpha, o->rgl,       o->desc,   o->grp_off, o->tile_grp, o->gperm,
+                o->gcell, o->gout, o->ginit, o->reg_first, o->tfirst, o->phases,  o->ph_off};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   *o = PackOut();
@@ -715,6 +754,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     ua.keys = nullptr;
     ua.vals = nullptr;
     ua.recs = nullptr;
+    ua.upins = nullptr;
     int64_t NU = 0;
     if (n_blocks > 0) {
       const unsigned gridb = (unsigned)((n_blocks + kFwdThreads - 1) / kFwdThreads);
@@ -743,9 +783,9 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
                        align256((size_t)(n_tiles + 1) * 4) + align256((size_t)scan_sums_items(n_tiles + 1) * 4) +
                        align256((size_t)(ng_max + 1) * 8) + align256((size_t)scan_sums_items(ng_max + 1) * 8) +
                        align256((size_t)std::max<int64_t>(n_reg, 1) * 8) +
-                       align256((size_t)ng_max * 8) + align256((size_t)ng_max * sizeof(int4)) +
+                       2 * align256((size_t)ng_max * sizeof(int4)) +
                        align256((size_t)(n_tiles + 1) * 4) + align256((size_t)scan_sums_items(n_tiles + 1) * 4) +
-                       align256((size_t)n_cells * 8) + 4096;
+                       align256((size_t)n_cells * 8) + (in.wide_cells ? align256((size_t)NU * 8) : 0) + 4096;
     PK(reserve(ws2b, ws2));
     Bump wc{(char*)ws2b->p, ws2b->bytes};
     uint64_t* keys = wc.take<uint64_t>((size_t)NU);
@@ -759,11 +799,12 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     int64_t* glen = wc.take<int64_t>((size_t)ng_max + 1);
     int64_t* gsums = wc.take<int64_t>((size_t)scan_sums_items(ng_max + 1));
     int64_t* rev = wc.take<int64_t>((size_t)std::max<int64_t>(n_reg, 1));
-    int2* gcells = wc.take<int2>((size_t)ng_max);
+    int4* gquads = wc.take<int4>((size_t)ng_max);
     int4* ph_tmp = wc.take<int4>((size_t)ng_max);
     uint32_t* nph = wc.take<uint32_t>((size_t)n_tiles + 1);
     uint32_t* psums = wc.take<uint32_t>((size_t)scan_sums_items(n_tiles + 1));
-    if (!psums) {
+    uint2* upins = in.wide_cells ? wc.take<uint2>((size_t)NU) : nullptr;
+    if (!psums || (in.wide_cells && !upins)) {
       snprintf(err, err_len, "pack: workspace of %zu bytes too small", ws2b->bytes);
       st = hipErrorOutOfMemory;
       goto fail;
@@ -778,6 +819,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       ua.keys = keys;
       ua.vals = vals;
       ua.recs = recs;
+      ua.upins = upins;
       const unsigned gridb = (unsigned)((n_blocks + kFwdThreads - 1) / kFwdThreads);
       hipLaunchKernelGGL((k_pk_units<true>), dim3(gridb), dim3(kFwdThreads), 0, s, ua, n_blocks);
       PKLAUNCH("k_pk_units<emit>");
@@ -854,6 +896,10 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     PK(e2);
     o.desc = (uint2*)own((size_t)ng * kGroupUnits * 8, e2);
     PK(e2);
+    if (in.glitch_clk > 0) {
+      o.rgl = (float*)own((size_t)N * 4, e2);
+      PK(e2);
+    }
     if (ng > 0) {
       FillArgs fa;
       fa.ev = in.ev;
@@ -873,6 +919,10 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       fa.desc = o.desc;
       fa.alpha_span = (int32_t*)d_nu;
       fa.max_bin = (int32_t*)d_nu + 1;
+      fa.gperm = o.gperm;
+      fa.glitch_clk = in.glitch_clk;
+      fa.rgl = o.rgl;
+      fa.upins = upins;
       const size_t lds = (size_t)((in.lib.lds_words + 3) & ~3) * 4 + ((size_t)4 << B.tile_log2);
       if (in.unit_events <= 8) {
         PK(hipFuncSetAttribute((const void*)k_pk_fill<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
@@ -898,12 +948,11 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       PK(hipMemcpyAsync(d_cq, in.cq_lo.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
       PK(hipMemcpyAsync(d_cq + n_cells, in.cq_hi.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
       const int64_t threads = ng * kGroupUnits;
-      hipLaunchKernelGGL(k_pk_group_cells, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, o.desc, ng,
-                         gcells);
-      PKLAUNCH("k_pk_group_cells");
-      hipLaunchKernelGGL(k_pk_phases, dim3((unsigned)n_tiles), dim3(64), 0, s, (const int2*)gcells,
-                         (const uint32_t*)o.tile_grp, (const int32_t*)d_cq, (const int32_t*)(d_cq + n_cells), n_cells,
-                         (int64_t)in.slot_quads, ph_tmp, nph, (int32_t*)d_nu + 5);
+      hipLaunchKernelGGL(k_pk_group_quads, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, o.desc, ng,
+                         (const int32_t*)d_cq, (const int32_t*)(d_cq + n_cells), n_cells, gquads);
+      PKLAUNCH("k_pk_group_quads");
+      hipLaunchKernelGGL(k_pk_phases, dim3((unsigned)n_tiles), dim3(64), 0, s, (const int4*)gquads,
+                         (const uint32_t*)o.tile_grp, (int64_t)in.slot_quads, ph_tmp, nph, (int32_t*)d_nu + 5);
       PKLAUNCH("k_pk_phases");
       hipLaunchKernelGGL(k_pk_fill_u32, dim3(1), dim3(256), 0, s, nph + n_tiles, (int64_t)1, 0u);
       PKLAUNCH("k_pk_fill_u32");

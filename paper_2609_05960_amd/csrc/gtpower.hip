@@ -87,6 +87,7 @@ struct gtp_ctx_s {
   // library
   bool lib_ok = false;
   int32_t n_cells = 0, n_slew = 0, n_load = 0, n_map = 0, n_leak = 0;
+  int32_t all_pins = 0;       // the library's states cover every pin (bit I = output)
   int64_t n_tables = 0;
   int32_t lds_words = 0;
   // fixed-point range inputs (see choose_mfix): largest |table entry|, the
@@ -99,6 +100,8 @@ struct gtp_ctx_s {
   std::vector<int32_t> h_gate_cell;  // host copy of the netlist's cells
   DevBuf lib_img;             // meta | leak | map_q | slew | slew_inv
   DevBuf load_axis, load_inv, quads;
+  DevBuf wide_cell, wide_pat, wide_sipl;   // cells with more than 8 state pins
+  bool has_wide = false;
 
   // netlist
   bool net_ok = false;
@@ -159,6 +162,7 @@ struct gtp_ctx_s {
   DevBuf gprep, gparam, X, S, exS, L0, flag, first_bad;
   DevBuf l0_part, tile_tot, tile_base;   // packed forward: leakage-rate partials and tile sums
   DevBuf adj_w, adj_c, adj_exc, adj_wg, adj_gtile, adj_total, gC, gL;
+  DevBuf rep_small;                       // report: totals, latest event time, peak
 
   // packed adjoint work items (built from the pack's region tables)
   bool adj_ok = false;
@@ -338,6 +342,10 @@ LibView lib_view(gtp_ctx c) {
   L.n_leak = c->n_leak;
   L.lds_words = c->lds_words;
   L.lds_words_ml = 4 * c->n_cells + c->n_leak + 2 * nl;
+  L.all_pins = c->all_pins;
+  L.wide.cell = c->has_wide ? ptr<WideCell>(c->wide_cell) : nullptr;
+  L.wide.pat = c->has_wide ? ptr<uint2>(c->wide_pat) : nullptr;
+  L.wide.sipl = c->has_wide ? ptr<uint8_t>(c->wide_sipl) : nullptr;
   return L;
 }
 
@@ -349,6 +357,7 @@ float rate_scale_of(int32_t m) { return (float)(std::ldexp(1.0, m) * 1e-6); }
 constexpr int32_t kAnyMfix = 32;
 constexpr int32_t kMaxMfix = 40;   // energy unit 2^-40 fJ at most
 constexpr int32_t kMinMfix = 30;   // below this the quantised leakage rates lose the 1e-5 budget
+constexpr int32_t kSiplMaxPins = 16;   // direct per-state arrays up to this many state pins (Sec. 4.1)
 
 LutArgs lut_args(gtp_ctx c, int32_t m) {
   LutArgs A;
@@ -473,33 +482,29 @@ hipError_t lds_limit(K kern, size_t static_lds = 0) {
                              (int)(kMaxLds - static_lds));
 }
 
-hipError_t set_packed_lds_limits() {
-  hipError_t e = hipSuccess;
-  const hipError_t r[] = {lds_limit(k_fwd_packed<256, 8, false>),
-                          lds_limit(k_fwd_packed<512, 8, false>),
-                          lds_limit(k_fwd_packed<1024, 8, false>),
-                          lds_limit(k_fwd_packed<256, 16, false>),
-                          lds_limit(k_fwd_packed<512, 16, false>),
-                          lds_limit(k_fwd_packed<256, 8, true>),
-                          lds_limit(k_fwd_packed<512, 8, true>),
-                          lds_limit(k_fwd_packed<1024, 8, true>),
-                          lds_limit(k_fwd_packed<256, 16, true>),
-                          lds_limit(k_fwd_packed<512, 16, true>),
-                          lds_limit(k_fwd_batched<256, 8, false>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<512, 8, false>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<1024, 8, false>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<256, 16, false>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<512, 16, false>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<256, 8, true>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<512, 8, true>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<1024, 8, true>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<256, 16, true>, kBatchStaticLds),
-                          lds_limit(k_fwd_batched<512, 16, true>, kBatchStaticLds),
-                          lds_limit(k_adjoint_packed<1024, 8>),
-                          lds_limit(k_adjoint_packed<512, 16>)};
+template <int TH, int SL, bool SO, bool GL>
+hipError_t lds_limits_one() {
+  hipError_t e1 = lds_limit(k_fwd_packed<TH, SL, SO, GL>);
+  hipError_t e2 = lds_limit(k_fwd_batched<TH, SL, SO, GL>, kBatchStaticLds);
+  return e1 != hipSuccess ? e1 : e2;
+}
+
+template <bool GL>
+hipError_t lds_limits_gl() {
+  const hipError_t r[] = {lds_limits_one<256, 8, false, GL>(),  lds_limits_one<512, 8, false, GL>(),
+                          lds_limits_one<1024, 8, false, GL>(), lds_limits_one<256, 16, false, GL>(),
+                          lds_limits_one<512, 16, false, GL>(), lds_limits_one<256, 8, true, GL>(),
+                          lds_limits_one<512, 8, true, GL>(),   lds_limits_one<1024, 8, true, GL>(),
+                          lds_limits_one<256, 16, true, GL>(),  lds_limits_one<512, 16, true, GL>(),
+                          lds_limit(k_adjoint_packed<1024, 8, GL>), lds_limit(k_adjoint_packed<512, 16, GL>)};
   for (hipError_t x : r)
-    if (x != hipSuccess) e = x;
-  return e;
+    if (x != hipSuccess) return x;
+  return hipSuccess;
+}
+
+hipError_t set_packed_lds_limits() {
+  const hipError_t e = lds_limits_gl<false>();
+  return e != hipSuccess ? e : lds_limits_gl<true>();
 }
 
 void drop_batch_packs(gtp_ctx c);
@@ -597,6 +602,8 @@ gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, Bin
   in.bins = B;
   in.stream = c->stream;
   in.ws = c->pk_ws;
+  in.glitch_clk = c->par.glitch_clk_ps;
+  in.wide_cells = c->has_wide;
   const size_t ws_before = c->pk_ws[0].bytes + c->pk_ws[1].bytes;
   char msg[256] = {0};
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -774,6 +781,7 @@ gtp_status gate_prep(gtp_ctx c, const float* net_load, const float* leak_scale, 
   a.leak_scale = leak_scale;
   a.meta = L.meta;
   a.leak = L.leak;
+  a.wide = L.wide;
   a.load = ptr<float>(c->load_axis);
   a.load_inv = ptr<float>(c->load_inv);
   a.n_load = c->n_load;
@@ -783,6 +791,7 @@ gtp_status gate_prep(gtp_ctx c, const float* net_load, const float* leak_scale, 
   a.rate_scale = rate_scale_of(m);
   a.max_scale = GTP_MAX_LEAK_SCALE;
   a.load_cap = (float)c->load_cap;
+  a.all_pins = c->all_pins;
   a.out = ptr<GatePrep>(c->gprep);
   a.L0 = ptr<unsigned long long>(c->L0);
   a.flag = ptr<int32_t>(c->flag);
@@ -811,6 +820,37 @@ gtp_status gtp_fixed_point_bits(const gtp_range* r, int32_t* m_out) {
     --m;
   if (m < kMinMfix) return GTP_ERR_UNSUPPORTED;
   *m_out = m;
+  return GTP_OK;
+}
+
+gtp_status gtp_expand_when(int32_t n_pins, int32_t n_patterns, const uint32_t* care, const uint32_t* value,
+                           const int32_t* item, int32_t default_item, int32_t* out) {
+  if (n_pins < 0 || n_pins > kSiplMaxPins || n_patterns < 0 || !out ||
+      (n_patterns > 0 && (!care || !value || !item)))
+    return GTP_ERR_INVALID_ARG;
+  const uint32_t full = (1u << n_pins) - 1u;
+  for (int32_t k = 0; k < n_patterns; ++k)
+    if (care[k] & ~full) return GTP_ERR_INVALID_ARG;
+  const int64_t n = 1ll << n_pins;
+  std::vector<uint8_t> done((size_t)n, 0);
+  // patterns in order; every assignment of a pattern's don't-care pins
+  // (the submasks of its free pins) names one entry, which keeps the item of
+  // the first pattern that reached it
+  for (int32_t k = 0; k < n_patterns; ++k) {
+    const uint32_t fixed = value[k] & care[k], free_pins = full & ~care[k];
+    uint32_t sub = free_pins;
+    for (;;) {
+      const uint32_t s = fixed | sub;
+      if (!done[s]) {
+        done[s] = 1;
+        out[s] = item[k];
+      }
+      if (sub == 0) break;
+      sub = (sub - 1u) & free_pins;
+    }
+  }
+  for (int64_t s = 0; s < n; ++s)
+    if (!done[(size_t)s]) out[s] = default_item;
   return GTP_OK;
 }
 
@@ -870,10 +910,11 @@ gtp_status gtp_destroy(gtp_ctx c) {
   for (Workspace& w : c->pk_ws)
     if (w.p) (void)hipFree(w.p);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  DevBuf* all[] = {&c->lib_img, &c->load_axis, &c->load_inv, &c->quads, &c->gate_cell, &c->gate_out,
+  DevBuf* all[] = {&c->lib_img, &c->load_axis, &c->load_inv, &c->quads, &c->wide_cell, &c->wide_pat, &c->wide_sipl,
+                   &c->gate_cell, &c->gate_out,
                    &c->gate_init, &c->plan_blk, &c->blk_tmp, &c->blk_tmp2, &c->scan_sums, &c->gprep, &c->gparam, &c->l0_part, &c->tile_tot, &c->tile_base,
                    &c->X, &c->S, &c->exS, &c->L0, &c->flag, &c->first_bad, &c->adj_w, &c->adj_c, &c->adj_exc,
-                   &c->adj_wg, &c->adj_gtile, &c->adj_total, &c->gC, &c->gL, &c->adj_items, &c->adj_entries, &c->adj_gbs, &c->adj_gbrow, &c->adj_gbrows, &c->adj_part, &c->b_tab, &c->b_items, &c->b_queue,
+                   &c->adj_wg, &c->adj_gtile, &c->adj_total, &c->rep_small, &c->gC, &c->gL, &c->adj_items, &c->adj_entries, &c->adj_gbs, &c->adj_gbrow, &c->adj_gbrows, &c->adj_part, &c->b_tab, &c->b_items, &c->b_queue,
                    &c->b_fin, &c->b_X, &c->b_S, &c->b_exS, &c->tun_in, &c->tun_out};
   for (DevBuf* b : all) release(c, *b);
   prof_clear(c);
@@ -918,38 +959,124 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
   const int nc = lib->n_cells, ns = lib->n_slew, nl = lib->n_load;
   if (nc <= 0 || ns < 2 || ns > 16 || nl < 2 || nl > 16)
     return fail(c, GTP_ERR_INVALID_ARG, "library sizes n_cells=%d n_slew=%d n_load=%d", nc, ns, nl);
-  if (!lib->n_inputs || !lib->slew_axis_ps || !lib->load_axis_ff || !lib->map_base || !lib->state_to_table ||
-      !lib->table_base || !lib->tables_fj || !lib->leak_base || !lib->leak_nw)
+  if (!lib->n_inputs || !lib->slew_axis_ps || !lib->load_axis_ff || !lib->table_base || !lib->tables_fj)
     return fail(c, GTP_ERR_INVALID_ARG, "null library array");
-  if (lib->n_map <= 0 || lib->n_tables <= 0 || lib->n_leak <= 0)
-    return fail(c, GTP_ERR_INVALID_ARG, "library array lengths must be positive");
+  if (lib->n_tables <= 0) return fail(c, GTP_ERR_INVALID_ARG, "library without tables");
   const int64_t Q = (int64_t)(ns - 1) * (nl - 1);
   if (lib->n_tables * Q >= (int64_t)INT32_MAX) return fail(c, GTP_ERR_UNSUPPORTED, "tables too large");
   std::vector<CellMeta> meta(nc);
   std::vector<int32_t> cq_lo(nc), cq_hi(nc);   // quads of each cell's tables
   std::vector<int32_t> mapq;
   std::vector<float> leak;
+  std::vector<double> cell_leak_max(nc, 0.0);
   float leak_max = 0.f;
+  if (lib->all_pin_state != 0 && lib->all_pin_state != 1)
+    return fail(c, GTP_ERR_INVALID_ARG, "all_pin_state %d (0 or 1)", lib->all_pin_state);
+  const int allp = lib->all_pin_state;
+  const bool pats = lib->n_tpat != nullptr;
+  if (pats && (!lib->tpat_base || !lib->tpat_care || !lib->tpat_value || !lib->tpat_table || !lib->n_lpat ||
+               !lib->lpat_base || !lib->lpat_care || !lib->lpat_value || !lib->lpat_leak_nw ||
+               lib->n_tpat_total < 0 || lib->n_lpat_total < 0))
+    return fail(c, GTP_ERR_INVALID_ARG, "null or negative-length state-pattern array");
+  std::vector<WideCell> wcell((size_t)nc, WideCell{0, 0, 0, 0, 0, 0});
+  std::vector<uint2> wpat;
+  std::vector<uint8_t> wsipl;
+  bool has_wide = false;
   for (int cc = 0; cc < nc; ++cc) {
     const int I = lib->n_inputs[cc];
-    if (I < 1 || I > 8) return fail(c, GTP_ERR_UNSUPPORTED, "cell %d has %d inputs (supported 1..8)", cc, I);
-    const int64_t nst = 1ll << I;
-    const int64_t mb = lib->map_base[cc], tb = lib->table_base[cc], lbs = lib->leak_base[cc];
-    if (mb < 0 || mb + 2 * nst > lib->n_map || lbs < 0 || lbs + nst > lib->n_leak || tb < 0 || tb >= lib->n_tables)
-      return fail(c, GTP_ERR_INVALID_ARG, "cell %d: map/leak/table base out of range", cc);
+    const bool by_pat = pats && lib->n_tpat[cc] > 0;
+    const int nsp = I + allp;   // state pins
+    if (!by_pat && (I < 1 || nsp > 8))
+      return fail(c, GTP_ERR_UNSUPPORTED, "cell %d: %d inputs given as per-state arrays (1..%d; wider cells need "
+                  "state patterns)", cc, I, 8 - allp);
+    if (by_pat && (I < 1 || I > 31))
+      return fail(c, GTP_ERR_UNSUPPORTED, "cell %d has %d inputs (supported 1..31)", cc, I);
+    const int64_t tb = lib->table_base[cc];
+    if (tb < 0 || tb >= lib->n_tables) return fail(c, GTP_ERR_INVALID_ARG, "cell %d: table base out of range", cc);
     for (int i = 0; i + 1 < ns; ++i)
       if (!(lib->slew_axis_ps[cc * ns + i] < lib->slew_axis_ps[cc * ns + i + 1]))
         return fail(c, GTP_ERR_INVALID_ARG, "cell %d: slew axis not strictly increasing", cc);
     for (int j = 0; j + 1 < nl; ++j)
       if (!(lib->load_axis_ff[cc * nl + j] < lib->load_axis_ff[cc * nl + j + 1]))
         return fail(c, GTP_ERR_INVALID_ARG, "cell %d: load axis not strictly increasing", cc);
-    meta[cc].n_in = I;
+    // the cell's map entries (local table ids, fall and rise per entry) and
+    // leakage values: per state for a kCellDirect cell, per pattern otherwise
+    std::vector<int64_t> tid;
+    std::vector<float> lv;
+    int16_t mode = kCellDirect;
+    if (!by_pat) {
+      if (!lib->map_base || !lib->state_to_table || !lib->leak_base || !lib->leak_nw)
+        return fail(c, GTP_ERR_INVALID_ARG, "cell %d: null per-state array", cc);
+      const int64_t nst = 1ll << nsp;
+      const int64_t mb = lib->map_base[cc], lbs = lib->leak_base[cc];
+      if (mb < 0 || mb + 2 * nst > lib->n_map || lbs < 0 || lbs + nst > lib->n_leak)
+        return fail(c, GTP_ERR_INVALID_ARG, "cell %d: map/leak base out of range", cc);
+      tid.assign(lib->state_to_table + mb, lib->state_to_table + mb + 2 * nst);
+      lv.assign(lib->leak_nw + lbs, lib->leak_nw + lbs + nst);
+    } else {
+      const int64_t nt = lib->n_tpat[cc], nlp = lib->n_lpat[cc];
+      const int64_t t0 = lib->tpat_base[cc], l0 = lib->lpat_base[cc];
+      if (nt > 256 || nlp < 1 || nlp > 256)
+        return fail(c, GTP_ERR_INVALID_ARG, "cell %d: %lld table and %lld leakage patterns (1..256 each)", cc,
+                    (long long)nt, (long long)nlp);
+      if (t0 < 0 || t0 + nt > lib->n_tpat_total || l0 < 0 || l0 + nlp > lib->n_lpat_total)
+        return fail(c, GTP_ERR_INVALID_ARG, "cell %d: pattern base out of range", cc);
+      const uint32_t smask = nsp >= 32 ? 0xffffffffu : (1u << nsp) - 1u;
+      for (int64_t k = 0; k < nt; ++k)
+        if (lib->tpat_care[t0 + k] & ~smask)
+          return fail(c, GTP_ERR_INVALID_ARG, "cell %d: table pattern %lld names a pin outside the state", cc,
+                      (long long)k);
+      for (int64_t k = 0; k < nlp; ++k)
+        if (lib->lpat_care[l0 + k] & ~smask)
+          return fail(c, GTP_ERR_INVALID_ARG, "cell %d: leakage pattern %lld names a pin outside the state", cc,
+                      (long long)k);
+      if (lib->tpat_care[t0 + nt - 1] != 0u || lib->lpat_care[l0 + nlp - 1] != 0u)
+        return fail(c, GTP_ERR_INVALID_ARG, "cell %d: the last pattern of each list must have no care pins", cc);
+      if (nsp <= kSiplMaxPins) {
+        // expand both lists into per-state pattern indices
+        const int64_t nst = 1ll << nsp;
+        std::vector<int32_t> idx((size_t)std::max(nt, nlp)), it((size_t)nst), il((size_t)nst);
+        for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int32_t)k;
+        if (gtp_expand_when(nsp, (int32_t)nt, lib->tpat_care + t0, lib->tpat_value + t0, idx.data(),
+                            (int32_t)nt - 1, it.data()) != GTP_OK ||
+            gtp_expand_when(nsp, (int32_t)nlp, lib->lpat_care + l0, lib->lpat_value + l0, idx.data(),
+                            (int32_t)nlp - 1, il.data()) != GTP_OK)
+          return fail(c, GTP_ERR_INVALID_ARG, "cell %d: state patterns", cc);
+        if (nsp <= 8) {
+          for (int64_t st = 0; st < nst; ++st) {
+            tid.push_back(lib->tpat_table[2 * (t0 + it[st])]);
+            tid.push_back(lib->tpat_table[2 * (t0 + it[st]) + 1]);
+            lv.push_back(lib->lpat_leak_nw[l0 + il[st]]);
+          }
+        } else {
+          mode = kCellSipl;
+          wcell[cc].t_sipl = (int64_t)wsipl.size();
+          for (int64_t st = 0; st < nst; ++st) wsipl.push_back((uint8_t)it[st]);
+          wcell[cc].l_sipl = (int64_t)wsipl.size();
+          for (int64_t st = 0; st < nst; ++st) wsipl.push_back((uint8_t)il[st]);
+        }
+      } else {
+        mode = kCellScan;
+        wcell[cc].t_first = (int32_t)wpat.size();
+        for (int64_t k = 0; k < nt; ++k) wpat.push_back(make_uint2(lib->tpat_care[t0 + k], lib->tpat_value[t0 + k]));
+        wcell[cc].l_first = (int32_t)wpat.size();
+        for (int64_t k = 0; k < nlp; ++k) wpat.push_back(make_uint2(lib->lpat_care[l0 + k], lib->lpat_value[l0 + k]));
+      }
+      if (mode != kCellDirect) {
+        has_wide = true;
+        wcell[cc].t_n = (int32_t)nt;
+        wcell[cc].l_n = (int32_t)nlp;
+        tid.assign(lib->tpat_table + 2 * t0, lib->tpat_table + 2 * (t0 + nt));
+        lv.assign(lib->lpat_leak_nw + l0, lib->lpat_leak_nw + l0 + nlp);
+      }
+    }
+    meta[cc].n_in = (int16_t)I;
+    meta[cc].mode = mode;
     meta[cc].map_off = (int32_t)mapq.size();
     meta[cc].leak_off = (int32_t)leak.size();
     meta[cc].axis_off = cc * ns;
     int64_t t_lo = INT64_MAX, t_hi = -1;
-    for (int64_t e = 0; e < 2 * nst; ++e) {
-      const int64_t k = lib->state_to_table[mb + e];
+    for (const int64_t k : tid) {
       if (k < 0 || tb + k >= lib->n_tables)
         return fail(c, GTP_ERR_INVALID_ARG, "cell %d: table id %lld out of range", cc, (long long)k);
       mapq.push_back((int32_t)((tb + k) * Q));
@@ -958,12 +1085,14 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
     }
     cq_lo[cc] = (int32_t)(t_lo * Q);
     cq_hi[cc] = (int32_t)((t_hi + 1) * Q);
-    for (int64_t s = 0; s < nst; ++s) {
-      const float v = lib->leak_nw[lbs + s];
+    for (const float v : lv) {
       if (!(v >= 0.f) || !std::isfinite(v)) return fail(c, GTP_ERR_INVALID_ARG, "cell %d: bad leakage value", cc);
       leak.push_back(v);
       leak_max = std::max(leak_max, v);
+      cell_leak_max[cc] = std::max(cell_leak_max[cc], (double)v);
     }
+    if (mapq.size() >= (size_t)INT32_MAX / 2 || leak.size() >= (size_t)INT32_MAX / 2 || wpat.size() >= (size_t)INT32_MAX)
+      return fail(c, GTP_ERR_UNSUPPORTED, "library too large");
   }
   for (int64_t i = 0; i < lib->n_tables * ns * nl; ++i)
     if (!std::isfinite(lib->tables_fj[i])) return fail(c, GTP_ERR_INVALID_ARG, "non-finite table entry %lld",
@@ -1011,6 +1140,15 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
         q[3] = tb[(i + 1) * nl + j + 1];
       }
   }
+  if (has_wide) {
+    TRY(ensure(c, c->wide_cell, wcell.size() * sizeof(WideCell)));
+    TRY(ensure(c, c->wide_pat, std::max<size_t>(wpat.size(), 1) * sizeof(uint2)));
+    TRY(ensure(c, c->wide_sipl, std::max<size_t>(wsipl.size(), 1)));
+    HIPCHK(c, hipMemcpy(c->wide_cell.p, wcell.data(), wcell.size() * sizeof(WideCell), hipMemcpyHostToDevice));
+    if (!wpat.empty())
+      HIPCHK(c, hipMemcpy(c->wide_pat.p, wpat.data(), wpat.size() * sizeof(uint2), hipMemcpyHostToDevice));
+    if (!wsipl.empty()) HIPCHK(c, hipMemcpy(c->wide_sipl.p, wsipl.data(), wsipl.size(), hipMemcpyHostToDevice));
+  }
   TRY(ensure(c, c->lib_img, img.size() * 4));
   TRY(ensure(c, c->load_axis, load.size() * 4));
   TRY(ensure(c, c->load_inv, load_inv.size() * 4));
@@ -1025,6 +1163,8 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
   c->n_map = n_map;
   c->n_leak = n_leak;
   c->n_tables = lib->n_tables;
+  c->all_pins = allp;
+  c->has_wide = has_wide;
   c->lds_words = (int32_t)words;
   c->h_nin.assign(lib->n_inputs, lib->n_inputs + nc);
   c->h_cq_lo = cq_lo;
@@ -1051,10 +1191,7 @@ gtp_status gtp_load_library(gtp_ctx c, const gtp_library* lib) {
     c->lib_leak_max = leak_max;
     c->load_cap = cap;
     c->beta_span = span;
-    c->h_leak_max.assign((size_t)nc, 0.0);
-    for (int cc = 0; cc < nc; ++cc)
-      for (int64_t st = 0; st < (1ll << lib->n_inputs[cc]); ++st)
-        c->h_leak_max[cc] = std::max(c->h_leak_max[cc], (double)lib->leak_nw[lib->leak_base[cc] + st]);
+    c->h_leak_max = cell_leak_max;
   }
   c->lib_ok = true;
   c->net_ok = false;
@@ -1215,7 +1352,7 @@ gtp_status gtp_load_events(gtp_ctx c, const gtp_events* ev, int validate) {
 gtp_status gtp_set_params(gtp_ctx c, const gtp_params* p) {
   TRY(need(c, true, false, false, false));
   if (!p || !(p->vdd > 0.0) || !std::isfinite(p->vdd) || p->bin_ps < 1 || p->bin_ps > (1 << 22) ||
-      (p->sw_mode != 0 && p->sw_mode != 1))
+      (p->sw_mode != 0 && p->sw_mode != 1) || p->glitch_clk_ps < 0)
     return fail(c, GTP_ERR_INVALID_ARG, "bad parameters");
   c->par = *p;
   BinSpec& B = c->bins;
@@ -1332,10 +1469,12 @@ gtp_status gate_params_into(gtp_ctx c, const PackOut& pk, const float* net_load,
   a.leak_scale = leak_scale;
   a.meta = L.meta;
   a.leak = L.leak;
+  a.wide = L.wide;
   a.n_gates = c->n_gates;
   a.rate_scale = rate_scale_of(pk.mfix);
   a.max_scale = GTP_MAX_LEAK_SCALE;
   a.load_cap = (float)c->load_cap;
+  a.all_pins = c->all_pins;
   a.out = out;
   a.l0_part = l0_part;
   a.flag = ptr<int32_t>(c->flag);
@@ -1402,13 +1541,19 @@ gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, in
   const dim3 grid((unsigned)B.n_tiles);
   // every quad from the LDS slots when every phase holds all its groups' quads
   const bool so = ph && pk.phases_full;
-#define GTP_PACKED_CASE(TH, SL)                                                            \
-  if (th == TH && sl == SL) {                                                              \
-    if (so)                                                                                \
-      LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, SL, true>), grid, dim3(TH), lds, a);     \
-    else                                                                                   \
-      LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, SL, false>), grid, dim3(TH), lds, a);    \
-    return GTP_OK;                                                                         \
+  a.rgl = pk.rgl;
+  const bool gl = pk.rgl != nullptr;
+#define GTP_PACKED_CASE(TH, SL)                                                                     \
+  if (th == TH && sl == SL) {                                                                       \
+    if (so && gl)                                                                                   \
+      LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, SL, true, true>), grid, dim3(TH), lds, a);        \
+    else if (so)                                                                                    \
+      LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, SL, true, false>), grid, dim3(TH), lds, a);       \
+    else if (gl)                                                                                    \
+      LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, SL, false, true>), grid, dim3(TH), lds, a);       \
+    else                                                                                            \
+      LAUNCH(c, "k_fwd_packed", (k_fwd_packed<TH, SL, false, false>), grid, dim3(TH), lds, a);      \
+    return GTP_OK;                                                                                  \
   }
   GTP_PACKED_CASE(256, 8)
   GTP_PACKED_CASE(512, 8)
@@ -1527,6 +1672,7 @@ gtp_status build_batch(gtp_ctx c) {
     tab[i] = TraceDev{t.pk.w32,
                       t.pk.row,
                       t.pk.alpha,
+                      t.pk.rgl,
                       ph ? t.pk.phases : nullptr,
                       ph ? t.pk.ph_off : nullptr,
                       ph ? t.pk.slot_quads : 0,
@@ -1610,12 +1756,17 @@ gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_s
     per_cu = std::min(per_cu, 2048 / th);
     const int64_t wgs = std::min<int64_t>(c->batch_items, (int64_t)c->n_cu * per_cu);
     const dim3 grid((unsigned)wgs);
-#define GTP_BATCH_CASE(TH, SL)                                                                \
-  if (th == TH && sl == SL) {                                                                 \
-    if (so)                                                                                   \
-      LAUNCH(c, "k_fwd_batched", (k_fwd_batched<TH, SL, true>), grid, dim3(TH), lds, a);      \
-    else                                                                                      \
-      LAUNCH(c, "k_fwd_batched", (k_fwd_batched<TH, SL, false>), grid, dim3(TH), lds, a);     \
+    const bool gl = c->par.glitch_clk_ps > 0;
+#define GTP_BATCH_CASE(TH, SL)                                                                       \
+  if (th == TH && sl == SL) {                                                                        \
+    if (so && gl)                                                                                    \
+      LAUNCH(c, "k_fwd_batched", (k_fwd_batched<TH, SL, true, true>), grid, dim3(TH), lds, a);       \
+    else if (so)                                                                                     \
+      LAUNCH(c, "k_fwd_batched", (k_fwd_batched<TH, SL, true, false>), grid, dim3(TH), lds, a);      \
+    else if (gl)                                                                                     \
+      LAUNCH(c, "k_fwd_batched", (k_fwd_batched<TH, SL, false, true>), grid, dim3(TH), lds, a);      \
+    else                                                                                             \
+      LAUNCH(c, "k_fwd_batched", (k_fwd_batched<TH, SL, false, false>), grid, dim3(TH), lds, a);     \
   }
     GTP_BATCH_CASE(256, 8)
     GTP_BATCH_CASE(512, 8)
@@ -1700,6 +1851,7 @@ gtp_status gtp_forward(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       a.lib = lib_view(c);
       a.lut = lut_args(c, m);
       a.bins = c->bins;
+      a.glitch_clk = c->par.glitch_clk_ps;
       a.X = ptr<unsigned long long>(c->X);
       a.S = ptr<unsigned long long>(c->S);
       LAUNCH(c, "k_gate_serial", k_gate_serial, dim3(grid_for(c->n_gates, kFwdThreads)), dim3(kFwdThreads), lib_lds_bytes(c), a);
@@ -1990,6 +2142,7 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       a.f.grp_off = pk.grp_off;
       a.f.tile_grp = pk.tile_grp;
       a.f.bins = c->bins;
+      a.f.rgl = pk.rgl;
       a.entries = ptr<int4>(c->adj_entries);
       a.items = ptr<AdjItem>(c->adj_items);
       a.gb_start = ptr<int32_t>(c->adj_gbs);
@@ -2000,12 +2153,19 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       a.dsw_rise = dsw_rise;
       a.dsw_fall = dsw_fall;
       a.slot_quads = adj_slot_quads(c, c->adj_max_gb);
+      const dim3 gi((unsigned)c->adj_n_items);
+      const size_t al = adj_lds_bytes(c, c->adj_max_gb);
+      const bool gl = pk.rgl != nullptr;
       if (slots_of(c) == 8) {
-        LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<1024, 8>), dim3((unsigned)c->adj_n_items), dim3(1024),
-               adj_lds_bytes(c, c->adj_max_gb), a);
+        if (gl)
+          LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<1024, 8, true>), gi, dim3(1024), al, a);
+        else
+          LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<1024, 8, false>), gi, dim3(1024), al, a);
       } else {
-        LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<512, 16>), dim3((unsigned)c->adj_n_items), dim3(512),
-               adj_lds_bytes(c, c->adj_max_gb), a);
+        if (gl)
+          LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<512, 16, true>), gi, dim3(512), al, a);
+        else
+          LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<512, 16, false>), gi, dim3(512), al, a);
       }
     }
     if (c->n_nets > 0)
@@ -2025,10 +2185,12 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       o.gate_init = ptr<uint32_t>(c->gate_init);
       o.meta = lib_view(c).meta;
       o.leak = lib_view(c).leak;
+      o.wide = lib_view(c).wide;
       o.grad_load = grad_net_load;
       o.grad_scale = grad_leak_scale;
       o.n_gates = c->n_gates;
       o.unique_out = c->unique_out ? 1 : 0;
+      o.all_pins = c->all_pins;
       LAUNCH(c, "k_adj_out_sorted", k_adj_out_sorted, dim3(grid_for(c->n_gates, 256)), dim3(256), 0, o);
     }
     return GTP_OK;
@@ -2049,6 +2211,7 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
     a.wg = ptr<double2>(c->adj_wg);
     a.dsw_rise = dsw_rise;
     a.dsw_fall = dsw_fall;
+    a.glitch_clk = c->par.glitch_clk_ps;
     a.gC = ptr<double>(c->gC);
     a.gL = ptr<double>(c->gL);
     LAUNCH(c, "k_adjoint_events", k_adjoint_events, dim3(grid_for(c->n_blocks, kFwdThreads)), dim3(kFwdThreads), lib_lds_bytes(c), a);
@@ -2063,12 +2226,76 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
     o.gate_init = ptr<uint32_t>(c->gate_init);
     o.meta = lib_view(c).meta;
     o.leak = lib_view(c).leak;
+    o.wide = lib_view(c).wide;
     o.grad_load = grad_net_load;
     o.grad_scale = grad_leak_scale;
     o.n_nets = c->n_nets;
     o.n_gates = c->n_gates;
+    o.all_pins = c->all_pins;
     LAUNCH(c, "k_adj_out", k_adj_out, dim3(grid_for(n, 256)), dim3(256), 0, o);
   }
+  return GTP_OK;
+}
+
+gtp_status gtp_gate_report(gtp_ctx c, const float* net_load_ff, const float* leak_scale, const float* power_mw,
+                           double* gate_energy_fj, double* totals) {
+  TRY(need(c, true, true, true, true));
+  if (!net_load_ff || !gate_energy_fj || !totals) return fail(c, GTP_ERR_INVALID_ARG, "null report argument");
+  HIPCHK(c, hipSetDevice(c->dev));
+  const int64_t G = c->n_gates, NB = c->bins.n_bins;
+  TRY(ensure(c, c->rep_small, 64));
+  double* d_tot = ptr<double>(c->rep_small);                                           // [4]
+  unsigned long long* d_tmax = reinterpret_cast<unsigned long long*>(d_tot + 4);       // [1]
+  uint32_t* d_peak = reinterpret_cast<uint32_t*>(d_tot + 5);                           // [1]
+  TRY(fill_u64(c, c->rep_small.p, 8, 0ull));
+  TRY(gate_prep(c, net_load_ff, leak_scale, kAnyMfix));
+  if (G > 0) TRY(fill_u64(c, gate_energy_fj, 4 * G, 0ull));
+  if (c->n_blocks > 0) {
+    ReportArgs a;
+    a.ev = ev_view(c);
+    a.plan = ptr<uint2>(c->plan_blk);
+    a.gprep = ptr<GatePrep>(c->gprep);
+    a.lib = lib_view(c);
+    a.lut = lut_args(c, kAnyMfix);
+    a.bins = c->bins;
+    a.glitch_clk = c->par.glitch_clk_ps;
+    a.ge = gate_energy_fj;
+    a.t_max = d_tmax;
+    LAUNCH(c, "k_gate_report", k_gate_report, dim3(grid_for(c->n_blocks, kFwdThreads)), dim3(kFwdThreads),
+           lib_lds_bytes(c), a);
+  }
+  if (G > 0) {
+    const LibView L = lib_view(c);
+    LAUNCH(c, "k_report_finalize", k_report_finalize, dim3(grid_for(G, 256)), dim3(256), 0,
+           (const GatePrep*)ptr<GatePrep>(c->gprep), L.meta, L.leak, L.wide, c->all_pins, G, c->bins.t_end,
+           gate_energy_fj, d_tot);
+  }
+  if (power_mw && NB > 0)
+    LAUNCH(c, "k_peak", k_peak, dim3((unsigned)std::min<int64_t>(grid_for(NB, 256), 4096)), dim3(256), 0, power_mw,
+           NB, d_peak);
+  double h[6] = {0, 0, 0, 0, 0, 0};
+  HIPCHK(c, hipMemcpyAsync(h, c->rep_small.p, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  uint64_t tm = 0;
+  uint32_t pk = 0;
+  memcpy(&tm, &h[4], 8);
+  memcpy(&pk, &h[5], 4);
+  const bool has_ev = c->ev.n_events > 0;
+  const double t_max = has_ev ? (double)tm : -1.0;
+  const double nan = std::nan("");
+  for (int k = 0; k < 4; ++k) totals[k] = h[k];
+  totals[4] = t_max;
+  if (power_mw && NB > 0) {
+    const uint32_t u = (pk & 0x80000000u) ? (pk & 0x7fffffffu) : ~pk;
+    float f;
+    memcpy(&f, &u, 4);
+    totals[5] = f;
+  } else {
+    totals[5] = nan;
+  }
+  for (int k = 0; k < 4; ++k) totals[6 + k] = t_max > 0 ? h[k] / t_max : nan;
+  totals[10] = (h[0] + h[1] + h[2] + h[3]) / (double)c->bins.t_end;
+  totals[11] = (double)c->bins.t_end;
   return GTP_OK;
 }
 

@@ -62,6 +62,17 @@ class Library:
     tables: np.ndarray          # float32 [n_tables*n_slew*n_load] fJ, [table][slew][load]
     leak_base: np.ndarray       # int64 [n_cells]
     leak: np.ndarray            # float32 nW, [2^I] per cell
+    # optional state patterns (a cell with n_tpat[c] > 0 is given by them)
+    n_tpat: Optional[np.ndarray] = None      # int32 [n_cells]
+    tpat_base: Optional[np.ndarray] = None   # int64 [n_cells]
+    tpat_care: Optional[np.ndarray] = None   # uint32, bit p = pin p named by the pattern
+    tpat_value: Optional[np.ndarray] = None  # uint32, values of the named pins
+    tpat_table: Optional[np.ndarray] = None  # int16 [2 * patterns]: local table id (fall, rise)
+    n_lpat: Optional[np.ndarray] = None
+    lpat_base: Optional[np.ndarray] = None
+    lpat_care: Optional[np.ndarray] = None
+    lpat_value: Optional[np.ndarray] = None
+    lpat_leak: Optional[np.ndarray] = None   # float32 nW
 
 
 @dataclasses.dataclass
@@ -128,6 +139,77 @@ def make_library(seed: int, n_cells: int, i_max: int, n_slew: int = 7, n_load: i
                            _p(leak_base), _p(leak)), "library")
     return Library(n_cells, n_slew, n_load, n_inputs, slew_axis, load_axis, map_base, s2t, table_base,
                    tables, leak_base, leak)
+
+
+def add_pattern_cells(lib: Library, seed: int, wide_inputs=(), convert=(), all_pins: int = 0,
+                      n_pat=(2, 12), max_care: int = 4, leak_range=(1.0, 50.0)) -> Library:
+    """A copy of `lib` with cells given by state patterns: new cells with the
+    input counts in `wide_inputs` (appended, up to 31 inputs) and the existing
+    cells listed in `convert` (their per-state arrays stay but are unused).
+    Each cell gets 1 + U{n_pat} table patterns and as many leakage patterns
+    drawn the same way: every pattern but the last names 1..max_care random
+    state pins (value bits are random on every pin, named or not), the last
+    names none (the default). Table pattern k selects two new tables of the
+    cell (fall, rise), with entries of the same family as make_library's;
+    leakage values ~ U(leak_range) nW. numpy generator seeded with `seed`."""
+    rng = np.random.default_rng(seed)
+    ns, nl = lib.n_slew, lib.n_load
+    n_old = lib.n_cells
+    n_cells = n_old + len(wide_inputs)
+    n_inputs = np.concatenate([lib.n_inputs, np.asarray(wide_inputs, np.int32)]).astype(np.int32)
+    slew_axis = np.concatenate([lib.slew_axis] + [lib.slew_axis[:ns]] * len(wide_inputs)).astype(np.float32)
+    load_axis = np.concatenate([lib.load_axis] + [lib.load_axis[:nl]] * len(wide_inputs)).astype(np.float32)
+    map_base = np.concatenate([lib.map_base, np.zeros(len(wide_inputs), np.int64)])
+    leak_base = np.concatenate([lib.leak_base, np.zeros(len(wide_inputs), np.int64)])
+    table_base = np.concatenate([lib.table_base, np.zeros(len(wide_inputs), np.int64)])
+    tables = [lib.tables]
+    n_tab = lib.tables.size // (ns * nl)
+    n_tpat = np.zeros(n_cells, np.int32)
+    n_lpat = np.zeros(n_cells, np.int32)
+    tpat_base = np.zeros(n_cells, np.int64)
+    lpat_base = np.zeros(n_cells, np.int64)
+    tc, tv, tt, lc, lv, ll = [], [], [], [], [], []
+    patterned = list(convert) + list(range(n_old, n_cells))
+
+    def patterns(nsp, n):
+        care, value = [], []
+        for k in range(n):
+            c = 0
+            if k + 1 < n:
+                m = int(rng.integers(1, min(max_care, nsp) + 1))
+                for p in rng.choice(nsp, size=m, replace=False):
+                    c |= 1 << int(p)
+            care.append(c)
+            value.append(int(rng.integers(0, 1 << 32, dtype=np.uint64)) & 0xffffffff)
+        return care, value
+
+    for c in patterned:
+        nsp = int(n_inputs[c]) + all_pins
+        nt = 1 + int(rng.integers(n_pat[0], n_pat[1] + 1))
+        nlp = 1 + int(rng.integers(n_pat[0], n_pat[1] + 1))
+        tpat_base[c], lpat_base[c] = len(tc), len(lc)
+        n_tpat[c], n_lpat[c] = nt, nlp
+        care, value = patterns(nsp, nt)
+        tc += care
+        tv += value
+        tt += list(range(2 * nt))
+        care, value = patterns(nsp, nlp)
+        lc += care
+        lv += value
+        ll += list(rng.uniform(*leak_range, nlp))
+        table_base[c] = n_tab
+        sv = slew_axis[c * ns:(c + 1) * ns].astype(np.float64)[:, None] / 100.0
+        cv = load_axis[c * nl:(c + 1) * nl].astype(np.float64)[None, :] / 10.0
+        for _ in range(2 * nt):
+            e = rng.uniform(0.05, 2.0, 4)
+            tables.append((e[0] + e[1] * sv + e[2] * cv + e[3] * np.sqrt(sv * cv)).astype(np.float32).ravel())
+        n_tab += 2 * nt
+    return Library(n_cells, ns, nl, n_inputs, slew_axis, load_axis, map_base, lib.state_to_table, table_base,
+                   np.concatenate(tables).astype(np.float32), leak_base, lib.leak,
+                   n_tpat=n_tpat, tpat_base=tpat_base, tpat_care=np.asarray(tc, np.uint32),
+                   tpat_value=np.asarray(tv, np.uint32), tpat_table=np.asarray(tt, np.int16), n_lpat=n_lpat,
+                   lpat_base=lpat_base, lpat_care=np.asarray(lc, np.uint32), lpat_value=np.asarray(lv, np.uint32),
+                   lpat_leak=np.asarray(ll, np.float32))
 
 
 def make_netlist(seed: int, lib: Library, n_gates: int, load_range=(0.5, 50.0), n_pi: Optional[int] = None) -> Netlist:

@@ -83,14 +83,37 @@ def to_device_ctx(prob, algo=0, tile_log2=0, validate=True):
 
     dev = torch.device("cuda", 0)
     ctx = gtp.Context(0)
-    ctx.load_library(prob.lib)
+    ctx.load_library(prob.lib, all_pin_state=int(getattr(prob, "state_all_pins", 0)))
     net, ev = prob.net, prob.ev
     ctx.load_netlist(torch.from_numpy(net.gate_cell).to(dev), torch.from_numpy(net.gate_out_net).to(dev),
                      torch.from_numpy(net.gate_init.view(np.int32)).to(dev), net.n_nets)
     tens = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.gate_off, ev.t, ev.pin_bit, ev.slew)]
     ctx.load_events(*tens, t_end=ev.t_end, validate=validate)
-    ctx.set_params(vdd=prob.vdd, bin_ps=prob.bin_ps, sw_mode=prob.sw_mode)
+    ctx.set_params(vdd=prob.vdd, bin_ps=prob.bin_ps, sw_mode=prob.sw_mode,
+                   glitch_clk_ps=int(getattr(prob, "glitch_clk", 0)))
     ctx.set_tuning(algo=algo, bins_per_tile_log2=tile_log2)
     load = torch.from_numpy(net.net_load).to(dev)
     lam = torch.from_numpy(net.leak_scale).to(dev)
     return ctx, load, lam
+
+
+def all_pin_library(lib, seed=0):
+    """The library re-indexed over every pin (bit I = the output): the output
+    value selects a different table and scales the leakage, so the state the
+    output holds matters (same construction as the oracle pins use)."""
+    rng = np.random.default_rng(seed)
+    map_base, s2t, leak_base, leak = [], [], [], []
+    for c in range(lib.n_cells):
+        I = int(lib.n_inputs[c])
+        n_tab = 2 << I
+        map_base.append(len(s2t))
+        leak_base.append(len(leak))
+        for s in range(2 << I):
+            si, out = s & ((1 << I) - 1), s >> I
+            for d in range(2):
+                k = int(lib.state_to_table[lib.map_base[c] + 2 * si + d])
+                s2t.append(k if out == 0 else (k + 1) % n_tab)
+            leak.append(float(lib.leak[lib.leak_base[c] + si]) * (1.0 + out * float(rng.uniform(0.2, 1.0))))
+    return synth.Library(lib.n_cells, lib.n_slew, lib.n_load, lib.n_inputs, lib.slew_axis, lib.load_axis,
+                         np.array(map_base, np.int64), np.array(s2t, np.int16), lib.table_base, lib.tables,
+                         np.array(leak_base, np.int64), np.array(leak, np.float32))

@@ -63,3 +63,54 @@ def test_fixed_point_bits():
     with pytest.raises(gtp.GtpError) as ei:
         f(-1, 50, 1.0, 1.0, 1.0)
     assert ei.value.status == "INVALID_ARG"
+
+
+def test_expand_when_golden():
+    """The hand-computed state-pattern fixture through the host expansion."""
+    import json
+    with open(os.path.join(ROOT, "tests", "golden", "when_patterns.json")) as f:
+        fx = json.load(f)
+    out = gtp.expand_when(fx["n_pins"], fx["care"], fx["value"], [10, 11, 12], -5)
+    assert out.tolist() == [[10, 11, 12][k] for k in fx["expect_first_match"]]
+    p = fx["partial"]
+    out = gtp.expand_when(fx["n_pins"], p["care"], p["value"], [10, 11], -5)
+    assert out.tolist() == [-5 if k < 0 else [10, 11][k] for k in p["expect_first_match"]]
+
+
+@pytest.mark.parametrize("n_pins", [0, 1, 5, 9, 16])
+def test_expand_when_matches_pattern_scan(n_pins):
+    """Every entry of the expansion equals the item of the oracle's
+    first-match scan over the patterns (default where none matches)."""
+    import numpy as np
+
+    import oracle
+    O = oracle.get()
+    rng = np.random.default_rng(n_pins)
+    for trial in range(3):
+        n_pat = int(rng.integers(0, 12))
+        care = np.zeros(n_pat, np.uint32)
+        for k in range(n_pat):
+            for p in range(n_pins):
+                if rng.random() < min(0.5, 3.0 / max(n_pins, 1)):
+                    care[k] |= np.uint32(1 << p)
+        value = rng.integers(0, 1 << 32, n_pat, dtype=np.uint64).astype(np.uint32)
+        item = rng.integers(-100, 100, n_pat).astype(np.int32)
+        out = gtp.expand_when(n_pins, care, value, item, 7777)
+        states = range(1 << n_pins) if n_pins <= 9 else rng.integers(0, 1 << n_pins, 3000)
+        for s in states:
+            k = O.pattern_scan(care, value, int(s))
+            assert out[s] == (7777 if k < 0 else item[k]), (n_pins, trial, int(s))
+
+
+def test_expand_when_errors():
+    L = gtp.load_library()
+    import numpy as np
+    out = np.zeros(1 << 4, np.int32)
+    care = np.array([1 << 4], np.uint32)   # a pin above n_pins
+    z = np.zeros(1, np.uint32)
+    it = np.zeros(1, np.int32)
+    assert L.gtp_expand_when(4, 1, care.ctypes.data, z.ctypes.data, it.ctypes.data, 0, out.ctypes.data) == 1
+    assert L.gtp_expand_when(17, 0, None, None, None, 0, out.ctypes.data) == 1
+    assert L.gtp_expand_when(4, 1, None, None, None, 0, out.ctypes.data) == 1
+    assert L.gtp_expand_when(4, 0, None, None, None, 3, out.ctypes.data) == 0
+    assert out.tolist() == [3] * 16

@@ -17,7 +17,7 @@ from scipy.interpolate import RegularGridInterpolator
 
 import oracle
 import synth
-from _problems import GOLDEN, build_problem, load_golden
+from _problems import GOLDEN, all_pin_library, build_problem, load_golden
 
 pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
 
@@ -173,6 +173,30 @@ def pin_leakage_closed_form(O):
         assert abs(P[10] - 1e-6 * rate * 50 / 100) < 1e-13 * rate
 
 
+def _match(care, value, s):
+    """First pattern whose named pins all carry the values it gives, checked
+    pin by pin (-1: none)."""
+    for k in range(len(care)):
+        if all(((s >> p) & 1) == ((int(value[k]) >> p) & 1) for p in range(32) if (int(care[k]) >> p) & 1):
+            return k
+    return -1
+
+
+def _table_id(lib, c, s, d):
+    if lib.n_tpat is not None and lib.n_tpat[c] > 0:
+        b, n = int(lib.tpat_base[c]), int(lib.n_tpat[c])
+        k = _match(lib.tpat_care[b:b + n], lib.tpat_value[b:b + n], s)
+        return int(lib.tpat_table[2 * (b + k) + d])
+    return int(lib.state_to_table[lib.map_base[c] + 2 * s + d])
+
+
+def _leak_nw(lib, c, s):
+    if lib.n_tpat is not None and lib.n_tpat[c] > 0:
+        b, n = int(lib.lpat_base[c]), int(lib.n_lpat[c])
+        return float(lib.lpat_leak[b + _match(lib.lpat_care[b:b + n], lib.lpat_value[b:b + n], s)])
+    return float(lib.leak[lib.leak_base[c] + s])
+
+
 def _bruteforce(prob):
     """Plain-definition waveform and per-gate energies: dynamic energy of every
     event in its bin, and leakage integrated picosecond by picosecond at the
@@ -214,7 +238,7 @@ def _bruteforce(prob):
         for q in range(o1 - o0):
             t = int(ts[q])
             s = state_at(t, strict=True)  # state before the event's timestamp
-            k = int(lib.state_to_table[lib.map_base[c] + 2 * s + int(vals[q])])
+            k = _table_id(lib, c, s, int(vals[q]))
             Tab = lib.tables[(lib.table_base[c] + k) * ns * nl:(lib.table_base[c] + k + 1) * ns * nl]
             rgi = RegularGridInterpolator((sa, la), Tab.reshape(ns, nl).astype(float), method="linear",
                                           bounds_error=False, fill_value=None)
@@ -235,9 +259,12 @@ def _bruteforce(prob):
                 E[t // prob.bin_ps] += ei + es
                 GE[g, 1] += ei
                 GE[g, 2] += es
+        leak_of = {}
         for t in range(ev.t_end):
             s = state_at(t, strict=False)
-            e = lam * float(lib.leak[lib.leak_base[c] + s]) * 1e-6
+            if s not in leak_of:
+                leak_of[s] = _leak_nw(lib, c, s)
+            e = lam * leak_of[s] * 1e-6
             E[t // prob.bin_ps] += e
             GE[g, 0] += e
     return E, GE
@@ -245,28 +272,6 @@ def _bruteforce(prob):
 
 def _bruteforce_bins(prob):
     return _bruteforce(prob)[0]
-
-
-def all_pin_library(lib, seed=0):
-    """The library re-indexed over every pin (bit I = the output): the output
-    value selects a different table and scales the leakage, so the state the
-    output holds matters."""
-    rng = np.random.default_rng(seed)
-    map_base, s2t, leak_base, leak = [], [], [], []
-    for c in range(lib.n_cells):
-        I = int(lib.n_inputs[c])
-        n_tab = 2 << I   # the cell's tables, one per (input state, direction)
-        map_base.append(len(s2t))
-        leak_base.append(len(leak))
-        for s in range(2 << I):
-            si, out = s & ((1 << I) - 1), s >> I
-            for d in range(2):
-                k = int(lib.state_to_table[lib.map_base[c] + 2 * si + d])
-                s2t.append(k if out == 0 else (k + 1) % n_tab)
-            leak.append(float(lib.leak[lib.leak_base[c] + si]) * (1.0 + out * float(rng.uniform(0.2, 1.0))))
-    return synth.Library(lib.n_cells, lib.n_slew, lib.n_load, lib.n_inputs, lib.slew_axis, lib.load_axis,
-                         np.array(map_base, np.int64), np.array(s2t, np.int16), lib.table_base, lib.tables,
-                         np.array(leak_base, np.int64), np.array(leak, np.float32))
 
 
 def pin_bruteforce_random(O):
@@ -289,6 +294,38 @@ def pin_bruteforce_random(O):
             assert tmax == int(prob.ev.t.max())
             if T:
                 assert GEbf[:, 3].sum() > 0, "the case holds glitches"
+
+
+def pin_when_golden(O):
+    """Hand-computed first-match items of the state-pattern fixture."""
+    with open(os.path.join(GOLDEN, "when_patterns.json")) as f:
+        fx = json.load(f)
+    for case in (fx, fx["partial"]):
+        got = [O.pattern_scan(case["care"], case["value"], st) for st in range(1 << fx["n_pins"])]
+        assert got == case["expect_first_match"], got
+
+
+def pin_patterns_random(O):
+    """Random tiny problems whose cells are given by state patterns (two cells
+    converted, two wide cells of 9 and 11 inputs) against the brute-force
+    definition with the pin-by-pin pattern match; state over the inputs and
+    over every pin, with and without glitch detection."""
+    for seed, allp, T in ((11, 0, 0), (12, 1, 0), (13, 0, 120), (14, 1, 90)):
+        prob = synth.make_random_small(seed, n_gates=6, n_cells=3, i_max=3, n_events=70, t_end=600, bin_ps=60,
+                                       p_tie=0.3)
+        if allp:
+            prob.lib = all_pin_library(prob.lib, seed)
+        lib = synth.add_pattern_cells(prob.lib, seed, wide_inputs=(9, 11), convert=(0, 2), all_pins=allp,
+                                      n_pat=(1, 5), max_care=2)
+        net = synth.make_netlist(seed, lib, 8)
+        counts, clk = synth.make_counts(seed, 8, 0, 0, "lognormal", 1.0, 1.0, 90, 600)
+        prob = synth.Problem(lib, net, synth.make_events(seed, lib, net, counts, clk, 600, 1000, p_tie=0.3),
+                             vdd=0.8, bin_ps=60, state_all_pins=allp, glitch_clk=T)
+        assert set(net.gate_cell.tolist()) & {0, 2, 3, 4}, "patterned cells are used"
+        Ebf, GEbf = _bruteforce(prob)
+        np.testing.assert_allclose(O.forward(prob), Ebf, rtol=1e-9, atol=1e-12)
+        GE, _ = O.gate_report(prob)
+        np.testing.assert_allclose(GE, GEbf, rtol=1e-9, atol=1e-12)
 
 
 def pin_state_enumeration(O):
@@ -380,7 +417,8 @@ def pin_euler_identity(O):
 
 
 PINS = [pin_golden_a, pin_golden_b, pin_golden_c, pin_bin_index, pin_interp, pin_switching, pin_leakage_closed_form,
-        pin_bruteforce_random, pin_state_enumeration, pin_energy_invariant, pin_adjoint_fd, pin_euler_identity]
+        pin_bruteforce_random, pin_state_enumeration, pin_energy_invariant, pin_adjoint_fd, pin_euler_identity,
+        pin_when_golden, pin_patterns_random]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
@@ -481,7 +519,8 @@ def O_free_validate(prob):
 PLANTS = {1: "intermediate state in a group", 2: "transposed table", 3: "switching 2x", 4: "leak after-state",
           5: "rounded bin", 6: "tail leakage dropped", 7: "wrong direction table", 9: "switching term dropped in grad",
           10: "partial bins dropped in grad", 11: "glitch ratio without the factor 2",
-          12: "glitch energy unscaled in the waveform", 13: "output left out of an all-pin state"}
+          12: "glitch energy unscaled in the waveform", 13: "output left out of an all-pin state",
+          14: "pattern value bits outside its care pins compared"}
 
 
 @pytest.mark.parametrize("plant", sorted(PLANTS), ids=[PLANTS[k] for k in sorted(PLANTS)])
