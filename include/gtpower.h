@@ -404,6 +404,46 @@ gtp_status gtp_gate_report(gtp_ctx ctx, const float* net_load_ff, const float* l
                            double* gate_energy_fj, double* totals);
 
 /*
+ * Streamed evaluation of one trace larger than device memory (Sec. 5: the
+ * events are split into chunks that fit the GPU, and the next chunk is made
+ * ready while the GPU works on the current one). The trace [0, t_end) is cut
+ * at times 0 = t_0 < t_1 < ... < t_K = t_end; window k holds every event with
+ * t_k <= t < t_{k+1}, as a gate-major CSR over all gates of the netlist with
+ * absolute times (the layout of gtp_load_events; its t_end_ps is not used).
+ * Each cut is a multiple of bin_ps, and of glitch_clk_ps when glitch
+ * detection is on, so every bin and every clock cycle lies inside one window.
+ * The library carries every gate's pin values from one window into the next,
+ * so the result is the waveform of the whole trace (each window's bins are
+ * evaluated with the fixed-point exponent its own events allow).
+ *
+ *   gtp_stream_begin  opens a stream of t_end_ps (library, netlist and
+ *       parameters loaded; the loaded events are dropped). validate = 1
+ *       checks every window's events as gtp_load_events does (an error ends
+ *       the stream). While a stream is open every other call on ctx returns
+ *       GTP_ERR_INVALID_ARG.
+ *   gtp_stream_push   enqueues the copy of the next window's HOST arrays
+ *       (pinned memory lets the copy overlap the GPU work) into one of two
+ *       device staging slots, on a copy stream of the library; at most two
+ *       windows are pending. Waits only for the window that last used the
+ *       slot. The host arrays must stay unchanged until the gtp_stream_step
+ *       that evaluates the window returns.
+ *   gtp_stream_step   evaluates the oldest pending window and writes its bins
+ *       [t_k / bin_ps, ceil(t_{k+1} / bin_ps)) of power_mw (DEVICE,
+ *       ceil(t_end / bin_ps) floats for the whole trace); net_load_ff and
+ *       leak_scale as in gtp_forward. The copy of a window pushed before the
+ *       step overlaps it.
+ *   gtp_stream_end    closes the stream (pending windows are dropped) and
+ *       restores the netlist's initial pin values.
+ * Errors: GTP_ERR_INVALID_ARG for cuts out of order or off the bin (clock)
+ * grid, a third pending window, a window gate_off that does not run from 0
+ * to its n_events; GTP_ERR_NOT_LOADED without an open stream.
+ */
+gtp_status gtp_stream_begin(gtp_ctx ctx, int64_t t_end_ps, int32_t validate);
+gtp_status gtp_stream_push(gtp_ctx ctx, const gtp_events* window_host, int64_t t0_ps, int64_t t1_ps);
+gtp_status gtp_stream_step(gtp_ctx ctx, const float* net_load_ff, const float* leak_scale, float* power_mw);
+gtp_status gtp_stream_end(gtp_ctx ctx);
+
+/*
  * Per-event trace of the state tracking (DEVICE outputs, [n_events]):
  * state_before[e] = input state of e's gate before e's timestamp group
  * (the state every event of the group is looked up with, Algorithm 1),

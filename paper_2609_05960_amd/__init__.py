@@ -39,7 +39,8 @@ ABI_SYMBOLS = ["gtp_create", "gtp_destroy", "gtp_set_stream", "gtp_last_error", 
                "gtp_set_tuning", "gtp_get_tuning", "gtp_plan_info", "gtp_autotune", "gtp_load_traces",
                "gtp_batch_bins", "gtp_forward_batched", "gtp_forward_trace", "gtp_forward", "gtp_adjoint", "gtp_debug_event_trace",
                "gtp_device_bytes", "gtp_profile_enable", "gtp_profile_read", "gtp_fixed_point_bits",
-               "gtp_forward_noalloc", "gtp_gate_report", "gtp_expand_when"]
+               "gtp_forward_noalloc", "gtp_gate_report", "gtp_expand_when", "gtp_stream_begin", "gtp_stream_push",
+               "gtp_stream_step", "gtp_stream_end"]
 
 
 def build(out: Optional[str] = None) -> str:
@@ -117,6 +118,19 @@ def fixed_point_bits(max_bin_events: int, bin_ps: int, event_energy_fj: float, l
     return m.value
 
 
+def _host(a, dtype):
+    """(address, length, keep-alive) of a host array: a numpy array or a CPU
+    tensor (pinned or not) of the given dtype, contiguous."""
+    if hasattr(a, "data_ptr"):
+        if a.device.type != "cpu" or not a.is_contiguous():
+            raise ValueError("stream windows are contiguous host arrays")
+        if a.element_size() != np.dtype(dtype).itemsize:
+            raise ValueError(f"window array of element size {a.element_size()}, want {np.dtype(dtype).itemsize}")
+        return a.data_ptr(), a.numel(), a
+    a = np.ascontiguousarray(a, dtype)
+    return a.ctypes.data, a.size, a
+
+
 def expand_when(n_pins: int, care, value, item, default_item: int) -> np.ndarray:
     """Per-state item array of state patterns with don't-care pins
     (gtp_expand_when): entry s holds the item of the first pattern whose
@@ -168,6 +182,8 @@ def load_library(path: Optional[str] = None):
         "gtp_debug_event_trace": [vp, vp, vp],
         "gtp_fixed_point_bits": [ctypes.POINTER(_Range), ctypes.POINTER(ctypes.c_int32)],
         "gtp_expand_when": [i32, i32, vp, vp, vp, i32, vp],
+        "gtp_stream_begin": [vp, i64, i32], "gtp_stream_push": [vp, ctypes.POINTER(_Events), i64, i64],
+        "gtp_stream_step": [vp, vp, vp, vp], "gtp_stream_end": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -420,6 +436,42 @@ class Context:
         out = self._out(out, self.n_bins)
         self._chk(self.L.gtp_forward(self.h, _dptr(net_load), _dptr(leak_scale), _dptr(out)))
         return out
+
+    # -- streamed windows ----------------------------------------------------
+    def stream_begin(self, t_end: int, validate: bool = False):
+        """gtp_stream_begin: evaluate one trace of t_end ps window by window;
+        returns the FP32 power tensor of the whole trace the steps fill."""
+        self._chk(self.L.gtp_stream_begin(self.h, int(t_end), 1 if validate else 0))
+        self._stream = {"n_bins": -(-int(t_end) // self.bin_ps), "pending": []}
+        t = self.torch
+        return t.empty(self._stream["n_bins"], dtype=t.float32, device=self.device)
+
+    def stream_push(self, gate_off, t_ps, pin_bit, slew_ps, t0: int, t1: int):
+        """gtp_stream_push: host arrays of the window [t0, t1) (numpy, or
+        pinned CPU tensors); kept alive here until their window is stepped."""
+        arrs = [_host(a, dt) for a, dt in ((gate_off, np.int64), (t_ps, np.int64), (pin_bit, np.uint8),
+                                           (slew_ps, np.float32))]
+        E = _Events()
+        E.n_events, E.t_end_ps = int(arrs[1][1]), int(t1)
+        E.gate_off, E.t_ps, E.pin_bit, E.slew_ps = (a[0] for a in arrs)
+        self._chk(self.L.gtp_stream_push(self.h, ctypes.byref(E), int(t0), int(t1)))
+        self._stream["pending"].append(arrs)
+
+    def stream_step(self, net_load, leak_scale, out):
+        """gtp_stream_step: evaluate the oldest pushed window into out."""
+        net_load = self._vec(net_load, self.n_nets, "net_load")
+        leak_scale = self._vec(leak_scale, self.n_gates, "leak_scale")
+        out = self._out(out, self._stream["n_bins"])
+        try:
+            self._chk(self.L.gtp_stream_step(self.h, _dptr(net_load), _dptr(leak_scale), _dptr(out)))
+        finally:
+            if self._stream["pending"]:
+                self._stream["pending"].pop(0)
+        return out
+
+    def stream_end(self):
+        self._chk(self.L.gtp_stream_end(self.h))
+        self._stream = None
 
     def forward_noalloc(self, net_load, leak_scale=None, out=None):
         """gtp_forward_noalloc: the forward without device allocation (the packed

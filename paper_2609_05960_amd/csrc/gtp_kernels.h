@@ -1488,6 +1488,37 @@ __global__ void __launch_bounds__(kFwdThreads) k_validate(ValArgs a) {
   if (vis.best != ~0ull) atomicMin(a.first, vis.best);
 }
 
+// ---------------------------------------------------------------------------
+// streamed windows
+// ---------------------------------------------------------------------------
+// Times of a window's events made relative to the window start.
+__global__ void __launch_bounds__(256) k_shift_times(int64_t* t, int64_t n, int64_t t0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] -= t0;
+}
+
+// The pin values every gate carries out of a window: each lane block XORs the
+// toggles of each gate it holds and applies them to that gate's carried
+// values (one atomic per gate and block).
+struct CarryVisitor {
+  uint32_t* init;
+  uint32_t x = 0;
+  __device__ __forceinline__ void begin_gate(int64_t, uint32_t) { x = 0; }
+  __device__ __forceinline__ void end_gate(int64_t g) {
+    if (x) atomicXor(&init[g], x);
+  }
+  __device__ __forceinline__ void event(int64_t, int64_t, int pin, int, float, uint32_t, uint32_t) {
+    x ^= 1u << (pin & 31);
+  }
+};
+
+__global__ void __launch_bounds__(kFwdThreads) k_stream_carry(EvView ev, const uint2* plan, uint32_t* init) {
+  const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  CarryVisitor vis;
+  vis.init = init;
+  walk_block(kb, ev, plan, vis);
+}
+
 // per-event trace without the tiled records (one lane block per thread)
 struct TraceArgs {
   EvView ev;

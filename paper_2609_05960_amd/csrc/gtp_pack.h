@@ -83,6 +83,7 @@ struct PackIn {
   Workspace* ws = nullptr;        // [2] temporaries (caller-owned)
   int64_t glitch_clk = 0;         // > 0: per-event glitch factors for this clock period
   bool wide_cells = false;        // some cell has more than 8 state pins (its units carry every pin value)
+  Workspace* arena = nullptr;     // optional: output arrays carved from it while it has room
 };
 
 struct PackOut {
@@ -129,6 +130,9 @@ struct PackOut {
   int64_t max_bin_events = 0;
   float alpha_span = 1.0f;
   int32_t mfix = 0;                // fixed-point exponent chosen for this layout (set by the ctx)
+  char* arena_lo = nullptr;        // the arena the output arrays were carved from (not freed by pack_free)
+  size_t arena_len = 0;
+  size_t need_bytes = 0;           // bytes of all output arrays (an arena of this size holds them all)
 };
 
 // Builds the packed layout on in.stream (synchronises it). Returns

@@ -592,8 +592,10 @@ int64_t scan_sums_items(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1;
 void pack_free(PackOut* o) {
   void* ps[] = {o->w32,  o->row,  o->alpha, o->rgl,       o->desc,   o->grp_off, o->tile_grp, o->gperm,
                 o->gcell, o->gout, o->ginit, o->reg_first, o->tfirst, o->phases,  o->ph_off};
-  for (void* p : ps)
-    if (p) (void)hipFree(p);
+  for (void* p : ps) {
+    const char* q = static_cast<const char*>(p);
+    if (p && !(o->arena_lo && q >= o->arena_lo && q < o->arena_lo + o->arena_len)) (void)hipFree(p);
+  }
   *o = PackOut();
 }
 
@@ -626,10 +628,23 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     }                                                                              \
   } while (0)
 
-  // owned output arrays
+  // owned output arrays: carved from the arena while it has room, else
+  // allocated (and freed by pack_free)
+  size_t arena_used = 0;
+  if (in.arena && in.arena->p) {
+    o.arena_lo = static_cast<char*>(in.arena->p);
+    o.arena_len = in.arena->bytes;
+  }
   auto own = [&](size_t bytes, hipError_t& e) -> void* {
     void* p = nullptr;
-    bytes = std::max<size_t>(bytes, 256);
+    bytes = align256(std::max<size_t>(bytes, 256));
+    o.need_bytes += bytes;
+    if (o.arena_lo && arena_used + bytes <= o.arena_len) {
+      p = o.arena_lo + arena_used;
+      arena_used += bytes;
+      e = hipSuccess;
+      return p;
+    }
     e = hipMalloc(&p, bytes);
     if (e == hipSuccess) held += (int64_t)bytes;
     return p;

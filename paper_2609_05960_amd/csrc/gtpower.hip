@@ -98,6 +98,8 @@ struct gtp_ctx_s {
   std::vector<int32_t> h_nin;
   std::vector<int32_t> h_cq_lo, h_cq_hi;   // per cell: quad index range of its tables
   std::vector<int32_t> h_gate_cell;  // host copy of the netlist's cells
+  Workspace pk_arena{nullptr, 0};    // output arrays of the single-trace layout
+  size_t pk_arena_want = 0;          // the largest layout's bytes so far
   DevBuf lib_img;             // meta | leak | map_q | slew | slew_inv
   DevBuf load_axis, load_inv, quads;
   DevBuf wide_cell, wide_pat, wide_sipl;   // cells with more than 8 state pins
@@ -138,6 +140,21 @@ struct gtp_ctx_s {
   DevBuf b_tab, b_items, b_queue, b_fin, b_X, b_S, b_exS;
   DevBuf tun_in, tun_out;  // autotuner inputs and output
   hipStream_t cap_stream = nullptr;
+
+  // streamed windows (gtp_stream_*): two staging slots filled on copy_stream
+  struct StreamSlot {
+    DevBuf gate_off, t, pb, slew;
+    int64_t n = 0, t0 = 0, t1 = 0;
+    hipEvent_t copied = nullptr, done = nullptr;
+    bool used = false;   // done has been recorded
+  };
+  StreamSlot st_slot[2];
+  hipStream_t copy_stream = nullptr;
+  bool st_on = false, st_inside = false;
+  int32_t st_validate = 0;
+  int64_t st_end = 0, st_next_push = 0, st_next_step = 0;
+  int st_head = 0, st_pending = 0;
+  DevBuf st_init;   // the netlist's initial pin values while a stream carries its own
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   const void* gkey[3] = {nullptr, nullptr, nullptr};
@@ -398,6 +415,8 @@ Div32 make_div32(uint32_t d) {
 
 gtp_status need(gtp_ctx c, bool lib, bool net, bool ev, bool par) {
   if (!c) return GTP_ERR_INVALID_ARG;
+  if (c->st_on && !c->st_inside)
+    return fail(c, GTP_ERR_INVALID_ARG, "a stream is open: only gtp_stream_push/step/end until gtp_stream_end");
   if (lib && !c->lib_ok) return fail(c, GTP_ERR_NOT_LOADED, "no library loaded");
   if (net && !c->net_ok) return fail(c, GTP_ERR_NOT_LOADED, "no netlist loaded");
   if (ev && !c->ev_ok) return fail(c, GTP_ERR_NOT_LOADED, "no events loaded");
@@ -568,7 +587,7 @@ gtp_status choose_mfix(gtp_ctx c, const PackOut& pk, int64_t bin_ps, int32_t* m)
 // sets B.tile_log2 / B.n_tiles.
 gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, BinSpec& B, PackOut& pk, double& pack_ms,
                     int32_t* dbg_state = nullptr, int64_t* dbg_bin = nullptr,
-                    const std::vector<int64_t>* gate_weight = nullptr) {
+                    const std::vector<int64_t>* gate_weight = nullptr, Workspace* arena = nullptr) {
   if (B.r_bits > kTimeBits) return fail(c, GTP_ERR_UNSUPPORTED, "bin width above 2^%d ps", kTimeBits);
   int lb = c->tun.bins_per_tile_log2 ? c->tun.bins_per_tile_log2 : auto_tile_log2(B.n_bins, B.r_bits, c->n_cu);
   if (lb + B.r_bits > kTimeBits)
@@ -604,6 +623,7 @@ gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, Bin
   in.ws = c->pk_ws;
   in.glitch_clk = c->par.glitch_clk_ps;
   in.wide_cells = c->has_wide;
+  in.arena = arena;
   const size_t ws_before = c->pk_ws[0].bytes + c->pk_ws[1].bytes;
   char msg[256] = {0};
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -636,10 +656,35 @@ gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, Bin
   return GTP_OK;
 }
 
+// The single-trace layout's output arrays come from an arena sized by the
+// largest earlier layout, so rebuilding the layout (new events, or the next
+// window of a stream) allocates and frees nothing once it has grown; the
+// arena is grown only here, after drop_pack has waited for every kernel that
+// read the previous layout.
+gtp_status grow_pack_arena(gtp_ctx c) {
+  if (c->pk_arena_want <= c->pk_arena.bytes) return GTP_OK;
+  const size_t want = c->pk_arena_want + c->pk_arena_want / 8;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->pk_arena.p) (void)hipFree(c->pk_arena.p);
+  c->dev_bytes -= (int64_t)c->pk_arena.bytes;
+  c->pk_arena = Workspace{nullptr, 0};
+  if (hipMalloc(&c->pk_arena.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    c->pk_arena = Workspace{nullptr, 0};
+    c->pk_arena_want = 0;   // fall back to per-array allocations
+    return GTP_OK;
+  }
+  c->pk_arena.bytes = want;
+  c->dev_bytes += (int64_t)want;
+  return GTP_OK;
+}
+
 gtp_status build_pack(gtp_ctx c) {
   if (c->pack_ok) return GTP_OK;
   drop_pack(c);
-  TRY(pack_for(c, c->ev, c->plan_blk, c->bins, c->pk, c->pack_ms));
+  TRY(grow_pack_arena(c));
+  TRY(pack_for(c, c->ev, c->plan_blk, c->bins, c->pk, c->pack_ms, nullptr, nullptr, nullptr, &c->pk_arena));
+  c->pk_arena_want = std::max(c->pk_arena_want, c->pk.need_bytes);
   c->pack_ok = true;
   return GTP_OK;
 }
@@ -909,6 +954,15 @@ gtp_status gtp_destroy(gtp_ctx c) {
   drop_batch(c);
   for (Workspace& w : c->pk_ws)
     if (w.p) (void)hipFree(w.p);
+  if (c->pk_arena.p) (void)hipFree(c->pk_arena.p);
+  if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
+  for (auto& sl : c->st_slot) {
+    for (DevBuf* b : {&sl.gate_off, &sl.t, &sl.pb, &sl.slew}) release(c, *b);
+    if (sl.copied) (void)hipEventDestroy(sl.copied);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+  }
+  release(c, c->st_init);
+  if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   DevBuf* all[] = {&c->lib_img, &c->load_axis, &c->load_inv, &c->quads, &c->wide_cell, &c->wide_pat, &c->wide_sipl,
                    &c->gate_cell, &c->gate_out,
@@ -2366,6 +2420,152 @@ gtp_status gtp_profile_read(gtp_ctx c, int32_t cap, const char** names, int64_t*
     total_ms[i] = ms[i];
   }
   *n_out = n;
+  return GTP_OK;
+}
+
+// ---- streamed windows (chunked evaluation of a long trace) ----------------
+
+}  // extern "C"
+
+namespace {
+// Evaluates the window held by slot sl: times made relative to its start, its
+// lane-block plan, the forward into its bins of the trace's power array, then
+// the pin values every gate carries out of it (into the netlist's initial
+// values, which the next window starts from).
+template <class Slot>
+gtp_status stream_window(gtp_ctx c, Slot& sl, const float* net_load_ff, const float* leak_scale, float* power_mw) {
+  if (sl.n > 0)
+    LAUNCH(c, "k_shift_times", k_shift_times, dim3(grid_for(sl.n, 256)), dim3(256), 0, ptr<int64_t>(sl.t), sl.n, sl.t0);
+  gtp_events ev;
+  ev.n_events = sl.n;
+  ev.t_end_ps = sl.t1 - sl.t0;
+  ev.gate_off = ptr<int64_t>(sl.gate_off);
+  ev.t_ps = ptr<int64_t>(sl.t);
+  ev.pin_bit = ptr<uint8_t>(sl.pb);
+  ev.slew_ps = ptr<float>(sl.slew);
+  c->ev = ev;
+  c->ev_ok = false;
+  drop_pack(c);
+  TRY(build_block_plan(c));
+  c->ev_ok = true;
+  c->bins = bins_for(c, ev.t_end_ps);
+  if (c->st_validate) TRY(validate_events(c, ev, c->plan_blk, c->n_blocks));
+  TRY(gtp_forward(c, net_load_ff, leak_scale, power_mw + sl.t0 / c->par.bin_ps));
+  if (c->n_blocks > 0)
+    LAUNCH(c, "k_stream_carry", k_stream_carry, dim3(grid_for(c->n_blocks, kFwdThreads)), dim3(kFwdThreads), 0,
+           ev_view(c), (const uint2*)ptr<uint2>(c->plan_blk), ptr<uint32_t>(c->gate_init));
+  return GTP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+gtp_status gtp_stream_begin(gtp_ctx c, int64_t t_end_ps, int32_t validate) {
+  TRY(need(c, true, true, false, true));
+  if (t_end_ps < 1 || (validate != 0 && validate != 1))
+    return fail(c, GTP_ERR_INVALID_ARG, "stream of %lld ps, validate %d", (long long)t_end_ps, validate);
+  HIPCHK(c, hipSetDevice(c->dev));
+  if (!c->copy_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+  for (auto& sl : c->st_slot) {
+    if (!sl.copied) HIPCHK(c, hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming));
+    if (!sl.done) HIPCHK(c, hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    sl.used = false;
+  }
+  c->ev_ok = false;
+  drop_pack(c);
+  drop_graph(c);
+  const size_t gb = (size_t)std::max<int64_t>(c->n_gates, 1) * 4;
+  TRY(ensure(c, c->st_init, gb));
+  HIPCHK(c, hipMemcpyAsync(c->st_init.p, c->gate_init.p, gb, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->st_on = true;
+  c->st_validate = validate;
+  c->st_end = t_end_ps;
+  c->st_next_push = c->st_next_step = 0;
+  c->st_head = c->st_pending = 0;
+  return GTP_OK;
+}
+
+gtp_status gtp_stream_push(gtp_ctx c, const gtp_events* ev, int64_t t0_ps, int64_t t1_ps) {
+  if (!c || !ev) return GTP_ERR_INVALID_ARG;
+  if (!c->st_on) return fail(c, GTP_ERR_NOT_LOADED, "no stream open (gtp_stream_begin)");
+  if (c->st_pending >= 2) return fail(c, GTP_ERR_INVALID_ARG, "two windows are pending: gtp_stream_step first");
+  const int64_t D = c->par.bin_ps, clk = c->par.glitch_clk_ps;
+  if (t0_ps != c->st_next_push || t1_ps <= t0_ps || t1_ps > c->st_end)
+    return fail(c, GTP_ERR_INVALID_ARG, "window [%lld, %lld): windows must tile [0, %lld) in order (next starts at %lld)",
+                (long long)t0_ps, (long long)t1_ps, (long long)c->st_end, (long long)c->st_next_push);
+  if (t0_ps % D != 0 || (t1_ps % D != 0 && t1_ps != c->st_end))
+    return fail(c, GTP_ERR_INVALID_ARG, "window cuts must be multiples of the %lld ps bin", (long long)D);
+  if (clk > 0 && (t0_ps % clk != 0 || (t1_ps % clk != 0 && t1_ps != c->st_end)))
+    return fail(c, GTP_ERR_INVALID_ARG, "window cuts must be multiples of the %lld ps glitch clock", (long long)clk);
+  const int64_t N = ev->n_events, G = c->n_gates;
+  if (N < 0 || !ev->gate_off || (N > 0 && (!ev->t_ps || !ev->pin_bit || !ev->slew_ps)))
+    return fail(c, GTP_ERR_INVALID_ARG, "window event arrays");
+  if (ev->gate_off[0] != 0 || ev->gate_off[G] != N)
+    return fail(c, GTP_ERR_INVALID_ARG, "window gate_off must run from 0 to n_events");
+  for (int64_t g = 0; g < G; ++g)
+    if (ev->gate_off[g + 1] < ev->gate_off[g]) return fail(c, GTP_ERR_INVALID_ARG, "window gate_off decreases at %lld",
+                                                          (long long)g);
+  HIPCHK(c, hipSetDevice(c->dev));
+  auto& sl = c->st_slot[(c->st_head + c->st_pending) % 2];
+  if (sl.used) HIPCHK(c, hipEventSynchronize(sl.done));   // the window that last used the slot is done
+  TRY(ensure(c, sl.gate_off, (size_t)(G + 1) * 8));
+  TRY(ensure(c, sl.t, (size_t)std::max<int64_t>(N, 1) * 8));
+  TRY(ensure(c, sl.pb, (size_t)((std::max<int64_t>(N, 1) + 15) & ~(int64_t)15)));
+  TRY(ensure(c, sl.slew, (size_t)std::max<int64_t>(N, 1) * 4));
+  HIPCHK(c, hipMemcpyAsync(sl.gate_off.p, ev->gate_off, (size_t)(G + 1) * 8, hipMemcpyHostToDevice, c->copy_stream));
+  if (N > 0) {
+    HIPCHK(c, hipMemcpyAsync(sl.t.p, ev->t_ps, (size_t)N * 8, hipMemcpyHostToDevice, c->copy_stream));
+    HIPCHK(c, hipMemcpyAsync(sl.pb.p, ev->pin_bit, (size_t)N, hipMemcpyHostToDevice, c->copy_stream));
+    HIPCHK(c, hipMemcpyAsync(sl.slew.p, ev->slew_ps, (size_t)N * 4, hipMemcpyHostToDevice, c->copy_stream));
+  }
+  HIPCHK(c, hipEventRecord(sl.copied, c->copy_stream));
+  sl.n = N;
+  sl.t0 = t0_ps;
+  sl.t1 = t1_ps;
+  c->st_pending += 1;
+  c->st_next_push = t1_ps;
+  return GTP_OK;
+}
+
+gtp_status gtp_stream_step(gtp_ctx c, const float* net_load_ff, const float* leak_scale, float* power_mw) {
+  if (!c) return GTP_ERR_INVALID_ARG;
+  if (!c->st_on) return fail(c, GTP_ERR_NOT_LOADED, "no stream open (gtp_stream_begin)");
+  if (c->st_pending == 0) return fail(c, GTP_ERR_INVALID_ARG, "no window pushed");
+  if (!net_load_ff || !power_mw) return fail(c, GTP_ERR_INVALID_ARG, "null stream argument");
+  HIPCHK(c, hipSetDevice(c->dev));
+  auto& sl = c->st_slot[c->st_head];
+  // the caller's host arrays are free once the copy is done
+  HIPCHK(c, hipEventSynchronize(sl.copied));
+  HIPCHK(c, hipStreamWaitEvent(c->stream, sl.copied, 0));
+  c->st_inside = true;
+  const gtp_status st = stream_window(c, sl, net_load_ff, leak_scale, power_mw);
+  c->st_inside = false;
+  if (st != GTP_OK) {
+    // the carried values are no longer those of a window boundary: end the stream
+    (void)gtp_stream_end(c);
+    return st;
+  }
+  HIPCHK(c, hipEventRecord(sl.done, c->stream));
+  sl.used = true;
+  c->st_head = (c->st_head + 1) % 2;
+  c->st_pending -= 1;
+  c->st_next_step = sl.t1;
+  return GTP_OK;
+}
+
+gtp_status gtp_stream_end(gtp_ctx c) {
+  if (!c) return GTP_ERR_INVALID_ARG;
+  if (!c->st_on) return GTP_OK;
+  HIPCHK(c, hipSetDevice(c->dev));
+  if (c->copy_stream) HIPCHK(c, hipStreamSynchronize(c->copy_stream));
+  const size_t gb = (size_t)std::max<int64_t>(c->n_gates, 1) * 4;
+  HIPCHK(c, hipMemcpyAsync(c->gate_init.p, c->st_init.p, gb, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->st_on = false;
+  c->st_pending = 0;
+  c->ev_ok = false;
+  drop_pack(c);
   return GTP_OK;
 }
 

@@ -259,6 +259,29 @@ def make_events(seed: int, lib: Library, net: Netlist, counts: np.ndarray, is_cl
     return Events(N, t_end, gate_off, t, pin_bit, slew)
 
 
+def window(ev: Events, t0: int, t1: int, out=None):
+    """The events of ev with t0 <= t < t1 as a gate-major CSR (absolute
+    times): (gate_off, t, pin_bit, slew). `out` may give the four arrays to
+    fill (e.g. views of pinned buffers, each large enough); the returned
+    arrays are then views of them."""
+    L = _load()
+    G = len(ev.gate_off) - 1
+    off = np.empty(G + 1, np.int64) if out is None else out[0][:G + 1]
+    n = ctypes.c_int64()
+    _check(L.synth_window(ctypes.c_int64(G), _p(ev.gate_off), _p(ev.t), _p(ev.pin_bit), _p(ev.slew),
+                          ctypes.c_int64(t0), ctypes.c_int64(t1), _p(off), None, None, None, ctypes.byref(n)),
+           "window count")
+    m = n.value
+    if out is None:
+        t, pb, sl = np.empty(m, np.int64), np.empty(m, np.uint8), np.empty(m, np.float32)
+    else:
+        t, pb, sl = out[1][:m], out[2][:m], out[3][:m]
+    _check(L.synth_window(ctypes.c_int64(G), _p(ev.gate_off), _p(ev.t), _p(ev.pin_bit), _p(ev.slew),
+                          ctypes.c_int64(t0), ctypes.c_int64(t1), _p(off), _p(t), _p(pb), _p(sl), ctypes.byref(n)),
+           "window")
+    return off, t, pb, sl
+
+
 # Named configurations (sizes of the synthetic workloads; recipe in DESIGN.md).
 CONFIGS = {
     # 1k gates, 8 cells (1-3 inputs), 100k events over 1,000 cycles of 1 ns,

@@ -286,3 +286,42 @@ int synth_draws(uint64_t seed, uint64_t stream, uint64_t start, int64_t n, uint6
   for (int64_t i = 0; i < n; ++i) out[i] = draw(seed, stream, start + (uint64_t)i);
   return SYN_OK;
 }
+
+/*
+ * Time window [t0, t1) of a gate-major CSR trace (times sorted within each
+ * gate): out_off[G+1] and the window's events (absolute times), in gate
+ * order. Pass out arrays NULL to get only out_off (the count); *n_out = the
+ * window's events.
+ */
+static int64_t lower_bound_t(const int64_t* t, int64_t lo, int64_t hi, int64_t x) {
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (t[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+int synth_window(int64_t n_gates, const int64_t* gate_off, const int64_t* t, const uint8_t* pin_bit,
+                 const float* slew, int64_t t0, int64_t t1, int64_t* out_off, int64_t* out_t, uint8_t* out_pb,
+                 float* out_slew, int64_t* n_out) {
+  if (n_gates < 0 || t1 < t0 || !gate_off || !out_off) return SYN_ERR_ARG;
+  out_off[0] = 0;
+#pragma omp parallel for schedule(static)
+  for (int64_t g = 0; g < n_gates; ++g) {
+    int64_t a = lower_bound_t(t, gate_off[g], gate_off[g + 1], t0);
+    int64_t b = lower_bound_t(t, a, gate_off[g + 1], t1);
+    out_off[g + 1] = b - a;
+  }
+  for (int64_t g = 0; g < n_gates; ++g) out_off[g + 1] += out_off[g];
+  if (n_out) *n_out = out_off[n_gates];
+  if (!out_t) return SYN_OK;
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t g = 0; g < n_gates; ++g) {
+    int64_t a = lower_bound_t(t, gate_off[g], gate_off[g + 1], t0);
+    int64_t n = out_off[g + 1] - out_off[g];
+    memcpy(out_t + out_off[g], t + a, (size_t)n * 8);
+    memcpy(out_pb + out_off[g], pin_bit + a, (size_t)n);
+    memcpy(out_slew + out_off[g], slew + a, (size_t)n * 4);
+  }
+  return SYN_OK;
+}
