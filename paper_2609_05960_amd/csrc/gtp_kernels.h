@@ -471,6 +471,7 @@ struct TraceDev {
   const int32_t* tile_grp;
   BinSpec bins;
   int64_t bin_off;   // first bin of the trace in the concatenated bins
+  int64_t tile_off;  // first tile of the trace in the concatenated tiles
 };
 
 struct BatchFwdArgs {
@@ -478,51 +479,41 @@ struct BatchFwdArgs {
   const TraceDev* traces;
   const int2* items;           // (trace, tile), largest first
   int64_t n_items;
-  unsigned long long* queue;   // next item (zeroed before the launch)
   int64_t* X;                  // concatenated bins
-  int64_t* S;
+  int64_t* S;                  // within-tile exclusive prefix of the leakage steps
+  long long* tile_tot;         // per concatenated tile: total leakage step
 };
 
-// Workgroups stay resident and take work items from the queue until it is
-// empty; every workgroup ends once it draws an index past the last item.
+// One workgroup per work item (trace, tile): the items are listed largest
+// first, so the hardware's in-order dispatch hands out the long tiles first
+// and the short ones fill in at the end. Each workgroup reads its item once,
+// with a uniform index, so the trace record stays in scalar registers.
 // kSlotOnly: every trace has table phases that hold all their groups' quads.
 template <int kThreads, int kS, bool kSlotOnly, bool kGl>
 __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
   extern __shared__ uint32_t lds[];
-  __shared__ long long item_sh;
   const LdsLib L = stage_library_ml(a.base.lib, lds);
-  for (;;) {
-    __syncthreads();  // the previous item is done with item_sh and the LDS bins
-    if (threadIdx.x == 0) item_sh = (long long)atomicAdd(a.queue, 1ull);
-    __syncthreads();
-    // the item index is the same on every lane: make it scalar, so the
-    // trace record and everything derived from it stay in scalar registers
-    const long long it0 = item_sh;
-    const long long it = (long long)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(it0 >> 32)) << 32) |
-                                     (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)it0));
-    if (it >= a.n_items) break;
-    const int2 w = a.items[it];
-    const TraceDev T = a.traces[w.x];
-    PackedFwdArgs p = a.base;
-    p.w32 = T.w32;
-    p.row = T.row;
-    p.alpha = T.alpha;
-    p.rgl = T.rgl;
-    p.desc = T.desc;
-    p.grp_off = T.grp_off;
-    p.tile_grp = T.tile_grp;
-    p.bins = T.bins;
-    p.X = a.X + T.bin_off;
-    p.S = a.S + T.bin_off;
-    p.phases = T.phases;
-    p.ph_off = T.ph_off;
-    p.slot_quads = T.slot_quads;
-    unsigned long long* xs =
-        reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.base.lib.lds_words_ml));
-    unsigned long long* ss = xs + (1 << T.bins.tile_log2);
-    float4* slots = T.phases ? reinterpret_cast<float4*>(ss + (1 << T.bins.tile_log2)) : nullptr;
-    fwd_tile_body<kThreads, kS, kSlotOnly, kGl>(p, L, xs, ss, w.y, slots);
-  }
+  const int2 w = a.items[blockIdx.x];
+  const TraceDev T = a.traces[w.x];
+  PackedFwdArgs p = a.base;
+  p.w32 = T.w32;
+  p.row = T.row;
+  p.alpha = T.alpha;
+  p.rgl = T.rgl;
+  p.desc = T.desc;
+  p.grp_off = T.grp_off;
+  p.tile_grp = T.tile_grp;
+  p.bins = T.bins;
+  p.X = a.X + T.bin_off;
+  p.S = a.S + T.bin_off;
+  p.phases = T.phases;
+  p.ph_off = T.ph_off;
+  p.slot_quads = T.slot_quads;
+  p.tile_tot = a.tile_tot ? a.tile_tot + T.tile_off : nullptr;
+  unsigned long long* xs = reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.base.lib.lds_words_ml));
+  unsigned long long* ss = xs + (1 << T.bins.tile_log2);
+  float4* slots = T.phases ? reinterpret_cast<float4*>(ss + (1 << T.bins.tile_log2)) : nullptr;
+  fwd_tile_body<kThreads, kS, kSlotOnly, kGl>(p, L, xs, ss, w.y, slots);
 }
 
 // Per-call gate records (output load, leakage scale) in cell-sorted order,
@@ -823,39 +814,84 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs a) {
   a.P[b] = (float)((double)E * a.out_scale);
 }
 
-// Finalize of concatenated traces: the leakage prefix restarts at every
-// trace (exS is the exclusive prefix over the concatenation).
+// Finalize of concatenated traces. The forward leaves, per bin, the energy X
+// and the within-tile exclusive prefix S of the leakage steps, and per tile
+// the total of its steps; k_tile_base_batched turns the tile totals of each
+// trace into the leakage rate at every tile start (starting from L0 at each
+// trace: the traces share the netlist's initial state), and
+// k_finalize_batched gives every bin its energy as k_finalize_tiles does.
 struct FinTrace {
   int64_t bin_off, n_bins, t_end;
+  int64_t tile_off, n_tiles;
+  int64_t block_off;   // first finalize block (kFinBins bins each) of the trace
 };
+constexpr int kFinBins = 256;
+
+__global__ void __launch_bounds__(1024) k_tile_base_batched(const unsigned long long* L0, const FinTrace* traces,
+                                                            const long long* tot, long long* base) {
+  __shared__ long long ws[17];
+  const FinTrace T = traces[blockIdx.x];
+  const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+  long long carry = (long long)*L0;
+  for (int64_t c0 = 0; c0 < T.n_tiles; c0 += 1024) {
+    const int64_t i = c0 + threadIdx.x;
+    const long long x = i < T.n_tiles ? tot[T.tile_off + i] : 0;
+    long long inc = x;  // inclusive scan within the wavefront
+    for (int o = 1; o < 64; o <<= 1) {
+      const long long t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    if (lane == 63) ws[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long acc = 0;
+      for (int w = 0; w < 16; ++w) {
+        const long long t = ws[w];
+        ws[w] = acc;
+        acc += t;
+      }
+      ws[16] = acc;
+    }
+    __syncthreads();
+    if (i < T.n_tiles) base[T.tile_off + i] = carry + ws[wave] + inc - x;
+    carry += ws[16];
+    __syncthreads();
+  }
+}
 
 struct FinBatchArgs {
   const int64_t* X;
-  const int64_t* S;
-  const int64_t* exS;
-  const unsigned long long* L0;
+  const int64_t* S;            // within-tile exclusive prefix of the steps
+  const long long* base;       // rate at every concatenated tile's start
+  const long long* tot;        // steps of every concatenated tile
   const FinTrace* traces;
   int32_t n_traces;
+  int32_t tile_log2;
   float* P;
   int64_t total_bins, D;
   double out_scale;
 };
 
-__global__ void __launch_bounds__(256) k_finalize_batched(FinBatchArgs a) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= a.total_bins) return;
-  int32_t lo = 0, hi = a.n_traces;  // last trace starting at or before b
+// One block of kFinBins bins of one trace per workgroup: the trace is found
+// once per workgroup (a uniform search, in scalar registers).
+__global__ void __launch_bounds__(kFinBins) k_finalize_batched(FinBatchArgs a) {
+  const int64_t blk = blockIdx.x;
+  int32_t lo = 0, hi = a.n_traces;  // last trace whose blocks start at or before blk
   while (hi - lo > 1) {
     const int32_t mid = (lo + hi) >> 1;
-    if (a.traces[mid].bin_off <= b) lo = mid; else hi = mid;
+    if (a.traces[mid].block_off <= blk) lo = mid; else hi = mid;
   }
   const FinTrace T = a.traces[lo];
-  const int64_t bl = b - T.bin_off;
-  const int64_t R = (int64_t)*a.L0 + a.exS[b] - a.exS[T.bin_off];
+  const int64_t bl = (blk - T.block_off) * kFinBins + threadIdx.x;
+  if (bl >= T.n_bins) return;
+  const int64_t b = T.bin_off + bl;
+  const int64_t k = T.tile_off + (bl >> a.tile_log2);
+  const int64_t R = (int64_t)a.base[k] + a.S[b];
   int64_t E;
   if (bl == T.n_bins - 1 && T.n_bins * a.D != T.t_end) {
     const int64_t w = T.t_end - bl * a.D;
-    E = a.X[b] - a.S[b] * (T.n_bins * a.D - T.t_end) + w * R;
+    const int64_t S = (int64_t)a.tot[k] - a.S[b];
+    E = a.X[b] - S * (T.n_bins * a.D - T.t_end) + w * R;
   } else {
     E = a.X[b] + a.D * R;
   }

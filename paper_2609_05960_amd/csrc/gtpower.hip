@@ -137,7 +137,8 @@ struct gtp_ctx_s {
   bool batch_packed = false;
   int64_t batch_total_bins = 0;
   int64_t batch_items = 0;
-  DevBuf b_tab, b_items, b_queue, b_fin, b_X, b_S, b_exS;
+  DevBuf b_tab, b_items, b_fin, b_X, b_S, b_tile_tot, b_tile_base;
+  int64_t batch_total_tiles = 0, batch_fin_blocks = 0;
   DevBuf tun_in, tun_out;  // autotuner inputs and output
   hipStream_t cap_stream = nullptr;
 
@@ -968,8 +969,8 @@ gtp_status gtp_destroy(gtp_ctx c) {
                    &c->gate_cell, &c->gate_out,
                    &c->gate_init, &c->plan_blk, &c->blk_tmp, &c->blk_tmp2, &c->scan_sums, &c->gprep, &c->gparam, &c->l0_part, &c->tile_tot, &c->tile_base,
                    &c->X, &c->S, &c->exS, &c->L0, &c->flag, &c->first_bad, &c->adj_w, &c->adj_c, &c->adj_exc,
-                   &c->adj_wg, &c->adj_gtile, &c->adj_total, &c->rep_small, &c->gC, &c->gL, &c->adj_items, &c->adj_entries, &c->adj_gbs, &c->adj_gbrow, &c->adj_gbrows, &c->adj_part, &c->b_tab, &c->b_items, &c->b_queue,
-                   &c->b_fin, &c->b_X, &c->b_S, &c->b_exS, &c->tun_in, &c->tun_out};
+                   &c->adj_wg, &c->adj_gtile, &c->adj_total, &c->rep_small, &c->gC, &c->gL, &c->adj_items, &c->adj_entries, &c->adj_gbs, &c->adj_gbrow, &c->adj_gbrows, &c->adj_part, &c->b_tab, &c->b_items,
+                   &c->b_fin, &c->b_X, &c->b_S, &c->b_tile_tot, &c->b_tile_base, &c->tun_in, &c->tun_out};
   for (DevBuf* b : all) release(c, *b);
   prof_clear(c);
   for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
@@ -1712,7 +1713,7 @@ gtp_status build_batch(gtp_ctx c) {
   std::vector<TraceDev> tab((size_t)nt);
   std::vector<FinTrace> fin((size_t)nt);
   std::vector<std::pair<int64_t, int2>> items;
-  int64_t off = 0;
+  int64_t off = 0, toff = 0, boff = 0;
   for (int32_t i = 0; i < nt; ++i) {
     auto& t = c->batch[i];
     t.bins = bins_for(c, t.ev.t_end_ps);
@@ -1734,9 +1735,12 @@ gtp_status build_batch(gtp_ctx c) {
                       t.pk.grp_off,
                       t.pk.tile_grp,
                       t.bins,
-                      off};
-    fin[i] = FinTrace{off, t.bins.n_bins, t.bins.t_end};
+                      off,
+                      toff};
+    fin[i] = FinTrace{off, t.bins.n_bins, t.bins.t_end, toff, t.bins.n_tiles, boff};
+    boff += (t.bins.n_bins + kFinBins - 1) / kFinBins;
     off += t.bins.n_bins;
+    toff += t.bins.n_tiles;
     // events per tile, for the largest-first order
     const int32_t ntile = t.bins.n_tiles;
     std::vector<int32_t> tg((size_t)ntile + 1);
@@ -1758,11 +1762,14 @@ gtp_status build_batch(gtp_ctx c) {
   std::vector<int2> it(items.size());
   for (size_t j = 0; j < items.size(); ++j) it[j] = items[j].second;
   c->batch_total_bins = off;
+  c->batch_total_tiles = toff;
+  c->batch_fin_blocks = boff;
   c->batch_items = (int64_t)it.size();
   TRY(ensure(c, c->b_tab, tab.size() * sizeof(TraceDev)));
   TRY(ensure(c, c->b_fin, fin.size() * sizeof(FinTrace)));
   TRY(ensure(c, c->b_items, std::max<size_t>(it.size(), 1) * sizeof(int2)));
-  TRY(ensure(c, c->b_queue, 256));
+  TRY(ensure(c, c->b_tile_tot, (size_t)std::max<int64_t>(toff, 1) * 8));
+  TRY(ensure(c, c->b_tile_base, (size_t)std::max<int64_t>(toff, 1) * 8));
   if (nt > 0) {
     HIPCHK(c, hipMemcpy(c->b_tab.p, tab.data(), tab.size() * sizeof(TraceDev), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->b_fin.p, fin.data(), fin.size() * sizeof(FinTrace), hipMemcpyHostToDevice));
@@ -1771,8 +1778,6 @@ gtp_status build_batch(gtp_ctx c) {
   const int64_t NB = std::max<int64_t>(off, 1);
   TRY(ensure(c, c->b_X, (size_t)NB * 8));
   TRY(ensure(c, c->b_S, (size_t)NB * 8));
-  TRY(ensure(c, c->b_exS, (size_t)NB * 8));
-  TRY(ensure(c, c->scan_sums, (size_t)((NB + kScanTile - 1) / kScanTile) * 8 + 8));
   TRY(ensure(c, c->gparam, (size_t)std::max<int64_t>(c->n_gates, 1) * sizeof(GateParam)));
   TRY(ensure(c, c->L0, 8));
   TRY(ensure(c, c->l0_part, (size_t)l0_parts(c) * 8));
@@ -1785,7 +1790,6 @@ gtp_status build_batch(gtp_ctx c) {
 gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_scale, float* power_mw) {
   TRY(gate_params_for(c, c->batch[0].pk, net_load, leak_scale));
   TRY(sum_l0(c));
-  TRY(fill_u64(c, c->b_queue.p, 1, 0ull));
   const int lb = c->batch[0].bins.tile_log2;
   if (c->batch_items > 0) {
     BatchFwdArgs a;
@@ -1793,9 +1797,9 @@ gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_s
     a.traces = ptr<TraceDev>(c->b_tab);
     a.items = ptr<int2>(c->b_items);
     a.n_items = c->batch_items;
-    a.queue = ptr<unsigned long long>(c->b_queue);
     a.X = ptr<int64_t>(c->b_X);
     a.S = ptr<int64_t>(c->b_S);
+    a.tile_tot = ptr<long long>(c->b_tile_tot);
     int32_t sq = 0;  // every trace's pack has the same slot size (same tile size)
     bool so = true;  // every trace's phases hold all their groups' quads
     for (auto& t : c->batch) {
@@ -1805,11 +1809,7 @@ gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_s
     const size_t lds = packed_lds_bytes(c, lb) + slot_bytes(sq);
     const int sl = slots_of(c);
     const int th = threads_for_slots(tile_threads(c), sl);
-    // resident workgroups: as many as fit (LDS-limited), at most one per item
-    int per_cu = (int)std::max<size_t>(1, kMaxLds / lds);
-    per_cu = std::min(per_cu, 2048 / th);
-    const int64_t wgs = std::min<int64_t>(c->batch_items, (int64_t)c->n_cu * per_cu);
-    const dim3 grid((unsigned)wgs);
+    const dim3 grid((unsigned)c->batch_items);   // one workgroup per (trace, tile) item
     const bool gl = c->par.glitch_clk_ps > 0;
 #define GTP_BATCH_CASE(TH, SL)                                                                       \
   if (th == TH && sl == SL) {                                                                        \
@@ -1830,19 +1830,25 @@ gtp_status batched_enqueue(gtp_ctx c, const float* net_load, const float* leak_s
 #undef GTP_BATCH_CASE
   }
   const int64_t NB = c->batch_total_bins;
-  TRY(scan_exclusive<int64_t, OpAdd>(c, ptr<int64_t>(c->b_S), ptr<int64_t>(c->b_exS), NB, (int64_t)0, OpAdd()));
+  const int32_t n_traces = (int32_t)c->batch.size();
+  if (c->batch_total_tiles > 0)
+    LAUNCH(c, "k_tile_base_batched", k_tile_base_batched, dim3((unsigned)n_traces), dim3(1024), 0,
+           (const unsigned long long*)ptr<unsigned long long>(c->L0), (const FinTrace*)ptr<FinTrace>(c->b_fin),
+           (const long long*)ptr<long long>(c->b_tile_tot), ptr<long long>(c->b_tile_base));
   FinBatchArgs f;
   f.X = ptr<int64_t>(c->b_X);
   f.S = ptr<int64_t>(c->b_S);
-  f.exS = ptr<int64_t>(c->b_exS);
-  f.L0 = ptr<unsigned long long>(c->L0);
+  f.base = ptr<long long>(c->b_tile_base);
+  f.tot = ptr<long long>(c->b_tile_tot);
   f.traces = ptr<FinTrace>(c->b_fin);
-  f.n_traces = (int32_t)c->batch.size();
+  f.n_traces = n_traces;
+  f.tile_log2 = lb;
   f.P = power_mw;
   f.total_bins = NB;
   f.D = c->bins.D;
   f.out_scale = std::ldexp(1.0, -c->batch[0].pk.mfix) / (double)c->bins.D;
-  if (NB > 0) LAUNCH(c, "k_finalize_batched", k_finalize_batched, dim3(grid_for(NB, 256)), dim3(256), 0, f);
+  if (NB > 0)
+    LAUNCH(c, "k_finalize_batched", k_finalize_batched, dim3((unsigned)c->batch_fin_blocks), dim3(kFinBins), 0, f);
   return GTP_OK;
 }
 

@@ -259,6 +259,18 @@ def make_events(seed: int, lib: Library, net: Netlist, counts: np.ndarray, is_cl
     return Events(N, t_end, gate_off, t, pin_bit, slew)
 
 
+def window_size(ev: Events, t0: int, t1: int) -> int:
+    """Number of events of ev with t0 <= t < t1."""
+    L = _load()
+    G = len(ev.gate_off) - 1
+    off = np.empty(G + 1, np.int64)
+    n = ctypes.c_int64()
+    _check(L.synth_window(ctypes.c_int64(G), _p(ev.gate_off), _p(ev.t), _p(ev.pin_bit), _p(ev.slew),
+                          ctypes.c_int64(t0), ctypes.c_int64(t1), _p(off), None, None, None, ctypes.byref(n)),
+           "window count")
+    return n.value
+
+
 def window(ev: Events, t0: int, t1: int, out=None):
     """The events of ev with t0 <= t < t1 as a gate-major CSR (absolute
     times): (gate_off, t, pin_bit, slew). `out` may give the four arrays to
@@ -321,6 +333,31 @@ def make_problem(name: str = "C1", scale: float = 1.0, p_tie: float = 0.0, **ove
     return Problem(lib, net, ev, vdd=0.8, bin_ps=cfg["bin_ps"], sw_mode=0, name=name)
 
 
+def batch_plan(n_traces: int = 64, cycles=(10_000, 1_000_000), events_per_cycle: int = 500, n_gates: int = 200_000,
+               n_cells: int = 32, i_max: int = 4, t_clk: int = 1000, bin_ps: int = 50, seed: int = 4):
+    """The batched workload of make_batch without generating its traces:
+    (library, netlist, [(trace seed, t_end, events)], bin_ps); batch_trace
+    generates one trace of it (the same arrays make_batch returns)."""
+    L = _load()
+    lib = make_library(seed, n_cells, i_max, load_range=(0.5, 50.0))
+    net = make_netlist(seed, lib, n_gates, load_range=(0.5, 50.0))
+    draws = np.zeros(n_traces, np.uint64)
+    _check(L.synth_draws(ctypes.c_uint64(seed), ctypes.c_uint64(4), ctypes.c_uint64(0), ctypes.c_int64(n_traces),
+                         _p(draws)), "draws")
+    lo, hi = int(cycles[0]), int(cycles[1])
+    items = []
+    for i in range(n_traces):
+        n_cyc = lo + int(draws[i] % np.uint64(hi - lo + 1))
+        items.append((seed * 1_000_003 + i + 1, n_cyc * t_clk, events_per_cycle * n_cyc))
+    return lib, net, items, bin_ps
+
+
+def batch_trace(lib: Library, net: Netlist, item, t_clk: int = 1000, p_tie: float = 0.0) -> Events:
+    tseed, t_end, total = item
+    counts, is_clock = make_counts(tseed, net.n_gates, 0, 0, "lognormal", 0.0, 2.0, total, t_end)
+    return make_events(tseed, lib, net, counts, is_clock, t_end, t_clk, p_tie=p_tie)
+
+
 def make_batch(n_traces: int = 64, cycles=(10_000, 1_000_000), events_per_cycle: int = 500, n_gates: int = 200_000,
                n_cells: int = 32, i_max: int = 4, t_clk: int = 1000, bin_ps: int = 50, seed: int = 4,
                p_tie: float = 0.0):
@@ -329,22 +366,9 @@ def make_batch(n_traces: int = 64, cycles=(10_000, 1_000_000), events_per_cycle:
     (counter stream 4, index i), with events_per_cycle * N_cyc,i events whose
     per-gate counts follow lognormal(0, 2) weights redrawn per trace; no clock
     gates. Returns (library, netlist, [Events], bin_ps)."""
-    L = _load()
-    lib = make_library(seed, n_cells, i_max, load_range=(0.5, 50.0))
-    net = make_netlist(seed, lib, n_gates, load_range=(0.5, 50.0))
-    draws = np.zeros(n_traces, np.uint64)
-    _check(L.synth_draws(ctypes.c_uint64(seed), ctypes.c_uint64(4), ctypes.c_uint64(0), ctypes.c_int64(n_traces),
-                         _p(draws)), "draws")
-    lo, hi = int(cycles[0]), int(cycles[1])
-    traces = []
-    for i in range(n_traces):
-        n_cyc = lo + int(draws[i] % np.uint64(hi - lo + 1))
-        t_end = n_cyc * t_clk
-        total = events_per_cycle * n_cyc
-        tseed = seed * 1_000_003 + i + 1
-        counts, is_clock = make_counts(tseed, n_gates, 0, 0, "lognormal", 0.0, 2.0, total, t_end)
-        traces.append(make_events(tseed, lib, net, counts, is_clock, t_end, t_clk, p_tie=p_tie))
-    return lib, net, traces, bin_ps
+    lib, net, items, bin_ps = batch_plan(n_traces, cycles, events_per_cycle, n_gates, n_cells, i_max, t_clk, bin_ps,
+                                         seed)
+    return lib, net, [batch_trace(lib, net, it, t_clk, p_tie) for it in items], bin_ps
 
 
 def make_random_small(seed: int, n_gates: int = 20, n_cells: int = 4, i_max: int = 3, n_events: int = 400,
