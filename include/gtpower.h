@@ -253,9 +253,10 @@ gtp_status gtp_num_bins(gtp_ctx ctx, int64_t* n_bins);
  * LDS). tile_threads: threads per time-tile workgroup of the packed path,
  * 0 = automatic, else 256, 512 or 1024. unit_events: longest run of one
  * gate's events one lane takes (the density split: denser gates are cut into
- * more runs), 0 = 16, else 1..16. gate_block_log2: gates per sort block of the
- * packed layout (log2), 0 = 13, else 6..20. Both paths give bit-identical
- * waveforms.
+ * more runs), 0 = 8, else 1..16. gate_block_log2: gates per sort block of the
+ * packed layout (log2), 0 = 13, else 6..20 (the packed adjoint holds 16 bytes
+ * per gate of a block in LDS; when they do not fit it runs the gate-major
+ * walk). Both paths give bit-identical waveforms.
  */
 typedef struct {
   int32_t algo;
