@@ -67,6 +67,11 @@ struct UnitArgs {
   uint32_t* vals;
   UnitRec* recs;
   uint2* upins;           // emit pass, optional: every pin value before each unit's first event and its group
+  // emit pass: the workgroup's units staged in LDS (null: written directly)
+  uint64_t* lkeys;
+  UnitRec* lrecs;
+  uint2* lpins;
+  uint32_t u0;            // first unit of the workgroup
 };
 
 template <bool kEmit>
@@ -94,14 +99,21 @@ struct UnitVisitor {
       const uint64_t key = ((uint64_t)u_tile << (A->ks.gb_bits + 5 + A->ks.gb_log2)) |
                            ((uint64_t)gblock << (5 + A->ks.gb_log2)) | ((uint64_t)(16 - u_len) << A->ks.gb_log2) |
                            (uint64_t)gin;
-      A->keys[u] = key;
-      A->vals[u] = u;
       UnitRec r;
       r.src = u_src;
       r.x = (uint32_t)gs | ((uint32_t)(u_len - 1) << 28);
       r.y = u_st;
-      A->recs[u] = r;
-      if (A->upins) A->upins[u] = u_pins;
+      if (A->lkeys) {   // staged: the workgroup writes its units out together
+        const uint32_t i = u - A->u0;
+        A->lkeys[i] = key;
+        A->lrecs[i] = r;
+        if (A->lpins) A->lpins[i] = u_pins;
+      } else {
+        A->keys[u] = key;
+        A->vals[u] = u;
+        A->recs[u] = r;
+        if (A->upins) A->upins[u] = u_pins;
+      }
     }
     ++n;
     open = false;
@@ -136,15 +148,47 @@ struct UnitVisitor {
   }
 };
 
+// Emit pass: a workgroup's lane blocks own one contiguous run of units
+// [base[kb0], base[kb1]); when the run fits kEmitCap units, the lanes write
+// their units into LDS and the workgroup stores the run with coalesced writes
+// (each lane's units are scattered over the run otherwise).
+constexpr uint32_t kEmitCap = 2048;
 template <bool kEmit>
 __global__ void __launch_bounds__(kFwdThreads) k_pk_units(UnitArgs a, int64_t n_blocks) {
   const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (kb >= n_blocks) return;
-  UnitVisitor<kEmit> vis;
-  vis.A = &a;
-  vis.kb = kb;
-  walk_block(kb, a.ev, a.plan, vis);
-  if (!kEmit) a.counts[kb] = vis.n;
+  if (!kEmit) {
+    if (kb >= n_blocks) return;
+    UnitVisitor<false> vis;
+    vis.A = &a;
+    vis.kb = kb;
+    walk_block(kb, a.ev, a.plan, vis);
+    a.counts[kb] = vis.n;
+    return;
+  }
+  extern __shared__ uint64_t lds64[];
+  const int64_t kb0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t kb1 = min(kb0 + (int64_t)blockDim.x, n_blocks);
+  const uint32_t u0 = a.base[kb0], n_u = a.base[kb1] - u0;
+  const bool staged = n_u <= kEmitCap;   // uniform over the workgroup
+  UnitArgs la = a;
+  la.lkeys = staged ? lds64 : nullptr;
+  la.lrecs = staged ? reinterpret_cast<UnitRec*>(lds64 + kEmitCap) : nullptr;
+  la.lpins = (staged && a.upins) ? reinterpret_cast<uint2*>(lds64 + 3 * kEmitCap) : nullptr;
+  la.u0 = u0;
+  if (kb < n_blocks) {
+    UnitVisitor<true> vis;
+    vis.A = &la;
+    vis.kb = kb;
+    walk_block(kb, a.ev, a.plan, vis);
+  }
+  if (!staged) return;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n_u; i += blockDim.x) {
+    a.keys[u0 + i] = la.lkeys[i];
+    a.vals[u0 + i] = u0 + i;
+    a.recs[u0 + i] = la.lrecs[i];
+    if (la.lpins) a.upins[u0 + i] = la.lpins[i];
+  }
 }
 
 __global__ void __launch_bounds__(256) k_pk_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
@@ -770,6 +814,10 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     ua.vals = nullptr;
     ua.recs = nullptr;
     ua.upins = nullptr;
+    ua.lkeys = nullptr;
+    ua.lrecs = nullptr;
+    ua.lpins = nullptr;
+    ua.u0 = 0;
     int64_t NU = 0;
     if (n_blocks > 0) {
       const unsigned gridb = (unsigned)((n_blocks + kFwdThreads - 1) / kFwdThreads);
@@ -836,7 +884,8 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       ua.recs = recs;
       ua.upins = upins;
       const unsigned gridb = (unsigned)((n_blocks + kFwdThreads - 1) / kFwdThreads);
-      hipLaunchKernelGGL((k_pk_units<true>), dim3(gridb), dim3(kFwdThreads), 0, s, ua, n_blocks);
+      const size_t elds = (size_t)kEmitCap * (sizeof(uint64_t) + sizeof(UnitRec) + (upins ? sizeof(uint2) : 0));
+      hipLaunchKernelGGL((k_pk_units<true>), dim3(gridb), dim3(kFwdThreads), elds, s, ua, n_blocks);
       PKLAUNCH("k_pk_units<emit>");
       // ---- 4. sort --------------------------------------------------------
       size_t tb = usort_tmp;
