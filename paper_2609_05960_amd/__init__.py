@@ -162,6 +162,10 @@ def load_library(path: Optional[str] = None):
     p = path or SO_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"{p} is not built: run paper_2609_05960_amd.build() (no CPU fallback exists)")
+    # torch's HIP runtime first: the library then binds to that same runtime
+    # (its stream handles are torch's). Loaded the other way round, the
+    # process would hold two HIP runtimes and the library would see no device.
+    import torch  # noqa: F401
     L = ctypes.CDLL(p)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     sig = {
