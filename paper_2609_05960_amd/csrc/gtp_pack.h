@@ -82,7 +82,6 @@ struct PackIn {
   int32_t slot_quads = 0;         // quads one LDS table slot holds (0: no phases)
   Workspace* ws = nullptr;        // [2] temporaries (caller-owned)
   int64_t glitch_clk = 0;         // > 0: per-event glitch factors for this clock period
-  bool wide_cells = false;        // some cell has more than 8 state pins (its units carry every pin value)
   Workspace* arena = nullptr;     // optional: output arrays carved from it while it has room
 };
 

@@ -9,20 +9,21 @@
 //   2. k_pk_units (count pass): every gate-major lane block of 16 events is
 //      walked in order and split into units wherever the gate or the time
 //      tile changes; units per block, exclusive scan;
-//   3. k_pk_units (emit pass): the same walk writes one record per unit
-//      (first event, gate, length, carried-in pin values) and its sort key
-//      (tile, gate block, 16 - length, gate within the block);
-//   4. device radix sort of the unit keys (stable);
+//   3. k_pk_units (emit pass): the same walk writes every unit's sort key
+//      (tile, gate block, length class, gate within the block; 32 bits when
+//      the fields fit) and its first event, staged in LDS per workgroup;
+//   4. device radix sort of the keys with the first events (stable);
 //   5. k_pk_tile_first + suffix minimum: each tile's first unit; groups of 64
 //      units per tile, scanned into tile_grp;
 //   6. k_pk_group_len: per group its events and longest unit (from the sorted
 //      keys), scanned into group offsets; per (tile, gate block) region its
 //      events and first unit;
 //   7. k_pk_fill: one workgroup per tile, one wavefront per group: the unit
-//      descriptors and every event's record in the unit-interleaved order,
-//      and the most events in one bin (LDS histogram of the tile);
-//   8. k_pk_group_quads + k_pk_phases + k_pk_phase_copy (the table phases of
-//      every tile).
+//      descriptors, every event's record in the unit-interleaved order, the
+//      group's table quad range, and the most events in one bin (LDS
+//      histogram of the tile); a unit's carried-in pin values come from the
+//      lane-block plan and the pins of its block;
+//   8. k_pk_phases + k_pk_phase_copy (the table phases of every tile).
 // Temporaries live in a workspace the caller keeps between packs; the pack
 // runs once per event set and bin width, its time is reported apart from the
 // forward.
@@ -39,21 +40,44 @@
 namespace gtp {
 namespace {
 
-struct UnitRec {
-  int64_t src;   // gate-major index of the first event
-  uint32_t x;    // cell-sorted gate | (len - 1) << 28
-  uint32_t y;    // pin values before the first event | before its group << 16
+// Sort key of a unit, fields from the most significant: tile, gate block,
+// 2^len_bits - length, gate within the block. Every field is exact, so the
+// fill reads the unit's gate and length back from its key. 32-bit keys when
+// the fields fit (fewer bytes per radix pass), else 64-bit.
+struct KeyLayout {
+  int32_t len_bits;    // length field (unit lengths 1..2^len_bits)
+  int32_t gin_bits;    // gate-within-block field (the gate-block size, log2)
+  int32_t gb_bits;     // gate-block field
+  int32_t tile_bits;
 };
 
+__host__ __device__ __forceinline__ int key_low(const KeyLayout& L) { return L.len_bits + L.gin_bits; }
+
+template <class K>
+__device__ __forceinline__ uint32_t key_len(K key, const KeyLayout& L) {
+  return (1u << L.len_bits) - (uint32_t)((key >> L.gin_bits) & (K)((1u << L.len_bits) - 1u));
+}
+template <class K>
+__device__ __forceinline__ uint32_t key_gb(K key, const KeyLayout& L) {
+  return (uint32_t)((key >> key_low(L)) & (K)((1ull << L.gb_bits) - 1ull));
+}
+
 struct KeySpec {
-  int32_t gb_bits;                // bits of the gate-block field
-  int32_t gb_log2;                // gates per gate block (log2)
+  KeyLayout L;
   int32_t unit_cap;               // longest unit
   const int32_t* rank;            // gate -> cell-sorted index
   const int32_t* cell_start;      // [n_cells] first sorted index of the cell
   const int32_t* gb_base;         // [n_cells] first gate block of the cell
 };
 
+// Table item of state st and leakage item of state sl of a cell with more
+// than 8 state pins (kept out of line: rare, and it would stop the event loop
+// of the emit pass from unrolling).
+__device__ __noinline__ uint2 wide_items(WideView W, int cell, int mode, uint32_t st, uint32_t sl) {
+  return make_uint2((uint32_t)wide_item(W, cell, mode, st, false), (uint32_t)wide_item(W, cell, mode, sl, true));
+}
+
+template <class K>
 struct UnitArgs {
   EvView ev;
   const uint2* plan;
@@ -63,102 +87,147 @@ struct UnitArgs {
   KeySpec ks;
   uint32_t* counts;       // count pass: units per lane block
   const uint32_t* base;   // emit pass: first unit of each lane block
-  uint64_t* keys;
-  uint32_t* vals;
-  UnitRec* recs;
-  uint2* upins;           // emit pass, optional: every pin value before each unit's first event and its group
-  // emit pass: the workgroup's units staged in LDS (null: written directly)
-  uint64_t* lkeys;
-  UnitRec* lrecs;
-  uint2* lpins;
+  K* keys;                // emit pass: sort key of every unit
+  uint32_t* srcs;         // emit pass: gate-major index of every unit's first event
+  // emit pass: the workgroup's units staged in LDS
+  K* lkeys;
+  uint32_t* lsrcs;
   uint32_t u0;            // first unit of the workgroup
+  // emit pass: every packed event's record, gate-major (see EvRec)
+  LibView lib;
+  uint4* rec;
+  float* rgl;             // glitch detection on: energy factor of every event, gate-major
+  int64_t glitch_clk;
+  int32_t* dbg_state;     // optional, gate-major: state before the event's group
+  int64_t* dbg_bin;       // optional, gate-major: bin of the event
+  int32_t* alpha_span;    // max over events of |1 - alpha| + |alpha| (FP32 bits; positive floats order as ints)
 };
 
-template <bool kEmit>
+// Record of a packed event (16 bytes, gate-major, written by the emit pass
+// and gathered unit by unit by the fill): x = the event word (in-tile bin,
+// in-bin offset, leakage state after the event), y = the table row at the
+// slew segment | output flag | new value, z = the slew weight (FP32 bits),
+// w = for a unit's first event, the leakage state before it (its pin values
+// for a kCellDirect cell, else its leakage item) | the cell << 16.
+
+template <bool kEmit, class K>
 struct UnitVisitor {
-  const UnitArgs* A;
+  const UnitArgs<K>* A;
+  LdsLib L;                // emit pass: the library in LDS
   int64_t kb;
   uint32_t n = 0;          // units closed in this block
-  uint32_t init = 0;
-  int32_t gs = 0;          // cell-sorted gate index
   uint32_t gblock = 0;
   uint32_t gin = 0;        // index of the gate within its gate block
   bool open = false;
   int64_t u_src = 0;
   int32_t u_len = 0;
   int64_t u_tile = 0;
-  uint32_t u_st = 0;
-  uint2 u_pins{0u, 0u};
+  // emit pass: the gate
+  int cell = 0;
+  uint32_t init = 0;
+  int64_t gstart = 0;
+  float span = 1.0f;
 
   __device__ __forceinline__ void close() {
     if (!open) return;
     if (kEmit) {
-      const uint32_t u = A->base[kb] + n;
-      // (tile, gate block, 16 - length, gate within the block): lanes of one
-      // length class read neighbouring gate records
-      const uint64_t key = ((uint64_t)u_tile << (A->ks.gb_bits + 5 + A->ks.gb_log2)) |
-                           ((uint64_t)gblock << (5 + A->ks.gb_log2)) | ((uint64_t)(16 - u_len) << A->ks.gb_log2) |
-                           (uint64_t)gin;
-      UnitRec r;
-      r.src = u_src;
-      r.x = (uint32_t)gs | ((uint32_t)(u_len - 1) << 28);
-      r.y = u_st;
-      if (A->lkeys) {   // staged: the workgroup writes its units out together
-        const uint32_t i = u - A->u0;
-        A->lkeys[i] = key;
-        A->lrecs[i] = r;
-        if (A->lpins) A->lpins[i] = u_pins;
-      } else {
-        A->keys[u] = key;
-        A->vals[u] = u;
-        A->recs[u] = r;
-        if (A->upins) A->upins[u] = u_pins;
-      }
+      const KeyLayout& KL = A->ks.L;
+      const int low = key_low(KL);
+      const K key = ((K)u_tile << (KL.gb_bits + low)) | ((K)gblock << low) |
+                    ((K)((1u << KL.len_bits) - (uint32_t)u_len) << KL.gin_bits) | (K)gin;
+      const uint32_t i = A->base[kb] + n - A->u0;
+      A->lkeys[i] = key;
+      A->lsrcs[i] = (uint32_t)u_src;
     }
     ++n;
     open = false;
   }
   __device__ __forceinline__ void begin_gate(int64_t g, uint32_t) {
-    init = A->gate_init[g];
     const int32_t c = A->gate_cell[g];
-    gs = A->ks.rank[g];
-    gblock = (uint32_t)(A->ks.gb_base[c] + ((gs - A->ks.cell_start[c]) >> A->ks.gb_log2));
-    gin = (uint32_t)(gs - A->ks.cell_start[c]) & ((1u << A->ks.gb_log2) - 1u);
+    const int32_t gs = A->ks.rank[g];
+    gblock = (uint32_t)(A->ks.gb_base[c] + ((gs - A->ks.cell_start[c]) >> A->ks.L.gin_bits));
+    gin = (uint32_t)(gs - A->ks.cell_start[c]) & ((1u << A->ks.L.gin_bits) - 1u);
     open = false;
+    if (kEmit) {
+      cell = c;
+      init = A->gate_init[g];
+      if (A->glitch_clk > 0) gstart = A->ev.gate_off[g];
+    }
   }
   __device__ __forceinline__ void end_gate(int64_t) { close(); }
-  __device__ __forceinline__ void event(int64_t e, int64_t t, int, int, float, uint32_t par_gs, uint32_t par) {
+  __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
+                                        uint32_t par) {
     const BinSpec& B = A->bins;
     if (t < 0 || t >= B.t_end) {  // outside the window: not packed
       close();
       return;
     }
-    const int64_t tile = bin_of(t, B) >> B.tile_log2;
-    if (open && tile == u_tile && u_len < A->ks.unit_cap) {
+    const int64_t bin = bin_of(t, B);
+    const int64_t tile = bin >> B.tile_log2;
+    const bool first = !(open && tile == u_tile && u_len < A->ks.unit_cap);
+    if (!first) {
       ++u_len;
-      return;
+    } else {
+      close();
+      open = true;
+      u_src = e;
+      u_len = 1;
+      u_tile = tile;
     }
-    close();
-    open = true;
-    u_src = e;
-    u_len = 1;
-    u_tile = tile;
-    u_st = ((init ^ par) & 0xffffu) | (((init ^ par_gs) & 0xffffu) << 16);
-    u_pins = make_uint2(init ^ par, init ^ par_gs);
+    if (kEmit) {
+      // Algorithm 1 per event: the table of the input state before the
+      // event's timestamp group, the leakage state once its pin has toggled
+      const CellMeta cm = L.meta[cell];
+      const uint32_t in_mask = state_mask(cm.n_in, L.all_pins);
+      const uint32_t before = init ^ par;
+      const uint32_t st = (init ^ par_gs) & in_mask;
+      uint32_t ti = st, li = (before ^ (1u << (pin & 31))) & in_mask;
+      uint32_t lk0 = 0;
+      if (cm.mode != kCellDirect) {
+        const uint2 w = wide_items(L.wide, cell, cm.mode, st, li);
+        ti = w.x;
+        li = w.y;
+        if (first) lk0 = wide_items(L.wide, cell, cm.mode, 0u, before & in_mask).y;
+      } else {
+        lk0 = before & 0xffffu;
+      }
+      int i;
+      float al;
+      slew_segment(L.slew + cm.axis_off, L.slew_inv + cm.axis_off, A->lib.n_slew, slew, i, al);
+      const uint32_t q = (uint32_t)(L.map_q[cm.map_off + 2 * (int)ti + v] + i * (A->lib.n_load - 1));
+      const uint32_t bl = (uint32_t)(bin - (tile << B.tile_log2));
+      const uint32_t rr = (uint32_t)(t - bin * B.D);
+      uint4 r;
+      r.x = (bl << B.r_bits) | rr | (li << kStateShift);
+      r.y = q | ((pin == cm.n_in ? 1u : 0u) << kOutBit) | ((uint32_t)v << 31);
+      r.z = __float_as_uint(al);
+      r.w = first ? (lk0 | ((uint32_t)cell << 16)) : 0u;
+      A->rec[e] = r;
+      span = fmaxf(span, fabsf(1.0f - al) + fabsf(al));
+      if (A->glitch_clk > 0) {
+        const float rg = glitch_ratio(A->ev.t, A->ev.pb, A->ev.slew, gstart, e, t, pin, slew, A->glitch_clk);
+        A->rgl[e] = rg > 0.f ? rg : 1.0f;
+      }
+      if (A->dbg_state) {
+        A->dbg_state[e] = (int32_t)st;
+        A->dbg_bin[e] = bin;
+      }
+    }
   }
 };
 
 // Emit pass: a workgroup's lane blocks own one contiguous run of units
-// [base[kb0], base[kb1]); when the run fits kEmitCap units, the lanes write
+// [base[kb0], base[kb1]) of at most 16 units per lane block; the lanes write
 // their units into LDS and the workgroup stores the run with coalesced writes
-// (each lane's units are scattered over the run otherwise).
-constexpr uint32_t kEmitCap = 2048;
-template <bool kEmit>
-__global__ void __launch_bounds__(kFwdThreads) k_pk_units(UnitArgs a, int64_t n_blocks) {
+// (each lane's units would be scattered over the run otherwise). Every lane
+// writes its block's event records itself (16 contiguous records per lane).
+constexpr uint32_t kEmitCap = (uint32_t)kLaneEvents * kFwdThreads;
+template <bool kEmit, class K>
+__global__ void __launch_bounds__(kFwdThreads) k_pk_units(UnitArgs<K> a, int64_t n_blocks) {
   const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (!kEmit) {
     if (kb >= n_blocks) return;
-    UnitVisitor<false> vis;
+    UnitVisitor<false, K> vis;
     vis.A = &a;
     vis.kb = kb;
     walk_block(kb, a.ev, a.plan, vis);
@@ -168,26 +237,27 @@ __global__ void __launch_bounds__(kFwdThreads) k_pk_units(UnitArgs a, int64_t n_
   extern __shared__ uint64_t lds64[];
   const int64_t kb0 = (int64_t)blockIdx.x * blockDim.x;
   const int64_t kb1 = min(kb0 + (int64_t)blockDim.x, n_blocks);
-  const uint32_t u0 = a.base[kb0], n_u = a.base[kb1] - u0;
-  const bool staged = n_u <= kEmitCap;   // uniform over the workgroup
-  UnitArgs la = a;
-  la.lkeys = staged ? lds64 : nullptr;
-  la.lrecs = staged ? reinterpret_cast<UnitRec*>(lds64 + kEmitCap) : nullptr;
-  la.lpins = (staged && a.upins) ? reinterpret_cast<uint2*>(lds64 + 3 * kEmitCap) : nullptr;
+  const uint32_t u0 = a.base[kb0], n_u = a.base[kb1] - u0;   // n_u <= kEmitCap
+  UnitArgs<K> la = a;
+  la.lkeys = reinterpret_cast<K*>(lds64);
+  la.lsrcs = reinterpret_cast<uint32_t*>(lds64 + kEmitCap * sizeof(K) / 8);
   la.u0 = u0;
+  uint32_t* llib = reinterpret_cast<uint32_t*>(lds64 + kEmitCap * (sizeof(K) + 4) / 8);
+  UnitVisitor<true, K> vis;
+  vis.L = stage_library(a.lib, llib);
+  __syncthreads();
   if (kb < n_blocks) {
-    UnitVisitor<true> vis;
     vis.A = &la;
     vis.kb = kb;
     walk_block(kb, a.ev, a.plan, vis);
   }
-  if (!staged) return;
+  float span = vis.span;
+  for (int o = 32; o > 0; o >>= 1) span = fmaxf(span, __shfl_xor(span, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(a.alpha_span, __float_as_int(span));
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < n_u; i += blockDim.x) {
     a.keys[u0 + i] = la.lkeys[i];
-    a.vals[u0 + i] = u0 + i;
-    a.recs[u0 + i] = la.lrecs[i];
-    if (la.lpins) a.upins[u0 + i] = la.lpins[i];
+    a.srcs[u0 + i] = la.lsrcs[i];
   }
 }
 
@@ -202,22 +272,22 @@ __global__ void __launch_bounds__(256) k_pk_fill_u64(uint64_t* p, int64_t n, uin
 }
 
 // First sorted unit of every non-empty tile (others keep their fill value).
-__global__ void __launch_bounds__(256) k_pk_tile_first(const uint64_t* skey, int64_t nu, int32_t shift,
-                                                       uint32_t* tfirst) {
+template <class K>
+__global__ void __launch_bounds__(256) k_pk_tile_first(const K* skey, int64_t nu, int32_t shift, uint32_t* tfirst) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nu) return;
-  const uint64_t t = skey[j] >> shift;
-  if (j == 0 || (skey[j - 1] >> shift) != t) tfirst[t] = (uint32_t)j;
+  const uint64_t t = (uint64_t)(skey[j] >> shift);
+  if (j == 0 || (uint64_t)(skey[j - 1] >> shift) != t) tfirst[t] = (uint32_t)j;
 }
 
 // First sorted unit of every non-empty (tile, gate block) region.
-__global__ void __launch_bounds__(256) k_pk_region_first(const uint64_t* skey, int64_t nu, int32_t gb_bits, int32_t low,
-                                                         int32_t n_gb, uint32_t* rfirst) {
+template <class K>
+__global__ void __launch_bounds__(256) k_pk_region_first(const K* skey, int64_t nu, KeyLayout L, int32_t n_gb,
+                                                         uint32_t* rfirst) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nu) return;
-  auto region = [&](uint64_t k) -> int64_t {
-    return (int64_t)(k >> (gb_bits + low)) * n_gb + (int64_t)((k >> low) & ((1ull << gb_bits) - 1ull));
-  };
+  const int shift = L.gb_bits + key_low(L);
+  auto region = [&](K k) -> int64_t { return (int64_t)(k >> shift) * n_gb + (int64_t)key_gb(k, L); };
   const int64_t r = region(skey[j]);
   if (j == 0 || region(skey[j - 1]) != r) rfirst[r] = (uint32_t)j;
 }
@@ -259,31 +329,25 @@ __global__ void __launch_bounds__(256) k_pk_tile_groups(const uint32_t* tfirst, 
   gk[k] = (k < n_tiles) ? (tfirst[k + 1] - tfirst[k] + kGroupUnits - 1) / kGroupUnits : 0u;
 }
 
-// Length of a unit from its sort key (16 - length is the field below the
-// gate within the block).
-__device__ __forceinline__ uint32_t key_len(uint64_t key, int32_t gb_log2) {
-  return 16u - (uint32_t)((key >> gb_log2) & 31u);
-}
-
 // One workgroup per tile, one wavefront per group: the group's events
 // (glen), its longest unit (gmax, the lane steps it costs a wavefront), and the
 // events of every (tile, gate block) region (rev, zeroed before; a group spans
 // few regions, each summed over its lanes and added once).
-__global__ void __launch_bounds__(256) k_pk_group_len(const uint32_t* tile_grp, const uint32_t* tfirst,
-                                                      const uint64_t* skey, int32_t gb_log2, int32_t gb_bits,
-                                                      int32_t n_gb, int64_t* glen, unsigned long long* rev,
+constexpr int kGroupLenThreads = 1024;
+template <class K>
+__global__ void __launch_bounds__(kGroupLenThreads) k_pk_group_len(const uint32_t* tile_grp, const uint32_t* tfirst, const K* skey,
+                                                      KeyLayout L, int32_t n_gb, int64_t* glen, unsigned long long* rev,
                                                       unsigned long long* lane_steps, uint32_t* max_tile_groups) {
   const int32_t k = blockIdx.x;
   const int lane = (int)(threadIdx.x & 63);
   const int64_t g0 = tile_grp[k], g1 = tile_grp[k + 1];
   const int64_t j1 = tfirst[k + 1];
-  const int low = 5 + gb_log2;
   unsigned long long steps = 0;
   for (int64_t g = g0 + (threadIdx.x >> 6); g < g1; g += blockDim.x >> 6) {
     const int64_t j = tfirst[k] + (g - g0) * kGroupUnits + lane;
     const bool act = j < j1;
-    const uint64_t key = act ? skey[j] : 0ull;
-    const uint32_t len = act ? key_len(key, gb_log2) : 0u;
+    const K key = act ? skey[j] : (K)0;
+    const uint32_t len = act ? key_len(key, L) : 0u;
     uint32_t s = len, mx = len;
     for (int o = 32; o > 0; o >>= 1) {
       s += __shfl_xor(s, o, 64);
@@ -294,7 +358,7 @@ __global__ void __launch_bounds__(256) k_pk_group_len(const uint32_t* tile_grp, 
       steps += mx;
     }
     // region events: one pass per distinct region among the active lanes
-    const int64_t reg = (int64_t)k * n_gb + (int64_t)((key >> low) & ((1ull << gb_bits) - 1ull));
+    const int64_t reg = (int64_t)k * n_gb + (int64_t)key_gb(key, L);
     uint64_t todo = __ballot(act);
     while (todo) {
       const int first = __ffsll((unsigned long long)todo) - 1;
@@ -312,94 +376,96 @@ __global__ void __launch_bounds__(256) k_pk_group_len(const uint32_t* tile_grp, 
 }
 
 struct FillArgs {
-  EvView ev;
   BinSpec bins;
-  LibView lib;                // device pointers of the library image
-  const int32_t* gcell;
+  KeyLayout kl;
+  const void* skeys;          // sorted unit keys
+  const uint32_t* ssrc;       // gate-major index of each sorted unit's first event
+  const int32_t* gb_start;    // [n_gb] first cell-sorted gate of each gate block
+  const uint4* rec;           // event records (gate-major)
+  const float* rgl_g;         // glitch detection on: energy factors (gate-major)
   const uint32_t* tile_grp;
   const uint32_t* tfirst;
-  const uint32_t* sidx;
-  const UnitRec* recs;
   const int64_t* grp_off;
   uint32_t* w32;
   uint32_t* row;
   float* alpha;
+  float* rgl;
   uint2* desc;
-  int32_t* dbg_state;         // optional, gate-major: state before the event's group
-  int64_t* dbg_bin;           // optional, gate-major: bin of the event
-  int32_t* alpha_span;        // max over events of |1 - alpha| + |alpha| (FP32 bits; positive floats order as ints)
+  int4* gquads;               // optional: quad range of every group's cells (see below)
+  const int32_t* cq_lo;       // [n_cells] quad range of each cell's tables
+  const int32_t* cq_hi;
   int32_t* max_bin;           // most events in one bin
-  const int32_t* gperm;       // cell-sorted index -> gate
-  int64_t glitch_clk;         // > 0: glitch detection with this clock period
-  float* rgl;                 // energy factor per event (glitch detection on)
-  const uint2* upins;         // per unit, all pin values (set when some cell has more than 8 state pins)
 };
 
-// Table item of state st and leakage item of state sl of a cell with more
-// than 8 state pins (kept out of line: rare, and it would stop the event loop
-// of k_pk_fill from unrolling).
-__device__ __noinline__ uint2 wide_items(WideView W, int cell, int mode, uint32_t st, uint32_t sl) {
-  return make_uint2((uint32_t)wide_item(W, cell, mode, st, false), (uint32_t)wide_item(W, cell, mode, sl, true));
-}
+// Item of workgroup w in a grid of n workgroups (n a multiple of 8), so that
+// XCD x = w % 8 takes items [x n/8, (x+1) n/8) in launch order.
+__device__ __forceinline__ int64_t xcd_item(int64_t w, int64_t n) { return (w % 8) * (n / 8) + w / 8; }
 
 // One workgroup per tile, one wavefront per group of the tile, one lane per
-// unit: the unit descriptor, and every event's record in the unit-interleaved
-// order. The lane tracks its gate's pin values from the carried-in values, as
-// the gate-major walk does: the table is selected by the input state before
-// the event's timestamp group, the leakage state after the event is the input
-// state once the event's pin has toggled. All of a unit's event loads are
-// issued before any is used (the unit's events are scattered over the
-// gate-major array, so the loads are latency-bound), and the library's map
-// and axes are read from LDS.
-template <int kS>
-__global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
+// unit: the unit descriptor (its gate and length from the sort key, the
+// leakage state before it and its cell from its first event's record), and
+// its event records moved to the unit-interleaved order (the loads of a
+// unit's records are issued before any is used: they are scattered over the
+// gate-major record array). With gquads set, every group also leaves the
+// union of its cells' table quad ranges and its first unit's cell range (lo,
+// hi, first lo, first hi; all -1 for an empty group).
+constexpr int kFillThreads = 1024;
+template <int kS, class K>
+__global__ void __launch_bounds__(kFillThreads) k_pk_fill(FillArgs a) {
+  // tiles go to XCDs in contiguous ranges (workgroup w runs on XCD w % 8):
+  // a gate's records of neighbouring tiles share cache lines, and the
+  // workgroups of neighbouring tiles then read them through one L2
+  const int32_t k = (int32_t)xcd_item(blockIdx.x, gridDim.x);
+  if (k >= a.bins.n_tiles) return;
   extern __shared__ uint32_t lds[];
-  const LdsLib L = stage_library(a.lib, lds);
-  int32_t* hist = reinterpret_cast<int32_t*>(lds + ((a.lib.lds_words + 3) & ~3));   // events per bin of the tile
+  int32_t* hist = reinterpret_cast<int32_t*>(lds);   // events per bin of the tile
   const BinSpec& B = a.bins;
   for (int i = threadIdx.x; i < (1 << B.tile_log2); i += blockDim.x) hist[i] = 0;
   __syncthreads();
-  const int32_t k = blockIdx.x;
   const int lane = (int)(threadIdx.x & 63);
   const int64_t g0 = a.tile_grp[k], g1 = a.tile_grp[k + 1];
   const int64_t jend = a.tfirst[k + 1];
-  const int32_t qstride = a.lib.n_load - 1;
-  float span = 1.0f;   // |1 - alpha| + |alpha| of the lane's events (1 inside the axis)
+  const K* skeys = static_cast<const K*>(a.skeys);
+  const KeyLayout kl = a.kl;
   for (int64_t gi = g0 + (threadIdx.x >> 6); gi < g1; gi += blockDim.x >> 6) {
     const int64_t j = (int64_t)a.tfirst[k] + (gi - g0) * kGroupUnits + lane;
     const bool act = j < jend;
-    UnitRec r{0, 0xffffffffu, 0u};
-    if (act) r = a.recs[a.sidx[j]];
-    const int cell = act ? a.gcell[r.x & 0x0fffffffu] : 0;
-    uint32_t cur = r.y & 0xffffu;   // pin values before the unit's first event
-    uint32_t gsv = r.y >> 16;       // pin values before that event's timestamp group
-    if (a.upins && act) {
-      const uint2 up = a.upins[a.sidx[j]];
-      cur = up.x;
-      gsv = up.y;
+    int len = 0;
+    uint32_t rank = 0;
+    int64_t src = 0;
+    if (act) {
+      const K key = skeys[j];
+      src = (int64_t)a.ssrc[j];
+      len = (int)key_len(key, kl);
+      rank = (uint32_t)a.gb_start[key_gb(key, kl)] + (uint32_t)(key & (K)((1u << kl.gin_bits) - 1u));
     }
-    const CellMeta cm = L.meta[cell];
-    const uint32_t in_mask = state_mask(cm.n_in, L.all_pins);   // pins of the state index
-    // descriptor: y = the leakage state before the unit's first event (its
-    // pin values for a kCellDirect cell, else its leakage item) | cell << 16
-    const uint32_t lk0 = cm.mode == kCellDirect ? (cur & 0xffffu) : wide_items(L.wide, cell, cm.mode, 0u, cur & in_mask).y;
-    a.desc[gi * kGroupUnits + lane] = make_uint2(r.x, lk0 | ((uint32_t)cell << 16));
-    const int len = act ? (int)(r.x >> 28) + 1 : 0;
-    int64_t tt[kS];
-    uint32_t pb[kS];
-    float sl[kS];
+    uint4 r[kS];
+    float rg[kS];
 #pragma unroll
     for (int kk = 0; kk < kS; ++kk) {
       if (kk < len) {
-        tt[kk] = a.ev.t[r.src + kk];
-        pb[kk] = a.ev.pb[r.src + kk];
-        sl[kk] = a.ev.slew[r.src + kk];
+        r[kk] = a.rec[src + kk];
+        if (a.rgl) rg[kk] = a.rgl_g[src + kk];
       }
     }
-    const int64_t gstart = (a.glitch_clk > 0 && act) ? a.ev.gate_off[a.gperm[r.x & 0x0fffffffu]] : 0;
-    const float* axis = L.slew + cm.axis_off;
-    const float* inv = L.slew_inv + cm.axis_off;
-    int64_t tprev = 0;
+    const uint32_t dy = act ? r[0].w : 0u;   // leakage state before the unit | cell << 16
+    const uint32_t dx = act ? (rank | ((uint32_t)(len - 1) << 28)) : 0xffffffffu;
+    a.desc[gi * kGroupUnits + lane] = make_uint2(dx, dy);
+    if (a.gquads) {
+      const uint64_t m = __ballot(act);
+      if (m == 0) {
+        if (lane == 0) a.gquads[gi] = make_int4(-1, -1, -1, -1);
+      } else {
+        const int cell = (int)(dy >> 16);
+        const int32_t clo = act ? a.cq_lo[cell] : INT32_MAX, chi = act ? a.cq_hi[cell] : INT32_MIN;
+        int32_t lo = clo, hi = chi;
+        for (int o = 32; o > 0; o >>= 1) {
+          lo = min(lo, __shfl_xor(lo, o, 64));
+          hi = max(hi, __shfl_xor(hi, o, 64));
+        }
+        if (lane == __ffsll((unsigned long long)m) - 1) a.gquads[gi] = make_int4(lo, hi, clo, chi);
+      }
+    }
     int64_t off = a.grp_off[gi];
 #pragma unroll
     for (int kk = 0; kk < kS; ++kk) {
@@ -409,47 +475,15 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
       if (on) {
         const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
         const int64_t pos = off + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-        const int64_t t = tt[kk];
-        if (kk > 0 && t != tprev) gsv = cur;
-        tprev = t;
-        const uint32_t pin = (pb[kk] >> 1) & 31u;
-        const uint32_t v = pb[kk] & 1u;
-        const uint32_t st = gsv & in_mask;
-        cur ^= 1u << pin;
-        const int64_t bin = bin_of(t, B);
-        const uint32_t bl = (uint32_t)(bin - ((int64_t)k << B.tile_log2));
-        const uint32_t rr = (uint32_t)(t - bin * B.D);
-        int i;
-        float al;
-        slew_segment(axis, inv, a.lib.n_slew, sl[kk], i, al);
-        uint32_t ti = st, li = cur & in_mask;   // table and leakage entries relative to the cell's first
-        if (cm.mode != kCellDirect) {
-          const uint2 w = wide_items(L.wide, cell, cm.mode, st, li);
-          ti = w.x;
-          li = w.y;
-        }
-        const uint32_t q = (uint32_t)(L.map_q[cm.map_off + 2 * (int)ti + (int)v] + i * qstride);
-        atomicAdd(&hist[bl], 1);
-        a.w32[pos] = (bl << B.r_bits) | rr | (li << kStateShift);
-        a.row[pos] = q | ((pin == (uint32_t)cm.n_in ? 1u : 0u) << kOutBit) | (v << 31);
-        a.alpha[pos] = al;
-        if (a.glitch_clk > 0) {
-          const float rg = glitch_ratio(a.ev.t, a.ev.pb, a.ev.slew, gstart, r.src + kk, t, (int)(pb[kk] >> 1), sl[kk],
-                                        a.glitch_clk);
-          a.rgl[pos] = rg > 0.f ? rg : 1.0f;
-        }
-        span = fmaxf(span, fabsf(1.0f - al) + fabsf(al));
-        if (a.dbg_state) {
-          const int64_t e = r.src + kk;
-          a.dbg_state[e] = (int32_t)st;
-          a.dbg_bin[e] = bin;
-        }
+        atomicAdd(&hist[(r[kk].x & kTimeMask) >> B.r_bits], 1);
+        a.w32[pos] = r[kk].x;
+        a.row[pos] = r[kk].y;
+        a.alpha[pos] = __uint_as_float(r[kk].z);
+        if (a.rgl) a.rgl[pos] = rg[kk];
       }
       off += __popcll(m);
     }
   }
-  for (int o = 32; o > 0; o >>= 1) span = fmaxf(span, __shfl_xor(span, o, 64));
-  if (lane == 0) atomicMax(a.alpha_span, __float_as_int(span));
   __syncthreads();
   int mx = 0;
   for (int i = threadIdx.x; i < (1 << B.tile_log2); i += blockDim.x) mx = max(mx, hist[i]);
@@ -457,73 +491,62 @@ __global__ void __launch_bounds__(256) k_pk_fill(FillArgs a) {
   if (lane == 0 && mx > 0) atomicMax(a.max_bin, mx);
 }
 
-// Quad range of a group: the union of its units' cell table ranges
-// [cq_lo, cq_hi) (the table ranges of cells need not follow the cell order),
-// and the range of its first unit's cell: (lo, hi, first lo, first hi), all
-// -1 for an empty group.
-__global__ void __launch_bounds__(256) k_pk_group_quads(const uint2* desc, int64_t n_groups, const int32_t* cq_lo,
-                                                        const int32_t* cq_hi, int32_t n_cells, int4* gq) {
-  const int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroupUnits;
-  const int lane = (int)(threadIdx.x & (kGroupUnits - 1));
-  if (gi >= n_groups) return;
-  const uint2 d = desc[gi * kGroupUnits + lane];
-  const int cell = (int)(d.y >> 16);
-  const bool v = d.x != 0xffffffffu && cell < n_cells;
-  const uint64_t m = __ballot(v);
-  if (m == 0) {
-    if (lane == 0) gq[gi] = make_int4(-1, -1, -1, -1);
-    return;
-  }
-  int32_t lo = v ? cq_lo[cell] : INT32_MAX, hi = v ? cq_hi[cell] : INT32_MIN;
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = min(lo, __shfl_xor(lo, o, 64));
-    hi = max(hi, __shfl_xor(hi, o, 64));
-  }
-  const int first = __ffsll((unsigned long long)m) - 1;
-  if (lane == first) gq[gi] = make_int4(lo, hi, cq_lo[cell], cq_hi[cell]);
-}
-
-// Table phases of one tile (one wavefront per tile, the decisions taken in
-// lockstep by every lane): a phase starts at a group and grows while the
-// union of its groups' cell table ranges [cq_lo, cq_hi) fits the slot; a
+// Table phases of one tile (one wavefront per tile): a phase starts at a
+// group and grows while the union of its groups' cell table ranges
+// [cq_lo, cq_hi) fits the slot (empty groups join the phase they fall in); a
 // single group whose cells exceed the slot keeps its first cell's quads
-// (full = 0: the other lanes read global memory). Phases are written at the
-// tile's first group index (a tile has at most as many phases as groups) and
-// counted in n_ph; k_pk_phase_copy compacts them.
-constexpr int kPhaseChunk = 2048;   // groups staged in LDS at a time
+// (full = 0: the other lanes read global memory). The wavefront looks at 64
+// groups at a time: the span of the union grows with every group, so the
+// phase ends at the first lane whose prefix union exceeds the slot. Phases are
+// written at the tile's first group index (a tile has at most as many phases
+// as groups) and counted in n_ph; k_pk_phase_copy compacts them.
 __global__ void __launch_bounds__(64) k_pk_phases(const int4* gq, const uint32_t* tile_grp, int64_t cap,
                                                   int4* ph_tmp, uint32_t* n_ph, int32_t* all_full) {
-  __shared__ int4 cc_sh[kPhaseChunk];
   const int32_t k = blockIdx.x;
+  const int lane = (int)threadIdx.x;
   const int64_t g0 = tile_grp[k], g1 = tile_grp[k + 1];
-  bool staged = false;   // cc_sh holds groups [cbase, cbase + kPhaseChunk)
-  int64_t cbase = 0;
   // quad ranges of group e (an inconsistent range counts as an empty group)
   auto quads_of = [&](int64_t e) -> int4 {
-    if (!staged || e < cbase || e >= cbase + kPhaseChunk) {
-      __syncthreads();
-      staged = true;
-      cbase = e;
-      for (int i = threadIdx.x; i < kPhaseChunk; i += 64)
-        cc_sh[i] = (e + i < g1) ? gq[e + i] : make_int4(-1, -1, -1, -1);
-      __syncthreads();
-    }
-    const int4 r = cc_sh[e - cbase];
+    const int4 r = gq[e];
     return (r.x >= 0 && r.y >= r.x && r.z >= r.x && r.w >= r.z && r.w <= r.y) ? r : make_int4(-1, -1, -1, -1);
   };
   uint32_t np = 0;
   int32_t full_all = 1;
   int64_t g = g0;
   while (g < g1) {
-    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    int64_t lo = INT64_MAX, hi = INT64_MIN;   // union of the phase's groups so far
     int64_t e = g;
-    for (; e < g1; ++e) {
-      const int4 r = quads_of(e);
-      if (r.x < 0) continue;
-      const int64_t nl = min(lo, (int64_t)r.x), nh = max(hi, (int64_t)r.y);
-      if (e > g && nh - nl > cap) break;
-      lo = nl;
-      hi = nh;
+    for (;;) {
+      const int64_t idx = e + lane;
+      const int4 r = idx < g1 ? quads_of(idx) : make_int4(-1, -1, -1, -1);
+      const bool val = r.x >= 0;
+      int64_t plo = val ? (int64_t)r.x : INT64_MAX, phi = val ? (int64_t)r.y : INT64_MIN;
+      for (int o = 1; o < 64; o <<= 1) {   // inclusive prefix union over the lanes
+        const int64_t ulo = __shfl_up(plo, o, 64), uhi = __shfl_up(phi, o, 64);
+        if (lane >= o) {
+          plo = min(plo, ulo);
+          phi = max(phi, uhi);
+        }
+      }
+      const int64_t nl = min(lo, plo), nh = max(hi, phi);
+      const uint64_t brk = __ballot(val && idx > g && nh - nl > cap);
+      if (brk) {
+        const int f = __ffsll((unsigned long long)brk) - 1;   // > 0 unless the phase started in an earlier chunk
+        const int64_t bl = __shfl(nl, max(f - 1, 0), 64), bh = __shfl(nh, max(f - 1, 0), 64);
+        if (f > 0) {
+          lo = bl;
+          hi = bh;
+        }
+        e += f;
+        break;
+      }
+      lo = __shfl(nl, 63, 64);
+      hi = __shfl(nh, 63, 64);
+      e += 64;
+      if (e >= g1) {
+        e = g1;
+        break;
+      }
     }
     if (lo == INT64_MAX) {  // only empty groups: nothing to stage
       lo = 0;
@@ -537,11 +560,11 @@ __global__ void __launch_bounds__(64) k_pk_phases(const int4* gq, const uint32_t
       full = 0;
       full_all = 0;
     }
-    if (threadIdx.x == 0) ph_tmp[g0 + np] = make_int4((int32_t)(e - g0), (int32_t)lo, (int32_t)(hi - lo), full);
+    if (lane == 0) ph_tmp[g0 + np] = make_int4((int32_t)(e - g0), (int32_t)lo, (int32_t)(hi - lo), full);
     ++np;
     g = e;
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     n_ph[k] = np;
     if (!full_all) atomicAnd(all_full, 0);
   }
@@ -630,6 +653,70 @@ void scan_add(const T* in, T* out, T* sums, int64_t n, hipStream_t s) {
 }
 
 int64_t scan_sums_items(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+// Key-type dispatch of the unit steps.
+template <class K>
+hipError_t launch_emit(const UnitArgs<uint32_t>& u, void* keys, uint32_t* srcs, int64_t n_blocks, unsigned grid,
+                       hipStream_t s) {
+  UnitArgs<K> a;
+  a.ev = u.ev;
+  a.plan = u.plan;
+  a.gate_cell = u.gate_cell;
+  a.gate_init = u.gate_init;
+  a.bins = u.bins;
+  a.ks = u.ks;
+  a.counts = u.counts;
+  a.base = u.base;
+  a.keys = static_cast<K*>(keys);
+  a.srcs = srcs;
+  a.lkeys = nullptr;
+  a.lsrcs = nullptr;
+  a.u0 = 0;
+  a.lib = u.lib;
+  a.rec = u.rec;
+  a.rgl = u.rgl;
+  a.glitch_clk = u.glitch_clk;
+  a.dbg_state = u.dbg_state;
+  a.dbg_bin = u.dbg_bin;
+  a.alpha_span = u.alpha_span;
+  // staged keys and first events, then the library image
+  const size_t lds = (size_t)kEmitCap * (sizeof(K) + sizeof(uint32_t)) + (size_t)((u.lib.lds_words + 3) & ~3) * 4;
+  const hipError_t e =
+      hipFuncSetAttribute((const void*)k_pk_units<true, K>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_pk_units<true, K>), dim3(grid), dim3(kFwdThreads), lds, s, a, n_blocks);
+  return hipSuccess;
+}
+
+// Stable radix sort of the unit keys with their first events (tmp null:
+// the temporary size only).
+hipError_t sort_units(bool key64, void* tmp, size_t& tb, void* keys, void* skeys, uint32_t* srcs, uint32_t* ssrc,
+                      int64_t n, int bits, hipStream_t s) {
+  if (key64)
+    return rocprim::radix_sort_pairs(tmp, tb, static_cast<uint64_t*>(keys), static_cast<uint64_t*>(skeys), srcs, ssrc,
+                                     n, 0, bits, s);
+  return rocprim::radix_sort_pairs(tmp, tb, static_cast<uint32_t*>(keys), static_cast<uint32_t*>(skeys), srcs, ssrc,
+                                   n, 0, bits, s);
+}
+
+hipError_t launch_fill(bool short_units, bool key64, const FillArgs& fa, unsigned grid, size_t lds, hipStream_t s) {
+  const void* fn = short_units ? (key64 ? (const void*)k_pk_fill<8, uint64_t> : (const void*)k_pk_fill<8, uint32_t>)
+                               : (key64 ? (const void*)k_pk_fill<16, uint64_t> : (const void*)k_pk_fill<16, uint32_t>);
+  const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e != hipSuccess) return e;
+  if (short_units) {
+    if (key64)
+      hipLaunchKernelGGL((k_pk_fill<8, uint64_t>), dim3(grid), dim3(kFillThreads), lds, s, fa);
+    else
+      hipLaunchKernelGGL((k_pk_fill<8, uint32_t>), dim3(grid), dim3(kFillThreads), lds, s, fa);
+  } else {
+    if (key64)
+      hipLaunchKernelGGL((k_pk_fill<16, uint64_t>), dim3(grid), dim3(kFillThreads), lds, s, fa);
+    else
+      hipLaunchKernelGGL((k_pk_fill<16, uint32_t>), dim3(grid), dim3(kFillThreads), lds, s, fa);
+  }
+  return hipSuccess;
+}
 
 }  // namespace
 
@@ -736,12 +823,22 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       snprintf(err, err_len, "pack: %d cells, %lld gates", n_cells, (long long)G);
       return hipErrorInvalidValue;
     }
-    const int gb_bits = ceil_log2_u64((uint64_t)n_gb);
-    const int tile_bits = std::max(1, ceil_log2_u64((uint64_t)n_tiles));
-    const int low = 5 + in.gate_block_log2;   // length and gate-within-block fields
-    const int key_bits = tile_bits + gb_bits + low;
+    KeyLayout kl;
+    kl.len_bits = ceil_log2_u64((uint64_t)std::max(in.unit_events, 1));
+    kl.gin_bits = in.gate_block_log2;
+    kl.gb_bits = ceil_log2_u64((uint64_t)n_gb);
+    kl.tile_bits = std::max(1, ceil_log2_u64((uint64_t)n_tiles));
+    const int gb_bits = kl.gb_bits;
+    const int low = key_low(kl);   // length and gate-within-block fields
+    const int key_bits = kl.tile_bits + gb_bits + low;
     if (key_bits > 64) {
       snprintf(err, err_len, "pack: sort key of %d bits", key_bits);
+      return hipErrorInvalidValue;
+    }
+    const bool key64 = key_bits > 32;
+    const size_t ksz = key64 ? 8 : 4;
+    if (N >= (int64_t)UINT32_MAX) {   // units name their first event with 32 bits
+      snprintf(err, err_len, "pack: %lld events in one layout (at most 2^32 - 1; use time windows)", (long long)N);
       return hipErrorInvalidValue;
     }
     const int64_t n_blocks = (N + kLaneEvents - 1) / kLaneEvents;
@@ -762,7 +859,8 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
                                   48 + std::max(1, ceil_log2_u64((uint64_t)n_cells)), s));
     const size_t ws1 = align256((size_t)G * 4) + 2 * align256((size_t)n_cells * 4) + 3 * align256((size_t)G * 8) +
                        align256(gsort_tmp) + 2 * align256((size_t)(n_blocks + 1) * 4) +
-                       align256((size_t)scan_sums_items(n_blocks + 1) * 4) + align256(64);
+                       align256((size_t)scan_sums_items(n_blocks + 1) * 4) + align256(64) +
+                       align256((size_t)n_gb * 4);
     PK(reserve(ws, ws1));
     Bump wb{(char*)ws->p, ws->bytes};
     int32_t* d_rank = wb.take<int32_t>((size_t)G);
@@ -772,6 +870,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     uint32_t* ubase = wb.take<uint32_t>((size_t)n_blocks + 1);
     uint32_t* usums = wb.take<uint32_t>((size_t)scan_sums_items(n_blocks + 1));
     uint32_t* d_nu = wb.take<uint32_t>(16);
+    int32_t* d_gbs = wb.take<int32_t>((size_t)n_gb);
     if (G > 0) {
       uint64_t* gk = wb.take<uint64_t>((size_t)G);
       uint64_t* gks = wb.take<uint64_t>((size_t)G);
@@ -794,16 +893,16 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     }
     PK(hipMemcpyAsync(d_cs, cell_start.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
     PK(hipMemcpyAsync(d_gbb, gb_base.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
+    PK(hipMemcpyAsync(d_gbs, o.h_gb_start.data(), (size_t)n_gb * 4, hipMemcpyHostToDevice, s));
 
     // ---- 2. unit counts ----------------------------------------------------
-    UnitArgs ua;
+    UnitArgs<uint32_t> ua;
     ua.ev = in.ev;
     ua.plan = in.plan_blk;
     ua.gate_cell = in.gate_cell;
     ua.gate_init = in.gate_init;
     ua.bins = B;
-    ua.ks.gb_bits = gb_bits;
-    ua.ks.gb_log2 = in.gate_block_log2;
+    ua.ks.L = kl;
     ua.ks.unit_cap = in.unit_events;
     ua.ks.rank = d_rank;
     ua.ks.cell_start = d_cs;
@@ -811,17 +910,21 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     ua.counts = counts;
     ua.base = ubase;
     ua.keys = nullptr;
-    ua.vals = nullptr;
-    ua.recs = nullptr;
-    ua.upins = nullptr;
+    ua.srcs = nullptr;
     ua.lkeys = nullptr;
-    ua.lrecs = nullptr;
-    ua.lpins = nullptr;
+    ua.lsrcs = nullptr;
     ua.u0 = 0;
+    ua.lib = LibView();
+    ua.rec = nullptr;
+    ua.rgl = nullptr;
+    ua.glitch_clk = 0;
+    ua.dbg_state = nullptr;
+    ua.dbg_bin = nullptr;
+    ua.alpha_span = nullptr;
     int64_t NU = 0;
     if (n_blocks > 0) {
       const unsigned gridb = (unsigned)((n_blocks + kFwdThreads - 1) / kFwdThreads);
-      hipLaunchKernelGGL((k_pk_units<false>), dim3(gridb), dim3(kFwdThreads), 0, s, ua, n_blocks);
+      hipLaunchKernelGGL((k_pk_units<false, uint32_t>), dim3(gridb), dim3(kFwdThreads), 0, s, ua, n_blocks);
       PKLAUNCH("k_pk_units<count>");
       hipLaunchKernelGGL(k_pk_fill_u32, dim3(1), dim3(256), 0, s, counts + n_blocks, (int64_t)1, 0u);
       PKLAUNCH("k_pk_fill_u32");
@@ -837,25 +940,22 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
 
     // workspace, phase 2 (a second buffer: the first one's pieces stay in use)
     size_t usort_tmp = 0;
-    if (NU > 0)
-      PK(rocprim::radix_sort_pairs(nullptr, usort_tmp, (uint64_t*)nullptr, (uint64_t*)nullptr, (uint32_t*)nullptr,
-                                   (uint32_t*)nullptr, (int64_t)NU, 0, key_bits, s));
+    if (NU > 0) PK(sort_units(key64, nullptr, usort_tmp, nullptr, nullptr, nullptr, nullptr, NU, key_bits, s));
     const int64_t ng_max = NU / kGroupUnits + n_tiles + 1;   // groups per tile: ceil(units / 64)
-    const size_t ws2 = 2 * align256((size_t)NU * 8) + 2 * align256((size_t)NU * 4) +
-                       align256((size_t)NU * sizeof(UnitRec)) + align256(usort_tmp) +
+    const size_t ws2 = 2 * align256((size_t)NU * ksz) + 2 * align256((size_t)NU * 4) + align256(usort_tmp) +
                        align256((size_t)(n_tiles + 1) * 4) + align256((size_t)scan_sums_items(n_tiles + 1) * 4) +
                        align256((size_t)(ng_max + 1) * 8) + align256((size_t)scan_sums_items(ng_max + 1) * 8) +
                        align256((size_t)std::max<int64_t>(n_reg, 1) * 8) +
                        2 * align256((size_t)ng_max * sizeof(int4)) +
                        align256((size_t)(n_tiles + 1) * 4) + align256((size_t)scan_sums_items(n_tiles + 1) * 4) +
-                       align256((size_t)n_cells * 8) + (in.wide_cells ? align256((size_t)NU * 8) : 0) + 4096;
+                       align256((size_t)n_cells * 8) + align256((size_t)N * sizeof(uint4)) +
+                       (in.glitch_clk > 0 ? align256((size_t)N * 4) : 0) + 4096;
     PK(reserve(ws2b, ws2));
     Bump wc{(char*)ws2b->p, ws2b->bytes};
-    uint64_t* keys = wc.take<uint64_t>((size_t)NU);
-    uint64_t* skeys = wc.take<uint64_t>((size_t)NU);
-    uint32_t* vals = wc.take<uint32_t>((size_t)NU);
-    uint32_t* sidx = wc.take<uint32_t>((size_t)NU);
-    UnitRec* recs = wc.take<UnitRec>((size_t)NU);
+    void* keys = wc.take<char>((size_t)NU * ksz);
+    void* skeys = wc.take<char>((size_t)NU * ksz);
+    uint32_t* srcs = wc.take<uint32_t>((size_t)NU);
+    uint32_t* ssrc = wc.take<uint32_t>((size_t)NU);
     void* tsortu = wc.take<char>(usort_tmp);
     uint32_t* gk = wc.take<uint32_t>((size_t)n_tiles + 1);
     uint32_t* tsums = wc.take<uint32_t>((size_t)scan_sums_items(n_tiles + 1));
@@ -866,8 +966,10 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     int4* ph_tmp = wc.take<int4>((size_t)ng_max);
     uint32_t* nph = wc.take<uint32_t>((size_t)n_tiles + 1);
     uint32_t* psums = wc.take<uint32_t>((size_t)scan_sums_items(n_tiles + 1));
-    uint2* upins = in.wide_cells ? wc.take<uint2>((size_t)NU) : nullptr;
-    if (!psums || (in.wide_cells && !upins)) {
+    int32_t* d_cq = wc.take<int32_t>(2 * (size_t)n_cells);
+    uint4* rec = wc.take<uint4>((size_t)N);
+    float* rgl_g = in.glitch_clk > 0 ? wc.take<float>((size_t)N) : nullptr;
+    if (!d_cq || !rec || (in.glitch_clk > 0 && !rgl_g)) {
       snprintf(err, err_len, "pack: workspace of %zu bytes too small", ws2b->bytes);
       st = hipErrorOutOfMemory;
       goto fail;
@@ -879,17 +981,21 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       PK(hipMemcpyAsync(d_nu, init, sizeof init, hipMemcpyHostToDevice, s));
     }
     if (NU > 0) {
-      ua.keys = keys;
-      ua.vals = vals;
-      ua.recs = recs;
-      ua.upins = upins;
+      // ---- 3. units --------------------------------------------------------
       const unsigned gridb = (unsigned)((n_blocks + kFwdThreads - 1) / kFwdThreads);
-      const size_t elds = (size_t)kEmitCap * (sizeof(uint64_t) + sizeof(UnitRec) + (upins ? sizeof(uint2) : 0));
-      hipLaunchKernelGGL((k_pk_units<true>), dim3(gridb), dim3(kFwdThreads), elds, s, ua, n_blocks);
+      ua.lib = in.lib;
+      ua.rec = rec;
+      ua.rgl = rgl_g;
+      ua.glitch_clk = in.glitch_clk;
+      ua.dbg_state = in.dbg_state;
+      ua.dbg_bin = in.dbg_bin;
+      ua.alpha_span = (int32_t*)d_nu;
+      PK(key64 ? launch_emit<uint64_t>(ua, keys, srcs, n_blocks, gridb, s)
+               : launch_emit<uint32_t>(ua, keys, srcs, n_blocks, gridb, s));
       PKLAUNCH("k_pk_units<emit>");
       // ---- 4. sort --------------------------------------------------------
       size_t tb = usort_tmp;
-      PK(rocprim::radix_sort_pairs(tsortu, tb, keys, skeys, vals, sidx, (int64_t)NU, 0, key_bits, s));
+      PK(sort_units(key64, tsortu, tb, keys, skeys, srcs, ssrc, NU, key_bits, s));
     }
     // ---- 5. tiles and groups -------------------------------------------
     o.tfirst = (uint32_t*)own((size_t)(n_tiles + 1) * 4, e2);
@@ -900,8 +1006,13 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
                        (int64_t)(n_tiles + 1), (uint32_t)NU);
     PKLAUNCH("k_pk_fill_u32");
     if (NU > 0) {
-      hipLaunchKernelGGL(k_pk_tile_first, dim3((unsigned)((NU + 255) / 256)), dim3(256), 0, s, skeys, NU,
-                         gb_bits + low, o.tfirst);
+      const dim3 gu((unsigned)((NU + 255) / 256));
+      if (key64)
+        hipLaunchKernelGGL(k_pk_tile_first<uint64_t>, gu, dim3(256), 0, s, (const uint64_t*)skeys, NU,
+                           gb_bits + low, o.tfirst);
+      else
+        hipLaunchKernelGGL(k_pk_tile_first<uint32_t>, gu, dim3(256), 0, s, (const uint32_t*)skeys, NU,
+                           gb_bits + low, o.tfirst);
       PKLAUNCH("k_pk_tile_first");
     }
     hipLaunchKernelGGL(k_pk_suffix_min, dim3(1), dim3(1024), 0, s, o.tfirst, (int64_t)(n_tiles + 1));
@@ -931,9 +1042,14 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
                          (uint64_t)0);
       PKLAUNCH("k_pk_fill_u64");
     }
-    hipLaunchKernelGGL(k_pk_group_len, dim3((unsigned)n_tiles), dim3(256), 0, s, (const uint32_t*)o.tile_grp,
-                       (const uint32_t*)o.tfirst, (const uint64_t*)skeys, (int32_t)in.gate_block_log2, (int32_t)gb_bits,
-                       n_gb, glen, (unsigned long long*)rev, (unsigned long long*)(d_nu + 2), d_nu + 4);
+    if (key64)
+      hipLaunchKernelGGL(k_pk_group_len<uint64_t>, dim3((unsigned)n_tiles), dim3(kGroupLenThreads), 0, s,
+                         (const uint32_t*)o.tile_grp, (const uint32_t*)o.tfirst, (const uint64_t*)skeys, kl, n_gb,
+                         glen, (unsigned long long*)rev, (unsigned long long*)(d_nu + 2), d_nu + 4);
+    else
+      hipLaunchKernelGGL(k_pk_group_len<uint32_t>, dim3((unsigned)n_tiles), dim3(kGroupLenThreads), 0, s,
+                         (const uint32_t*)o.tile_grp, (const uint32_t*)o.tfirst, (const uint32_t*)skeys, kl, n_gb,
+                         glen, (unsigned long long*)rev, (unsigned long long*)(d_nu + 2), d_nu + 4);
     PKLAUNCH("k_pk_group_len");
     scan_add<int64_t>(glen, o.grp_off, gsums, ng + 1, s);
     PKLAUNCH("scan of group events");
@@ -943,8 +1059,13 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
                        n_reg + 1, (uint32_t)NU);
     PKLAUNCH("k_pk_fill_u32");
     if (NU > 0) {
-      hipLaunchKernelGGL(k_pk_region_first, dim3((unsigned)((NU + 255) / 256)), dim3(256), 0, s, skeys, NU, gb_bits,
-                         low, n_gb, o.reg_first);
+      const dim3 gu((unsigned)((NU + 255) / 256));
+      if (key64)
+        hipLaunchKernelGGL(k_pk_region_first<uint64_t>, gu, dim3(256), 0, s, (const uint64_t*)skeys, NU, kl, n_gb,
+                           o.reg_first);
+      else
+        hipLaunchKernelGGL(k_pk_region_first<uint32_t>, gu, dim3(256), 0, s, (const uint32_t*)skeys, NU, kl, n_gb,
+                           o.reg_first);
       PKLAUNCH("k_pk_region_first");
     }
     hipLaunchKernelGGL(k_pk_suffix_min, dim3(1), dim3(1024), 0, s, o.reg_first, n_reg + 1);
@@ -964,68 +1085,56 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       o.rgl = (float*)own((size_t)N * 4, e2);
       PK(e2);
     }
-    if (ng > 0) {
-      FillArgs fa;
-      fa.ev = in.ev;
-      fa.bins = B;
-      fa.lib = in.lib;
-      fa.gcell = o.gcell;
-      fa.tile_grp = (const uint32_t*)o.tile_grp;
-      fa.tfirst = o.tfirst;
-      fa.sidx = sidx;
-      fa.recs = recs;
-      fa.grp_off = o.grp_off;
-      fa.w32 = o.w32;
-      fa.row = o.row;
-      fa.alpha = o.alpha;
-      fa.dbg_state = in.dbg_state;
-      fa.dbg_bin = in.dbg_bin;
-      fa.desc = o.desc;
-      fa.alpha_span = (int32_t*)d_nu;
-      fa.max_bin = (int32_t*)d_nu + 1;
-      fa.gperm = o.gperm;
-      fa.glitch_clk = in.glitch_clk;
-      fa.rgl = o.rgl;
-      fa.upins = upins;
-      const size_t lds = (size_t)((in.lib.lds_words + 3) & ~3) * 4 + ((size_t)4 << B.tile_log2);
-      if (in.unit_events <= 8) {
-        PK(hipFuncSetAttribute((const void*)k_pk_fill<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        hipLaunchKernelGGL(k_pk_fill<8>, dim3((unsigned)n_tiles), dim3(256), lds, s, fa);
-      } else {
-        PK(hipFuncSetAttribute((const void*)k_pk_fill<16>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        hipLaunchKernelGGL(k_pk_fill<16>, dim3((unsigned)n_tiles), dim3(256), lds, s, fa);
+    {
+      const bool phases = in.slot_quads > 0 && ng > 0;
+      if (phases) {
+        PK(hipMemcpyAsync(d_cq, in.cq_lo.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
+        PK(hipMemcpyAsync(d_cq + n_cells, in.cq_hi.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
       }
-      PKLAUNCH("k_pk_fill");
-    }
-    // ---- 8. table phases --------------------------------------------------
-    if (in.slot_quads > 0 && ng > 0) {
-      o.phases = (int4*)own((size_t)ng * sizeof(int4), e2);
-      PK(e2);
-      o.ph_off = (int32_t*)own((size_t)(n_tiles + 1) * 4, e2);
-      PK(e2);
-      int32_t* d_cq = (int32_t*)wc.take<int32_t>(2 * (size_t)n_cells);
-      if (!d_cq) {
-        snprintf(err, err_len, "pack: workspace of %zu bytes too small", ws2b->bytes);
-        st = hipErrorOutOfMemory;
-        goto fail;
+      if (ng > 0) {
+        FillArgs fa;
+        fa.bins = B;
+        fa.kl = kl;
+        fa.skeys = skeys;
+        fa.ssrc = ssrc;
+        fa.gb_start = d_gbs;
+        fa.rec = rec;
+        fa.rgl_g = rgl_g;
+        fa.tile_grp = (const uint32_t*)o.tile_grp;
+        fa.tfirst = o.tfirst;
+        fa.grp_off = o.grp_off;
+        fa.w32 = o.w32;
+        fa.row = o.row;
+        fa.alpha = o.alpha;
+        fa.rgl = o.rgl;
+        fa.desc = o.desc;
+        fa.gquads = phases ? gquads : nullptr;
+        fa.cq_lo = d_cq;
+        fa.cq_hi = d_cq + n_cells;
+        fa.max_bin = (int32_t*)d_nu + 1;
+        const size_t lds = (size_t)4 << B.tile_log2;
+        const unsigned gridf = (unsigned)((n_tiles + 7) / 8 * 8);   // a multiple of the XCD count
+        PK(launch_fill(in.unit_events <= 8, key64, fa, gridf, lds, s));
+        PKLAUNCH("k_pk_fill");
       }
-      PK(hipMemcpyAsync(d_cq, in.cq_lo.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
-      PK(hipMemcpyAsync(d_cq + n_cells, in.cq_hi.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
-      const int64_t threads = ng * kGroupUnits;
-      hipLaunchKernelGGL(k_pk_group_quads, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, o.desc, ng,
-                         (const int32_t*)d_cq, (const int32_t*)(d_cq + n_cells), n_cells, gquads);
-      PKLAUNCH("k_pk_group_quads");
-      hipLaunchKernelGGL(k_pk_phases, dim3((unsigned)n_tiles), dim3(64), 0, s, (const int4*)gquads,
-                         (const uint32_t*)o.tile_grp, (int64_t)in.slot_quads, ph_tmp, nph, (int32_t*)d_nu + 5);
-      PKLAUNCH("k_pk_phases");
-      hipLaunchKernelGGL(k_pk_fill_u32, dim3(1), dim3(256), 0, s, nph + n_tiles, (int64_t)1, 0u);
-      PKLAUNCH("k_pk_fill_u32");
-      scan_add<uint32_t>(nph, (uint32_t*)o.ph_off, psums, n_tiles + 1, s);
-      PKLAUNCH("scan of phase counts");
-      hipLaunchKernelGGL(k_pk_phase_copy, dim3((unsigned)n_tiles), dim3(256), 0, s, (const int4*)ph_tmp,
-                         (const uint32_t*)o.tile_grp, (const uint32_t*)o.ph_off, n_tiles, o.phases);
-      PKLAUNCH("k_pk_phase_copy");
-      o.slot_quads = in.slot_quads;
+      // ---- 8. table phases ------------------------------------------------
+      if (phases) {
+        o.phases = (int4*)own((size_t)ng * sizeof(int4), e2);
+        PK(e2);
+        o.ph_off = (int32_t*)own((size_t)(n_tiles + 1) * 4, e2);
+        PK(e2);
+        hipLaunchKernelGGL(k_pk_phases, dim3((unsigned)n_tiles), dim3(64), 0, s, (const int4*)gquads,
+                           (const uint32_t*)o.tile_grp, (int64_t)in.slot_quads, ph_tmp, nph, (int32_t*)d_nu + 5);
+        PKLAUNCH("k_pk_phases");
+        hipLaunchKernelGGL(k_pk_fill_u32, dim3(1), dim3(256), 0, s, nph + n_tiles, (int64_t)1, 0u);
+        PKLAUNCH("k_pk_fill_u32");
+        scan_add<uint32_t>(nph, (uint32_t*)o.ph_off, psums, n_tiles + 1, s);
+        PKLAUNCH("scan of phase counts");
+        hipLaunchKernelGGL(k_pk_phase_copy, dim3((unsigned)n_tiles), dim3(256), 0, s, (const int4*)ph_tmp,
+                           (const uint32_t*)o.tile_grp, (const uint32_t*)o.ph_off, n_tiles, o.phases);
+        PKLAUNCH("k_pk_phase_copy");
+        o.slot_quads = in.slot_quads;
+      }
     }
     // ---- statistics back to the host (one wait) -----------------------------
     {

@@ -623,7 +623,6 @@ gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, Bin
   in.stream = c->stream;
   in.ws = c->pk_ws;
   in.glitch_clk = c->par.glitch_clk_ps;
-  in.wide_cells = c->has_wide;
   in.arena = arena;
   const size_t ws_before = c->pk_ws[0].bytes + c->pk_ws[1].bytes;
   char msg[256] = {0};
