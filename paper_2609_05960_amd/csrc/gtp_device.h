@@ -402,7 +402,7 @@ struct EvView {
 //
 // Visitor interface:
 //   begin_gate(g, par)  par = parity the gate carries into this block
-//   event(e, t, pin, v, slew, par_group, par_now)
+//   event(k, e, t, pin, v, slew, par_group, par_now)   k = e - first event of the block
 //   end_gate(g)
 // Events of one gate that share a timestamp form a group; par_group is the
 // parity before the group (Algorithm 1 looks up every event of a group with
@@ -489,7 +489,7 @@ __device__ __forceinline__ void walk_block(int64_t kb, const EvView& E, const ui
         par_gs = par;
         tprev = tt[k];
       }
-      vis.event(e, tt[k], pin, v, sl[k], par_gs, par);
+      vis.event(k, e, tt[k], pin, v, sl[k], par_gs, par);
       par ^= 1u << (pin & 31);
     }
   }

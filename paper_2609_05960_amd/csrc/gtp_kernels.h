@@ -942,7 +942,7 @@ struct AdjVisitor {
     acc_c = 0.0;
     acc_l = 0.0;
   }
-  __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
+  __device__ __forceinline__ void event(int /*k*/, int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
                                         uint32_t par) {
     const BinSpec& B = A->bins;
     const uint32_t s_new = (G.gp.init ^ par ^ (1u << (pin & 31))) & G.in_mask;
@@ -1342,7 +1342,7 @@ struct RepVisitor {
     }
     spans_in = false;
   }
-  __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
+  __device__ __forceinline__ void event(int /*k*/, int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
                                         uint32_t par) {
     const BinSpec& B = A->bins;
     const uint32_t s_new = (G.gp.init ^ par ^ (1u << (pin & 31))) & G.in_mask;
@@ -1496,7 +1496,7 @@ struct ValVisitor {
     gstart = A->ev.gate_off[g];
   }
   __device__ __forceinline__ void end_gate(int64_t) {}
-  __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float, uint32_t, uint32_t par) {
+  __device__ __forceinline__ void event(int /*k*/, int64_t e, int64_t t, int pin, int v, float, uint32_t, uint32_t par) {
     int code = 0;
     if (t < 0 || t >= A->t_end) code = 1;
     else if (e > gstart && A->ev.t[e - 1] > t) code = 2;
@@ -1543,7 +1543,7 @@ struct CarryVisitor {
   __device__ __forceinline__ void end_gate(int64_t g) {
     if (x) atomicXor(&init[g], x);
   }
-  __device__ __forceinline__ void event(int64_t, int64_t, int pin, int, float, uint32_t, uint32_t) {
+  __device__ __forceinline__ void event(int /*k*/, int64_t, int64_t, int pin, int, float, uint32_t, uint32_t) {
     x ^= 1u << (pin & 31);
   }
 };
@@ -1575,7 +1575,7 @@ struct TraceVisitor {
     gate_begin(G, A->gprep, *L, g, par, A->lut.rate_scale);
   }
   __device__ __forceinline__ void end_gate(int64_t) {}
-  __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
+  __device__ __forceinline__ void event(int /*k*/, int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
                                         uint32_t par) {
     const EventOut o = event_energy(G, *L, A->lut, pin, v, slew, par_gs, par);
     A->state[e] = o.s;

@@ -127,6 +127,28 @@ struct UnitVisitor {
   uint32_t init = 0;
   int64_t gstart = 0;
   float span = 1.0f;
+  uint4 rbuf[4];           // emit pass: the records of the current 4-event group of the block
+
+  // Records leave in bursts of 4 (64 contiguous bytes per lane), so that
+  // every 64-byte piece of the record array is written whole at once.
+  __device__ __forceinline__ void put(int k, int64_t e, uint4 r) {   // k: e - the block's first event
+    rbuf[k & 3] = r;
+    if ((k & 3) == 3) {
+      uint4* p = A->rec + (e - 3);
+      p[0] = rbuf[0];
+      p[1] = rbuf[1];
+      p[2] = rbuf[2];
+      p[3] = rbuf[3];
+    }
+  }
+  // the last block's final partial group of records (e_end = one past its last event)
+  __device__ __forceinline__ void flush(int64_t e_end) {
+    const int n = (int)(e_end & 3);
+    uint4* p = A->rec + (e_end - n);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (i < n) p[i] = rbuf[i];
+  }
 
   __device__ __forceinline__ void close() {
     if (!open) return;
@@ -155,11 +177,12 @@ struct UnitVisitor {
     }
   }
   __device__ __forceinline__ void end_gate(int64_t) { close(); }
-  __device__ __forceinline__ void event(int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
+  __device__ __forceinline__ void event(int k, int64_t e, int64_t t, int pin, int v, float slew, uint32_t par_gs,
                                         uint32_t par) {
     const BinSpec& B = A->bins;
     if (t < 0 || t >= B.t_end) {  // outside the window: not packed
       close();
+      if (kEmit) put(k, e, make_uint4(0u, 0u, 0u, 0u));
       return;
     }
     const int64_t bin = bin_of(t, B);
@@ -202,7 +225,7 @@ struct UnitVisitor {
       r.y = q | ((pin == cm.n_in ? 1u : 0u) << kOutBit) | ((uint32_t)v << 31);
       r.z = __float_as_uint(al);
       r.w = first ? (lk0 | ((uint32_t)cell << 16)) : 0u;
-      A->rec[e] = r;
+      put(k, e, r);
       span = fmaxf(span, fabsf(1.0f - al) + fabsf(al));
       if (A->glitch_clk > 0) {
         const float rg = glitch_ratio(A->ev.t, A->ev.pb, A->ev.slew, gstart, e, t, pin, slew, A->glitch_clk);
@@ -220,7 +243,8 @@ struct UnitVisitor {
 // [base[kb0], base[kb1]) of at most 16 units per lane block; the lanes write
 // their units into LDS and the workgroup stores the run with coalesced writes
 // (each lane's units would be scattered over the run otherwise). Every lane
-// writes its block's event records itself (16 contiguous records per lane).
+// writes its block's event records itself (16 contiguous records per lane,
+// in four bursts of four).
 constexpr uint32_t kEmitCap = (uint32_t)kLaneEvents * kFwdThreads;
 template <bool kEmit, class K>
 __global__ void __launch_bounds__(kFwdThreads) k_pk_units(UnitArgs<K> a, int64_t n_blocks) {
@@ -250,6 +274,8 @@ __global__ void __launch_bounds__(kFwdThreads) k_pk_units(UnitArgs<K> a, int64_t
     vis.A = &la;
     vis.kb = kb;
     walk_block(kb, a.ev, a.plan, vis);
+    const int64_t e_end = min((kb + 1) * kLaneEvents, a.ev.n);
+    if (e_end & 3) vis.flush(e_end);
   }
   float span = vis.span;
   for (int o = 32; o > 0; o >>= 1) span = fmaxf(span, __shfl_xor(span, o, 64));
