@@ -65,9 +65,6 @@ __device__ __forceinline__ uint32_t key_gb(K key, const KeyLayout& L) {
 struct KeySpec {
   KeyLayout L;
   int32_t unit_cap;               // longest unit
-  const int32_t* rank;            // gate -> cell-sorted index
-  const int32_t* cell_start;      // [n_cells] first sorted index of the cell
-  const int32_t* gb_base;         // [n_cells] first gate block of the cell
 };
 
 // Table item of state st and leakage item of state sl of a cell with more
@@ -81,18 +78,19 @@ template <class K>
 struct UnitArgs {
   EvView ev;
   const uint2* plan;
-  const int32_t* gate_cell;
-  const uint32_t* gate_init;
+  const uint4* ginfo;     // per gate: cell, initial pin values, gate block, index within the block
   BinSpec bins;
   KeySpec ks;
   uint32_t* counts;       // count pass: units per lane block
   const uint32_t* base;   // emit pass: first unit of each lane block
   K* keys;                // emit pass: sort key of every unit
   uint32_t* srcs;         // emit pass: gate-major index of every unit's first event
-  // emit pass: the workgroup's units staged in LDS
+  // emit pass: the workgroup's units staged in LDS (first events as offsets
+  // from the workgroup's first event: a workgroup walks kEmitCap events)
   K* lkeys;
-  uint32_t* lsrcs;
+  uint16_t* lsrcs;
   uint32_t u0;            // first unit of the workgroup
+  int64_t e0;             // first event of the workgroup
   // emit pass: every packed event's record, gate-major (see EvRec)
   LibView lib;
   uint4* rec;
@@ -122,10 +120,13 @@ struct UnitVisitor {
   int64_t u_src = 0;
   int32_t u_len = 0;
   int64_t u_tile = 0;
-  // emit pass: the gate
+  // emit pass: the gate, its cell record and (7-knot slew axes) its knots
   int cell = 0;
   uint32_t init = 0;
   int64_t gstart = 0;
+  CellMeta cm;
+  uint32_t in_mask = 0;
+  float ax[7], ainv[6];
   float span = 1.0f;
   uint4 rbuf[4];           // emit pass: the records of the current 4-event group of the block
 
@@ -159,21 +160,28 @@ struct UnitVisitor {
                     ((K)((1u << KL.len_bits) - (uint32_t)u_len) << KL.gin_bits) | (K)gin;
       const uint32_t i = A->base[kb] + n - A->u0;
       A->lkeys[i] = key;
-      A->lsrcs[i] = (uint32_t)u_src;
+      A->lsrcs[i] = (uint16_t)(u_src - A->e0);
     }
     ++n;
     open = false;
   }
   __device__ __forceinline__ void begin_gate(int64_t g, uint32_t) {
-    const int32_t c = A->gate_cell[g];
-    const int32_t gs = A->ks.rank[g];
-    gblock = (uint32_t)(A->ks.gb_base[c] + ((gs - A->ks.cell_start[c]) >> A->ks.L.gin_bits));
-    gin = (uint32_t)(gs - A->ks.cell_start[c]) & ((1u << A->ks.L.gin_bits) - 1u);
     open = false;
     if (kEmit) {
-      cell = c;
-      init = A->gate_init[g];
+      const uint4 gi = A->ginfo[g];
+      cell = (int)gi.x;
+      init = gi.y;
+      gblock = gi.z;
+      gin = gi.w;
       if (A->glitch_clk > 0) gstart = A->ev.gate_off[g];
+      cm = L.meta[cell];
+      in_mask = state_mask(cm.n_in, L.all_pins);
+      if (A->lib.n_slew == 7) {
+#pragma unroll
+        for (int m = 0; m < 7; ++m) ax[m] = L.slew[cm.axis_off + m];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) ainv[m] = L.slew_inv[cm.axis_off + m];
+      }
     }
   }
   __device__ __forceinline__ void end_gate(int64_t) { close(); }
@@ -200,8 +208,6 @@ struct UnitVisitor {
     if (kEmit) {
       // Algorithm 1 per event: the table of the input state before the
       // event's timestamp group, the leakage state once its pin has toggled
-      const CellMeta cm = L.meta[cell];
-      const uint32_t in_mask = state_mask(cm.n_in, L.all_pins);
       const uint32_t before = init ^ par;
       const uint32_t st = (init ^ par_gs) & in_mask;
       uint32_t ti = st, li = (before ^ (1u << (pin & 31))) & in_mask;
@@ -216,7 +222,20 @@ struct UnitVisitor {
       }
       int i;
       float al;
-      slew_segment(L.slew + cm.axis_off, L.slew_inv + cm.axis_off, A->lib.n_slew, slew, i, al);
+      if (A->lib.n_slew == 7) {   // the knots are in registers: the same segment and weight as slew_segment
+        i = 0;
+#pragma unroll
+        for (int m = 1; m < 6; ++m) i += (ax[m] <= slew) ? 1 : 0;
+        float a0 = ax[0], iv = ainv[0];
+#pragma unroll
+        for (int m = 1; m < 6; ++m) {
+          a0 = (i == m) ? ax[m] : a0;
+          iv = (i == m) ? ainv[m] : iv;
+        }
+        al = __fmul_rn(__fsub_rn(slew, a0), iv);
+      } else {
+        slew_segment(L.slew + cm.axis_off, L.slew_inv + cm.axis_off, A->lib.n_slew, slew, i, al);
+      }
       const uint32_t q = (uint32_t)(L.map_q[cm.map_off + 2 * (int)ti + v] + i * (A->lib.n_load - 1));
       const uint32_t bl = (uint32_t)(bin - (tile << B.tile_log2));
       const uint32_t rr = (uint32_t)(t - bin * B.D);
@@ -238,6 +257,29 @@ struct UnitVisitor {
     }
   }
 };
+
+// The parts of the library image the emit pass reads (cell records, then the
+// table map and slew axes; the leakage values and load axes are left out).
+__host__ __device__ __forceinline__ int32_t emit_lib_words(const LibView& L) {
+  return 4 * L.n_cells + L.n_map + 2 * L.n_cells * L.n_slew;
+}
+__device__ __forceinline__ LdsLib stage_library_emit(const LibView& L, uint32_t* lds) {
+  const uint32_t* meta = reinterpret_cast<const uint32_t*>(L.meta);
+  const uint32_t* tail = reinterpret_cast<const uint32_t*>(L.map_q);   // map_q | slew | slew_inv
+  const int32_t nm = 4 * L.n_cells, nt = L.n_map + 2 * L.n_cells * L.n_slew;
+  for (int w = threadIdx.x; w < nm + nt; w += blockDim.x) lds[w] = w < nm ? meta[w] : tail[w - nm];
+  LdsLib S;
+  S.all_pins = L.all_pins;
+  S.wide = L.wide;
+  S.meta = reinterpret_cast<const CellMeta*>(lds);
+  S.leak = nullptr;
+  S.load = nullptr;
+  S.load_inv = nullptr;
+  S.map_q = reinterpret_cast<const int32_t*>(lds + nm);
+  S.slew = reinterpret_cast<const float*>(S.map_q + L.n_map);
+  S.slew_inv = S.slew + L.n_cells * L.n_slew;
+  return S;
+}
 
 // Emit pass: a workgroup's lane blocks own one contiguous run of units
 // [base[kb0], base[kb1]) of at most 16 units per lane block; the lanes write
@@ -264,11 +306,12 @@ __global__ void __launch_bounds__(kFwdThreads) k_pk_units(UnitArgs<K> a, int64_t
   const uint32_t u0 = a.base[kb0], n_u = a.base[kb1] - u0;   // n_u <= kEmitCap
   UnitArgs<K> la = a;
   la.lkeys = reinterpret_cast<K*>(lds64);
-  la.lsrcs = reinterpret_cast<uint32_t*>(lds64 + kEmitCap * sizeof(K) / 8);
+  la.lsrcs = reinterpret_cast<uint16_t*>(lds64 + kEmitCap * sizeof(K) / 8);
   la.u0 = u0;
-  uint32_t* llib = reinterpret_cast<uint32_t*>(lds64 + kEmitCap * (sizeof(K) + 4) / 8);
+  la.e0 = kb0 * kLaneEvents;
+  uint32_t* llib = reinterpret_cast<uint32_t*>(lds64 + kEmitCap * (sizeof(K) + 2) / 8);
   UnitVisitor<true, K> vis;
-  vis.L = stage_library(a.lib, llib);
+  vis.L = stage_library_emit(a.lib, llib);
   __syncthreads();
   if (kb < n_blocks) {
     vis.A = &la;
@@ -283,7 +326,7 @@ __global__ void __launch_bounds__(kFwdThreads) k_pk_units(UnitArgs<K> a, int64_t
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < n_u; i += blockDim.x) {
     a.keys[u0 + i] = la.lkeys[i];
-    a.srcs[u0 + i] = la.lsrcs[i];
+    a.srcs[u0 + i] = (uint32_t)(la.e0 + la.lsrcs[i]);
   }
 }
 
@@ -605,14 +648,23 @@ __global__ void __launch_bounds__(256) k_pk_phase_copy(const int4* ph_tmp, const
 
 // Output nets and initial pin values in cell-sorted gate order (the per-call
 // gate records then read them contiguously).
-__global__ void __launch_bounds__(256) k_pk_gate_sorted(const int32_t* gperm, const int32_t* gate_out,
-                                                        const uint32_t* gate_init, int64_t n_gates, int32_t* gout,
-                                                        uint32_t* ginit) {
+// Also the per-gate record of the unit walk (cell, initial pin values, gate
+// block, index within the block).
+__global__ void __launch_bounds__(256) k_pk_gate_sorted(const int32_t* gperm, const int32_t* gcell,
+                                                        const int32_t* gate_out, const uint32_t* gate_init,
+                                                        const int32_t* cell_start, const int32_t* gb_base,
+                                                        int32_t gb_log2, int64_t n_gates, int32_t* gout,
+                                                        uint32_t* ginit, uint4* ginfo) {
   const int64_t gs = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gs >= n_gates) return;
   const int32_t g = gperm[gs];
+  const int32_t c = gcell[gs];
+  const uint32_t init = gate_init[g];
   gout[gs] = gate_out[g];
-  ginit[gs] = gate_init[g];
+  ginit[gs] = init;
+  const int32_t in_cell = (int32_t)gs - cell_start[c];
+  ginfo[g] = make_uint4((uint32_t)c, init, (uint32_t)(gb_base[c] + (in_cell >> gb_log2)),
+                        (uint32_t)in_cell & ((1u << gb_log2) - 1u));
 }
 
 // Sort key of gate g for the cell-sorted gate order: cell, then decreasing
@@ -628,16 +680,14 @@ __global__ void __launch_bounds__(256) k_pk_gate_keys(const int32_t* gate_cell, 
   keys[g] = ((uint64_t)(uint32_t)gate_cell[g] << 48) | (wq << 28) | (uint64_t)g;
 }
 
-// The sorted keys as the permutation (sorted index -> gate), its inverse and
-// each sorted gate's cell.
+// The sorted keys as the permutation (sorted index -> gate) and each sorted
+// gate's cell.
 __global__ void __launch_bounds__(256) k_pk_gate_order(const uint64_t* skeys, int64_t n_gates, int32_t* perm,
-                                                       int32_t* rank, int32_t* pcell) {
+                                                       int32_t* pcell) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_gates) return;
   const uint64_t k = skeys[r];
-  const int32_t g = (int32_t)(k & ((1u << 28) - 1u));
-  perm[r] = g;
-  rank[g] = (int32_t)r;
+  perm[r] = (int32_t)(k & ((1u << 28) - 1u));
   pcell[r] = (int32_t)(k >> 48);
 }
 
@@ -687,8 +737,7 @@ hipError_t launch_emit(const UnitArgs<uint32_t>& u, void* keys, uint32_t* srcs, 
   UnitArgs<K> a;
   a.ev = u.ev;
   a.plan = u.plan;
-  a.gate_cell = u.gate_cell;
-  a.gate_init = u.gate_init;
+  a.ginfo = u.ginfo;
   a.bins = u.bins;
   a.ks = u.ks;
   a.counts = u.counts;
@@ -706,7 +755,7 @@ hipError_t launch_emit(const UnitArgs<uint32_t>& u, void* keys, uint32_t* srcs, 
   a.dbg_bin = u.dbg_bin;
   a.alpha_span = u.alpha_span;
   // staged keys and first events, then the library image
-  const size_t lds = (size_t)kEmitCap * (sizeof(K) + sizeof(uint32_t)) + (size_t)((u.lib.lds_words + 3) & ~3) * 4;
+  const size_t lds = (size_t)kEmitCap * (sizeof(K) + sizeof(uint16_t)) + (size_t)emit_lib_words(u.lib) * 4;
   const hipError_t e =
       hipFuncSetAttribute((const void*)k_pk_units<true, K>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e != hipSuccess) return e;
@@ -883,13 +932,12 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     if (G > 0)
       PK(rocprim::radix_sort_keys(nullptr, gsort_tmp, (uint64_t*)nullptr, (uint64_t*)nullptr, (int64_t)G, 0,
                                   48 + std::max(1, ceil_log2_u64((uint64_t)n_cells)), s));
-    const size_t ws1 = align256((size_t)G * 4) + 2 * align256((size_t)n_cells * 4) + 3 * align256((size_t)G * 8) +
+    const size_t ws1 = 2 * align256((size_t)n_cells * 4) + 3 * align256((size_t)G * 8) +
                        align256(gsort_tmp) + 2 * align256((size_t)(n_blocks + 1) * 4) +
                        align256((size_t)scan_sums_items(n_blocks + 1) * 4) + align256(64) +
-                       align256((size_t)n_gb * 4);
+                       align256((size_t)n_gb * 4) + align256((size_t)G * sizeof(uint4));
     PK(reserve(ws, ws1));
     Bump wb{(char*)ws->p, ws->bytes};
-    int32_t* d_rank = wb.take<int32_t>((size_t)G);
     int32_t* d_cs = wb.take<int32_t>((size_t)n_cells);
     int32_t* d_gbb = wb.take<int32_t>((size_t)n_cells);
     uint32_t* counts = wb.take<uint32_t>((size_t)n_blocks + 1);
@@ -897,6 +945,10 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     uint32_t* usums = wb.take<uint32_t>((size_t)scan_sums_items(n_blocks + 1));
     uint32_t* d_nu = wb.take<uint32_t>(16);
     int32_t* d_gbs = wb.take<int32_t>((size_t)n_gb);
+    uint4* ginfo = wb.take<uint4>((size_t)G);
+    PK(hipMemcpyAsync(d_cs, cell_start.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
+    PK(hipMemcpyAsync(d_gbb, gb_base.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
+    PK(hipMemcpyAsync(d_gbs, o.h_gb_start.data(), (size_t)n_gb * 4, hipMemcpyHostToDevice, s));
     if (G > 0) {
       uint64_t* gk = wb.take<uint64_t>((size_t)G);
       uint64_t* gks = wb.take<uint64_t>((size_t)G);
@@ -911,28 +963,22 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       size_t tb = gsort_tmp;
       PK(rocprim::radix_sort_keys(tsort, tb, gk, gks, (int64_t)G, 0,
                                   48 + std::max(1, ceil_log2_u64((uint64_t)n_cells)), s));
-      hipLaunchKernelGGL(k_pk_gate_order, gg, dim3(256), 0, s, gks, (int64_t)G, o.gperm, d_rank, o.gcell);
+      hipLaunchKernelGGL(k_pk_gate_order, gg, dim3(256), 0, s, gks, (int64_t)G, o.gperm, o.gcell);
       PKLAUNCH("k_pk_gate_order");
-      hipLaunchKernelGGL(k_pk_gate_sorted, gg, dim3(256), 0, s, o.gperm, in.gate_out, in.gate_init, (int64_t)G, o.gout,
-                         o.ginit);
+      hipLaunchKernelGGL(k_pk_gate_sorted, gg, dim3(256), 0, s, o.gperm, o.gcell, in.gate_out, in.gate_init,
+                         (const int32_t*)d_cs, (const int32_t*)d_gbb, (int32_t)in.gate_block_log2, (int64_t)G, o.gout,
+                         o.ginit, ginfo);
       PKLAUNCH("k_pk_gate_sorted");
     }
-    PK(hipMemcpyAsync(d_cs, cell_start.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
-    PK(hipMemcpyAsync(d_gbb, gb_base.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
-    PK(hipMemcpyAsync(d_gbs, o.h_gb_start.data(), (size_t)n_gb * 4, hipMemcpyHostToDevice, s));
 
     // ---- 2. unit counts ----------------------------------------------------
     UnitArgs<uint32_t> ua;
     ua.ev = in.ev;
     ua.plan = in.plan_blk;
-    ua.gate_cell = in.gate_cell;
-    ua.gate_init = in.gate_init;
+    ua.ginfo = ginfo;
     ua.bins = B;
     ua.ks.L = kl;
     ua.ks.unit_cap = in.unit_events;
-    ua.ks.rank = d_rank;
-    ua.ks.cell_start = d_cs;
-    ua.ks.gb_base = d_gbb;
     ua.counts = counts;
     ua.base = ubase;
     ua.keys = nullptr;
