@@ -283,7 +283,12 @@ __device__ __forceinline__ UnitLut unit_lut(const LdsLib& L, int32_t n_load, int
                                             int32_t sw_mode) {
   const float* la = L.load + cell * n_load;
   int j = 0;
-  for (int m = 1; m < n_load - 1; ++m) j += (la[m] <= C) ? 1 : 0;
+  if (n_load == 7) {   // the usual 7 knots: the five interior knots read together
+#pragma unroll
+    for (int m = 1; m < 6; ++m) j += (la[m] <= C) ? 1 : 0;
+  } else {
+    for (int m = 1; m < n_load - 1; ++m) j += (la[m] <= C) ? 1 : 0;
+  }
   UnitLut u;
   u.jq = (uint32_t)j;
   u.dbdc = L.load_inv[cell * n_load + j];

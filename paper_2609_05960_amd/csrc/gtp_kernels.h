@@ -1087,7 +1087,7 @@ __device__ __forceinline__ void lds_add_f64(double* p, double v) {
 // FP32 terms stay as small as the tile's share of the integral). The unit's
 // sums go into FP64 LDS accumulators of its gate.
 // Lookups are double-buffered by event parity as in the forward.
-template <int kS, bool kGl>
+template <int kS, bool kGl, bool kTabOnly>
 __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const LdsLib& L, const GroupRegs<kS>& G,
                                                   bool mine, int32_t tile, int32_t gs0, double* acc_c, double* acc_l,
                                                   const float4* tab, uint32_t q_lo, uint32_t q_n) {
@@ -1109,14 +1109,18 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
   struct Pre {
     float4 q;        // table quad
     float lk_after;  // leakage value of the input state after the event
-    float2 wg;       // the bin's (w_b, G_b)
   };
   auto prefetch = [&](int k, Pre& P) {
-    const uint32_t w = G.wv[k];
-    P.q = quad_at(quads, lds_ptr(tab), q_lo, q_n, (G.rv[k] & kRowMask) + (uint32_t)jq);
-    P.lk_after = lk[w >> kStateShift];
-    P.wg = a.wg[tile_b0 + (int64_t)((w & kTimeMask) >> B.r_bits)];
+    const uint32_t qi = (G.rv[k] & kRowMask) + (uint32_t)jq;
+    P.q = kTabOnly ? quad_slot(lds_ptr(tab), q_lo, q_n, qi) : quad_at(quads, lds_ptr(tab), q_lo, q_n, qi);
+    P.lk_after = lk[G.wv[k] >> kStateShift];
   };
+  // the bins' (w_b, G_b) of all the unit's events, requested together: one
+  // cache round trip per group rather than one per event
+  float2 wg[kS];
+#pragma unroll
+  for (int kk = 0; kk < kS; ++kk)
+    if (kk < G.kmax && len > kk) wg[kk] = a.wg[tile_b0 + (int64_t)((G.wv[kk] & kTimeMask) >> B.r_bits)];
   float ac = 0.f, al = 0.f;
   Pre pre[2];
   if (len > 0) prefetch(0, pre[0]);
@@ -1130,13 +1134,13 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
       float dedc = __fmul_rn(bilerp_dbeta(P.q, G.av[kk]), dbdc);
       if (rv & (1u << kOutBit)) dedc = __fadd_rn(dedc, (rv >> 31) ? a.dsw_rise : a.dsw_fall);
       if (kGl) dedc = __fmul_rn(dedc, G.gv[kk]);
-      ac = __fmaf_rn(P.wg.x, dedc, ac);
+      ac = __fmaf_rn(wg[kk].x, dedc, ac);
       // an output event leaves the input state unchanged: step 0, no branch
       const uint32_t tl = w & kTimeMask;
       const int64_t b = tile_b0 + (int64_t)(tl >> B.r_bits);
       const int32_t width = (b == B.n_bins - 1) ? a.last_w : D32;
       const float tail = (float)(width - (int32_t)(tl & rmask));
-      al = __fmaf_rn(__fsub_rn(P.lk_after, lk_cur), __fmaf_rn(P.wg.x, tail, P.wg.y), al);
+      al = __fmaf_rn(__fsub_rn(P.lk_after, lk_cur), __fmaf_rn(wg[kk].x, tail, wg[kk].y), al);
       lk_cur = P.lk_after;
     }
   }
@@ -1148,7 +1152,10 @@ __device__ __forceinline__ void adj_process_group(const AdjPackedArgs& a, const 
   }
 }
 
-template <int kThreads, int kS, bool kGl>
+// kTabOnly: every item's LDS table holds all of its cell's quads, so no
+// quad comes from global memory and the next group's loads stay in flight
+// while a group is processed.
+template <int kThreads, int kS, bool kGl, bool kTabOnly>
 __global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
   extern __shared__ uint32_t lds[];
   const AdjItem it = a.items[blockIdx.x];
@@ -1164,8 +1171,23 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
   const int lane = (int)(threadIdx.x & 63);
   constexpr int nwave = kThreads / 64;
   const int64_t e1 = it.e1;
-  // wave-uniform entry index: the entry loads go through the scalar unit
+  // wave-uniform entry index. The entry and group-offset loads are vector
+  // loads (through a zero the compiler cannot see through): a scalar load
+  // shares its wait counter with LDS, so every LDS access of a group would
+  // wait for the next entries' cache round trip.
   int64_t e = it.e0 + (int64_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  int32_t z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  auto ventry = [&](int64_t i) -> int4 {
+    const int4 v = a.entries[i + z];
+    return make_int4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
+                     __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
+  };
+  auto voff = [&](int32_t g) -> int64_t {
+    const int64_t v = a.f.grp_off[(int64_t)g + z];
+    return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(v >> 32)) << 32) |
+                     (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)v));
+  };
   GroupRegs<kS> ga, gb;
   bool ma = false, mb = false;
   int32_t ta = 0, tb = 0;
@@ -1182,25 +1204,25 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
     en1 = en2;
     if (en + nwave < e1) {
       dn = a.f.desc[(int64_t)en1.x * kGroupUnits + lane];
-      offn = a.f.grp_off[en1.x];
+      offn = voff(en1.x);
     }
-    if (en + 2 * nwave < e1) en2 = a.entries[en + 2 * nwave];
+    if (en + 2 * nwave < e1) en2 = ventry(en + 2 * nwave);
   };
   if (e < e1) {
-    en1 = a.entries[e];
+    en1 = ventry(e);
     dn = a.f.desc[(int64_t)en1.x * kGroupUnits + lane];
-    offn = a.f.grp_off[en1.x];
-    if (e + nwave < e1) en2 = a.entries[e + nwave];
+    offn = voff(en1.x);
+    if (e + nwave < e1) en2 = ventry(e + nwave);
     issue(e, ga, ma, ta);
   }
   __syncthreads();
   while (e < e1) {
     if (e + nwave < e1) issue(e + nwave, gb, mb, tb);
-    adj_process_group<kS, kGl>(a, L, ga, ma, ta, gs0, acc_c, acc_l, tab, (uint32_t)it.q_lo, (uint32_t)it.q_n);
+    adj_process_group<kS, kGl, kTabOnly>(a, L, ga, ma, ta, gs0, acc_c, acc_l, tab, (uint32_t)it.q_lo, (uint32_t)it.q_n);
     e += nwave;
     if (e >= e1) break;
     if (e + nwave < e1) issue(e + nwave, ga, ma, ta);
-    adj_process_group<kS, kGl>(a, L, gb, mb, tb, gs0, acc_c, acc_l, tab, (uint32_t)it.q_lo, (uint32_t)it.q_n);
+    adj_process_group<kS, kGl, kTabOnly>(a, L, gb, mb, tb, gs0, acc_c, acc_l, tab, (uint32_t)it.q_lo, (uint32_t)it.q_n);
     e += nwave;
   }
   __syncthreads();

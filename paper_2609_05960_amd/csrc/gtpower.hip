@@ -184,6 +184,7 @@ struct gtp_ctx_s {
 
   // packed adjoint work items (built from the pack's region tables)
   bool adj_ok = false;
+  bool adj_tab_only = false;   // every adjoint item's LDS table holds all of its cell's quads
   int64_t adj_n_items = 0;
   int32_t adj_max_gb = 0;   // gates in the largest gate block
   DevBuf adj_items, adj_entries, adj_gbs, adj_gbrow, adj_gbrows, adj_part;
@@ -516,7 +517,8 @@ hipError_t lds_limits_gl() {
                           lds_limits_one<512, 16, false, GL>(), lds_limits_one<256, 8, true, GL>(),
                           lds_limits_one<512, 8, true, GL>(),   lds_limits_one<1024, 8, true, GL>(),
                           lds_limits_one<256, 16, true, GL>(),  lds_limits_one<512, 16, true, GL>(),
-                          lds_limit(k_adjoint_packed<1024, 8, GL>), lds_limit(k_adjoint_packed<512, 16, GL>)};
+                          lds_limit(k_adjoint_packed<1024, 8, GL, false>), lds_limit(k_adjoint_packed<512, 16, GL, false>),
+                          lds_limit(k_adjoint_packed<1024, 8, GL, true>), lds_limit(k_adjoint_packed<512, 16, GL, true>)};
   for (hipError_t x : r)
     if (x != hipSuccess) return x;
   return hipSuccess;
@@ -761,12 +763,14 @@ gtp_status adj_plan(gtp_ctx c) {
   std::vector<int32_t> gb_rows((size_t)n_gb, 0);
   std::vector<AdjItem> h(std::max<size_t>(items.size(), 1));
   int64_t rows = 0;
+  bool tab_only = true;   // every item's table slot holds all of its cell's quads
   for (size_t i = 0; i < items.size(); ++i) {
     const int32_t g = items[i].gb;
     const int64_t ng = pk.h_gb_start[g + 1] - pk.h_gb_start[g];
     if (gb_rows[g] == 0) gb_row[g] = rows;
     const int32_t cell = pk.h_gb_cell[g];
     const int32_t qn = std::min(c->h_cq_hi[cell] - c->h_cq_lo[cell], adj_slot_quads(c, max_gb));
+    if (qn < c->h_cq_hi[cell] - c->h_cq_lo[cell]) tab_only = false;
     h[i] = AdjItem{g, (int32_t)items[i].e0, (int32_t)items[i].e1, c->h_cq_lo[cell], gb_row[g] + gb_rows[g] * ng, qn, 0};
     gb_rows[g]++;
     rows += ng;
@@ -808,6 +812,7 @@ gtp_status adj_plan(gtp_ctx c) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->adj_n_items = items.empty() ? 0 : (int64_t)hs.size();
   c->adj_max_gb = max_gb;
+  c->adj_tab_only = tab_only;
   c->adj_ok = true;
   return GTP_OK;
 }
@@ -2215,17 +2220,22 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       const dim3 gi((unsigned)c->adj_n_items);
       const size_t al = adj_lds_bytes(c, c->adj_max_gb);
       const bool gl = pk.rgl != nullptr;
+      const bool to = c->adj_tab_only;
+#define ADJ_LAUNCH(TH, SL, GL, TO) LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<TH, SL, GL, TO>), gi, dim3(TH), al, a)
       if (slots_of(c) == 8) {
-        if (gl)
-          LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<1024, 8, true>), gi, dim3(1024), al, a);
-        else
-          LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<1024, 8, false>), gi, dim3(1024), al, a);
+        if (gl) {
+          if (to) ADJ_LAUNCH(1024, 8, true, true); else ADJ_LAUNCH(1024, 8, true, false);
+        } else {
+          if (to) ADJ_LAUNCH(1024, 8, false, true); else ADJ_LAUNCH(1024, 8, false, false);
+        }
       } else {
-        if (gl)
-          LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<512, 16, true>), gi, dim3(512), al, a);
-        else
-          LAUNCH(c, "k_adjoint_packed", (k_adjoint_packed<512, 16, false>), gi, dim3(512), al, a);
+        if (gl) {
+          if (to) ADJ_LAUNCH(512, 16, true, true); else ADJ_LAUNCH(512, 16, true, false);
+        } else {
+          if (to) ADJ_LAUNCH(512, 16, false, true); else ADJ_LAUNCH(512, 16, false, false);
+        }
       }
+#undef ADJ_LAUNCH
     }
     if (c->n_nets > 0)
       LAUNCH(c, "k_fill_i32", k_fill_i32, dim3(grid_for(c->n_nets, 256)), dim3(256), 0, (int32_t*)grad_net_load,
