@@ -41,12 +41,15 @@ namespace gtp {
 namespace {
 
 // Sort key of a unit, fields from the most significant: tile, gate block,
-// 2^len_bits - length, gate within the block. Every field is exact, so the
-// fill reads the unit's gate and length back from its key. 32-bit keys when
-// the fields fit (fewer bytes per radix pass), else 64-bit.
+// 2^len_bits - length, the gate's index within the block shifted right by
+// gin_shift. Within one key the units keep the gate-major order of the walk
+// (stable sort); the exact index within the block travels in the unit's first
+// event record. The fields are narrowed to 24 bits when the gate index allows
+// it (three radix passes), else kept whole in 32 or 64 bits.
 struct KeyLayout {
   int32_t len_bits;    // length field (unit lengths 1..2^len_bits)
-  int32_t gin_bits;    // gate-within-block field (the gate-block size, log2)
+  int32_t gin_bits;    // width of the gate-index field
+  int32_t gin_shift;   // the field holds the gate's index within its block >> gin_shift
   int32_t gb_bits;     // gate-block field
   int32_t tile_bits;
 };
@@ -106,7 +109,8 @@ struct UnitArgs {
 // in-bin offset, leakage state after the event), y = the table row at the
 // slew segment | output flag | new value, z = the slew weight (FP32 bits),
 // w = for a unit's first event, the leakage state before it (its pin values
-// for a kCellDirect cell, else its leakage item) | the cell << 16.
+// for a kCellDirect cell, else its leakage item) | the gate's index within its
+// gate block << 16.
 
 template <bool kEmit, class K>
 struct UnitVisitor {
@@ -157,7 +161,7 @@ struct UnitVisitor {
       const KeyLayout& KL = A->ks.L;
       const int low = key_low(KL);
       const K key = ((K)u_tile << (KL.gb_bits + low)) | ((K)gblock << low) |
-                    ((K)((1u << KL.len_bits) - (uint32_t)u_len) << KL.gin_bits) | (K)gin;
+                    ((K)((1u << KL.len_bits) - (uint32_t)u_len) << KL.gin_bits) | (K)(gin >> KL.gin_shift);
       const uint32_t i = A->base[kb] + n - A->u0;
       A->lkeys[i] = key;
       A->lsrcs[i] = (uint16_t)(u_src - A->e0);
@@ -243,7 +247,7 @@ struct UnitVisitor {
       r.x = (bl << B.r_bits) | rr | (li << kStateShift);
       r.y = q | ((pin == cm.n_in ? 1u : 0u) << kOutBit) | ((uint32_t)v << 31);
       r.z = __float_as_uint(al);
-      r.w = first ? (lk0 | ((uint32_t)cell << 16)) : 0u;
+      r.w = first ? (lk0 | (gin << 16)) : 0u;
       put(k, e, r);
       span = fmaxf(span, fabsf(1.0f - al) + fabsf(al));
       if (A->glitch_clk > 0) {
@@ -450,6 +454,7 @@ struct FillArgs {
   const void* skeys;          // sorted unit keys
   const uint32_t* ssrc;       // gate-major index of each sorted unit's first event
   const int32_t* gb_start;    // [n_gb] first cell-sorted gate of each gate block
+  const int32_t* gb_cell;     // [n_gb] cell of each gate block
   const uint4* rec;           // event records (gate-major)
   const float* rgl_g;         // glitch detection on: energy factors (gate-major)
   const uint32_t* tile_grp;
@@ -500,14 +505,17 @@ __global__ void __launch_bounds__(kFillThreads) k_pk_fill(FillArgs a) {
     const int64_t j = (int64_t)a.tfirst[k] + (gi - g0) * kGroupUnits + lane;
     const bool act = j < jend;
     int len = 0;
-    uint32_t rank = 0;
+    uint32_t gb = 0, gin_k = 0;   // gin_k: the gate-index field (the whole index when not shifted)
     int64_t src = 0;
     if (act) {
       const K key = skeys[j];
       src = (int64_t)a.ssrc[j];
       len = (int)key_len(key, kl);
-      rank = (uint32_t)a.gb_start[key_gb(key, kl)] + (uint32_t)(key & (K)((1u << kl.gin_bits) - 1u));
+      gb = key_gb(key, kl);
+      gin_k = (uint32_t)(key & (K)((1ull << kl.gin_bits) - 1ull));
     }
+    const uint32_t gs0 = act ? (uint32_t)a.gb_start[gb] : 0u;
+    const int cell = act ? a.gb_cell[gb] : 0;
     uint4 r[kS];
     float rg[kS];
 #pragma unroll
@@ -517,15 +525,17 @@ __global__ void __launch_bounds__(kFillThreads) k_pk_fill(FillArgs a) {
         if (a.rgl) rg[kk] = a.rgl_g[src + kk];
       }
     }
-    const uint32_t dy = act ? r[0].w : 0u;   // leakage state before the unit | cell << 16
-    const uint32_t dx = act ? (rank | ((uint32_t)(len - 1) << 28)) : 0xffffffffu;
+    // descriptor: the cell-sorted gate | (length - 1) << 28, the leakage state
+    // before the unit | cell << 16
+    const uint32_t dy = act ? ((r[0].w & 0xffffu) | ((uint32_t)cell << 16)) : 0u;
+    const uint32_t gin = kl.gin_shift ? (r[0].w >> 16) : gin_k;
+    const uint32_t dx = act ? ((gs0 + gin) | ((uint32_t)(len - 1) << 28)) : 0xffffffffu;
     a.desc[gi * kGroupUnits + lane] = make_uint2(dx, dy);
     if (a.gquads) {
       const uint64_t m = __ballot(act);
       if (m == 0) {
         if (lane == 0) a.gquads[gi] = make_int4(-1, -1, -1, -1);
       } else {
-        const int cell = (int)(dy >> 16);
         const int32_t clo = act ? a.cq_lo[cell] : INT32_MAX, chi = act ? a.cq_hi[cell] : INT32_MIN;
         int32_t lo = clo, hi = chi;
         for (int o = 32; o > 0; o >>= 1) {
@@ -900,11 +910,19 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     }
     KeyLayout kl;
     kl.len_bits = ceil_log2_u64((uint64_t)std::max(in.unit_events, 1));
-    kl.gin_bits = in.gate_block_log2;
     kl.gb_bits = ceil_log2_u64((uint64_t)n_gb);
     kl.tile_bits = std::max(1, ceil_log2_u64((uint64_t)n_tiles));
+    {
+      // the gate-index field takes what is left of 24 bits, else of 32 (or
+      // all 64: every field whole); the record carries the index in 16 bits,
+      // so larger gate blocks keep it whole in the key
+      const int head = kl.tile_bits + kl.gb_bits + kl.len_bits;
+      const int room = head <= 24 ? 24 - head : (head <= 32 ? 32 - head : in.gate_block_log2);
+      kl.gin_bits = in.gate_block_log2 > 16 ? in.gate_block_log2 : std::min(room, in.gate_block_log2);
+      kl.gin_shift = in.gate_block_log2 - kl.gin_bits;
+    }
     const int gb_bits = kl.gb_bits;
-    const int low = key_low(kl);   // length and gate-within-block fields
+    const int low = key_low(kl);   // length and gate-index fields
     const int key_bits = kl.tile_bits + gb_bits + low;
     if (key_bits > 64) {
       snprintf(err, err_len, "pack: sort key of %d bits", key_bits);
@@ -935,7 +953,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     const size_t ws1 = 2 * align256((size_t)n_cells * 4) + 3 * align256((size_t)G * 8) +
                        align256(gsort_tmp) + 2 * align256((size_t)(n_blocks + 1) * 4) +
                        align256((size_t)scan_sums_items(n_blocks + 1) * 4) + align256(64) +
-                       align256((size_t)n_gb * 4) + align256((size_t)G * sizeof(uint4));
+                       2 * align256((size_t)n_gb * 4) + align256((size_t)G * sizeof(uint4));
     PK(reserve(ws, ws1));
     Bump wb{(char*)ws->p, ws->bytes};
     int32_t* d_cs = wb.take<int32_t>((size_t)n_cells);
@@ -945,10 +963,12 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     uint32_t* usums = wb.take<uint32_t>((size_t)scan_sums_items(n_blocks + 1));
     uint32_t* d_nu = wb.take<uint32_t>(16);
     int32_t* d_gbs = wb.take<int32_t>((size_t)n_gb);
+    int32_t* d_gbc = wb.take<int32_t>((size_t)n_gb);
     uint4* ginfo = wb.take<uint4>((size_t)G);
     PK(hipMemcpyAsync(d_cs, cell_start.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
     PK(hipMemcpyAsync(d_gbb, gb_base.data(), (size_t)n_cells * 4, hipMemcpyHostToDevice, s));
     PK(hipMemcpyAsync(d_gbs, o.h_gb_start.data(), (size_t)n_gb * 4, hipMemcpyHostToDevice, s));
+    PK(hipMemcpyAsync(d_gbc, o.h_gb_cell.data(), (size_t)n_gb * 4, hipMemcpyHostToDevice, s));
     if (G > 0) {
       uint64_t* gk = wb.take<uint64_t>((size_t)G);
       uint64_t* gks = wb.take<uint64_t>((size_t)G);
@@ -1170,6 +1190,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
         fa.skeys = skeys;
         fa.ssrc = ssrc;
         fa.gb_start = d_gbs;
+        fa.gb_cell = d_gbc;
         fa.rec = rec;
         fa.rgl_g = rgl_g;
         fa.tile_grp = (const uint32_t*)o.tile_grp;
