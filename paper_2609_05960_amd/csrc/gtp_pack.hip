@@ -13,11 +13,12 @@
 //      (tile, gate block, length class, gate within the block; 32 bits when
 //      the fields fit) and its first event, staged in LDS per workgroup;
 //   4. device radix sort of the keys with the first events (stable);
-//   5. k_pk_tile_first + suffix minimum: each tile's first unit; groups of 64
-//      units per tile, scanned into tile_grp;
+//   5. k_pk_bounds: each tile's and each (tile, gate block) region's first
+//      unit by binary search over the sorted keys; groups of 64 units per
+//      tile, scanned into tile_grp;
 //   6. k_pk_group_len: per group its events and longest unit (from the sorted
 //      keys), scanned into group offsets; per (tile, gate block) region its
-//      events and first unit;
+//      events;
 //   7. k_pk_fill: one workgroup per tile, one wavefront per group: the unit
 //      descriptors, every event's record in the unit-interleaved order, the
 //      group's table quad range, and the most events in one bin (LDS
@@ -344,55 +345,39 @@ __global__ void __launch_bounds__(256) k_pk_fill_u64(uint64_t* p, int64_t n, uin
   if (i < n) p[i] = v;
 }
 
-// First sorted unit of every non-empty tile (others keep their fill value).
+// First sorted unit at or after a boundary key, by binary search over the
+// sorted keys: thread i < n_first gives tile i (i = n_tiles: the end), the
+// others the (tile, gate block) regions r = i - n_first (r = n_reg: the end).
+// An empty tile or region gets the first unit of the next non-empty one.
 template <class K>
-__global__ void __launch_bounds__(256) k_pk_tile_first(const K* skey, int64_t nu, int32_t shift, uint32_t* tfirst) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nu) return;
-  const uint64_t t = (uint64_t)(skey[j] >> shift);
-  if (j == 0 || (uint64_t)(skey[j - 1] >> shift) != t) tfirst[t] = (uint32_t)j;
-}
-
-// First sorted unit of every non-empty (tile, gate block) region.
-template <class K>
-__global__ void __launch_bounds__(256) k_pk_region_first(const K* skey, int64_t nu, KeyLayout L, int32_t n_gb,
-                                                         uint32_t* rfirst) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nu) return;
-  const int shift = L.gb_bits + key_low(L);
-  auto region = [&](K k) -> int64_t { return (int64_t)(k >> shift) * n_gb + (int64_t)key_gb(k, L); };
-  const int64_t r = region(skey[j]);
-  if (j == 0 || region(skey[j - 1]) != r) rfirst[r] = (uint32_t)j;
-}
-
-// In place, p[i] = min(p[i], p[i+1], ..., p[n-1]) (one workgroup of 1024
-// threads, chunks of 1024 from the end): fills the entries of empty tiles and
-// regions with the first unit of the next non-empty one.
-__global__ void __launch_bounds__(1024) k_pk_suffix_min(uint32_t* p, int64_t n) {
-  __shared__ uint32_t wmin[16];
-  __shared__ uint32_t carry_sh;
-  const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
-  uint32_t carry = 0xffffffffu;
-  for (int64_t end = n; end > 0; end -= 1024) {
-    // element end - 1 - threadIdx.x: thread 0 holds the last element
-    const int64_t i = end - 1 - (int64_t)threadIdx.x;
-    uint32_t v = i >= 0 ? p[i] : 0xffffffffu;
-    // inclusive min over threads 0..threadIdx.x (= elements i..end-1)
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t t = __shfl_up(v, o, 64);
-      if (lane >= o) v = min(v, t);
-    }
-    if (lane == 63) wmin[wave] = v;
-    __syncthreads();
-    uint32_t pre = carry;
-    for (int w = 0; w < wave; ++w) pre = min(pre, wmin[w]);
-    v = min(v, pre);
-    if (i >= 0) p[i] = v;
-    if (threadIdx.x == 1023) carry_sh = v;
-    __syncthreads();
-    carry = carry_sh;
-    __syncthreads();
+__global__ void __launch_bounds__(256) k_pk_bounds(const K* skey, int64_t nu, KeyLayout L, int32_t n_tiles,
+                                                   int32_t n_gb, uint32_t* tfirst, uint32_t* rfirst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_first = (int64_t)n_tiles + 1, n_reg = (int64_t)n_tiles * n_gb;
+  if (i >= n_first + n_reg + 1) return;
+  const int low = key_low(L), tshift = L.gb_bits + low;
+  K target;
+  bool end;
+  if (i < n_first) {
+    end = i == n_tiles;
+    target = (K)i << tshift;
+  } else {
+    const int64_t r = i - n_first;
+    end = r == n_reg;
+    target = ((K)(r / n_gb) << tshift) | ((K)(r % n_gb) << low);
   }
+  int64_t lo = end ? nu : 0, hi = nu;   // the first j with skey[j] >= target
+  while (lo < hi) {
+    const int64_t m = (lo + hi) >> 1;
+    if (skey[m] < target)
+      lo = m + 1;
+    else
+      hi = m;
+  }
+  if (i < n_first)
+    tfirst[i] = (uint32_t)lo;
+  else
+    rfirst[i - n_first] = (uint32_t)lo;
 }
 
 // Groups of every tile: ceil(units / 64).
@@ -1094,21 +1079,19 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     PK(e2);
     o.tile_grp = (int32_t*)own((size_t)(n_tiles + 1) * 4, e2);
     PK(e2);
-    hipLaunchKernelGGL(k_pk_fill_u32, dim3((unsigned)((n_tiles + 1 + 255) / 256)), dim3(256), 0, s, o.tfirst,
-                       (int64_t)(n_tiles + 1), (uint32_t)NU);
-    PKLAUNCH("k_pk_fill_u32");
-    if (NU > 0) {
-      const dim3 gu((unsigned)((NU + 255) / 256));
+    o.reg_first = (uint32_t*)own((size_t)(n_reg + 1) * 4, e2);
+    PK(e2);
+    {
+      const int64_t nb = (int64_t)n_tiles + 1 + n_reg + 1;
+      const dim3 gbd((unsigned)((nb + 255) / 256));
       if (key64)
-        hipLaunchKernelGGL(k_pk_tile_first<uint64_t>, gu, dim3(256), 0, s, (const uint64_t*)skeys, NU,
-                           gb_bits + low, o.tfirst);
+        hipLaunchKernelGGL(k_pk_bounds<uint64_t>, gbd, dim3(256), 0, s, (const uint64_t*)skeys, NU, kl, n_tiles, n_gb,
+                           o.tfirst, o.reg_first);
       else
-        hipLaunchKernelGGL(k_pk_tile_first<uint32_t>, gu, dim3(256), 0, s, (const uint32_t*)skeys, NU,
-                           gb_bits + low, o.tfirst);
-      PKLAUNCH("k_pk_tile_first");
+        hipLaunchKernelGGL(k_pk_bounds<uint32_t>, gbd, dim3(256), 0, s, (const uint32_t*)skeys, NU, kl, n_tiles, n_gb,
+                           o.tfirst, o.reg_first);
+      PKLAUNCH("k_pk_bounds");
     }
-    hipLaunchKernelGGL(k_pk_suffix_min, dim3(1), dim3(1024), 0, s, o.tfirst, (int64_t)(n_tiles + 1));
-    PKLAUNCH("k_pk_suffix_min");
     hipLaunchKernelGGL(k_pk_tile_groups, dim3((unsigned)((n_tiles + 1 + 255) / 256)), dim3(256), 0, s,
                        (const uint32_t*)o.tfirst, n_tiles, gk);
     PKLAUNCH("k_pk_tile_groups");
@@ -1145,23 +1128,6 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     PKLAUNCH("k_pk_group_len");
     scan_add<int64_t>(glen, o.grp_off, gsums, ng + 1, s);
     PKLAUNCH("scan of group events");
-    o.reg_first = (uint32_t*)own((size_t)(n_reg + 1) * 4, e2);
-    PK(e2);
-    hipLaunchKernelGGL(k_pk_fill_u32, dim3((unsigned)((n_reg + 1 + 255) / 256)), dim3(256), 0, s, o.reg_first,
-                       n_reg + 1, (uint32_t)NU);
-    PKLAUNCH("k_pk_fill_u32");
-    if (NU > 0) {
-      const dim3 gu((unsigned)((NU + 255) / 256));
-      if (key64)
-        hipLaunchKernelGGL(k_pk_region_first<uint64_t>, gu, dim3(256), 0, s, (const uint64_t*)skeys, NU, kl, n_gb,
-                           o.reg_first);
-      else
-        hipLaunchKernelGGL(k_pk_region_first<uint32_t>, gu, dim3(256), 0, s, (const uint32_t*)skeys, NU, kl, n_gb,
-                           o.reg_first);
-      PKLAUNCH("k_pk_region_first");
-    }
-    hipLaunchKernelGGL(k_pk_suffix_min, dim3(1), dim3(1024), 0, s, o.reg_first, n_reg + 1);
-    PKLAUNCH("k_pk_suffix_min");
     // ---- 7. fill --------------------------------------------------------
     // every event may be packed (events outside the window are not: the
     // arrays keep room for them)
