@@ -452,7 +452,12 @@ __global__ void __launch_bounds__(kThreads) k_fwd_packed(PackedFwdArgs a) {
   unsigned long long* xs = reinterpret_cast<unsigned long long*>(lds + packed_bins_word_offset(a.lib.lds_words_ml));
   unsigned long long* ss = xs + (1 << a.bins.tile_log2);
   float4* slots = a.phases ? reinterpret_cast<float4*>(ss + (1 << a.bins.tile_log2)) : nullptr;
-  fwd_tile_body<kThreads, kS, kSlotOnly, kGl>(a, L, xs, ss, (int32_t)blockIdx.x, slots);
+  // one tile per workgroup; past the largest grid (a dispatch holds at most
+  // 2^32 work-items) the workgroups take further tiles in turn
+  for (int64_t tile = blockIdx.x; tile < a.bins.n_tiles; tile += gridDim.x) {
+    if (tile != blockIdx.x) __syncthreads();   // the previous tile is done with the LDS
+    fwd_tile_body<kThreads, kS, kSlotOnly, kGl>(a, L, xs, ss, (int32_t)tile, slots);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -392,45 +392,50 @@ __global__ void __launch_bounds__(256) k_pk_tile_groups(const uint32_t* tfirst, 
 // events of every (tile, gate block) region (rev, zeroed before; a group spans
 // few regions, each summed over its lanes and added once).
 constexpr int kGroupLenThreads = 1024;
+constexpr int64_t kMaxTileGrid = 1 << 20;   // workgroups of the per-tile builder kernels (a multiple of 8)
 template <class K>
 __global__ void __launch_bounds__(kGroupLenThreads) k_pk_group_len(const uint32_t* tile_grp, const uint32_t* tfirst, const K* skey,
                                                       KeyLayout L, int32_t n_gb, int64_t* glen, unsigned long long* rev,
-                                                      unsigned long long* lane_steps, uint32_t* max_tile_groups) {
-  const int32_t k = blockIdx.x;
+                                                      unsigned long long* lane_steps, uint32_t* max_tile_groups,
+                                                      int32_t n_tiles) {
   const int lane = (int)(threadIdx.x & 63);
-  const int64_t g0 = tile_grp[k], g1 = tile_grp[k + 1];
-  const int64_t j1 = tfirst[k + 1];
   unsigned long long steps = 0;
-  for (int64_t g = g0 + (threadIdx.x >> 6); g < g1; g += blockDim.x >> 6) {
-    const int64_t j = tfirst[k] + (g - g0) * kGroupUnits + lane;
-    const bool act = j < j1;
-    const K key = act ? skey[j] : (K)0;
-    const uint32_t len = act ? key_len(key, L) : 0u;
-    uint32_t s = len, mx = len;
-    for (int o = 32; o > 0; o >>= 1) {
-      s += __shfl_xor(s, o, 64);
-      mx = max(mx, __shfl_xor(mx, o, 64));
-    }
-    if (lane == 0) {
-      glen[g] = s;
-      steps += mx;
-    }
-    // region events: one pass per distinct region among the active lanes
-    const int64_t reg = (int64_t)k * n_gb + (int64_t)key_gb(key, L);
-    uint64_t todo = __ballot(act);
-    while (todo) {
-      const int first = __ffsll((unsigned long long)todo) - 1;
-      const int64_t r0 = __shfl(reg, first, 64);
-      const bool mine = act && reg == r0;
-      const uint64_t m = __ballot(mine);
-      uint32_t v = mine ? len : 0u;
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      if (lane == first) atomicAdd(&rev[r0], (unsigned long long)v);
-      todo &= ~m;
+  // workgroups stride over the tiles (a grid of one workgroup per tile would
+  // exceed the 2^32 work-items of a dispatch for millions of tiles)
+  for (int32_t k = blockIdx.x; k < n_tiles; k += gridDim.x) {
+    const int64_t g0 = tile_grp[k], g1 = tile_grp[k + 1];
+    const int64_t j1 = tfirst[k + 1];
+    if (threadIdx.x == 0) atomicMax(max_tile_groups, (uint32_t)(g1 - g0));
+    for (int64_t g = g0 + (threadIdx.x >> 6); g < g1; g += blockDim.x >> 6) {
+      const int64_t j = tfirst[k] + (g - g0) * kGroupUnits + lane;
+      const bool act = j < j1;
+      const K key = act ? skey[j] : (K)0;
+      const uint32_t len = act ? key_len(key, L) : 0u;
+      uint32_t s = len, mx = len;
+      for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o, 64);
+        mx = max(mx, __shfl_xor(mx, o, 64));
+      }
+      if (lane == 0) {
+        glen[g] = s;
+        steps += mx;
+      }
+      // region events: one pass per distinct region among the active lanes
+      const int64_t reg = (int64_t)k * n_gb + (int64_t)key_gb(key, L);
+      uint64_t todo = __ballot(act);
+      while (todo) {
+        const int first = __ffsll((unsigned long long)todo) - 1;
+        const int64_t r0 = __shfl(reg, first, 64);
+        const bool mine = act && reg == r0;
+        const uint64_t m = __ballot(mine);
+        uint32_t v = mine ? len : 0u;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == first) atomicAdd(&rev[r0], (unsigned long long)v);
+        todo &= ~m;
+      }
     }
   }
   if (lane == 0 && steps) atomicAdd(lane_steps, steps);
-  if (threadIdx.x == 0) atomicMax(max_tile_groups, (uint32_t)(g1 - g0));
 }
 
 struct FillArgs {
@@ -456,7 +461,8 @@ struct FillArgs {
   int32_t* max_bin;           // most events in one bin
 };
 
-// Item of workgroup w in a grid of n workgroups (n a multiple of 8), so that
+// Item of workgroup w in a launch of n items (n a multiple of 8; items past
+// the grid are taken by the workgroups again, w + gridDim.x, ...), so that
 // XCD x = w % 8 takes items [x n/8, (x+1) n/8) in launch order.
 __device__ __forceinline__ int64_t xcd_item(int64_t w, int64_t n) { return (w % 8) * (n / 8) + w / 8; }
 
@@ -474,85 +480,91 @@ __global__ void __launch_bounds__(kFillThreads) k_pk_fill(FillArgs a) {
   // tiles go to XCDs in contiguous ranges (workgroup w runs on XCD w % 8):
   // a gate's records of neighbouring tiles share cache lines, and the
   // workgroups of neighbouring tiles then read them through one L2
-  const int32_t k = (int32_t)xcd_item(blockIdx.x, gridDim.x);
-  if (k >= a.bins.n_tiles) return;
   extern __shared__ uint32_t lds[];
   int32_t* hist = reinterpret_cast<int32_t*>(lds);   // events per bin of the tile
   const BinSpec& B = a.bins;
-  for (int i = threadIdx.x; i < (1 << B.tile_log2); i += blockDim.x) hist[i] = 0;
-  __syncthreads();
-  const int lane = (int)(threadIdx.x & 63);
-  const int64_t g0 = a.tile_grp[k], g1 = a.tile_grp[k + 1];
-  const int64_t jend = a.tfirst[k + 1];
-  const K* skeys = static_cast<const K*>(a.skeys);
-  const KeyLayout kl = a.kl;
-  for (int64_t gi = g0 + (threadIdx.x >> 6); gi < g1; gi += blockDim.x >> 6) {
-    const int64_t j = (int64_t)a.tfirst[k] + (gi - g0) * kGroupUnits + lane;
-    const bool act = j < jend;
-    int len = 0;
-    uint32_t gb = 0, gin_k = 0;   // gin_k: the gate-index field (the whole index when not shifted)
-    int64_t src = 0;
-    if (act) {
-      const K key = skeys[j];
-      src = (int64_t)a.ssrc[j];
-      len = (int)key_len(key, kl);
-      gb = key_gb(key, kl);
-      gin_k = (uint32_t)(key & (K)((1ull << kl.gin_bits) - 1ull));
-    }
-    const uint32_t gs0 = act ? (uint32_t)a.gb_start[gb] : 0u;
-    const int cell = act ? a.gb_cell[gb] : 0;
-    uint4 r[kS];
-    float rg[kS];
-#pragma unroll
-    for (int kk = 0; kk < kS; ++kk) {
-      if (kk < len) {
-        r[kk] = a.rec[src + kk];
-        if (a.rgl) rg[kk] = a.rgl_g[src + kk];
+  // workgroups stride over the tiles beyond kMaxTileGrid (a multiple of 8,
+  // so a workgroup keeps its XCD's range)
+  const int64_t n_items = ((int64_t)B.n_tiles + 7) / 8 * 8;
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int32_t k = (int32_t)xcd_item(it, n_items);
+    if (k >= B.n_tiles) continue;   // uniform over the workgroup
+    __syncthreads();   // the previous tile's histogram has been read
+    for (int i = threadIdx.x; i < (1 << B.tile_log2); i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t g0 = a.tile_grp[k], g1 = a.tile_grp[k + 1];
+    const int64_t jend = a.tfirst[k + 1];
+    const K* skeys = static_cast<const K*>(a.skeys);
+    const KeyLayout kl = a.kl;
+    for (int64_t gi = g0 + (threadIdx.x >> 6); gi < g1; gi += blockDim.x >> 6) {
+      const int64_t j = (int64_t)a.tfirst[k] + (gi - g0) * kGroupUnits + lane;
+      const bool act = j < jend;
+      int len = 0;
+      uint32_t gb = 0, gin_k = 0;   // gin_k: the gate-index field (the whole index when not shifted)
+      int64_t src = 0;
+      if (act) {
+        const K key = skeys[j];
+        src = (int64_t)a.ssrc[j];
+        len = (int)key_len(key, kl);
+        gb = key_gb(key, kl);
+        gin_k = (uint32_t)(key & (K)((1ull << kl.gin_bits) - 1ull));
       }
-    }
-    // descriptor: the cell-sorted gate | (length - 1) << 28, the leakage state
-    // before the unit | cell << 16
-    const uint32_t dy = act ? ((r[0].w & 0xffffu) | ((uint32_t)cell << 16)) : 0u;
-    const uint32_t gin = kl.gin_shift ? (r[0].w >> 16) : gin_k;
-    const uint32_t dx = act ? ((gs0 + gin) | ((uint32_t)(len - 1) << 28)) : 0xffffffffu;
-    a.desc[gi * kGroupUnits + lane] = make_uint2(dx, dy);
-    if (a.gquads) {
-      const uint64_t m = __ballot(act);
-      if (m == 0) {
-        if (lane == 0) a.gquads[gi] = make_int4(-1, -1, -1, -1);
-      } else {
-        const int32_t clo = act ? a.cq_lo[cell] : INT32_MAX, chi = act ? a.cq_hi[cell] : INT32_MIN;
-        int32_t lo = clo, hi = chi;
-        for (int o = 32; o > 0; o >>= 1) {
-          lo = min(lo, __shfl_xor(lo, o, 64));
-          hi = max(hi, __shfl_xor(hi, o, 64));
+      const uint32_t gs0 = act ? (uint32_t)a.gb_start[gb] : 0u;
+      const int cell = act ? a.gb_cell[gb] : 0;
+      uint4 r[kS];
+      float rg[kS];
+  #pragma unroll
+      for (int kk = 0; kk < kS; ++kk) {
+        if (kk < len) {
+          r[kk] = a.rec[src + kk];
+          if (a.rgl) rg[kk] = a.rgl_g[src + kk];
         }
-        if (lane == __ffsll((unsigned long long)m) - 1) a.gquads[gi] = make_int4(lo, hi, clo, chi);
+      }
+      // descriptor: the cell-sorted gate | (length - 1) << 28, the leakage state
+      // before the unit | cell << 16
+      const uint32_t dy = act ? ((r[0].w & 0xffffu) | ((uint32_t)cell << 16)) : 0u;
+      const uint32_t gin = kl.gin_shift ? (r[0].w >> 16) : gin_k;
+      const uint32_t dx = act ? ((gs0 + gin) | ((uint32_t)(len - 1) << 28)) : 0xffffffffu;
+      a.desc[gi * kGroupUnits + lane] = make_uint2(dx, dy);
+      if (a.gquads) {
+        const uint64_t m = __ballot(act);
+        if (m == 0) {
+          if (lane == 0) a.gquads[gi] = make_int4(-1, -1, -1, -1);
+        } else {
+          const int32_t clo = act ? a.cq_lo[cell] : INT32_MAX, chi = act ? a.cq_hi[cell] : INT32_MIN;
+          int32_t lo = clo, hi = chi;
+          for (int o = 32; o > 0; o >>= 1) {
+            lo = min(lo, __shfl_xor(lo, o, 64));
+            hi = max(hi, __shfl_xor(hi, o, 64));
+          }
+          if (lane == __ffsll((unsigned long long)m) - 1) a.gquads[gi] = make_int4(lo, hi, clo, chi);
+        }
+      }
+      int64_t off = a.grp_off[gi];
+  #pragma unroll
+      for (int kk = 0; kk < kS; ++kk) {
+        const bool on = len > kk;
+        const uint64_t m = __ballot(on);
+        if (m == 0) break;
+        if (on) {
+          const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+          const int64_t pos = off + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+          atomicAdd(&hist[(r[kk].x & kTimeMask) >> B.r_bits], 1);
+          a.w32[pos] = r[kk].x;
+          a.row[pos] = r[kk].y;
+          a.alpha[pos] = __uint_as_float(r[kk].z);
+          if (a.rgl) a.rgl[pos] = rg[kk];
+        }
+        off += __popcll(m);
       }
     }
-    int64_t off = a.grp_off[gi];
-#pragma unroll
-    for (int kk = 0; kk < kS; ++kk) {
-      const bool on = len > kk;
-      const uint64_t m = __ballot(on);
-      if (m == 0) break;
-      if (on) {
-        const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
-        const int64_t pos = off + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-        atomicAdd(&hist[(r[kk].x & kTimeMask) >> B.r_bits], 1);
-        a.w32[pos] = r[kk].x;
-        a.row[pos] = r[kk].y;
-        a.alpha[pos] = __uint_as_float(r[kk].z);
-        if (a.rgl) a.rgl[pos] = rg[kk];
-      }
-      off += __popcll(m);
-    }
+    __syncthreads();
+    int mx = 0;
+    for (int i = threadIdx.x; i < (1 << B.tile_log2); i += blockDim.x) mx = max(mx, hist[i]);
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0 && mx > 0) atomicMax(a.max_bin, mx);
   }
-  __syncthreads();
-  int mx = 0;
-  for (int i = threadIdx.x; i < (1 << B.tile_log2); i += blockDim.x) mx = max(mx, hist[i]);
-  for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
-  if (lane == 0 && mx > 0) atomicMax(a.max_bin, mx);
 }
 
 // Table phases of one tile (one wavefront per tile): a phase starts at a
@@ -1117,14 +1129,17 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
                          (uint64_t)0);
       PKLAUNCH("k_pk_fill_u64");
     }
+    // workgroups of the per-tile kernels: one per tile up to kMaxTileGrid (a
+    // multiple of 8), striding beyond
+    const unsigned grid_tiles = (unsigned)std::min<int64_t>(((int64_t)n_tiles + 7) / 8 * 8, kMaxTileGrid);
     if (key64)
-      hipLaunchKernelGGL(k_pk_group_len<uint64_t>, dim3((unsigned)n_tiles), dim3(kGroupLenThreads), 0, s,
+      hipLaunchKernelGGL(k_pk_group_len<uint64_t>, dim3(grid_tiles), dim3(kGroupLenThreads), 0, s,
                          (const uint32_t*)o.tile_grp, (const uint32_t*)o.tfirst, (const uint64_t*)skeys, kl, n_gb,
-                         glen, (unsigned long long*)rev, (unsigned long long*)(d_nu + 2), d_nu + 4);
+                         glen, (unsigned long long*)rev, (unsigned long long*)(d_nu + 2), d_nu + 4, n_tiles);
     else
-      hipLaunchKernelGGL(k_pk_group_len<uint32_t>, dim3((unsigned)n_tiles), dim3(kGroupLenThreads), 0, s,
+      hipLaunchKernelGGL(k_pk_group_len<uint32_t>, dim3(grid_tiles), dim3(kGroupLenThreads), 0, s,
                          (const uint32_t*)o.tile_grp, (const uint32_t*)o.tfirst, (const uint32_t*)skeys, kl, n_gb,
-                         glen, (unsigned long long*)rev, (unsigned long long*)(d_nu + 2), d_nu + 4);
+                         glen, (unsigned long long*)rev, (unsigned long long*)(d_nu + 2), d_nu + 4, n_tiles);
     PKLAUNCH("k_pk_group_len");
     scan_add<int64_t>(glen, o.grp_off, gsums, ng + 1, s);
     PKLAUNCH("scan of group events");
@@ -1172,7 +1187,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
         fa.cq_hi = d_cq + n_cells;
         fa.max_bin = (int32_t*)d_nu + 1;
         const size_t lds = (size_t)4 << B.tile_log2;
-        const unsigned gridf = (unsigned)((n_tiles + 7) / 8 * 8);   // a multiple of the XCD count
+        const unsigned gridf = grid_tiles;   // a multiple of the XCD count
         PK(launch_fill(in.unit_events <= 8, key64, fa, gridf, lds, s));
         PKLAUNCH("k_pk_fill");
       }

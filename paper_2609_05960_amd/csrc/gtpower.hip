@@ -492,6 +492,7 @@ size_t slot_bytes(int32_t slot_quads) { return 2 * (size_t)slot_quads * 16; }
 // 512 threads (the registers of 1024 threads do not fit).
 constexpr int kDefaultUnitEvents = 8;
 constexpr int kXcds = 8;   // XCDs of the MI355X: workgroup i runs on XCD i % 8
+constexpr int64_t kMaxFwdGrid = 1 << 20;   // workgroups of a packed forward launch (tiles beyond are strided)
 int threads_for_slots(int th, int slots) { return (slots == 16 && th > 512) ? 512 : th; }
 int unit_events_of(gtp_ctx c) { return c->tun.unit_events ? c->tun.unit_events : kDefaultUnitEvents; }
 int slots_of(gtp_ctx c) { return unit_events_of(c) <= 8 ? 8 : 16; }
@@ -1597,7 +1598,7 @@ gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, in
   const size_t lds = packed_lds_bytes(c, B.tile_log2) + (ph ? slot_bytes(pk.slot_quads) : 0);
   const int sl = slots_of(c);
   const int th = threads_for_slots(tile_threads(c), sl);
-  const dim3 grid((unsigned)B.n_tiles);
+  const dim3 grid((unsigned)std::min<int64_t>(B.n_tiles, kMaxFwdGrid));
   // every quad from the LDS slots when every phase holds all its groups' quads
   const bool so = ph && pk.phases_full;
   a.rgl = pk.rgl;
