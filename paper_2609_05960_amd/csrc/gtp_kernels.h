@@ -83,9 +83,7 @@ __device__ __forceinline__ EventOut event_energy(GateCtx& G, const LdsLib& L, co
 // end the tile's bins are stored (each bin belongs to exactly one tile, so
 // no global atomics and no zero fill are needed).
 struct PackedFwdArgs {
-  const uint32_t* w32;       // event words
-  const uint32_t* row;       // table rows
-  const float* alpha;        // slew weights
+  const uint32_t* ev;        // per group: event words, table rows, slew weights (3 words per event)
   const uint2* desc;
   const int64_t* grp_off;
   const int32_t* tile_grp;
@@ -148,9 +146,13 @@ __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int
   // scalar base and a 32-bit lane offset
   const int64_t offu = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(off >> 32)) << 32) |
                                  (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)off));
-  const uint32_t* __restrict__ wp = a.w32 + offu;
-  const uint32_t* __restrict__ rp = a.row + offu;
-  const float* __restrict__ ap = a.alpha + offu;
+  // the group's block of 3 n_g words: n_g (its events) from the lengths
+  uint32_t n_g = 0;
+#pragma unroll
+  for (int kk = 0; kk < kS; ++kk) n_g += (uint32_t)__popcll(__ballot(G.len > kk));
+  const uint32_t* __restrict__ wp = a.ev + 3 * offu;
+  const uint32_t* __restrict__ rp = wp + n_g;
+  const float* __restrict__ ap = reinterpret_cast<const float*>(wp + 2 * n_g);
   uint32_t o = 0;
   G.kmax = 0;
   // slot kk holds event kk of every lane longer than kk; slots past the
@@ -464,9 +466,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_packed(PackedFwdArgs a) {
 // batched traces: one persistent launch over all (trace, tile) work items
 // ---------------------------------------------------------------------------
 struct TraceDev {
-  const uint32_t* w32;
-  const uint32_t* row;
-  const float* alpha;
+  const uint32_t* ev;
   const float* rgl;
   const int4* phases;
   const int32_t* ph_off;
@@ -501,9 +501,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_batched(BatchFwdArgs a) {
   const int2 w = a.items[blockIdx.x];
   const TraceDev T = a.traces[w.x];
   PackedFwdArgs p = a.base;
-  p.w32 = T.w32;
-  p.row = T.row;
-  p.alpha = T.alpha;
+  p.ev = T.ev;
   p.rgl = T.rgl;
   p.desc = T.desc;
   p.grp_off = T.grp_off;

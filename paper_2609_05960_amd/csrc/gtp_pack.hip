@@ -450,9 +450,7 @@ struct FillArgs {
   const uint32_t* tile_grp;
   const uint32_t* tfirst;
   const int64_t* grp_off;
-  uint32_t* w32;
-  uint32_t* row;
-  float* alpha;
+  uint32_t* ev;               // grouped event words, rows and slew weights
   float* rgl;
   uint2* desc;
   int4* gquads;               // optional: quad range of every group's cells (see below)
@@ -541,7 +539,11 @@ __global__ void __launch_bounds__(kFillThreads) k_pk_fill(FillArgs a) {
           if (lane == __ffsll((unsigned long long)m) - 1) a.gquads[gi] = make_int4(lo, hi, clo, chi);
         }
       }
-      int64_t off = a.grp_off[gi];
+      // the group's block: n_g event words, then n_g rows, then n_g weights
+      const int64_t off0 = a.grp_off[gi];
+      const int64_t n_g = a.grp_off[gi + 1] - off0;
+      uint32_t* const blk = a.ev + 3 * off0;
+      int64_t j0 = 0;   // the group's events before slot kk
   #pragma unroll
       for (int kk = 0; kk < kS; ++kk) {
         const bool on = len > kk;
@@ -549,14 +551,14 @@ __global__ void __launch_bounds__(kFillThreads) k_pk_fill(FillArgs a) {
         if (m == 0) break;
         if (on) {
           const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
-          const int64_t pos = off + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+          const int64_t j = j0 + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
           atomicAdd(&hist[(r[kk].x & kTimeMask) >> B.r_bits], 1);
-          a.w32[pos] = r[kk].x;
-          a.row[pos] = r[kk].y;
-          a.alpha[pos] = __uint_as_float(r[kk].z);
-          if (a.rgl) a.rgl[pos] = rg[kk];
+          blk[j] = r[kk].x;
+          blk[n_g + j] = r[kk].y;
+          blk[2 * n_g + j] = r[kk].z;
+          if (a.rgl) a.rgl[off0 + j] = rg[kk];
         }
-        off += __popcll(m);
+        j0 += __popcll(m);
       }
     }
     __syncthreads();
@@ -803,8 +805,8 @@ hipError_t launch_fill(bool short_units, bool key64, const FillArgs& fa, unsigne
 }  // namespace
 
 void pack_free(PackOut* o) {
-  void* ps[] = {o->w32,  o->row,  o->alpha, o->rgl,       o->desc,   o->grp_off, o->tile_grp, o->gperm,
-                o->gcell, o->gout, o->ginit, o->reg_first, o->tfirst, o->phases,  o->ph_off};
+  void* ps[] = {o->ev,   o->rgl,   o->desc,  o->grp_off, o->tile_grp, o->gperm, o->gcell,
+                o->gout, o->ginit, o->reg_first, o->tfirst, o->phases, o->ph_off};
   for (void* p : ps) {
     const char* q = static_cast<const char*>(p);
     if (p && !(o->arena_lo && q >= o->arena_lo && q < o->arena_lo + o->arena_len)) (void)hipFree(p);
@@ -1146,11 +1148,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     // ---- 7. fill --------------------------------------------------------
     // every event may be packed (events outside the window are not: the
     // arrays keep room for them)
-    o.w32 = (uint32_t*)own((size_t)N * 4, e2);
-    PK(e2);
-    o.row = (uint32_t*)own((size_t)N * 4, e2);
-    PK(e2);
-    o.alpha = (float*)own((size_t)N * 4, e2);
+    o.ev = (uint32_t*)own((size_t)N * 12, e2);
     PK(e2);
     o.desc = (uint2*)own((size_t)ng * kGroupUnits * 8, e2);
     PK(e2);
@@ -1177,9 +1175,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
         fa.tile_grp = (const uint32_t*)o.tile_grp;
         fa.tfirst = o.tfirst;
         fa.grp_off = o.grp_off;
-        fa.w32 = o.w32;
-        fa.row = o.row;
-        fa.alpha = o.alpha;
+        fa.ev = o.ev;
         fa.rgl = o.rgl;
         fa.desc = o.desc;
         fa.gquads = phases ? gquads : nullptr;

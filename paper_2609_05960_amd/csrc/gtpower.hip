@@ -534,7 +534,7 @@ void drop_batch_packs(gtp_ctx c);
 void drop_batch(gtp_ctx c);
 
 void drop_pack(gtp_ctx c) {
-  if (c->pk.w32 || c->pk.gperm) {
+  if (c->pk.ev || c->pk.gperm) {
     (void)hipStreamSynchronize(c->stream);
     c->dev_bytes -= c->pk.bytes;
     pack_free(&c->pk);
@@ -1582,9 +1582,7 @@ gtp_status packed_forward_for(gtp_ctx c, const PackOut& pk, const BinSpec& B, in
   PackedFwdArgs a = packed_common(c, pk.mfix);
   if (gparam) a.gparam = gparam;
   a.tile_tot = tile_tot;
-  a.w32 = pk.w32;
-  a.row = pk.row;
-  a.alpha = pk.alpha;
+  a.ev = pk.ev;
   a.desc = pk.desc;
   a.grp_off = pk.grp_off;
   a.tile_grp = pk.tile_grp;
@@ -1675,7 +1673,7 @@ void drop_batch_packs(gtp_ctx c) {
   drop_graph(c);
   if (c->batch_packed) (void)hipStreamSynchronize(c->stream);
   for (auto& t : c->batch) {
-    if (t.pk.w32 || t.pk.gperm) {
+    if (t.pk.ev || t.pk.gperm) {
       c->dev_bytes -= t.pk.bytes;
       pack_free(&t.pk);
     }
@@ -1729,9 +1727,7 @@ gtp_status build_batch(gtp_ctx c) {
     }
     t.bin_off = off;
     const bool ph = t.pk.phases && t.pk.slot_quads > 0;
-    tab[i] = TraceDev{t.pk.w32,
-                      t.pk.row,
-                      t.pk.alpha,
+    tab[i] = TraceDev{t.pk.ev,
                       t.pk.rgl,
                       ph ? t.pk.phases : nullptr,
                       ph ? t.pk.ph_off : nullptr,
@@ -2200,9 +2196,7 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       const PackOut& pk = c->pk;
       AdjPackedArgs a;
       a.f = packed_common(c, pk.mfix);
-      a.f.w32 = pk.w32;
-      a.f.row = pk.row;
-      a.f.alpha = pk.alpha;
+      a.f.ev = pk.ev;
       a.f.desc = pk.desc;
       a.f.grp_off = pk.grp_off;
       a.f.tile_grp = pk.tile_grp;
