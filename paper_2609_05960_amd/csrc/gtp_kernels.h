@@ -83,7 +83,7 @@ __device__ __forceinline__ EventOut event_energy(GateCtx& G, const LdsLib& L, co
 // end the tile's bins are stored (each bin belongs to exactly one tile, so
 // no global atomics and no zero fill are needed).
 struct PackedFwdArgs {
-  const uint32_t* ev;        // per group: event words, table rows, slew weights (3 words per event)
+  const uint32_t* ev;        // per event: word, table row, slew weight (3 words)
   const uint2* desc;
   const int64_t* grp_off;
   const int32_t* tile_grp;
@@ -146,13 +146,8 @@ __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int
   // scalar base and a 32-bit lane offset
   const int64_t offu = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(off >> 32)) << 32) |
                                  (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)off));
-  // the group's block of 3 n_g words: n_g (its events) from the lengths
-  uint32_t n_g = 0;
-#pragma unroll
-  for (int kk = 0; kk < kS; ++kk) n_g += (uint32_t)__popcll(__ballot(G.len > kk));
-  const uint32_t* __restrict__ wp = a.ev + 3 * offu;
-  const uint32_t* __restrict__ rp = wp + n_g;
-  const float* __restrict__ ap = reinterpret_cast<const float*>(wp + 2 * n_g);
+  // the group's events: word, row and slew weight of each, 12 bytes
+  const uint3* __restrict__ ep = reinterpret_cast<const uint3*>(a.ev) + offu;
   uint32_t o = 0;
   G.kmax = 0;
   // slot kk holds event kk of every lane longer than kk; slots past the
@@ -166,9 +161,10 @@ __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int
       if (on && mine) {
         const uint32_t r =
             o + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        G.wv[kk] = wp[r];
-        G.rv[kk] = rp[r];
-        G.av[kk] = ap[r];
+        const uint3 v = ep[r];
+        G.wv[kk] = v.x;
+        G.rv[kk] = v.y;
+        G.av[kk] = __uint_as_float(v.z);
         if (kGl) G.gv[kk] = a.rgl[offu + r];
       }
       o += (uint32_t)__popcll(m);

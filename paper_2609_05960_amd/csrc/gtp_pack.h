@@ -21,17 +21,15 @@
 //          length, increasing gates (the per-unit gate-record loads of a
 //          wavefront touch fewer cache lines).
 //   group  64 consecutive units of one tile, one per lane of a wavefront. The
-//          group's events are ordered unit-interleaved: event k of every unit
+//          group's events are stored unit-interleaved: event k of every unit
 //          longer than k, in lane order, then event k+1, ... So the k-th
-//          loads of a wavefront are adjacent words.
+//          loads of a wavefront are adjacent records.
 //
 // Arrays (device, owned by the ctx):
-//   ev[3n]    per group, one contiguous block of 3 n_g words (n_g its
-//             events, in the group's order): the n_g event words (see
-//             gtp_device.h: in-tile time, input state after the event), then
-//             the n_g table rows (row at the slew segment, output flag,
-//             value), then the n_g slew weights (FP32); a group's block
-//             starts at word 3 grp_off[g]
+//   ev[3n]    per event, in the groups' order (group g from grp_off[g]),
+//             three words: the event word (see gtp_device.h: in-tile time,
+//             input state after the event), the table row (row at the slew
+//             segment, output flag, value) and the slew weight (FP32 bits)
 //   rgl[n]    energy factor (glitch detection on only): the glitch scaling
 //             ratio of a glitch event, 1 for a regular event
 //   desc[64 * n_groups]   unit descriptor: x = cell-sorted gate index
@@ -88,7 +86,7 @@ struct PackIn {
 };
 
 struct PackOut {
-  uint32_t* ev = nullptr;     // 3 words per event, grouped (see above)
+  uint32_t* ev = nullptr;     // 3 words per event (see above)
   float* rgl = nullptr;       // energy factor per event (glitch detection on), else null
   uint2* desc = nullptr;
   int64_t* grp_off = nullptr;

@@ -539,10 +539,9 @@ __global__ void __launch_bounds__(kFillThreads) k_pk_fill(FillArgs a) {
           if (lane == __ffsll((unsigned long long)m) - 1) a.gquads[gi] = make_int4(lo, hi, clo, chi);
         }
       }
-      // the group's block: n_g event words, then n_g rows, then n_g weights
+      // the group's events: per event (in the group's order) its word, row and weight
       const int64_t off0 = a.grp_off[gi];
-      const int64_t n_g = a.grp_off[gi + 1] - off0;
-      uint32_t* const blk = a.ev + 3 * off0;
+      uint3* const blk = reinterpret_cast<uint3*>(a.ev) + off0;
       int64_t j0 = 0;   // the group's events before slot kk
   #pragma unroll
       for (int kk = 0; kk < kS; ++kk) {
@@ -553,9 +552,7 @@ __global__ void __launch_bounds__(kFillThreads) k_pk_fill(FillArgs a) {
           const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
           const int64_t j = j0 + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
           atomicAdd(&hist[(r[kk].x & kTimeMask) >> B.r_bits], 1);
-          blk[j] = r[kk].x;
-          blk[n_g + j] = r[kk].y;
-          blk[2 * n_g + j] = r[kk].z;
+          blk[j] = make_uint3(r[kk].x, r[kk].y, r[kk].z);
           if (a.rgl) a.rgl[off0 + j] = rg[kk];
         }
         j0 += __popcll(m);
