@@ -3,8 +3,8 @@
 // Steps (all on the caller's stream; the host waits twice, for the number of
 // units and the number of groups, which size the arrays, and once at the end
 // for the statistics):
-//   1. gate order: gates sorted by (cell, decreasing event count, gate) with
-//      a device radix sort of 64-bit keys; gate blocks of at most
+//   1. gate order: gates sorted by (cell, octave of the event count largest
+//      first, gate) with a device radix sort of 64-bit keys; gate blocks of at most
 //      2^gate_block_log2 gates of one cell;
 //   2. k_pk_units (count pass): every gate-major lane block of 16 events is
 //      walked in order and split into units wherever the gate or the time
@@ -673,17 +673,22 @@ __global__ void __launch_bounds__(256) k_pk_gate_sorted(const int32_t* gperm, co
                         (uint32_t)in_cell & ((1u << gb_log2) - 1u));
 }
 
-// Sort key of gate g for the cell-sorted gate order: cell, then decreasing
-// weight (its event count unless weights are given; capped at 2^20 - 1),
-// then the gate index (n_cells < 2^16, gates < 2^28).
-constexpr int64_t kWeightCap = (1 << 20) - 1;
+constexpr int kGateCellShift = 35;   // gate key: cell | 64 - octave (7 bits) | gate (28 bits)
+
+// Sort key of gate g for the cell-sorted gate order: cell, then the octave
+// of its weight (its event count unless weights are given), largest first,
+// then the gate index (n_cells < 2^16, gates < 2^28). Busy gates come first,
+// so the long units of a tile lie in a few cache lines of gate records; gates
+// of one octave keep the caller's order, which is the order the emit pass
+// meets them in, so units that tie on a narrowed sort key are already in gate
+// order (a wavefront's gate records then span fewer lines).
 __global__ void __launch_bounds__(256) k_pk_gate_keys(const int32_t* gate_cell, const int64_t* gate_off,
                                                       const int64_t* weight, int64_t n_gates, uint64_t* keys) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n_gates) return;
   const int64_t w = weight ? weight[g] : gate_off[g + 1] - gate_off[g];
-  const uint64_t wq = (uint64_t)(kWeightCap - min(max(w, (int64_t)0), kWeightCap));
-  keys[g] = ((uint64_t)(uint32_t)gate_cell[g] << 48) | (wq << 28) | (uint64_t)g;
+  const int oct = w > 0 ? 64 - __clzll((unsigned long long)w) : 0;   // bit length, 0..63
+  keys[g] = ((uint64_t)(uint32_t)gate_cell[g] << kGateCellShift) | ((uint64_t)(64 - oct) << 28) | (uint64_t)g;
 }
 
 // The sorted keys as the permutation (sorted index -> gate) and each sorted
@@ -694,7 +699,7 @@ __global__ void __launch_bounds__(256) k_pk_gate_order(const uint64_t* skeys, in
   if (r >= n_gates) return;
   const uint64_t k = skeys[r];
   perm[r] = (int32_t)(k & ((1u << 28) - 1u));
-  pcell[r] = (int32_t)(k >> 48);
+  pcell[r] = (int32_t)(k >> kGateCellShift);
 }
 
 int ceil_log2_u64(uint64_t x) {
@@ -945,7 +950,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     size_t gsort_tmp = 0;
     if (G > 0)
       PK(rocprim::radix_sort_keys(nullptr, gsort_tmp, (uint64_t*)nullptr, (uint64_t*)nullptr, (int64_t)G, 0,
-                                  48 + std::max(1, ceil_log2_u64((uint64_t)n_cells)), s));
+                                  kGateCellShift + std::max(1, ceil_log2_u64((uint64_t)n_cells)), s));
     const size_t ws1 = 2 * align256((size_t)n_cells * 4) + 3 * align256((size_t)G * 8) +
                        align256(gsort_tmp) + 2 * align256((size_t)(n_blocks + 1) * 4) +
                        align256((size_t)scan_sums_items(n_blocks + 1) * 4) + align256(64) +
@@ -978,7 +983,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       PKLAUNCH("k_pk_gate_keys");
       size_t tb = gsort_tmp;
       PK(rocprim::radix_sort_keys(tsort, tb, gk, gks, (int64_t)G, 0,
-                                  48 + std::max(1, ceil_log2_u64((uint64_t)n_cells)), s));
+                                  kGateCellShift + std::max(1, ceil_log2_u64((uint64_t)n_cells)), s));
       hipLaunchKernelGGL(k_pk_gate_order, gg, dim3(256), 0, s, gks, (int64_t)G, o.gperm, o.gcell);
       PKLAUNCH("k_pk_gate_order");
       hipLaunchKernelGGL(k_pk_gate_sorted, gg, dim3(256), 0, s, o.gperm, o.gcell, in.gate_out, in.gate_init,
