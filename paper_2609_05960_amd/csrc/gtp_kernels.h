@@ -1618,14 +1618,32 @@ __global__ void __launch_bounds__(kFwdThreads) k_event_trace(TraceArgs a) {
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
-// Block b (events [16b, 16b+16)): its first gate, by binary search of the CSR
-// offsets for the last gate starting at or before the block's first event.
+// Block b (events [16b, 16b+16)): its first gate, the last gate g with
+// gate_off[g] <= 16b. A wavefront's 64 blocks lie in one run of gates, which
+// its lanes find together: each round the 64 lanes probe 64 evenly spaced
+// gates of the current range and keep the tightest bounds around the run (a
+// 65-way search, 3 rounds cut a million gates to a few); each lane then
+// bisects the remaining range for its own block.
 __global__ void __launch_bounds__(256) k_plan_block_gate(const int64_t* gate_off, int64_t n_gates, int64_t n_events,
                                                          uint2* plan, int64_t n_blocks) {
   const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t kw0 = kb - lane;                                        // the wavefront's first block
+  const int64_t kw1 = min(kw0 + 64, n_blocks);                          // one past its last block
+  if (kw0 >= n_blocks) return;                                          // the whole wavefront
+  const int64_t ef = kw0 * kLaneEvents, el = (kw1 - 1) * kLaneEvents;   // first events of its first and last block
+  // invariant: gate_off[lo] <= ef and el < gate_off[hi] (gate_off[0] = 0, gate_off[n_gates] = n_events > el)
+  int64_t lo = 0, hi = n_gates;
+  for (int round = 0; round < 3 && hi - lo > 1; ++round) {
+    const int64_t p = lo + (hi - lo) * (lane + 1) / 65;                // lo < p < hi when hi - lo >= 65; else may equal
+    const int64_t v = gate_off[p];
+    const uint64_t below = __ballot(v <= ef);                           // lanes form a prefix (offsets ascend)
+    const uint64_t above = __ballot(v > el);                            // lanes form a suffix
+    if (below) lo = __shfl(p, 63 - __clzll((long long)below), 64);
+    if (above) hi = __shfl(p, __ffsll((long long)above) - 1, 64);
+  }
   if (kb >= n_blocks) return;
   const int64_t e0 = kb * kLaneEvents;
-  int64_t lo = 0, hi = n_gates;  // invariant: gate_off[lo] <= e0 < gate_off[hi]
   while (hi - lo > 1) {
     const int64_t mid = (lo + hi) >> 1;
     if (gate_off[mid] <= e0) lo = mid; else hi = mid;
@@ -1633,20 +1651,35 @@ __global__ void __launch_bounds__(256) k_plan_block_gate(const int64_t* gate_off
   plan[kb] = make_uint2((uint32_t)lo, 0u);
 }
 
-// XOR of the toggle masks of a block's events.
+// The toggle mask of an event: bit (pin) of its pin_bit byte (pin << 1 | value).
+__device__ __forceinline__ uint32_t toggle_bit(uint32_t b) { return 1u << ((b >> 1) & 31u); }
+// XOR of the toggle masks of the four events of a 32-bit word of pin_bit bytes.
+__device__ __forceinline__ uint32_t toggles4(uint32_t w) {
+  return toggle_bit(w & 0xffu) ^ toggle_bit((w >> 8) & 0xffu) ^ toggle_bit((w >> 16) & 0xffu) ^ toggle_bit(w >> 24);
+}
+
+// XOR of the toggle masks of a block's events (a whole block is one 16-byte
+// load: the caller's arrays are 16-byte aligned).
 __global__ void __launch_bounds__(256) k_plan_block_xor(const uint8_t* pb, int64_t n_events, uint32_t* bx,
                                                         int64_t n_blocks) {
   const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (kb >= n_blocks) return;
   const int64_t e0 = kb * kLaneEvents, e1 = min(e0 + kLaneEvents, n_events);
   uint32_t x = 0;
-  for (int64_t e = e0; e < e1; ++e) x ^= 1u << ((pb[e] >> 1) & 31);
+  if (e1 - e0 == kLaneEvents) {
+    const uint4 p4 = *reinterpret_cast<const uint4*>(pb + e0);
+    x = toggles4(p4.x) ^ toggles4(p4.y) ^ toggles4(p4.z) ^ toggles4(p4.w);
+  } else {
+    for (int64_t e = e0; e < e1; ++e) x ^= toggle_bit(pb[e]);
+  }
   bx[kb] = x;
 }
 
 // Carried parity: with P(x) the XOR of all toggle masks before event x (any
 // gate), the parity gate g carries into block b is P(16b) ^ P(gate_off[g]):
-// the events of earlier gates cancel.
+// the events of earlier gates cancel. P(gate_off[g]) is the prefix of its
+// block plus the block's events before gate_off[g] (that block is whole: it
+// ends at or before block b starts).
 __global__ void __launch_bounds__(256) k_plan_block_carry(const int64_t* gate_off, const uint8_t* pb,
                                                           const uint32_t* bpre, uint2* plan, int64_t n_blocks) {
   const int64_t kb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1657,8 +1690,13 @@ __global__ void __launch_bounds__(256) k_plan_block_carry(const int64_t* gate_of
   uint32_t carry = 0;
   if (gs < e0) {
     const int64_t kb0 = gs / kLaneEvents;
+    const int n = (int)(gs - kb0 * kLaneEvents);   // events of block kb0 before the gate, 0..15
+    const uint4 p4 = *reinterpret_cast<const uint4*>(pb + kb0 * kLaneEvents);
+    const uint32_t w[4] = {p4.x, p4.y, p4.z, p4.w};
     uint32_t p = bpre[kb0];
-    for (int64_t e = kb0 * kLaneEvents; e < gs; ++e) p ^= 1u << ((pb[e] >> 1) & 31);
+#pragma unroll
+    for (int i = 0; i < kLaneEvents; ++i)
+      if (i < n) p ^= toggle_bit((w[i >> 2] >> (8 * (i & 3))) & 0xffu);
     carry = bpre[kb] ^ p;
   }
   plan[kb].y = carry;
