@@ -450,7 +450,7 @@ struct FillArgs {
   const uint32_t* tile_grp;
   const uint32_t* tfirst;
   const int64_t* grp_off;
-  uint32_t* ev;               // grouped event words, rows and slew weights
+  uint32_t* ev;               // per event its word, table row and slew weight (12 bytes)
   float* rgl;
   uint2* desc;
   int4* gquads;               // optional: quad range of every group's cells (see below)
