@@ -83,6 +83,8 @@ struct PackIn {
   Workspace* ws = nullptr;        // [2] temporaries (caller-owned)
   int64_t glitch_clk = 0;         // > 0: per-event glitch factors for this clock period
   Workspace* arena = nullptr;     // optional: output arrays carved from it while it has room
+  bool time_order = false;        // units of one (tile, gate block, length) ordered by the time of their
+                                  // first event instead of by gate (gate blocks of at most 2^16 gates)
 };
 
 struct PackOut {

@@ -53,6 +53,8 @@ struct KeyLayout {
   int32_t gin_shift;   // the field holds the gate's index within its block >> gin_shift
   int32_t gb_bits;     // gate-block field
   int32_t tile_bits;
+  int32_t time_key;    // 1: the low field holds the top gin_bits bits of the unit's first in-tile bin instead
+                       // (the gate index then always travels in the first event record)
 };
 
 __host__ __device__ __forceinline__ int key_low(const KeyLayout& L) { return L.len_bits + L.gin_bits; }
@@ -125,6 +127,7 @@ struct UnitVisitor {
   int64_t u_src = 0;
   int32_t u_len = 0;
   int64_t u_tile = 0;
+  uint32_t u_bl = 0;       // in-tile bin of the unit's first event
   // emit pass: the gate, its cell record and (7-knot slew axes) its knots
   int cell = 0;
   uint32_t init = 0;
@@ -161,8 +164,9 @@ struct UnitVisitor {
     if (kEmit) {
       const KeyLayout& KL = A->ks.L;
       const int low = key_low(KL);
+      const uint32_t field = KL.time_key ? (u_bl >> max(0, A->bins.tile_log2 - KL.gin_bits)) : (gin >> KL.gin_shift);
       const K key = ((K)u_tile << (KL.gb_bits + low)) | ((K)gblock << low) |
-                    ((K)((1u << KL.len_bits) - (uint32_t)u_len) << KL.gin_bits) | (K)(gin >> KL.gin_shift);
+                    ((K)((1u << KL.len_bits) - (uint32_t)u_len) << KL.gin_bits) | (K)field;
       const uint32_t i = A->base[kb] + n - A->u0;
       A->lkeys[i] = key;
       A->lsrcs[i] = (uint16_t)(u_src - A->e0);
@@ -209,6 +213,7 @@ struct UnitVisitor {
       u_src = e;
       u_len = 1;
       u_tile = tile;
+      u_bl = (uint32_t)(bin - (tile << B.tile_log2));
     }
     if (kEmit) {
       // Algorithm 1 per event: the table of the input state before the
@@ -522,7 +527,7 @@ __global__ void __launch_bounds__(kFillThreads) k_pk_fill(FillArgs a) {
       // descriptor: the cell-sorted gate | (length - 1) << 28, the leakage state
       // before the unit | cell << 16
       const uint32_t dy = act ? ((r[0].w & 0xffffu) | ((uint32_t)cell << 16)) : 0u;
-      const uint32_t gin = kl.gin_shift ? (r[0].w >> 16) : gin_k;
+      const uint32_t gin = (kl.gin_shift || kl.time_key) ? (r[0].w >> 16) : gin_k;
       const uint32_t dx = act ? ((gs0 + gin) | ((uint32_t)(len - 1) << 28)) : 0xffffffffu;
       a.desc[gi * kGroupUnits + lane] = make_uint2(dx, dy);
       if (a.gquads) {
@@ -921,6 +926,7 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       const int room = head <= 24 ? 24 - head : (head <= 32 ? 32 - head : in.gate_block_log2);
       kl.gin_bits = in.gate_block_log2 > 16 ? in.gate_block_log2 : std::min(room, in.gate_block_log2);
       kl.gin_shift = in.gate_block_log2 - kl.gin_bits;
+      kl.time_key = (in.time_order && in.gate_block_log2 <= 16) ? 1 : 0;
     }
     const int gb_bits = kl.gb_bits;
     const int low = key_low(kl);   // length and gate-index fields

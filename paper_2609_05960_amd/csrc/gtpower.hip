@@ -166,6 +166,10 @@ struct gtp_ctx_s {
   PackOut pk;
   double pack_ms = 0.0;
   Workspace pk_ws[2];   // the pack's temporaries, kept between packs
+  // the adjoint's own layout (units ordered by time within a run), built on
+  // the first packed adjoint after the layout was (re)built
+  bool pack_adj_ok = false;
+  PackOut pk_adj;
 
   // kernel timing (gtp_profile_enable)
   bool prof_on = false;
@@ -534,12 +538,17 @@ void drop_batch_packs(gtp_ctx c);
 void drop_batch(gtp_ctx c);
 
 void drop_pack(gtp_ctx c) {
+  if (c->pk.ev || c->pk.gperm || c->pk_adj.ev || c->pk_adj.gperm) (void)hipStreamSynchronize(c->stream);
   if (c->pk.ev || c->pk.gperm) {
-    (void)hipStreamSynchronize(c->stream);
     c->dev_bytes -= c->pk.bytes;
     pack_free(&c->pk);
   }
+  if (c->pk_adj.ev || c->pk_adj.gperm) {
+    c->dev_bytes -= c->pk_adj.bytes;
+    pack_free(&c->pk_adj);
+  }
   c->pack_ok = false;
+  c->pack_adj_ok = false;
   c->adj_ok = false;
 }
 
@@ -591,7 +600,8 @@ gtp_status choose_mfix(gtp_ctx c, const PackOut& pk, int64_t bin_ps, int32_t* m)
 // sets B.tile_log2 / B.n_tiles.
 gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, BinSpec& B, PackOut& pk, double& pack_ms,
                     int32_t* dbg_state = nullptr, int64_t* dbg_bin = nullptr,
-                    const std::vector<int64_t>* gate_weight = nullptr, Workspace* arena = nullptr) {
+                    const std::vector<int64_t>* gate_weight = nullptr, Workspace* arena = nullptr,
+                    bool time_order = false) {
   if (B.r_bits > kTimeBits) return fail(c, GTP_ERR_UNSUPPORTED, "bin width above 2^%d ps", kTimeBits);
   int lb = c->tun.bins_per_tile_log2 ? c->tun.bins_per_tile_log2 : auto_tile_log2(B.n_bins, B.r_bits, c->n_cu);
   if (lb + B.r_bits > kTimeBits)
@@ -627,6 +637,7 @@ gtp_status pack_for(gtp_ctx c, const gtp_events& ev, const DevBuf& plan_buf, Bin
   in.ws = c->pk_ws;
   in.glitch_clk = c->par.glitch_clk_ps;
   in.arena = arena;
+  in.time_order = time_order;
   const size_t ws_before = c->pk_ws[0].bytes + c->pk_ws[1].bytes;
   char msg[256] = {0};
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -692,6 +703,32 @@ gtp_status build_pack(gtp_ctx c) {
   return GTP_OK;
 }
 
+// The adjoint's layout: the same units, groups and gate order as the
+// forward's, but inside a run of one (tile, gate block, length) the units are
+// ordered by the time of their first event, so a group's bin-weight gathers
+// fall in fewer cache lines (the forward keeps gate order: its gate-record
+// gathers prefer it). Built once per layout, on the first adjoint; when it
+// cannot be built (gate blocks above 2^16 gates, or no memory for it) the
+// adjoint reads the forward's layout.
+gtp_status build_pack_adj(gtp_ctx c) {
+  if (c->pack_adj_ok) return GTP_OK;
+  const int gbl = c->tun.gate_block_log2 ? c->tun.gate_block_log2 : kGateBlockLog2;
+  if (gbl > 16) return GTP_OK;
+  BinSpec B = c->bins;
+  double ms = 0.0;
+  if (pack_for(c, c->ev, c->plan_blk, B, c->pk_adj, ms, nullptr, nullptr, nullptr, nullptr, true) != GTP_OK) {
+    if (c->pk_adj.ev || c->pk_adj.gperm) {
+      c->dev_bytes -= c->pk_adj.bytes;
+      pack_free(&c->pk_adj);
+    }
+    return GTP_OK;   // the forward's layout serves
+  }
+  c->pack_adj_ok = true;
+  return GTP_OK;
+}
+
+const PackOut& adj_pack(gtp_ctx c) { return c->pack_adj_ok ? c->pk_adj : c->pk; }
+
 // LDS of the packed adjoint: the library prefix, one cell's table quads (as
 // many as fit, at most one slot), two FP64 accumulators per gate of the
 // largest gate block.
@@ -710,7 +747,7 @@ size_t adj_lds_bytes(gtp_ctx c, int32_t max_gb) {
 // shared by all blocks (about three items per CU in all).
 gtp_status adj_plan(gtp_ctx c) {
   if (c->adj_ok) return GTP_OK;
-  const PackOut& pk = c->pk;
+  const PackOut& pk = adj_pack(c);
   const int32_t n_gb = pk.n_gb, n_tiles = c->bins.n_tiles;
   const int64_t n_reg = (int64_t)n_tiles * n_gb;
   if (pk.n_groups >= ((int64_t)1 << 31)) return fail(c, GTP_ERR_UNSUPPORTED, "too many groups for the adjoint");
@@ -2163,6 +2200,7 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
   bool packed = c->tun.algo == 0;
   if (packed) {
     TRY(build_pack(c));
+    TRY(build_pack_adj(c));
     TRY(adj_plan(c));
     packed = adj_lds_bytes(c, c->adj_max_gb) <= kMaxLds;  // else the gate-major kernel
   }
@@ -2193,7 +2231,7 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
            ptr<double>(c->adj_total), NB, (int32_t)c->bins.tile_log2);
     TRY(gate_params(c, net_load_ff, leak_scale));
     if (c->adj_n_items > 0) {
-      const PackOut& pk = c->pk;
+      const PackOut& pk = adj_pack(c);
       AdjPackedArgs a;
       a.f = packed_common(c, pk.mfix);
       a.f.ev = pk.ev;
