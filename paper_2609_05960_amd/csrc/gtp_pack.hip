@@ -927,6 +927,10 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
       kl.gin_bits = in.gate_block_log2 > 16 ? in.gate_block_log2 : std::min(room, in.gate_block_log2);
       kl.gin_shift = in.gate_block_log2 - kl.gin_bits;
       kl.time_key = (in.time_order && in.gate_block_log2 <= 16) ? 1 : 0;
+      if (kl.time_key) {   // the whole in-tile bin, in 32 bits when 24 do not hold it
+        const int tb = in.bins.tile_log2;
+        kl.gin_bits = head + tb <= 32 ? tb : std::max(0, std::min(tb, 64 - head));
+      }
     }
     const int gb_bits = kl.gb_bits;
     const int low = key_low(kl);   // length and gate-index fields
