@@ -2279,10 +2279,11 @@ gtp_status gtp_adjoint(gtp_ctx c, const float* net_load_ff, const float* leak_sc
       o.gb_row = ptr<int64_t>(c->adj_gbrow);
       o.gb_rows = ptr<int32_t>(c->adj_gbrows);
       o.gb_start = ptr<int32_t>(c->adj_gbs);
-      o.n_gb = c->pk.n_gb;
+      const PackOut& pa = adj_pack(c);   // the layout the adjoint's partial rows follow
+      o.n_gb = pa.n_gb;
       o.total = ptr<double>(c->adj_total);
-      o.gperm = c->pk.gperm;
-      o.gcell = c->pk.gcell;
+      o.gperm = pa.gperm;
+      o.gcell = pa.gcell;
       o.gate_out = ptr<int32_t>(c->gate_out);
       o.gate_init = ptr<uint32_t>(c->gate_init);
       o.meta = lib_view(c).meta;
