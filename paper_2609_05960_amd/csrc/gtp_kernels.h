@@ -127,12 +127,22 @@ struct GroupRegs {
   float gv[kS];   // energy factors (glitch detection on only)
 };
 
+// A unit descriptor loaded non-temporally (the adjoint reads each once).
+typedef unsigned int desc_vec __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint2 desc_nt(const uint2* p) {
+  const desc_vec v = __builtin_nontemporal_load(reinterpret_cast<const desc_vec*>(p));
+  return make_uint2(v.x, v.y);
+}
+
 // Issue every load of one group (descriptor and offset already loaded).
 // With mine false the lane's length still counts for the positions of the
 // other lanes, but its own loads are skipped.
 // kS is the longest unit the layout holds (its unit_events), 8 or 16; kGl:
-// the events' energy factors are loaded too (glitch detection on).
-template <int kS, bool kGl>
+// the events' energy factors are loaded too (glitch detection on); kNt: the
+// records load non-temporally (read once: their lines leave the L2 first, so
+// that the gathered lines that are read again, bin weights and gate records,
+// stay; the adjoint runs about 2 % faster with it, the forward not measurably).
+template <int kS, bool kGl, bool kNt = false>
 __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int64_t off, GroupRegs<kS>& G,
                                             bool mine = true) {
   G.d = d;
@@ -161,7 +171,15 @@ __device__ __forceinline__ void group_issue(const PackedFwdArgs& a, uint2 d, int
       if (on && mine) {
         const uint32_t r =
             o + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        const uint3 v = ep[r];
+        uint3 v;
+        if (kNt) {
+          const uint32_t* vp = reinterpret_cast<const uint32_t*>(ep + r);
+          v.x = __builtin_nontemporal_load(vp);
+          v.y = __builtin_nontemporal_load(vp + 1);
+          v.z = __builtin_nontemporal_load(vp + 2);
+        } else {
+          v = ep[r];
+        }
         G.wv[kk] = v.x;
         G.rv[kk] = v.y;
         G.av[kk] = __uint_as_float(v.z);
@@ -1199,17 +1217,17 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_packed(AdjPackedArgs a) {
   auto issue = [&](int64_t en, GroupRegs<kS>& R, bool& m, int32_t& t) {
     m = lane >= (en1.z & 0xff) && lane < (en1.z >> 8);
     t = en1.y;
-    group_issue<kS, kGl>(a.f, dn, offn, R, m);
+    group_issue<kS, kGl, true>(a.f, dn, offn, R, m);
     en1 = en2;
     if (en + nwave < e1) {
-      dn = a.f.desc[(int64_t)en1.x * kGroupUnits + lane];
+      dn = desc_nt(a.f.desc + (int64_t)en1.x * kGroupUnits + lane);
       offn = voff(en1.x);
     }
     if (en + 2 * nwave < e1) en2 = ventry(en + 2 * nwave);
   };
   if (e < e1) {
     en1 = ventry(e);
-    dn = a.f.desc[(int64_t)en1.x * kGroupUnits + lane];
+    dn = desc_nt(a.f.desc + (int64_t)en1.x * kGroupUnits + lane);
     offn = voff(en1.x);
     if (e + nwave < e1) en2 = ventry(e + nwave);
     issue(e, ga, ma, ta);
