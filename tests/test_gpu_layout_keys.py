@@ -3,8 +3,9 @@
 The unit sort key holds (tile, gate block, length class, gate index within
 the block). It is 24 bits wide when the first three fields leave room (the
 gate index then shifted, its whole value carried by the unit's first event
-record), else 32 bits, else 64 bits with every field whole. The workloads of
-the other tests use 24-bit keys; these problems force the wider ones (many
+record), else at most 30 bits (sorted in three passes of 10-bit digits), else
+32 bits, else 64 bits with every field whole. The workloads of the other tests
+use 24-bit keys; these problems force the wider ones (many
 4-bin tiles, small gate blocks, 16-event units) and check every bin against
 the FP64 oracle, every event's state and bin bit for bit, and the packed path
 against one gate per thread bit for bit.
@@ -49,7 +50,7 @@ def run(prob, algo, **tune):
 @pytest.mark.parametrize("case", ["key32", "key64"])
 def test_wide_sort_keys(O, case):
     if case == "key32":
-        # 2^16 tiles (16 bits), 64 one-block cells (6), 8-event units (3): 25 bits
+        # 2^16 tiles (16 bits), 64 one-block cells (6), 8-event units (3): 25 bits, a 30-bit key
         prob = synth.make_random_small(71, n_gates=512, n_cells=64, i_max=3, n_events=60000, t_end=1 << 19,
                                        bin_ps=2, p_tie=0.1, n_clock=2)
         tune = dict(bins_per_tile_log2=2, tile_threads=256)
